@@ -1,0 +1,181 @@
+/*
+ * nrlsh.h -- C ABI of libnrlsh, norm-ranging LSH for maximum inner product
+ * search (Yan, Li, Dai, Chen, Cheng, "Norm-Ranging LSH for Maximum Inner
+ * Product Search", NeurIPS 2018) on AMD Instinct MI355X (gfx950).
+ *
+ * Problem (Section 1, Eq. 1): given n items x in R^d and a query q, return the
+ * k items with the largest inner products q^T x, approximately.
+ *
+ * Index (Algorithm 1): items are ranked by 2-norm and cut into m sub-datasets
+ * of (almost) equal size by norm percentile; sub-dataset j is normalised by
+ * its own maximum norm U_j, transformed with SimpleLSH (Eq. 8,
+ * P(x) = [x; sqrt(1 - ||x||^2)]) and hashed with L sign random projections
+ * (Eq. 4) into an L-bit code.  One projection matrix serves all sub-datasets.
+ *
+ * Query (Algorithm 2 realised as the single-table multi-probe of
+ * Section 3.3): the query code is P(q) = [q; 0] hashed with the same
+ * projections; each item scores l = number of bits identical to the query
+ * code, buckets (j, l) are probed in descending order of the similarity
+ * metric s_hat = U_j cos[pi (1 - l/L)] (Eq. 12, via the sorted (U_j, l)
+ * structure built with the index), the first T probed items are re-ranked by
+ * their exact inner product and the best k are returned.
+ *
+ * Conventions shared by every call
+ *   - Matrices are row-major and dense: items n x d, queries nq x d (float32).
+ *   - Item / query / output pointers are HOST pointers unless an _ex call is
+ *     given opts->device_ptrs = 1, in which case they are device pointers on
+ *     the current HIP device (e.g. a torch tensor's data_ptr()).
+ *   - Every call is synchronous: when it returns, outputs are written and
+ *     the caller may reuse or free its inputs.  nrlsh_build copies the items;
+ *     the index owns all of its device memory until nrlsh_free.
+ *   - Ids are 0-based original item indices.  Results are ordered by
+ *     (inner product descending, id ascending).  When fewer than k items are
+ *     probed (min(T, n) < k) the tail is padded with id -1 and ip -INFINITY.
+ *   - The index is immutable after build; concurrent nrlsh_query calls on one
+ *     index are safe (each call allocates its own scratch).
+ *   - Errors: a non-OK status is returned and nrlsh_last_error() gives a
+ *     thread-local message.  No C++ exception crosses this ABI.  Arguments
+ *     are validated on the host before any device work.
+ */
+#ifndef NRLSH_H
+#define NRLSH_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nrlsh_index nrlsh_index; /* opaque */
+
+typedef enum nrlsh_status {
+    NRLSH_OK = 0,
+    NRLSH_E_INVALID_ARG = 1,   /* an argument is out of range or a pointer is NULL */
+    NRLSH_E_NOT_FINITE = 2,    /* an item or query holds NaN or +-Inf */
+    NRLSH_E_OUT_OF_MEMORY = 3, /* a device or host allocation failed */
+    NRLSH_E_DEVICE = 4,        /* a HIP runtime call failed */
+    NRLSH_E_INTERNAL = 5       /* an internal invariant failed */
+} nrlsh_status;
+
+/* Limits enforced by validation. */
+#define NRLSH_MAX_L 64         /* code bits per item (1 <= L <= 64) */
+#define NRLSH_MAX_K 1024       /* results per query */
+#define NRLSH_MAX_N 2147483647 /* items per index (positions are int32) */
+
+/* ---------------------------------------------------------------- build --
+ * nrlsh_build: Algorithm 1 plus the sorted (U_j, l) structure of Section 3.3.
+ *   items  n x d float32 (host pointer), finite.
+ *   n      1 <= n <= NRLSH_MAX_N;  d >= 1;  1 <= m <= n;  1 <= L <= 64.
+ *   seed   seeds the projection matrix A (L x (d+1), i.i.d. N(0,1) per Eq. 4):
+ *          entry (r, c) is the Box-Muller transform of SplitMix64 outputs
+ *          2t and 2t+1, t = r (d+1) + c, rounded to float32.
+ *   out    receives the new index (caller frees with nrlsh_free).
+ * Sub-dataset j (0-based) holds the items of norm rank [ceil(j n/m),
+ * ceil((j+1) n/m)) in ascending (squared norm, index) order; the squared norm
+ * is summed in FP64 in ascending coordinate order.  Hash bit r of an item is
+ * [A_r . P(x/U_j) > 0] with the sign decided exactly as in FP64 (projections
+ * too close to zero for the FP32 matrix-core pass are recomputed in FP64). */
+nrlsh_status nrlsh_build(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
+                         uint64_t seed, nrlsh_index **out);
+
+typedef struct nrlsh_build_opts {
+    int32_t struct_size; /* sizeof(nrlsh_build_opts) */
+    int32_t device_ptrs; /* 1: items is a device pointer */
+    void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
+    double eps;          /* adjusted metric s_hat = U_j cos[pi (1-eps)(1 - l/L)]
+                            (Section 3.3), 0 <= eps < 1; 0 = Eq. 12 */
+} nrlsh_build_opts;
+
+nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
+                            uint64_t seed, const nrlsh_build_opts *opts, nrlsh_index **out);
+
+/* Releases every resource of the index.  NULL is a no-op. */
+void nrlsh_free(nrlsh_index *ix);
+
+/* ---------------------------------------------------------------- query --
+ * nrlsh_query: multi-probe MIPS (Section 3.3) with exact re-rank (Algorithm 2).
+ *   queries       nq x d float32 (host), finite; nq >= 0 (0 is a no-op).
+ *   k             1 <= k <= NRLSH_MAX_K.
+ *   probe_budget  T >= 1 items to probe per query; clamped to n.
+ *   out_ids       nq x k int64 (host): original item ids.
+ *   out_ips       nq x k float32 (host): q^T x computed in FP64 (ascending
+ *                 coordinate order) and rounded to float32.
+ * The probed set is exactly the first min(T, n) items in the order
+ * (bucket rank of (j, l) ascending, id ascending): the bucket where the budget
+ * runs out is cut by id.  The result is the top-k of that set by
+ * (FP64 inner product desc, id asc). */
+nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                         int64_t probe_budget, int64_t *out_ids, float *out_ips);
+
+typedef struct nrlsh_query_opts {
+    int32_t struct_size; /* sizeof(nrlsh_query_opts) */
+    int32_t device_ptrs; /* 1: queries, out_ids, out_ips are device pointers */
+    void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
+} nrlsh_query_opts;
+
+nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                            int64_t probe_budget, const nrlsh_query_opts *opts,
+                            int64_t *out_ids, float *out_ips);
+
+/* Thread-local message for the last non-OK status of this thread. */
+const char *nrlsh_last_error(void);
+
+/* ----------------------------------------------------------- inspection --
+ * Copies of index internals to HOST buffers, for parity tests and reports.
+ * All are synchronous and return NRLSH_E_INVALID_ARG on NULL arguments. */
+
+/* n, d, m, L and the padded row stride dp (floats) of the stored item copy. */
+nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int32_t *m,
+                              int32_t *L, int32_t *dp);
+
+/* A: L x (d+1) float32, row r = hash function r (Eq. 4). */
+nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A);
+
+/* key: n float64 squared 2-norms in original order (Algorithm 1 ranking key). */
+nrlsh_status nrlsh_get_keys(const nrlsh_index *ix, double *key);
+
+/* sid: n int32 sub-dataset of each original item; keymax: m float64 largest
+ * squared norm of each sub-dataset; U: m float64 = sqrt(keymax). */
+nrlsh_status nrlsh_get_partition(const nrlsh_index *ix, int32_t *sid, double *keymax, double *U);
+
+/* perm: n int32, original id at each stored position (sub-dataset major,
+ * ascending id inside a sub-dataset); off: m+1 int64 sub-dataset offsets. */
+nrlsh_status nrlsh_get_layout(const nrlsh_index *ix, int32_t *perm, int64_t *off);
+
+/* codes: n uint64 item codes in original order; bit r = hash r, bits >= L zero. */
+nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes);
+
+/* R: m x (L+1) int32 probing rank of bucket (j, l) (0 = probed first). */
+nrlsh_status nrlsh_get_rank_table(const nrlsh_index *ix, int32_t *R);
+
+typedef struct nrlsh_build_stats {
+    int64_t recomputed_items; /* items with at least one bit recomputed in FP64 */
+    int64_t recomputed_bits;  /* (item, bit) projections recomputed in FP64 */
+    int64_t recompute_flips;  /* of those, bits whose FP32 sign differed from FP64 */
+} nrlsh_build_stats;
+
+nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st);
+
+/* Query codes: nq uint64 (host in, host out), bit r = [A_r[:d] . q > 0]. */
+nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,
+                               uint64_t *codes);
+
+/* Probed set of each query: cand is nq x min(T, n) int64 original ids (host),
+ * listed sub-dataset by sub-dataset in stored order. */
+nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                    int64_t probe_budget, int64_t *cand);
+
+/* ------------------------------------------------------------ profiling --
+ * Optional per-kernel timing with HIP events recorded on the stream each
+ * kernel is launched on.  Off by default; enabling adds one event pair per
+ * timed launch.  Names: "keys", "sort", "hash", "hash_fixup", "qhash",
+ * "scan_hist", "threshold", "scan_emit", "rerank". */
+void nrlsh_profile_enable(int32_t on);
+void nrlsh_profile_reset(void);
+/* Total milliseconds and launch count of kernel `name` since the last reset. */
+nrlsh_status nrlsh_profile_get(const char *name, double *total_ms, int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NRLSH_H */

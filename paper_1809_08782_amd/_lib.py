@@ -1,0 +1,288 @@
+"""ctypes binding of libnrlsh (argument marshalling only).
+
+Names follow the C ABI of ``include/nrlsh.h``.  Host numpy arrays go through
+the host-pointer entry points; CUDA/HIP torch tensors go through the ``_ex``
+entry points with device pointers and torch's current stream.  There is no
+fallback: if ``libnrlsh.so`` is missing or fails to load, every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnrlsh.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "nrlsh.h")
+
+NRLSH_OK = 0
+STATUS_NAMES = {0: "NRLSH_OK", 1: "NRLSH_E_INVALID_ARG", 2: "NRLSH_E_NOT_FINITE",
+                3: "NRLSH_E_OUT_OF_MEMORY", 4: "NRLSH_E_DEVICE", 5: "NRLSH_E_INTERNAL"}
+
+
+class NrlshError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class BuildOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32),
+                ("stream", C.c_void_p), ("eps", C.c_double)]
+
+
+class QueryOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p)]
+
+
+class BuildStats(C.Structure):
+    _fields_ = [("recomputed_items", C.c_int64), ("recomputed_bits", C.c_int64),
+                ("recompute_flips", C.c_int64)]
+
+
+_lib = None
+P = C.c_void_p
+I32, I64, U64, F64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
+
+
+def lib():
+    """Load libnrlsh.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing; build it with "
+                              "`python -m paper_1809_08782_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int
+        L.nrlsh_build.argtypes = [P, I64, I32, I32, I32, U64, C.POINTER(P)]
+        L.nrlsh_build.restype = st
+        L.nrlsh_build_ex.argtypes = [P, I64, I32, I32, I32, U64, C.POINTER(BuildOpts), C.POINTER(P)]
+        L.nrlsh_build_ex.restype = st
+        L.nrlsh_free.argtypes = [P]
+        L.nrlsh_free.restype = None
+        L.nrlsh_query.argtypes = [P, P, I64, I32, I64, P, P]
+        L.nrlsh_query.restype = st
+        L.nrlsh_query_ex.argtypes = [P, P, I64, I32, I64, C.POINTER(QueryOpts), P, P]
+        L.nrlsh_query_ex.restype = st
+        L.nrlsh_last_error.argtypes = []
+        L.nrlsh_last_error.restype = C.c_char_p
+        L.nrlsh_index_info.argtypes = [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I32),
+                                       C.POINTER(I32), C.POINTER(I32)]
+        L.nrlsh_index_info.restype = st
+        for name in ("nrlsh_get_projection", "nrlsh_get_keys", "nrlsh_get_codes",
+                     "nrlsh_get_rank_table"):
+            f = getattr(L, name)
+            f.argtypes = [P, P]
+            f.restype = st
+        L.nrlsh_get_partition.argtypes = [P, P, P, P]
+        L.nrlsh_get_partition.restype = st
+        L.nrlsh_get_layout.argtypes = [P, P, P]
+        L.nrlsh_get_layout.restype = st
+        L.nrlsh_get_build_stats.argtypes = [P, C.POINTER(BuildStats)]
+        L.nrlsh_get_build_stats.restype = st
+        L.nrlsh_query_codes.argtypes = [P, P, I64, P]
+        L.nrlsh_query_codes.restype = st
+        L.nrlsh_query_candidates.argtypes = [P, P, I64, I64, P]
+        L.nrlsh_query_candidates.restype = st
+        L.nrlsh_profile_enable.argtypes = [I32]
+        L.nrlsh_profile_enable.restype = None
+        L.nrlsh_profile_reset.argtypes = []
+        L.nrlsh_profile_reset.restype = None
+        L.nrlsh_profile_get.argtypes = [C.c_char_p, C.POINTER(F64), C.POINTER(I64)]
+        L.nrlsh_profile_get.restype = st
+        _lib = L
+    return _lib
+
+
+def header_symbols() -> list:
+    """Function names declared in include/nrlsh.h."""
+    with open(HEADER_PATH) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"\b(nrlsh_[a-z_0-9]+)\s*\(", text)))
+
+
+def _check(status: int):
+    if status != NRLSH_OK:
+        raise NrlshError(status, lib().nrlsh_last_error().decode(errors="replace"))
+
+
+def _is_torch_device(t) -> bool:
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        return False
+    return isinstance(t, torch.Tensor) and t.is_cuda
+
+
+def _torch_stream(t):
+    import torch
+    return P(torch.cuda.current_stream(t.device).cuda_stream)
+
+
+def _host_f32(a) -> np.ndarray:
+    a = np.ascontiguousarray(a, dtype=np.float32)
+    if a.ndim != 2:
+        raise ValueError("expected a 2-D (rows x d) array")
+    return a
+
+
+class Index:
+    """Owns an ``nrlsh_index*`` (Algorithm 1 output).  Free with close()."""
+
+    def __init__(self, handle: int):
+        self._h = P(handle)
+        n, d, m, L, dp = I64(), I32(), I32(), I32(), I32()
+        _check(lib().nrlsh_index_info(self._h, C.byref(n), C.byref(d), C.byref(m), C.byref(L),
+                                      C.byref(dp)))
+        self.n, self.d, self.m, self.L, self.dp = n.value, d.value, m.value, L.value, dp.value
+
+    @property
+    def handle(self):
+        if not self._h:
+            raise ValueError("index is closed")
+        return self._h
+
+    def close(self):
+        if self._h:
+            lib().nrlsh_free(self._h)
+            self._h = P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -------------------------------------------------- inspection
+    def projection(self) -> np.ndarray:
+        A = np.empty((self.L, self.d + 1), dtype=np.float32)
+        _check(lib().nrlsh_get_projection(self.handle, A.ctypes.data))
+        return A
+
+    def keys(self) -> np.ndarray:
+        k = np.empty(self.n, dtype=np.float64)
+        _check(lib().nrlsh_get_keys(self.handle, k.ctypes.data))
+        return k
+
+    def partition(self):
+        sid = np.empty(self.n, dtype=np.int32)
+        keymax = np.empty(self.m, dtype=np.float64)
+        U = np.empty(self.m, dtype=np.float64)
+        _check(lib().nrlsh_get_partition(self.handle, sid.ctypes.data, keymax.ctypes.data,
+                                         U.ctypes.data))
+        return sid, keymax, U
+
+    def layout(self):
+        perm = np.empty(self.n, dtype=np.int32)
+        off = np.empty(self.m + 1, dtype=np.int64)
+        _check(lib().nrlsh_get_layout(self.handle, perm.ctypes.data, off.ctypes.data))
+        return perm, off
+
+    def codes(self) -> np.ndarray:
+        c = np.empty(self.n, dtype=np.uint64)
+        _check(lib().nrlsh_get_codes(self.handle, c.ctypes.data))
+        return c
+
+    def rank_table(self) -> np.ndarray:
+        R = np.empty((self.m, self.L + 1), dtype=np.int32)
+        _check(lib().nrlsh_get_rank_table(self.handle, R.ctypes.data))
+        return R
+
+    def build_stats(self) -> dict:
+        st = BuildStats()
+        _check(lib().nrlsh_get_build_stats(self.handle, C.byref(st)))
+        return {"recomputed_items": st.recomputed_items, "recomputed_bits": st.recomputed_bits,
+                "recompute_flips": st.recompute_flips}
+
+    def query_codes(self, queries) -> np.ndarray:
+        Q = _host_f32(queries)
+        out = np.empty(Q.shape[0], dtype=np.uint64)
+        _check(lib().nrlsh_query_codes(self.handle, Q.ctypes.data, Q.shape[0], out.ctypes.data))
+        return out
+
+    def query_candidates(self, queries, probe_budget: int) -> np.ndarray:
+        Q = _host_f32(queries)
+        Tq = min(int(probe_budget), self.n)
+        out = np.empty((Q.shape[0], Tq), dtype=np.int64)
+        _check(lib().nrlsh_query_candidates(self.handle, Q.ctypes.data, Q.shape[0],
+                                            int(probe_budget), out.ctypes.data))
+        return out
+
+
+# ------------------------------------------------------------------ C-ABI names
+def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None) -> Index:
+    """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
+    tensor (n, d) float32 (device pointer, torch's current stream)."""
+    h = P()
+    if _is_torch_device(items):
+        if items.dtype.__str__() != "torch.float32" or items.dim() != 2:
+            raise ValueError("items must be a 2-D float32 tensor")
+        items = items.contiguous()
+        opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps))
+        _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
+                                    seed, C.byref(opts), C.byref(h)))
+    else:
+        X = _host_f32(items)
+        if eps != 0.0 or stream is not None:
+            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps))
+            _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
+                                        C.byref(opts), C.byref(h)))
+        else:
+            _check(lib().nrlsh_build(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
+                                     C.byref(h)))
+    return Index(h.value)
+
+
+def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None):
+    """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
+    numpy for host queries, torch tensors for CUDA torch queries."""
+    if _is_torch_device(queries):
+        import torch
+        Q = queries.contiguous()
+        nq = Q.shape[0]
+        if out is None:
+            ids = torch.empty((nq, k), dtype=torch.int64, device=Q.device)
+            ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
+        else:
+            ids, ips = out
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q))
+        _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
+                                    C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
+        return ids, ips
+    Q = _host_f32(queries)
+    nq = Q.shape[0]
+    ids = np.empty((nq, k), dtype=np.int64)
+    ips = np.empty((nq, k), dtype=np.float32)
+    _check(lib().nrlsh_query(ix.handle, Q.ctypes.data, nq, k, int(probe_budget), ids.ctypes.data,
+                             ips.ctypes.data))
+    return ids, ips
+
+
+def nrlsh_free(ix: Index):
+    ix.close()
+
+
+def nrlsh_last_error() -> str:
+    return lib().nrlsh_last_error().decode(errors="replace")
+
+
+def nrlsh_profile_enable(on: bool = True):
+    lib().nrlsh_profile_enable(1 if on else 0)
+
+
+def nrlsh_profile_reset():
+    lib().nrlsh_profile_reset()
+
+
+def nrlsh_profile_get(name: str):
+    ms, n = F64(), I64()
+    _check(lib().nrlsh_profile_get(name.encode(), C.byref(ms), C.byref(n)))
+    return ms.value, n.value

@@ -1,0 +1,784 @@
+// Host side of libnrlsh: argument validation, device memory, the projection
+// matrix generator, the sorted (U_j, l) structure and the launch sequence of
+// index build (Algorithm 1) and query (Section 3.3 multi-probe + Algorithm 2
+// re-rank).  Every data-parallel step runs in the kernels of k_build.hip and
+// k_query.hip; the host only computes O(L d) and O(m L log(m L)) set-up
+// tables.
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nrlsh.h"
+#include "nrlsh_internal.h"
+
+using namespace nrlsh;
+
+// ================================================================= errors
+namespace {
+
+thread_local std::string g_err;
+
+nrlsh_status fail(nrlsh_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+struct Failure {
+    nrlsh_status st;
+    std::string msg;
+};
+
+[[noreturn]] void throw_hip(hipError_t e, const char *what)
+{
+    if (e == hipErrorOutOfMemory)
+        throw Failure{NRLSH_E_OUT_OF_MEMORY, std::string(what) + ": out of device memory"};
+    throw Failure{NRLSH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
+}
+
+#define HIPX(call)                                      \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) throw_hip(e_, #call);     \
+    } while (0)
+
+// ================================================================= profiling
+struct ProfEntry {
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::map<std::string, ProfEntry> g_prof;
+
+// Records an event pair around each timed launch; settle() must run after the
+// stream has been synchronised.
+class Timer {
+  public:
+    explicit Timer(hipStream_t s) : s_(s), on_(g_prof_on.load() != 0) {}
+    ~Timer()
+    {
+        for (auto &p : pending_) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    }
+    void begin(const char *name)
+    {
+        if (!on_) return;
+        Pending p;
+        p.name = name;
+        HIPX(hipEventCreate(&p.a));
+        HIPX(hipEventCreate(&p.b));
+        HIPX(hipEventRecord(p.a, s_));
+        pending_.push_back(p);
+    }
+    void end()
+    {
+        if (!on_) return;
+        HIPX(hipEventRecord(pending_.back().b, s_));
+    }
+    void settle()
+    {
+        if (!on_) return;
+        std::lock_guard<std::mutex> g(g_prof_mu);
+        for (auto &p : pending_) {
+            float ms = 0.f;
+            HIPX(hipEventElapsedTime(&ms, p.a, p.b));
+            ProfEntry &e = g_prof[p.name];
+            e.ms += ms;
+            e.launches += 1;
+        }
+    }
+
+  private:
+    struct Pending {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    hipStream_t s_;
+    bool on_;
+    std::vector<Pending> pending_;
+};
+
+// ================================================================= device memory
+std::mutex g_dev_mu;
+std::map<int, hipStream_t> g_streams;
+std::map<int, bool> g_pool_ready;
+
+hipStream_t library_stream(int dev)
+{
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    auto it = g_streams.find(dev);
+    if (it != g_streams.end()) return it->second;
+    hipStream_t s;
+    HIPX(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    g_streams[dev] = s;
+    return s;
+}
+
+void prepare_pool(int dev)
+{
+    std::lock_guard<std::mutex> g(g_dev_mu);
+    if (g_pool_ready[dev]) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t thr = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
+    }
+    g_pool_ready[dev] = true;
+}
+
+// Stream-ordered device buffer; freed on the stream it was allocated on.
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    hipStream_t s = nullptr;
+    DBuf() = default;
+    DBuf(size_t count, hipStream_t st) : s(st)
+    {
+        if (count == 0) count = 1;
+        void *v = nullptr;
+        hipError_t e = hipMallocAsync(&v, count * sizeof(T), st);
+        if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
+        p = static_cast<T *>(v);
+    }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        reset();
+        p = o.p;
+        s = o.s;
+        o.p = nullptr;
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void reset()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+    }
+    T *get() const { return p; }
+};
+
+// ================================================================= projection
+// SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) addressed by position: output
+// k of the generator seeded with `seed` is mix(seed + (k+1) * gamma).
+uint64_t splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t z = seed + (k + 1u) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// Gaussian entries of the projection matrix (Eq. 4: i.i.d. N(0,1)).  Entry
+// (r, c) takes outputs 2t and 2t+1, t = r (d+1) + c, through Box-Muller with
+// u1 in (0, 1] and u2 in [0, 1), and is rounded to float32.
+void make_projection(uint64_t seed, int L, int d, std::vector<float> &A)
+{
+    A.resize((size_t)L * (d + 1));
+    for (int r = 0; r < L; ++r)
+        for (int c = 0; c <= d; ++c) {
+            const uint64_t t = (uint64_t)r * (uint64_t)(d + 1) + (uint64_t)c;
+            const uint64_t h1 = splitmix64_at(seed, 2u * t);
+            const uint64_t h2 = splitmix64_at(seed, 2u * t + 1u);
+            const double u1 = (double)((h1 >> 11) + 1u) * (1.0 / 9007199254740992.0);
+            const double u2 = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
+            const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+            A[(size_t)r * (d + 1) + c] = (float)g;
+        }
+}
+
+// ================================================================= rank table
+// Level factor of the similarity metric s_hat = U_j cos[pi (1-eps)(1 - l/L)]
+// (Eq. 12 and its adjusted form).  For eps = 0 the zero at l = L/2 is exact
+// and the factor is antisymmetric about it, so that sub-datasets tie exactly
+// there instead of through the rounding of cos(pi/2).
+double level_factor(int l, int L, double eps)
+{
+    if (eps != 0.0) return std::cos(M_PI * (1.0 - eps) * (double)(L - l) / (double)L);
+    if (2 * l == L) return 0.0;
+    if (2 * l > L) return std::cos(M_PI * (double)(L - l) / (double)L);
+    return -std::cos(M_PI * (double)l / (double)L);
+}
+
+// R[j][l] = probing position of bucket (j, l), ordered by (s_hat desc,
+// j desc, l desc) -- the sorted structure of Section 3.3.  inv[b] is the
+// histogram index j*(L+1) + (L - l) of the bucket at position b.
+void make_rank_table(const std::vector<double> &U, int L, double eps, std::vector<int32_t> &R,
+                     std::vector<int32_t> &inv)
+{
+    const int m = (int)U.size(), L1 = L + 1;
+    struct E {
+        double s;
+        int j, l;
+    };
+    std::vector<E> e((size_t)m * L1);
+    for (int j = 0; j < m; ++j)
+        for (int l = 0; l <= L; ++l) e[(size_t)j * L1 + l] = E{U[j] * level_factor(l, L, eps), j, l};
+    std::sort(e.begin(), e.end(), [](const E &a, const E &b) {
+        if (a.s != b.s) return a.s > b.s;
+        if (a.j != b.j) return a.j > b.j;
+        return a.l > b.l;
+    });
+    R.assign((size_t)m * L1, 0);
+    inv.assign((size_t)m * L1, 0);
+    for (size_t b = 0; b < e.size(); ++b) {
+        R[(size_t)e[b].j * L1 + e[b].l] = (int32_t)b;
+        inv[b] = e[b].j * L1 + (L - e[b].l);
+    }
+}
+
+int current_device()
+{
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    return dev;
+}
+
+bool all_finite(const float *p, int64_t count)
+{
+    for (int64_t i = 0; i < count; ++i)
+        if (!std::isfinite(p[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+// ================================================================= the index
+struct nrlsh_index {
+    int device = 0;
+    int64_t n = 0;
+    int32_t d = 0, dp = 0, m = 0, L = 0, W = 1;
+    uint64_t seed = 0;
+    double eps = 0.0;
+    std::vector<float> A_h;
+    std::vector<double> keymax_h, U_h;
+    std::vector<int64_t> off_h;
+    std::vector<int32_t> R_h;
+    nrlsh_build_stats stats{};
+    hipStream_t home = nullptr;  // library stream that releases the device buffers
+    DBuf<float> Xp, A, At;
+    DBuf<double> key, keymax, U;
+    DBuf<int32_t> sid, perm, off, R, inv;
+    DBuf<uint32_t> codes_l, codes_o;
+};
+
+namespace {
+
+hipStream_t pick_stream(void *user, int dev)
+{
+    return user ? static_cast<hipStream_t>(user) : library_stream(dev);
+}
+
+void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_t s, Timer &tm)
+{
+    const int64_t n = ix->n;
+    const int d = ix->d, dp = ix->dp, m = ix->m, L = ix->L, W = ix->W;
+
+    // projection matrix, its transpose and the FP32 uncertainty band factors
+    make_projection(ix->seed, L, d, ix->A_h);
+    std::vector<float> At_h((size_t)d * L), tau_h(L);
+    for (int r = 0; r < L; ++r) {
+        double nrm2 = 0.0;
+        for (int c = 0; c <= d; ++c) {
+            const double a = ix->A_h[(size_t)r * (d + 1) + c];
+            nrm2 += a * a;
+            if (c < d) At_h[(size_t)c * L + r] = (float)a;
+        }
+        // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
+        // rounded up so that the band is never narrower than the bound.
+        const double ku = (double)(d + 3) * 0x1p-24;
+        const double tau = 2.0 * (ku / (1.0 - ku)) * std::sqrt(nrm2) * (1.0 + 0x1p-20);
+        tau_h[r] = std::nextafter((float)tau, INFINITY);
+    }
+
+    ix->Xp = DBuf<float>((size_t)n * dp, s);
+    ix->A = DBuf<float>(ix->A_h.size(), s);
+    ix->At = DBuf<float>(At_h.size(), s);
+    ix->key = DBuf<double>(n, s);
+    ix->keymax = DBuf<double>(m, s);
+    ix->U = DBuf<double>(m, s);
+    ix->sid = DBuf<int32_t>(n, s);
+    ix->perm = DBuf<int32_t>(n, s);
+    ix->off = DBuf<int32_t>(m + 1, s);
+    ix->R = DBuf<int32_t>((size_t)m * (L + 1), s);
+    ix->inv = DBuf<int32_t>((size_t)m * (L + 1), s);
+    ix->codes_l = DBuf<uint32_t>((size_t)n * W, s);
+    ix->codes_o = DBuf<uint32_t>((size_t)n * W, s);
+
+    DBuf<float> tau(L, s);
+    DBuf<uint64_t> ka(n, s), kb(n, s);
+    DBuf<int32_t> va(n, s), vb(n, s);
+    DBuf<uint8_t> rtmp(radix_sort_tmp_bytes(n), s);
+    DBuf<FixEntry> fix(n, s);
+    DBuf<BuildCounters> ctr(1, s);
+    DBuf<float> staging;
+    const float *X = items;
+    if (!on_device) {
+        staging = DBuf<float>((size_t)n * d, s);
+        HIPX(hipMemcpyAsync(staging.get(), items, (size_t)n * d * sizeof(float),
+                            hipMemcpyHostToDevice, s));
+        X = staging.get();
+    }
+    HIPX(hipMemcpyAsync(ix->A.get(), ix->A_h.data(), ix->A_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->At.get(), At_h.data(), At_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(tau.get(), tau_h.data(), tau_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemsetAsync(ctr.get(), 0, sizeof(BuildCounters), s));
+
+    // Algorithm 1: rank by 2-norm, cut into m percentile ranges
+    tm.begin("keys");
+    HIPX(launch_keys_copy(X, n, d, dp, ix->Xp.get(), ix->key.get(), ka.get(), va.get(), ctr.get(), s));
+    tm.end();
+    bool in_b = false;
+    tm.begin("sort");
+    HIPX(radix_sort(ka.get(), va.get(), kb.get(), vb.get(), n, 64, rtmp.get(), &in_b, s));
+    tm.end();
+    uint64_t *sk = in_b ? kb.get() : ka.get();
+    int32_t *sv = in_b ? vb.get() : va.get();
+    uint64_t *lk = in_b ? ka.get() : kb.get();
+    int32_t *lv = in_b ? va.get() : vb.get();
+    HIPX(launch_assign_subsets(sk, sv, n, m, ix->sid.get(), lk, lv, ix->keymax.get(), s));
+
+    BuildCounters hc{};
+    ix->keymax_h.resize(m);
+    HIPX(hipMemcpyAsync(ix->keymax_h.data(), ix->keymax.get(), m * sizeof(double),
+                        hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    if (hc.nonfinite) throw Failure{NRLSH_E_NOT_FINITE, "items hold NaN or Inf"};
+
+    // U_j and the sorted (U_j, l) structure (host, FP64)
+    ix->U_h.resize(m);
+    for (int j = 0; j < m; ++j) ix->U_h[j] = std::sqrt(ix->keymax_h[j]);
+    std::vector<int32_t> inv_h;
+    make_rank_table(ix->U_h, L, ix->eps, ix->R_h, inv_h);
+    ix->off_h.resize(m + 1);
+    std::vector<int32_t> off32(m + 1);
+    for (int j = 0; j <= m; ++j) {
+        ix->off_h[j] = ((int64_t)j * n + m - 1) / m;
+        off32[j] = (int32_t)ix->off_h[j];
+    }
+    HIPX(hipMemcpyAsync(ix->U.get(), ix->U_h.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->R.get(), ix->R_h.data(), ix->R_h.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->inv.get(), inv_h.data(), inv_h.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->off.get(), off32.data(), off32.size() * sizeof(int32_t),
+                        hipMemcpyHostToDevice, s));
+
+    // stored order: sub-dataset major, ascending original index inside
+    int bits = 0;
+    while ((1ll << bits) < (int64_t)m) ++bits;
+    bits = (bits + 7) / 8 * 8;
+    const int32_t *perm_src = lv;
+    if (bits > 0) {
+        bool lb = false;
+        HIPX(radix_sort(lk, lv, sk, sv, n, bits, rtmp.get(), &lb, s));
+        perm_src = lb ? sv : lv;
+    }
+    HIPX(hipMemcpyAsync(ix->perm.get(), perm_src, (size_t)n * sizeof(int32_t),
+                        hipMemcpyDeviceToDevice, s));
+
+    // SimpleLSH transform + sign random projection, then the FP64 fix-up
+    tm.begin("hash");
+    HIPX(launch_hash(ix->Xp.get(), n, d, dp, ix->A.get(), L, ix->key.get(), ix->sid.get(),
+                     ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_o.get(), fix.get(),
+                     ctr.get(), s));
+    tm.end();
+    tm.begin("hash_fixup");
+    HIPX(launch_hash_fixup(ix->Xp.get(), d, dp, ix->A.get(), L, ix->key.get(), ix->sid.get(),
+                           ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), ix->codes_o.get(),
+                           n, s));
+    tm.end();
+    HIPX(launch_permute_codes(ix->codes_o.get(), ix->perm.get(), n, W, ix->codes_l.get(), s));
+
+    HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    // long-lived buffers are released on the library stream by nrlsh_free
+    for (auto *b : {&ix->Xp, &ix->A, &ix->At}) b->s = ix->home;
+    for (auto *b : {&ix->key, &ix->keymax, &ix->U}) b->s = ix->home;
+    for (auto *b : {&ix->sid, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
+    for (auto *b : {&ix->codes_l, &ix->codes_o}) b->s = ix->home;
+    ix->stats.recomputed_items = hc.fix_count;
+    ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
+    ix->stats.recompute_flips = (int64_t)hc.fix_flips;
+}
+
+nrlsh_status validate_build(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
+                            double eps, nrlsh_index **out)
+{
+    if (!out) return fail(NRLSH_E_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!items) return fail(NRLSH_E_INVALID_ARG, "items is NULL");
+    if (n < 1 || n > NRLSH_MAX_N) return fail(NRLSH_E_INVALID_ARG, "n = %lld out of [1, %d]", (long long)n, NRLSH_MAX_N);
+    if (d < 1 || d > (1 << 24)) return fail(NRLSH_E_INVALID_ARG, "d = %d out of [1, 2^24]", d);
+    if (m < 1 || (int64_t)m > n) return fail(NRLSH_E_INVALID_ARG, "m = %d out of [1, n]", m);
+    if (L < 1 || L > NRLSH_MAX_L) return fail(NRLSH_E_INVALID_ARG, "L = %d out of [1, 64]", L);
+    if ((int64_t)m * (L + 1) > INT32_MAX) return fail(NRLSH_E_INVALID_ARG, "m (L+1) too large");
+    if (!(eps >= 0.0 && eps < 1.0)) return fail(NRLSH_E_INVALID_ARG, "eps out of [0, 1)");
+    return NRLSH_OK;
+}
+
+nrlsh_status validate_query(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                            int64_t T, const void *ids, const void *ips)
+{
+    if (!ix) return fail(NRLSH_E_INVALID_ARG, "index is NULL");
+    if (nq < 0) return fail(NRLSH_E_INVALID_ARG, "nq < 0");
+    if (k < 1 || k > NRLSH_MAX_K) return fail(NRLSH_E_INVALID_ARG, "k = %d out of [1, %d]", k, NRLSH_MAX_K);
+    if (T < 1) return fail(NRLSH_E_INVALID_ARG, "probe_budget < 1");
+    if (nq > 0 && (!queries || !ids || !ips)) return fail(NRLSH_E_INVALID_ARG, "NULL query or output pointer");
+    if (nq > (int64_t)INT32_MAX) return fail(NRLSH_E_INVALID_ARG, "nq too large");
+    return NRLSH_OK;
+}
+
+// Runs the query steps on device queries Qd for nq queries.  When cand_out is
+// given, the probed stored positions of each query are copied there (nq x Tq)
+// and the re-rank is skipped.
+void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
+               int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
+               hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+{
+    QueryShape sh;
+    sh.n = ix->n;
+    sh.d = ix->d;
+    sh.dp = ix->dp;
+    sh.m = ix->m;
+    sh.L = ix->L;
+    sh.W = ix->W;
+    sh.Tq = std::min<int64_t>(T, ix->n);
+    sh.k = k;
+    // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^28 entries
+    int64_t B = (int64_t(1) << 28) / sh.Tq;
+    B = std::max<int64_t>(64, B / 64 * 64);
+    B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
+    const int64_t tiles = B / 64;
+    const int L1 = sh.L + 1;
+    DBuf<uint32_t> qcodes(qcodes_out_d ? 1 : (size_t)B * sh.W, s);
+    DBuf<uint32_t> ghist((size_t)tiles * sh.m * L1 * 64, s);
+    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s);
+    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
+    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
+    DBuf<int32_t> cand(cand_out_d ? 1 : (size_t)B * sh.Tq, s);
+    for (int64_t b0 = 0; b0 < nq; b0 += B) {
+        const int64_t nb = std::min<int64_t>(B, nq - b0);
+        const float *Qb = Qd + b0 * sh.d;
+        uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.W : qcodes.get();
+        int32_t *cb = cand_out_d ? cand_out_d + b0 * sh.Tq : cand.get();
+        tm.begin("qhash");
+        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qc, nonfinite_d, s));
+        tm.end();
+        tm.begin("scan_hist");
+        HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
+        tm.end();
+        tm.begin("threshold");
+        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
+                              ghthr.get(), gtie.get(), s));
+        tm.end();
+        tm.begin("scan_emit");
+        HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
+                              ghthr.get(), gtie.get(), cb, s));
+        tm.end();
+        if (cand_out_d) continue;
+        tm.begin("rerank");
+        HIPX(launch_rerank(ix->Xp.get(), ix->perm.get(), Qb, nb, sh, cb, ids_d + b0 * k,
+                           ips_d + b0 * k, s));
+        tm.end();
+    }
+}
+
+template <typename F>
+nrlsh_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const Failure &e) {
+        return fail(e.st, "%s", e.msg.c_str());
+    } catch (const std::bad_alloc &) {
+        return fail(NRLSH_E_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(NRLSH_E_INTERNAL, "unexpected exception");
+    }
+}
+
+}  // namespace
+
+// ================================================================= C ABI
+extern "C" {
+
+nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
+                            uint64_t seed, const nrlsh_build_opts *opts, nrlsh_index **out)
+{
+    const double eps = opts ? opts->eps : 0.0;
+    nrlsh_status st = validate_build(items, n, d, m, L, eps, out);
+    if (st != NRLSH_OK) return st;
+    const bool on_device = opts && opts->device_ptrs;
+    return guarded([&]() -> nrlsh_status {
+        const int dev = current_device();
+        prepare_pool(dev);
+        hipStream_t s = pick_stream(opts ? opts->stream : nullptr, dev);
+        nrlsh_index *ix = new nrlsh_index();
+        ix->device = dev;
+        ix->n = n;
+        ix->d = d;
+        ix->dp = (d + 7) / 8 * 8;
+        ix->m = m;
+        ix->L = L;
+        ix->W = L > 32 ? 2 : 1;
+        ix->seed = seed;
+        ix->eps = eps;
+        ix->home = library_stream(dev);
+        Timer tm(s);
+        try {
+            build_index(ix, items, on_device, s, tm);
+            tm.settle();
+        } catch (...) {
+            delete ix;
+            (void)hipStreamSynchronize(s);
+            throw;
+        }
+        *out = ix;
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_build(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
+                         uint64_t seed, nrlsh_index **out)
+{
+    return nrlsh_build_ex(items, n, d, m, L, seed, nullptr, out);
+}
+
+void nrlsh_free(nrlsh_index *ix)
+{
+    if (!ix) return;
+    hipStream_t s = ix->home;
+    delete ix;  // buffers are released on their home stream
+    (void)hipStreamSynchronize(s);
+}
+
+nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                            int64_t probe_budget, const nrlsh_query_opts *opts, int64_t *out_ids,
+                            float *out_ips)
+{
+    nrlsh_status st = validate_query(ix, queries, nq, k, probe_budget, out_ids, out_ips);
+    if (st != NRLSH_OK || nq == 0) return st;
+    const bool on_device = opts && opts->device_ptrs;
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        hipStream_t s = pick_stream(opts ? opts->stream : nullptr, ix->device);
+        Timer tm(s);
+        DBuf<uint32_t> flag(1, s);
+        HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        if (on_device) {
+            run_query(ix, queries, nq, k, probe_budget, out_ids, out_ips, nullptr, nullptr, s, tm,
+                      flag.get());
+        } else {
+            DBuf<float> Qd((size_t)nq * ix->d, s);
+            DBuf<int64_t> ids((size_t)nq * k, s);
+            DBuf<float> ips((size_t)nq * k, s);
+            HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
+                                hipMemcpyHostToDevice, s));
+            run_query(ix, Qd.get(), nq, k, probe_budget, ids.get(), ips.get(), nullptr, nullptr, s,
+                      tm, flag.get());
+            HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
+                                hipMemcpyDeviceToHost, s));
+            HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),
+                                hipMemcpyDeviceToHost, s));
+        }
+        uint32_t bad = 0;
+        HIPX(hipMemcpyAsync(&bad, flag.get(), sizeof bad, hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        tm.settle();
+        if (bad) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                         int64_t probe_budget, int64_t *out_ids, float *out_ips)
+{
+    return nrlsh_query_ex(ix, queries, nq, k, probe_budget, nullptr, out_ids, out_ips);
+}
+
+const char *nrlsh_last_error(void) { return g_err.c_str(); }
+
+nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int32_t *m,
+                              int32_t *L, int32_t *dp)
+{
+    if (!ix || !n || !d || !m || !L || !dp) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    *n = ix->n;
+    *d = ix->d;
+    *m = ix->m;
+    *L = ix->L;
+    *dp = ix->dp;
+    return NRLSH_OK;
+}
+
+nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A)
+{
+    if (!ix || !A) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    std::memcpy(A, ix->A_h.data(), ix->A_h.size() * sizeof(float));
+    return NRLSH_OK;
+}
+
+nrlsh_status nrlsh_get_keys(const nrlsh_index *ix, double *key)
+{
+    if (!ix || !key) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        HIPX(hipMemcpy(key, ix->key.get(), (size_t)ix->n * sizeof(double), hipMemcpyDeviceToHost));
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_get_partition(const nrlsh_index *ix, int32_t *sid, double *keymax, double *U)
+{
+    if (!ix || !sid || !keymax || !U) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        HIPX(hipMemcpy(sid, ix->sid.get(), (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::memcpy(keymax, ix->keymax_h.data(), ix->m * sizeof(double));
+        std::memcpy(U, ix->U_h.data(), ix->m * sizeof(double));
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_get_layout(const nrlsh_index *ix, int32_t *perm, int64_t *off)
+{
+    if (!ix || !perm || !off) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        HIPX(hipMemcpy(perm, ix->perm.get(), (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        std::memcpy(off, ix->off_h.data(), (ix->m + 1) * sizeof(int64_t));
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes)
+{
+    if (!ix || !codes) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        std::vector<uint32_t> w((size_t)ix->n * ix->W);
+        HIPX(hipMemcpy(w.data(), ix->codes_o.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < ix->n; ++i) {
+            uint64_t c = w[(size_t)i * ix->W];
+            if (ix->W == 2) c |= (uint64_t)w[(size_t)i * 2 + 1] << 32;
+            codes[i] = c;
+        }
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_get_rank_table(const nrlsh_index *ix, int32_t *R)
+{
+    if (!ix || !R) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    std::memcpy(R, ix->R_h.data(), ix->R_h.size() * sizeof(int32_t));
+    return NRLSH_OK;
+}
+
+nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st)
+{
+    if (!ix || !st) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    *st = ix->stats;
+    return NRLSH_OK;
+}
+
+nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,
+                               uint64_t *codes)
+{
+    if (!ix || (nq > 0 && (!queries || !codes)) || nq < 0)
+        return fail(NRLSH_E_INVALID_ARG, "bad argument");
+    if (nq == 0) return NRLSH_OK;
+    if (!all_finite(queries, nq * (int64_t)ix->d)) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        hipStream_t s = library_stream(ix->device);
+        DBuf<float> Qd((size_t)nq * ix->d, s);
+        DBuf<uint32_t> qc((size_t)nq * ix->W, s);
+        DBuf<uint32_t> flag(1, s);
+        HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));
+        HIPX(launch_query_hash(Qd.get(), nq, ix->d, ix->At.get(), ix->L, ix->W, qc.get(), flag.get(), s));
+        std::vector<uint32_t> w((size_t)nq * ix->W);
+        HIPX(hipMemcpyAsync(w.data(), qc.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        for (int64_t i = 0; i < nq; ++i) {
+            uint64_t c = w[(size_t)i * ix->W];
+            if (ix->W == 2) c |= (uint64_t)w[(size_t)i * 2 + 1] << 32;
+            codes[i] = c;
+        }
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                    int64_t probe_budget, int64_t *cand)
+{
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !cand)) || probe_budget < 1)
+        return fail(NRLSH_E_INVALID_ARG, "bad argument");
+    if (nq == 0) return NRLSH_OK;
+    if (!all_finite(queries, nq * (int64_t)ix->d)) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        hipStream_t s = library_stream(ix->device);
+        const int64_t Tq = std::min<int64_t>(probe_budget, ix->n);
+        Timer tm(s);
+        DBuf<float> Qd((size_t)nq * ix->d, s);
+        DBuf<int32_t> cd((size_t)nq * Tq, s);
+        DBuf<uint32_t> qc((size_t)nq * ix->W, s);
+        DBuf<uint32_t> flag(1, s);
+        HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));
+        run_query(ix, Qd.get(), nq, 1, probe_budget, nullptr, nullptr, cd.get(), qc.get(), s, tm, flag.get());
+        std::vector<int32_t> pos((size_t)nq * Tq), perm(ix->n);
+        HIPX(hipMemcpyAsync(pos.data(), cd.get(), pos.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(perm.data(), ix->perm.get(), perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        for (size_t e = 0; e < pos.size(); ++e) {
+            if (pos[e] < 0 || pos[e] >= ix->n) throw Failure{NRLSH_E_INTERNAL, "probed position out of range"};
+            cand[e] = perm[pos[e]];
+        }
+        return NRLSH_OK;
+    });
+}
+
+void nrlsh_profile_enable(int32_t on) { g_prof_on.store(on ? 1 : 0); }
+
+void nrlsh_profile_reset(void)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    g_prof.clear();
+}
+
+nrlsh_status nrlsh_profile_get(const char *name, double *total_ms, int64_t *launches)
+{
+    if (!name || !total_ms || !launches) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    auto it = g_prof.find(name);
+    *total_ms = it == g_prof.end() ? 0.0 : it->second.ms;
+    *launches = it == g_prof.end() ? 0 : it->second.launches;
+    return NRLSH_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,526 @@
+// Index-build kernels of norm-ranging LSH (Algorithm 1) for gfx950.
+//
+//   keys_copy   squared 2-norms (FP64, ascending coordinate order) and the
+//               zero-padded item copy                     [Algorithm 1, ranking]
+//   radix sort  stable LSD sort of (key bits, index)      [Algorithm 1, ranking]
+//   assign      sub-dataset by norm percentile, U_j        [Algorithm 1, partition]
+//   hash        SimpleLSH transform (Eq. 8) + sign random projection (Eq. 4)
+//               on the FP32 matrix cores, sign packing, uncertainty band
+//   hash_fixup  FP64 recompute of in-band projections as the definition
+#include "nrlsh_internal.h"
+
+namespace nrlsh {
+namespace {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
+
+// ---------------------------------------------------------------- keys_copy
+// One wave owns 64 consecutive rows.  Columns are streamed 32 at a time:
+// each load instruction covers two rows x 128 contiguous bytes, the chunk is
+// transposed through LDS, and lane r then adds the squares of row r in
+// ascending column order.  Squares of FP32 values are exact in FP64, so the
+// sum is bit-identical to a sequential FP64 loop.
+constexpr int KC_ROWS = 64;
+
+__global__ __launch_bounds__(256) void k_keys_copy(const float *__restrict__ X, int64_t n, int d,
+                                                   int dp, float *__restrict__ Xp,
+                                                   double *__restrict__ key,
+                                                   uint64_t *__restrict__ skey,
+                                                   int32_t *__restrict__ sval,
+                                                   BuildCounters *__restrict__ ctr)
+{
+    __shared__ float tile[4][KC_ROWS][33];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * KC_ROWS;
+    const int half = lane >> 5, col = lane & 31;
+    double acc = 0.0;
+    bool bad = false;
+    for (int c0 = 0; c0 < dp; c0 += 32) {
+#pragma unroll 8
+        for (int it = 0; it < 32; ++it) {
+            const int r = 2 * it + half;
+            const int64_t row = row0 + r;
+            const int c = c0 + col;
+            float v = 0.0f;
+            if (row < n) {
+                if (c < d) {
+                    v = X[row * d + c];
+                    bad |= !__builtin_isfinite(v);
+                }
+                if (c < dp) Xp[row * dp + c] = v;
+            }
+            tile[wave][r][col] = v;
+        }
+        __syncthreads();
+        const int cend = min(32, d - c0);
+        for (int t = 0; t < cend; ++t) {
+            const double x = (double)tile[wave][lane][t];
+            acc = acc + x * x;
+        }
+        __syncthreads();
+    }
+    const int64_t myrow = row0 + lane;
+    if (myrow < n) {
+        key[myrow] = acc;
+        skey[myrow] = (uint64_t)__double_as_longlong(acc);
+        sval[myrow] = (int32_t)myrow;
+    }
+    if (__ballot(bad) != 0ull && lane == 0) atomicOr(&ctr->nonfinite, 1u);
+}
+
+// ---------------------------------------------------------------- radix sort
+constexpr int RS_THREADS = 256;
+constexpr int RS_ITEMS = 16;
+constexpr int RS_TILE = RS_THREADS * RS_ITEMS;
+
+__global__ __launch_bounds__(RS_THREADS) void k_rs_hist(const uint64_t *__restrict__ keys,
+                                                        int64_t n, int shift,
+                                                        uint32_t *__restrict__ bhist, int nblocks)
+{
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * RS_TILE;
+#pragma unroll 4
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t e = base + it * RS_THREADS + threadIdx.x;
+        if (e < n) atomicAdd(&h[(keys[e] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    bhist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+__device__ __forceinline__ uint32_t block_incl_scan_256(uint32_t v, uint32_t *s)
+{
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+        const uint32_t t = threadIdx.x >= (unsigned)off ? s[threadIdx.x - off] : 0u;
+        __syncthreads();
+        s[threadIdx.x] += t;
+        __syncthreads();
+    }
+    return s[threadIdx.x];
+}
+
+// One block per digit: exclusive scan of that digit's per-block counts.
+__global__ __launch_bounds__(256) void k_rs_scan(uint32_t *__restrict__ bhist, int nblocks,
+                                                 uint32_t *__restrict__ totals)
+{
+    __shared__ uint32_t s[256];
+    uint32_t *row = bhist + (int64_t)blockIdx.x * nblocks;
+    uint32_t carry = 0;
+    for (int c0 = 0; c0 < nblocks; c0 += 256) {
+        const int i = c0 + threadIdx.x;
+        const uint32_t v = i < nblocks ? row[i] : 0u;
+        const uint32_t incl = block_incl_scan_256(v, s);  // s[] still holds the scan
+        if (i < nblocks) row[i] = carry + incl - v;
+        carry += s[255];  // total of this chunk
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) totals[blockIdx.x] = carry;
+}
+
+// Stable scatter of one 8-bit digit.  Each block walks its tile in order,
+// 256 keys per round; ranks inside a wave come from ballot matching, ranks
+// across the 4 waves from per-wave digit counts in LDS.
+__global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
+    const uint64_t *__restrict__ kin, const int32_t *__restrict__ vin, int64_t n, int shift,
+    const uint32_t *__restrict__ bhist, int nblocks, const uint32_t *__restrict__ totals,
+    uint64_t *__restrict__ kout, int32_t *__restrict__ vout)
+{
+    __shared__ uint32_t sbuf[256];
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t woff[4][256];
+    const int t = threadIdx.x, wave = t >> 6, lane = t & 63;
+    const uint32_t tot = totals[t];
+    const uint32_t incl = block_incl_scan_256(tot, sbuf);
+    base[t] = incl - tot + bhist[(int64_t)t * nblocks + blockIdx.x];
+#pragma unroll
+    for (int w = 0; w < 4; ++w) wcnt[w][t] = 0u;
+    __syncthreads();
+    const int64_t tile = (int64_t)blockIdx.x * RS_TILE;
+    for (int it = 0; it < RS_ITEMS; ++it) {
+        const int64_t e = tile + it * RS_THREADS + t;
+        const bool valid = e < n;
+        uint64_t k = 0;
+        int32_t v = 0;
+        if (valid) {
+            k = kin[e];
+            v = vin[e];
+        }
+        const uint32_t dg = (uint32_t)(k >> shift) & 255u;
+        uint64_t match = __ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            const uint64_t bal = __ballot((dg >> b) & 1u);
+            match &= ((dg >> b) & 1u) ? bal : ~bal;
+        }
+        const uint32_t rank = (uint32_t)__popcll(match & lanemask_lt(lane));
+        const bool last = valid && ((match >> lane) >> 1) == 0ull;
+        if (last) wcnt[wave][dg] = (uint32_t)__popcll(match);
+        __syncthreads();
+        {
+            uint32_t run = base[t];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                woff[w][t] = run;
+                run += wcnt[w][t];
+                wcnt[w][t] = 0u;
+            }
+            base[t] = run;
+        }
+        __syncthreads();
+        if (valid) {
+            const uint32_t pos = woff[wave][dg] + rank;
+            kout[pos] = k;
+            vout[pos] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- partition
+__global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ skey,
+                                                const int32_t *__restrict__ sidx, int64_t n, int m,
+                                                int32_t *__restrict__ sid,
+                                                uint64_t *__restrict__ lkey,
+                                                int32_t *__restrict__ lval,
+                                                double *__restrict__ keymax)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const int32_t i = sidx[r];
+    const int64_t s = (r * (int64_t)m) / n;
+    sid[i] = (int32_t)s;
+    lkey[i] = (uint64_t)s;
+    lval[r] = (int32_t)r;
+    // the last rank of each sub-dataset holds its largest key
+    if (r == n - 1 || ((r + 1) * (int64_t)m) / n != s) keymax[s] = __longlong_as_double((long long)skey[r]);
+}
+
+__global__ __launch_bounds__(256) void k_invert(const int32_t *__restrict__ perm, int64_t n,
+                                                int32_t *__restrict__ pos)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p < n) pos[perm[p]] = (int32_t)p;
+}
+
+// ---------------------------------------------------------------- hash
+// Items are the rows (M), hash bits the columns (N), coordinates the
+// reduction (K) of v_mfma_f32_16x16x4_f32.  Each wave owns 64 items (4 row
+// blocks of 16) and all L bits (CB column blocks of 16).  Per 16 coordinates
+// a lane loads one float4 of a row (4 lanes cover 64 contiguous bytes of a
+// row) and one float4 of a projection row from LDS, and issues 4 MFMAs per
+// (row block, column block): in MFMA j, lane group g contributes coordinate
+// 16 kk + 4 g + j for both operands, which is a permutation of the reduction
+// and leaves the product unchanged.
+//
+// Epilogue (scaled SimpleLSH transform, Eq. 8): with s_i = sqrt(keymax_j -
+// key_i), U_j a^T P(x_i / U_j) = a[:d]^T x_i + a_d s_i, whose sign is the
+// hash bit (U_j > 0).  The FP32 result is trusted only outside the band
+// |p| <= tau_r U_j, tau_r = 2 gamma_{d+3} ||a_r||, which bounds the rounding
+// error of any summation order; in-band bits and sub-datasets with U_j
+// outside [2^-60, 2^60] are recomputed in FP64 by k_hash_fixup.
+constexpr int H_WAVES = 8;
+constexpr int H_KC = 128;
+constexpr int H_KS = H_KC + 4;
+
+template <int CB>
+__global__ __launch_bounds__(H_WAVES * 64) void k_hash(
+    const float *__restrict__ Xp, int64_t n, int d, int dp, const float *__restrict__ A, int L,
+    const double *__restrict__ key, const int32_t *__restrict__ sid,
+    const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ tau,
+    uint32_t *__restrict__ codes_o, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr)
+{
+    constexpr int NB = 16 * CB;
+    __shared__ float As[NB * H_KS];
+    __shared__ float sq_s[H_WAVES][64];
+    __shared__ float uf_s[H_WAVES][64];
+    __shared__ int sp_s[H_WAVES][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = ((int64_t)blockIdx.x * H_WAVES + wave) * 64;
+    {
+        const int64_t i = i0 + lane;
+        float sq = 0.f, uf = 0.f;
+        int sp = 1;
+        if (i < n) {
+            const int s = sid[i];
+            const double km = keymax[s], u = U[s];
+            sq = sqrtf((float)(km - key[i]));
+            uf = (float)u;
+            sp = !(u >= 0x1p-60 && u <= 0x1p60);
+        }
+        sq_s[wave][lane] = sq;
+        uf_s[wave][lane] = uf;
+        sp_s[wave][lane] = sp;
+    }
+    floatx4 acc[4][CB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int r16 = lane & 15, g = lane >> 4;
+    for (int kc0 = 0; kc0 < dp; kc0 += H_KC) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * H_KC; e += H_WAVES * 64) {
+            const int r = e / H_KC, c = e - (e / H_KC) * H_KC, k = kc0 + c;
+            As[r * H_KS + c] = (r < L && k < d) ? A[(int64_t)r * (d + 1) + k] : 0.f;
+        }
+        __syncthreads();
+        const int kend = min(H_KC, dp - kc0);
+        for (int kk = 0; kk < kend; kk += 16) {
+            const int k = kc0 + kk + 4 * g;
+            floatx4 xa[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int64_t row = i0 + 16 * rb + r16;
+                xa[rb] = (row < n && k < dp)
+                             ? *reinterpret_cast<const floatx4 *>(Xp + row * dp + k)
+                             : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+            floatx4 bq[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb)
+                bq[cb] = *reinterpret_cast<const floatx4 *>(&As[(16 * cb + r16) * H_KS + kk + 4 * g]);
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[rb][j], bq[cb][j],
+                                                                           acc[rb][cb], 0, 0, 0);
+        }
+    }
+
+    // lane l assembles the code of item i0 + l (row l = 16 rb + 4 g + v)
+    const int my_rb = lane >> 4, my_g = (lane >> 2) & 3, my_v = lane & 3;
+    uint64_t mycode = 0, myfix = 0;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int r = 16 * cb + r16;
+        const float alast = (r < L) ? A[(int64_t)r * (d + 1) + d] : 0.f;
+        const float tr = (r < L) ? tau[r] : 0.f;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rb + 4 * g + v;
+                const float p = acc[rb][cb][v] + alast * sq_s[wave][row];
+                const bool inb = (r < L) && (i0 + row < n);
+                const bool flag = inb && (sp_s[wave][row] != 0 || fabsf(p) <= tr * uf_s[wave][row]);
+                const bool bit = inb && (p > 0.f);
+                const uint64_t bb = __ballot(bit);
+                const uint64_t fb = __ballot(flag);
+                if (rb == my_rb && v == my_v) {
+                    mycode |= ((bb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                    myfix |= ((fb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                }
+            }
+        }
+    }
+    const int64_t i = i0 + lane;
+    const bool valid = i < n;
+    if (valid) {
+        if (CB <= 2) {
+            codes_o[i] = (uint32_t)mycode;
+        } else {
+            codes_o[2 * i] = (uint32_t)mycode;
+            codes_o[2 * i + 1] = (uint32_t)(mycode >> 32);
+        }
+    }
+    const bool has = valid && myfix != 0ull;
+    const uint64_t hb = __ballot(has);
+    if (hb != 0ull) {
+        const int leader = __ffsll((long long)hb) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctr->fix_count, (uint32_t)__popcll(hb));
+        base = __shfl(base, leader, 64);
+        if (has) {
+            const uint32_t slot = base + (uint32_t)__popcll(hb & lanemask_lt(lane));
+            FixEntry fe;
+            fe.mask = myfix;
+            fe.item = (int32_t)i;
+            fe.pad = 0;
+            fix[slot] = fe;
+        }
+    }
+}
+
+// One thread per list entry: recompute every flagged bit in FP64 exactly as
+// the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
+// when U_j = 0; sum over coordinates in ascending order, no contraction).
+__global__ __launch_bounds__(256) void k_hash_fixup(
+    const float *__restrict__ Xp, int d, int dp, const float *__restrict__ A, int L,
+    const double *__restrict__ key, const int32_t *__restrict__ sid,
+    const double *__restrict__ keymax, const double *__restrict__ U,
+    const FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr,
+    uint32_t *__restrict__ codes_o, int W)
+{
+    const uint32_t cnt = ctr->fix_count;
+    unsigned long long nbits = 0, nflip = 0;
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
+        const FixEntry fe = fix[e];
+        const int64_t i = fe.item;
+        const int s = sid[i];
+        const double u = U[s], km = keymax[s], kk = key[i];
+        uint64_t code = codes_o[W * i];
+        if (W == 2) code |= (uint64_t)codes_o[W * i + 1] << 32;
+        double vd = 1.0;
+        if (u != 0.0) {
+            double t = 1.0 - kk / km;
+            if (t < 0.0) t = 0.0;
+            vd = __builtin_sqrt(t);
+        }
+        const float *x = Xp + i * dp;
+        uint64_t mask = fe.mask;
+        while (mask != 0ull) {
+            const int r = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            const float *a = A + (int64_t)r * (d + 1);
+            double sacc = 0.0;
+            if (u == 0.0) {
+                for (int c = 0; c < d; ++c) sacc = sacc + (double)a[c] * 0.0;
+            } else {
+                for (int c = 0; c < d; ++c) sacc = sacc + (double)a[c] * ((double)x[c] / u);
+            }
+            sacc = sacc + (double)a[d] * vd;
+            const uint64_t bit = sacc > 0.0 ? 1ull : 0ull;
+            nflip += ((code >> r) & 1ull) != bit;
+            ++nbits;
+            code = (code & ~(1ull << r)) | (bit << r);
+        }
+        codes_o[W * i] = (uint32_t)code;
+        if (W == 2) codes_o[W * i + 1] = (uint32_t)(code >> 32);
+    }
+    if (nbits) {
+        atomicAdd(&ctr->fix_bits, nbits);
+        atomicAdd(&ctr->fix_flips, nflip);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_permute_codes(const uint32_t *__restrict__ codes_o,
+                                                       const int32_t *__restrict__ perm, int64_t n,
+                                                       int W, uint32_t *__restrict__ codes_l)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n) return;
+    const int64_t i = perm[p];
+    codes_l[W * p] = codes_o[W * i];
+    if (W == 2) codes_l[W * p + 1] = codes_o[W * i + 1];
+}
+
+inline unsigned grid_for(int64_t n, int per_block)
+{
+    return (unsigned)((n + per_block - 1) / per_block);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- launchers
+hipError_t launch_keys_copy(const float *X, int64_t n, int d, int dp, float *Xp, double *key,
+                            uint64_t *sort_key, int32_t *sort_val, BuildCounters *ctr,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_keys_copy, dim3(grid_for(n, 4 * KC_ROWS)), dim3(256), 0, s, X, n, d, dp,
+                       Xp, key, sort_key, sort_val, ctr);
+    return hipGetLastError();
+}
+
+size_t radix_sort_tmp_bytes(int64_t n)
+{
+    const int64_t nb = (n + RS_TILE - 1) / RS_TILE;
+    return (size_t)(256 * nb + 256) * sizeof(uint32_t);
+}
+
+hipError_t radix_sort(uint64_t *ka, int32_t *va, uint64_t *kb, int32_t *vb, int64_t n, int nbits,
+                      void *tmp, bool *result_in_b, hipStream_t s)
+{
+    const int nb = (int)((n + RS_TILE - 1) / RS_TILE);
+    uint32_t *bhist = static_cast<uint32_t *>(tmp);
+    uint32_t *totals = bhist + (int64_t)256 * nb;
+    bool in_b = false;
+    for (int shift = 0; shift < nbits; shift += 8) {
+        const uint64_t *ki = in_b ? kb : ka;
+        const int32_t *vi = in_b ? vb : va;
+        uint64_t *ko = in_b ? ka : kb;
+        int32_t *vo = in_b ? va : vb;
+        hipLaunchKernelGGL(k_rs_hist, dim3(nb), dim3(RS_THREADS), 0, s, ki, n, shift, bhist, nb);
+        hipLaunchKernelGGL(k_rs_scan, dim3(256), dim3(256), 0, s, bhist, nb, totals);
+        hipLaunchKernelGGL(k_rs_scatter, dim3(nb), dim3(RS_THREADS), 0, s, ki, vi, n, shift, bhist,
+                           nb, totals, ko, vo);
+        in_b = !in_b;
+    }
+    *result_in_b = in_b;
+    return hipGetLastError();
+}
+
+hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sorted_idx, int64_t n,
+                                 int m, int32_t *sid, uint64_t *layout_key, int32_t *layout_val,
+                                 double *keymax, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_assign, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted_key, sorted_idx,
+                       n, m, sid, layout_key, layout_val, keymax);
+    return hipGetLastError();
+}
+
+hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *pos, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, s, perm, n, pos);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash(const float *Xp, int64_t n, int d, int dp, const float *A, int L,
+                       const double *key, const int32_t *sid, const double *keymax,
+                       const double *U, const float *tau, uint32_t *codes_o, FixEntry *fix,
+                       BuildCounters *ctr, hipStream_t s)
+{
+    const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
+    switch ((L + 15) / 16) {
+    case 1:
+        hipLaunchKernelGGL(k_hash<1>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
+                           tau, codes_o, fix, ctr);
+        break;
+    case 2:
+        hipLaunchKernelGGL(k_hash<2>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
+                           tau, codes_o, fix, ctr);
+        break;
+    case 3:
+        hipLaunchKernelGGL(k_hash<3>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
+                           tau, codes_o, fix, ctr);
+        break;
+    default:
+        hipLaunchKernelGGL(k_hash<4>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
+                           tau, codes_o, fix, ctr);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_fixup(const float *Xp, int d, int dp, const float *A, int L,
+                             const double *key, const int32_t *sid, const double *keymax,
+                             const double *U, const FixEntry *fix, BuildCounters *ctr,
+                             uint32_t *codes_o, int64_t max_entries, hipStream_t s)
+{
+    const int W = L > 32 ? 2 : 1;
+    int64_t blocks = (max_entries + 255) / 256;
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xp, d, dp, A, L, key,
+                       sid, keymax, U, fix, ctr, codes_o, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_permute_codes(const uint32_t *codes_o, const int32_t *perm, int64_t n, int W,
+                                uint32_t *codes_l, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_permute_codes, dim3(grid_for(n, 256)), dim3(256), 0, s, codes_o, perm, n,
+                       W, codes_l);
+    return hipGetLastError();
+}
+
+}  // namespace nrlsh

@@ -1,0 +1,102 @@
+// Internal declarations of libnrlsh: launch wrappers implemented in the
+// kernel translation units and called by the host orchestration (api.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace nrlsh {
+
+constexpr int kWave = 64;
+
+// Entry of the list of items whose hash needs an FP64 recompute: `mask` has
+// bit r set when projection r fell inside the FP32 uncertainty band.
+struct FixEntry {
+    uint64_t mask;
+    int32_t item;
+    int32_t pad;
+};
+
+// Build-side counters kept on the device (one struct per build).
+struct BuildCounters {
+    uint32_t nonfinite;      // items holding NaN / Inf
+    uint32_t fix_count;      // entries appended to the FixEntry list
+    unsigned long long fix_bits;
+    unsigned long long fix_flips;
+};
+
+// ------------------------------------------------------------------ build
+// Squared norms in FP64 (ascending coordinate order) plus a zero-padded copy
+// of the items with row stride dp; also emits (key bits, index) pairs for the
+// radix sort and flags non-finite values.
+hipError_t launch_keys_copy(const float *X, int64_t n, int d, int dp, float *Xp, double *key,
+                            uint64_t *sort_key, int32_t *sort_val, BuildCounters *ctr,
+                            hipStream_t s);
+
+// Stable LSD radix sort of (uint64 key, int32 value) pairs on bits
+// [0, nbits).  Buffers a/b are ping-pong; returns in *result_in_b whether the
+// sorted data ended in the b buffers.  `tmp` must hold
+// radix_sort_tmp_bytes(n) bytes.
+size_t radix_sort_tmp_bytes(int64_t n);
+hipError_t radix_sort(uint64_t *ka, int32_t *va, uint64_t *kb, int32_t *vb, int64_t n, int nbits,
+                      void *tmp, bool *result_in_b, hipStream_t s);
+
+// Sub-dataset of every item from its rank (s = floor(rank m / n)), the
+// largest key of each sub-dataset, and (sid, index) pairs for the layout sort.
+hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sorted_idx, int64_t n,
+                                 int m, int32_t *sid, uint64_t *layout_key, int32_t *layout_val,
+                                 double *keymax, hipStream_t s);
+
+// pos[perm[p]] = p
+hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *pos, hipStream_t s);
+
+// SimpleLSH transform + sign random projection on the FP32 matrix cores.
+hipError_t launch_hash(const float *Xp, int64_t n, int d, int dp, const float *A, int L,
+                       const double *key, const int32_t *sid, const double *keymax,
+                       const double *U, const float *tau, uint32_t *codes_o, FixEntry *fix,
+                       BuildCounters *ctr, hipStream_t s);
+
+// FP64 recompute of the flagged projections, exactly as the definition.
+hipError_t launch_hash_fixup(const float *Xp, int d, int dp, const float *A, int L,
+                             const double *key, const int32_t *sid, const double *keymax,
+                             const double *U, const FixEntry *fix, BuildCounters *ctr,
+                             uint32_t *codes_o, int64_t max_entries, hipStream_t s);
+
+// codes_l[p] = codes_o[perm[p]]  (W 32-bit words per code)
+hipError_t launch_permute_codes(const uint32_t *codes_o, const int32_t *perm, int64_t n, int W,
+                                uint32_t *codes_l, hipStream_t s);
+
+// ------------------------------------------------------------------ query
+struct QueryShape {
+    int64_t n;
+    int d, dp, m, L, W;
+    int64_t Tq;      // probed items per query, min(T, n)
+    int k;
+};
+
+// Query codes (FP64 exact sign of A[:, :d] q); flags non-finite queries.
+hipError_t launch_query_hash(const float *Q, int64_t nq, int d, const float *At, int L, int W,
+                             uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s);
+
+// Pass 1: per query tile and sub-dataset, histogram of Hamming distance.
+hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                            int64_t nq, const QueryShape &sh, uint32_t *ghist, hipStream_t s);
+
+// Threshold bucket, tie cut and per-sub-dataset emission bounds and offsets.
+hipError_t launch_threshold(const uint32_t *ghist, const int32_t *R, const int32_t *inv, int64_t nq,
+                            const QueryShape &sh, int32_t *gbase, int32_t *ghthr, int32_t *gtie,
+                            hipStream_t s);
+
+// Pass 2: emit the probed items (stored positions) of every query.
+hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                            int64_t nq, const QueryShape &sh, const int32_t *gbase,
+                            const int32_t *ghthr, const int32_t *gtie, int32_t *cand,
+                            hipStream_t s);
+
+// Exact FP64 re-rank of the probed items and top-k selection.
+hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
+                         const QueryShape &sh, const int32_t *cand, int64_t *out_ids,
+                         float *out_ips, hipStream_t s);
+
+}  // namespace nrlsh

@@ -1,0 +1,166 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 CPU oracle,
+step by step, on seeded inputs spanning several tiles and ragged tails, plus
+the degenerate cases of the method."""
+import numpy as np
+import pytest
+
+import oracle.oracle as orc
+import paper_1809_08782_amd as nr
+from parity_util import check_build, check_query, say
+from workloads import make_items, make_queries, tiny
+
+pytestmark = pytest.mark.gpu
+
+# (n, d, m, L, nq, k, T): tiles of 64 rows / 16 hash bits / 32 coordinates,
+# with ragged tails in every dimension; m = 1 (SimpleLSH), m = n, n = 1, d = 1
+SHAPES = [
+    (1000, 16, 4, 16, 70, 10, 100),
+    (3001, 33, 7, 31, 65, 10, 257),
+    (4097, 64, 8, 32, 130, 7, 1000),
+    (2500, 130, 16, 33, 64, 10, 300),
+    (5000, 75, 13, 64, 100, 100, 700),
+    (777, 8, 1, 17, 33, 5, 50),
+    (64, 5, 64, 8, 10, 3, 20),
+    (1, 3, 1, 5, 4, 2, 1),
+    (300, 1, 3, 12, 20, 4, 30),
+    (2049, 300, 32, 32, 65, 10, 200),
+    (999, 150, 9, 1, 40, 10, 99),
+    (1500, 40, 6, 63, 40, 64, 1500),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "n%d_d%d_m%d_L%d" % s[:4])
+def test_parity_shapes(shape):
+    n, d, m, L, nq, k, T = shape
+    say(f"case n={n} d={d} m={m} L={L} nq={nq} k={k} T={T}")
+    X = make_items("lognormal", n, d, seed=n + d, sigma=0.9)
+    Q = make_queries(nq, d, seed=n + 7)
+    oix = orc.OracleIndex(X, m, L, seed=1234 + L, threads=8)
+    with nr.nrlsh_build(X, m, L, 1234 + L) as gix:
+        check_build(gix, oix, f"n{n}")
+        check_query(gix, oix, Q, k, T, f"n{n}")
+        # budgets around the edges: smaller than k, exactly n, above n
+        for TT in (1, max(1, k - 1), n, n + 5):
+            ids, _ = nr.nrlsh_query(gix, Q[:8], k, TT)
+            oids, _ = oix.query(Q[:8], k, TT)
+            assert np.array_equal(ids, oids), f"T={TT}"
+
+
+def test_parity_tiny_config():
+    """The small recipe end to end: n = 1e4, d = 64, m = 8, L = 16, 100 queries,
+    top-10, budget 500."""
+    w = tiny()
+    say("case tiny config")
+    X, Q = w.items(), w.queries()
+    oix = orc.OracleIndex(X, w.m, w.L, seed=w.index_seed, threads=8)
+    with nr.nrlsh_build(X, w.m, w.L, w.index_seed) as gix:
+        check_build(gix, oix, "tiny")
+        check_query(gix, oix, Q, w.k, w.budgets[0], "tiny")
+
+
+def test_edge_duplicates_zero_rows_zero_query():
+    say("case duplicates / zero rows / zero query")
+    n, d = 1200, 24
+    X = make_items("lognormal", n, d, seed=5, sigma=0.7)
+    X[100:400] = 0.0            # all-zero rows: the lowest sub-datasets get U_j = 0
+    X[500:520] = X[600]         # duplicate rows (equal keys, ties broken by index)
+    X[700] = X[701] = X[702] = X[900]
+    Q = make_queries(20, d, seed=6)
+    Q[3] = 0.0                  # zero query: all-zero code, all inner products 0
+    Q[4] = X[600] / np.linalg.norm(X[600])
+    oix = orc.OracleIndex(X, 10, 32, seed=77, threads=8)
+    assert oix.U[0] == 0.0
+    with nr.nrlsh_build(X, 10, 32, 77) as gix:
+        check_build(gix, oix, "edge")
+        check_query(gix, oix, Q, 10, 150, "edge")
+        check_query(gix, oix, Q, 10, n, "edge-full")
+
+
+def test_edge_extreme_magnitudes():
+    """Sub-datasets with U_j far below 2^-60 or above 2^60 take the FP64 path."""
+    say("case extreme magnitudes")
+    n, d = 900, 12
+    X = make_items("lognormal", n, d, seed=9, sigma=0.5)
+    X[:300] *= np.float32(1e-25)
+    X[600:] *= np.float32(1e25)
+    Q = make_queries(16, d, seed=10)
+    oix = orc.OracleIndex(X, 3, 20, seed=3, threads=8)
+    with nr.nrlsh_build(X, 3, 20, 3) as gix:
+        st = check_build(gix, oix, "extreme")
+        assert st["recomputed_items"] >= 600
+        check_query(gix, oix, Q, 10, 100, "extreme")
+
+
+def test_all_equal_norms():
+    """Equal norms: every sub-dataset has the same U_j (Section 3.2 remark)."""
+    say("case equal norms")
+    rng = np.random.default_rng(3)
+    base = np.array([3, -1, 2, 0, 5, -4, 1, 1], dtype=np.float32)
+    X = np.stack([rng.permutation(base) * rng.choice([-1, 1], size=8) for _ in range(640)])
+    X = X.astype(np.float32)
+    Q = make_queries(12, 8, seed=4)
+    oix = orc.OracleIndex(X, 8, 16, seed=8, threads=8)
+    with nr.nrlsh_build(X, 8, 16, 8) as gix:
+        check_build(gix, oix, "equal")
+        check_query(gix, oix, Q, 10, 64, "equal")
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.25])
+def test_adjusted_metric(eps):
+    """Adjusted similarity metric with eps > 0 (Section 3.3)."""
+    say(f"case eps={eps}")
+    X = make_items("lognormal", 4000, 32, seed=21, sigma=0.8)
+    Q = make_queries(70, 32, seed=22)
+    oix = orc.OracleIndex(X, 8, 16, seed=5, eps=eps, threads=8)
+    with nr.nrlsh_build(X, 8, 16, 5, eps=eps) as gix:
+        check_build(gix, oix, f"eps{eps}")
+        check_query(gix, oix, Q, 10, 400, f"eps{eps}")
+
+
+def test_non_finite_inputs_rejected():
+    say("case non-finite")
+    X = make_items("lognormal", 100, 4, seed=1)
+    X[17, 2] = np.nan
+    with pytest.raises(nr.NrlshError) as e:
+        nr.nrlsh_build(X, 2, 8, 1)
+    assert e.value.status == 2
+    X[17, 2] = 1.0
+    with nr.nrlsh_build(X, 2, 8, 1) as gix:
+        Q = make_queries(3, 4, seed=2)
+        Q[1, 0] = np.inf
+        with pytest.raises(nr.NrlshError) as e:
+            nr.nrlsh_query(gix, Q, 3, 10)
+        assert e.value.status == 2
+
+
+def test_deterministic_and_batch_independent():
+    say("case determinism")
+    X = make_items("lognormal", 6000, 48, seed=31, sigma=1.0)
+    Q = make_queries(300, 48, seed=32)
+    with nr.nrlsh_build(X, 12, 32, 9) as a, nr.nrlsh_build(X, 12, 32, 9) as b:
+        assert np.array_equal(a.codes(), b.codes())
+        i1, p1 = nr.nrlsh_query(a, Q, 10, 600)
+        i2, p2 = nr.nrlsh_query(b, Q, 10, 600)
+        assert np.array_equal(i1, i2) and np.array_equal(p1, p2)
+        parts = [nr.nrlsh_query(a, Q[s:e], 10, 600) for s, e in ((0, 1), (1, 64), (64, 199), (199, 300))]
+        assert np.array_equal(np.concatenate([p[0] for p in parts]), i1)
+        assert np.array_equal(np.concatenate([p[1] for p in parts]), p1)
+
+
+def test_device_pointer_path_matches_host_path():
+    """The _ex entry points on torch device tensors give the host-path results."""
+    import torch
+    say("case device pointers")
+    X = make_items("lognormal", 5000, 64, seed=41, sigma=0.6)
+    Q = make_queries(200, 64, seed=42)
+    with nr.nrlsh_build(X, 8, 32, 11) as h:
+        ih, ph = nr.nrlsh_query(h, Q, 10, 500)
+        hc = h.codes()
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    with nr.nrlsh_build(Xd, 8, 32, 11) as g:
+        assert np.array_equal(g.codes(), hc)
+        idd, ipd = nr.nrlsh_query(g, Qd, 10, 500)
+        torch.cuda.synchronize()
+        assert np.array_equal(idd.cpu().numpy(), ih)
+        assert np.array_equal(ipd.cpu().numpy(), ph)
