@@ -468,8 +468,8 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     sh.W = ix->W;
     sh.Tq = std::min<int64_t>(T, ix->n);
     sh.k = k;
-    // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^28 entries
-    int64_t B = (int64_t(1) << 28) / sh.Tq;
+    // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^29 entries
+    int64_t B = (int64_t(1) << 29) / sh.Tq;
     B = std::max<int64_t>(64, B / 64 * 64);
     B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
     const int64_t tiles = B / 64;
@@ -480,6 +480,9 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
     DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
     DBuf<int32_t> cand(cand_out_d ? 1 : (size_t)B * sh.Tq, s);
+    const int nsplit = rerank_splits(B, sh.Tq);
+    DBuf<double> part_v(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
+    DBuf<int32_t> part_i(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
@@ -501,8 +504,8 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
         tm.end();
         if (cand_out_d) continue;
         tm.begin("rerank");
-        HIPX(launch_rerank(ix->Xp.get(), ix->perm.get(), Qb, nb, sh, cb, ids_d + b0 * k,
-                           ips_d + b0 * k, s));
+        HIPX(launch_rerank(ix->Xp.get(), ix->perm.get(), Qb, nb, sh, cb, nsplit, part_v.get(),
+                           part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
         tm.end();
     }
 }

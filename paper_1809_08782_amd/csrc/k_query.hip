@@ -228,11 +228,13 @@ __global__ __launch_bounds__(64) void k_scan_emit(const uint32_t *__restrict__ c
 }
 
 // ---------------------------------------------------------------- rerank
-// One wave per query.  Candidates are taken 64 at a time (lane = candidate);
-// their rows are streamed in 32-float chunks: each load instruction brings
-// 8 rows x 128 contiguous bytes, the chunk is transposed through LDS and lane
-// c adds q_t x_ct in FP64 in ascending t.  The running top-k (sorted by
-// (ip desc, id asc)) lives in registers, S entries per lane.
+// One wave per (query, slice of its probed list).  Candidates are taken 64
+// at a time (lane = candidate); their rows are streamed in 32-float chunks:
+// each load instruction brings 8 rows x 128 contiguous bytes, the chunk is
+// transposed through LDS and lane c adds q_t x_ct in FP64 in ascending t.
+// The running top-k (sorted by (ip desc, id asc)) lives in registers, S
+// entries per lane.  With several slices per query, each slice writes a
+// partial list and k_topk_merge combines them.
 constexpr int RR_STRIDE = 36;  // floats per LDS row (16-byte aligned, conflict-free b128)
 
 __device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t ib)
@@ -240,34 +242,93 @@ __device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t i
     return a > b || (a == b && ia < ib);
 }
 
+// Sorted top-k list held by one wave: entry e = s*64 + lane.
+template <int S>
+struct WaveTopK {
+    double tv[S];
+    int32_t ti[S];
+    double th_v;
+    int32_t th_i;
+    int ks, kl;
+
+    __device__ void init(int k)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            tv[s] = -INFINITY;
+            ti[s] = INT_MAX;
+        }
+        th_v = -INFINITY;
+        th_i = INT_MAX;
+        ks = (k - 1) >> 6;
+        kl = (k - 1) & 63;
+    }
+
+    // Offer one value per lane (ok = lane has a real candidate).
+    __device__ void offer(double v, int32_t id, bool ok, int lane)
+    {
+        uint64_t mask = __ballot(ok && better(v, id, th_v, th_i));
+        while (mask != 0ull) {
+            const int src = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            const double nv = __shfl(v, src, 64);
+            const int32_t ni = __shfl(id, src, 64);
+            if (!better(nv, ni, th_v, th_i)) continue;
+            int pos = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) pos += __popcll(__ballot(better(tv[s], ti[s], nv, ni)));
+            double nvv[S];
+            int32_t nii[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double up_v = __shfl_up(tv[s], 1, 64);
+                int32_t up_i = __shfl_up(ti[s], 1, 64);
+                const double carry_v = s > 0 ? __shfl(tv[s > 0 ? s - 1 : 0], 63, 64) : -INFINITY;
+                const int32_t carry_i = s > 0 ? __shfl(ti[s > 0 ? s - 1 : 0], 63, 64) : INT_MAX;
+                if (lane == 0) {
+                    up_v = carry_v;
+                    up_i = carry_i;
+                }
+                const int e = s * 64 + lane;
+                nvv[s] = e > pos ? up_v : (e == pos ? nv : tv[s]);
+                nii[s] = e > pos ? up_i : (e == pos ? ni : ti[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tv[s] = nvv[s];
+                ti[s] = nii[s];
+            }
+            th_v = __shfl(tv[ks], kl, 64);
+            th_i = __shfl(ti[ks], kl, 64);
+        }
+    }
+};
+
 template <int S>
 __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
                                                const int32_t *__restrict__ perm,
                                                const float *__restrict__ Q, int64_t n, int d,
                                                int dp, int64_t Tq, int k,
-                                               const int32_t *__restrict__ cand,
-                                               int64_t *__restrict__ out_ids,
-                                               float *__restrict__ out_ips)
+                                               const int32_t *__restrict__ cand, int nsplit,
+                                               int64_t slice, int64_t *__restrict__ out_ids,
+                                               float *__restrict__ out_ips,
+                                               double *__restrict__ part_v,
+                                               int32_t *__restrict__ part_i)
 {
     __shared__ float tile[64 * RR_STRIDE];
     const int lane = threadIdx.x;
     const int64_t q = blockIdx.x;
+    const int split = blockIdx.y;
     const float *qv = Q + q * d;
     const int32_t *cq = cand + q * Tq;
-    double tv[S];
-    int32_t ti[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        tv[s] = -INFINITY;
-        ti[s] = INT_MAX;
-    }
-    const int ks = (k - 1) >> 6, kl = (k - 1) & 63;
-    double th_v = -INFINITY;
-    int32_t th_i = INT_MAX;
+    const int64_t cbeg = (int64_t)split * slice;
+    const int64_t cend = min(Tq, cbeg + slice);
+    WaveTopK<S> top;
+    top.init(k);
     const int sub = lane >> 3, seg = 4 * (lane & 7);
 
-    for (int64_t c0 = 0; c0 < Tq; c0 += 64) {
-        bool valid = c0 + lane < Tq;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
+        bool valid = c0 + lane < cend;
         int32_t id = 0;
         if (valid) {
             const int32_t p = cq[c0 + lane];
@@ -305,49 +366,50 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
             }
             __syncthreads();
         }
-
-        const bool ok = valid && better(acc, id, th_v, th_i);
-        uint64_t mask = __ballot(ok);
-        while (mask != 0ull) {
-            const int src = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            const double nv = __shfl(acc, src, 64);
-            const int32_t ni = __shfl(id, src, 64);
-            if (!better(nv, ni, th_v, th_i)) continue;
-            int pos = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) pos += __popcll(__ballot(better(tv[s], ti[s], nv, ni)));
-            double nvv[S];
-            int32_t nii[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                double up_v = __shfl_up(tv[s], 1, 64);
-                int32_t up_i = __shfl_up(ti[s], 1, 64);
-                const double carry_v = s > 0 ? __shfl(tv[s > 0 ? s - 1 : 0], 63, 64) : -INFINITY;
-                const int32_t carry_i = s > 0 ? __shfl(ti[s > 0 ? s - 1 : 0], 63, 64) : INT_MAX;
-                if (lane == 0) {
-                    up_v = carry_v;
-                    up_i = carry_i;
-                }
-                const int e = s * 64 + lane;
-                nvv[s] = e > pos ? up_v : (e == pos ? nv : tv[s]);
-                nii[s] = e > pos ? up_i : (e == pos ? ni : ti[s]);
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                tv[s] = nvv[s];
-                ti[s] = nii[s];
-            }
-            th_v = __shfl(tv[ks], kl, 64);
-            th_i = __shfl(ti[ks], kl, 64);
-        }
+        top.offer(acc, id, valid, lane);
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int e = s * 64 + lane;
         if (e < k) {
-            out_ids[q * k + e] = ti[s] == INT_MAX ? -1 : (int64_t)ti[s];
-            out_ips[q * k + e] = (float)tv[s];
+            if (nsplit == 1) {
+                out_ids[q * k + e] = top.ti[s] == INT_MAX ? -1 : (int64_t)top.ti[s];
+                out_ips[q * k + e] = (float)top.tv[s];
+            } else {
+                const int64_t o = (q * nsplit + split) * k + e;
+                part_v[o] = top.tv[s];
+                part_i[o] = top.ti[s];
+            }
+        }
+    }
+}
+
+// Merge the nsplit partial top-k lists of each query (one wave per query).
+template <int S>
+__global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ part_v,
+                                                   const int32_t *__restrict__ part_i, int nsplit,
+                                                   int k, int64_t *__restrict__ out_ids,
+                                                   float *__restrict__ out_ips)
+{
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    WaveTopK<S> top;
+    top.init(k);
+    const int64_t total = (int64_t)nsplit * k;
+    const double *pv = part_v + q * total;
+    const int32_t *pi = part_i + q * total;
+    for (int64_t e0 = 0; e0 < total; e0 += 64) {
+        const bool ok = e0 + lane < total && pi[min(e0 + lane, total - 1)] != INT_MAX;
+        const double v = ok ? pv[e0 + lane] : -INFINITY;
+        const int32_t id = ok ? pi[e0 + lane] : INT_MAX;
+        top.offer(v, id, ok, lane);
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int e = s * 64 + lane;
+        if (e < k) {
+            out_ids[q * k + e] = top.ti[s] == INT_MAX ? -1 : (int64_t)top.ti[s];
+            out_ips[q * k + e] = (float)top.tv[s];
         }
     }
 }
@@ -402,15 +464,34 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
     return hipGetLastError();
 }
 
-hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
-                         const QueryShape &sh, const int32_t *cand, int64_t *out_ids,
-                         float *out_ips, hipStream_t s)
+int rerank_splits(int64_t nq, int64_t Tq)
 {
-    const dim3 grid((unsigned)nq), block(64);
+    // enough waves to cover the machine (256 CUs x 32 waves) without slices
+    // shorter than 16 candidate batches
+    int64_t want = (8192 + nq - 1) / nq;
+    const int64_t cap = (Tq + 1023) / 1024;
+    if (want > cap) want = cap;
+    if (want < 1) want = 1;
+    if (want > 64) want = 64;
+    return (int)want;
+}
+
+hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
+                         const QueryShape &sh, const int32_t *cand, int nsplit, double *part_v,
+                         int32_t *part_i, int64_t *out_ids, float *out_ips, hipStream_t s)
+{
     const int S = (sh.k + 63) / 64;
-#define NRLSH_RERANK(SS)                                                                        \
-    hipLaunchKernelGGL(k_rerank<SS>, grid, block, 0, s, Xp, perm, Q, sh.n, sh.d, sh.dp, sh.Tq, \
-                       sh.k, cand, out_ids, out_ips)
+    int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
+    slice = (slice + 63) / 64 * 64;
+    const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
+#define NRLSH_RERANK(SS)                                                                         \
+    do {                                                                                         \
+        hipLaunchKernelGGL(k_rerank<SS>, grid, block, 0, s, Xp, perm, Q, sh.n, sh.d, sh.dp,      \
+                           sh.Tq, sh.k, cand, nsplit, slice, out_ids, out_ips, part_v, part_i);  \
+        if (nsplit > 1)                                                                          \
+            hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
+                               nsplit, sh.k, out_ids, out_ips);                                  \
+    } while (0)
     if (S <= 1) NRLSH_RERANK(1);
     else if (S <= 2) NRLSH_RERANK(2);
     else if (S <= 4) NRLSH_RERANK(4);

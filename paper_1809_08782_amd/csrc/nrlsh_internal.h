@@ -94,9 +94,12 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
                             const int32_t *ghthr, const int32_t *gtie, int32_t *cand,
                             hipStream_t s);
 
-// Exact FP64 re-rank of the probed items and top-k selection.
+// Exact FP64 re-rank of the probed items and top-k selection.  Each query's
+// probed list is cut into nsplit slices (rerank_splits); with nsplit > 1 the
+// partial lists go to part_v / part_i (nq x nsplit x k) and are merged.
+int rerank_splits(int64_t nq, int64_t Tq);
 hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
-                         const QueryShape &sh, const int32_t *cand, int64_t *out_ids,
-                         float *out_ips, hipStream_t s);
+                         const QueryShape &sh, const int32_t *cand, int nsplit, double *part_v,
+                         int32_t *part_i, int64_t *out_ids, float *out_ips, hipStream_t s);
 
 }  // namespace nrlsh

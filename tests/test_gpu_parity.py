@@ -46,6 +46,22 @@ def test_parity_shapes(shape):
             assert np.array_equal(ids, oids), f"T={TT}"
 
 
+@pytest.mark.parametrize("k", [10, 100])
+def test_parity_large_budget_split_rerank(k):
+    """Budgets above 1024 with few queries split each probed list across waves."""
+    say(f"case split rerank k={k}")
+    n, d = 20000, 40
+    X = make_items("lognormal", n, d, seed=51, sigma=1.0)
+    Q = make_queries(9, d, seed=52)
+    oix = orc.OracleIndex(X, 16, 32, seed=13, threads=8)
+    with nr.nrlsh_build(X, 16, 32, 13) as gix:
+        for T in (3000, 17777, n):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T)
+            oids, oips = oix.query(Q, k, T)
+            assert np.array_equal(ids, oids), f"T={T}"
+            assert np.array_equal(ips, oips.astype(np.float32)), f"T={T}"
+
+
 def test_parity_tiny_config():
     """The small recipe end to end: n = 1e4, d = 64, m = 8, L = 16, 100 queries,
     top-10, budget 500."""
