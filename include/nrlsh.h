@@ -107,10 +107,20 @@ void nrlsh_free(nrlsh_index *ix);
 nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
                          int64_t probe_budget, int64_t *out_ids, float *out_ips);
 
+/* How the probed items are re-ranked; every mode returns the same result.
+ *   GATHER: each query's probed list is materialised and its rows gathered.
+ *   SCREEN: queries are tiled 64 at a time against chunks of stored rows on
+ *           the FP32 matrix cores; pairs that are probed and whose FP32 inner
+ *           product (with a rigorous rounding bound) can still reach a lower
+ *           bound of the k-th best are re-ranked exactly in FP64.
+ *   AUTO:   SCREEN for large budgets (T >= n/40, >= 64 queries), else GATHER. */
+typedef enum { NRLSH_RERANK_AUTO = 0, NRLSH_RERANK_GATHER = 1, NRLSH_RERANK_SCREEN = 2 } nrlsh_rerank_mode;
+
 typedef struct nrlsh_query_opts {
     int32_t struct_size; /* sizeof(nrlsh_query_opts) */
     int32_t device_ptrs; /* 1: queries, out_ids, out_ips are device pointers */
     void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
+    int32_t rerank_mode; /* nrlsh_rerank_mode (read when struct_size covers it) */
 } nrlsh_query_opts;
 
 nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -168,8 +178,9 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
 /* ------------------------------------------------------------ profiling --
  * Optional per-kernel timing with HIP events recorded on the stream each
  * kernel is launched on.  Off by default; enabling adds one event pair per
- * timed launch.  Names: "keys", "sort", "hash", "hash_fixup", "qhash",
- * "scan_hist", "threshold", "scan_emit", "rerank". */
+ * timed launch.  Names: "keys", "sort", "layout", "hash", "hash_fixup",
+ * "qhash", "scan_hist", "threshold", "scan_emit", "rerank", "tie_locate",
+ * "screen", "rerank_exact". */
 void nrlsh_profile_enable(int32_t on);
 void nrlsh_profile_reset(void);
 /* Total milliseconds and launch count of kernel `name` since the last reset. */

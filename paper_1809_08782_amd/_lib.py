@@ -34,7 +34,11 @@ class BuildOpts(C.Structure):
 
 
 class QueryOpts(C.Structure):
-    _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p)]
+    _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
+                ("rerank_mode", C.c_int32)]
+
+
+RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2}
 
 
 class BuildStats(C.Structure):
@@ -241,9 +245,13 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
     return Index(h.value)
 
 
-def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None):
+def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None,
+                rerank: str = "auto"):
     """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
-    numpy for host queries, torch tensors for CUDA torch queries."""
+    numpy for host queries, torch tensors for CUDA torch queries.  ``rerank``
+    selects the re-rank mode ("auto", "gather", "screen"); all give the same
+    result."""
+    mode = RERANK_MODES[rerank]
     if _is_torch_device(queries):
         import torch
         Q = queries.contiguous()
@@ -253,7 +261,7 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
             ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         else:
             ids, ips = out
-        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q))
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode)
         _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
                                     C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
         return ids, ips
@@ -261,8 +269,13 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
     nq = Q.shape[0]
     ids = np.empty((nq, k), dtype=np.int64)
     ips = np.empty((nq, k), dtype=np.float32)
-    _check(lib().nrlsh_query(ix.handle, Q.ctypes.data, nq, k, int(probe_budget), ids.ctypes.data,
-                             ips.ctypes.data))
+    if mode or stream is not None:
+        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode)
+        _check(lib().nrlsh_query_ex(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
+                                    C.byref(opts), ids.ctypes.data, ips.ctypes.data))
+    else:
+        _check(lib().nrlsh_query(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
+                                 ids.ctypes.data, ips.ctypes.data))
     return ids, ips
 
 

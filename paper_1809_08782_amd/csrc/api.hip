@@ -8,6 +8,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdarg>
+#include <cstddef>
 #include <cstdio>
 #include <cstring>
 #include <map>
@@ -275,10 +276,10 @@ struct nrlsh_index {
     std::vector<int32_t> R_h;
     nrlsh_build_stats stats{};
     hipStream_t home = nullptr;  // library stream that releases the device buffers
-    DBuf<float> Xp, A, At;
-    DBuf<double> key, keymax, U;
-    DBuf<int32_t> sid, perm, off, R, inv;
-    DBuf<uint32_t> codes_l, codes_o;
+    DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
+    DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
+    DBuf<int32_t> sid, sid_l, perm, off, R, inv;
+    DBuf<uint32_t> codes_l;              // stored order
 };
 
 namespace {
@@ -310,19 +311,20 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         tau_h[r] = std::nextafter((float)tau, INFINITY);
     }
 
-    ix->Xp = DBuf<float>((size_t)n * dp, s);
+    ix->Xl = DBuf<float>((size_t)n * dp, s);
     ix->A = DBuf<float>(ix->A_h.size(), s);
     ix->At = DBuf<float>(At_h.size(), s);
     ix->key = DBuf<double>(n, s);
+    ix->key_l = DBuf<double>(n, s);
     ix->keymax = DBuf<double>(m, s);
     ix->U = DBuf<double>(m, s);
     ix->sid = DBuf<int32_t>(n, s);
+    ix->sid_l = DBuf<int32_t>(n, s);
     ix->perm = DBuf<int32_t>(n, s);
     ix->off = DBuf<int32_t>(m + 1, s);
     ix->R = DBuf<int32_t>((size_t)m * (L + 1), s);
     ix->inv = DBuf<int32_t>((size_t)m * (L + 1), s);
     ix->codes_l = DBuf<uint32_t>((size_t)n * W, s);
-    ix->codes_o = DBuf<uint32_t>((size_t)n * W, s);
 
     DBuf<float> tau(L, s);
     DBuf<uint64_t> ka(n, s), kb(n, s);
@@ -348,7 +350,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
 
     // Algorithm 1: rank by 2-norm, cut into m percentile ranges
     tm.begin("keys");
-    HIPX(launch_keys_copy(X, n, d, dp, ix->Xp.get(), ix->key.get(), ka.get(), va.get(), ctr.get(), s));
+    HIPX(launch_keys(X, n, d, ix->key.get(), ka.get(), va.get(), ctr.get(), s));
     tm.end();
     bool in_b = false;
     tm.begin("sort");
@@ -399,27 +401,30 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     }
     HIPX(hipMemcpyAsync(ix->perm.get(), perm_src, (size_t)n * sizeof(int32_t),
                         hipMemcpyDeviceToDevice, s));
+    tm.begin("layout");
+    HIPX(launch_layout(X, n, d, dp, ix->perm.get(), ix->key.get(), ix->sid.get(), ix->Xl.get(),
+                       ix->key_l.get(), ix->sid_l.get(), s));
+    tm.end();
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
     tm.begin("hash");
-    HIPX(launch_hash(ix->Xp.get(), n, d, dp, ix->A.get(), L, ix->key.get(), ix->sid.get(),
-                     ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_o.get(), fix.get(),
+    HIPX(launch_hash(ix->Xl.get(), n, d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
+                     ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_l.get(), fix.get(),
                      ctr.get(), s));
     tm.end();
     tm.begin("hash_fixup");
-    HIPX(launch_hash_fixup(ix->Xp.get(), d, dp, ix->A.get(), L, ix->key.get(), ix->sid.get(),
-                           ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), ix->codes_o.get(),
+    HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
+                           ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), ix->codes_l.get(),
                            n, s));
     tm.end();
-    HIPX(launch_permute_codes(ix->codes_o.get(), ix->perm.get(), n, W, ix->codes_l.get(), s));
 
     HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
     HIPX(hipStreamSynchronize(s));
     // long-lived buffers are released on the library stream by nrlsh_free
-    for (auto *b : {&ix->Xp, &ix->A, &ix->At}) b->s = ix->home;
-    for (auto *b : {&ix->key, &ix->keymax, &ix->U}) b->s = ix->home;
-    for (auto *b : {&ix->sid, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
-    for (auto *b : {&ix->codes_l, &ix->codes_o}) b->s = ix->home;
+    for (auto *b : {&ix->Xl, &ix->A, &ix->At}) b->s = ix->home;
+    for (auto *b : {&ix->key, &ix->key_l, &ix->keymax, &ix->U}) b->s = ix->home;
+    for (auto *b : {&ix->sid, &ix->sid_l, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
+    ix->codes_l.s = ix->home;
     ix->stats.recomputed_items = hc.fix_count;
     ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
     ix->stats.recompute_flips = (int64_t)hc.fix_flips;
@@ -452,12 +457,7 @@ nrlsh_status validate_query(const nrlsh_index *ix, const float *queries, int64_t
     return NRLSH_OK;
 }
 
-// Runs the query steps on device queries Qd for nq queries.  When cand_out is
-// given, the probed stored positions of each query are copied there (nq x Tq)
-// and the re-rank is skipped.
-void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
-               int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
-               hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
 {
     QueryShape sh;
     sh.n = ix->n;
@@ -468,6 +468,17 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     sh.W = ix->W;
     sh.Tq = std::min<int64_t>(T, ix->n);
     sh.k = k;
+    return sh;
+}
+
+// Gather path: materialise each query's probed list, then re-rank it.  When
+// cand_out_d is given, the probed stored positions are copied there (nq x Tq)
+// and the re-rank is skipped.
+void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
+                      int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
+                      hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+{
+    const QueryShape sh = make_shape(ix, T, k);
     // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^29 entries
     int64_t B = (int64_t(1) << 29) / sh.Tq;
     B = std::max<int64_t>(64, B / 64 * 64);
@@ -504,10 +515,132 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
         tm.end();
         if (cand_out_d) continue;
         tm.begin("rerank");
-        HIPX(launch_rerank(ix->Xp.get(), ix->perm.get(), Qb, nb, sh, cb, nsplit, part_v.get(),
-                           part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, nullptr, nsplit,
+                           part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
         tm.end();
     }
+}
+
+size_t screen_lds_bytes(const nrlsh_index *ix) { return (size_t)64 * (ix->dp + 4) * sizeof(float) + 4096; }
+
+bool screen_fits(const nrlsh_index *ix)
+{
+    int lim = 0;
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
+        return false;
+    return screen_lds_bytes(ix) <= (size_t)lim;
+}
+
+// Screen path: threshold theta_q from an exact re-rank at budget T0 <= T,
+// query-tiled MFMA screen of the probed set, exact re-rank of the kept pairs.
+void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
+                      int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                      uint32_t *nonfinite_d)
+{
+    const QueryShape sh = make_shape(ix, T, k);
+    const int64_t T0 = std::min<int64_t>(sh.Tq, std::max<int64_t>(1024, 4 * (int64_t)k));
+    const QueryShape sh0 = make_shape(ix, T0, k);
+    int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
+    const int64_t tiles = B / 64;
+    const int L1 = sh.L + 1;
+    int64_t cap = std::min<int64_t>(sh.Tq, 1024);
+
+    // chunks of <= screen_chunk_items() stored items inside one sub-dataset
+    std::vector<int32_t> ch;
+    for (int j = 0; j < sh.m; ++j)
+        for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += screen_chunk_items()) {
+            ch.push_back(j);
+            ch.push_back((int32_t)p);
+            ch.push_back((int32_t)std::min<int64_t>(p + screen_chunk_items(), ix->off_h[j + 1]));
+        }
+    const int nchunks = (int)(ch.size() / 3);
+    DBuf<int32_t> chunks(ch.size(), s);
+    HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+    DBuf<uint32_t> qcodes((size_t)B * sh.W, s);
+    DBuf<uint32_t> ghist((size_t)tiles * sh.m * L1 * 64, s);
+    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s), gbase0((size_t)tiles * (sh.m + 1) * 64, s);
+    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s), ghthr0((size_t)tiles * sh.m * 64, s);
+    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s), gtie0((size_t)tiles * 4 * 64, s);
+    DBuf<int32_t> gpstar((size_t)B, s);
+    DBuf<int32_t> cand0((size_t)B * T0, s);
+    DBuf<int64_t> ids0((size_t)B * k, s);
+    DBuf<float> ips0((size_t)B * k, s);
+    DBuf<int32_t> counts((size_t)B, s);
+    DBuf<int32_t> lists((size_t)B * cap, s);
+    std::vector<int32_t> hcounts((size_t)B);
+    const int nsplit0 = rerank_splits(B, T0);
+    DBuf<double> part_v(nsplit0 > 1 ? (size_t)B * nsplit0 * k : 1, s);
+    DBuf<int32_t> part_i(nsplit0 > 1 ? (size_t)B * nsplit0 * k : 1, s);
+    for (int64_t b0 = 0; b0 < nq; b0 += B) {
+        const int64_t nb = std::min<int64_t>(B, nq - b0);
+        const float *Qb = Qd + b0 * sh.d;
+        tm.begin("qhash");
+        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qcodes.get(), nonfinite_d, s));
+        tm.end();
+        tm.begin("scan_hist");
+        HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh, ghist.get(), s));
+        tm.end();
+        tm.begin("threshold");
+        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
+                              ghthr.get(), gtie.get(), s));
+        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh0, gbase0.get(),
+                              ghthr0.get(), gtie0.get(), s));
+        tm.end();
+        tm.begin("tie_locate");
+        HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, gtie.get(),
+                               gpstar.get(), s));
+        tm.end();
+        // theta: exact top-k over the probed set of the budget T0 (a prefix of the T set)
+        tm.begin("scan_emit");
+        HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh0, gbase0.get(),
+                              ghthr0.get(), gtie0.get(), cand0.get(), s));
+        tm.end();
+        tm.begin("rerank");
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh0, cand0.get(), nullptr, nsplit0,
+                           part_v.get(), part_i.get(), ids0.get(), ips0.get(), s));
+        tm.end();
+        for (;;) {
+            HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
+            tm.begin("screen");
+            HIPX(launch_screen(ix->Xl.get(), ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+                               chunks.get(), nchunks, qcodes.get(), ghthr.get(), gtie.get(),
+                               gpstar.get(), ips0.get(), ids0.get(), (int)cap, counts.get(),
+                               lists.get(), s));
+            tm.end();
+            HIPX(hipMemcpyAsync(hcounts.data(), counts.get(), (size_t)nb * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            int64_t mx = 0;
+            for (int64_t i = 0; i < nb; ++i) mx = std::max<int64_t>(mx, hcounts[i]);
+            if (mx <= cap) break;
+            // a list overflowed: grow the lists and screen this batch again
+            cap = std::min<int64_t>(sh.Tq, std::max<int64_t>(mx, 2 * cap));
+            lists = DBuf<int32_t>((size_t)B * cap, s);
+        }
+        QueryShape shl = sh;
+        shl.Tq = cap;  // list stride; lengths come from counts
+        const int nsplit = rerank_splits(nb, cap);
+        DBuf<double> pv(nsplit > 1 ? (size_t)nb * nsplit * k : 1, s);
+        DBuf<int32_t> pi(nsplit > 1 ? (size_t)nb * nsplit * k : 1, s);
+        tm.begin("rerank_exact");
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(), counts.get(),
+                           nsplit, pv.get(), pi.get(), ids_d + b0 * k, ips_d + b0 * k, s));
+        tm.end();
+    }
+}
+
+void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
+               int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+{
+    const int64_t Tq = std::min<int64_t>(T, ix->n);
+    bool screen = mode == NRLSH_RERANK_SCREEN ||
+                  (mode == NRLSH_RERANK_AUTO && Tq * 40 >= ix->n && nq >= 64 && Tq >= 2048);
+    if (screen && !screen_fits(ix)) screen = false;
+    if (screen)
+        run_query_screen(ix, Qd, nq, k, T, ids_d, ips_d, s, tm, nonfinite_d);
+    else
+        run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d);
 }
 
 template <typename F>
@@ -584,7 +717,11 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
                             float *out_ips)
 {
     nrlsh_status st = validate_query(ix, queries, nq, k, probe_budget, out_ids, out_ips);
-    if (st != NRLSH_OK || nq == 0) return st;
+    if (st != NRLSH_OK) return st;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)) &&
+        (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN))
+        return fail(NRLSH_E_INVALID_ARG, "rerank_mode %d unknown", opts->rerank_mode);
+    if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
@@ -592,17 +729,18 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         Timer tm(s);
         DBuf<uint32_t> flag(1, s);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        int mode = NRLSH_RERANK_AUTO;
+        if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)))
+            mode = opts->rerank_mode;
         if (on_device) {
-            run_query(ix, queries, nq, k, probe_budget, out_ids, out_ips, nullptr, nullptr, s, tm,
-                      flag.get());
+            run_query(ix, queries, nq, k, probe_budget, mode, out_ids, out_ips, s, tm, flag.get());
         } else {
             DBuf<float> Qd((size_t)nq * ix->d, s);
             DBuf<int64_t> ids((size_t)nq * k, s);
             DBuf<float> ips((size_t)nq * k, s);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
-            run_query(ix, Qd.get(), nq, k, probe_budget, ids.get(), ips.get(), nullptr, nullptr, s,
-                      tm, flag.get());
+            run_query(ix, Qd.get(), nq, k, probe_budget, mode, ids.get(), ips.get(), s, tm, flag.get());
             HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),
@@ -683,11 +821,13 @@ nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes)
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
         std::vector<uint32_t> w((size_t)ix->n * ix->W);
-        HIPX(hipMemcpy(w.data(), ix->codes_o.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
-        for (int64_t i = 0; i < ix->n; ++i) {
-            uint64_t c = w[(size_t)i * ix->W];
-            if (ix->W == 2) c |= (uint64_t)w[(size_t)i * 2 + 1] << 32;
-            codes[i] = c;
+        std::vector<int32_t> perm(ix->n);
+        HIPX(hipMemcpy(w.data(), ix->codes_l.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIPX(hipMemcpy(perm.data(), ix->perm.get(), perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t p = 0; p < ix->n; ++p) {
+            uint64_t c = w[(size_t)p * ix->W];
+            if (ix->W == 2) c |= (uint64_t)w[(size_t)p * 2 + 1] << 32;
+            codes[perm[p]] = c;
         }
         return NRLSH_OK;
     });
@@ -753,7 +893,8 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
         DBuf<uint32_t> flag(1, s);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
         HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));
-        run_query(ix, Qd.get(), nq, 1, probe_budget, nullptr, nullptr, cd.get(), qc.get(), s, tm, flag.get());
+        run_query_gather(ix, Qd.get(), nq, 1, probe_budget, nullptr, nullptr, cd.get(), qc.get(), s, tm,
+                         flag.get());
         std::vector<int32_t> pos((size_t)nq * Tq), perm(ix->n);
         HIPX(hipMemcpyAsync(pos.data(), cd.get(), pos.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
         HIPX(hipMemcpyAsync(perm.data(), ix->perm.get(), perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));

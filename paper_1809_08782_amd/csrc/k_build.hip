@@ -1,9 +1,10 @@
 // Index-build kernels of norm-ranging LSH (Algorithm 1) for gfx950.
 //
-//   keys_copy   squared 2-norms (FP64, ascending coordinate order) and the
-//               zero-padded item copy                     [Algorithm 1, ranking]
+//   keys        squared 2-norms (FP64, ascending coordinate order)
+//                                                          [Algorithm 1, ranking]
 //   radix sort  stable LSD sort of (key bits, index)      [Algorithm 1, ranking]
 //   assign      sub-dataset by norm percentile, U_j        [Algorithm 1, partition]
+//   layout      zero-padded item copy in stored order (sub-dataset major)
 //   hash        SimpleLSH transform (Eq. 8) + sign random projection (Eq. 4)
 //               on the FP32 matrix cores, sign packing, uncertainty band
 //   hash_fixup  FP64 recompute of in-band projections as the definition
@@ -16,7 +17,7 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
-// ---------------------------------------------------------------- keys_copy
+// ---------------------------------------------------------------- keys
 // One wave owns 64 consecutive rows.  Columns are streamed 32 at a time:
 // each load instruction covers two rows x 128 contiguous bytes, the chunk is
 // transposed through LDS, and lane r then adds the squares of row r in
@@ -24,12 +25,11 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 // sum is bit-identical to a sequential FP64 loop.
 constexpr int KC_ROWS = 64;
 
-__global__ __launch_bounds__(256) void k_keys_copy(const float *__restrict__ X, int64_t n, int d,
-                                                   int dp, float *__restrict__ Xp,
-                                                   double *__restrict__ key,
-                                                   uint64_t *__restrict__ skey,
-                                                   int32_t *__restrict__ sval,
-                                                   BuildCounters *__restrict__ ctr)
+__global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64_t n, int d,
+                                              double *__restrict__ key,
+                                              uint64_t *__restrict__ skey,
+                                              int32_t *__restrict__ sval,
+                                              BuildCounters *__restrict__ ctr)
 {
     __shared__ float tile[4][KC_ROWS][33];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -37,19 +37,16 @@ __global__ __launch_bounds__(256) void k_keys_copy(const float *__restrict__ X, 
     const int half = lane >> 5, col = lane & 31;
     double acc = 0.0;
     bool bad = false;
-    for (int c0 = 0; c0 < dp; c0 += 32) {
+    for (int c0 = 0; c0 < d; c0 += 32) {
 #pragma unroll 8
         for (int it = 0; it < 32; ++it) {
             const int r = 2 * it + half;
             const int64_t row = row0 + r;
             const int c = c0 + col;
             float v = 0.0f;
-            if (row < n) {
-                if (c < d) {
-                    v = X[row * d + c];
-                    bad |= !__builtin_isfinite(v);
-                }
-                if (c < dp) Xp[row * dp + c] = v;
+            if (row < n && c < d) {
+                v = X[row * d + c];
+                bad |= !__builtin_isfinite(v);
             }
             tile[wave][r][col] = v;
         }
@@ -201,11 +198,33 @@ __global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ ske
     if (r == n - 1 || ((r + 1) * (int64_t)m) / n != s) keymax[s] = __longlong_as_double((long long)skey[r]);
 }
 
-__global__ __launch_bounds__(256) void k_invert(const int32_t *__restrict__ perm, int64_t n,
-                                                int32_t *__restrict__ pos)
+// Stored copy: row p of Xl is item perm[p], zero-padded to dp floats; the
+// key and sub-dataset of each stored row come along.  One wave copies
+// LY_ROWS rows, 64 floats per instruction.
+constexpr int LY_ROWS = 8;
+
+__global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int64_t n, int d,
+                                                int dp, const int32_t *__restrict__ perm,
+                                                const double *__restrict__ key,
+                                                const int32_t *__restrict__ sid,
+                                                float *__restrict__ Xl, double *__restrict__ key_l,
+                                                int32_t *__restrict__ sid_l)
 {
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p < n) pos[perm[p]] = (int32_t)p;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * LY_ROWS;
+#pragma unroll
+    for (int r = 0; r < LY_ROWS; ++r) {
+        const int64_t p = p0 + r;
+        if (p >= n) break;
+        const int64_t i = perm[p];
+        const float *src = X + i * d;
+        float *dst = Xl + p * dp;
+        for (int c = lane; c < dp; c += 64) dst[c] = c < d ? src[c] : 0.0f;
+        if (lane == 0) {
+            key_l[p] = key[i];
+            sid_l[p] = sid[i];
+        }
+    }
 }
 
 // ---------------------------------------------------------------- hash
@@ -230,10 +249,10 @@ constexpr int H_KS = H_KC + 4;
 
 template <int CB>
 __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
-    const float *__restrict__ Xp, int64_t n, int d, int dp, const float *__restrict__ A, int L,
-    const double *__restrict__ key, const int32_t *__restrict__ sid,
+    const float *__restrict__ Xl, int64_t n, int d, int dp, const float *__restrict__ A, int L,
+    const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
     const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ tau,
-    uint32_t *__restrict__ codes_o, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr)
+    uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr)
 {
     constexpr int NB = 16 * CB;
     __shared__ float As[NB * H_KS];
@@ -247,9 +266,9 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
         float sq = 0.f, uf = 0.f;
         int sp = 1;
         if (i < n) {
-            const int s = sid[i];
+            const int s = sid_l[i];
             const double km = keymax[s], u = U[s];
-            sq = sqrtf((float)(km - key[i]));
+            sq = sqrtf((float)(km - key_l[i]));
             uf = (float)u;
             sp = !(u >= 0x1p-60 && u <= 0x1p60);
         }
@@ -279,7 +298,7 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
             for (int rb = 0; rb < 4; ++rb) {
                 const int64_t row = i0 + 16 * rb + r16;
                 xa[rb] = (row < n && k < dp)
-                             ? *reinterpret_cast<const floatx4 *>(Xp + row * dp + k)
+                             ? *reinterpret_cast<const floatx4 *>(Xl + row * dp + k)
                              : floatx4{0.f, 0.f, 0.f, 0.f};
             }
             floatx4 bq[CB];
@@ -327,10 +346,10 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
     const bool valid = i < n;
     if (valid) {
         if (CB <= 2) {
-            codes_o[i] = (uint32_t)mycode;
+            codes_l[i] = (uint32_t)mycode;
         } else {
-            codes_o[2 * i] = (uint32_t)mycode;
-            codes_o[2 * i + 1] = (uint32_t)(mycode >> 32);
+            codes_l[2 * i] = (uint32_t)mycode;
+            codes_l[2 * i + 1] = (uint32_t)(mycode >> 32);
         }
     }
     const bool has = valid && myfix != 0ull;
@@ -355,28 +374,28 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
 // the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
 // when U_j = 0; sum over coordinates in ascending order, no contraction).
 __global__ __launch_bounds__(256) void k_hash_fixup(
-    const float *__restrict__ Xp, int d, int dp, const float *__restrict__ A, int L,
-    const double *__restrict__ key, const int32_t *__restrict__ sid,
+    const float *__restrict__ Xl, int d, int dp, const float *__restrict__ A, int L,
+    const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
     const double *__restrict__ keymax, const double *__restrict__ U,
     const FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr,
-    uint32_t *__restrict__ codes_o, int W)
+    uint32_t *__restrict__ codes_l, int W)
 {
     const uint32_t cnt = ctr->fix_count;
     unsigned long long nbits = 0, nflip = 0;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
         const FixEntry fe = fix[e];
         const int64_t i = fe.item;
-        const int s = sid[i];
-        const double u = U[s], km = keymax[s], kk = key[i];
-        uint64_t code = codes_o[W * i];
-        if (W == 2) code |= (uint64_t)codes_o[W * i + 1] << 32;
+        const int s = sid_l[i];
+        const double u = U[s], km = keymax[s], kk = key_l[i];
+        uint64_t code = codes_l[W * i];
+        if (W == 2) code |= (uint64_t)codes_l[W * i + 1] << 32;
         double vd = 1.0;
         if (u != 0.0) {
             double t = 1.0 - kk / km;
             if (t < 0.0) t = 0.0;
             vd = __builtin_sqrt(t);
         }
-        const float *x = Xp + i * dp;
+        const float *x = Xl + i * dp;
         uint64_t mask = fe.mask;
         while (mask != 0ull) {
             const int r = __ffsll((long long)mask) - 1;
@@ -394,24 +413,13 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
             ++nbits;
             code = (code & ~(1ull << r)) | (bit << r);
         }
-        codes_o[W * i] = (uint32_t)code;
-        if (W == 2) codes_o[W * i + 1] = (uint32_t)(code >> 32);
+        codes_l[W * i] = (uint32_t)code;
+        if (W == 2) codes_l[W * i + 1] = (uint32_t)(code >> 32);
     }
     if (nbits) {
         atomicAdd(&ctr->fix_bits, nbits);
         atomicAdd(&ctr->fix_flips, nflip);
     }
-}
-
-__global__ __launch_bounds__(256) void k_permute_codes(const uint32_t *__restrict__ codes_o,
-                                                       const int32_t *__restrict__ perm, int64_t n,
-                                                       int W, uint32_t *__restrict__ codes_l)
-{
-    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
-    const int64_t i = perm[p];
-    codes_l[W * p] = codes_o[W * i];
-    if (W == 2) codes_l[W * p + 1] = codes_o[W * i + 1];
 }
 
 inline unsigned grid_for(int64_t n, int per_block)
@@ -422,12 +430,11 @@ inline unsigned grid_for(int64_t n, int per_block)
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
-hipError_t launch_keys_copy(const float *X, int64_t n, int d, int dp, float *Xp, double *key,
-                            uint64_t *sort_key, int32_t *sort_val, BuildCounters *ctr,
-                            hipStream_t s)
+hipError_t launch_keys(const float *X, int64_t n, int d, double *key, uint64_t *sort_key,
+                       int32_t *sort_val, BuildCounters *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_keys_copy, dim3(grid_for(n, 4 * KC_ROWS)), dim3(256), 0, s, X, n, d, dp,
-                       Xp, key, sort_key, sort_val, ctr);
+    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 4 * KC_ROWS)), dim3(256), 0, s, X, n, d, key,
+                       sort_key, sort_val, ctr);
     return hipGetLastError();
 }
 
@@ -468,58 +475,53 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
     return hipGetLastError();
 }
 
-hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *pos, hipStream_t s)
+hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
+                         const double *key, const int32_t *sid, float *Xl, double *key_l,
+                         int32_t *sid_l, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_invert, dim3(grid_for(n, 256)), dim3(256), 0, s, perm, n, pos);
+    hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 4 * LY_ROWS)), dim3(256), 0, s, X, n, d, dp,
+                       perm, key, sid, Xl, key_l, sid_l);
     return hipGetLastError();
 }
 
-hipError_t launch_hash(const float *Xp, int64_t n, int d, int dp, const float *A, int L,
-                       const double *key, const int32_t *sid, const double *keymax,
-                       const double *U, const float *tau, uint32_t *codes_o, FixEntry *fix,
+hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
+                       const double *key_l, const int32_t *sid_l, const double *keymax,
+                       const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
                        BuildCounters *ctr, hipStream_t s)
 {
     const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
     switch ((L + 15) / 16) {
     case 1:
-        hipLaunchKernelGGL(k_hash<1>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
-                           tau, codes_o, fix, ctr);
+        hipLaunchKernelGGL(k_hash<1>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
+                           tau, codes_l, fix, ctr);
         break;
     case 2:
-        hipLaunchKernelGGL(k_hash<2>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
-                           tau, codes_o, fix, ctr);
+        hipLaunchKernelGGL(k_hash<2>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
+                           tau, codes_l, fix, ctr);
         break;
     case 3:
-        hipLaunchKernelGGL(k_hash<3>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
-                           tau, codes_o, fix, ctr);
+        hipLaunchKernelGGL(k_hash<3>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
+                           tau, codes_l, fix, ctr);
         break;
     default:
-        hipLaunchKernelGGL(k_hash<4>, grid, block, 0, s, Xp, n, d, dp, A, L, key, sid, keymax, U,
-                           tau, codes_o, fix, ctr);
+        hipLaunchKernelGGL(k_hash<4>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
+                           tau, codes_l, fix, ctr);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_hash_fixup(const float *Xp, int d, int dp, const float *A, int L,
-                             const double *key, const int32_t *sid, const double *keymax,
+hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L,
+                             const double *key_l, const int32_t *sid_l, const double *keymax,
                              const double *U, const FixEntry *fix, BuildCounters *ctr,
-                             uint32_t *codes_o, int64_t max_entries, hipStream_t s)
+                             uint32_t *codes_l, int64_t max_entries, hipStream_t s)
 {
     const int W = L > 32 ? 2 : 1;
     int64_t blocks = (max_entries + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xp, d, dp, A, L, key,
-                       sid, keymax, U, fix, ctr, codes_o, W);
-    return hipGetLastError();
-}
-
-hipError_t launch_permute_codes(const uint32_t *codes_o, const int32_t *perm, int64_t n, int W,
-                                uint32_t *codes_l, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_permute_codes, dim3(grid_for(n, 256)), dim3(256), 0, s, codes_o, perm, n,
-                       W, codes_l);
+    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xl, d, dp, A, L, key_l,
+                       sid_l, keymax, U, fix, ctr, codes_l, W);
     return hipGetLastError();
 }
 

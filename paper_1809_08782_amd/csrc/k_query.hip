@@ -305,11 +305,12 @@ struct WaveTopK {
 };
 
 template <int S>
-__global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
+__global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                const int32_t *__restrict__ perm,
                                                const float *__restrict__ Q, int64_t n, int d,
                                                int dp, int64_t Tq, int k,
-                                               const int32_t *__restrict__ cand, int nsplit,
+                                               const int32_t *__restrict__ cand,
+                                               const int32_t *__restrict__ counts, int nsplit,
                                                int64_t slice, int64_t *__restrict__ out_ids,
                                                float *__restrict__ out_ips,
                                                double *__restrict__ part_v,
@@ -321,18 +322,19 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
     const int split = blockIdx.y;
     const float *qv = Q + q * d;
     const int32_t *cq = cand + q * Tq;
+    const int64_t len = counts ? min((int64_t)counts[q], Tq) : Tq;
     const int64_t cbeg = (int64_t)split * slice;
-    const int64_t cend = min(Tq, cbeg + slice);
+    const int64_t cend = min(len, cbeg + slice);
     WaveTopK<S> top;
     top.init(k);
     const int sub = lane >> 3, seg = 4 * (lane & 7);
 
     for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
         bool valid = c0 + lane < cend;
-        int32_t id = 0;
+        int32_t id = 0, p = 0;
         if (valid) {
-            const int32_t p = cq[c0 + lane];
-            valid = p >= 0 && (int64_t)p < n;  // positions come from scan_emit; never trust blindly
+            p = cq[c0 + lane];
+            valid = p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
             if (valid) id = perm[p];
         }
         int64_t roff[8];
@@ -340,7 +342,7 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
             const int rr = 8 * it + sub;
-            roff[it] = (int64_t)__shfl(id, rr, 64) * dp;
+            roff[it] = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
             rval[it] = __shfl((int)valid, rr, 64) != 0;
         }
         double acc = 0.0;
@@ -349,7 +351,7 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xp,
 #pragma unroll
             for (int it = 0; it < 8; ++it) {
                 floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-                if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xp + roff[it] + col);
+                if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
                 *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
             }
             __syncthreads();
@@ -414,6 +416,188 @@ __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ pa
     }
 }
 
+// ---------------------------------------------------------------- tie locate
+// Stored position of the r*-th item of the threshold bucket (j*, h*) of each
+// query: with it the probed set becomes a per-pair predicate,
+//   p in C_T  <=>  h <= hthr[q][j]  or  (j = j*, h = h*, p <= P*).
+template <int W>
+__global__ __launch_bounds__(64) void k_tie_locate(const uint32_t *__restrict__ codes_l,
+                                                   const int32_t *__restrict__ off,
+                                                   const uint32_t *__restrict__ qcodes,
+                                                   int64_t nq, const int32_t *__restrict__ gtie,
+                                                   int32_t *__restrict__ gpstar)
+{
+    const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (q >= nq) return;
+    const int tile = (int)(q >> 6), lane = (int)(q & 63);
+    const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
+    const int jstar = tie[lane], hstar = tie[64 + lane], rstar = tie[128 + lane];
+    int32_t P = -1;
+    if (jstar >= 0) {
+        const uint32_t q0 = qcodes[q * W], q1 = W == 2 ? qcodes[q * W + 1] : 0u;
+        int cnt = 0;
+        for (int64_t p = off[jstar]; p < off[jstar + 1]; ++p) {
+            int h = __popc(codes_l[p * W] ^ q0);
+            if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+            if (h == hstar && ++cnt == rstar) {
+                P = (int32_t)p;
+                break;
+            }
+        }
+    }
+    gpstar[q] = P;
+}
+
+// ---------------------------------------------------------------- screen
+// Query-tiled screen of the probed set on the FP32 matrix cores.  A block
+// holds 64 queries (staged in LDS) and one chunk of <= SC_CHUNK stored items
+// of a single sub-dataset; each wave computes 64 queries x 32 items per
+// iteration with v_mfma_f32_16x16x4_f32 (queries = M, items = N).  A pair is
+// kept for the exact re-rank when it is probed (the predicate above) and its
+// FP32 inner product can still reach theta_q, a lower bound on the k-th best
+// exact inner product of the probed set:
+//   keep  <=>  not (ip32 + e < theta_q),  e = g ||q|| ||x|| + 2^-100,
+// with g = 2 gamma_d a bound on the rounding error of any summation order.
+// theta_q is the k-th best exact value over a smaller budget T0 <= T, whose
+// probed set is a prefix of the probed set of T.  Kept stored positions are
+// appended to the query's list (capacity cap); counts may exceed cap, which
+// the host detects.
+constexpr int SC_CHUNK = 2048;
+
+template <int W>
+__global__ __launch_bounds__(256) void k_screen(
+    const float *__restrict__ Xl, int d, int dp, const uint32_t *__restrict__ codes_l,
+    const double *__restrict__ key_l, const float *__restrict__ Q, int64_t nq,
+    const int32_t *__restrict__ chunks, int m, const uint32_t *__restrict__ qcodes,
+    const int32_t *__restrict__ ghthr, const int32_t *__restrict__ gtie,
+    const int32_t *__restrict__ gpstar, const float *__restrict__ ips0,
+    const int64_t *__restrict__ ids0, int k, float gam, int cap, int32_t *__restrict__ counts,
+    int32_t *__restrict__ lists)
+{
+    extern __shared__ float qs[];  // 64 x qstride
+    __shared__ float th_s[64], qn_s[64];
+    __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
+    __shared__ uint32_t qc_s[64 * W];
+    __shared__ int any_s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tile = blockIdx.x;
+    const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
+              pend = chunks[3 * blockIdx.y + 2];
+    const int qstride = dp + 4;
+    const int64_t q0 = (int64_t)tile * 64;
+
+    if (tid < 64) {
+        const int64_t q = q0 + tid;
+        int hthr = -1, htie = -1, pstar = -1;
+        float th = -INFINITY;
+        if (q < nq) {
+            hthr = ghthr[((int64_t)tile * m + j) * 64 + tid];
+            const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
+            if (tie[tid] == j) {
+                htie = tie[64 + tid];
+                pstar = gpstar[q];
+            }
+            if (ids0[q * k + k - 1] >= 0) {
+                const float f = ips0[q * k + k - 1];
+                th = f - fabsf(f) * 0x1p-22f - 0x1p-126f;  // <= the FP64 value f was rounded from
+            }
+#pragma unroll
+            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
+        }
+        hthr_s[tid] = hthr;
+        htie_s[tid] = htie;
+        pstar_s[tid] = pstar;
+        th_s[tid] = th;
+        const bool any = hthr >= 0 || htie >= 0;
+        const uint64_t b = __ballot(any);
+        if (tid == 0) any_s = b != 0ull;
+    }
+    __syncthreads();
+    if (!any_s) return;  // no query of this tile probes this chunk's sub-dataset
+
+    // stage the query tile, zero-padded to dp columns
+    for (int e = tid; e < 64 * dp; e += 256) {
+        const int r = e / dp, c = e - (e / dp) * dp;
+        const int64_t q = q0 + r;
+        qs[r * qstride + c] = (q < nq && c < d) ? Q[q * d + c] : 0.f;
+    }
+    __syncthreads();
+    if (tid < 64) {  // an upper bound on ||q||: exact squares, FP64 sum, rounded up
+        double s2 = 0.0;
+        for (int c = 0; c < d; ++c) s2 += (double)qs[tid * qstride + c] * (double)qs[tid * qstride + c];
+        qn_s[tid] = (float)__builtin_sqrt(s2) * (1.0f + 0x1p-18f);
+    }
+    __syncthreads();
+
+    const int r16 = lane & 15, g = lane >> 4;
+    for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
+        // this lane's two items (column blocks ib = 0, 1)
+        int32_t pit[2];
+        uint32_t cw[2][W];
+        float xn[2];
+        bool iv[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+            pit[ib] = p0 + 16 * ib + r16;
+            iv[ib] = pit[ib] < pend;
+            const int64_t pp = iv[ib] ? pit[ib] : pbeg;
+#pragma unroll
+            for (int w = 0; w < W; ++w) cw[ib][w] = codes_l[pp * W + w];
+            xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
+        }
+        floatx4 acc[4][2];
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < dp; kk += 16) {
+            const int kc = kk + 4 * g;
+            floatx4 bx[2];
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib)
+                bx[ib] = (iv[ib] && kc < dp)
+                             ? *reinterpret_cast<const floatx4 *>(Xl + (int64_t)pit[ib] * dp + kc)
+                             : floatx4{0.f, 0.f, 0.f, 0.f};
+            floatx4 aq[4];
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+                aq[qb] = kc < dp ? *reinterpret_cast<const floatx4 *>(&qs[(16 * qb + r16) * qstride + kc])
+                                 : floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj)
+#pragma unroll
+                for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                    for (int ib = 0; ib < 2; ++ib)
+                        acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x4f32(aq[qb][jj], bx[ib][jj],
+                                                                           acc[qb][ib], 0, 0, 0);
+        }
+        // epilogue: lane holds C[q = 16 qb + 4 g + v][item = 16 ib + r16]
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ql = 16 * qb + 4 * g + v;
+                const int hthr = hthr_s[ql], htie = htie_s[ql];
+                const float th = th_s[ql], qn = qn_s[ql];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
+                    if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
+                    const bool probed = h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]);
+                    const float ip = acc[qb][ib][v];
+                    const float e = gam * qn * xn[ib] + 0x1p-100f;
+                    if (iv[ib] && probed && !(ip + e < th)) {
+                        const int64_t q = q0 + ql;
+                        const int slot = atomicAdd(&counts[q], 1);
+                        if (slot < cap) lists[q * cap + slot] = pit[ib];
+                    }
+                }
+            }
+        }
+    }
+}
+
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -464,6 +648,45 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
     return hipGetLastError();
 }
 
+hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                             int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s)
+{
+    if (W == 1)
+        hipLaunchKernelGGL(k_tie_locate<1>, dim3(ceil_div(nq, 64)), dim3(64), 0, s, codes_l, off,
+                           qcodes, nq, gtie, gpstar);
+    else
+        hipLaunchKernelGGL(k_tie_locate<2>, dim3(ceil_div(nq, 64)), dim3(64), 0, s, codes_l, off,
+                           qcodes, nq, gtie, gpstar);
+    return hipGetLastError();
+}
+
+int screen_chunk_items() { return SC_CHUNK; }
+
+hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                         int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
+                         const int32_t *gtie, const int32_t *gpstar, const float *ips0,
+                         const int64_t *ids0, int cap, int32_t *counts, int32_t *lists,
+                         hipStream_t s)
+{
+    const double ud = (double)sh.d * 0x1p-24;
+    const float gam = (float)(2.0 * ud / (1.0 - ud) * (1.0 + 0x1p-16));
+    const size_t lds = (size_t)64 * (sh.dp + 4) * sizeof(float);
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    hipError_t e = hipFuncSetAttribute(sh.W == 1 ? (const void *)k_screen<1> : (const void *)k_screen<2>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_screen<1>, grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l, key_l, Q,
+                           nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, ips0, ids0, sh.k, gam,
+                           cap, counts, lists);
+    else
+        hipLaunchKernelGGL(k_screen<2>, grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l, key_l, Q,
+                           nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, ips0, ids0, sh.k, gam,
+                           cap, counts, lists);
+    return hipGetLastError();
+}
+
 int rerank_splits(int64_t nq, int64_t Tq)
 {
     // enough waves to cover the machine (256 CUs x 32 waves) without slices
@@ -476,9 +699,10 @@ int rerank_splits(int64_t nq, int64_t Tq)
     return (int)want;
 }
 
-hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
-                         const QueryShape &sh, const int32_t *cand, int nsplit, double *part_v,
-                         int32_t *part_i, int64_t *out_ids, float *out_ips, hipStream_t s)
+hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, int64_t nq,
+                         const QueryShape &sh, const int32_t *cand, const int32_t *counts,
+                         int nsplit, double *part_v, int32_t *part_i, int64_t *out_ids,
+                         float *out_ips, hipStream_t s)
 {
     const int S = (sh.k + 63) / 64;
     int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
@@ -486,8 +710,9 @@ hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, i
     const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
 #define NRLSH_RERANK(SS)                                                                         \
     do {                                                                                         \
-        hipLaunchKernelGGL(k_rerank<SS>, grid, block, 0, s, Xp, perm, Q, sh.n, sh.d, sh.dp,      \
-                           sh.Tq, sh.k, cand, nsplit, slice, out_ids, out_ips, part_v, part_i);  \
+        hipLaunchKernelGGL(k_rerank<SS>, grid, block, 0, s, Xl, perm, Q, sh.n, sh.d, sh.dp,      \
+                           sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips, part_v,   \
+                           part_i);                                                              \
         if (nsplit > 1)                                                                          \
             hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
                                nsplit, sh.k, out_ids, out_ips);                                  \

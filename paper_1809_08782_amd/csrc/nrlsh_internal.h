@@ -27,12 +27,10 @@ struct BuildCounters {
 };
 
 // ------------------------------------------------------------------ build
-// Squared norms in FP64 (ascending coordinate order) plus a zero-padded copy
-// of the items with row stride dp; also emits (key bits, index) pairs for the
-// radix sort and flags non-finite values.
-hipError_t launch_keys_copy(const float *X, int64_t n, int d, int dp, float *Xp, double *key,
-                            uint64_t *sort_key, int32_t *sort_val, BuildCounters *ctr,
-                            hipStream_t s);
+// Squared norms in FP64 (ascending coordinate order); also emits (key bits,
+// index) pairs for the radix sort and flags non-finite values.
+hipError_t launch_keys(const float *X, int64_t n, int d, double *key, uint64_t *sort_key,
+                       int32_t *sort_val, BuildCounters *ctr, hipStream_t s);
 
 // Stable LSD radix sort of (uint64 key, int32 value) pairs on bits
 // [0, nbits).  Buffers a/b are ping-pong; returns in *result_in_b whether the
@@ -48,24 +46,24 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
                                  int m, int32_t *sid, uint64_t *layout_key, int32_t *layout_val,
                                  double *keymax, hipStream_t s);
 
-// pos[perm[p]] = p
-hipError_t launch_invert_perm(const int32_t *perm, int64_t n, int32_t *pos, hipStream_t s);
+// Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
+// key and sub-dataset of each stored row.
+hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
+                         const double *key, const int32_t *sid, float *Xl, double *key_l,
+                         int32_t *sid_l, hipStream_t s);
 
-// SimpleLSH transform + sign random projection on the FP32 matrix cores.
-hipError_t launch_hash(const float *Xp, int64_t n, int d, int dp, const float *A, int L,
-                       const double *key, const int32_t *sid, const double *keymax,
-                       const double *U, const float *tau, uint32_t *codes_o, FixEntry *fix,
+// SimpleLSH transform + sign random projection on the FP32 matrix cores, over
+// the stored rows (all arrays in stored order); writes the codes codes_l.
+hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
+                       const double *key_l, const int32_t *sid_l, const double *keymax,
+                       const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
                        BuildCounters *ctr, hipStream_t s);
 
 // FP64 recompute of the flagged projections, exactly as the definition.
-hipError_t launch_hash_fixup(const float *Xp, int d, int dp, const float *A, int L,
-                             const double *key, const int32_t *sid, const double *keymax,
+hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L,
+                             const double *key_l, const int32_t *sid_l, const double *keymax,
                              const double *U, const FixEntry *fix, BuildCounters *ctr,
-                             uint32_t *codes_o, int64_t max_entries, hipStream_t s);
-
-// codes_l[p] = codes_o[perm[p]]  (W 32-bit words per code)
-hipError_t launch_permute_codes(const uint32_t *codes_o, const int32_t *perm, int64_t n, int W,
-                                uint32_t *codes_l, hipStream_t s);
+                             uint32_t *codes_l, int64_t max_entries, hipStream_t s);
 
 // ------------------------------------------------------------------ query
 struct QueryShape {
@@ -97,9 +95,27 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
 // Exact FP64 re-rank of the probed items and top-k selection.  Each query's
 // probed list is cut into nsplit slices (rerank_splits); with nsplit > 1 the
 // partial lists go to part_v / part_i (nq x nsplit x k) and are merged.
+// With counts != NULL, query q's list holds min(counts[q], Tq) entries (stride Tq).
 int rerank_splits(int64_t nq, int64_t Tq);
-hipError_t launch_rerank(const float *Xp, const int32_t *perm, const float *Q, int64_t nq,
-                         const QueryShape &sh, const int32_t *cand, int nsplit, double *part_v,
-                         int32_t *part_i, int64_t *out_ids, float *out_ips, hipStream_t s);
+hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, int64_t nq,
+                         const QueryShape &sh, const int32_t *cand, const int32_t *counts,
+                         int nsplit, double *part_v, int32_t *part_i, int64_t *out_ids,
+                         float *out_ips, hipStream_t s);
+
+// Stored position of the r*-th item of each query's threshold bucket (-1 if none).
+hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                             int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s);
+
+// Query-tiled FP32-MFMA screen of the probed set against theta (from the
+// exact top-k ips0 / ids0 of a smaller budget); appends kept stored positions
+// to lists (nq x cap) and counts every kept pair in counts (zeroed by caller).
+// chunks holds nchunks triples (sub-dataset, first, end) of <= screen_chunk_items().
+int screen_chunk_items();
+hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                         int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
+                         const int32_t *gtie, const int32_t *gpstar, const float *ips0,
+                         const int64_t *ids0, int cap, int32_t *counts, int32_t *lists,
+                         hipStream_t s);
 
 }  // namespace nrlsh

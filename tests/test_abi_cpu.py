@@ -80,6 +80,17 @@ def test_query_rejects_bad_arguments():
     assert L.nrlsh_query(fake, None, 0, 4, 10, None, None) == 0
 
 
+def test_query_rejects_unknown_rerank_mode():
+    L = nr.lib()
+    Q = np.ones((2, 4), np.float32)
+    ids = np.empty((2, 4), np.int64)
+    ips = np.empty((2, 4), np.float32)
+    fake = C.c_void_p(1)  # never dereferenced: argument checks come first
+    opts = _lib.QueryOpts(C.sizeof(_lib.QueryOpts), 0, None, 7)
+    assert L.nrlsh_query_ex(fake, Q.ctypes.data, 2, 4, 10, C.byref(opts), ids.ctypes.data,
+                            ips.ctypes.data) == INVALID
+
+
 def test_free_null_and_profile_registry():
     nr.lib().nrlsh_free(None)
     nr.nrlsh_profile_reset()

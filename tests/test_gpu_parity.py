@@ -62,6 +62,52 @@ def test_parity_large_budget_split_rerank(k):
             assert np.array_equal(ips, oips.astype(np.float32)), f"T={T}"
 
 
+SCREEN_CASES = [
+    # (n, d, m, L, nq, k, T)
+    (20000, 64, 8, 32, 150, 10, 20000),     # T = n: every item probed
+    (30011, 75, 16, 32, 130, 10, 4000),     # T < n: predicate with a cut bucket
+    (25000, 128, 32, 64, 64, 100, 25000),   # L = 64, k = 100
+    (12000, 300, 13, 17, 200, 16, 5000),    # d = 300, ragged L
+    (9000, 33, 1, 20, 70, 10, 3000),        # m = 1
+    (7000, 8, 4, 16, 65, 64, 6999),         # small d, T = n - 1
+]
+
+
+@pytest.mark.parametrize("case", SCREEN_CASES, ids=lambda c: "n%d_d%d_m%d_L%d_T%d" % (c[0], c[1], c[2], c[3], c[6]))
+def test_parity_screen_rerank(case):
+    """The query-tiled FP32 screen + FP64 re-rank gives the oracle's top-k."""
+    n, d, m, L, nq, k, T = case
+    say(f"case screen n={n} d={d} m={m} L={L} nq={nq} k={k} T={T}")
+    X = make_items("lognormal", n, d, seed=n + 3, sigma=0.9)
+    Q = make_queries(nq, d, seed=n + 4)
+    oix = orc.OracleIndex(X, m, L, seed=17, threads=8)
+    with nr.nrlsh_build(X, m, L, 17) as gix:
+        ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="screen")
+        oids, oips = oix.query(Q, k, T, threads=8)
+        assert np.array_equal(ids, oids)
+        assert np.array_equal(ips, oips.astype(np.float32))
+        gi, gp = nr.nrlsh_query(gix, Q, k, T, rerank="gather")
+        assert np.array_equal(gi, ids) and np.array_equal(gp, ips)
+
+
+def test_screen_with_duplicates_and_zero_rows():
+    say("case screen duplicates")
+    n, d = 8000, 24
+    X = make_items("lognormal", n, d, seed=71, sigma=0.7)
+    X[100:900] = 0.0
+    X[2000:2100] = X[5000]
+    Q = make_queries(80, d, seed=72)
+    Q[5] = X[5000] / np.linalg.norm(X[5000])
+    Q[6] = 0.0
+    oix = orc.OracleIndex(X, 10, 32, seed=5, threads=8)
+    with nr.nrlsh_build(X, 10, 32, 5) as gix:
+        for T in (3000, n):
+            ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank="screen")
+            oids, oips = oix.query(Q, 10, T, threads=8)
+            assert np.array_equal(ids, oids), f"T={T}"
+            assert np.array_equal(ips, oips.astype(np.float32)), f"T={T}"
+
+
 def test_parity_tiny_config():
     """The small recipe end to end: n = 1e4, d = 64, m = 8, L = 16, 100 queries,
     top-10, budget 500."""
