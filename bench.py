@@ -146,8 +146,8 @@ def main():
         nr.nrlsh_profile_enable(False)
         return el / steps
 
-    names = ["keys", "sort", "hash", "hash_fixup", "qhash", "scan_hist", "threshold", "scan_emit",
-             "rerank"]
+    names = ["keys", "sort", "layout", "hash", "hash_fixup", "qhash", "scan_hist", "threshold",
+             "tie_locate", "scan_emit", "rerank", "screen", "rerank_exact"]
     # unprofiled timing for the headline, profiled run for the per-kernel split
     s_step = timed(T_op, args.steps, args.warmup, False)
     ids_op = ids_buf.clone()

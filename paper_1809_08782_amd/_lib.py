@@ -104,7 +104,8 @@ def header_symbols() -> list:
     """Function names declared in include/nrlsh.h."""
     with open(HEADER_PATH) as f:
         text = f.read()
-    return sorted(set(re.findall(r"\b(nrlsh_[a-z_0-9]+)\s*\(", text)))
+    decl = r"^(?:nrlsh_status|void|const char\s*\*)\s*\*?\s*(nrlsh_[a-z_0-9]+)\s*\("
+    return sorted(set(re.findall(decl, text, re.M)))
 
 
 def _check(status: int):

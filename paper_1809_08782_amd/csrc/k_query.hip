@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_screen(
     const int64_t *__restrict__ ids0, int k, float gam, int cap, int32_t *__restrict__ counts,
     int32_t *__restrict__ lists)
 {
-    extern __shared__ float qs[];  // 64 x qstride
+    extern __shared__ __align__(16) float qs[];  // 64 x qstride
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * W];
