@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
+FP32_MFMA_PEAK_TFS = 157.3  # MI355X dense FP32 matrix
 
 
 def log(*a):
@@ -147,9 +148,10 @@ def main():
         return el / steps
 
     names = ["keys", "sort", "layout", "hash", "hash_fixup", "qhash", "scan_hist", "threshold",
-             "tie_locate", "scan_emit", "rerank", "screen", "rerank_exact"]
+             "tie_locate", "scan_emit", "rerank", "screen_max", "screen", "rerank_exact"]
     # unprofiled timing for the headline, profiled run for the per-kernel split
     s_step = timed(T_op, args.steps, args.warmup, False)
+    qstats = nr.nrlsh_get_query_stats()
     ids_op = ids_buf.clone()
     timed(T_op, max(2, args.steps // 2), 0, True)
     kern = {}
@@ -167,16 +169,25 @@ def main():
                             "recall": curve.get(T)})
             log(f"budget T={T}: {st * 1e3:.2f} ms/step recall {curve.get(T)}")
 
-    # ---------------------------------------------------------------- roofline (rerank)
+    # ---------------------------------------------------------------- roofline
     Tq = min(T_op, w.n)
     dom = max(kern, key=lambda nm: kern[nm]["avg_ms"] * kern[nm]["launches_per_step"]) if kern else None
     roof = None
-    if "rerank" in kern:
-        # algorithmic bytes per candidate: its row (4d), its stored position and id (8)
-        launches = kern["rerank"]["launches_per_step"]
+    if dom == "screen":
+        # algorithmic work of one screen launch: the FP32 inner products of the
+        # probed pairs, 2 d flop each ((queries per launch) x T pairs)
+        launches = kern["screen"]["launches_per_step"]
+        flops = 2.0 * w.d * (w.nq / launches) * Tq
+        achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
+        roof = {"kernel": "screen", "bound": "mfma", "achieved": achieved,
+                "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFS,
+                "traffic": None, "flops_per_launch": flops, "dominant_kernel": dom}
+    elif dom in ("rerank", "rerank_exact"):
+        # algorithmic bytes per probed item: its row (4d), stored position and id (8)
+        launches = kern[dom]["launches_per_step"]
         per_launch_bytes = (w.nq / launches) * Tq * (4 * w.d + 8)
-        achieved = per_launch_bytes / (kern["rerank"]["avg_ms"] * 1e-3) / 1e9
-        roof = {"kernel": "rerank", "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+        achieved = per_launch_bytes / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": per_launch_bytes, "dominant_kernel": dom}
 
@@ -219,6 +230,7 @@ def main():
         "kernels": kern,
         "hashed_items_per_s": (w.n / (kern["hash"]["avg_ms"] * 1e-3)) if "hash" in kern else None,
         "build_stats": build_stats,
+        "query_stats": qstats,
         "norm_stats": norm_stats,
         "roofline": roof,
         "cpu_baseline": cpu,

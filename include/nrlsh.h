@@ -175,12 +175,22 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
 nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
                                     int64_t probe_budget, int64_t *cand);
 
+/* Re-rank statistics of this thread's last nrlsh_query / nrlsh_query_ex. */
+typedef struct nrlsh_query_stats {
+    int32_t mode;          /* nrlsh_rerank_mode actually used (GATHER or SCREEN) */
+    int32_t screen_passes; /* screen launches (more than one per batch = a list overflowed) */
+    int64_t kept_total;    /* SCREEN: pairs kept for the exact re-rank, all queries */
+    int64_t kept_max;      /* SCREEN: largest kept list of one query */
+} nrlsh_query_stats;
+
+nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);
+
 /* ------------------------------------------------------------ profiling --
  * Optional per-kernel timing with HIP events recorded on the stream each
  * kernel is launched on.  Off by default; enabling adds one event pair per
  * timed launch.  Names: "keys", "sort", "layout", "hash", "hash_fixup",
  * "qhash", "scan_hist", "threshold", "scan_emit", "rerank", "tie_locate",
- * "screen", "rerank_exact". */
+ * "screen_max", "screen", "rerank_exact". */
 void nrlsh_profile_enable(int32_t on);
 void nrlsh_profile_reset(void);
 /* Total milliseconds and launch count of kernel `name` since the last reset. */

@@ -46,6 +46,11 @@ class BuildStats(C.Structure):
                 ("recompute_flips", C.c_int64)]
 
 
+class QueryStats(C.Structure):
+    _fields_ = [("mode", C.c_int32), ("screen_passes", C.c_int32), ("kept_total", C.c_int64),
+                ("kept_max", C.c_int64)]
+
+
 _lib = None
 P = C.c_void_p
 I32, I64, U64, F64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -90,6 +95,8 @@ def lib():
         L.nrlsh_query_codes.restype = st
         L.nrlsh_query_candidates.argtypes = [P, P, I64, I64, P]
         L.nrlsh_query_candidates.restype = st
+        L.nrlsh_get_query_stats.argtypes = [C.POINTER(QueryStats)]
+        L.nrlsh_get_query_stats.restype = st
         L.nrlsh_profile_enable.argtypes = [I32]
         L.nrlsh_profile_enable.restype = None
         L.nrlsh_profile_reset.argtypes = []
@@ -286,6 +293,15 @@ def nrlsh_free(ix: Index):
 
 def nrlsh_last_error() -> str:
     return lib().nrlsh_last_error().decode(errors="replace")
+
+
+def nrlsh_get_query_stats() -> dict:
+    """Re-rank statistics of this thread's last query call."""
+    st = QueryStats()
+    _check(lib().nrlsh_get_query_stats(C.byref(st)))
+    return {"mode": {1: "gather", 2: "screen"}.get(st.mode, "none"),
+            "screen_passes": st.screen_passes, "kept_total": st.kept_total,
+            "kept_max": st.kept_max}
 
 
 def nrlsh_profile_enable(on: bool = True):

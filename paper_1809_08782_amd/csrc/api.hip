@@ -26,6 +26,7 @@ using namespace nrlsh;
 namespace {
 
 thread_local std::string g_err;
+thread_local nrlsh_query_stats g_qstats;
 
 nrlsh_status fail(nrlsh_status st, const char *fmt, ...)
 {
@@ -531,47 +532,54 @@ bool screen_fits(const nrlsh_index *ix)
     return screen_lds_bytes(ix) <= (size_t)lim;
 }
 
-// Screen path: threshold theta_q from an exact re-rank at budget T0 <= T,
-// query-tiled MFMA screen of the probed set, exact re-rank of the kept pairs.
+// Screen path: (1) theta_q from the largest FP32 lower bounds of small cells
+// of the highest-norm sub-datasets, (2) query-tiled MFMA screen of the whole
+// probed set against theta_q, (3) exact FP64 re-rank of the kept pairs.
+std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo)
+{
+    std::vector<int32_t> ch;
+    for (int j = ix->m - 1; j >= j_lo; --j)
+        for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += items) {
+            ch.push_back(j);
+            ch.push_back((int32_t)p);
+            ch.push_back((int32_t)std::min<int64_t>(p + items, ix->off_h[j + 1]));
+        }
+    return ch;
+}
+
 void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
                       int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
                       uint32_t *nonfinite_d)
 {
     const QueryShape sh = make_shape(ix, T, k);
-    const int64_t T0 = std::min<int64_t>(sh.Tq, std::max<int64_t>(1024, 4 * (int64_t)k));
-    const QueryShape sh0 = make_shape(ix, T0, k);
     int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
     int64_t cap = std::min<int64_t>(sh.Tq, 1024);
 
-    // chunks of <= screen_chunk_items() stored items inside one sub-dataset
-    std::vector<int32_t> ch;
-    for (int j = 0; j < sh.m; ++j)
-        for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += screen_chunk_items()) {
-            ch.push_back(j);
-            ch.push_back((int32_t)p);
-            ch.push_back((int32_t)std::min<int64_t>(p + screen_chunk_items(), ix->off_h[j + 1]));
-        }
-    const int nchunks = (int)(ch.size() / 3);
-    DBuf<int32_t> chunks(ch.size(), s);
+    // pass-1 cells: the top sub-datasets in cells of screen_cell_items(), at
+    // least max(64, 4k) of them; pass-2 chunks: every sub-dataset
+    const int64_t want = std::max<int64_t>(64, 4 * (int64_t)k);
+    int j_lo = ix->m - 1;
+    while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
+    std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo);
+    std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
+    const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
+    DBuf<int32_t> cells(ce.size(), s), chunks(ch.size(), s);
+    HIPX(hipMemcpyAsync(cells.get(), ce.data(), ce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
     DBuf<uint32_t> qcodes((size_t)B * sh.W, s);
     DBuf<uint32_t> ghist((size_t)tiles * sh.m * L1 * 64, s);
-    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s), gbase0((size_t)tiles * (sh.m + 1) * 64, s);
-    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s), ghthr0((size_t)tiles * sh.m * 64, s);
-    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s), gtie0((size_t)tiles * 4 * 64, s);
+    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s);
+    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
+    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
     DBuf<int32_t> gpstar((size_t)B, s);
-    DBuf<int32_t> cand0((size_t)B * T0, s);
-    DBuf<int64_t> ids0((size_t)B * k, s);
-    DBuf<float> ips0((size_t)B * k, s);
+    DBuf<float> cmax((size_t)B * ncells, s);
+    DBuf<float> theta((size_t)B, s);
     DBuf<int32_t> counts((size_t)B, s);
     DBuf<int32_t> lists((size_t)B * cap, s);
     std::vector<int32_t> hcounts((size_t)B);
-    const int nsplit0 = rerank_splits(B, T0);
-    DBuf<double> part_v(nsplit0 > 1 ? (size_t)B * nsplit0 * k : 1, s);
-    DBuf<int32_t> part_i(nsplit0 > 1 ? (size_t)B * nsplit0 * k : 1, s);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
@@ -584,36 +592,37 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         tm.begin("threshold");
         HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
                               ghthr.get(), gtie.get(), s));
-        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh0, gbase0.get(),
-                              ghthr0.get(), gtie0.get(), s));
         tm.end();
         tm.begin("tie_locate");
         HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, gtie.get(),
                                gpstar.get(), s));
         tm.end();
-        // theta: exact top-k over the probed set of the budget T0 (a prefix of the T set)
-        tm.begin("scan_emit");
-        HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh0, gbase0.get(),
-                              ghthr0.get(), gtie0.get(), cand0.get(), s));
-        tm.end();
-        tm.begin("rerank");
-        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh0, cand0.get(), nullptr, nsplit0,
-                           part_v.get(), part_i.get(), ids0.get(), ips0.get(), s));
+        tm.begin("screen_max");
+        HIPX(launch_screen_max(ix->Xl.get(), ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+                               cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),
+                               gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
         for (;;) {
             HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("screen");
             HIPX(launch_screen(ix->Xl.get(), ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
                                chunks.get(), nchunks, qcodes.get(), ghthr.get(), gtie.get(),
-                               gpstar.get(), ips0.get(), ids0.get(), (int)cap, counts.get(),
-                               lists.get(), s));
+                               gpstar.get(), theta.get(), (int)cap, counts.get(), lists.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hcounts.data(), counts.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
-            int64_t mx = 0;
-            for (int64_t i = 0; i < nb; ++i) mx = std::max<int64_t>(mx, hcounts[i]);
-            if (mx <= cap) break;
+            int64_t mx = 0, tot = 0;
+            for (int64_t i = 0; i < nb; ++i) {
+                mx = std::max<int64_t>(mx, hcounts[i]);
+                tot += hcounts[i];
+            }
+            g_qstats.screen_passes += 1;
+            if (mx <= cap) {
+                g_qstats.kept_total += tot;
+                g_qstats.kept_max = std::max<int64_t>(g_qstats.kept_max, mx);
+                break;
+            }
             // a list overflowed: grow the lists and screen this batch again
             cap = std::min<int64_t>(sh.Tq, std::max<int64_t>(mx, 2 * cap));
             lists = DBuf<int32_t>((size_t)B * cap, s);
@@ -637,6 +646,7 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     bool screen = mode == NRLSH_RERANK_SCREEN ||
                   (mode == NRLSH_RERANK_AUTO && Tq * 40 >= ix->n && nq >= 64 && Tq >= 2048);
     if (screen && !screen_fits(ix)) screen = false;
+    g_qstats.mode = screen ? NRLSH_RERANK_SCREEN : NRLSH_RERANK_GATHER;
     if (screen)
         run_query_screen(ix, Qd, nq, k, T, ids_d, ips_d, s, tm, nonfinite_d);
     else
@@ -718,6 +728,7 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
 {
     nrlsh_status st = validate_query(ix, queries, nq, k, probe_budget, out_ids, out_ips);
     if (st != NRLSH_OK) return st;
+    g_qstats = nrlsh_query_stats{};
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)) &&
         (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN))
         return fail(NRLSH_E_INVALID_ARG, "rerank_mode %d unknown", opts->rerank_mode);
@@ -905,6 +916,13 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
         }
         return NRLSH_OK;
     });
+}
+
+nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st)
+{
+    if (!st) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    *st = g_qstats;
+    return NRLSH_OK;
 }
 
 void nrlsh_profile_enable(int32_t on) { g_prof_on.store(on ? 1 : 0); }

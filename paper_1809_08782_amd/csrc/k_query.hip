@@ -118,6 +118,7 @@ __global__ __launch_bounds__(64) void k_threshold(const uint32_t *__restrict__ g
 
     int64_t cum = 0;
     int32_t bstar = -1, rstar = 0, jstar = -1, hstar = -1;
+    bool rfull = false;  // the budget ends exactly at the end of bucket b*
     bool done = !valid;
     for (int64_t b = 0; b < P; b += 16) {
         if (__ballot(!done) == 0ull) break;
@@ -134,6 +135,7 @@ __global__ __launch_bounds__(64) void k_threshold(const uint32_t *__restrict__ g
                 if (cum + (int64_t)c[u] >= Tq) {
                     bstar = (int32_t)(b + u);
                     rstar = (int32_t)(Tq - cum);
+                    rfull = cum + (int64_t)c[u] == Tq;
                     jstar = io[u] / L1;
                     hstar = io[u] - jstar * L1;
                     done = true;
@@ -164,7 +166,7 @@ __global__ __launch_bounds__(64) void k_threshold(const uint32_t *__restrict__ g
     int32_t *tie = gtie + (int64_t)tile * 4 * 64;
     tie[0 * 64 + lane] = valid ? jstar : -1;
     tie[1 * 64 + lane] = hstar;
-    tie[2 * 64 + lane] = rstar;
+    tie[2 * 64 + lane] = rfull ? INT_MAX : rstar;  // INT_MAX: every item of the bucket
     tie[3 * 64 + lane] = bstar;
 }
 
@@ -420,64 +422,94 @@ __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ pa
 // Stored position of the r*-th item of the threshold bucket (j*, h*) of each
 // query: with it the probed set becomes a per-pair predicate,
 //   p in C_T  <=>  h <= hthr[q][j]  or  (j = j*, h = h*, p <= P*).
+// One wave per query walks sub-dataset j* 64 items at a time; a bucket that
+// is probed whole (r* = INT_MAX) needs no walk.
 template <int W>
-__global__ __launch_bounds__(64) void k_tie_locate(const uint32_t *__restrict__ codes_l,
-                                                   const int32_t *__restrict__ off,
-                                                   const uint32_t *__restrict__ qcodes,
-                                                   int64_t nq, const int32_t *__restrict__ gtie,
-                                                   int32_t *__restrict__ gpstar)
+__global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__ codes_l,
+                                                    const int32_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ qcodes,
+                                                    int64_t nq, const int32_t *__restrict__ gtie,
+                                                    int32_t *__restrict__ gpstar)
 {
-    const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     if (q >= nq) return;
-    const int tile = (int)(q >> 6), lane = (int)(q & 63);
+    const int tile = (int)(q >> 6), ql = (int)(q & 63);
     const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
-    const int jstar = tie[lane], hstar = tie[64 + lane], rstar = tie[128 + lane];
+    const int jstar = tie[ql], hstar = tie[64 + ql], rstar = tie[128 + ql];
     int32_t P = -1;
-    if (jstar >= 0) {
+    if (jstar >= 0 && rstar == INT_MAX) {
+        P = INT_MAX;
+    } else if (jstar >= 0) {
         const uint32_t q0 = qcodes[q * W], q1 = W == 2 ? qcodes[q * W + 1] : 0u;
+        const int64_t pe = off[jstar + 1];
         int cnt = 0;
-        for (int64_t p = off[jstar]; p < off[jstar + 1]; ++p) {
-            int h = __popc(codes_l[p * W] ^ q0);
-            if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
-            if (h == hstar && ++cnt == rstar) {
-                P = (int32_t)p;
+        for (int64_t p0 = off[jstar]; p0 < pe; p0 += 64) {
+            const int64_t p = p0 + lane;
+            bool match = false;
+            if (p < pe) {
+                int h = __popc(codes_l[p * W] ^ q0);
+                if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+                match = h == hstar;
+            }
+            const uint64_t bal = __ballot(match);
+            const int c = __popcll(bal);
+            if (cnt + c >= rstar) {
+                const int need = rstar - cnt;  // 1-based rank inside this group
+                const int rank = __popcll(bal & ((1ull << lane) - 1ull));
+                const uint64_t sel = __ballot(match && rank == need - 1);
+                P = (int32_t)(p0 + __ffsll((long long)sel) - 1);
                 break;
             }
+            cnt += c;
         }
     }
-    gpstar[q] = P;
+    if (lane == 0) gpstar[q] = P;
 }
 
 // ---------------------------------------------------------------- screen
 // Query-tiled screen of the probed set on the FP32 matrix cores.  A block
-// holds 64 queries (staged in LDS) and one chunk of <= SC_CHUNK stored items
-// of a single sub-dataset; each wave computes 64 queries x 32 items per
-// iteration with v_mfma_f32_16x16x4_f32 (queries = M, items = N).  A pair is
-// kept for the exact re-rank when it is probed (the predicate above) and its
-// FP32 inner product can still reach theta_q, a lower bound on the k-th best
-// exact inner product of the probed set:
-//   keep  <=>  not (ip32 + e < theta_q),  e = g ||q|| ||x|| + 2^-100,
-// with g = 2 gamma_d a bound on the rounding error of any summation order.
-// theta_q is the k-th best exact value over a smaller budget T0 <= T, whose
-// probed set is a prefix of the probed set of T.  Kept stored positions are
-// appended to the query's list (capacity cap); counts may exceed cap, which
-// the host detects.
+// holds 64 queries (staged in LDS) and one chunk of stored items of a single
+// sub-dataset; each wave computes 64 queries x 32 items per iteration with
+// v_mfma_f32_16x16x4_f32 (queries = M, items = N).  With e = g ||q|| ||x||
+// + 2^-100, g = 2 gamma_d (a bound on the rounding error of any summation
+// order), every probed pair satisfies ip32 - e <= ip <= ip32 + e.
+//   MAXMODE = true : writes, per (query, chunk), the largest lower bound
+//                    ip32 - e over the chunk's probed items (-inf if none).
+//                    The k-th largest of these over distinct chunks is a lower
+//                    bound theta_q of the k-th best exact inner product.
+//   MAXMODE = false: keeps every probed pair with not (ip32 + e < theta_q)
+//                    and appends its stored position to the query's list
+//                    (capacity cap; counts may exceed cap, which the host
+//                    detects).  The exact top-k of the probed set lies in it.
 constexpr int SC_CHUNK = 2048;
+constexpr int SC_CELL = 256;
 
-template <int W>
+__device__ __forceinline__ uint32_t f2ord(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(uint32_t o)
+{
+    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+template <int W, bool MAXMODE>
 __global__ __launch_bounds__(256) void k_screen(
     const float *__restrict__ Xl, int d, int dp, const uint32_t *__restrict__ codes_l,
     const double *__restrict__ key_l, const float *__restrict__ Q, int64_t nq,
     const int32_t *__restrict__ chunks, int m, const uint32_t *__restrict__ qcodes,
     const int32_t *__restrict__ ghthr, const int32_t *__restrict__ gtie,
-    const int32_t *__restrict__ gpstar, const float *__restrict__ ips0,
-    const int64_t *__restrict__ ids0, int k, float gam, int cap, int32_t *__restrict__ counts,
-    int32_t *__restrict__ lists)
+    const int32_t *__restrict__ gpstar, const float *__restrict__ theta, float gam, int cap,
+    int32_t *__restrict__ counts, int32_t *__restrict__ lists, float *__restrict__ cmax,
+    int ncol)
 {
     extern __shared__ __align__(16) float qs[];  // 64 x qstride
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * W];
+    __shared__ uint32_t mx_s[64];
     __shared__ int any_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
@@ -497,10 +529,7 @@ __global__ __launch_bounds__(256) void k_screen(
                 htie = tie[64 + tid];
                 pstar = gpstar[q];
             }
-            if (ids0[q * k + k - 1] >= 0) {
-                const float f = ips0[q * k + k - 1];
-                th = f - fabsf(f) * 0x1p-22f - 0x1p-126f;  // <= the FP64 value f was rounded from
-            }
+            if (!MAXMODE) th = theta[q];
 #pragma unroll
             for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
         }
@@ -508,18 +537,20 @@ __global__ __launch_bounds__(256) void k_screen(
         htie_s[tid] = htie;
         pstar_s[tid] = pstar;
         th_s[tid] = th;
-        const bool any = hthr >= 0 || htie >= 0;
-        const uint64_t b = __ballot(any);
+        mx_s[tid] = f2ord(-INFINITY);
+        const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
         if (tid == 0) any_s = b != 0ull;
     }
     __syncthreads();
-    if (!any_s) return;  // no query of this tile probes this chunk's sub-dataset
+    if (!any_s) {  // no query of this tile probes this chunk
+        if (MAXMODE && tid < 64 && q0 + tid < nq) cmax[(q0 + tid) * ncol + blockIdx.y] = -INFINITY;
+        return;
+    }
 
     // stage the query tile, zero-padded to dp columns
-    for (int e = tid; e < 64 * dp; e += 256) {
-        const int r = e / dp, c = e - (e / dp) * dp;
+    for (int r = wave; r < 64; r += 4) {
         const int64_t q = q0 + r;
-        qs[r * qstride + c] = (q < nq && c < d) ? Q[q * d + c] : 0.f;
+        for (int c = lane; c < dp; c += 64) qs[r * qstride + c] = (q < nq && c < d) ? Q[q * d + c] : 0.f;
     }
     __syncthreads();
     if (tid < 64) {  // an upper bound on ||q||: exact squares, FP64 sum, rounded up
@@ -530,6 +561,11 @@ __global__ __launch_bounds__(256) void k_screen(
     __syncthreads();
 
     const int r16 = lane & 15, g = lane >> 4;
+    float wmax[4][4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) wmax[qb][v] = -INFINITY;
     for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
         // this lane's two items (column blocks ib = 0, 1)
         int32_t pit[2];
@@ -584,10 +620,13 @@ __global__ __launch_bounds__(256) void k_screen(
                 for (int ib = 0; ib < 2; ++ib) {
                     int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
                     if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
-                    const bool probed = h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]);
+                    const bool probed =
+                        iv[ib] && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-100f;
-                    if (iv[ib] && probed && !(ip + e < th)) {
+                    if (MAXMODE) {
+                        if (probed) wmax[qb][v] = fmaxf(wmax[qb][v], ip - e);
+                    } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
                         if (slot < cap) lists[q * cap + slot] = pit[ib];
@@ -595,6 +634,43 @@ __global__ __launch_bounds__(256) void k_screen(
                 }
             }
         }
+    }
+    if (MAXMODE) {
+        // reduce over the 16 lanes that share a query, then across the waves
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float x = wmax[qb][v];
+#pragma unroll
+                for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+                if (r16 == 0) atomicMax(&mx_s[16 * qb + 4 * g + v], f2ord(x));
+            }
+        __syncthreads();
+        if (tid < 64 && q0 + tid < nq) cmax[(q0 + tid) * ncol + blockIdx.y] = ord2f(mx_s[tid]);
+    }
+}
+
+// theta_q = the k-th largest chunk maximum (a lower bound of the k-th best
+// exact inner product), lowered by 2^-22 relative to cover float rounding;
+// -inf when fewer than k chunks hold probed items.  One wave per query.
+template <int S>
+__global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int ncol, int k,
+                                              float *__restrict__ theta)
+{
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    WaveTopK<S> top;
+    top.init(k);
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+        const int c = c0 + lane;
+        const float v = c < ncol ? cmax[q * ncol + c] : -INFINITY;
+        top.offer((double)v, c, c < ncol && v > -INFINITY, lane);
+    }
+    const double kth = __shfl(top.tv[top.ks], top.kl, 64);
+    if (lane == 0) {
+        const float f = (float)kth;
+        theta[q] = kth == -INFINITY ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
     }
 }
 
@@ -652,39 +728,70 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
                              int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s)
 {
     if (W == 1)
-        hipLaunchKernelGGL(k_tie_locate<1>, dim3(ceil_div(nq, 64)), dim3(64), 0, s, codes_l, off,
+        hipLaunchKernelGGL(k_tie_locate<1>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
                            qcodes, nq, gtie, gpstar);
     else
-        hipLaunchKernelGGL(k_tie_locate<2>, dim3(ceil_div(nq, 64)), dim3(64), 0, s, codes_l, off,
+        hipLaunchKernelGGL(k_tie_locate<2>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
                            qcodes, nq, gtie, gpstar);
     return hipGetLastError();
 }
 
 int screen_chunk_items() { return SC_CHUNK; }
+int screen_cell_items() { return SC_CELL; }
 
-hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
-                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
-                         int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
-                         const int32_t *gtie, const int32_t *gpstar, const float *ips0,
-                         const int64_t *ids0, int cap, int32_t *counts, int32_t *lists,
-                         hipStream_t s)
+template <bool MAXMODE>
+static hipError_t launch_screen_t(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                                  const float *Q, int64_t nq, const QueryShape &sh,
+                                  const int32_t *chunks, int nchunks, const uint32_t *qcodes,
+                                  const int32_t *ghthr, const int32_t *gtie,
+                                  const int32_t *gpstar, const float *theta, int cap,
+                                  int32_t *counts, int32_t *lists, float *cmax, hipStream_t s)
 {
     const double ud = (double)sh.d * 0x1p-24;
     const float gam = (float)(2.0 * ud / (1.0 - ud) * (1.0 + 0x1p-16));
     const size_t lds = (size_t)64 * (sh.dp + 4) * sizeof(float);
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
-    hipError_t e = hipFuncSetAttribute(sh.W == 1 ? (const void *)k_screen<1> : (const void *)k_screen<2>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const void *fn = sh.W == 1 ? (const void *)k_screen<1, MAXMODE> : (const void *)k_screen<2, MAXMODE>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (sh.W == 1)
-        hipLaunchKernelGGL(k_screen<1>, grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l, key_l, Q,
-                           nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, ips0, ids0, sh.k, gam,
-                           cap, counts, lists);
+        hipLaunchKernelGGL((k_screen<1, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
+                           key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
+                           counts, lists, cmax, nchunks);
     else
-        hipLaunchKernelGGL(k_screen<2>, grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l, key_l, Q,
-                           nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, ips0, ids0, sh.k, gam,
-                           cap, counts, lists);
+        hipLaunchKernelGGL((k_screen<2, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
+                           key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
+                           counts, lists, cmax, nchunks);
     return hipGetLastError();
+}
+
+hipError_t launch_screen_max(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
+                             int ncells, const uint32_t *qcodes, const int32_t *ghthr,
+                             const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
+                             hipStream_t s)
+{
+    hipError_t e = launch_screen_t<true>(Xl, key_l, codes_l, Q, nq, sh, cells, ncells, qcodes, ghthr,
+                                         gtie, gpstar, nullptr, 0, nullptr, nullptr, cmax, s);
+    if (e != hipSuccess) return e;
+    const int S = (sh.k + 63) / 64;
+    const dim3 grid((unsigned)nq), block(64);
+    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                         int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
+                         const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
+                         int32_t *counts, int32_t *lists, hipStream_t s)
+{
+    return launch_screen_t<false>(Xl, key_l, codes_l, Q, nq, sh, chunks, nchunks, qcodes, ghthr,
+                                  gtie, gpstar, theta, cap, counts, lists, nullptr, s);
 }
 
 int rerank_splits(int64_t nq, int64_t Tq)

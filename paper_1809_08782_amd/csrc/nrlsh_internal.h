@@ -106,16 +106,25 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
                              int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s);
 
-// Query-tiled FP32-MFMA screen of the probed set against theta (from the
-// exact top-k ips0 / ids0 of a smaller budget); appends kept stored positions
-// to lists (nq x cap) and counts every kept pair in counts (zeroed by caller).
-// chunks holds nchunks triples (sub-dataset, first, end) of <= screen_chunk_items().
+// Query-tiled FP32-MFMA screen of the probed set.  Chunks / cells are
+// (sub-dataset, first, end) triples of stored items.
+//   launch_screen_max: per (query, cell) the largest FP32 lower bound over the
+//     cell's probed items, then theta[q] = the k-th largest of them (lowered
+//     for rounding; -inf if fewer than k cells hold probed items).
+//   launch_screen: appends every probed pair whose FP32 upper bound reaches
+//     theta[q] to lists (nq x cap) and counts all of them (counts zeroed by
+//     the caller; counts[q] > cap means the list overflowed).
 int screen_chunk_items();
+int screen_cell_items();
+hipError_t launch_screen_max(const float *Xl, const double *key_l, const uint32_t *codes_l,
+                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
+                             int ncells, const uint32_t *qcodes, const int32_t *ghthr,
+                             const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
+                             hipStream_t s);
 hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
                          const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
-                         const int32_t *gtie, const int32_t *gpstar, const float *ips0,
-                         const int64_t *ids0, int cap, int32_t *counts, int32_t *lists,
-                         hipStream_t s);
+                         const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
+                         int32_t *counts, int32_t *lists, hipStream_t s);
 
 }  // namespace nrlsh
