@@ -164,9 +164,15 @@ def main():
     budgets = []
     if not args.no_budgets:
         for T in w.budgets:
-            st = timed(T, max(2, args.steps // 2), 1, False)
+            st = timed(T, max(2, args.steps // 2), 1, True)
+            bk = {}
+            for nm in names:
+                ms, cnt = nr.nrlsh_profile_get(nm)
+                if cnt:
+                    bk[nm] = round(ms / max(2, args.steps // 2), 3)
             budgets.append({"T": T, "frac_of_n": T / w.n, "qps": w.nq / st, "ms_per_step": st * 1e3,
-                            "recall": curve.get(T)})
+                            "recall": curve.get(T), "query_stats": nr.nrlsh_get_query_stats(),
+                            "kernel_ms_per_step": bk})
             log(f"budget T={T}: {st * 1e3:.2f} ms/step recall {curve.get(T)}")
 
     # ---------------------------------------------------------------- roofline
