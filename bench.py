@@ -65,6 +65,8 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=256, help="queries the oracle baseline times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rerank", default="auto", choices=["auto", "gather", "screen", "screen_fp32"],
+                    help="re-rank mode (all give identical results)")
     ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the untimed recall sweep (needs --budget); used under a profiler so "
@@ -129,7 +131,7 @@ def main():
     # ---------------------------------------------------------------- timed steps
     def step(T):
         with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed) as sx:
-            nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf))
+            nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf), rerank=args.rerank)
 
     def timed(T, steps, warmup, profile):
         for i in range(warmup):

@@ -108,13 +108,20 @@ nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq
                          int64_t probe_budget, int64_t *out_ids, float *out_ips);
 
 /* How the probed items are re-ranked; every mode returns the same result.
- *   GATHER: each query's probed list is materialised and its rows gathered.
- *   SCREEN: queries are tiled 64 at a time against chunks of stored rows on
- *           the FP32 matrix cores; pairs that are probed and whose FP32 inner
- *           product (with a rigorous rounding bound) can still reach a lower
- *           bound of the k-th best are re-ranked exactly in FP64.
- *   AUTO:   SCREEN for large budgets (T >= n/40, >= 64 queries), else GATHER. */
-typedef enum { NRLSH_RERANK_AUTO = 0, NRLSH_RERANK_GATHER = 1, NRLSH_RERANK_SCREEN = 2 } nrlsh_rerank_mode;
+ *   GATHER:      each query's probed list is materialised and its rows gathered.
+ *   SCREEN:      queries are tiled 64 at a time against chunks of stored rows on
+ *                the matrix cores with a bfloat16 hi/lo split (three bf16
+ *                products per pair); pairs that are probed and whose inner
+ *                product (with a rigorous rounding bound) can still reach a
+ *                lower bound of the k-th best are re-ranked exactly in FP64.
+ *   SCREEN_FP32: the same screen with FP32 matrix-core products.
+ *   AUTO:        SCREEN for large budgets (T >= n/40, >= 64 queries), else GATHER. */
+typedef enum {
+    NRLSH_RERANK_AUTO = 0,
+    NRLSH_RERANK_GATHER = 1,
+    NRLSH_RERANK_SCREEN = 2,
+    NRLSH_RERANK_SCREEN_FP32 = 3
+} nrlsh_rerank_mode;
 
 typedef struct nrlsh_query_opts {
     int32_t struct_size; /* sizeof(nrlsh_query_opts) */
@@ -177,7 +184,7 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
 
 /* Re-rank statistics of this thread's last nrlsh_query / nrlsh_query_ex. */
 typedef struct nrlsh_query_stats {
-    int32_t mode;          /* nrlsh_rerank_mode actually used (GATHER or SCREEN) */
+    int32_t mode;          /* nrlsh_rerank_mode actually used (GATHER, SCREEN, SCREEN_FP32) */
     int32_t screen_passes; /* screen launches (more than one per batch = a list overflowed) */
     int64_t kept_total;    /* SCREEN: pairs kept for the exact re-rank, all queries */
     int64_t kept_max;      /* SCREEN: largest kept list of one query */

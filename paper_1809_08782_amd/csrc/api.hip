@@ -278,6 +278,7 @@ struct nrlsh_index {
     nrlsh_build_stats stats{};
     hipStream_t home = nullptr;  // library stream that releases the device buffers
     DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
+    DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
     DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
     DBuf<int32_t> sid, sid_l, perm, off, R, inv;
     DBuf<uint32_t> codes_l;              // stored order
@@ -313,6 +314,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     }
 
     ix->Xl = DBuf<float>((size_t)n * dp, s);
+    ix->Xh = DBuf<uint16_t>((size_t)n * dp, s);
+    ix->Xlo = DBuf<uint16_t>((size_t)n * dp, s);
     ix->A = DBuf<float>(ix->A_h.size(), s);
     ix->At = DBuf<float>(At_h.size(), s);
     ix->key = DBuf<double>(n, s);
@@ -404,7 +407,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                         hipMemcpyDeviceToDevice, s));
     tm.begin("layout");
     HIPX(launch_layout(X, n, d, dp, ix->perm.get(), ix->key.get(), ix->sid.get(), ix->Xl.get(),
-                       ix->key_l.get(), ix->sid_l.get(), s));
+                       ix->Xh.get(), ix->Xlo.get(), ix->key_l.get(), ix->sid_l.get(), s));
     tm.end();
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
@@ -423,6 +426,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(hipStreamSynchronize(s));
     // long-lived buffers are released on the library stream by nrlsh_free
     for (auto *b : {&ix->Xl, &ix->A, &ix->At}) b->s = ix->home;
+    for (auto *b : {&ix->Xh, &ix->Xlo}) b->s = ix->home;
     for (auto *b : {&ix->key, &ix->key_l, &ix->keymax, &ix->U}) b->s = ix->home;
     for (auto *b : {&ix->sid, &ix->sid_l, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
     ix->codes_l.s = ix->home;
@@ -522,14 +526,12 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     }
 }
 
-size_t screen_lds_bytes(const nrlsh_index *ix) { return (size_t)64 * (ix->dp + 4) * sizeof(float) + 4096; }
-
-bool screen_fits(const nrlsh_index *ix)
+bool screen_fits(const nrlsh_index *ix, bool bf16x3)
 {
     int lim = 0;
     if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
         return false;
-    return screen_lds_bytes(ix) <= (size_t)lim;
+    return screen_lds_bytes(ix->dp, bf16x3) + 4096 <= (size_t)lim;
 }
 
 // Screen path: (1) theta_q from the largest FP32 lower bounds of small cells
@@ -548,9 +550,11 @@ std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo)
 }
 
 void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
-                      int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                      bool bf16x3, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
                       uint32_t *nonfinite_d)
 {
+    const uint16_t *Xh = bf16x3 ? ix->Xh.get() : nullptr;
+    const uint16_t *Xlo = bf16x3 ? ix->Xlo.get() : nullptr;
     const QueryShape sh = make_shape(ix, T, k);
     int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
     const int64_t tiles = B / 64;
@@ -558,7 +562,8 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     int64_t cap = std::min<int64_t>(sh.Tq, 1024);
 
     // pass-1 cells: the top sub-datasets in cells of screen_cell_items(), at
-    // least max(64, 4k) of them; pass-2 chunks: every sub-dataset
+    // least max(64, 4k) of them and at least one whole sub-dataset; pass-2
+    // chunks: every sub-dataset
     const int64_t want = std::max<int64_t>(64, 4 * (int64_t)k);
     int j_lo = ix->m - 1;
     while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
@@ -575,7 +580,7 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
     DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
     DBuf<int32_t> gpstar((size_t)B, s);
-    DBuf<float> cmax((size_t)B * ncells, s);
+    DBuf<float> cmax((size_t)B * ncells * screen_cell_groups(), s);
     DBuf<float> theta((size_t)B, s);
     DBuf<int32_t> counts((size_t)B, s);
     DBuf<int32_t> lists((size_t)B * cap, s);
@@ -598,14 +603,14 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                gpstar.get(), s));
         tm.end();
         tm.begin("screen_max");
-        HIPX(launch_screen_max(ix->Xl.get(), ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+        HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
                                cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
         for (;;) {
             HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("screen");
-            HIPX(launch_screen(ix->Xl.get(), ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+            HIPX(launch_screen(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
                                chunks.get(), nchunks, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), theta.get(), (int)cap, counts.get(), lists.get(), s));
             tm.end();
@@ -643,12 +648,13 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
                int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
-    bool screen = mode == NRLSH_RERANK_SCREEN ||
+    bool screen = mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
                   (mode == NRLSH_RERANK_AUTO && Tq * 40 >= ix->n && nq >= 64 && Tq >= 2048);
-    if (screen && !screen_fits(ix)) screen = false;
-    g_qstats.mode = screen ? NRLSH_RERANK_SCREEN : NRLSH_RERANK_GATHER;
+    const bool b3 = mode != NRLSH_RERANK_SCREEN_FP32;
+    if (screen && !screen_fits(ix, b3)) screen = false;
+    g_qstats.mode = screen ? (b3 ? NRLSH_RERANK_SCREEN : NRLSH_RERANK_SCREEN_FP32) : NRLSH_RERANK_GATHER;
     if (screen)
-        run_query_screen(ix, Qd, nq, k, T, ids_d, ips_d, s, tm, nonfinite_d);
+        run_query_screen(ix, Qd, nq, k, T, b3, ids_d, ips_d, s, tm, nonfinite_d);
     else
         run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d);
 }
@@ -730,7 +736,7 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     if (st != NRLSH_OK) return st;
     g_qstats = nrlsh_query_stats{};
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)) &&
-        (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN))
+        (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN_FP32))
         return fail(NRLSH_E_INVALID_ARG, "rerank_mode %d unknown", opts->rerank_mode);
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;

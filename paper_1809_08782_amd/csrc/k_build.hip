@@ -199,15 +199,27 @@ __global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ ske
 }
 
 // Stored copy: row p of Xl is item perm[p], zero-padded to dp floats; the
-// key and sub-dataset of each stored row come along.  One wave copies
-// LY_ROWS rows, 64 floats per instruction.
+// key and sub-dataset of each stored row come along.  The same rows are also
+// split into two bfloat16 parts, x = hi + lo + r with hi = bf16(x) and
+// lo = bf16(x - hi) (round to nearest even; |r| <= 2^-16 |x|), for the
+// query-tiled screen.  One wave copies LY_ROWS rows, 64 floats per
+// instruction.
 constexpr int LY_ROWS = 8;
+
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
 
 __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int64_t n, int d,
                                                 int dp, const int32_t *__restrict__ perm,
                                                 const double *__restrict__ key,
                                                 const int32_t *__restrict__ sid,
-                                                float *__restrict__ Xl, double *__restrict__ key_l,
+                                                float *__restrict__ Xl, uint16_t *__restrict__ Xh,
+                                                uint16_t *__restrict__ Xlo,
+                                                double *__restrict__ key_l,
                                                 int32_t *__restrict__ sid_l)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -219,7 +231,13 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
         const int64_t i = perm[p];
         const float *src = X + i * d;
         float *dst = Xl + p * dp;
-        for (int c = lane; c < dp; c += 64) dst[c] = c < d ? src[c] : 0.0f;
+        for (int c = lane; c < dp; c += 64) {
+            const float v = c < d ? src[c] : 0.0f;
+            const uint16_t hi = bf16_rne(v);
+            dst[c] = v;
+            Xh[p * dp + c] = hi;
+            Xlo[p * dp + c] = bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
+        }
         if (lane == 0) {
             key_l[p] = key[i];
             sid_l[p] = sid[i];
@@ -476,11 +494,11 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
 }
 
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
-                         const double *key, const int32_t *sid, float *Xl, double *key_l,
-                         int32_t *sid_l, hipStream_t s)
+                         const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
+                         uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s)
 {
     hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 4 * LY_ROWS)), dim3(256), 0, s, X, n, d, dp,
-                       perm, key, sid, Xl, key_l, sid_l);
+                       perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
     return hipGetLastError();
 }
 

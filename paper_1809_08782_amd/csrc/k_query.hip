@@ -474,26 +474,18 @@ __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__
 // v_mfma_f32_16x16x4_f32 (queries = M, items = N).  With e = g ||q|| ||x||
 // + 2^-100, g = 2 gamma_d (a bound on the rounding error of any summation
 // order), every probed pair satisfies ip32 - e <= ip <= ip32 + e.
-//   MAXMODE = true : writes, per (query, chunk), the largest lower bound
-//                    ip32 - e over the chunk's probed items (-inf if none).
-//                    The k-th largest of these over distinct chunks is a lower
-//                    bound theta_q of the k-th best exact inner product.
+//   MAXMODE = true : writes, per (query, 16-item group of a cell), the
+//                    largest lower bound ip32 - e over the group's probed items
+//                    (-inf if none).  The k-th largest of these over distinct
+//                    groups is a lower bound theta_q of the k-th best exact
+//                    inner product.
 //   MAXMODE = false: keeps every probed pair with not (ip32 + e < theta_q)
 //                    and appends its stored position to the query's list
 //                    (capacity cap; counts may exceed cap, which the host
 //                    detects).  The exact top-k of the probed set lies in it.
 constexpr int SC_CHUNK = 2048;
 constexpr int SC_CELL = 256;
-
-__device__ __forceinline__ uint32_t f2ord(float f)
-{
-    const uint32_t b = __float_as_uint(f);
-    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-}
-__device__ __forceinline__ float ord2f(uint32_t o)
-{
-    return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
-}
+constexpr int SC_GROUPS = SC_CELL / 16;  // 16-item groups per cell (MAXMODE outputs)
 
 template <int W, bool MAXMODE>
 __global__ __launch_bounds__(256) void k_screen(
@@ -509,7 +501,6 @@ __global__ __launch_bounds__(256) void k_screen(
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * W];
-    __shared__ uint32_t mx_s[64];
     __shared__ int any_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
@@ -537,15 +528,13 @@ __global__ __launch_bounds__(256) void k_screen(
         htie_s[tid] = htie;
         pstar_s[tid] = pstar;
         th_s[tid] = th;
-        mx_s[tid] = f2ord(-INFINITY);
         const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
         if (tid == 0) any_s = b != 0ull;
     }
+    if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
+        for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
     __syncthreads();
-    if (!any_s) {  // no query of this tile probes this chunk
-        if (MAXMODE && tid < 64 && q0 + tid < nq) cmax[(q0 + tid) * ncol + blockIdx.y] = -INFINITY;
-        return;
-    }
+    if (!any_s) return;  // no query of this tile probes this chunk
 
     // stage the query tile, zero-padded to dp columns
     for (int r = wave; r < 64; r += 4) {
@@ -561,11 +550,6 @@ __global__ __launch_bounds__(256) void k_screen(
     __syncthreads();
 
     const int r16 = lane & 15, g = lane >> 4;
-    float wmax[4][4];
-#pragma unroll
-    for (int qb = 0; qb < 4; ++qb)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) wmax[qb][v] = -INFINITY;
     for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
         // this lane's two items (column blocks ib = 0, 1)
         int32_t pit[2];
@@ -625,7 +609,12 @@ __global__ __launch_bounds__(256) void k_screen(
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-100f;
                     if (MAXMODE) {
-                        if (probed) wmax[qb][v] = fmaxf(wmax[qb][v], ip - e);
+                        // largest lower bound of this 16-item group for query ql
+                        float x = probed ? ip - e : -INFINITY;
+#pragma unroll
+                        for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+                        if (r16 == 0 && q0 + ql < nq && iv[ib])
+                            cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (pit[ib] - pbeg) / 16] = x;
                     } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
@@ -635,25 +624,183 @@ __global__ __launch_bounds__(256) void k_screen(
             }
         }
     }
-    if (MAXMODE) {
-        // reduce over the 16 lanes that share a query, then across the waves
+}
+
+// bf16x3 variant of k_screen: items and queries are split x = hi + lo (+ a
+// residual of at most 2^-16 |x|) in bfloat16 and each inner product is
+// hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 (products of bfloat16
+// pairs are exact in FP32).  Per coordinate the dropped terms are at most
+// 3.1 * 2^-16 |q_t x_t|, and FP32 accumulation of the 3d products adds at
+// most gamma_{3d} (1.02 sum |q_t x_t|); the caller's g covers both with the
+// same factor-2 margin as the FP32 screen.  In MFMA j of a 32-coordinate
+// step, lane group g carries coordinates 32 kk + 8 g .. + 7 of both operands.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t q_bf16_rne(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
+
+template <int W, bool MAXMODE>
+__global__ __launch_bounds__(256) void k_screen3(
+    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int d, int dp,
+    const uint32_t *__restrict__ codes_l, const double *__restrict__ key_l,
+    const float *__restrict__ Q, int64_t nq, const int32_t *__restrict__ chunks, int m,
+    const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,
+    const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,
+    const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,
+    int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb)
+{
+    extern __shared__ __align__(16) uint16_t qsh[];  // hi: 64 x qsb, then lo: 64 x qsb
+    uint16_t *qsl = qsh + 64 * qsb;
+    __shared__ float th_s[64], qn_s[64];
+    __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
+    __shared__ uint32_t qc_s[64 * W];
+    __shared__ int any_s;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tile = blockIdx.x;
+    const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
+              pend = chunks[3 * blockIdx.y + 2];
+    const int64_t q0 = (int64_t)tile * 64;
+
+    if (tid < 64) {
+        const int64_t q = q0 + tid;
+        int hthr = -1, htie = -1, pstar = -1;
+        float th = -INFINITY;
+        if (q < nq) {
+            hthr = ghthr[((int64_t)tile * m + j) * 64 + tid];
+            const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
+            if (tie[tid] == j) {
+                htie = tie[64 + tid];
+                pstar = gpstar[q];
+            }
+            if (!MAXMODE) th = theta[q];
+#pragma unroll
+            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
+        }
+        hthr_s[tid] = hthr;
+        htie_s[tid] = htie;
+        pstar_s[tid] = pstar;
+        th_s[tid] = th;
+        const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
+        if (tid == 0) any_s = b != 0ull;
+    }
+    if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
+        for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
+    __syncthreads();
+    if (!any_s) return;  // no query of this tile probes this chunk
+
+    // stage the query tile as hi / lo bfloat16, zero-padded to dp columns;
+    // ||q|| (an upper bound: exact squares, FP64 sum, rounded up) per row
+    for (int r = wave; r < 64; r += 4) {
+        const int64_t q = q0 + r;
+        double s2 = 0.0;
+        for (int c = lane; c < dp; c += 64) {
+            const float f = (q < nq && c < d) ? Q[q * d + c] : 0.f;
+            const uint16_t hi = q_bf16_rne(f);
+            qsh[r * qsb + c] = hi;
+            qsl[r * qsb + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
+            s2 += (double)f * (double)f;
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+        if (lane == 0) qn_s[r] = (float)__builtin_sqrt(s2) * (1.0f + 0x1p-18f);
+    }
+    __syncthreads();
+
+    const int r16 = lane & 15, g = lane >> 4;
+    const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
+        int32_t pit[2];
+        uint32_t cw[2][W];
+        float xn[2];
+        bool iv[2];
+#pragma unroll
+        for (int ib = 0; ib < 2; ++ib) {
+            pit[ib] = p0 + 16 * ib + r16;
+            iv[ib] = pit[ib] < pend;
+            const int64_t pp = iv[ib] ? pit[ib] : pbeg;
+#pragma unroll
+            for (int w = 0; w < W; ++w) cw[ib][w] = codes_l[pp * W + w];
+            xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
+        }
+        floatx4 acc[4][2];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                float x = wmax[qb][v];
+            for (int ib = 0; ib < 2; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int kk = 0; kk < dp; kk += 32) {
+            const int kc = kk + 8 * g;
+            const bool kin = kc < dp;
+            u16x8 bh[2], bl[2];
 #pragma unroll
-                for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-                if (r16 == 0) atomicMax(&mx_s[16 * qb + 4 * g + v], f2ord(x));
+            for (int ib = 0; ib < 2; ++ib) {
+                const bool ok = iv[ib] && kin;
+                const int64_t o = (int64_t)pit[ib] * dp + kc;
+                bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
+                bl[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
             }
-        __syncthreads();
-        if (tid < 64 && q0 + tid < nq) cmax[(q0 + tid) * ncol + blockIdx.y] = ord2f(mx_s[tid]);
+            u16x8 ah[4], al[4];
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+                const int o = (16 * qb + r16) * qsb + kc;
+                ah[qb] = kin ? *reinterpret_cast<const u16x8 *>(&qsh[o]) : z8;
+                al[qb] = kin ? *reinterpret_cast<const u16x8 *>(&qsl[o]) : z8;
+            }
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        as_bf16x8(ah[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        as_bf16x8(ah[qb]), as_bf16x8(bl[ib]), acc[qb][ib], 0, 0, 0);
+                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                        as_bf16x8(al[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                }
+        }
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ql = 16 * qb + 4 * g + v;
+                const int hthr = hthr_s[ql], htie = htie_s[ql];
+                const float th = th_s[ql], qn = qn_s[ql];
+#pragma unroll
+                for (int ib = 0; ib < 2; ++ib) {
+                    int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
+                    if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
+                    const bool probed =
+                        iv[ib] && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                    const float ip = acc[qb][ib][v];
+                    const float e = gam * qn * xn[ib] + 0x1p-90f;
+                    if (MAXMODE) {
+                        // largest lower bound of this 16-item group for query ql
+                        float x = probed ? ip - e : -INFINITY;
+#pragma unroll
+                        for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
+                        if (r16 == 0 && q0 + ql < nq && iv[ib])
+                            cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (pit[ib] - pbeg) / 16] = x;
+                    } else if (probed && !(ip + e < th)) {
+                        const int64_t q = q0 + ql;
+                        const int slot = atomicAdd(&counts[q], 1);
+                        if (slot < cap) lists[q * cap + slot] = pit[ib];
+                    }
+                }
+            }
+        }
     }
 }
 
-// theta_q = the k-th largest chunk maximum (a lower bound of the k-th best
-// exact inner product), lowered by 2^-22 relative to cover float rounding;
-// -inf when fewer than k chunks hold probed items.  One wave per query.
+// theta_q = the k-th largest group maximum (a lower bound of the k-th best
+// exact inner product: k distinct items reach it), lowered by 2^-22 relative
+// to cover float rounding; -inf when fewer than k groups hold probed items.
+// One wave per query.
 template <int S>
 __global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int ncol, int k,
                                               float *__restrict__ theta)
@@ -738,60 +885,98 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 
 int screen_chunk_items() { return SC_CHUNK; }
 int screen_cell_items() { return SC_CELL; }
+int screen_cell_groups() { return SC_GROUPS; }
+
+// bf16 row stride of the staged query tile: dp + 8 or dp + 16 so that the
+// row stride in dwords is an odd multiple of 4 (16 lanes reading 16 bytes of
+// 16 rows hit 16 distinct 4-bank groups)
+static int screen_qsb(int dp) { return dp + (((dp / 8) % 2 == 0) ? 8 : 16); }
+
+size_t screen_lds_bytes(int dp, bool bf16x3)
+{
+    return bf16x3 ? (size_t)2 * 64 * screen_qsb(dp) * sizeof(uint16_t)
+                  : (size_t)64 * (dp + 4) * sizeof(float);
+}
 
 template <bool MAXMODE>
-static hipError_t launch_screen_t(const float *Xl, const double *key_l, const uint32_t *codes_l,
-                                  const float *Q, int64_t nq, const QueryShape &sh,
-                                  const int32_t *chunks, int nchunks, const uint32_t *qcodes,
-                                  const int32_t *ghthr, const int32_t *gtie,
-                                  const int32_t *gpstar, const float *theta, int cap,
-                                  int32_t *counts, int32_t *lists, float *cmax, hipStream_t s)
+static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
+                                  const double *key_l, const uint32_t *codes_l, const float *Q,
+                                  int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                                  int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
+                                  const int32_t *gtie, const int32_t *gpstar, const float *theta,
+                                  int cap, int32_t *counts, int32_t *lists, float *cmax,
+                                  hipStream_t s)
 {
+    const bool b3 = Xh != nullptr && Xlo != nullptr;
+    const size_t lds = screen_lds_bytes(sh.dp, b3);
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    const int ncol = MAXMODE ? nchunks * SC_GROUPS : 0;
+    if (b3) {
+        // per coordinate 3.1 * 2^-16 |q x| dropped by the split, plus FP32
+        // accumulation of 3d exact products: 2 * 1.02 * gamma_{3d}
+        const double u3 = 3.0 * sh.d * 0x1p-24;
+        const float gam = (float)((3.2 * 0x1p-16 + 2.1 * u3 / (1.0 - u3)) * (1.0 + 0x1p-16));
+        const int qsb = screen_qsb(sh.dp);
+        const void *fn = sh.W == 1 ? (const void *)k_screen3<1, MAXMODE> : (const void *)k_screen3<2, MAXMODE>;
+        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        if (sh.W == 1)
+            hipLaunchKernelGGL((k_screen3<1, MAXMODE>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
+                               codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar,
+                               theta, gam, cap, counts, lists, cmax, ncol, qsb);
+        else
+            hipLaunchKernelGGL((k_screen3<2, MAXMODE>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
+                               codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar,
+                               theta, gam, cap, counts, lists, cmax, ncol, qsb);
+        return hipGetLastError();
+    }
     const double ud = (double)sh.d * 0x1p-24;
     const float gam = (float)(2.0 * ud / (1.0 - ud) * (1.0 + 0x1p-16));
-    const size_t lds = (size_t)64 * (sh.dp + 4) * sizeof(float);
-    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
     const void *fn = sh.W == 1 ? (const void *)k_screen<1, MAXMODE> : (const void *)k_screen<2, MAXMODE>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     if (sh.W == 1)
         hipLaunchKernelGGL((k_screen<1, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, nchunks);
+                           counts, lists, cmax, ncol);
     else
         hipLaunchKernelGGL((k_screen<2, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, nchunks);
+                           counts, lists, cmax, ncol);
     return hipGetLastError();
 }
 
-hipError_t launch_screen_max(const float *Xl, const double *key_l, const uint32_t *codes_l,
+hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
+                             const double *key_l, const uint32_t *codes_l,
                              const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
                              int ncells, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s)
 {
-    hipError_t e = launch_screen_t<true>(Xl, key_l, codes_l, Q, nq, sh, cells, ncells, qcodes, ghthr,
-                                         gtie, gpstar, nullptr, 0, nullptr, nullptr, cmax, s);
+    hipError_t e = launch_screen_t<true>(Xl, Xh, Xlo, key_l, codes_l, Q, nq, sh, cells, ncells,
+                                         qcodes, ghthr, gtie, gpstar, nullptr, 0, nullptr, nullptr,
+                                         cmax, s);
     if (e != hipSuccess) return e;
     const int S = (sh.k + 63) / 64;
+    const int ncol = ncells * SC_GROUPS;
     const dim3 grid((unsigned)nq), block(64);
-    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, ncells, sh.k, theta);
-    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, ncells, sh.k, theta);
-    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, ncells, sh.k, theta);
-    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, ncells, sh.k, theta);
-    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, ncells, sh.k, theta);
+    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, ncol, sh.k, theta);
+    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, ncol, sh.k, theta);
+    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, ncol, sh.k, theta);
+    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, ncol, sh.k, theta);
+    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, ncol, sh.k, theta);
     return hipGetLastError();
 }
 
-hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
+hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
+                         const double *key_l, const uint32_t *codes_l,
                          const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
                          int32_t *counts, int32_t *lists, hipStream_t s)
 {
-    return launch_screen_t<false>(Xl, key_l, codes_l, Q, nq, sh, chunks, nchunks, qcodes, ghthr,
-                                  gtie, gpstar, theta, cap, counts, lists, nullptr, s);
+    return launch_screen_t<false>(Xl, Xh, Xlo, key_l, codes_l, Q, nq, sh, chunks, nchunks, qcodes,
+                                  ghthr, gtie, gpstar, theta, cap, counts, lists, nullptr, s);
 }
 
 int rerank_splits(int64_t nq, int64_t Tq)

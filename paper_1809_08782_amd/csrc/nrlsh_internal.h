@@ -47,10 +47,10 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
                                  double *keymax, hipStream_t s);
 
 // Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
-// key and sub-dataset of each stored row.
+// key and sub-dataset of each stored row, plus its bfloat16 hi / lo split.
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
-                         const double *key, const int32_t *sid, float *Xl, double *key_l,
-                         int32_t *sid_l, hipStream_t s);
+                         const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
+                         uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s);
 
 // SimpleLSH transform + sign random projection on the FP32 matrix cores, over
 // the stored rows (all arrays in stored order); writes the codes codes_l.
@@ -108,20 +108,27 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 
 // Query-tiled FP32-MFMA screen of the probed set.  Chunks / cells are
 // (sub-dataset, first, end) triples of stored items.
-//   launch_screen_max: per (query, cell) the largest FP32 lower bound over the
-//     cell's probed items, then theta[q] = the k-th largest of them (lowered
-//     for rounding; -inf if fewer than k cells hold probed items).
+//   launch_screen_max: per (query, 16-item group of a cell) the largest lower
+//     bound over the group's probed items (cmax: nq x ncells x groups), then
+//     theta[q] = the k-th largest of them (lowered for rounding; -inf if fewer
+//     than k groups hold probed items).
 //   launch_screen: appends every probed pair whose FP32 upper bound reaches
 //     theta[q] to lists (nq x cap) and counts all of them (counts zeroed by
 //     the caller; counts[q] > cap means the list overflowed).
+// Xh / Xlo != NULL selects the bf16x3 matrix-core screen (x = hi + lo split,
+// products hi.hi + hi.lo + lo.hi), otherwise the FP32 matrix-core screen.
 int screen_chunk_items();
 int screen_cell_items();
-hipError_t launch_screen_max(const float *Xl, const double *key_l, const uint32_t *codes_l,
+int screen_cell_groups();  // lower-bound maxima kept per cell and query
+size_t screen_lds_bytes(int dp, bool bf16x3);
+hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
+                             const double *key_l, const uint32_t *codes_l,
                              const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
                              int ncells, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s);
-hipError_t launch_screen(const float *Xl, const double *key_l, const uint32_t *codes_l,
+hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
+                         const double *key_l, const uint32_t *codes_l,
                          const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,

@@ -82,12 +82,13 @@ def test_parity_screen_rerank(case):
     Q = make_queries(nq, d, seed=n + 4)
     oix = orc.OracleIndex(X, m, L, seed=17, threads=8)
     with nr.nrlsh_build(X, m, L, 17) as gix:
-        ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="screen")
         oids, oips = oix.query(Q, k, T, threads=8)
-        assert np.array_equal(ids, oids)
-        assert np.array_equal(ips, oips.astype(np.float32))
-        gi, gp = nr.nrlsh_query(gix, Q, k, T, rerank="gather")
-        assert np.array_equal(gi, ids) and np.array_equal(gp, ips)
+        for mode in ("screen", "screen_fp32", "gather"):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank=mode)
+            st = nr.nrlsh_get_query_stats()
+            assert st["mode"] == mode, st
+            assert np.array_equal(ids, oids), mode
+            assert np.array_equal(ips, oips.astype(np.float32)), mode
 
 
 def test_screen_with_duplicates_and_zero_rows():
@@ -102,10 +103,11 @@ def test_screen_with_duplicates_and_zero_rows():
     oix = orc.OracleIndex(X, 10, 32, seed=5, threads=8)
     with nr.nrlsh_build(X, 10, 32, 5) as gix:
         for T in (3000, n):
-            ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank="screen")
             oids, oips = oix.query(Q, 10, T, threads=8)
-            assert np.array_equal(ids, oids), f"T={T}"
-            assert np.array_equal(ips, oips.astype(np.float32)), f"T={T}"
+            for mode in ("screen", "screen_fp32"):
+                ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank=mode)
+                assert np.array_equal(ids, oids), f"T={T} {mode}"
+                assert np.array_equal(ips, oips.astype(np.float32)), f"T={T} {mode}"
 
 
 def test_parity_tiny_config():
