@@ -115,7 +115,8 @@ nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq
  *                product (with a rigorous rounding bound) can still reach a
  *                lower bound of the k-th best are re-ranked exactly in FP64.
  *   SCREEN_FP32: the same screen with FP32 matrix-core products.
- *   AUTO:        SCREEN for large budgets (T >= n/40, >= 64 queries), else GATHER. */
+ *   AUTO:        SCREEN for large budgets (T >= n/128, T >= 2048, >= 64 queries),
+ *                else GATHER. */
 typedef enum {
     NRLSH_RERANK_AUTO = 0,
     NRLSH_RERANK_GATHER = 1,
@@ -188,6 +189,7 @@ typedef struct nrlsh_query_stats {
     int32_t screen_passes; /* screen launches (more than one per batch = a list overflowed) */
     int64_t kept_total;    /* SCREEN: pairs kept for the exact re-rank, all queries */
     int64_t kept_max;      /* SCREEN: largest kept list of one query */
+    int64_t theta_unset;   /* SCREEN: queries whose lower bound theta stayed -inf */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

@@ -48,7 +48,7 @@ class BuildStats(C.Structure):
 
 class QueryStats(C.Structure):
     _fields_ = [("mode", C.c_int32), ("screen_passes", C.c_int32), ("kept_total", C.c_int64),
-                ("kept_max", C.c_int64)]
+                ("kept_max", C.c_int64), ("theta_unset", C.c_int64)]
 
 
 _lib = None
@@ -301,7 +301,7 @@ def nrlsh_get_query_stats() -> dict:
     _check(lib().nrlsh_get_query_stats(C.byref(st)))
     return {"mode": {1: "gather", 2: "screen", 3: "screen_fp32"}.get(st.mode, "none"),
             "screen_passes": st.screen_passes, "kept_total": st.kept_total,
-            "kept_max": st.kept_max}
+            "kept_max": st.kept_max, "theta_unset": st.theta_unset}
 
 
 def nrlsh_profile_enable(on: bool = True):

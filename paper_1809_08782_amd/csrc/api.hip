@@ -537,15 +537,22 @@ bool screen_fits(const nrlsh_index *ix, bool bf16x3)
 // Screen path: (1) theta_q from the largest FP32 lower bounds of small cells
 // of the highest-norm sub-datasets, (2) query-tiled MFMA screen of the whole
 // probed set against theta_q, (3) exact FP64 re-rank of the kept pairs.
-std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo)
+// (sub-dataset, first, end) triples of <= `items` stored items covering
+// sub-datasets j >= j_lo entirely and, below j_lo, every `stride`-th cell
+// (stride 0: none).
+std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo, int stride = 0)
 {
     std::vector<int32_t> ch;
-    for (int j = ix->m - 1; j >= j_lo; --j)
-        for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += items) {
+    for (int j = ix->m - 1; j >= 0; --j) {
+        if (j < j_lo && stride == 0) break;
+        int64_t c = 0;
+        for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += items, ++c) {
+            if (j < j_lo && (c + j) % stride != 0) continue;
             ch.push_back(j);
             ch.push_back((int32_t)p);
             ch.push_back((int32_t)std::min<int64_t>(p + items, ix->off_h[j + 1]));
         }
+    }
     return ch;
 }
 
@@ -561,13 +568,15 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int L1 = sh.L + 1;
     int64_t cap = std::min<int64_t>(sh.Tq, 1024);
 
-    // pass-1 cells: the top sub-datasets in cells of screen_cell_items(), at
-    // least max(64, 4k) of them and at least one whole sub-dataset; pass-2
-    // chunks: every sub-dataset
+    // pass-1 cells: the top sub-datasets whole (at least max(64, 4k) cells of
+    // screen_cell_items()) plus every 16th cell of the others, so that the
+    // witnesses of theta sit wherever a query's probed items are (a
+    // sub-dataset normalised by an outlying U_j can hash almost all of its
+    // items alike and be probed late); pass-2 chunks: every sub-dataset
     const int64_t want = std::max<int64_t>(64, 4 * (int64_t)k);
     int j_lo = ix->m - 1;
     while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
-    std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo);
+    std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, 16);
     std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
     DBuf<int32_t> cells(ce.size(), s), chunks(ch.size(), s);
@@ -607,6 +616,12 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
+        {
+            std::vector<float> th((size_t)nb);
+            HIPX(hipMemcpyAsync(th.data(), theta.get(), (size_t)nb * sizeof(float), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            for (float t : th) g_qstats.theta_unset += std::isinf(t) && t < 0 ? 1 : 0;
+        }
         for (;;) {
             HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("screen");
@@ -649,7 +664,7 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
     bool screen = mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
-                  (mode == NRLSH_RERANK_AUTO && Tq * 40 >= ix->n && nq >= 64 && Tq >= 2048);
+                  (mode == NRLSH_RERANK_AUTO && Tq * 128 >= ix->n && nq >= 64 && Tq >= 2048);
     const bool b3 = mode != NRLSH_RERANK_SCREEN_FP32;
     if (screen && !screen_fits(ix, b3)) screen = false;
     g_qstats.mode = screen ? (b3 ? NRLSH_RERANK_SCREEN : NRLSH_RERANK_SCREEN_FP32) : NRLSH_RERANK_GATHER;
