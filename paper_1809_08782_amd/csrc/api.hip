@@ -568,12 +568,12 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int L1 = sh.L + 1;
     int64_t cap = std::min<int64_t>(sh.Tq, 1024);
 
-    // pass-1 cells: the top sub-datasets whole (at least max(64, 4k) cells of
-    // screen_cell_items()) plus every 16th cell of the others, so that the
+    // pass-1 cells: the top sub-datasets whole (at least 16 k lower-bound
+    // groups) plus every 16th cell of the others, so that the
     // witnesses of theta sit wherever a query's probed items are (a
     // sub-dataset normalised by an outlying U_j can hash almost all of its
     // items alike and be probed late); pass-2 chunks: every sub-dataset
-    const int64_t want = std::max<int64_t>(64, 4 * (int64_t)k);
+    const int64_t want = std::max<int64_t>(2, 16 * (int64_t)k / screen_cell_groups());
     int j_lo = ix->m - 1;
     while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
     std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, 16);

@@ -474,7 +474,7 @@ __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__
 // v_mfma_f32_16x16x4_f32 (queries = M, items = N).  With e = g ||q|| ||x||
 // + 2^-100, g = 2 gamma_d (a bound on the rounding error of any summation
 // order), every probed pair satisfies ip32 - e <= ip <= ip32 + e.
-//   MAXMODE = true : writes, per (query, 16-item group of a cell), the
+//   MAXMODE = true : writes, per (query, 32-item group of a cell), the
 //                    largest lower bound ip32 - e over the group's probed items
 //                    (-inf if none).  The k-th largest of these over distinct
 //                    groups is a lower bound theta_q of the k-th best exact
@@ -484,8 +484,8 @@ __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__
 //                    (capacity cap; counts may exceed cap, which the host
 //                    detects).  The exact top-k of the probed set lies in it.
 constexpr int SC_CHUNK = 2048;
-constexpr int SC_CELL = 256;
-constexpr int SC_GROUPS = SC_CELL / 16;  // 16-item groups per cell (MAXMODE outputs)
+constexpr int SC_CELL = 1024;
+constexpr int SC_GROUPS = SC_CELL / 32;  // 32-item groups per cell (MAXMODE outputs)
 
 template <int W, bool MAXMODE>
 __global__ __launch_bounds__(256) void k_screen(
@@ -600,6 +600,7 @@ __global__ __launch_bounds__(256) void k_screen(
                 const int ql = 16 * qb + 4 * g + v;
                 const int hthr = hthr_s[ql], htie = htie_s[ql];
                 const float th = th_s[ql], qn = qn_s[ql];
+                float gmax = -INFINITY;  // MAXMODE: this lane's two items for query ql
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
                     int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
@@ -609,17 +610,19 @@ __global__ __launch_bounds__(256) void k_screen(
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-100f;
                     if (MAXMODE) {
-                        // largest lower bound of this 16-item group for query ql
-                        float x = probed ? ip - e : -INFINITY;
-#pragma unroll
-                        for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-                        if (r16 == 0 && q0 + ql < nq && iv[ib])
-                            cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (pit[ib] - pbeg) / 16] = x;
+                        if (probed) gmax = fmaxf(gmax, ip - e);
                     } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
                         if (slot < cap) lists[q * cap + slot] = pit[ib];
                     }
+                }
+                if (MAXMODE) {
+                    // largest lower bound of this iteration's 32 items for query ql
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
+                    if (r16 == 0 && q0 + ql < nq && p0 < pend)
+                        cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32] = gmax;
                 }
             }
         }
@@ -771,6 +774,7 @@ __global__ __launch_bounds__(256) void k_screen3(
                 const int ql = 16 * qb + 4 * g + v;
                 const int hthr = hthr_s[ql], htie = htie_s[ql];
                 const float th = th_s[ql], qn = qn_s[ql];
+                float gmax = -INFINITY;  // MAXMODE: this lane's two items for query ql
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
                     int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
@@ -780,17 +784,19 @@ __global__ __launch_bounds__(256) void k_screen3(
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-90f;
                     if (MAXMODE) {
-                        // largest lower bound of this 16-item group for query ql
-                        float x = probed ? ip - e : -INFINITY;
-#pragma unroll
-                        for (int o = 1; o < 16; o <<= 1) x = fmaxf(x, __shfl_xor(x, o, 64));
-                        if (r16 == 0 && q0 + ql < nq && iv[ib])
-                            cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (pit[ib] - pbeg) / 16] = x;
+                        if (probed) gmax = fmaxf(gmax, ip - e);
                     } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
                         if (slot < cap) lists[q * cap + slot] = pit[ib];
                     }
+                }
+                if (MAXMODE) {
+                    // largest lower bound of this iteration's 32 items for query ql
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
+                    if (r16 == 0 && q0 + ql < nq && p0 < pend)
+                        cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32] = gmax;
                 }
             }
         }

@@ -108,7 +108,7 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 
 // Query-tiled FP32-MFMA screen of the probed set.  Chunks / cells are
 // (sub-dataset, first, end) triples of stored items.
-//   launch_screen_max: per (query, 16-item group of a cell) the largest lower
+//   launch_screen_max: per (query, 32-item group of a cell) the largest lower
 //     bound over the group's probed items (cmax: nq x ncells x groups), then
 //     theta[q] = the k-th largest of them (lowered for rounding; -inf if fewer
 //     than k groups hold probed items).
