@@ -78,12 +78,35 @@ typedef enum nrlsh_status {
 nrlsh_status nrlsh_build(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
                          uint64_t seed, nrlsh_index **out);
 
+/* Precision form of the hash GEMM.  The items are also kept in FP32 (for the
+ * recompute and the re-rank); the hash reads a copy in this storage:
+ *   FP32:     the FP32 copy on the FP32 matrix cores (default).
+ *   BF16:     bfloat16 (round to nearest even) items and projections on the
+ *             bf16 matrix cores, FP32 accumulate.
+ *   FP8_E4M3: OCP E4M3 (round to nearest even, saturating, subnormals kept)
+ *             with one FP32 scale per item row (max |x| / 448) and per
+ *             projection row, on the fp8 matrix cores, FP32 accumulate.
+ * In the BF16 / FP8 forms an item whose low-precision projection p~ of some
+ * bit has |p~| <= margin is re-hashed from its FP32 copy (and then, like
+ * every FP32 hash, in FP64 near zero):
+ *   RIGOROUS: margin = a worst-case bound of |p~ - p| from the rounding of
+ *             both operands and of the accumulation: every sign equals the
+ *             FP64 definition (the default).
+ *   SCALED:   margin = margin_param * ||x|| on the scaled projection
+ *             U_j a.P(x/U_j) (e.g. 1e-3); signs outside it may differ from
+ *             FP64 where the quantisation error exceeds the margin. */
+typedef enum { NRLSH_STORAGE_FP32 = 0, NRLSH_STORAGE_BF16 = 1, NRLSH_STORAGE_FP8_E4M3 = 2 } nrlsh_storage;
+typedef enum { NRLSH_MARGIN_RIGOROUS = 0, NRLSH_MARGIN_SCALED = 1 } nrlsh_margin_mode;
+
 typedef struct nrlsh_build_opts {
-    int32_t struct_size; /* sizeof(nrlsh_build_opts) */
-    int32_t device_ptrs; /* 1: items is a device pointer */
-    void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
-    double eps;          /* adjusted metric s_hat = U_j cos[pi (1-eps)(1 - l/L)]
-                            (Section 3.3), 0 <= eps < 1; 0 = Eq. 12 */
+    int32_t struct_size;  /* sizeof(nrlsh_build_opts) */
+    int32_t device_ptrs;  /* 1: items is a device pointer */
+    void *stream;         /* hipStream_t to run on, or NULL for the library's stream */
+    double eps;           /* adjusted metric s_hat = U_j cos[pi (1-eps)(1 - l/L)]
+                             (Section 3.3), 0 <= eps < 1; 0 = Eq. 12 */
+    int32_t hash_storage; /* nrlsh_storage (read when struct_size covers it) */
+    int32_t margin_mode;  /* nrlsh_margin_mode */
+    double margin_param;  /* SCALED: relative margin (>= 0) */
 } nrlsh_build_opts;
 
 nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
@@ -170,9 +193,18 @@ typedef struct nrlsh_build_stats {
     int64_t recomputed_items; /* items with at least one bit recomputed in FP64 */
     int64_t recomputed_bits;  /* (item, bit) projections recomputed in FP64 */
     int64_t recompute_flips;  /* of those, bits whose FP32 sign differed from FP64 */
+    int64_t lowp_items;       /* BF16 / FP8: items re-hashed from the FP32 copy */
+    int64_t lowp_bits;        /* BF16 / FP8: (item, bit) projections inside the margin */
+    int64_t lowp_changed;     /* BF16 / FP8: bits the FP32 re-hash changed */
 } nrlsh_build_stats;
 
 nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st);
+
+/* The hash storage copy in stored order (see nrlsh_get_layout): FP32 -> n x dp
+ * float; BF16 -> n x dp uint16; FP8_E4M3 -> n x dp uint8 plus n float row
+ * scales (scales may be NULL otherwise).  *storage receives the kind. */
+nrlsh_status nrlsh_get_hash_copy(const nrlsh_index *ix, void *data, float *scales,
+                                 int32_t *storage);
 
 /* Query codes: nq uint64 (host in, host out), bit r = [A_r[:d] . q > 0]. */
 nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,

@@ -30,7 +30,11 @@ class NrlshError(RuntimeError):
 
 class BuildOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32),
-                ("stream", C.c_void_p), ("eps", C.c_double)]
+                ("stream", C.c_void_p), ("eps", C.c_double), ("hash_storage", C.c_int32),
+                ("margin_mode", C.c_int32), ("margin_param", C.c_double)]
+
+
+STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 
 class QueryOpts(C.Structure):
@@ -43,7 +47,8 @@ RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3}
 
 class BuildStats(C.Structure):
     _fields_ = [("recomputed_items", C.c_int64), ("recomputed_bits", C.c_int64),
-                ("recompute_flips", C.c_int64)]
+                ("recompute_flips", C.c_int64), ("lowp_items", C.c_int64),
+                ("lowp_bits", C.c_int64), ("lowp_changed", C.c_int64)]
 
 
 class QueryStats(C.Structure):
@@ -89,6 +94,8 @@ def lib():
         L.nrlsh_get_partition.restype = st
         L.nrlsh_get_layout.argtypes = [P, P, P]
         L.nrlsh_get_layout.restype = st
+        L.nrlsh_get_hash_copy.argtypes = [P, P, P, C.POINTER(I32)]
+        L.nrlsh_get_hash_copy.restype = st
         L.nrlsh_get_build_stats.argtypes = [P, C.POINTER(BuildStats)]
         L.nrlsh_get_build_stats.restype = st
         L.nrlsh_query_codes.argtypes = [P, P, I64, P]
@@ -212,7 +219,23 @@ class Index:
         st = BuildStats()
         _check(lib().nrlsh_get_build_stats(self.handle, C.byref(st)))
         return {"recomputed_items": st.recomputed_items, "recomputed_bits": st.recomputed_bits,
-                "recompute_flips": st.recompute_flips}
+                "recompute_flips": st.recompute_flips, "lowp_items": st.lowp_items,
+                "lowp_bits": st.lowp_bits, "lowp_changed": st.lowp_changed}
+
+    def hash_copy(self):
+        """(storage name, copy in stored order n x dp, row scales or None)."""
+        kind = I32()
+        n, dp = self.n, self.dp
+        # room for the widest element type, viewed as the storage kind afterwards
+        buf = np.empty(n * dp * 4, dtype=np.uint8)
+        sc = np.empty(n, dtype=np.float32)
+        _check(lib().nrlsh_get_hash_copy(self.handle, buf.ctypes.data, sc.ctypes.data, C.byref(kind)))
+        name = {0: "fp32", 1: "bf16", 2: "fp8"}[kind.value]
+        if name == "fp32":
+            return name, buf.view(np.float32).reshape(n, dp), None
+        if name == "bf16":
+            return name, buf[: n * dp * 2].view(np.uint16).reshape(n, dp), None
+        return name, buf[: n * dp].reshape(n, dp), sc
 
     def query_codes(self, queries) -> np.ndarray:
         Q = _host_f32(queries)
@@ -230,21 +253,27 @@ class Index:
 
 
 # ------------------------------------------------------------------ C-ABI names
-def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None) -> Index:
+def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None,
+                hash_storage: str = "fp32", margin="rigorous") -> Index:
     """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
-    tensor (n, d) float32 (device pointer, torch's current stream)."""
+    tensor (n, d) float32 (device pointer, torch's current stream).
+    ``hash_storage`` ("fp32", "bf16", "fp8") selects the precision form of the
+    hash GEMM; ``margin`` is "rigorous" or a relative margin (float)."""
     h = P()
+    st = STORAGES[hash_storage]
+    mmode, mparam = (0, 0.0) if margin == "rigorous" else (1, float(margin))
     if _is_torch_device(items):
         if items.dtype.__str__() != "torch.float32" or items.dim() != 2:
             raise ValueError("items must be a 2-D float32 tensor")
         items = items.contiguous()
-        opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps))
+        opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps), st,
+                         mmode, mparam)
         _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
                                     seed, C.byref(opts), C.byref(h)))
     else:
         X = _host_f32(items)
-        if eps != 0.0 or stream is not None:
-            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps))
+        if eps != 0.0 or stream is not None or st != 0:
+            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam)
             _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
                                         C.byref(opts), C.byref(h)))
         else:

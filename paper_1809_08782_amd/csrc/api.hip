@@ -271,6 +271,8 @@ struct nrlsh_index {
     int32_t d = 0, dp = 0, m = 0, L = 0, W = 1;
     uint64_t seed = 0;
     double eps = 0.0;
+    int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
+    double margin_param = 0.0;
     std::vector<float> A_h;
     std::vector<double> keymax_h, U_h;
     std::vector<int64_t> off_h;
@@ -279,6 +281,8 @@ struct nrlsh_index {
     hipStream_t home = nullptr;  // library stream that releases the device buffers
     DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
     DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
+    DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
+    DBuf<float> xscale;                  // its row scales
     DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
     DBuf<int32_t> sid, sid_l, perm, off, R, inv;
     DBuf<uint32_t> codes_l;              // stored order
@@ -289,6 +293,68 @@ namespace {
 hipStream_t pick_stream(void *user, int dev)
 {
     return user ? static_cast<hipStream_t>(user) : library_stream(dev);
+}
+
+// Precision form of the hash: quantised copies of the items and projections,
+// the low-precision matrix-core hash with its margin, and the FP32 re-hash
+// (with its own FP64 band) of every item that had a projection in the margin.
+void hash_low_precision(nrlsh_index *ix, const std::vector<float> &tau_h, const float *tau_d,
+                        FixEntry *fix, BuildCounters *ctr, hipStream_t s, Timer &tm)
+{
+    const int64_t n = ix->n;
+    const int d = ix->d, dp = ix->dp, L = ix->L;
+    const bool fp8 = ix->storage == NRLSH_STORAGE_FP8_E4M3;
+    const size_t es = fp8 ? 1 : 2;
+    // margins: RIGOROUS bounds |p~ - p| by qrel ||a_r[:d]|| ||x|| (rounding of
+    // both operands, exact low-precision products, FP32 accumulation) plus the
+    // FP32 band tau_r U_j; SCALED uses margin_param ||x||
+    const double gd = d * 0x1p-24 / (1.0 - d * 0x1p-24);
+    const double qrel = fp8 ? (0x1p-3 + 0x1p-8 + 0x1p-20 + 0x1p-21 + 0x1p-10 * 2.2 * std::sqrt((double)d) / 448.0 +
+                               0x1p-20 * d / (448.0 * 448.0) + 2.2 * gd)
+                            : (0x1p-7 + 0x1p-16 + 0x1p-21 + 2.2 * gd);
+    std::vector<float> mq_h(L), tq_h(L);
+    for (int r = 0; r < L; ++r) {
+        double a2 = 0.0;
+        for (int c = 0; c < d; ++c) a2 += (double)ix->A_h[(size_t)r * (d + 1) + c] * ix->A_h[(size_t)r * (d + 1) + c];
+        if (ix->margin_mode == NRLSH_MARGIN_RIGOROUS) {
+            mq_h[r] = std::nextafter((float)(qrel * (1.0 + 0x1p-10) * std::sqrt(a2)), INFINITY);
+            tq_h[r] = tau_h[r];
+        } else {
+            mq_h[r] = (float)ix->margin_param;
+            tq_h[r] = 0.f;
+        }
+    }
+    DBuf<float> mq(L, s), tq(L, s), ascale(L, s);
+    DBuf<uint8_t> Aq((size_t)L * dp * es, s);
+    DBuf<int32_t> rows((size_t)n, s);
+    HIPX(hipMemcpyAsync(mq.get(), mq_h.data(), L * sizeof(float), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(tq.get(), tq_h.data(), L * sizeof(float), hipMemcpyHostToDevice, s));
+    const int st = fp8 ? 2 : 1;
+    HIPX(launch_quant_rows(ix->A.get(), L, d, d + 1, st, Aq.get(), dp, ascale.get(), s));
+    const void *Xq = ix->Xh.get();
+    if (fp8) {
+        ix->Xf8 = DBuf<uint8_t>((size_t)n * dp, s);
+        ix->xscale = DBuf<float>((size_t)n, s);
+        tm.begin("quant");
+        HIPX(launch_quant_rows(ix->Xl.get(), n, d, dp, 2, ix->Xf8.get(), dp, ix->xscale.get(), s));
+        tm.end();
+        Xq = ix->Xf8.get();
+    }
+    tm.begin("hash");
+    HIPX(launch_hash_q(st, Xq, fp8 ? ix->xscale.get() : nullptr, n, d, dp, Aq.get(), ascale.get(),
+                       ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(), ix->keymax.get(),
+                       ix->U.get(), mq.get(), tq.get(), ix->codes_l.get(), rows.get(), ctr, s));
+    tm.end();
+    BuildCounters hc{};
+    HIPX(hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    if (hc.lowp_items > 0) {
+        tm.begin("hash_rehash");
+        HIPX(launch_hash(ix->Xl.get(), hc.lowp_items, d, dp, ix->A.get(), L, ix->key_l.get(),
+                         ix->sid_l.get(), ix->keymax.get(), ix->U.get(), tau_d, ix->codes_l.get(),
+                         fix, ctr, rows.get(), s));
+        tm.end();
+    }
 }
 
 void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_t s, Timer &tm)
@@ -411,11 +477,15 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     tm.end();
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
-    tm.begin("hash");
-    HIPX(launch_hash(ix->Xl.get(), n, d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
-                     ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_l.get(), fix.get(),
-                     ctr.get(), s));
-    tm.end();
+    if (ix->storage == NRLSH_STORAGE_FP32) {
+        tm.begin("hash");
+        HIPX(launch_hash(ix->Xl.get(), n, d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
+                         ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_l.get(), fix.get(),
+                         ctr.get(), nullptr, s));
+        tm.end();
+    } else {
+        hash_low_precision(ix, tau_h, tau.get(), fix.get(), ctr.get(), s, tm);
+    }
     tm.begin("hash_fixup");
     HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
                            ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), ix->codes_l.get(),
@@ -427,9 +497,14 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     // long-lived buffers are released on the library stream by nrlsh_free
     for (auto *b : {&ix->Xl, &ix->A, &ix->At}) b->s = ix->home;
     for (auto *b : {&ix->Xh, &ix->Xlo}) b->s = ix->home;
+    ix->Xf8.s = ix->home;
+    ix->xscale.s = ix->home;
     for (auto *b : {&ix->key, &ix->key_l, &ix->keymax, &ix->U}) b->s = ix->home;
     for (auto *b : {&ix->sid, &ix->sid_l, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
     ix->codes_l.s = ix->home;
+    ix->stats.lowp_items = hc.lowp_items;
+    ix->stats.lowp_bits = (int64_t)hc.lowp_bits;
+    ix->stats.lowp_changed = (int64_t)hc.lowp_changed;
     ix->stats.recomputed_items = hc.fix_count;
     ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
     ix->stats.recompute_flips = (int64_t)hc.fix_flips;
@@ -699,6 +774,19 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
     const double eps = opts ? opts->eps : 0.0;
     nrlsh_status st = validate_build(items, n, d, m, L, eps, out);
     if (st != NRLSH_OK) return st;
+    int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
+    double margin_param = 0.0;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, margin_param) + sizeof(double))) {
+        storage = opts->hash_storage;
+        margin_mode = opts->margin_mode;
+        margin_param = opts->margin_param;
+    }
+    if (storage < NRLSH_STORAGE_FP32 || storage > NRLSH_STORAGE_FP8_E4M3)
+        return fail(NRLSH_E_INVALID_ARG, "hash_storage %d unknown", storage);
+    if (margin_mode != NRLSH_MARGIN_RIGOROUS && margin_mode != NRLSH_MARGIN_SCALED)
+        return fail(NRLSH_E_INVALID_ARG, "margin_mode %d unknown", margin_mode);
+    if (!(margin_param >= 0.0 && margin_param < 1e30))
+        return fail(NRLSH_E_INVALID_ARG, "margin_param must be finite and >= 0");
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
         const int dev = current_device();
@@ -714,6 +802,9 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         ix->W = L > 32 ? 2 : 1;
         ix->seed = seed;
         ix->eps = eps;
+        ix->storage = storage;
+        ix->margin_mode = margin_mode;
+        ix->margin_param = margin_param;
         ix->home = library_stream(dev);
         Timer tm(s);
         try {
@@ -860,6 +951,26 @@ nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes)
             uint64_t c = w[(size_t)p * ix->W];
             if (ix->W == 2) c |= (uint64_t)w[(size_t)p * 2 + 1] << 32;
             codes[perm[p]] = c;
+        }
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_get_hash_copy(const nrlsh_index *ix, void *data, float *scales, int32_t *storage)
+{
+    if (!ix || !data || !storage) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        const size_t cnt = (size_t)ix->n * ix->dp;
+        *storage = ix->storage;
+        if (ix->storage == NRLSH_STORAGE_FP32) {
+            HIPX(hipMemcpy(data, ix->Xl.get(), cnt * sizeof(float), hipMemcpyDeviceToHost));
+        } else if (ix->storage == NRLSH_STORAGE_BF16) {
+            HIPX(hipMemcpy(data, ix->Xh.get(), cnt * sizeof(uint16_t), hipMemcpyDeviceToHost));
+        } else {
+            if (!scales) return fail(NRLSH_E_INVALID_ARG, "scales is NULL");
+            HIPX(hipMemcpy(data, ix->Xf8.get(), cnt, hipMemcpyDeviceToHost));
+            HIPX(hipMemcpy(scales, ix->xscale.get(), (size_t)ix->n * sizeof(float), hipMemcpyDeviceToHost));
         }
         return NRLSH_OK;
     });

@@ -14,6 +14,8 @@ namespace nrlsh {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane) - 1ull; }
 
@@ -265,12 +267,15 @@ constexpr int H_WAVES = 8;
 constexpr int H_KC = 128;
 constexpr int H_KS = H_KC + 4;
 
+// With `rows` != NULL the kernel re-hashes the items rows[0 .. n) (a list of
+// stored positions, n = its length) and counts the bits it changes.
 template <int CB>
 __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
     const float *__restrict__ Xl, int64_t n, int d, int dp, const float *__restrict__ A, int L,
     const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
     const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ tau,
-    uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr)
+    uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr,
+    const int32_t *__restrict__ rows)
 {
     constexpr int NB = 16 * CB;
     __shared__ float As[NB * H_KS];
@@ -284,15 +289,22 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
         float sq = 0.f, uf = 0.f;
         int sp = 1;
         if (i < n) {
-            const int s = sid_l[i];
+            const int s = sid_l[rows ? rows[i] : i];
             const double km = keymax[s], u = U[s];
-            sq = sqrtf((float)(km - key_l[i]));
+            sq = sqrtf((float)(km - key_l[rows ? rows[i] : i]));
             uf = (float)u;
             sp = !(u >= 0x1p-60 && u <= 0x1p60);
         }
         sq_s[wave][lane] = sq;
         uf_s[wave][lane] = uf;
         sp_s[wave][lane] = sp;
+    }
+    // stored positions of this lane's four row-block rows (identity without a list)
+    int64_t rowpos[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) {
+        const int64_t row = i0 + 16 * rb + (lane & 15);
+        rowpos[rb] = (rows && row < n) ? (int64_t)rows[row] : row;
     }
     floatx4 acc[4][CB];
 #pragma unroll
@@ -316,7 +328,7 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
             for (int rb = 0; rb < 4; ++rb) {
                 const int64_t row = i0 + 16 * rb + r16;
                 xa[rb] = (row < n && k < dp)
-                             ? *reinterpret_cast<const floatx4 *>(Xl + row * dp + k)
+                             ? *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + k)
                              : floatx4{0.f, 0.f, 0.f, 0.f};
             }
             floatx4 bq[CB];
@@ -360,9 +372,15 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
             }
         }
     }
-    const int64_t i = i0 + lane;
-    const bool valid = i < n;
+    const bool valid = i0 + lane < n;
+    const int64_t i = valid && rows ? (int64_t)rows[i0 + lane] : i0 + lane;
     if (valid) {
+        if (rows) {  // bits the FP32 re-hash changes in the low-precision code
+            uint64_t old = codes_l[(CB <= 2 ? 1 : 2) * i];
+            if (CB > 2) old |= (uint64_t)codes_l[2 * i + 1] << 32;
+            const unsigned long long ch = (unsigned long long)__popcll(old ^ mycode);
+            if (ch) atomicAdd(&ctr->lowp_changed, ch);
+        }
         if (CB <= 2) {
             codes_l[i] = (uint32_t)mycode;
         } else {
@@ -385,6 +403,222 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
             fe.pad = 0;
             fix[slot] = fe;
         }
+    }
+}
+
+// ---------------------------------------------------------------- precision form
+// OCP E4M3: 1 sign, 4 exponent (bias 7), 3 mantissa bits; largest finite
+// 448 (0x7E), 0x7F is NaN, subnormals m * 2^-9.  Round to nearest even,
+// saturating at +-448.
+__device__ __forceinline__ uint8_t f32_to_e4m3(float f)
+{
+    const uint8_t sign = (__float_as_uint(f) >> 24) & 0x80u;
+    const float a = fabsf(f);
+    if (!(a < 448.0f)) return sign | 0x7Eu;
+    if (a < 0x1p-6f) {  // subnormal: a = m 2^-9, m in [0, 8]; m = 8 is the smallest normal
+        const int m = (int)__builtin_rintf(a * 512.0f);
+        return sign | (uint8_t)m;
+    }
+    int e;
+    const float fr = frexpf(a, &e);  // a = fr 2^e, fr in [0.5, 1)
+    int E = e - 1;                   // a = (2 fr) 2^E, 2 fr in [1, 2)
+    int m = (int)__builtin_rintf((2.0f * fr - 1.0f) * 8.0f);
+    if (m == 8) {
+        m = 0;
+        ++E;
+    }
+    const int code = ((E + 7) << 3) | m;
+    return sign | (uint8_t)(code > 0x7E ? 0x7E : code);
+}
+
+// Quantise `rows` rows of `d` floats (source stride `ss`) into bfloat16 (ST = 1)
+// or E4M3 with a per-row scale max|x| / 448 (ST = 2; 1 for an all-zero row),
+// zero-padded to dst stride `ds`.  One wave per row.
+template <int ST>
+__global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ src, int64_t rows,
+                                                    int d, int ss, void *__restrict__ dst, int ds,
+                                                    float *__restrict__ scales)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.x * 4 + wave;
+    if (r >= rows) return;
+    const float *x = src + r * ss;
+    if (ST == 1) {
+        uint16_t *o = static_cast<uint16_t *>(dst) + r * ds;
+        for (int c = lane; c < ds; c += 64) o[c] = c < d ? bf16_rne(x[c]) : (uint16_t)0;
+        return;
+    }
+    float mx = 0.f;
+    for (int c = lane; c < d; c += 64) mx = fmaxf(mx, fabsf(x[c]));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) mx = fmaxf(mx, __shfl_xor(mx, o, 64));
+    const float sc = mx > 0.f ? mx / 448.0f : 1.0f;
+    uint8_t *o = static_cast<uint8_t *>(dst) + r * ds;
+    for (int c = lane; c < ds; c += 64) o[c] = c < d ? f32_to_e4m3(x[c] / sc) : (uint8_t)0;
+    if (lane == 0) scales[r] = sc;
+}
+
+// Low-precision hash (ST = 1 bfloat16, ST = 2 E4M3 with row scales) on the
+// bf16 / fp8 matrix cores (16x16x32, FP32 accumulate): items = M, hash bits =
+// N; in an MFMA lane group g carries coordinates kk + 8 g .. + 7 of both
+// operands.  p~ = (scales) acc + a_d sqrt(keymax_j - key_i).  Every bit gets
+// sign(p~); an item with |p~| <= mq_r ||x_i|| + tq_r U_j for some bit (or with
+// U_j outside [2^-60, 2^60]) is appended to `rows` for the FP32 re-hash.
+template <int CB, int ST>
+__global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
+    const void *__restrict__ Xq, const float *__restrict__ xscale, int64_t n, int d, int dp,
+    const void *__restrict__ Aq, const float *__restrict__ ascale, const float *__restrict__ A,
+    int L, const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
+    const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ mq,
+    const float *__restrict__ tq, uint32_t *__restrict__ codes_l, int32_t *__restrict__ rows,
+    BuildCounters *__restrict__ ctr)
+{
+    constexpr int NB = 16 * CB;
+    constexpr int ES = ST == 1 ? 2 : 1;       // bytes per element
+    constexpr int KCQ = 128;                  // coordinates staged per chunk
+    constexpr int RB = KCQ * ES + (ST == 1 ? 16 : 8);  // LDS row stride in bytes
+    __shared__ __align__(16) uint8_t As[NB * RB];
+    __shared__ float sq_s[H_WAVES][64], uf_s[H_WAVES][64], xn_s[H_WAVES][64], xs_s[H_WAVES][64];
+    __shared__ int sp_s[H_WAVES][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t i0 = ((int64_t)blockIdx.x * H_WAVES + wave) * 64;
+    {
+        const int64_t i = i0 + lane;
+        float sq = 0.f, uf = 0.f, xn = 0.f, xs = 1.f;
+        int sp = 1;
+        if (i < n) {
+            const int s = sid_l[i];
+            const double km = keymax[s], u = U[s];
+            sq = sqrtf((float)(km - key_l[i]));
+            uf = (float)u;
+            xn = sqrtf((float)key_l[i]) * (1.0f + 0x1p-18f);
+            sp = !(u >= 0x1p-60 && u <= 0x1p60);
+            if (ST == 2) xs = xscale[i];
+        }
+        sq_s[wave][lane] = sq;
+        uf_s[wave][lane] = uf;
+        xn_s[wave][lane] = xn;
+        xs_s[wave][lane] = xs;
+        sp_s[wave][lane] = sp;
+    }
+    floatx4 acc[4][CB];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    const int r16 = lane & 15, g = lane >> 4;
+    const uint8_t *X8 = static_cast<const uint8_t *>(Xq);
+    const uint8_t *A8 = static_cast<const uint8_t *>(Aq);
+    for (int kc0 = 0; kc0 < dp; kc0 += KCQ) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < NB * KCQ; e += H_WAVES * 64) {
+            const int r = e / KCQ, c = e - (e / KCQ) * KCQ, k = kc0 + c;
+            if (ST == 1) {
+                reinterpret_cast<uint16_t *>(As + r * RB)[c] =
+                    (r < L && k < dp) ? reinterpret_cast<const uint16_t *>(A8)[(int64_t)r * dp + k] : (uint16_t)0;
+            } else {
+                As[r * RB + c] = (r < L && k < dp) ? A8[(int64_t)r * dp + k] : (uint8_t)0;
+            }
+        }
+        __syncthreads();
+        const int kend = min(KCQ, dp - kc0);
+        for (int kk = 0; kk < kend; kk += 32) {
+            const int k = kc0 + kk + 8 * g;
+            const bool kin = kk + 8 * g < kend;
+            if (ST == 1) {
+                bf16x8 xa[4], bq[CB];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int64_t row = i0 + 16 * rb + r16;
+                    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    if (row < n && kin) v = *reinterpret_cast<const u16x8 *>(X8 + (row * dp + k) * 2);
+                    xa[rb] = __builtin_bit_cast(bf16x8, v);
+                }
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb) {
+                    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    if (kin) v = *reinterpret_cast<const u16x8 *>(As + (16 * cb + r16) * RB + (kk + 8 * g) * 2);
+                    bq[cb] = __builtin_bit_cast(bf16x8, v);
+                }
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xa[rb], bq[cb], acc[rb][cb], 0, 0, 0);
+            } else {
+                long xa[4], bq[CB];
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) {
+                    const int64_t row = i0 + 16 * rb + r16;
+                    xa[rb] = (row < n && kin) ? *reinterpret_cast<const long *>(X8 + row * dp + k) : 0l;
+                }
+#pragma unroll
+                for (int cb = 0; cb < CB; ++cb)
+                    bq[cb] = kin ? *reinterpret_cast<const long *>(As + (16 * cb + r16) * RB + kk + 8 * g) : 0l;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(xa[rb], bq[cb], acc[rb][cb], 0, 0, 0);
+            }
+        }
+    }
+
+    const int my_rb = lane >> 4, my_g = (lane >> 2) & 3, my_v = lane & 3;
+    uint64_t mycode = 0, myflag = 0;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+        const int r = 16 * cb + r16;
+        const float alast = (r < L) ? A[(int64_t)r * (d + 1) + d] : 0.f;
+        const float m1 = (r < L) ? mq[r] : 0.f, m2 = (r < L) ? tq[r] : 0.f;
+        const float as = (ST == 2 && r < L) ? ascale[r] : 1.f;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = 16 * rb + 4 * g + v;
+                float p = acc[rb][cb][v];
+                if (ST == 2) p = p * (xs_s[wave][row] * as);
+                p = p + alast * sq_s[wave][row];
+                const bool inb = (r < L) && (i0 + row < n);
+                const float mg = m1 * xn_s[wave][row] + m2 * uf_s[wave][row];
+                const bool flag = inb && (sp_s[wave][row] != 0 || !(fabsf(p) > mg));
+                const bool bit = inb && (p > 0.f);
+                const uint64_t bb = __ballot(bit);
+                const uint64_t fb = __ballot(flag);
+                if (rb == my_rb && v == my_v) {
+                    mycode |= ((bb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                    myflag |= ((fb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                }
+            }
+        }
+    }
+    const int64_t i = i0 + lane;
+    const bool valid = i < n;
+    if (valid) {
+        if (CB <= 2) {
+            codes_l[i] = (uint32_t)mycode;
+        } else {
+            codes_l[2 * i] = (uint32_t)mycode;
+            codes_l[2 * i + 1] = (uint32_t)(mycode >> 32);
+        }
+    }
+    const bool has = valid && myflag != 0ull;
+    const uint64_t hb = __ballot(has);
+    const unsigned long long nbits = (unsigned long long)__popcll(valid ? myflag : 0ull);
+    unsigned long long wbits = nbits;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) wbits += __shfl_xor(wbits, o, 64);
+    if (hb != 0ull) {
+        const int leader = __ffsll((long long)hb) - 1;
+        uint32_t base = 0;
+        if (lane == leader) {
+            base = atomicAdd(&ctr->lowp_items, (uint32_t)__popcll(hb));
+            atomicAdd(&ctr->lowp_bits, wbits);
+        }
+        base = __shfl(base, leader, 64);
+        if (has) rows[base + (uint32_t)__popcll(hb & lanemask_lt(lane))] = (int32_t)i;
     }
 }
 
@@ -502,28 +736,65 @@ hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t
     return hipGetLastError();
 }
 
+hipError_t launch_quant_rows(const float *src, int64_t rows, int d, int ss, int storage, void *dst,
+                             int ds, float *scales, hipStream_t s)
+{
+    const dim3 grid(grid_for(rows, 4)), block(256);
+    if (storage == 1)
+        hipLaunchKernelGGL(k_quant_rows<1>, grid, block, 0, s, src, rows, d, ss, dst, ds, scales);
+    else
+        hipLaunchKernelGGL(k_quant_rows<2>, grid, block, 0, s, src, rows, d, ss, dst, ds, scales);
+    return hipGetLastError();
+}
+
+hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64_t n, int d, int dp,
+                         const void *Aq, const float *ascale, const float *A, int L,
+                         const double *key_l, const int32_t *sid_l, const double *keymax,
+                         const double *U, const float *mq, const float *tq, uint32_t *codes_l,
+                         int32_t *rows, BuildCounters *ctr, hipStream_t s)
+{
+    const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
+    const int cb = (L + 15) / 16;
+#define NRLSH_HQ(CB, ST)                                                                          \
+    hipLaunchKernelGGL((k_hash_q<CB, ST>), grid, block, 0, s, Xq, xscale, n, d, dp, Aq, ascale, A, L, \
+                       key_l, sid_l, keymax, U, mq, tq, codes_l, rows, ctr)
+    if (storage == 1) {
+        if (cb == 1) NRLSH_HQ(1, 1);
+        else if (cb == 2) NRLSH_HQ(2, 1);
+        else if (cb == 3) NRLSH_HQ(3, 1);
+        else NRLSH_HQ(4, 1);
+    } else {
+        if (cb == 1) NRLSH_HQ(1, 2);
+        else if (cb == 2) NRLSH_HQ(2, 2);
+        else if (cb == 3) NRLSH_HQ(3, 2);
+        else NRLSH_HQ(4, 2);
+    }
+#undef NRLSH_HQ
+    return hipGetLastError();
+}
+
 hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
                        const double *key_l, const int32_t *sid_l, const double *keymax,
                        const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
-                       BuildCounters *ctr, hipStream_t s)
+                       BuildCounters *ctr, const int32_t *rows, hipStream_t s)
 {
     const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
     switch ((L + 15) / 16) {
     case 1:
         hipLaunchKernelGGL(k_hash<1>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr);
+                           tau, codes_l, fix, ctr, rows);
         break;
     case 2:
         hipLaunchKernelGGL(k_hash<2>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr);
+                           tau, codes_l, fix, ctr, rows);
         break;
     case 3:
         hipLaunchKernelGGL(k_hash<3>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr);
+                           tau, codes_l, fix, ctr, rows);
         break;
     default:
         hipLaunchKernelGGL(k_hash<4>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr);
+                           tau, codes_l, fix, ctr, rows);
         break;
     }
     return hipGetLastError();

@@ -24,6 +24,10 @@ struct BuildCounters {
     uint32_t fix_count;      // entries appended to the FixEntry list
     unsigned long long fix_bits;
     unsigned long long fix_flips;
+    uint32_t lowp_items;     // items appended for the FP32 re-hash (precision form)
+    uint32_t pad;
+    unsigned long long lowp_bits;
+    unsigned long long lowp_changed;
 };
 
 // ------------------------------------------------------------------ build
@@ -54,10 +58,22 @@ hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t
 
 // SimpleLSH transform + sign random projection on the FP32 matrix cores, over
 // the stored rows (all arrays in stored order); writes the codes codes_l.
+// rows != NULL: re-hash only the stored positions rows[0 .. n).
 hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
                        const double *key_l, const int32_t *sid_l, const double *keymax,
                        const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
-                       BuildCounters *ctr, hipStream_t s);
+                       BuildCounters *ctr, const int32_t *rows, hipStream_t s);
+
+// Precision form: quantise rows to bfloat16 (storage 1) or E4M3 with row scales
+// (storage 2), then hash from the quantised copy; items inside the margin
+// mq_r ||x|| + tq_r U_j are appended to rows (count in ctr->lowp_items).
+hipError_t launch_quant_rows(const float *src, int64_t rows, int d, int ss, int storage, void *dst,
+                             int ds, float *scales, hipStream_t s);
+hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64_t n, int d, int dp,
+                         const void *Aq, const float *ascale, const float *A, int L,
+                         const double *key_l, const int32_t *sid_l, const double *keymax,
+                         const double *U, const float *mq, const float *tq, uint32_t *codes_l,
+                         int32_t *rows, BuildCounters *ctr, hipStream_t s);
 
 // FP64 recompute of the flagged projections, exactly as the definition.
 hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L,
