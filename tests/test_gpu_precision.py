@@ -43,9 +43,9 @@ def _stored_rows(ix, X):
 
 
 def test_fp8_copy_rounds_to_nearest_even():
-    """Every finite E4M3 value maps to its own code; midpoints between
-    neighbours go to the even code; beyond 448 saturates (scale fixed at 1 by
-    a 448 in every row)."""
+    """Every finite E4M3 value maps to its own code and midpoints between
+    neighbours go to the even code (the row scale max|x| / 448 is fixed at 1 by
+    a 448 in every row, so values above 448 cannot occur)."""
     say("case fp8 rounding")
     finite = [c for c in range(256) if (c & 0x7F) != 0x7F]
     vals, want = [], []
@@ -58,8 +58,6 @@ def test_fp8_copy_rounds_to_nearest_even():
         even = a if (a & 1) == 0 else b
         vals += [mid, -mid]
         want += [even, even | 0x80]
-    vals += [460.0, 1000.0, -3.0e38]
-    want += [0x7E, 0x7E, 0xFE]
     d = 64
     nrow = -(-len(vals) // (d - 1))
     X = np.zeros((nrow, d), np.float32)
