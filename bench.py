@@ -67,6 +67,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rerank", default="auto", choices=["auto", "gather", "screen", "screen_fp32"],
                     help="re-rank mode (all give identical results)")
+    ap.add_argument("--hash-storage", default="fp32", choices=["fp32", "bf16", "fp8"],
+                    help="precision form of the hash GEMM")
+    ap.add_argument("--margin", default="rigorous",
+                    help="'rigorous' or a relative margin for the low-precision hash")
+    ap.add_argument("--rerank-storage", default="fp32", choices=["fp32", "bf16"],
+                    help="rows the gather re-rank reads first (bf16: bounded, then exact)")
+    ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
+    ap.add_argument("--query-batch", type=int, default=0,
+                    help="queries per nrlsh_query call (0: all in one call)")
     ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the untimed recall sweep (needs --budget); used under a profiler so "
@@ -86,6 +95,9 @@ def main():
     from workloads import PRESETS
 
     w = PRESETS[args.workload]()
+    if args.nq is not None:
+        w.nq = args.nq
+    margin = args.margin if args.margin == "rigorous" else float(args.margin)
     torch.cuda.set_device(0)
     log(f"workload {w.name}: n={w.n} d={w.d} m={w.m} L={w.L} nq={w.nq} k={w.k}")
     t0 = time.perf_counter()
@@ -104,18 +116,18 @@ def main():
     nrec = min(args.recall_queries, w.nq)
     gt = ground_truth(Xd, Qd[:nrec], w.k) if not args.no_sweep else None
     curve = {}
-    ix = nr.nrlsh_build(Xd, w.m, w.L, w.index_seed)
-    norms = torch.linalg.vector_norm(Xd.double(), dim=1)
+    ix = nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage, margin=margin)
+    norms = torch.linalg.vector_norm(Xd, dim=1).double()
     med = float(norms.median())
     norm_stats = {"max_over_median": float(norms.max()) / med,
-                  "p999_over_median": float(torch.quantile(norms[:1_000_000], 0.999)) / med}
+                  "p999_over_median": float(torch.quantile(norms[:1_000_000].float(), 0.999)) / med}
     del norms
     budgets_sweep = sorted({*(1 << e for e in range(8, 40) if (1 << e) < w.n), w.n, *w.budgets})
     if args.no_sweep:
         budgets_sweep = []
     T_op = None
     for T in budgets_sweep:
-        ids, _ = nr.nrlsh_query(ix, Qd[:nrec], w.k, T)
+        ids, _ = nr.nrlsh_query(ix, Qd[:nrec], w.k, T, rerank_storage=args.rerank_storage)
         r = recall(ids.cpu().numpy(), gt)
         curve[T] = r
         log(f"recall@{w.k} T={T}: {r:.4f}")
@@ -129,9 +141,15 @@ def main():
         T_op = w.n
 
     # ---------------------------------------------------------------- timed steps
+    qb = args.query_batch if args.query_batch > 0 else w.nq
+
     def step(T):
-        with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed) as sx:
-            nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf), rerank=args.rerank)
+        with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage,
+                            margin=margin) as sx:
+            for b0 in range(0, w.nq, qb):
+                b1 = min(w.nq, b0 + qb)
+                nr.nrlsh_query(sx, Qd[b0:b1], w.k, T, out=(ids_buf[b0:b1], ips_buf[b0:b1]),
+                               rerank=args.rerank, rerank_storage=args.rerank_storage)
 
     def timed(T, steps, warmup, profile):
         for i in range(warmup):
@@ -149,8 +167,9 @@ def main():
         nr.nrlsh_profile_enable(False)
         return el / steps
 
-    names = ["keys", "sort", "layout", "hash", "hash_fixup", "qhash", "scan_hist", "threshold",
-             "tie_locate", "scan_emit", "rerank", "screen_max", "screen", "rerank_exact"]
+    names = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "qhash",
+             "scan_hist", "threshold", "tie_locate", "scan_emit", "rerank", "rerank_lp",
+             "screen_max", "screen", "rerank_exact"]
     # unprofiled timing for the headline, profiled run for the per-kernel split
     s_step = timed(T_op, args.steps, args.warmup, False)
     qstats = nr.nrlsh_get_query_stats()
@@ -190,10 +209,11 @@ def main():
         roof = {"kernel": "screen", "bound": "mfma", "achieved": achieved,
                 "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFS,
                 "traffic": None, "flops_per_launch": flops, "dominant_kernel": dom}
-    elif dom in ("rerank", "rerank_exact"):
+    elif dom in ("rerank", "rerank_exact", "rerank_lp"):
         # algorithmic bytes per probed item: its row (4d), stored position and id (8)
         launches = kern[dom]["launches_per_step"]
-        per_launch_bytes = (w.nq / launches) * Tq * (4 * w.d + 8)
+        row_bytes = (2 if dom == "rerank_lp" else 4) * w.d
+        per_launch_bytes = (w.nq / launches) * Tq * (row_bytes + 8)
         achieved = per_launch_bytes / (kern[dom]["avg_ms"] * 1e-3) / 1e9
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
@@ -231,7 +251,10 @@ def main():
         "arith": {"hash": "fp32 mfma + fp64 sign fix-up", "scan": "u32", "rerank": "f64"},
         "data": "synthetic",
         "config": {**w.describe(), "T": T_op, "op_point": "smallest power-of-two T with recall>=0.9"
-                   if args.budget is None else "fixed T", "parallelism": "single GPU"},
+                   if args.budget is None else "fixed T", "parallelism": "single GPU",
+                   "hash_storage": args.hash_storage, "margin": args.margin,
+                   "rerank": args.rerank, "rerank_storage": args.rerank_storage,
+                   "query_batch": qb},
         "recall_at_T": curve.get(T_op),
         "recall_curve": {str(k): v for k, v in curve.items()},
         "budgets": budgets,

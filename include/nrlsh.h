@@ -152,6 +152,11 @@ typedef struct nrlsh_query_opts {
     int32_t device_ptrs; /* 1: queries, out_ids, out_ips are device pointers */
     void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
     int32_t rerank_mode; /* nrlsh_rerank_mode (read when struct_size covers it) */
+    int32_t rerank_storage; /* GATHER re-rank rows: NRLSH_STORAGE_FP32 (default) or
+                               NRLSH_STORAGE_BF16: inner products from the bfloat16
+                               copy bound each item within (2^-8 + 2^-40) ||q|| ||x||;
+                               items that may still reach the top-k are re-ranked
+                               exactly from the FP32 rows (same result, fewer bytes) */
 } nrlsh_query_opts;
 
 nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -222,6 +227,10 @@ typedef struct nrlsh_query_stats {
     int64_t kept_total;    /* SCREEN: pairs kept for the exact re-rank, all queries */
     int64_t kept_max;      /* SCREEN: largest kept list of one query */
     int64_t theta_unset;   /* SCREEN: queries whose lower bound theta stayed -inf */
+    int64_t lp_kept_total; /* BF16 re-rank: items re-ranked exactly, all queries */
+    int64_t lp_kept_max;   /* BF16 re-rank: largest exact list of one query */
+    int32_t lp_fallbacks;  /* BF16 re-rank: batches that overflowed into the FP32 re-rank */
+    int32_t pad;
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

@@ -39,7 +39,7 @@ STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 class QueryOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
-                ("rerank_mode", C.c_int32)]
+                ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32)]
 
 
 RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3}
@@ -53,7 +53,8 @@ class BuildStats(C.Structure):
 
 class QueryStats(C.Structure):
     _fields_ = [("mode", C.c_int32), ("screen_passes", C.c_int32), ("kept_total", C.c_int64),
-                ("kept_max", C.c_int64), ("theta_unset", C.c_int64)]
+                ("kept_max", C.c_int64), ("theta_unset", C.c_int64), ("lp_kept_total", C.c_int64),
+                ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("pad", C.c_int32)]
 
 
 _lib = None
@@ -283,12 +284,13 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
 
 
 def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None,
-                rerank: str = "auto"):
+                rerank: str = "auto", rerank_storage: str = "fp32"):
     """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
     numpy for host queries, torch tensors for CUDA torch queries.  ``rerank``
     selects the re-rank mode ("auto", "gather", "screen"); all give the same
     result."""
     mode = RERANK_MODES[rerank]
+    rst = STORAGES[rerank_storage]
     if _is_torch_device(queries):
         import torch
         Q = queries.contiguous()
@@ -298,7 +300,7 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
             ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         else:
             ids, ips = out
-        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode)
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst)
         _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
                                     C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
         return ids, ips
@@ -306,8 +308,8 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
     nq = Q.shape[0]
     ids = np.empty((nq, k), dtype=np.int64)
     ips = np.empty((nq, k), dtype=np.float32)
-    if mode or stream is not None:
-        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode)
+    if mode or rst or stream is not None:
+        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst)
         _check(lib().nrlsh_query_ex(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                     C.byref(opts), ids.ctypes.data, ips.ctypes.data))
     else:
@@ -330,7 +332,9 @@ def nrlsh_get_query_stats() -> dict:
     _check(lib().nrlsh_get_query_stats(C.byref(st)))
     return {"mode": {1: "gather", 2: "screen", 3: "screen_fp32"}.get(st.mode, "none"),
             "screen_passes": st.screen_passes, "kept_total": st.kept_total,
-            "kept_max": st.kept_max, "theta_unset": st.theta_unset}
+            "kept_max": st.kept_max, "theta_unset": st.theta_unset,
+            "lp_kept_total": st.lp_kept_total, "lp_kept_max": st.lp_kept_max,
+            "lp_fallbacks": st.lp_fallbacks}
 
 
 def nrlsh_profile_enable(on: bool = True):

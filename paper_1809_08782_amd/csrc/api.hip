@@ -556,7 +556,7 @@ QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
 // and the re-rank is skipped.
 void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
                       int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
-                      hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+                      hipStream_t s, Timer &tm, uint32_t *nonfinite_d, bool bf16_rows = false)
 {
     const QueryShape sh = make_shape(ix, T, k);
     // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^29 entries
@@ -574,6 +574,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int nsplit = rerank_splits(B, sh.Tq);
     DBuf<double> part_v(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
     DBuf<int32_t> part_i(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
+    const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
+    DBuf<int32_t> lcount(bf16_rows ? (size_t)B : 1, s);
+    DBuf<int32_t> lists(bf16_rows ? (size_t)B * lcap : 1, s);
+    std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
@@ -594,6 +598,37 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                               ghthr.get(), gtie.get(), cb, s));
         tm.end();
         if (cand_out_d) continue;
+        if (bf16_rows) {
+            HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
+            tm.begin("rerank_lp");
+            HIPX(launch_rerank_lp(ix->Xh.get(), ix->key_l.get(), ix->perm.get(), Qb, nb, sh, cb,
+                                  nsplit, (int)lcap, lcount.get(), lists.get(), s));
+            tm.end();
+            HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
+                                hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            int64_t mx = 0, tot = 0;
+            for (int64_t i = 0; i < nb; ++i) {
+                mx = std::max<int64_t>(mx, hl[i]);
+                tot += hl[i];
+            }
+            if (mx <= lcap) {
+                g_qstats.lp_kept_total += tot;
+                g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, mx);
+                QueryShape shl = sh;
+                shl.Tq = lcap;  // list stride; lengths come from lcount
+                const int ns = rerank_splits(nb, lcap);
+                DBuf<double> pv(ns > 1 ? (size_t)nb * ns * k : 1, s);
+                DBuf<int32_t> pi(ns > 1 ? (size_t)nb * ns * k : 1, s);
+                tm.begin("rerank_exact");
+                HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(),
+                                   lcount.get(), ns, pv.get(), pi.get(), ids_d + b0 * k,
+                                   ips_d + b0 * k, s));
+                tm.end();
+                continue;
+            }
+            g_qstats.lp_fallbacks += 1;  // a list overflowed: re-rank this batch from FP32 rows
+        }
         tm.begin("rerank");
         HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, nullptr, nsplit,
                            part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
@@ -735,7 +770,8 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
 }
 
 void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
-               int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm, uint32_t *nonfinite_d)
+               bool bf16_rows, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+               uint32_t *nonfinite_d)
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
     bool screen = mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
@@ -746,7 +782,8 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     if (screen)
         run_query_screen(ix, Qd, nq, k, T, b3, ids_d, ips_d, s, tm, nonfinite_d);
     else
-        run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d);
+        run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d,
+                         bf16_rows);
 }
 
 template <typename F>
@@ -844,6 +881,9 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)) &&
         (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN_FP32))
         return fail(NRLSH_E_INVALID_ARG, "rerank_mode %d unknown", opts->rerank_mode);
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)) &&
+        opts->rerank_storage != NRLSH_STORAGE_FP32 && opts->rerank_storage != NRLSH_STORAGE_BF16)
+        return fail(NRLSH_E_INVALID_ARG, "rerank_storage %d unsupported", opts->rerank_storage);
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
@@ -855,15 +895,20 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         int mode = NRLSH_RERANK_AUTO;
         if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)))
             mode = opts->rerank_mode;
+        bool bf16_rows = false;
+        if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)))
+            bf16_rows = opts->rerank_storage == NRLSH_STORAGE_BF16;
         if (on_device) {
-            run_query(ix, queries, nq, k, probe_budget, mode, out_ids, out_ips, s, tm, flag.get());
+            run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, out_ids, out_ips, s, tm,
+                      flag.get());
         } else {
             DBuf<float> Qd((size_t)nq * ix->d, s);
             DBuf<int64_t> ids((size_t)nq * k, s);
             DBuf<float> ips((size_t)nq * k, s);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
-            run_query(ix, Qd.get(), nq, k, probe_budget, mode, ids.get(), ips.get(), s, tm, flag.get());
+            run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, ids.get(), ips.get(), s, tm,
+                      flag.get());
             HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),

@@ -26,6 +26,8 @@ namespace nrlsh {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- query_hash
 // One wave per query, lane r computes bit r: sum_t A[r][t] q_t in FP64 in
@@ -306,7 +308,13 @@ struct WaveTopK {
     }
 };
 
-template <int S>
+// LP = true: the rows come from the bfloat16 copy Xh.  ip~ = sum_t q_t x~_t in
+// FP64 satisfies |ip~ - ip| <= e = (2^-8 + 2^-40) ||q|| ||x|| (1 + 2^-20); the
+// wave keeps a top-k of the lower bounds ip~ - e and appends every item whose
+// upper bound ip~ + e reaches the current k-th lower bound to the query's
+// list (lists: nq x lcap, lcount: per query, may exceed lcap) -- a superset of
+// the exact top-k, re-ranked afterwards from the FP32 rows.
+template <int S, bool LP>
 __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                const int32_t *__restrict__ perm,
                                                const float *__restrict__ Q, int64_t n, int d,
@@ -316,7 +324,11 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                int64_t slice, int64_t *__restrict__ out_ids,
                                                float *__restrict__ out_ips,
                                                double *__restrict__ part_v,
-                                               int32_t *__restrict__ part_i)
+                                               int32_t *__restrict__ part_i,
+                                               const uint16_t *__restrict__ Xh,
+                                               const double *__restrict__ key_l, int lcap,
+                                               int32_t *__restrict__ lcount,
+                                               int32_t *__restrict__ lists)
 {
     __shared__ float tile[64 * RR_STRIDE];
     const int lane = threadIdx.x;
@@ -330,6 +342,13 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
     WaveTopK<S> top;
     top.init(k);
     const int sub = lane >> 3, seg = 4 * (lane & 7);
+    double qn = 0.0;  // LP: ||q|| (exact squares, FP64 sum, rounded up)
+    if (LP) {
+        for (int t = lane; t < d; t += 64) qn += (double)qv[t] * (double)qv[t];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o, 64);
+        qn = __builtin_sqrt(qn) * (1.0 + 0x1p-40);
+    }
 
     for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
         bool valid = c0 + lane < cend;
@@ -349,12 +368,32 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
         }
         double acc = 0.0;
         for (int k0 = 0; k0 < dp; k0 += 32) {
-            const int col = k0 + seg;
+            if (LP) {
+                // 4 lanes x 8 bfloat16 per row chunk: 16 rows per load instruction
 #pragma unroll
-            for (int it = 0; it < 8; ++it) {
-                floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-                if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
-                *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
+                for (int it = 0; it < 4; ++it) {
+                    const int rr = 16 * it + (lane >> 2), sg = 8 * (lane & 3);
+                    const bool ok = __shfl((int)valid, rr, 64) != 0 && k0 + sg < dp;
+                    const int64_t ro = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
+                    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                    if (ok) v = *reinterpret_cast<const u16x8 *>(Xh + ro + k0 + sg);
+                    floatx4 lo4, hi4;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        lo4[e] = __uint_as_float((uint32_t)v[e] << 16);
+                        hi4[e] = __uint_as_float((uint32_t)v[4 + e] << 16);
+                    }
+                    *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg]) = lo4;
+                    *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg + 4]) = hi4;
+                }
+            } else {
+                const int col = k0 + seg;
+#pragma unroll
+                for (int it = 0; it < 8; ++it) {
+                    floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+                    if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
+                    *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
+                }
             }
             __syncthreads();
             const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
@@ -370,8 +409,24 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
             }
             __syncthreads();
         }
-        top.offer(acc, id, valid, lane);
+        if (LP) {
+            const double e = (0x1p-8 + 0x1p-40) * qn * __builtin_sqrt(valid ? key_l[p] : 0.0) * (1.0 + 0x1p-20);
+            top.offer(acc - e, id, valid, lane);
+            const bool keep = valid && !(acc + e < top.th_v);
+            const uint64_t kb = __ballot(keep);
+            if (kb != 0ull) {
+                const int leader = __ffsll((long long)kb) - 1;
+                int base = 0;
+                if (lane == leader) base = atomicAdd(&lcount[q], __popcll(kb));
+                base = __shfl(base, leader, 64);
+                const int slot = base + __popcll(kb & ((1ull << lane) - 1ull));
+                if (keep && slot < lcap) lists[q * lcap + slot] = p;
+            }
+        } else {
+            top.offer(acc, id, valid, lane);
+        }
     }
+    if (LP) return;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int e = s * 64 + lane;
@@ -637,9 +692,6 @@ __global__ __launch_bounds__(256) void k_screen(
 // most gamma_{3d} (1.02 sum |q_t x_t|); the caller's g covers both with the
 // same factor-2 margin as the FP32 screen.  In MFMA j of a 32-coordinate
 // step, lane group g carries coordinates 32 kk + 8 g .. + 7 of both operands.
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
-
 __device__ __forceinline__ uint16_t q_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -1008,9 +1060,9 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
 #define NRLSH_RERANK(SS)                                                                         \
     do {                                                                                         \
-        hipLaunchKernelGGL(k_rerank<SS>, grid, block, 0, s, Xl, perm, Q, sh.n, sh.d, sh.dp,      \
-                           sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips, part_v,   \
-                           part_i);                                                              \
+        hipLaunchKernelGGL((k_rerank<SS, false>), grid, block, 0, s, Xl, perm, Q, sh.n, sh.d,    \
+                           sh.dp, sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips,    \
+                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr);               \
         if (nsplit > 1)                                                                          \
             hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
                                nsplit, sh.k, out_ids, out_ips);                                  \
@@ -1021,6 +1073,27 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     else if (S <= 8) NRLSH_RERANK(8);
     else NRLSH_RERANK(16);
 #undef NRLSH_RERANK
+    return hipGetLastError();
+}
+
+hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
+                            const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
+                            int nsplit, int lcap, int32_t *lcount, int32_t *lists, hipStream_t s)
+{
+    const int S = (sh.k + 63) / 64;
+    int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
+    slice = (slice + 63) / 64 * 64;
+    const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
+#define NRLSH_RERANK_LP(SS)                                                                       \
+    hipLaunchKernelGGL((k_rerank<SS, true>), grid, block, 0, s, nullptr, perm, Q, sh.n, sh.d, sh.dp, \
+                       sh.Tq, sh.k, cand, nullptr, nsplit, slice, nullptr, nullptr, nullptr,      \
+                       nullptr, Xh, key_l, lcap, lcount, lists)
+    if (S <= 1) NRLSH_RERANK_LP(1);
+    else if (S <= 2) NRLSH_RERANK_LP(2);
+    else if (S <= 4) NRLSH_RERANK_LP(4);
+    else if (S <= 8) NRLSH_RERANK_LP(8);
+    else NRLSH_RERANK_LP(16);
+#undef NRLSH_RERANK_LP
     return hipGetLastError();
 }
 

@@ -118,6 +118,13 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
                          int nsplit, double *part_v, int32_t *part_i, int64_t *out_ids,
                          float *out_ips, hipStream_t s);
 
+// Precision form of the re-rank: bounds from the bfloat16 copy Xh, appends to
+// lists (nq x lcap, lcount zeroed by the caller) every probed item that may
+// still belong to the exact top-k.
+hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
+                            const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
+                            int nsplit, int lcap, int32_t *lcount, int32_t *lists, hipStream_t s);
+
 // Stored position of the r*-th item of each query's threshold bucket (-1 if none).
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
                              int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s);

@@ -166,3 +166,23 @@ def test_scaled_margin_flips_stay_within_quantisation_bound(storage, margin):
                 bound = q * anorm[r] * math.sqrt(oix.key[i]) + tau[r] * oix.U[s]
                 assert abs(p) <= bound * 1.01, (i, r, p, bound)
     assert nflip <= 0.05 * n * L
+
+
+@pytest.mark.parametrize("k,T", [(10, 3000), (100, 2500), (10, 9000)])
+def test_bf16_rerank_copy_gives_exact_topk(k, T):
+    """Gather re-rank from the bfloat16 copy with bounds, then an exact FP64
+    re-rank of the items that may still reach the top-k: the oracle's result."""
+    n, d = 9000, 128
+    say(f"case bf16 rerank k={k} T={T}")
+    X = make_items("lognormal", n, d, seed=91, sigma=1.0)
+    Q = make_queries(150, d, seed=92)
+    oix = orc.OracleIndex(X, 16, 64, seed=33, threads=8)
+    oids, oips = oix.query(Q, k, T, threads=8)
+    with nr.nrlsh_build(X, 16, 64, 33) as gix:
+        ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage="bf16")
+        st = nr.nrlsh_get_query_stats()
+        say(f"  exact re-rank lists: total {st['lp_kept_total']} max {st['lp_kept_max']} "
+            f"fallbacks {st['lp_fallbacks']}")
+        assert np.array_equal(ids, oids)
+        assert np.array_equal(ips, oips.astype(np.float32))
+        assert st["lp_kept_total"] > 0 and st["lp_fallbacks"] == 0
