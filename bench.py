@@ -28,6 +28,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0       # MI355X HBM3E
 FP32_MFMA_PEAK_TFS = 157.3  # MI355X dense FP32 matrix
+BF16_MFMA_PEAK_TFS = 2500.0  # MI355X dense bf16 matrix
 
 
 def log(*a):
@@ -45,6 +46,33 @@ def ground_truth(Xd, Qs, k):
         out.append(torch.topk(sc, k, dim=0).indices.T.cpu())
     del X64
     return torch.cat(out).numpy()
+
+
+def traffic_record(kernel, workload, T):
+    """HBM bytes per launch of `kernel` from a committed counter summary
+    (profiles/*.md, a line "traffic_record: {json}"), provided the sources it
+    names still hash to what they were when the counters were taken."""
+    import glob
+    import hashlib
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        with open(path) as f:
+            lines = [ln for ln in f if ln.startswith("traffic_record: ")]
+        for ln in lines:
+            rec = json.loads(ln[len("traffic_record: "):])
+            if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("T") != T:
+                continue
+            same = True
+            for src, digest in rec.get("sources", {}).items():
+                fp = os.path.join(ROOT, src)
+                if not os.path.exists(fp):
+                    same = False
+                    break
+                with open(fp, "rb") as f:
+                    same &= hashlib.sha256(f.read()).hexdigest() == digest
+            if same:
+                rec["file"] = os.path.relpath(path, ROOT)
+                return rec
+    return None
 
 
 def recall(ids, gt):
@@ -77,6 +105,9 @@ def main():
     ap.add_argument("--query-batch", type=int, default=0,
                     help="queries per nrlsh_query call (0: all in one call)")
     ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy a MIB-MiB buffer 3 times before the steps (a kernel of known "
+                         "traffic that scales hardware byte counters)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the untimed recall sweep (needs --budget); used under a profiler so "
                          "that only timed-step kernels are launched")
@@ -140,6 +171,18 @@ def main():
     if T_op is None:
         T_op = w.n
 
+    if args.copy_calibration > 0:
+        # a fill (writes B bytes) and an elementwise copy (reads B, writes B)
+        # of B = MIB MiB: kernels of known traffic for the byte counters
+        nel = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(nel, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"copy calibration: fill + 3 elementwise copies of {args.copy_calibration} MiB")
+        del src, dst
+
     # ---------------------------------------------------------------- timed steps
     qb = args.query_batch if args.query_batch > 0 else w.nq
 
@@ -201,14 +244,27 @@ def main():
     dom = max(kern, key=lambda nm: kern[nm]["avg_ms"] * kern[nm]["launches_per_step"]) if kern else None
     roof = None
     if dom == "screen":
-        # algorithmic work of one screen launch: the FP32 inner products of the
-        # probed pairs, 2 d flop each ((queries per launch) x T pairs)
+        # algorithmic work of one screen launch: the inner products of the
+        # probed pairs ((queries per launch) x T pairs).  The bf16x3 screen
+        # forms each one from three bfloat16 products (hi*hi + hi*lo + lo*hi),
+        # 3 x 2d flop on the bf16 matrix cores; the FP32 screen 2d flop.
         launches = kern["screen"]["launches_per_step"]
-        flops = 2.0 * w.d * (w.nq / launches) * Tq
+        pairs = (w.nq / launches) * Tq
+        b3 = qstats.get("mode") == "screen"
+        flops = (6.0 if b3 else 2.0) * w.d * pairs
+        peak = BF16_MFMA_PEAK_TFS if b3 else FP32_MFMA_PEAK_TFS
         achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
-        roof = {"kernel": "screen", "bound": "mfma", "achieved": achieved,
-                "peak": FP32_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / FP32_MFMA_PEAK_TFS,
-                "traffic": None, "flops_per_launch": flops, "dominant_kernel": dom}
+        kname = "k_screen3<1, false>" if b3 else "k_screen<1, false>"
+        if w.L > 32:
+            kname = kname.replace("<1,", "<2,")
+        rec = traffic_record(kname, w.name, Tq)
+        roof = {"kernel": kname, "bound": "mfma",
+                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+                "traffic_source": rec, "mfma_dtype": "bf16" if b3 else "f32",
+                "flops_per_launch": flops, "pairs_per_launch": pairs,
+                "fp32_equivalent_tflops": 2.0 * w.d * pairs / (kern["screen"]["avg_ms"] * 1e-3) / 1e12,
+                "dominant_kernel": dom}
     elif dom in ("rerank", "rerank_exact", "rerank_lp"):
         # algorithmic bytes per probed item: its row (4d), stored position and id (8)
         launches = kern[dom]["launches_per_step"]
@@ -218,6 +274,16 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": per_launch_bytes, "dominant_kernel": dom}
+
+    # scan pass 1: effective code-stream rate (every query reads every code
+    # once: nq n 4W bytes) and (query, item) pairs per second
+    scan = None
+    if "scan_hist" in kern:
+        W = (w.L + 31) // 32
+        per = kern["scan_hist"]
+        qpl = w.nq / per["launches_per_step"]
+        scan = {"pairs_per_s": qpl * w.n / (per["avg_ms"] * 1e-3),
+                "code_stream_GBps": qpl * w.n * 4 * W / (per["avg_ms"] * 1e-3) / 1e9}
 
     # ---------------------------------------------------------------- CPU oracle baseline
     cpu = None
@@ -264,6 +330,7 @@ def main():
         "query_stats": qstats,
         "norm_stats": norm_stats,
         "roofline": roof,
+        "scan": scan,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -163,6 +163,101 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
                             int64_t probe_budget, const nrlsh_query_opts *opts,
                             int64_t *out_ids, float *out_ips);
 
+/* ------------------------------------------------------- batching form --
+ * Many indexes (uneven n, d, L, m), each with its own query batch (uneven nq)
+ * and probe budget, served together.  Each (index, batch) pair gets exactly
+ * what nrlsh_query gives it (Section 3.3 multi-probe, Algorithm 2 exact
+ * re-rank, same tie rules): the batching form changes how the work is
+ * scheduled, not what is computed.
+ *
+ * The work of all pairs is cut into items -- query hash (16 queries), scan
+ * pass 1 and scan pass 2 (one chunk of stored items of one sub-dataset for a
+ * tile of 64 queries), threshold (a tile), tie location (a query), re-rank
+ * (one slice of a query's probed list) and merge (a query) -- and each phase
+ * is ONE launch over the items of every pair (one wave per item); the seven
+ * launches of a run are captured once in a hipGraph and replayed.
+ *
+ * A plan fixes the set's shape (the indexes, each nq and probe budget, k) and
+ * owns the workspace, the captured graph and the tile shape of each pair:
+ * stored items per scan item ("chunk") and candidates per re-rank item
+ * ("slice").  Tile shapes come from a process-wide table keyed by (d rounded
+ * up to a power of two, L, batch class: nq <= 16, <= 256, > 256), filled by
+ * the autotuner, which times candidate shapes on the plan's own pairs
+ * (grouped by class) while the plan is created.
+ *
+ * A single persistent launch for all phases (items ordered by a work queue
+ * and waiting on per-tile counters) is implemented but disabled: requesting
+ * it (opts->persistent = 1) returns NRLSH_E_INVALID_ARG, because launches of
+ * it did not complete in testing. */
+typedef struct nrlsh_query_desc {
+    const nrlsh_index *index;
+    const float *queries; /* nq x d of that index (host, or device with device_ptrs) */
+    int64_t nq;           /* >= 0 (0: the pair is skipped) */
+    int64_t probe_budget; /* T >= 1, clamped to the index's n */
+    int64_t *out_ids;     /* nq x k */
+    float *out_ips;       /* nq x k */
+} nrlsh_query_desc;
+
+typedef enum {
+    NRLSH_TUNE_TABLE = 0,  /* shapes from the table; defaults for classes not in it */
+    NRLSH_TUNE_MISSING = 1,/* tune the classes of this set that are not in the table */
+    NRLSH_TUNE_ALL = 2,    /* re-tune every class of this set */
+    NRLSH_TUNE_DEFAULT = 3 /* fixed default shapes, table ignored */
+} nrlsh_tune_mode;
+
+typedef struct nrlsh_multi_opts {
+    int32_t struct_size; /* sizeof(nrlsh_multi_opts) */
+    int32_t device_ptrs; /* 1: queries / out_ids / out_ips are device pointers */
+    void *stream;        /* hipStream_t to run on, or NULL for the library's stream */
+    int32_t use_graph;   /* 1: replay a captured hipGraph (default); 0: launch directly */
+    int32_t tune;        /* nrlsh_tune_mode */
+    int32_t chunk;       /* > 0: force this chunk for every pair (multiple of 64) */
+    int32_t slice;       /* > 0: force this slice for every pair (multiple of 64) */
+    int32_t persistent;  /* 1: the single persistent launch (disabled, see above) */
+} nrlsh_multi_opts;
+
+typedef struct nrlsh_multi_plan nrlsh_multi_plan; /* opaque */
+
+/* Creates a plan for descs[0 .. count) (1 <= count <= 4096) at top-k k.  All
+ * indexes must live on one device.  Pointers in descs are only checked here;
+ * nrlsh_multi_run takes the pointers of its own descs.  With autotuning the
+ * plan runs the launch several times on these descs (their outputs are then
+ * overwritten by nrlsh_multi_run).  Limits: the probed lists of all pairs hold
+ * at most 2^31 entries in all. */
+nrlsh_status nrlsh_multi_plan_create(const nrlsh_query_desc *descs, int32_t count, int32_t k,
+                                     const nrlsh_multi_opts *opts, nrlsh_multi_plan **out);
+
+/* Runs the plan on descs of the same shape (same count, index, nq and probe
+ * budget per entry; query and output pointers may differ from call to call).
+ * Synchronous.  NRLSH_E_NOT_FINITE if a query holds NaN / Inf. */
+nrlsh_status nrlsh_multi_run(nrlsh_multi_plan *plan, const nrlsh_query_desc *descs, int32_t count);
+
+/* Releases the plan.  NULL is a no-op. */
+void nrlsh_multi_plan_free(nrlsh_multi_plan *plan);
+
+/* create + run + free. */
+nrlsh_status nrlsh_query_multi(const nrlsh_query_desc *descs, int32_t count, int32_t k,
+                               const nrlsh_multi_opts *opts);
+
+typedef struct nrlsh_multi_info {
+    int32_t grid;          /* work-groups (one wave each) of the largest launch */
+    int32_t graph;         /* 1: runs replay a captured hipGraph */
+    int64_t items[7];      /* work items per phase: QH HIST THR TIE EMIT RR MERGE */
+    int32_t tuned_classes; /* classes the autotuner timed while creating the plan */
+    int32_t pad;
+    double tune_ms;        /* wall-clock time spent tuning */
+} nrlsh_multi_info;
+
+/* Plan summary; chunk / slice (may be NULL) receive count tile shapes. */
+nrlsh_status nrlsh_multi_plan_info(const nrlsh_multi_plan *plan, nrlsh_multi_info *info,
+                                   int32_t *chunk, int32_t *slice);
+
+/* Drops every entry of the autotuner's table. */
+void nrlsh_tune_clear(void);
+
+/* Table entry of class (d, L, nq): 1 and the shape if present, else 0. */
+int32_t nrlsh_tune_lookup(int32_t d, int32_t L, int64_t nq, int32_t *chunk, int32_t *slice);
+
 /* Thread-local message for the last non-OK status of this thread. */
 const char *nrlsh_last_error(void);
 
@@ -240,7 +335,8 @@ nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);
  * kernel is launched on.  Off by default; enabling adds one event pair per
  * timed launch.  Names: "keys", "sort", "layout", "hash", "hash_fixup",
  * "qhash", "scan_hist", "threshold", "scan_emit", "rerank", "tie_locate",
- * "screen_max", "screen", "rerank_exact". */
+ * "screen_max", "screen", "rerank_exact", and "multi" (one persistent
+ * batching-form launch). */
 void nrlsh_profile_enable(int32_t on);
 void nrlsh_profile_reset(void);
 /* Total milliseconds and launch count of kernel `name` since the last reset. */

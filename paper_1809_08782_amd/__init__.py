@@ -3,12 +3,12 @@
 The compute path lives in ``libnrlsh.so`` (HIP kernels for gfx950 behind the C
 ABI of ``include/nrlsh.h``); this package is its thin ctypes binding.
 """
-from ._lib import (Index, NrlshError, header_symbols, lib, nrlsh_build, nrlsh_free,
-                   nrlsh_get_query_stats,
+from ._lib import (Index, MultiPlan, NrlshError, header_symbols, lib, nrlsh_build, nrlsh_free,
+                   nrlsh_get_query_stats, nrlsh_query_multi, nrlsh_tune_clear, nrlsh_tune_lookup,
                    nrlsh_last_error, nrlsh_profile_enable, nrlsh_profile_get,
                    nrlsh_profile_reset, nrlsh_query)
 
-__all__ = ["Index", "NrlshError", "header_symbols", "lib", "nrlsh_build", "nrlsh_free",
-           "nrlsh_get_query_stats",
+__all__ = ["Index", "MultiPlan", "NrlshError", "header_symbols", "lib", "nrlsh_build", "nrlsh_free",
+           "nrlsh_get_query_stats", "nrlsh_query_multi", "nrlsh_tune_clear", "nrlsh_tune_lookup",
            "nrlsh_last_error", "nrlsh_profile_enable", "nrlsh_profile_get",
            "nrlsh_profile_reset", "nrlsh_query"]

@@ -57,6 +57,25 @@ class QueryStats(C.Structure):
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("pad", C.c_int32)]
 
 
+class QueryDesc(C.Structure):
+    _fields_ = [("index", C.c_void_p), ("queries", C.c_void_p), ("nq", C.c_int64),
+                ("probe_budget", C.c_int64), ("out_ids", C.c_void_p), ("out_ips", C.c_void_p)]
+
+
+class MultiOpts(C.Structure):
+    _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
+                ("use_graph", C.c_int32), ("tune", C.c_int32), ("chunk", C.c_int32),
+                ("slice", C.c_int32), ("persistent", C.c_int32)]
+
+
+class MultiInfo(C.Structure):
+    _fields_ = [("grid", C.c_int32), ("graph", C.c_int32), ("items", C.c_int64 * 7),
+                ("tuned_classes", C.c_int32), ("pad", C.c_int32), ("tune_ms", C.c_double)]
+
+
+TUNE_MODES = {"table": 0, "missing": 1, "all": 2, "default": 3}
+MULTI_PHASES = ("qhash", "hist", "threshold", "tie", "emit", "rerank", "merge")
+
 _lib = None
 P = C.c_void_p
 I32, I64, U64, F64 = C.c_int32, C.c_int64, C.c_uint64, C.c_double
@@ -105,6 +124,21 @@ def lib():
         L.nrlsh_query_candidates.restype = st
         L.nrlsh_get_query_stats.argtypes = [C.POINTER(QueryStats)]
         L.nrlsh_get_query_stats.restype = st
+        L.nrlsh_multi_plan_create.argtypes = [C.POINTER(QueryDesc), I32, I32,
+                                              C.POINTER(MultiOpts), C.POINTER(P)]
+        L.nrlsh_multi_plan_create.restype = st
+        L.nrlsh_multi_run.argtypes = [P, C.POINTER(QueryDesc), I32]
+        L.nrlsh_multi_run.restype = st
+        L.nrlsh_multi_plan_free.argtypes = [P]
+        L.nrlsh_multi_plan_free.restype = None
+        L.nrlsh_query_multi.argtypes = [C.POINTER(QueryDesc), I32, I32, C.POINTER(MultiOpts)]
+        L.nrlsh_query_multi.restype = st
+        L.nrlsh_multi_plan_info.argtypes = [P, C.POINTER(MultiInfo), P, P]
+        L.nrlsh_multi_plan_info.restype = st
+        L.nrlsh_tune_clear.argtypes = []
+        L.nrlsh_tune_clear.restype = None
+        L.nrlsh_tune_lookup.argtypes = [I32, I32, I64, C.POINTER(I32), C.POINTER(I32)]
+        L.nrlsh_tune_lookup.restype = I32
         L.nrlsh_profile_enable.argtypes = [I32]
         L.nrlsh_profile_enable.restype = None
         L.nrlsh_profile_reset.argtypes = []
@@ -119,7 +153,7 @@ def header_symbols() -> list:
     """Function names declared in include/nrlsh.h."""
     with open(HEADER_PATH) as f:
         text = f.read()
-    decl = r"^(?:nrlsh_status|void|const char\s*\*)\s*\*?\s*(nrlsh_[a-z_0-9]+)\s*\("
+    decl = r"^(?:nrlsh_status|void|int32_t|const char\s*\*)\s*\*?\s*(nrlsh_[a-z_0-9]+)\s*\("
     return sorted(set(re.findall(decl, text, re.M)))
 
 
@@ -316,6 +350,119 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
         _check(lib().nrlsh_query(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                  ids.ctypes.data, ips.ctypes.data))
     return ids, ips
+
+
+class MultiPlan:
+    """Owns an ``nrlsh_multi_plan*``: the batching form for a fixed set of
+    (index, query batch, probe budget) pairs, served by one persistent launch.
+
+    ``pairs`` is a list of (Index, queries, probe_budget); the queries are all
+    CUDA torch tensors (device pointers, torch's current stream) or all host
+    arrays.  The plan owns one (ids, ips) output pair per entry; run() fills
+    them and returns the list."""
+
+    def __init__(self, pairs, k: int, *, use_graph: bool = True, tune: str = "table",
+                 chunk: int = 0, slice: int = 0, stream=None, persistent: bool = False):
+        self.k = k
+        self._h = P()
+        dev = [_is_torch_device(q) for _, q, _ in pairs]
+        if any(dev) and not all(dev):
+            raise ValueError("queries must be all device tensors or all host arrays")
+        self.device = bool(dev) and all(dev)
+        self._index = [ix for ix, _, _ in pairs]
+        self._budget = [int(T) for _, _, T in pairs]
+        self.outputs = []
+        for ix, q, _ in pairs:
+            nq = q.shape[0]
+            if self.device:
+                import torch
+                self.outputs.append((torch.empty((nq, k), dtype=torch.int64, device=q.device),
+                                     torch.empty((nq, k), dtype=torch.float32, device=q.device)))
+            else:
+                self.outputs.append((np.empty((nq, k), np.int64), np.empty((nq, k), np.float32)))
+        self._descs, self._keep = self._make_descs([q for _, q, _ in pairs])
+        if stream is None and self.device:
+            stream = _torch_stream(pairs[0][1])
+        opts = MultiOpts(C.sizeof(MultiOpts), 1 if self.device else 0, stream,
+                         1 if use_graph else 0, TUNE_MODES[tune], int(chunk), int(slice),
+                         1 if persistent else 0)
+        _check(lib().nrlsh_multi_plan_create(self._descs, len(pairs), k, C.byref(opts),
+                                             C.byref(self._h)))
+
+    def _make_descs(self, queries):
+        if len(queries) != len(self._index):
+            raise ValueError(f"expected {len(self._index)} query batches, got {len(queries)}")
+        arr = (QueryDesc * len(queries))()
+        keep = []
+        for i, (ix, q, T, (ids, ips)) in enumerate(zip(self._index, queries, self._budget,
+                                                         self.outputs)):
+            if self.device:
+                q = q.contiguous()
+                qp, ip, pp = q.data_ptr(), ids.data_ptr(), ips.data_ptr()
+            else:
+                q = _host_f32(q)
+                qp, ip, pp = q.ctypes.data, ids.ctypes.data, ips.ctypes.data
+            keep.append(q)
+            if q.shape[0] and q.shape[1] != ix.d:
+                raise ValueError(f"pair {i}: queries have {q.shape[1]} columns, index d = {ix.d}")
+            arr[i] = QueryDesc(ix.handle.value, qp, q.shape[0], T, ip, pp)
+        return arr, keep
+
+    def run(self, queries=None):
+        """Runs the plan (with new query batches of the same shapes if given)."""
+        if queries is None:
+            _check(lib().nrlsh_multi_run(self._h, self._descs, len(self._index)))
+            return self.outputs
+        descs, keep = self._make_descs(queries)
+        _check(lib().nrlsh_multi_run(self._h, descs, len(self._index)))
+        self._descs, self._keep = descs, keep
+        return self.outputs
+
+    def info(self) -> dict:
+        inf = MultiInfo()
+        n = len(self._index)
+        chunk = np.zeros(n, np.int32)
+        sl = np.zeros(n, np.int32)
+        _check(lib().nrlsh_multi_plan_info(self._h, C.byref(inf), chunk.ctypes.data, sl.ctypes.data))
+        return {"grid": inf.grid, "graph": bool(inf.graph),
+                "items": dict(zip(MULTI_PHASES, list(inf.items))),
+                "tuned_classes": inf.tuned_classes, "tune_ms": inf.tune_ms,
+                "chunk": chunk.tolist(), "slice": sl.tolist()}
+
+    def close(self):
+        if self._h:
+            lib().nrlsh_multi_plan_free(self._h)
+            self._h = P()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover
+            pass
+
+
+def nrlsh_query_multi(pairs, k: int, **kw):
+    """Batching form in one call (plan, run, free).  Returns [(ids, ips), ...]."""
+    with MultiPlan(pairs, k, **kw) as plan:
+        return plan.run()
+
+
+def nrlsh_tune_clear():
+    lib().nrlsh_tune_clear()
+
+
+def nrlsh_tune_lookup(d: int, L: int, nq: int):
+    """(chunk, slice) of the autotuner's table for class (d, L, nq), or None."""
+    c, s = I32(), I32()
+    if lib().nrlsh_tune_lookup(d, L, nq, C.byref(c), C.byref(s)):
+        return c.value, s.value
+    return None
 
 
 def nrlsh_free(ix: Index):

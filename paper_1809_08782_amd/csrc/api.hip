@@ -17,16 +17,36 @@
 #include <string>
 #include <vector>
 
+#include "host_common.h"
 #include "nrlsh.h"
 #include "nrlsh_internal.h"
 
 using namespace nrlsh;
+using namespace nrlsh::host;
 
-// ================================================================= errors
 namespace {
 
 thread_local std::string g_err;
 thread_local nrlsh_query_stats g_qstats;
+
+struct ProfEntry {
+    double ms = 0.0;
+    int64_t launches = 0;
+};
+
+std::atomic<int> g_prof_on{0};
+std::mutex g_prof_mu;
+std::map<std::string, ProfEntry> g_prof;
+
+std::mutex g_dev_mu;
+std::map<int, hipStream_t> g_streams;
+std::map<int, bool> g_pool_ready;
+
+}  // namespace
+
+// ================================================================= plumbing
+namespace nrlsh {
+namespace host {
 
 nrlsh_status fail(nrlsh_status st, const char *fmt, ...)
 {
@@ -39,11 +59,6 @@ nrlsh_status fail(nrlsh_status st, const char *fmt, ...)
     return st;
 }
 
-struct Failure {
-    nrlsh_status st;
-    std::string msg;
-};
-
 [[noreturn]] void throw_hip(hipError_t e, const char *what)
 {
     if (e == hipErrorOutOfMemory)
@@ -51,76 +66,15 @@ struct Failure {
     throw Failure{NRLSH_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e)};
 }
 
-#define HIPX(call)                                      \
-    do {                                                \
-        hipError_t e_ = (call);                         \
-        if (e_ != hipSuccess) throw_hip(e_, #call);     \
-    } while (0)
+bool prof_enabled() { return g_prof_on.load() != 0; }
 
-// ================================================================= profiling
-struct ProfEntry {
-    double ms = 0.0;
-    int64_t launches = 0;
-};
-
-std::atomic<int> g_prof_on{0};
-std::mutex g_prof_mu;
-std::map<std::string, ProfEntry> g_prof;
-
-// Records an event pair around each timed launch; settle() must run after the
-// stream has been synchronised.
-class Timer {
-  public:
-    explicit Timer(hipStream_t s) : s_(s), on_(g_prof_on.load() != 0) {}
-    ~Timer()
-    {
-        for (auto &p : pending_) {
-            (void)hipEventDestroy(p.a);
-            (void)hipEventDestroy(p.b);
-        }
-    }
-    void begin(const char *name)
-    {
-        if (!on_) return;
-        Pending p;
-        p.name = name;
-        HIPX(hipEventCreate(&p.a));
-        HIPX(hipEventCreate(&p.b));
-        HIPX(hipEventRecord(p.a, s_));
-        pending_.push_back(p);
-    }
-    void end()
-    {
-        if (!on_) return;
-        HIPX(hipEventRecord(pending_.back().b, s_));
-    }
-    void settle()
-    {
-        if (!on_) return;
-        std::lock_guard<std::mutex> g(g_prof_mu);
-        for (auto &p : pending_) {
-            float ms = 0.f;
-            HIPX(hipEventElapsedTime(&ms, p.a, p.b));
-            ProfEntry &e = g_prof[p.name];
-            e.ms += ms;
-            e.launches += 1;
-        }
-    }
-
-  private:
-    struct Pending {
-        const char *name;
-        hipEvent_t a, b;
-    };
-    hipStream_t s_;
-    bool on_;
-    std::vector<Pending> pending_;
-};
-
-// ================================================================= device memory
-std::mutex g_dev_mu;
-std::map<int, hipStream_t> g_streams;
-std::map<int, bool> g_pool_ready;
+void prof_record(const char *name, float ms)
+{
+    std::lock_guard<std::mutex> g(g_prof_mu);
+    ProfEntry &e = g_prof[name];
+    e.ms += ms;
+    e.launches += 1;
+}
 
 hipStream_t library_stream(int dev)
 {
@@ -145,39 +99,17 @@ void prepare_pool(int dev)
     g_pool_ready[dev] = true;
 }
 
-// Stream-ordered device buffer; freed on the stream it was allocated on.
-template <typename T>
-struct DBuf {
-    T *p = nullptr;
-    hipStream_t s = nullptr;
-    DBuf() = default;
-    DBuf(size_t count, hipStream_t st) : s(st)
-    {
-        if (count == 0) count = 1;
-        void *v = nullptr;
-        hipError_t e = hipMallocAsync(&v, count * sizeof(T), st);
-        if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
-        p = static_cast<T *>(v);
-    }
-    DBuf(const DBuf &) = delete;
-    DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
-    DBuf &operator=(DBuf &&o) noexcept
-    {
-        reset();
-        p = o.p;
-        s = o.s;
-        o.p = nullptr;
-        return *this;
-    }
-    ~DBuf() { reset(); }
-    void reset()
-    {
-        if (p) (void)hipFreeAsync(p, s);
-        p = nullptr;
-    }
-    T *get() const { return p; }
-};
+int current_device()
+{
+    int dev = 0;
+    HIPX(hipGetDevice(&dev));
+    return dev;
+}
+
+}  // namespace host
+}  // namespace nrlsh
+
+namespace {
 
 // ================================================================= projection
 // SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) addressed by position: output
@@ -248,13 +180,6 @@ void make_rank_table(const std::vector<double> &U, int L, double eps, std::vecto
     }
 }
 
-int current_device()
-{
-    int dev = 0;
-    HIPX(hipGetDevice(&dev));
-    return dev;
-}
-
 bool all_finite(const float *p, int64_t count)
 {
     for (int64_t i = 0; i < count; ++i)
@@ -263,30 +188,6 @@ bool all_finite(const float *p, int64_t count)
 }
 
 }  // namespace
-
-// ================================================================= the index
-struct nrlsh_index {
-    int device = 0;
-    int64_t n = 0;
-    int32_t d = 0, dp = 0, m = 0, L = 0, W = 1;
-    uint64_t seed = 0;
-    double eps = 0.0;
-    int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
-    double margin_param = 0.0;
-    std::vector<float> A_h;
-    std::vector<double> keymax_h, U_h;
-    std::vector<int64_t> off_h;
-    std::vector<int32_t> R_h;
-    nrlsh_build_stats stats{};
-    hipStream_t home = nullptr;  // library stream that releases the device buffers
-    DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
-    DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
-    DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
-    DBuf<float> xscale;                  // its row scales
-    DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
-    DBuf<int32_t> sid, sid_l, perm, off, R, inv;
-    DBuf<uint32_t> codes_l;              // stored order
-};
 
 namespace {
 
@@ -784,20 +685,6 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
     else
         run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d,
                          bf16_rows);
-}
-
-template <typename F>
-nrlsh_status guarded(F &&f)
-{
-    try {
-        return f();
-    } catch (const Failure &e) {
-        return fail(e.st, "%s", e.msg.c_str());
-    } catch (const std::bad_alloc &) {
-        return fail(NRLSH_E_OUT_OF_MEMORY, "host allocation failed");
-    } catch (...) {
-        return fail(NRLSH_E_INTERNAL, "unexpected exception");
-    }
 }
 
 }  // namespace

@@ -1,0 +1,178 @@
+// Device helpers of the exact re-rank (Algorithm 2: the item with the largest
+// inner product), shared by the per-index query kernels and the multi-index
+// persistent kernel.
+//
+// A wave takes 64 candidates at a time (lane = candidate).  Their rows are
+// streamed in 32-float chunks: each load instruction brings 8 rows x 128
+// contiguous bytes, the chunk is transposed through LDS and lane c adds
+// q_t x_ct in FP64 in ascending t (products of two floats are exact in FP64,
+// so the sum is the definition's, bit for bit).  The running top-k, sorted by
+// (ip desc, id asc), lives in registers, S entries per lane.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+#include <cstdint>
+
+namespace nrlsh {
+namespace dev {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int RR_STRIDE = 36;  // floats per LDS row (16-byte aligned, conflict-free b128)
+constexpr int RR_TILE_FLOATS = 64 * RR_STRIDE;
+
+__device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t ib)
+{
+    return a > b || (a == b && ia < ib);
+}
+
+// Sorted top-k list held by one wave: entry e = s*64 + lane.
+template <int S>
+struct WaveTopK {
+    double tv[S];
+    int32_t ti[S];
+    double th_v;
+    int32_t th_i;
+    int ks, kl;
+
+    __device__ void init(int k)
+    {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            tv[s] = -INFINITY;
+            ti[s] = INT_MAX;
+        }
+        th_v = -INFINITY;
+        th_i = INT_MAX;
+        ks = (k - 1) >> 6;
+        kl = (k - 1) & 63;
+    }
+
+    // Offer one value per lane (ok = lane has a real candidate).
+    __device__ void offer(double v, int32_t id, bool ok, int lane)
+    {
+        uint64_t mask = __ballot(ok && better(v, id, th_v, th_i));
+        while (mask != 0ull) {
+            const int src = __ffsll((long long)mask) - 1;
+            mask &= mask - 1ull;
+            const double nv = __shfl(v, src, 64);
+            const int32_t ni = __shfl(id, src, 64);
+            if (!better(nv, ni, th_v, th_i)) continue;
+            int pos = 0;
+#pragma unroll
+            for (int s = 0; s < S; ++s) pos += __popcll(__ballot(better(tv[s], ti[s], nv, ni)));
+            double nvv[S];
+            int32_t nii[S];
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                double up_v = __shfl_up(tv[s], 1, 64);
+                int32_t up_i = __shfl_up(ti[s], 1, 64);
+                const double carry_v = s > 0 ? __shfl(tv[s > 0 ? s - 1 : 0], 63, 64) : -INFINITY;
+                const int32_t carry_i = s > 0 ? __shfl(ti[s > 0 ? s - 1 : 0], 63, 64) : INT_MAX;
+                if (lane == 0) {
+                    up_v = carry_v;
+                    up_i = carry_i;
+                }
+                const int e = s * 64 + lane;
+                nvv[s] = e > pos ? up_v : (e == pos ? nv : tv[s]);
+                nii[s] = e > pos ? up_i : (e == pos ? ni : ti[s]);
+            }
+#pragma unroll
+            for (int s = 0; s < S; ++s) {
+                tv[s] = nvv[s];
+                ti[s] = nii[s];
+            }
+            th_v = __shfl(tv[ks], kl, 64);
+            th_i = __shfl(ti[ks], kl, 64);
+        }
+    }
+};
+
+// sum_t q_t x_pt in FP64, ascending t, for the stored row p of each lane
+// (valid lanes only; 0 otherwise).  Xl rows are dp floats, zero past d.
+__device__ __forceinline__ double ip64_rows_fp32(const float *__restrict__ Xl, int d, int dp,
+                                                 const float *__restrict__ qv, int32_t p, bool valid,
+                                                 int lane, float *tile)
+{
+    const int sub = lane >> 3, seg = 4 * (lane & 7);
+    int64_t roff[8];
+    bool rval[8];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        const int rr = 8 * it + sub;
+        roff[it] = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
+        rval[it] = __shfl((int)valid, rr, 64) != 0;
+    }
+    double acc = 0.0;
+    for (int k0 = 0; k0 < dp; k0 += 32) {
+        const int col = k0 + seg;
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
+            *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
+        }
+        __syncthreads();
+        const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt) {
+            const floatx4 x4 = row[tt];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = k0 + 4 * tt + u;
+                const float qt = t < d ? qv[t] : 0.f;
+                acc = acc + (double)qt * (double)x4[u];
+            }
+        }
+        __syncthreads();
+    }
+    return acc;
+}
+
+// The same sum over the bfloat16 copy Xh of the rows (rows of dp values).
+__device__ __forceinline__ double ip64_rows_bf16(const uint16_t *__restrict__ Xh, int d, int dp,
+                                                 const float *__restrict__ qv, int32_t p, bool valid,
+                                                 int lane, float *tile)
+{
+    double acc = 0.0;
+    for (int k0 = 0; k0 < dp; k0 += 32) {
+        // 4 lanes x 8 bfloat16 per row chunk: 16 rows per load instruction
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int rr = 16 * it + (lane >> 2), sg = 8 * (lane & 3);
+            const bool ok = __shfl((int)valid, rr, 64) != 0 && k0 + sg < dp;
+            const int64_t ro = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
+            u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+            if (ok) v = *reinterpret_cast<const u16x8 *>(Xh + ro + k0 + sg);
+            floatx4 lo4, hi4;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                lo4[e] = __uint_as_float((uint32_t)v[e] << 16);
+                hi4[e] = __uint_as_float((uint32_t)v[4 + e] << 16);
+            }
+            *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg]) = lo4;
+            *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg + 4]) = hi4;
+        }
+        __syncthreads();
+        const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
+#pragma unroll
+        for (int tt = 0; tt < 8; ++tt) {
+            const floatx4 x4 = row[tt];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int t = k0 + 4 * tt + u;
+                const float qt = t < d ? qv[t] : 0.f;
+                acc = acc + (double)qt * (double)x4[u];
+            }
+        }
+        __syncthreads();
+    }
+    return acc;
+}
+
+}  // namespace dev
+}  // namespace nrlsh

@@ -1,0 +1,168 @@
+// Host-side plumbing shared by the translation units of libnrlsh: errors,
+// per-launch timing, the library stream and stream-ordered device buffers,
+// and the index object itself.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "nrlsh.h"
+
+namespace nrlsh {
+namespace host {
+
+// ================================================================= errors
+// Records the thread's error text and returns st.
+nrlsh_status fail(nrlsh_status st, const char *fmt, ...);
+
+struct Failure {
+    nrlsh_status st;
+    std::string msg;
+};
+
+[[noreturn]] void throw_hip(hipError_t e, const char *what);
+
+#define HIPX(call)                                      \
+    do {                                                \
+        hipError_t e_ = (call);                         \
+        if (e_ != hipSuccess) throw_hip(e_, #call);     \
+    } while (0)
+
+// Runs f, turning exceptions into a status and the thread's error text.
+template <typename F>
+nrlsh_status guarded(F &&f)
+{
+    try {
+        return f();
+    } catch (const Failure &e) {
+        return fail(e.st, "%s", e.msg.c_str());
+    } catch (const std::bad_alloc &) {
+        return fail(NRLSH_E_OUT_OF_MEMORY, "host allocation failed");
+    } catch (...) {
+        return fail(NRLSH_E_INTERNAL, "unexpected exception");
+    }
+}
+
+
+// ================================================================= profiling
+bool prof_enabled();
+void prof_record(const char *name, float ms);
+
+// Records an event pair around each timed launch; settle() must run after the
+// stream has been synchronised.
+class Timer {
+  public:
+    explicit Timer(hipStream_t s) : s_(s), on_(prof_enabled()) {}
+    ~Timer()
+    {
+        for (auto &p : pending_) {
+            (void)hipEventDestroy(p.a);
+            (void)hipEventDestroy(p.b);
+        }
+    }
+    void begin(const char *name)
+    {
+        if (!on_) return;
+        Pending p;
+        p.name = name;
+        HIPX(hipEventCreate(&p.a));
+        HIPX(hipEventCreate(&p.b));
+        HIPX(hipEventRecord(p.a, s_));
+        pending_.push_back(p);
+    }
+    void end()
+    {
+        if (!on_) return;
+        HIPX(hipEventRecord(pending_.back().b, s_));
+    }
+    void settle()
+    {
+        if (!on_) return;
+        for (auto &p : pending_) {
+            float ms = 0.f;
+            HIPX(hipEventElapsedTime(&ms, p.a, p.b));
+            prof_record(p.name, ms);
+        }
+    }
+
+  private:
+    struct Pending {
+        const char *name;
+        hipEvent_t a, b;
+    };
+    hipStream_t s_;
+    bool on_;
+    std::vector<Pending> pending_;
+};
+
+// ================================================================= device memory
+// The library's own non-blocking stream on device dev (default priority).
+hipStream_t library_stream(int dev);
+// Keeps freed stream-ordered memory in the device pool.
+void prepare_pool(int dev);
+int current_device();
+
+// Stream-ordered device buffer; freed on the stream it was allocated on.
+template <typename T>
+struct DBuf {
+    T *p = nullptr;
+    hipStream_t s = nullptr;
+    DBuf() = default;
+    DBuf(size_t count, hipStream_t st) : s(st)
+    {
+        if (count == 0) count = 1;
+        void *v = nullptr;
+        hipError_t e = hipMallocAsync(&v, count * sizeof(T), st);
+        if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
+        p = static_cast<T *>(v);
+    }
+    DBuf(const DBuf &) = delete;
+    DBuf &operator=(const DBuf &) = delete;
+    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+    DBuf &operator=(DBuf &&o) noexcept
+    {
+        reset();
+        p = o.p;
+        s = o.s;
+        o.p = nullptr;
+        return *this;
+    }
+    ~DBuf() { reset(); }
+    void reset()
+    {
+        if (p) (void)hipFreeAsync(p, s);
+        p = nullptr;
+    }
+    T *get() const { return p; }
+};
+
+}  // namespace host
+}  // namespace nrlsh
+
+// ================================================================= the index
+struct nrlsh_index {
+    int device = 0;
+    int64_t n = 0;
+    int32_t d = 0, dp = 0, m = 0, L = 0, W = 1;
+    uint64_t seed = 0;
+    double eps = 0.0;
+    int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
+    double margin_param = 0.0;
+    std::vector<float> A_h;
+    std::vector<double> keymax_h, U_h;
+    std::vector<int64_t> off_h;
+    std::vector<int32_t> R_h;
+    nrlsh_build_stats stats{};
+    hipStream_t home = nullptr;  // library stream that releases the device buffers
+    nrlsh::host::DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
+    nrlsh::host::DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
+    nrlsh::host::DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
+    nrlsh::host::DBuf<float> xscale;                  // its row scales
+    nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
+    nrlsh::host::DBuf<int32_t> sid, sid_l, perm, off, R, inv;
+    nrlsh::host::DBuf<uint32_t> codes_l;              // stored order
+};

@@ -20,6 +20,7 @@
 #include <climits>
 #include <cmath>
 
+#include "dev_rerank.h"
 #include "nrlsh_internal.h"
 
 namespace nrlsh {
@@ -232,81 +233,12 @@ __global__ __launch_bounds__(64) void k_scan_emit(const uint32_t *__restrict__ c
 }
 
 // ---------------------------------------------------------------- rerank
-// One wave per (query, slice of its probed list).  Candidates are taken 64
-// at a time (lane = candidate); their rows are streamed in 32-float chunks:
-// each load instruction brings 8 rows x 128 contiguous bytes, the chunk is
-// transposed through LDS and lane c adds q_t x_ct in FP64 in ascending t.
-// The running top-k (sorted by (ip desc, id asc)) lives in registers, S
-// entries per lane.  With several slices per query, each slice writes a
-// partial list and k_topk_merge combines them.
-constexpr int RR_STRIDE = 36;  // floats per LDS row (16-byte aligned, conflict-free b128)
-
-__device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t ib)
-{
-    return a > b || (a == b && ia < ib);
-}
-
-// Sorted top-k list held by one wave: entry e = s*64 + lane.
-template <int S>
-struct WaveTopK {
-    double tv[S];
-    int32_t ti[S];
-    double th_v;
-    int32_t th_i;
-    int ks, kl;
-
-    __device__ void init(int k)
-    {
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            tv[s] = -INFINITY;
-            ti[s] = INT_MAX;
-        }
-        th_v = -INFINITY;
-        th_i = INT_MAX;
-        ks = (k - 1) >> 6;
-        kl = (k - 1) & 63;
-    }
-
-    // Offer one value per lane (ok = lane has a real candidate).
-    __device__ void offer(double v, int32_t id, bool ok, int lane)
-    {
-        uint64_t mask = __ballot(ok && better(v, id, th_v, th_i));
-        while (mask != 0ull) {
-            const int src = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            const double nv = __shfl(v, src, 64);
-            const int32_t ni = __shfl(id, src, 64);
-            if (!better(nv, ni, th_v, th_i)) continue;
-            int pos = 0;
-#pragma unroll
-            for (int s = 0; s < S; ++s) pos += __popcll(__ballot(better(tv[s], ti[s], nv, ni)));
-            double nvv[S];
-            int32_t nii[S];
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                double up_v = __shfl_up(tv[s], 1, 64);
-                int32_t up_i = __shfl_up(ti[s], 1, 64);
-                const double carry_v = s > 0 ? __shfl(tv[s > 0 ? s - 1 : 0], 63, 64) : -INFINITY;
-                const int32_t carry_i = s > 0 ? __shfl(ti[s > 0 ? s - 1 : 0], 63, 64) : INT_MAX;
-                if (lane == 0) {
-                    up_v = carry_v;
-                    up_i = carry_i;
-                }
-                const int e = s * 64 + lane;
-                nvv[s] = e > pos ? up_v : (e == pos ? nv : tv[s]);
-                nii[s] = e > pos ? up_i : (e == pos ? ni : ti[s]);
-            }
-#pragma unroll
-            for (int s = 0; s < S; ++s) {
-                tv[s] = nvv[s];
-                ti[s] = nii[s];
-            }
-            th_v = __shfl(tv[ks], kl, 64);
-            th_i = __shfl(ti[ks], kl, 64);
-        }
-    }
-};
+// One wave per (query, slice of its probed list); the rows of 64 candidates
+// at a time are summed in FP64 (dev::ip64_rows_*), the running top-k kept by
+// dev::WaveTopK.  With several slices per query, each slice writes a partial
+// list and k_topk_merge combines them.
+using dev::RR_STRIDE;
+using dev::WaveTopK;
 
 // LP = true: the rows come from the bfloat16 copy Xh.  ip~ = sum_t q_t x~_t in
 // FP64 satisfies |ip~ - ip| <= e = (2^-8 + 2^-40) ||q|| ||x|| (1 + 2^-20); the
@@ -341,7 +273,6 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
     const int64_t cend = min(len, cbeg + slice);
     WaveTopK<S> top;
     top.init(k);
-    const int sub = lane >> 3, seg = 4 * (lane & 7);
     double qn = 0.0;  // LP: ||q|| (exact squares, FP64 sum, rounded up)
     if (LP) {
         for (int t = lane; t < d; t += 64) qn += (double)qv[t] * (double)qv[t];
@@ -358,57 +289,8 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
             valid = p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
             if (valid) id = perm[p];
         }
-        int64_t roff[8];
-        bool rval[8];
-#pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            const int rr = 8 * it + sub;
-            roff[it] = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
-            rval[it] = __shfl((int)valid, rr, 64) != 0;
-        }
-        double acc = 0.0;
-        for (int k0 = 0; k0 < dp; k0 += 32) {
-            if (LP) {
-                // 4 lanes x 8 bfloat16 per row chunk: 16 rows per load instruction
-#pragma unroll
-                for (int it = 0; it < 4; ++it) {
-                    const int rr = 16 * it + (lane >> 2), sg = 8 * (lane & 3);
-                    const bool ok = __shfl((int)valid, rr, 64) != 0 && k0 + sg < dp;
-                    const int64_t ro = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
-                    u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-                    if (ok) v = *reinterpret_cast<const u16x8 *>(Xh + ro + k0 + sg);
-                    floatx4 lo4, hi4;
-#pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        lo4[e] = __uint_as_float((uint32_t)v[e] << 16);
-                        hi4[e] = __uint_as_float((uint32_t)v[4 + e] << 16);
-                    }
-                    *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg]) = lo4;
-                    *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg + 4]) = hi4;
-                }
-            } else {
-                const int col = k0 + seg;
-#pragma unroll
-                for (int it = 0; it < 8; ++it) {
-                    floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-                    if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
-                    *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
-                }
-            }
-            __syncthreads();
-            const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
-#pragma unroll
-            for (int tt = 0; tt < 8; ++tt) {
-                const floatx4 x4 = row[tt];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int t = k0 + 4 * tt + u;
-                    const float qt = t < d ? qv[t] : 0.f;
-                    acc = acc + (double)qt * (double)x4[u];
-                }
-            }
-            __syncthreads();
-        }
+        const double acc = LP ? dev::ip64_rows_bf16(Xh, d, dp, qv, p, valid, lane, tile)
+                              : dev::ip64_rows_fp32(Xl, d, dp, qv, p, valid, lane, tile);
         if (LP) {
             const double e = (0x1p-8 + 0x1p-40) * qn * __builtin_sqrt(valid ? key_l[p] : 0.0) * (1.0 + 0x1p-20);
             top.offer(acc - e, id, valid, lane);

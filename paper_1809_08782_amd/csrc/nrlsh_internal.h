@@ -157,4 +157,83 @@ hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xl
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
                          int32_t *counts, int32_t *lists, hipStream_t s);
 
+// ------------------------------------------------------------------ batching form
+// One (index, query batch) pair of a multi-index launch.  Index arrays are
+// read-only during the launch; the workspace arrays belong to this pair.
+struct MultiDesc {
+    // index
+    const float *Xl;
+    const int32_t *perm;
+    const uint32_t *codes_l;
+    const int32_t *off;   // m + 1 stored-position bounds of the sub-datasets
+    const int32_t *R;     // rank table, m x (L+1)
+    const int32_t *inv;   // histogram index of each probing rank
+    const float *At;      // A[:, :d] transposed (d x L)
+    int64_t n;
+    int32_t d, dp, m, L, W;
+    int32_t tile_base;    // first per-tile counter of this pair
+    // queries and results
+    const float *Q;       // nq x d
+    int64_t nq;
+    int64_t Tq;           // min(T, n)
+    int64_t q_base;       // first per-query counter of this pair
+    int64_t *out_ids;     // nq x k
+    float *out_ips;       // nq x k
+    // workspace
+    uint32_t *qcodes;     // nq x W
+    uint32_t *ghist;      // tiles x m x (L+1) x 64, zero between launches
+    int32_t *ghthr;       // tiles x m x 64
+    int32_t *gtie;        // tiles x 4 x 64
+    int32_t *gpstar;      // nq
+    int32_t *cand;        // nq x Tq
+    double *part_v;       // nq x nsplit x k (nsplit > 1)
+    int32_t *part_i;
+    // tile shape
+    int32_t chunk;        // stored items per scan work item
+    int32_t nch;          // scan work items per sub-dataset
+    int32_t slice;        // candidates per re-rank work item
+    int32_t nsplit;       // re-rank work items per query
+};
+
+// Written by the last work-group of a multi-index launch.
+struct MultiResult {
+    int32_t done;       // 1 once the launch has drained
+    int32_t error;      // MULTI_ERR_* bits
+    int32_t nonfinite;  // queries held NaN / Inf
+    int32_t pad;
+};
+
+constexpr int MULTI_PHASES = 7;        // QH HIST THR TIE EMIT RR MERGE
+constexpr int MULTI_CTR_TILES = 16;    // first per-tile counter
+constexpr int MULTI_TILE_CTRS = 5;     // per tile: QH HIST THR TIE EMIT done
+constexpr int MULTI_ERR_TIMEOUT = 1;   // a wait exceeded its wall-clock limit
+constexpr int MULTI_ERR_COUNT = 2;     // a probed list did not hold min(T, n) items
+
+// Counter words of a launch with `tiles` query tiles and `nq` queries in all.
+__host__ __device__ inline int64_t multi_ctr_words(int64_t tiles, int64_t nq)
+{
+    return MULTI_CTR_TILES + MULTI_TILE_CTRS * tiles + 2 * nq;
+}
+
+// The persistent kernel over descs[0 .. nb) with phase-major item numbering
+// seg[ph * nb + b] (prefix sums, seg[7 nb] = item count).  descs, seg and
+// result live in one device block uploaded before the launch.
+size_t multi_lds_bytes(int maxL);
+hipError_t multi_occupancy(int k, size_t lds, int *blocks_per_cu);
+// Phase-per-launch form: one launch per phase with items[ph] work-groups
+// (phases without items are skipped); ctr_q: 2 nq_total words, the first
+// nq_total of which the threshold phase resets.  Errors and non-finite
+// queries are or-ed into *result (zeroed by the caller before the launches).
+hipError_t launch_multi_phases(const MultiDesc *descs, int nb, const int64_t *seg,
+                               const int64_t *items, MultiResult *result, int32_t *ctr_q,
+                               int64_t nq_total, int k, size_t lds, hipStream_t s);
+
+// Persistent form (one launch for all phases, items wait on counters).
+// ctr: multi_ctr_words(ntiles, nq_total) words, zero before the first
+// launch (each launch leaves them zero unless it reports an error).
+// limit_ticks bounds every wait of the launch, in wall_clock64 ticks.
+hipError_t launch_multi(const MultiDesc *descs, int nb, const int64_t *seg, MultiResult *result,
+                        int32_t *ctr, int64_t ntiles, int64_t nq_total, int k,
+                        int64_t limit_ticks, int grid, size_t lds, hipStream_t s);
+
 }  // namespace nrlsh

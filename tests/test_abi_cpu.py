@@ -106,3 +106,45 @@ def test_inspection_rejects_null():
     assert L.nrlsh_get_build_stats(None, None) == INVALID
     assert L.nrlsh_query_codes(None, None, 1, None) == INVALID
     assert L.nrlsh_query_candidates(None, None, 1, 1, None) == INVALID
+
+
+def _desc(index=1, queries=1, nq=2, T=10, ids=1, ips=1):
+    return _lib.QueryDesc(index, queries, nq, T, ids, ips)
+
+
+@pytest.mark.parametrize("field,bad", [("index", 0), ("nq", -1), ("T", 0), ("queries", 0),
+                                       ("ids", 0), ("ips", 0)])
+def test_multi_rejects_bad_descriptors(field, bad):
+    """Descriptor checks run on the host before any index is touched (the
+    index pointers here are never dereferenced)."""
+    d = (_lib.QueryDesc * 1)(_desc(**{field: bad}))
+    h = C.c_void_p()
+    assert nr.lib().nrlsh_multi_plan_create(d, 1, 10, None, C.byref(h)) == INVALID
+    assert not h.value
+    assert nr.nrlsh_last_error()
+
+
+def test_multi_rejects_bad_counts_k_and_options():
+    L = nr.lib()
+    d = (_lib.QueryDesc * 1)(_desc(index=0))
+    h = C.c_void_p()
+    assert L.nrlsh_multi_plan_create(None, 1, 10, None, C.byref(h)) == INVALID
+    assert L.nrlsh_multi_plan_create(d, 0, 10, None, C.byref(h)) == INVALID
+    assert L.nrlsh_multi_plan_create(d, 4097, 10, None, C.byref(h)) == INVALID
+    assert L.nrlsh_multi_plan_create(d, 1, 0, None, C.byref(h)) == INVALID
+    assert L.nrlsh_multi_plan_create(d, 1, 1025, None, C.byref(h)) == INVALID
+    assert L.nrlsh_multi_plan_create(d, 1, 10, None, None) == INVALID
+    # options are read first: the message names the option, not the descriptor
+    for key, v, word in (("tune", 9, "tune"), ("chunk", 100, "chunk"), ("slice", -64, "slice"),
+                         ("struct_size", 4, "struct_size"), ("persistent", 1, "persistent")):
+        o = _lib.MultiOpts(C.sizeof(_lib.MultiOpts), 0, None, 1, 0, 0, 0)
+        setattr(o, key, v)
+        assert L.nrlsh_multi_plan_create(d, 1, 10, C.byref(o), C.byref(h)) == INVALID
+        assert word in nr.nrlsh_last_error()
+    assert L.nrlsh_multi_run(None, d, 1) == INVALID
+    L.nrlsh_multi_plan_free(None)
+
+
+def test_tune_table_lookup_on_empty_table():
+    nr.nrlsh_tune_clear()
+    assert nr.nrlsh_tune_lookup(128, 32, 100) is None
