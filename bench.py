@@ -201,7 +201,7 @@ def main():
     ap.add_argument("--recall-queries", type=int, default=1000)
     ap.add_argument("--cpu-sample", type=int, default=256, help="queries the oracle baseline times")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--rerank", default="auto", choices=["auto", "gather", "screen", "screen_fp32"],
+    ap.add_argument("--rerank", default="auto", choices=["auto", "gather", "screen", "screen_fp32", "screen_bf16x3"],
                     help="re-rank mode (all give identical results)")
     ap.add_argument("--hash-storage", default="fp32", choices=["fp32", "bf16", "fp8"],
                     help="precision form of the hash GEMM")
@@ -382,23 +382,27 @@ def main():
     roof = None
     if dom == "screen":
         # algorithmic work of one screen launch: the inner products of the
-        # probed pairs ((queries per launch) x T pairs).  The bf16x3 screen
-        # forms each one from three bfloat16 products (hi*hi + hi*lo + lo*hi),
-        # 3 x 2d flop on the bf16 matrix cores; the FP32 screen 2d flop.
+        # probed pairs ((queries per launch) x T pairs), 2d flop each on the
+        # bf16 (or FP32) matrix cores; the bf16x3 screen forms each one from
+        # three bfloat16 products (hi*hi + hi*lo + lo*hi), 3 x 2d flop.
         launches = kern["screen"]["launches_per_step"]
         pairs = (w.nq / launches) * Tq
-        b3 = qstats.get("mode") == "screen"
-        flops = (6.0 if b3 else 2.0) * w.d * pairs
-        peak = BF16_MFMA_PEAK_TFS if b3 else FP32_MFMA_PEAK_TFS
+        smode = qstats.get("mode")
+        products = {"screen": 1, "screen_bf16x3": 3}.get(smode, 1)
+        b16 = smode in ("screen", "screen_bf16x3")
+        flops = 2.0 * products * w.d * pairs
+        peak = BF16_MFMA_PEAK_TFS if b16 else FP32_MFMA_PEAK_TFS
         achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
-        kname = "k_screen3<1, false>" if b3 else "k_screen<1, false>"
+        kname = {"screen": "k_screen3<1, false, false>",
+                 "screen_bf16x3": "k_screen3<1, false, true>"}.get(smode, "k_screen<1, false>")
         if w.L > 32:
             kname = kname.replace("<1,", "<2,")
         rec = traffic_record(kname, w.name, Tq)
         roof = {"kernel": kname, "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
                 "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
-                "traffic_source": rec, "mfma_dtype": "bf16" if b3 else "f32",
+                "traffic_source": rec, "mfma_dtype": "bf16" if b16 else "f32",
+                "bf16_products_per_pair": products if b16 else None,
                 "flops_per_launch": flops, "pairs_per_launch": pairs,
                 "fp32_equivalent_tflops": 2.0 * w.d * pairs / (kern["screen"]["avg_ms"] * 1e-3) / 1e12,
                 "dominant_kernel": dom}

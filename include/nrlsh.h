@@ -131,20 +131,24 @@ nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq
                          int64_t probe_budget, int64_t *out_ids, float *out_ips);
 
 /* How the probed items are re-ranked; every mode returns the same result.
- *   GATHER:      each query's probed list is materialised and its rows gathered.
- *   SCREEN:      queries are tiled 64 at a time against chunks of stored rows on
- *                the matrix cores with a bfloat16 hi/lo split (three bf16
- *                products per pair); pairs that are probed and whose inner
- *                product (with a rigorous rounding bound) can still reach a
- *                lower bound of the k-th best are re-ranked exactly in FP64.
- *   SCREEN_FP32: the same screen with FP32 matrix-core products.
- *   AUTO:        SCREEN for large budgets (T >= n/128, T >= 2048, >= 64 queries),
- *                else GATHER. */
+ *   GATHER:        each query's probed list is materialised and its rows gathered.
+ *   SCREEN:        queries are tiled 64 at a time against chunks of stored rows on
+ *                  the bf16 matrix cores with q and x rounded to bfloat16 (one
+ *                  product per pair); pairs that are probed and whose inner
+ *                  product (with a rigorous bound of the rounding,
+ *                  (2^-8 + 2^-17 + 2.1 gamma_d) ||q|| ||x||) can still reach a
+ *                  lower bound of the k-th best are re-ranked exactly in FP64.
+ *   SCREEN_FP32:   the same screen with FP32 matrix-core products.
+ *   SCREEN_BF16X3: the same screen with a bfloat16 hi/lo split (three bf16
+ *                  products per pair; tighter bounds, three times the work).
+ *   AUTO:          SCREEN for large budgets (T >= n/128, T >= 2048, >= 64
+ *                  queries), else GATHER. */
 typedef enum {
     NRLSH_RERANK_AUTO = 0,
     NRLSH_RERANK_GATHER = 1,
     NRLSH_RERANK_SCREEN = 2,
-    NRLSH_RERANK_SCREEN_FP32 = 3
+    NRLSH_RERANK_SCREEN_FP32 = 3,
+    NRLSH_RERANK_SCREEN_BF16X3 = 4
 } nrlsh_rerank_mode;
 
 typedef struct nrlsh_query_opts {
@@ -317,7 +321,7 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
 
 /* Re-rank statistics of this thread's last nrlsh_query / nrlsh_query_ex. */
 typedef struct nrlsh_query_stats {
-    int32_t mode;          /* nrlsh_rerank_mode actually used (GATHER, SCREEN, SCREEN_FP32) */
+    int32_t mode;          /* nrlsh_rerank_mode actually used (GATHER or a SCREEN mode) */
     int32_t screen_passes; /* screen launches (more than one per batch = a list overflowed) */
     int64_t kept_total;    /* SCREEN: pairs kept for the exact re-rank, all queries */
     int64_t kept_max;      /* SCREEN: largest kept list of one query */

@@ -42,7 +42,7 @@ class QueryOpts(C.Structure):
                 ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32)]
 
 
-RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3}
+RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3, "screen_bf16x3": 4}
 
 
 class BuildStats(C.Structure):
@@ -477,7 +477,7 @@ def nrlsh_get_query_stats() -> dict:
     """Re-rank statistics of this thread's last query call."""
     st = QueryStats()
     _check(lib().nrlsh_get_query_stats(C.byref(st)))
-    return {"mode": {1: "gather", 2: "screen", 3: "screen_fp32"}.get(st.mode, "none"),
+    return {"mode": {1: "gather", 2: "screen", 3: "screen_fp32", 4: "screen_bf16x3"}.get(st.mode, "none"),
             "screen_passes": st.screen_passes, "kept_total": st.kept_total,
             "kept_max": st.kept_max, "theta_unset": st.theta_unset,
             "lp_kept_total": st.lp_kept_total, "lp_kept_max": st.lp_kept_max,

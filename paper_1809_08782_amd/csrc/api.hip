@@ -537,12 +537,12 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     }
 }
 
-bool screen_fits(const nrlsh_index *ix, bool bf16x3)
+bool screen_fits(const nrlsh_index *ix, int kind)
 {
     int lim = 0;
     if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, ix->device) != hipSuccess)
         return false;
-    return screen_lds_bytes(ix->dp, bf16x3) + 4096 <= (size_t)lim;
+    return screen_lds_bytes(ix->dp, kind) + 4096 <= (size_t)lim;
 }
 
 // Screen path: (1) theta_q from the largest FP32 lower bounds of small cells
@@ -568,11 +568,11 @@ std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo, int
 }
 
 void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
-                      bool bf16x3, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                      int kind, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
                       uint32_t *nonfinite_d)
 {
-    const uint16_t *Xh = bf16x3 ? ix->Xh.get() : nullptr;
-    const uint16_t *Xlo = bf16x3 ? ix->Xlo.get() : nullptr;
+    const uint16_t *Xh = kind != SCREEN_FP32 ? ix->Xh.get() : nullptr;
+    const uint16_t *Xlo = kind == SCREEN_BF16X3 ? ix->Xlo.get() : nullptr;
     const QueryShape sh = make_shape(ix, T, k);
     int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
     const int64_t tiles = B / 64;
@@ -676,12 +676,18 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
     bool screen = mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
+                  mode == NRLSH_RERANK_SCREEN_BF16X3 ||
                   (mode == NRLSH_RERANK_AUTO && Tq * 128 >= ix->n && nq >= 64 && Tq >= 2048);
-    const bool b3 = mode != NRLSH_RERANK_SCREEN_FP32;
-    if (screen && !screen_fits(ix, b3)) screen = false;
-    g_qstats.mode = screen ? (b3 ? NRLSH_RERANK_SCREEN : NRLSH_RERANK_SCREEN_FP32) : NRLSH_RERANK_GATHER;
+    const int kind = mode == NRLSH_RERANK_SCREEN_FP32     ? SCREEN_FP32
+                     : mode == NRLSH_RERANK_SCREEN_BF16X3 ? SCREEN_BF16X3
+                                                          : SCREEN_BF16;
+    if (screen && !screen_fits(ix, kind)) screen = false;
+    g_qstats.mode = !screen                ? NRLSH_RERANK_GATHER
+                    : kind == SCREEN_FP32   ? NRLSH_RERANK_SCREEN_FP32
+                    : kind == SCREEN_BF16X3 ? NRLSH_RERANK_SCREEN_BF16X3
+                                            : NRLSH_RERANK_SCREEN;
     if (screen)
-        run_query_screen(ix, Qd, nq, k, T, b3, ids_d, ips_d, s, tm, nonfinite_d);
+        run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d);
     else
         run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d,
                          bf16_rows);
@@ -766,7 +772,7 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     if (st != NRLSH_OK) return st;
     g_qstats = nrlsh_query_stats{};
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)) &&
-        (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN_FP32))
+        (opts->rerank_mode < NRLSH_RERANK_AUTO || opts->rerank_mode > NRLSH_RERANK_SCREEN_BF16X3))
         return fail(NRLSH_E_INVALID_ARG, "rerank_mode %d unknown", opts->rerank_mode);
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)) &&
         opts->rerank_storage != NRLSH_STORAGE_FP32 && opts->rerank_storage != NRLSH_STORAGE_BF16)

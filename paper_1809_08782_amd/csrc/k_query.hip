@@ -432,13 +432,13 @@ __global__ __launch_bounds__(256) void k_screen(
     const int32_t *__restrict__ ghthr, const int32_t *__restrict__ gtie,
     const int32_t *__restrict__ gpstar, const float *__restrict__ theta, float gam, int cap,
     int32_t *__restrict__ counts, int32_t *__restrict__ lists, float *__restrict__ cmax,
-    int ncol)
+    int ncol, int L)
 {
     extern __shared__ __align__(16) float qs[];  // 64 x qstride
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * W];
-    __shared__ int any_s;
+    __shared__ int any_s, all_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
     const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
@@ -466,7 +466,11 @@ __global__ __launch_bounds__(256) void k_screen(
         pstar_s[tid] = pstar;
         th_s[tid] = th;
         const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
-        if (tid == 0) any_s = b != 0ull;
+        const uint64_t a = __ballot(hthr >= L);  // every possible h passes
+        if (tid == 0) {
+            any_s = b != 0ull;
+            all_s = a == ~0ull;
+        }
     }
     if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
         for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
@@ -487,6 +491,7 @@ __global__ __launch_bounds__(256) void k_screen(
     __syncthreads();
 
     const int r16 = lane & 15, g = lane >> 4;
+    const bool all = all_s != 0;
     for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
         // this lane's two items (column blocks ib = 0, 1)
         int32_t pit[2];
@@ -540,10 +545,12 @@ __global__ __launch_bounds__(256) void k_screen(
                 float gmax = -INFINITY;  // MAXMODE: this lane's two items for query ql
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
-                    int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
-                    if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
-                    const bool probed =
-                        iv[ib] && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                    bool probed = iv[ib];
+                    if (!all) {
+                        int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
+                        if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
+                        probed = probed && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                    }
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-100f;
                     if (MAXMODE) {
@@ -566,14 +573,19 @@ __global__ __launch_bounds__(256) void k_screen(
     }
 }
 
-// bf16x3 variant of k_screen: items and queries are split x = hi + lo (+ a
-// residual of at most 2^-16 |x|) in bfloat16 and each inner product is
-// hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x32_bf16 (products of bfloat16
-// pairs are exact in FP32).  Per coordinate the dropped terms are at most
-// 3.1 * 2^-16 |q_t x_t|, and FP32 accumulation of the 3d products adds at
-// most gamma_{3d} (1.02 sum |q_t x_t|); the caller's g covers both with the
-// same factor-2 margin as the FP32 screen.  In MFMA j of a 32-coordinate
-// step, lane group g carries coordinates 32 kk + 8 g .. + 7 of both operands.
+// bfloat16 variants of k_screen on v_mfma_f32_16x16x32_bf16 (products of
+// bfloat16 pairs are exact in FP32).  In MFMA j of a 32-coordinate step, lane
+// group g carries coordinates 32 kk + 8 g .. + 7 of both operands.
+//   X3 = false: q and x rounded to bfloat16 (RNE), one product per pair.
+//       |q.x - q~.x~| <= (2^-8 + 2^-18) sum |q_t x_t|, and FP32 accumulation
+//       of the d exact products adds at most gamma_d (1.01 sum |q_t x_t|).
+//   X3 = true:  q and x split x = hi + lo (+ a residual of at most
+//       2^-16 |x|), each inner product hi.hi + hi.lo + lo.hi; the dropped
+//       terms are at most 3.1 * 2^-16 |q_t x_t| per coordinate, and FP32
+//       accumulation of the 3d products adds at most gamma_{3d} (1.02 sum).
+// The caller's g covers either with the same factor-2 margin as the FP32
+// screen.  When every query of the tile probes every level of the chunk's
+// sub-dataset (h <= hthr for all h, as at T = n), the probe test is skipped.
 __device__ __forceinline__ uint16_t q_bf16_rne(float f)
 {
     uint32_t u = __float_as_uint(f);
@@ -583,7 +595,7 @@ __device__ __forceinline__ uint16_t q_bf16_rne(float f)
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
-template <int W, bool MAXMODE>
+template <int W, bool MAXMODE, bool X3>
 __global__ __launch_bounds__(256) void k_screen3(
     const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int d, int dp,
     const uint32_t *__restrict__ codes_l, const double *__restrict__ key_l,
@@ -591,14 +603,14 @@ __global__ __launch_bounds__(256) void k_screen3(
     const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,
     const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,
     const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,
-    int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb)
+    int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L)
 {
-    extern __shared__ __align__(16) uint16_t qsh[];  // hi: 64 x qsb, then lo: 64 x qsb
+    extern __shared__ __align__(16) uint16_t qsh[];  // hi: 64 x qsb, then (X3) lo: 64 x qsb
     uint16_t *qsl = qsh + 64 * qsb;
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * W];
-    __shared__ int any_s;
+    __shared__ int any_s, all_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
     const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
@@ -625,7 +637,11 @@ __global__ __launch_bounds__(256) void k_screen3(
         pstar_s[tid] = pstar;
         th_s[tid] = th;
         const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
-        if (tid == 0) any_s = b != 0ull;
+        const uint64_t a = __ballot(hthr >= L);  // every possible h passes
+        if (tid == 0) {
+            any_s = b != 0ull;
+            all_s = a == ~0ull;
+        }
     }
     if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
         for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
@@ -641,7 +657,7 @@ __global__ __launch_bounds__(256) void k_screen3(
             const float f = (q < nq && c < d) ? Q[q * d + c] : 0.f;
             const uint16_t hi = q_bf16_rne(f);
             qsh[r * qsb + c] = hi;
-            qsl[r * qsb + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
+            if (X3) qsl[r * qsb + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
             s2 += (double)f * (double)f;
         }
 #pragma unroll
@@ -652,6 +668,7 @@ __global__ __launch_bounds__(256) void k_screen3(
 
     const int r16 = lane & 15, g = lane >> 4;
     const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    const bool all = all_s != 0;
     for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
         int32_t pit[2];
         uint32_t cw[2][W];
@@ -680,14 +697,14 @@ __global__ __launch_bounds__(256) void k_screen3(
                 const bool ok = iv[ib] && kin;
                 const int64_t o = (int64_t)pit[ib] * dp + kc;
                 bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
-                bl[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
+                bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
             }
             u16x8 ah[4], al[4];
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb) {
                 const int o = (16 * qb + r16) * qsb + kc;
                 ah[qb] = kin ? *reinterpret_cast<const u16x8 *>(&qsh[o]) : z8;
-                al[qb] = kin ? *reinterpret_cast<const u16x8 *>(&qsl[o]) : z8;
+                al[qb] = (X3 && kin) ? *reinterpret_cast<const u16x8 *>(&qsl[o]) : z8;
             }
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb)
@@ -695,10 +712,12 @@ __global__ __launch_bounds__(256) void k_screen3(
                 for (int ib = 0; ib < 2; ++ib) {
                     acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         as_bf16x8(ah[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
-                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        as_bf16x8(ah[qb]), as_bf16x8(bl[ib]), acc[qb][ib], 0, 0, 0);
-                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        as_bf16x8(al[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                    if (X3) {
+                        acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            as_bf16x8(ah[qb]), as_bf16x8(bl[ib]), acc[qb][ib], 0, 0, 0);
+                        acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                            as_bf16x8(al[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                    }
                 }
         }
 #pragma unroll
@@ -711,10 +730,12 @@ __global__ __launch_bounds__(256) void k_screen3(
                 float gmax = -INFINITY;  // MAXMODE: this lane's two items for query ql
 #pragma unroll
                 for (int ib = 0; ib < 2; ++ib) {
-                    int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
-                    if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
-                    const bool probed =
-                        iv[ib] && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                    bool probed = iv[ib];
+                    if (!all) {
+                        int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
+                        if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
+                        probed = probed && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                    }
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-90f;
                     if (MAXMODE) {
@@ -832,10 +853,31 @@ int screen_cell_groups() { return SC_GROUPS; }
 // 16 rows hit 16 distinct 4-bank groups)
 static int screen_qsb(int dp) { return dp + (((dp / 8) % 2 == 0) ? 8 : 16); }
 
-size_t screen_lds_bytes(int dp, bool bf16x3)
+size_t screen_lds_bytes(int dp, int kind)
 {
-    return bf16x3 ? (size_t)2 * 64 * screen_qsb(dp) * sizeof(uint16_t)
-                  : (size_t)64 * (dp + 4) * sizeof(float);
+    if (kind == SCREEN_BF16X3) return (size_t)2 * 64 * screen_qsb(dp) * sizeof(uint16_t);
+    if (kind == SCREEN_BF16) return (size_t)64 * screen_qsb(dp) * sizeof(uint16_t);
+    return (size_t)64 * (dp + 4) * sizeof(float);
+}
+
+template <int W, bool MAXMODE, bool X3>
+static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, const double *key_l,
+                                     const uint32_t *codes_l, const float *Q, int64_t nq,
+                                     const QueryShape &sh, const int32_t *chunks, int nchunks,
+                                     const uint32_t *qcodes, const int32_t *ghthr,
+                                     const int32_t *gtie, const int32_t *gpstar,
+                                     const float *theta, float gam, int cap, int32_t *counts,
+                                     int32_t *lists, float *cmax, int ncol, hipStream_t s)
+{
+    const size_t lds = screen_lds_bytes(sh.dp, X3 ? SCREEN_BF16X3 : SCREEN_BF16);
+    hipError_t e = hipFuncSetAttribute((const void *)k_screen3<W, MAXMODE, X3>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
+                       codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta,
+                       gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+    return hipGetLastError();
 }
 
 template <bool MAXMODE>
@@ -847,29 +889,35 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
                                   int cap, int32_t *counts, int32_t *lists, float *cmax,
                                   hipStream_t s)
 {
-    const bool b3 = Xh != nullptr && Xlo != nullptr;
-    const size_t lds = screen_lds_bytes(sh.dp, b3);
-    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
     const int ncol = MAXMODE ? nchunks * SC_GROUPS : 0;
-    if (b3) {
+    if (Xh && Xlo) {
         // per coordinate 3.1 * 2^-16 |q x| dropped by the split, plus FP32
         // accumulation of 3d exact products: 2 * 1.02 * gamma_{3d}
         const double u3 = 3.0 * sh.d * 0x1p-24;
         const float gam = (float)((3.2 * 0x1p-16 + 2.1 * u3 / (1.0 - u3)) * (1.0 + 0x1p-16));
-        const int qsb = screen_qsb(sh.dp);
-        const void *fn = sh.W == 1 ? (const void *)k_screen3<1, MAXMODE> : (const void *)k_screen3<2, MAXMODE>;
-        hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        if (sh.W == 1)
-            hipLaunchKernelGGL((k_screen3<1, MAXMODE>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
-                               codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar,
-                               theta, gam, cap, counts, lists, cmax, ncol, qsb);
-        else
-            hipLaunchKernelGGL((k_screen3<2, MAXMODE>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
-                               codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar,
-                               theta, gam, cap, counts, lists, cmax, ncol, qsb);
-        return hipGetLastError();
+        return sh.W == 1
+                   ? launch_screen_bf16<1, MAXMODE, true>(Xh, Xlo, key_l, codes_l, Q, nq, sh, chunks,
+                                                          nchunks, qcodes, ghthr, gtie, gpstar, theta,
+                                                          gam, cap, counts, lists, cmax, ncol, s)
+                   : launch_screen_bf16<2, MAXMODE, true>(Xh, Xlo, key_l, codes_l, Q, nq, sh, chunks,
+                                                          nchunks, qcodes, ghthr, gtie, gpstar, theta,
+                                                          gam, cap, counts, lists, cmax, ncol, s);
     }
+    if (Xh) {
+        // rounding of both operands to bfloat16: (2^-8 + 2^-18) |q x| per
+        // coordinate, plus FP32 accumulation of d exact products: 2 * 1.01 * gamma_d
+        const double ud = sh.d * 0x1p-24;
+        const float gam = (float)((0x1p-8 + 0x1p-17 + 2.1 * ud / (1.0 - ud)) * (1.0 + 0x1p-16));
+        return sh.W == 1
+                   ? launch_screen_bf16<1, MAXMODE, false>(Xh, nullptr, key_l, codes_l, Q, nq, sh,
+                                                           chunks, nchunks, qcodes, ghthr, gtie, gpstar,
+                                                           theta, gam, cap, counts, lists, cmax, ncol, s)
+                   : launch_screen_bf16<2, MAXMODE, false>(Xh, nullptr, key_l, codes_l, Q, nq, sh,
+                                                           chunks, nchunks, qcodes, ghthr, gtie, gpstar,
+                                                           theta, gam, cap, counts, lists, cmax, ncol, s);
+    }
+    const size_t lds = screen_lds_bytes(sh.dp, SCREEN_FP32);
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
     const double ud = (double)sh.d * 0x1p-24;
     const float gam = (float)(2.0 * ud / (1.0 - ud) * (1.0 + 0x1p-16));
     const void *fn = sh.W == 1 ? (const void *)k_screen<1, MAXMODE> : (const void *)k_screen<2, MAXMODE>;
@@ -878,11 +926,11 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
     if (sh.W == 1)
         hipLaunchKernelGGL((k_screen<1, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, ncol);
+                           counts, lists, cmax, ncol, sh.L);
     else
         hipLaunchKernelGGL((k_screen<2, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, ncol);
+                           counts, lists, cmax, ncol, sh.L);
     return hipGetLastError();
 }
 

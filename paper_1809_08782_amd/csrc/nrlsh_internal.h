@@ -138,12 +138,14 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 //   launch_screen: appends every probed pair whose FP32 upper bound reaches
 //     theta[q] to lists (nq x cap) and counts all of them (counts zeroed by
 //     the caller; counts[q] > cap means the list overflowed).
-// Xh / Xlo != NULL selects the bf16x3 matrix-core screen (x = hi + lo split,
-// products hi.hi + hi.lo + lo.hi), otherwise the FP32 matrix-core screen.
+// Xh and Xlo != NULL select the bf16x3 matrix-core screen (x = hi + lo
+// split, products hi.hi + hi.lo + lo.hi), Xh alone the single-product bf16
+// screen (q and x rounded to bfloat16), neither the FP32 matrix-core screen.
+enum ScreenKind { SCREEN_FP32 = 0, SCREEN_BF16 = 1, SCREEN_BF16X3 = 2 };
 int screen_chunk_items();
 int screen_cell_items();
 int screen_cell_groups();  // lower-bound maxima kept per cell and query
-size_t screen_lds_bytes(int dp, bool bf16x3);
+size_t screen_lds_bytes(int dp, int kind);
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                              const double *key_l, const uint32_t *codes_l,
                              const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,

@@ -75,7 +75,8 @@ SCREEN_CASES = [
 
 @pytest.mark.parametrize("case", SCREEN_CASES, ids=lambda c: "n%d_d%d_m%d_L%d_T%d" % (c[0], c[1], c[2], c[3], c[6]))
 def test_parity_screen_rerank(case):
-    """The query-tiled FP32 screen + FP64 re-rank gives the oracle's top-k."""
+    """Every query-tiled matrix-core screen (bf16, FP32, bf16x3) followed by the
+    FP64 re-rank gives the oracle's top-k; T = n takes the all-probed path."""
     n, d, m, L, nq, k, T = case
     say(f"case screen n={n} d={d} m={m} L={L} nq={nq} k={k} T={T}")
     X = make_items("lognormal", n, d, seed=n + 3, sigma=0.9)
@@ -83,7 +84,7 @@ def test_parity_screen_rerank(case):
     oix = orc.OracleIndex(X, m, L, seed=17, threads=8)
     with nr.nrlsh_build(X, m, L, 17) as gix:
         oids, oips = oix.query(Q, k, T, threads=8)
-        for mode in ("screen", "screen_fp32", "gather"):
+        for mode in ("screen", "screen_fp32", "screen_bf16x3", "gather"):
             ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank=mode)
             st = nr.nrlsh_get_query_stats()
             assert st["mode"] == mode, st
@@ -104,7 +105,7 @@ def test_screen_with_duplicates_and_zero_rows():
     with nr.nrlsh_build(X, 10, 32, 5) as gix:
         for T in (3000, n):
             oids, oips = oix.query(Q, 10, T, threads=8)
-            for mode in ("screen", "screen_fp32"):
+            for mode in ("screen", "screen_fp32", "screen_bf16x3"):
                 ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank=mode)
                 assert np.array_equal(ids, oids), f"T={T} {mode}"
                 assert np.array_equal(ips, oips.astype(np.float32)), f"T={T} {mode}"
