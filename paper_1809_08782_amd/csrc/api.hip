@@ -280,33 +280,51 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         tau_h[r] = std::nextafter((float)tau, INFINITY);
     }
 
-    ix->Xl = DBuf<float>((size_t)n * dp, s);
-    ix->Xh = DBuf<uint16_t>((size_t)n * dp, s);
-    ix->Xlo = DBuf<uint16_t>((size_t)n * dp, s);
-    ix->A = DBuf<float>(ix->A_h.size(), s);
-    ix->At = DBuf<float>(At_h.size(), s);
-    ix->key = DBuf<double>(n, s);
-    ix->key_l = DBuf<double>(n, s);
-    ix->keymax = DBuf<double>(m, s);
-    ix->U = DBuf<double>(m, s);
-    ix->sid = DBuf<int32_t>(n, s);
-    ix->sid_l = DBuf<int32_t>(n, s);
-    ix->perm = DBuf<int32_t>(n, s);
-    ix->off = DBuf<int32_t>(m + 1, s);
-    ix->R = DBuf<int32_t>((size_t)m * (L + 1), s);
-    ix->inv = DBuf<int32_t>((size_t)m * (L + 1), s);
-    ix->codes_l = DBuf<uint32_t>((size_t)n * W, s);
+    Block &B = ix->mem;
+    const size_t oXl = B.reserve<float>((size_t)n * dp), oXh = B.reserve<uint16_t>((size_t)n * dp),
+                 oXlo = B.reserve<uint16_t>((size_t)n * dp), oA = B.reserve<float>(ix->A_h.size()),
+                 oAt = B.reserve<float>(At_h.size()), okey = B.reserve<double>(n),
+                 okeyl = B.reserve<double>(n), okm = B.reserve<double>(m), oU = B.reserve<double>(m),
+                 osid = B.reserve<int32_t>(n), osidl = B.reserve<int32_t>(n),
+                 operm = B.reserve<int32_t>(n), ooff = B.reserve<int32_t>(m + 1),
+                 oR = B.reserve<int32_t>((size_t)m * (L + 1)),
+                 oinv = B.reserve<int32_t>((size_t)m * (L + 1)),
+                 ocodes = B.reserve<uint32_t>((size_t)n * W);
+    B.allocate(s);
+    ix->Xl = B.view<float>(oXl);
+    ix->Xh = B.view<uint16_t>(oXh);
+    ix->Xlo = B.view<uint16_t>(oXlo);
+    ix->A = B.view<float>(oA);
+    ix->At = B.view<float>(oAt);
+    ix->key = B.view<double>(okey);
+    ix->key_l = B.view<double>(okeyl);
+    ix->keymax = B.view<double>(okm);
+    ix->U = B.view<double>(oU);
+    ix->sid = B.view<int32_t>(osid);
+    ix->sid_l = B.view<int32_t>(osidl);
+    ix->perm = B.view<int32_t>(operm);
+    ix->off = B.view<int32_t>(ooff);
+    ix->R = B.view<int32_t>(oR);
+    ix->inv = B.view<int32_t>(oinv);
+    ix->codes_l = B.view<uint32_t>(ocodes);
 
-    DBuf<float> tau(L, s);
-    DBuf<uint64_t> ka(n, s), kb(n, s);
-    DBuf<int32_t> va(n, s), vb(n, s);
-    DBuf<uint8_t> rtmp(radix_sort_tmp_bytes(n), s);
-    DBuf<FixEntry> fix(n, s);
-    DBuf<BuildCounters> ctr(1, s);
-    DBuf<float> staging;
+    // build-time scratch, one block
+    Block T;
+    const size_t otau = T.reserve<float>(L), oka = T.reserve<uint64_t>(n), okb = T.reserve<uint64_t>(n),
+                 ova = T.reserve<int32_t>(n), ovb = T.reserve<int32_t>(n),
+                 ortmp = T.reserve<uint8_t>(radix_sort_tmp_bytes(n)), ofix = T.reserve<FixEntry>(n),
+                 octr = T.reserve<BuildCounters>(1),
+                 ostg = T.reserve<float>(on_device ? 1 : (size_t)n * d);
+    T.allocate(s);
+    DBuf<float> tau = T.view<float>(otau);
+    DBuf<uint64_t> ka = T.view<uint64_t>(oka), kb = T.view<uint64_t>(okb);
+    DBuf<int32_t> va = T.view<int32_t>(ova), vb = T.view<int32_t>(ovb);
+    DBuf<uint8_t> rtmp = T.view<uint8_t>(ortmp);
+    DBuf<FixEntry> fix = T.view<FixEntry>(ofix);
+    DBuf<BuildCounters> ctr = T.view<BuildCounters>(octr);
+    DBuf<float> staging = T.view<float>(ostg);
     const float *X = items;
     if (!on_device) {
-        staging = DBuf<float>((size_t)n * d, s);
         HIPX(hipMemcpyAsync(staging.get(), items, (size_t)n * d * sizeof(float),
                             hipMemcpyHostToDevice, s));
         X = staging.get();
@@ -396,13 +414,9 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
     HIPX(hipStreamSynchronize(s));
     // long-lived buffers are released on the library stream by nrlsh_free
-    for (auto *b : {&ix->Xl, &ix->A, &ix->At}) b->s = ix->home;
-    for (auto *b : {&ix->Xh, &ix->Xlo}) b->s = ix->home;
+    ix->mem.mem.s = ix->home;
     ix->Xf8.s = ix->home;
     ix->xscale.s = ix->home;
-    for (auto *b : {&ix->key, &ix->key_l, &ix->keymax, &ix->U}) b->s = ix->home;
-    for (auto *b : {&ix->sid, &ix->sid_l, &ix->perm, &ix->off, &ix->R, &ix->inv}) b->s = ix->home;
-    ix->codes_l.s = ix->home;
     ix->stats.lowp_items = hc.lowp_items;
     ix->stats.lowp_bits = (int64_t)hc.lowp_bits;
     ix->stats.lowp_changed = (int64_t)hc.lowp_changed;
@@ -466,18 +480,31 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
-    DBuf<uint32_t> qcodes(qcodes_out_d ? 1 : (size_t)B * sh.W, s);
-    DBuf<uint32_t> ghist((size_t)tiles * sh.m * L1 * 64, s);
-    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s);
-    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
-    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
-    DBuf<int32_t> cand(cand_out_d ? 1 : (size_t)B * sh.Tq, s);
     const int nsplit = rerank_splits(B, sh.Tq);
-    DBuf<double> part_v(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
-    DBuf<int32_t> part_i(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1, s);
     const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
-    DBuf<int32_t> lcount(bf16_rows ? (size_t)B : 1, s);
-    DBuf<int32_t> lists(bf16_rows ? (size_t)B * lcap : 1, s);
+    const int lsplit = rerank_splits(B, lcap);
+    Block blk;
+    const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.W),
+                 o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
+                 o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
+                 o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
+                 o_ti = blk.reserve<int32_t>((size_t)tiles * 4 * 64),
+                 o_ca = blk.reserve<int32_t>(cand_out_d ? 1 : (size_t)B * sh.Tq),
+                 o_pv = blk.reserve<double>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
+                 o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
+                 o_lc = blk.reserve<int32_t>(bf16_rows ? (size_t)B : 1),
+                 o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
+                 o_lv = blk.reserve<double>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
+                 o_lp = blk.reserve<int32_t>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1);
+    blk.allocate(s);
+    DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
+    DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
+                  gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
+    DBuf<double> part_v = blk.view<double>(o_pv);
+    DBuf<int32_t> part_i = blk.view<int32_t>(o_pi);
+    DBuf<int32_t> lcount = blk.view<int32_t>(o_lc), lists = blk.view<int32_t>(o_li);
+    DBuf<double> lpart_v = blk.view<double>(o_lv);
+    DBuf<int32_t> lpart_i = blk.view<int32_t>(o_lp);
     std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
@@ -518,12 +545,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, mx);
                 QueryShape shl = sh;
                 shl.Tq = lcap;  // list stride; lengths come from lcount
-                const int ns = rerank_splits(nb, lcap);
-                DBuf<double> pv(ns > 1 ? (size_t)nb * ns * k : 1, s);
-                DBuf<int32_t> pi(ns > 1 ? (size_t)nb * ns * k : 1, s);
+                const int ns = std::min(rerank_splits(nb, lcap), lsplit);
                 tm.begin("rerank_exact");
                 HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(),
-                                   lcount.get(), ns, pv.get(), pi.get(), ids_d + b0 * k,
+                                   lcount.get(), ns, lpart_v.get(), lpart_i.get(), ids_d + b0 * k,
                                    ips_d + b0 * k, s));
                 tm.end();
                 continue;
@@ -590,20 +615,32 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, 16);
     std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
-    DBuf<int32_t> cells(ce.size(), s), chunks(ch.size(), s);
+    Block blk;
+    const size_t o_ce = blk.reserve<int32_t>(ce.size()), o_ch = blk.reserve<int32_t>(ch.size()),
+                 o_qc = blk.reserve<uint32_t>((size_t)B * sh.W),
+                 o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
+                 o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
+                 o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
+                 o_ti = blk.reserve<int32_t>((size_t)tiles * 4 * 64),
+                 o_ps = blk.reserve<int32_t>((size_t)B),
+                 o_cm = blk.reserve<float>((size_t)B * ncells * screen_cell_groups()),
+                 o_qh = blk.reserve<uint16_t>(kind != SCREEN_FP32 ? (size_t)B * sh.dp : 1),
+                 o_ql = blk.reserve<uint16_t>(kind == SCREEN_BF16X3 ? (size_t)B * sh.dp : 1),
+                 o_qn = blk.reserve<float>(kind != SCREEN_FP32 ? (size_t)B : 1),
+                 o_ta = blk.reserve<float>((size_t)B), o_co = blk.reserve<int32_t>((size_t)B),
+                 o_li = blk.reserve<int32_t>((size_t)B * cap);
+    blk.allocate(s);
+    DBuf<int32_t> cells = blk.view<int32_t>(o_ce), chunks = blk.view<int32_t>(o_ch);
     HIPX(hipMemcpyAsync(cells.get(), ce.data(), ce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
-    DBuf<uint32_t> qcodes((size_t)B * sh.W, s);
-    DBuf<uint32_t> ghist((size_t)tiles * sh.m * L1 * 64, s);
-    DBuf<int32_t> gbase((size_t)tiles * (sh.m + 1) * 64, s);
-    DBuf<int32_t> ghthr((size_t)tiles * sh.m * 64, s);
-    DBuf<int32_t> gtie((size_t)tiles * 4 * 64, s);
-    DBuf<int32_t> gpstar((size_t)B, s);
-    DBuf<float> cmax((size_t)B * ncells * screen_cell_groups(), s);
-    DBuf<float> theta((size_t)B, s);
-    DBuf<int32_t> counts((size_t)B, s);
-    DBuf<int32_t> lists((size_t)B * cap, s);
+    DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
+    DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
+                  gtie = blk.view<int32_t>(o_ti), gpstar = blk.view<int32_t>(o_ps);
+    DBuf<float> cmax = blk.view<float>(o_cm);
+    DBuf<uint16_t> qh = blk.view<uint16_t>(o_qh), ql = blk.view<uint16_t>(o_ql);
+    DBuf<float> qn = blk.view<float>(o_qn), theta = blk.view<float>(o_ta);
+    DBuf<int32_t> counts = blk.view<int32_t>(o_co), lists = blk.view<int32_t>(o_li);
     std::vector<int32_t> hcounts((size_t)B);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
@@ -611,6 +648,14 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         tm.begin("qhash");
         HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qcodes.get(), nonfinite_d, s));
         tm.end();
+        ScreenQueries sq{Qb, nullptr, nullptr, nullptr};
+        if (kind != SCREEN_FP32) {
+            sq.Qh = qh.get();
+            sq.Ql = kind == SCREEN_BF16X3 ? ql.get() : nullptr;
+            sq.qn = qn.get();
+            HIPX(launch_query_bf16(Qb, nb, sh.d, sh.dp, qh.get(), kind == SCREEN_BF16X3 ? ql.get() : nullptr,
+                                   qn.get(), s));
+        }
         tm.begin("scan_hist");
         HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh, ghist.get(), s));
         tm.end();
@@ -623,26 +668,42 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                gpstar.get(), s));
         tm.end();
         tm.begin("screen_max");
-        HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+        HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), sq, nb, sh,
                                cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
-        {
-            std::vector<float> th((size_t)nb);
-            HIPX(hipMemcpyAsync(th.data(), theta.get(), (size_t)nb * sizeof(float), hipMemcpyDeviceToHost, s));
-            HIPX(hipStreamSynchronize(s));
-            for (float t : th) g_qstats.theta_unset += std::isinf(t) && t < 0 ? 1 : 0;
-        }
-        for (;;) {
+        // screen, then the exact re-rank of the kept lists right behind it; the
+        // host checks afterwards whether a list overflowed (then the batch is
+        // screened again with longer lists, which overwrites the results)
+        std::vector<float> th((size_t)nb);
+        for (bool first = true;; first = false) {
             HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("screen");
-            HIPX(launch_screen(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), Qb, nb, sh,
+            HIPX(launch_screen(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), sq, nb, sh,
                                chunks.get(), nchunks, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), theta.get(), (int)cap, counts.get(), lists.get(), s));
             tm.end();
+            QueryShape shl = sh;
+            shl.Tq = cap;  // list stride; lengths come from counts
+            const int nsplit = rerank_splits(nb, cap);
+            Block pb;
+            const size_t o_pv = pb.reserve<double>(nsplit > 1 ? (size_t)nb * nsplit * k : 1),
+                         o_pi = pb.reserve<int32_t>(nsplit > 1 ? (size_t)nb * nsplit * k : 1);
+            pb.allocate(s);
+            DBuf<double> pv = pb.view<double>(o_pv);
+            DBuf<int32_t> pi = pb.view<int32_t>(o_pi);
+            tm.begin("rerank_exact");
+            HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(), counts.get(),
+                               nsplit, pv.get(), pi.get(), ids_d + b0 * k, ips_d + b0 * k, s));
+            tm.end();
+            if (first)
+                HIPX(hipMemcpyAsync(th.data(), theta.get(), (size_t)nb * sizeof(float),
+                                    hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(hcounts.data(), counts.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
+            if (first)
+                for (float t : th) g_qstats.theta_unset += std::isinf(t) && t < 0 ? 1 : 0;
             int64_t mx = 0, tot = 0;
             for (int64_t i = 0; i < nb; ++i) {
                 mx = std::max<int64_t>(mx, hcounts[i]);
@@ -658,15 +719,6 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             cap = std::min<int64_t>(sh.Tq, std::max<int64_t>(mx, 2 * cap));
             lists = DBuf<int32_t>((size_t)B * cap, s);
         }
-        QueryShape shl = sh;
-        shl.Tq = cap;  // list stride; lengths come from counts
-        const int nsplit = rerank_splits(nb, cap);
-        DBuf<double> pv(nsplit > 1 ? (size_t)nb * nsplit * k : 1, s);
-        DBuf<int32_t> pi(nsplit > 1 ? (size_t)nb * nsplit * k : 1, s);
-        tm.begin("rerank_exact");
-        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(), counts.get(),
-                           nsplit, pv.get(), pi.get(), ids_d + b0 * k, ips_d + b0 * k, s));
-        tm.end();
     }
 }
 
@@ -783,7 +835,13 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         HIPX(hipSetDevice(ix->device));
         hipStream_t s = pick_stream(opts ? opts->stream : nullptr, ix->device);
         Timer tm(s);
-        DBuf<uint32_t> flag(1, s);
+        Block blk;
+        const size_t o_fl = blk.reserve<uint32_t>(1),
+                     o_q = blk.reserve<float>(on_device ? 1 : (size_t)nq * ix->d),
+                     o_i = blk.reserve<int64_t>(on_device ? 1 : (size_t)nq * k),
+                     o_p = blk.reserve<float>(on_device ? 1 : (size_t)nq * k);
+        blk.allocate(s);
+        DBuf<uint32_t> flag = blk.view<uint32_t>(o_fl);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
         int mode = NRLSH_RERANK_AUTO;
         if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)))
@@ -795,9 +853,9 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
             run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, out_ids, out_ips, s, tm,
                       flag.get());
         } else {
-            DBuf<float> Qd((size_t)nq * ix->d, s);
-            DBuf<int64_t> ids((size_t)nq * k, s);
-            DBuf<float> ips((size_t)nq * k, s);
+            DBuf<float> Qd = blk.view<float>(o_q);
+            DBuf<int64_t> ids = blk.view<int64_t>(o_i);
+            DBuf<float> ips = blk.view<float>(o_p);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
             run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, ids.get(), ips.get(), s, tm,

@@ -106,11 +106,13 @@ hipStream_t library_stream(int dev);
 void prepare_pool(int dev);
 int current_device();
 
-// Stream-ordered device buffer; freed on the stream it was allocated on.
+// Stream-ordered device buffer; freed on the stream it was allocated on.  A
+// view (DBuf::view) points into memory owned elsewhere and frees nothing.
 template <typename T>
 struct DBuf {
     T *p = nullptr;
     hipStream_t s = nullptr;
+    bool own = true;
     DBuf() = default;
     DBuf(size_t count, hipStream_t st) : s(st)
     {
@@ -120,24 +122,57 @@ struct DBuf {
         if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
         p = static_cast<T *>(v);
     }
+    static DBuf view(T *ptr)
+    {
+        DBuf b;
+        b.p = ptr;
+        b.own = false;
+        return b;
+    }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s) { o.p = nullptr; }
+    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s), own(o.own) { o.p = nullptr; }
     DBuf &operator=(DBuf &&o) noexcept
     {
         reset();
         p = o.p;
         s = o.s;
+        own = o.own;
         o.p = nullptr;
         return *this;
     }
     ~DBuf() { reset(); }
     void reset()
     {
-        if (p) (void)hipFreeAsync(p, s);
+        if (p && own) (void)hipFreeAsync(p, s);
         p = nullptr;
     }
     T *get() const { return p; }
+};
+
+// Several buffers carved from one stream-ordered allocation: each
+// stream-ordered allocation and release costs tens of microseconds of host
+// time, so a call reserves all of its buffers, allocates once and takes
+// views (valid while the Block lives).
+class Block {
+  public:
+    template <typename T>
+    size_t reserve(size_t count)
+    {
+        const size_t off = (size_ + 255) / 256 * 256;
+        size_ = off + (count ? count : 1) * sizeof(T);
+        return off;
+    }
+    void allocate(hipStream_t s) { mem = DBuf<uint8_t>(size_ ? size_ : 1, s); }
+    template <typename T>
+    DBuf<T> view(size_t off) const
+    {
+        return DBuf<T>::view(reinterpret_cast<T *>(mem.get() + off));
+    }
+    DBuf<uint8_t> mem;
+
+  private:
+    size_t size_ = 0;
 };
 
 }  // namespace host
@@ -158,6 +193,7 @@ struct nrlsh_index {
     std::vector<int32_t> R_h;
     nrlsh_build_stats stats{};
     hipStream_t home = nullptr;  // library stream that releases the device buffers
+    nrlsh::host::Block mem;      // the long-lived buffers below are views into it
     nrlsh::host::DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
     nrlsh::host::DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
     nrlsh::host::DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)

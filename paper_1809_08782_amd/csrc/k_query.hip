@@ -420,7 +420,7 @@ __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__
 //                    and appends its stored position to the query's list
 //                    (capacity cap; counts may exceed cap, which the host
 //                    detects).  The exact top-k of the probed set lies in it.
-constexpr int SC_CHUNK = 2048;
+constexpr int SC_CHUNK = 4096;
 constexpr int SC_CELL = 1024;
 constexpr int SC_GROUPS = SC_CELL / 32;  // 32-item groups per cell (MAXMODE outputs)
 
@@ -595,11 +595,42 @@ __device__ __forceinline__ uint16_t q_bf16_rne(float f)
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// bfloat16 image of a query batch for the screen: hi = RNE(q), lo =
+// RNE(q - hi) (when Ql != NULL), rows zero-padded to dp columns, and qn = an
+// upper bound on ||q|| (exact squares, FP64 sum, rounded up).  One wave per
+// query.
+__global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q, int64_t nq, int d,
+                                                    int dp, uint16_t *__restrict__ Qh,
+                                                    uint16_t *__restrict__ Ql,
+                                                    float *__restrict__ qn)
+{
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
+    if (q >= nq) return;
+    double s2 = 0.0;
+    for (int c = lane; c < dp; c += 64) {
+        const float f = c < d ? Q[q * d + c] : 0.f;
+        const uint16_t hi = q_bf16_rne(f);
+        Qh[q * dp + c] = hi;
+        if (Ql) Ql[q * dp + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
+        s2 += (double)f * (double)f;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
+    if (lane == 0) qn[q] = (float)__builtin_sqrt(s2) * (1.0f + 0x1p-18f);
+}
+
+// A block holds 64 queries (their bfloat16 rows staged in LDS) and one chunk
+// of stored items of a single sub-dataset; each wave takes 64 items at a time
+// (4 column blocks of 16) against the 64 queries (4 row blocks of 16), and
+// fetches the item rows of the next 32-coordinate step while the matrix cores
+// work on the current one.
 template <int W, bool MAXMODE, bool X3>
 __global__ __launch_bounds__(256) void k_screen3(
-    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int d, int dp,
+    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int dp,
     const uint32_t *__restrict__ codes_l, const double *__restrict__ key_l,
-    const float *__restrict__ Q, int64_t nq, const int32_t *__restrict__ chunks, int m,
+    const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
+    const float *__restrict__ qnorm, int64_t nq, const int32_t *__restrict__ chunks, int m,
     const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,
     const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,
     const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,
@@ -620,7 +651,7 @@ __global__ __launch_bounds__(256) void k_screen3(
     if (tid < 64) {
         const int64_t q = q0 + tid;
         int hthr = -1, htie = -1, pstar = -1;
-        float th = -INFINITY;
+        float th = -INFINITY, qn = 0.f;
         if (q < nq) {
             hthr = ghthr[((int64_t)tile * m + j) * 64 + tid];
             const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
@@ -629,6 +660,7 @@ __global__ __launch_bounds__(256) void k_screen3(
                 pstar = gpstar[q];
             }
             if (!MAXMODE) th = theta[q];
+            qn = qnorm[q];
 #pragma unroll
             for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
         }
@@ -636,6 +668,7 @@ __global__ __launch_bounds__(256) void k_screen3(
         htie_s[tid] = htie;
         pstar_s[tid] = pstar;
         th_s[tid] = th;
+        qn_s[tid] = qn;
         const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
         const uint64_t a = __ballot(hthr >= L);  // every possible h passes
         if (tid == 0) {
@@ -648,57 +681,69 @@ __global__ __launch_bounds__(256) void k_screen3(
     __syncthreads();
     if (!any_s) return;  // no query of this tile probes this chunk
 
-    // stage the query tile as hi / lo bfloat16, zero-padded to dp columns;
-    // ||q|| (an upper bound: exact squares, FP64 sum, rounded up) per row
-    for (int r = wave; r < 64; r += 4) {
-        const int64_t q = q0 + r;
-        double s2 = 0.0;
-        for (int c = lane; c < dp; c += 64) {
-            const float f = (q < nq && c < d) ? Q[q * d + c] : 0.f;
-            const uint16_t hi = q_bf16_rne(f);
-            qsh[r * qsb + c] = hi;
-            if (X3) qsl[r * qsb + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
-            s2 += (double)f * (double)f;
-        }
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
-        if (lane == 0) qn_s[r] = (float)__builtin_sqrt(s2) * (1.0f + 0x1p-18f);
+    // stage the query tile (rows beyond nq are zero)
+    const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    const int v8 = dp / 8;
+    for (int idx = tid; idx < 64 * v8; idx += 256) {
+        const int r = idx / v8, c = 8 * (idx - r * v8);
+        const bool ok = q0 + r < nq;
+        *reinterpret_cast<u16x8 *>(&qsh[r * qsb + c]) =
+            ok ? *reinterpret_cast<const u16x8 *>(Qh + (q0 + r) * dp + c) : z8;
+        if (X3)
+            *reinterpret_cast<u16x8 *>(&qsl[r * qsb + c]) =
+                ok ? *reinterpret_cast<const u16x8 *>(Ql + (q0 + r) * dp + c) : z8;
     }
     __syncthreads();
 
     const int r16 = lane & 15, g = lane >> 4;
-    const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
     const bool all = all_s != 0;
-    for (int p0 = pbeg + wave * 32; p0 < pend; p0 += 128) {
-        int32_t pit[2];
-        uint32_t cw[2][W];
-        float xn[2];
-        bool iv[2];
+    for (int p0 = pbeg + wave * 64; p0 < pend; p0 += 256) {
+        int32_t pit[4];
+        uint32_t cw[4][W];
+        float xn[4];
+        bool iv[4];
 #pragma unroll
-        for (int ib = 0; ib < 2; ++ib) {
+        for (int ib = 0; ib < 4; ++ib) {
             pit[ib] = p0 + 16 * ib + r16;
             iv[ib] = pit[ib] < pend;
             const int64_t pp = iv[ib] ? pit[ib] : pbeg;
 #pragma unroll
-            for (int w = 0; w < W; ++w) cw[ib][w] = codes_l[pp * W + w];
+            for (int w = 0; w < W; ++w) cw[ib][w] = all ? 0u : codes_l[pp * W + w];
             xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
         }
-        floatx4 acc[4][2];
+        floatx4 acc[4][4];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int ib = 0; ib < 2; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int ib = 0; ib < 4; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+        // item operands of step kk: 8 coordinates of one row per lane
+        u16x8 bh[4], bl[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const bool ok = iv[ib] && 8 * g < dp;
+            const int64_t o = (int64_t)pit[ib] * dp + 8 * g;
+            bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
+            bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
+        }
         for (int kk = 0; kk < dp; kk += 32) {
+            u16x8 ch[4], cl[4];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) {
+                ch[ib] = bh[ib];
+                cl[ib] = bl[ib];
+            }
+            const int kn = kk + 32 + 8 * g;  // prefetch the next step
+            if (kk + 32 < dp) {
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    const bool ok = iv[ib] && kn < dp;
+                    const int64_t o = (int64_t)pit[ib] * dp + kn;
+                    bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
+                    bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
+                }
+            }
             const int kc = kk + 8 * g;
             const bool kin = kc < dp;
-            u16x8 bh[2], bl[2];
-#pragma unroll
-            for (int ib = 0; ib < 2; ++ib) {
-                const bool ok = iv[ib] && kin;
-                const int64_t o = (int64_t)pit[ib] * dp + kc;
-                bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
-                bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
-            }
             u16x8 ah[4], al[4];
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb) {
@@ -709,14 +754,14 @@ __global__ __launch_bounds__(256) void k_screen3(
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
+                for (int ib = 0; ib < 4; ++ib) {
                     acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                        as_bf16x8(ah[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                        as_bf16x8(ah[qb]), as_bf16x8(ch[ib]), acc[qb][ib], 0, 0, 0);
                     if (X3) {
                         acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            as_bf16x8(ah[qb]), as_bf16x8(bl[ib]), acc[qb][ib], 0, 0, 0);
+                            as_bf16x8(ah[qb]), as_bf16x8(cl[ib]), acc[qb][ib], 0, 0, 0);
                         acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                            as_bf16x8(al[qb]), as_bf16x8(bh[ib]), acc[qb][ib], 0, 0, 0);
+                            as_bf16x8(al[qb]), as_bf16x8(ch[ib]), acc[qb][ib], 0, 0, 0);
                     }
                 }
         }
@@ -727,9 +772,9 @@ __global__ __launch_bounds__(256) void k_screen3(
                 const int ql = 16 * qb + 4 * g + v;
                 const int hthr = hthr_s[ql], htie = htie_s[ql];
                 const float th = th_s[ql], qn = qn_s[ql];
-                float gmax = -INFINITY;  // MAXMODE: this lane's two items for query ql
+                float gmax[2] = {-INFINITY, -INFINITY};  // MAXMODE: groups of items 0-31, 32-63
 #pragma unroll
-                for (int ib = 0; ib < 2; ++ib) {
+                for (int ib = 0; ib < 4; ++ib) {
                     bool probed = iv[ib];
                     if (!all) {
                         int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
@@ -739,7 +784,7 @@ __global__ __launch_bounds__(256) void k_screen3(
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-90f;
                     if (MAXMODE) {
-                        if (probed) gmax = fmaxf(gmax, ip - e);
+                        if (probed) gmax[ib >> 1] = fmaxf(gmax[ib >> 1], ip - e);
                     } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
@@ -747,11 +792,14 @@ __global__ __launch_bounds__(256) void k_screen3(
                     }
                 }
                 if (MAXMODE) {
-                    // largest lower bound of this iteration's 32 items for query ql
+                    // largest lower bound of each 32-item group for query ql
 #pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
-                    if (r16 == 0 && q0 + ql < nq && p0 < pend)
-                        cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32] = gmax;
+                    for (int hg = 0; hg < 2; ++hg) {
+#pragma unroll
+                        for (int o = 1; o < 16; o <<= 1) gmax[hg] = fmaxf(gmax[hg], __shfl_xor(gmax[hg], o, 64));
+                        if (r16 == 0 && q0 + ql < nq && p0 + 32 * hg < pend)
+                            cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32 + hg] = gmax[hg];
+                    }
                 }
             }
         }
@@ -844,6 +892,13 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
     return hipGetLastError();
 }
 
+hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
+                             float *qn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_query_bf16, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, nq, d, dp, Qh, Ql, qn);
+    return hipGetLastError();
+}
+
 int screen_chunk_items() { return SC_CHUNK; }
 int screen_cell_items() { return SC_CELL; }
 int screen_cell_groups() { return SC_GROUPS; }
@@ -862,7 +917,7 @@ size_t screen_lds_bytes(int dp, int kind)
 
 template <int W, bool MAXMODE, bool X3>
 static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, const double *key_l,
-                                     const uint32_t *codes_l, const float *Q, int64_t nq,
+                                     const uint32_t *codes_l, const ScreenQueries &Q, int64_t nq,
                                      const QueryShape &sh, const int32_t *chunks, int nchunks,
                                      const uint32_t *qcodes, const int32_t *ghthr,
                                      const int32_t *gtie, const int32_t *gpstar,
@@ -874,15 +929,15 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
-    hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.d, sh.dp,
-                       codes_l, key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta,
-                       gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+    hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
+                       codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
+                       gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
     return hipGetLastError();
 }
 
 template <bool MAXMODE>
 static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
-                                  const double *key_l, const uint32_t *codes_l, const float *Q,
+                                  const double *key_l, const uint32_t *codes_l, const ScreenQueries &Q,
                                   int64_t nq, const QueryShape &sh, const int32_t *chunks,
                                   int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                                   const int32_t *gtie, const int32_t *gpstar, const float *theta,
@@ -925,18 +980,18 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
     if (e != hipSuccess) return e;
     if (sh.W == 1)
         hipLaunchKernelGGL((k_screen<1, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
-                           key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
+                           key_l, Q.Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
                            counts, lists, cmax, ncol, sh.L);
     else
         hipLaunchKernelGGL((k_screen<2, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
-                           key_l, Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
+                           key_l, Q.Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
                            counts, lists, cmax, ncol, sh.L);
     return hipGetLastError();
 }
 
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                              const double *key_l, const uint32_t *codes_l,
-                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
+                             const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
                              int ncells, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s)
@@ -958,7 +1013,7 @@ hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t
 
 hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                          const double *key_l, const uint32_t *codes_l,
-                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                         const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
                          int32_t *counts, int32_t *lists, hipStream_t s)

@@ -142,19 +142,29 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 // split, products hi.hi + hi.lo + lo.hi), Xh alone the single-product bf16
 // screen (q and x rounded to bfloat16), neither the FP32 matrix-core screen.
 enum ScreenKind { SCREEN_FP32 = 0, SCREEN_BF16 = 1, SCREEN_BF16X3 = 2 };
+// A query batch as the screens read it: the FP32 rows Q (nq x d) and, for
+// the bfloat16 screens, their bfloat16 image Qh (and its lo part Ql for
+// bf16x3), nq x dp, with an upper bound qn on each row's 2-norm.
+struct ScreenQueries {
+    const float *Q;
+    const uint16_t *Qh, *Ql;
+    const float *qn;
+};
+hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
+                             float *qn, hipStream_t s);
 int screen_chunk_items();
 int screen_cell_items();
 int screen_cell_groups();  // lower-bound maxima kept per cell and query
 size_t screen_lds_bytes(int dp, int kind);
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                              const double *key_l, const uint32_t *codes_l,
-                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
+                             const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
                              int ncells, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s);
 hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                          const double *key_l, const uint32_t *codes_l,
-                         const float *Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
+                         const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *chunks,
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
                          int32_t *counts, int32_t *lists, hipStream_t s);
