@@ -393,10 +393,10 @@ def main():
         flops = 2.0 * products * w.d * pairs
         peak = BF16_MFMA_PEAK_TFS if b16 else FP32_MFMA_PEAK_TFS
         achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
-        kname = {"screen": "k_screen3<1, false, false>",
+        kname = {"screen": "k_screen1<1>",
                  "screen_bf16x3": "k_screen3<1, false, true>"}.get(smode, "k_screen<1, false>")
         if w.L > 32:
-            kname = kname.replace("<1,", "<2,")
+            kname = kname.replace("<1", "<2")
         rec = traffic_record(kname, w.name, Tq)
         roof = {"kernel": kname, "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,

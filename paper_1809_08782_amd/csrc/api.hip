@@ -281,8 +281,11 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     }
 
     Block &B = ix->mem;
-    const size_t oXl = B.reserve<float>((size_t)n * dp), oXh = B.reserve<uint16_t>((size_t)n * dp),
-                 oXlo = B.reserve<uint16_t>((size_t)n * dp), oA = B.reserve<float>(ix->A_h.size()),
+    // the bfloat16 copies carry a zeroed tail pad of 32 values: the screen
+    // reads whole 32-coordinate steps past the last row's dp values
+    const size_t oXl = B.reserve<float>((size_t)n * dp),
+                 oXh = B.reserve<uint16_t>((size_t)n * dp + 32),
+                 oXlo = B.reserve<uint16_t>((size_t)n * dp + 32), oA = B.reserve<float>(ix->A_h.size()),
                  oAt = B.reserve<float>(At_h.size()), okey = B.reserve<double>(n),
                  okeyl = B.reserve<double>(n), okm = B.reserve<double>(m), oU = B.reserve<double>(m),
                  osid = B.reserve<int32_t>(n), osidl = B.reserve<int32_t>(n),
@@ -394,6 +397,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(launch_layout(X, n, d, dp, ix->perm.get(), ix->key.get(), ix->sid.get(), ix->Xl.get(),
                        ix->Xh.get(), ix->Xlo.get(), ix->key_l.get(), ix->sid_l.get(), s));
     tm.end();
+    HIPX(hipMemsetAsync(ix->Xh.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
+    HIPX(hipMemsetAsync(ix->Xlo.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
     if (ix->storage == NRLSH_STORAGE_FP32) {

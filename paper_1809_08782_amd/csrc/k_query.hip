@@ -625,16 +625,21 @@ __global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q,
 // (4 column blocks of 16) against the 64 queries (4 row blocks of 16), and
 // fetches the item rows of the next 32-coordinate step while the matrix cores
 // work on the current one.
+#define NRLSH_SCREEN_PARAMS                                                                    \
+    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int dp,                  \
+        const uint32_t *__restrict__ codes_l, const double *__restrict__ key_l,                 \
+        const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,                       \
+        const float *__restrict__ qnorm, int64_t nq, const int32_t *__restrict__ chunks, int m, \
+        const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,                 \
+        const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,                   \
+        const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,      \
+        int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L
+#define NRLSH_SCREEN_ARGS                                                                      \
+    Xh, Xlo, dp, codes_l, key_l, Qh, Ql, qnorm, nq, chunks, m, qcodes, ghthr, gtie, gpstar, theta, \
+        gam, cap, counts, lists, cmax, ncol, qsb, L
+
 template <int W, bool MAXMODE, bool X3>
-__global__ __launch_bounds__(256) void k_screen3(
-    const uint16_t *__restrict__ Xh, const uint16_t *__restrict__ Xlo, int dp,
-    const uint32_t *__restrict__ codes_l, const double *__restrict__ key_l,
-    const uint16_t *__restrict__ Qh, const uint16_t *__restrict__ Ql,
-    const float *__restrict__ qnorm, int64_t nq, const int32_t *__restrict__ chunks, int m,
-    const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,
-    const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,
-    const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,
-    int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L)
+__device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
 {
     extern __shared__ __align__(16) uint16_t qsh[];  // hi: 64 x qsb, then (X3) lo: 64 x qsb
     uint16_t *qsl = qsh + 64 * qsb;
@@ -681,12 +686,13 @@ __global__ __launch_bounds__(256) void k_screen3(
     __syncthreads();
     if (!any_s) return;  // no query of this tile probes this chunk
 
-    // stage the query tile (rows beyond nq are zero)
+    // stage the query tile (rows beyond nq and columns beyond dp, up to a
+    // multiple of 32, are zero)
     const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    const int v8 = dp / 8;
+    const int v8 = (dp + 31) / 32 * 4;
     for (int idx = tid; idx < 64 * v8; idx += 256) {
         const int r = idx / v8, c = 8 * (idx - r * v8);
-        const bool ok = q0 + r < nq;
+        const bool ok = q0 + r < nq && c < dp;
         *reinterpret_cast<u16x8 *>(&qsh[r * qsb + c]) =
             ok ? *reinterpret_cast<const u16x8 *>(Qh + (q0 + r) * dp + c) : z8;
         if (X3)
@@ -716,14 +722,24 @@ __global__ __launch_bounds__(256) void k_screen3(
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
             for (int ib = 0; ib < 4; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // item operands of step kk: 8 coordinates of one row per lane
+        // item operands of step kk: 8 coordinates of one row per lane.  The
+        // loads are unconditional: an invalid item reads a valid row (its
+        // results are never used), and coordinates past dp read the next
+        // row or the zeroed tail pad of the array -- finite values that meet
+        // the zero columns of the query tile.
+        const uint16_t *rh[4];
+        const uint16_t *rl[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const int64_t row = iv[ib] ? pit[ib] : pbeg;
+            rh[ib] = Xh + row * dp + 8 * g;
+            rl[ib] = X3 ? Xlo + row * dp + 8 * g : nullptr;
+        }
         u16x8 bh[4], bl[4];
 #pragma unroll
         for (int ib = 0; ib < 4; ++ib) {
-            const bool ok = iv[ib] && 8 * g < dp;
-            const int64_t o = (int64_t)pit[ib] * dp + 8 * g;
-            bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
-            bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
+            bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib]);
+            bl[ib] = X3 ? *reinterpret_cast<const u16x8 *>(rl[ib]) : z8;
         }
         for (int kk = 0; kk < dp; kk += 32) {
             u16x8 ch[4], cl[4];
@@ -732,24 +748,20 @@ __global__ __launch_bounds__(256) void k_screen3(
                 ch[ib] = bh[ib];
                 cl[ib] = bl[ib];
             }
-            const int kn = kk + 32 + 8 * g;  // prefetch the next step
-            if (kk + 32 < dp) {
+            if (kk + 32 < dp) {  // prefetch the next step
 #pragma unroll
                 for (int ib = 0; ib < 4; ++ib) {
-                    const bool ok = iv[ib] && kn < dp;
-                    const int64_t o = (int64_t)pit[ib] * dp + kn;
-                    bh[ib] = ok ? *reinterpret_cast<const u16x8 *>(Xh + o) : z8;
-                    bl[ib] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Xlo + o) : z8;
+                    bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib] + kk + 32);
+                    if (X3) bl[ib] = *reinterpret_cast<const u16x8 *>(rl[ib] + kk + 32);
                 }
             }
             const int kc = kk + 8 * g;
-            const bool kin = kc < dp;
             u16x8 ah[4], al[4];
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb) {
                 const int o = (16 * qb + r16) * qsb + kc;
-                ah[qb] = kin ? *reinterpret_cast<const u16x8 *>(&qsh[o]) : z8;
-                al[qb] = (X3 && kin) ? *reinterpret_cast<const u16x8 *>(&qsl[o]) : z8;
+                ah[qb] = *reinterpret_cast<const u16x8 *>(&qsh[o]);
+                al[qb] = X3 ? *reinterpret_cast<const u16x8 *>(&qsl[o]) : z8;
             }
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb)
@@ -804,6 +816,21 @@ __global__ __launch_bounds__(256) void k_screen3(
             }
         }
     }
+}
+
+template <int W, bool MAXMODE, bool X3>
+__global__ __launch_bounds__(256) void k_screen3(NRLSH_SCREEN_PARAMS)
+{
+    screen_bf16<W, MAXMODE, X3>(NRLSH_SCREEN_ARGS);
+}
+
+// Pass B of the single-product screen, the one that runs over every probed
+// pair: a register budget for three waves per SIMD (a few values spill)
+// hides the operand loads better than two waves with no spill.
+template <int W>
+__global__ __launch_bounds__(256, 3) void k_screen1(NRLSH_SCREEN_PARAMS)
+{
+    screen_bf16<W, false, false>(NRLSH_SCREEN_ARGS);
 }
 
 // theta_q = the k-th largest group maximum (a lower bound of the k-th best
@@ -906,7 +933,11 @@ int screen_cell_groups() { return SC_GROUPS; }
 // bf16 row stride of the staged query tile: dp + 8 or dp + 16 so that the
 // row stride in dwords is an odd multiple of 4 (16 lanes reading 16 bytes of
 // 16 rows hit 16 distinct 4-bank groups)
-static int screen_qsb(int dp) { return dp + (((dp / 8) % 2 == 0) ? 8 : 16); }
+// rows padded with zeros to a multiple of 32 coordinates (so that every
+// 32-coordinate step reads real columns), plus 8 so that the row stride in
+// dwords is an odd multiple of 4 (16 lanes reading 16 bytes of 16 rows hit 16
+// distinct 4-bank groups)
+static int screen_qsb(int dp) { return (dp + 31) / 32 * 32 + 8; }
 
 size_t screen_lds_bytes(int dp, int kind)
 {
@@ -925,13 +956,19 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
                                      int32_t *lists, float *cmax, int ncol, hipStream_t s)
 {
     const size_t lds = screen_lds_bytes(sh.dp, X3 ? SCREEN_BF16X3 : SCREEN_BF16);
-    hipError_t e = hipFuncSetAttribute((const void *)k_screen3<W, MAXMODE, X3>,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const bool one = !MAXMODE && !X3;
+    const void *fn = one ? (const void *)k_screen1<W> : (const void *)k_screen3<W, MAXMODE, X3>;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
-    hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
-                       codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
-                       gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+    if (one)
+        hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
+                           Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
+                           cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+    else
+        hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
+                           codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
+                           gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
     return hipGetLastError();
 }
 
