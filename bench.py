@@ -213,9 +213,11 @@ def main():
     ap.add_argument("--query-batch", type=int, default=0,
                     help="queries per nrlsh_query call (0: all in one call)")
     ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
-    ap.add_argument("--eps", default="0.1,0.2,0.3",
-                    help="adjusted-metric variants (Section 3.3) swept after the epsilon = 0 "
-                         "headline; '' for none")
+    ap.add_argument("--variants",
+                    default="eps:0.1,eps:0.2,eps:0.3,uniform,bits,uniform+bits,m:8,m:128",
+                    help="labelled variants timed after the headline, each at its own recall-0.9 "
+                         "budget: eps:E (adjusted metric), uniform (norm ranges), bits (paper's "
+                         "code-bit accounting), m:M (sub-datasets); combine with '+'; '' for none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-MiB buffer 3 times before the steps (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -354,27 +356,56 @@ def main():
                             "kernel_ms_per_step": bk})
             log(f"budget T={T}: {st * 1e3:.2f} ms/step recall {curve.get(T)}")
 
-    # ---------------------------------------------------------------- adjusted metric
-    # labelled variants: the same step with the rank table of
-    # s_hat = U_j cos[pi (1 - eps)(1 - l/L)]; each at its own recall-0.9 budget
-    eps_variants = []
-    eps_list = [float(e) for e in args.eps.split(",") if e.strip()] if not args.no_sweep else []
-    for eps in eps_list:
-        ex = nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage,
-                            margin=margin, eps=eps)
-        ecurve, eT = {}, None
+    # ---------------------------------------------------------------- labelled variants
+    # the same step under the paper's other settings, each at its own
+    # recall-0.9 budget: the adjusted metric s_hat = U_j cos[pi (1 - eps)(1 - l/L)]
+    # (Section 3.3), uniform norm ranges (Section 5), the paper's code-bit
+    # accounting (ceil(log2 m) of the L bits spent on the sub-dataset id,
+    # Section 4) and other sub-dataset counts (Figure 3b's sweep)
+    variants = []
+    spec = [v.strip() for v in args.variants.split(",") if v.strip()] if not args.no_sweep else []
+    for v in spec:
+        cfg = {"label": v, "eps": 0.0, "partition": "percentile", "m": w.m, "L": w.L}
+        for part in v.split("+"):
+            if part.startswith("eps:"):
+                cfg["eps"] = float(part[4:])
+            elif part == "uniform":
+                cfg["partition"] = "uniform"
+            elif part.startswith("m:"):
+                cfg["m"] = int(part[2:])
+            elif part != "bits":
+                ap.error(f"unknown variant {v}")
+        if "bits" in v.split("+"):  # after m is known
+            cfg["L"] = w.L - (math.ceil(math.log2(cfg["m"])) if cfg["m"] > 1 else 0)
+        ex = nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
+                            margin=margin, eps=cfg["eps"], partition=cfg["partition"])
+        vcurve, vT = {}, None
         for T in budgets_sweep:
             ids, _ = nr.nrlsh_query(ex, Qd[:nrec], w.k, T)
             r = recall(ids.cpu().numpy(), gt)
-            ecurve[str(T)] = r
-            if eT is None and r >= 0.9 and (T & (T - 1) == 0 or T == w.n):
-                eT = T
+            vcurve[str(T)] = r
+            if vT is None and r >= 0.9 and (T & (T - 1) == 0 or T == w.n):
+                vT = T
         ex.close()
-        eT = eT or w.n
-        est = timed(eT, max(2, args.steps // 2), 1, False, eps)
-        eps_variants.append({"eps": eps, "T": eT, "frac_of_n": eT / w.n, "recall_at_T": ecurve.get(str(eT)),
-                             "qps": w.nq / est, "ms_per_step": est * 1e3, "recall_curve": ecurve})
-        log(f"eps={eps}: T_op={eT} recall {ecurve.get(str(eT))} {est * 1e3:.2f} ms/step")
+        vT = vT or w.n
+
+        def vstep(T, cfg=cfg):
+            with nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
+                                margin=margin, eps=cfg["eps"], partition=cfg["partition"]) as sx:
+                nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf), rerank=args.rerank,
+                               rerank_storage=args.rerank_storage)
+        vstep(vT)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        reps = max(2, args.steps // 2)
+        for _ in range(reps):
+            vstep(vT)
+        torch.cuda.synchronize()
+        est = (time.perf_counter() - t) / reps
+        variants.append({**cfg, "T": vT, "frac_of_n": vT / w.n, "recall_at_T": vcurve.get(str(vT)),
+                         "qps": w.nq / est, "ms_per_step": est * 1e3, "recall_curve": vcurve})
+        log(f"variant {v}: m={cfg['m']} L={cfg['L']} T_op={vT} recall {vcurve.get(str(vT))} "
+            f"{est * 1e3:.2f} ms/step")
 
     # ---------------------------------------------------------------- roofline
     Tq = min(T_op, w.n)
@@ -472,7 +503,7 @@ def main():
         "norm_stats": norm_stats,
         "roofline": roof,
         "scan": scan,
-        "eps_variants": eps_variants,
+        "variants": variants,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

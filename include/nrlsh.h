@@ -98,6 +98,15 @@ nrlsh_status nrlsh_build(const float *items, int64_t n, int32_t d, int32_t m, in
 typedef enum { NRLSH_STORAGE_FP32 = 0, NRLSH_STORAGE_BF16 = 1, NRLSH_STORAGE_FP8_E4M3 = 2 } nrlsh_storage;
 typedef enum { NRLSH_MARGIN_RIGOROUS = 0, NRLSH_MARGIN_SCALED = 1 } nrlsh_margin_mode;
 
+/* How items are cut into the m sub-datasets.
+ *   PERCENTILE: by norm rank, sizes floor or ceil of n/m (Algorithm 1; default).
+ *   UNIFORM:    the alternative of Section 5: the 2-norm domain [nmin, nmax]
+ *               of the items is cut into m ranges of equal width; boundary j
+ *               (1 <= j < m) is b_j = nmin + j (nmax - nmin) / m (FP64, in this
+ *               order) and an item joins range #{j : key >= b_j * b_j}, where
+ *               key is its FP64 squared norm.  Ranges may be empty (U_j = 0). */
+typedef enum { NRLSH_PARTITION_PERCENTILE = 0, NRLSH_PARTITION_UNIFORM = 1 } nrlsh_partition;
+
 typedef struct nrlsh_build_opts {
     int32_t struct_size;  /* sizeof(nrlsh_build_opts) */
     int32_t device_ptrs;  /* 1: items is a device pointer */
@@ -107,6 +116,8 @@ typedef struct nrlsh_build_opts {
     int32_t hash_storage; /* nrlsh_storage (read when struct_size covers it) */
     int32_t margin_mode;  /* nrlsh_margin_mode */
     double margin_param;  /* SCALED: relative margin (>= 0) */
+    int32_t partition;    /* nrlsh_partition (read when struct_size covers it) */
+    int32_t pad;
 } nrlsh_build_opts;
 
 nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,

@@ -17,7 +17,10 @@
  *   - the ranking key is the FP64 sum of squares, ascending coordinate order
  *   - sign(0) is bit 0                                    (Eq. 4)
  *   - one projection matrix shared by all sub-datasets    (Section 3.3,
- *     single-table multi-probe)
+ *     single-table multi-probe); as an option each sub-dataset draws its own
+ *     L projections (rows j L .. j L + L - 1 of one m L x (d+1) matrix from
+ *     the same generator) and the query is hashed once per sub-dataset
+ *     (Section 1, "independently")
  *   - U_j = 0: the transformed item is [0; 1]             (Eq. 8)
  *   - probing order is descending s_hat (best first); cos(pi/2) is taken
  *     as exactly 0 and the table is antisymmetric about l = L/2; ties are
@@ -25,6 +28,11 @@
  *   - the probe budget T is a number of items; the bucket where the budget
  *     runs out is cut by original index                   (Section 3.3)
  *   - the query is not normalised (bits and argmax are scale invariant)
+ *   - uniform partitioning (Section 5, the alternative scheme): the 2-norm
+ *     domain [min, max] of the items is cut into m ranges of equal width;
+ *     boundary j (1 <= j < m) is b_j = nmin + j * w, w = (nmax - nmin) / m,
+ *     and an item joins the range of the boundaries its key reaches:
+ *     s = #{j : key >= b_j * b_j}; ranges may be empty
  *
  * Parity pins: every function here is checked by the CPU test-suite against
  * closed forms, invariants, brute force and published generator vectors.
@@ -127,6 +135,38 @@ void orc_partition(const double *key, const int64_t *rank, int64_t n, int32_t m,
     for (int32_t j = 0; j < m; ++j) U[j] = sqrt(keymax[j]);
 }
 
+/* Alternative partition of Section 5: uniformly spaced ranges of the 2-norm
+ * domain [nmin, nmax] (nmin, nmax = sqrt of the smallest / largest key).
+ * Boundary j = 1 .. m-1 is b_j = nmin + j w with w = (nmax - nmin) / m; the
+ * item goes to the number of boundaries whose square its key reaches, so the
+ * comparison is made on exact keys.  keymax_j = 0 for an empty range.        */
+void orc_partition_uniform(const double *key, int64_t n, int32_t m, int32_t *sid,
+                           double *keymax, double *U)
+{
+    double kmin = key[0], kmax = key[0];
+    for (int64_t i = 1; i < n; ++i) {
+        if (key[i] < kmin) kmin = key[i];
+        if (key[i] > kmax) kmax = key[i];
+    }
+    const double nmin = sqrt(kmin), nmax = sqrt(kmax);
+    const double w = (nmax - nmin) / (double)m;
+    double *B = (double *)malloc(sizeof(double) * (size_t)(m > 1 ? m - 1 : 1));
+    for (int32_t j = 1; j < m; ++j) {
+        const double b = nmin + (double)j * w;
+        B[j - 1] = b * b;
+    }
+    for (int32_t j = 0; j < m; ++j) keymax[j] = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t s = 0;
+        for (int32_t j = 1; j < m; ++j)
+            if (key[i] >= B[j - 1]) s = j;
+        sid[i] = s;
+        if (key[i] > keymax[s]) keymax[s] = key[i];
+    }
+    for (int32_t j = 0; j < m; ++j) U[j] = sqrt(keymax[j]);
+    free(B);
+}
+
 /* ------------------------------------------------------------------------ */
 /* SimpleLSH transform (Eq. 8) of item i of sub-dataset j after normalising
  * by U_j (Algorithm 1):  v = [x / U_j ; sqrt(max(0, 1 - key_i / keymax_j))],
@@ -159,17 +199,27 @@ uint64_t orc_hash_vec(const float *A, int32_t L, int32_t d, const double *v)
 
 /* Item codes for items [i0, i1): transform then hash (Algorithm 1, the
  * SimpleLSH index of each sub-dataset).                                    */
-void orc_item_codes(const float *X, int64_t i0, int64_t i1, int32_t d, int32_t L,
-                    const float *A, const double *key, const int32_t *sid,
-                    const double *keymax, const double *U, uint64_t *codes)
+/* Codes of items i0 .. i1-1; per_subset: item of sub-dataset s hashes with
+ * rows s L .. s L + L - 1 of A (independent projections per sub-dataset). */
+void orc_item_codes2(const float *X, int64_t i0, int64_t i1, int32_t d, int32_t L,
+                     const float *A, int32_t per_subset, const double *key, const int32_t *sid,
+                     const double *keymax, const double *U, uint64_t *codes)
 {
     double *v = (double *)malloc(sizeof(double) * (size_t)(d + 1));
     for (int64_t i = i0; i < i1; ++i) {
         int32_t s = sid[i];
+        const float *As = per_subset ? A + (int64_t)s * L * (d + 1) : A;
         orc_transform(X + i * (int64_t)d, d, key[i], keymax[s], U[s], v);
-        codes[i] = orc_hash_vec(A, L, d, v);
+        codes[i] = orc_hash_vec(As, L, d, v);
     }
     free(v);
+}
+
+void orc_item_codes(const float *X, int64_t i0, int64_t i1, int32_t d, int32_t L,
+                    const float *A, const double *key, const int32_t *sid,
+                    const double *keymax, const double *U, uint64_t *codes)
+{
+    orc_item_codes2(X, i0, i1, d, L, A, 0, key, sid, keymax, U, codes);
 }
 
 /* Query code (Eq. 8: P(q) = [q; 0]): bit r = [sum_{t<d} A_rt q_t > 0].     */
@@ -258,13 +308,15 @@ static int orc_cmp_ii(const void *a, const void *b)
     return 0;
 }
 
-int64_t orc_candidates(const uint64_t *codes, const int32_t *sid, int64_t n, int32_t L,
-                       const int32_t *R, uint64_t qcode, int64_t T, int64_t *cand,
-                       int32_t *l_out)
+/* qcodes: the query code for each sub-dataset (per_subset) or one code. */
+int64_t orc_candidates2(const uint64_t *codes, const int32_t *sid, int64_t n, int32_t L,
+                        const int32_t *R, const uint64_t *qcodes, int32_t per_subset, int64_t T,
+                        int64_t *cand, int32_t *l_out)
 {
     orc_ii *e = (orc_ii *)malloc(sizeof(orc_ii) * (size_t)(n > 0 ? n : 1));
     if (!e) return -1;
     for (int64_t i = 0; i < n; ++i) {
+        const uint64_t qcode = qcodes[per_subset ? sid[i] : 0];
         int32_t l = orc_same_bits(codes[i], qcode, L);
         e[i].key = R[(int64_t)sid[i] * (L + 1) + l];
         e[i].idx = i;
@@ -273,10 +325,17 @@ int64_t orc_candidates(const uint64_t *codes, const int32_t *sid, int64_t n, int
     int64_t Tq = T < n ? T : n;
     for (int64_t c = 0; c < Tq; ++c) {
         cand[c] = e[c].idx;
-        if (l_out) l_out[c] = orc_same_bits(codes[e[c].idx], qcode, L);
+        if (l_out) l_out[c] = orc_same_bits(codes[e[c].idx], qcodes[per_subset ? sid[e[c].idx] : 0], L);
     }
     free(e);
     return Tq;
+}
+
+int64_t orc_candidates(const uint64_t *codes, const int32_t *sid, int64_t n, int32_t L,
+                       const int32_t *R, uint64_t qcode, int64_t T, int64_t *cand,
+                       int32_t *l_out)
+{
+    return orc_candidates2(codes, sid, n, L, R, &qcode, 0, T, cand, l_out);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -328,7 +387,8 @@ int orc_topk(const float *X, int32_t d, const float *q, const int64_t *cand, int
  * queries (query); each thread runs the plain per-item / per-query loop.  */
 typedef struct {
     int64_t n; int32_t d, m, L;
-    float *A;          /* L x (d+1) */
+    int32_t per_subset; /* 1: sub-dataset j hashes with rows j L .. j L + L - 1 of A */
+    float *A;          /* L x (d+1), or m L x (d+1) with per_subset */
     double *key;       /* n */
     int64_t *rank;     /* n */
     int32_t *sid;      /* n */
@@ -347,8 +407,8 @@ static void *orc_build_worker(void *arg)
 {
     orc_build_job *jb = (orc_build_job *)arg;
     const orc_index *ix = jb->ix;
-    orc_item_codes(ix->X, jb->i0, jb->i1, ix->d, ix->L, ix->A, ix->key, ix->sid,
-                   ix->keymax, ix->U, ix->codes);
+    orc_item_codes2(ix->X, jb->i0, jb->i1, ix->d, ix->L, ix->A, ix->per_subset, ix->key, ix->sid,
+                    ix->keymax, ix->U, ix->codes);
     return NULL;
 }
 
@@ -371,14 +431,19 @@ void orc_free(orc_index *ix)
     free(ix);
 }
 
-orc_index *orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
-                     uint64_t seed, double eps, int32_t nthreads)
+/* partition: 0 = norm percentiles (Algorithm 1), 1 = uniform ranges (Section 5);
+ * per_subset: 1 = independent projections per sub-dataset */
+orc_index *orc_build3(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
+                      uint64_t seed, double eps, int32_t partition, int32_t per_subset,
+                      int32_t nthreads)
 {
     if (nthreads < 1) nthreads = 1;
     orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
     if (!ix) return NULL;
     ix->n = n; ix->d = d; ix->m = m; ix->L = L; ix->X = X;
-    ix->A = (float *)malloc(sizeof(float) * (size_t)L * (size_t)(d + 1));
+    ix->per_subset = per_subset ? 1 : 0;
+    const int32_t rows = per_subset ? m * L : L;
+    ix->A = (float *)malloc(sizeof(float) * (size_t)rows * (size_t)(d + 1));
     ix->key = (double *)malloc(sizeof(double) * (size_t)n);
     ix->rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     ix->sid = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
@@ -389,7 +454,7 @@ orc_index *orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
     if (!ix->A || !ix->key || !ix->rank || !ix->sid || !ix->keymax || !ix->U ||
         !ix->codes || !ix->R) { orc_free(ix); return NULL; }
 
-    orc_projection(seed, L, d, ix->A);
+    orc_projection(seed, rows, d, ix->A);
 
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
     orc_key_job *kj = (orc_key_job *)malloc(sizeof(orc_key_job) * (size_t)nthreads);
@@ -402,7 +467,10 @@ orc_index *orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
     for (int32_t t = 0; t < nthreads; ++t) pthread_join(th[t], NULL);
 
     orc_rank(ix->key, n, ix->rank);
-    orc_partition(ix->key, ix->rank, n, m, ix->sid, ix->keymax, ix->U);
+    if (partition == 1)
+        orc_partition_uniform(ix->key, n, m, ix->sid, ix->keymax, ix->U);
+    else
+        orc_partition(ix->key, ix->rank, n, m, ix->sid, ix->keymax, ix->U);
 
     for (int32_t t = 0; t < nthreads; ++t) {
         bj[t].ix = ix; bj[t].i0 = n * t / nthreads; bj[t].i1 = n * (t + 1) / nthreads;
@@ -413,6 +481,18 @@ orc_index *orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
 
     orc_rank_table(ix->U, m, L, eps, ix->R, NULL);
     return ix;
+}
+
+orc_index *orc_build2(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
+                      uint64_t seed, double eps, int32_t partition, int32_t nthreads)
+{
+    return orc_build3(X, n, d, m, L, seed, eps, partition, 0, nthreads);
+}
+
+orc_index *orc_build(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
+                     uint64_t seed, double eps, int32_t nthreads)
+{
+    return orc_build3(X, n, d, m, L, seed, eps, 0, 0, nthreads);
 }
 
 /* Accessors for the Python wrapper. */
@@ -433,15 +513,20 @@ static void *orc_query_worker(void *arg)
     orc_query_job *jb = (orc_query_job *)arg;
     const orc_index *ix = jb->ix;
     int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ix->n > 0 ? ix->n : 1));
-    if (!cand) { jb->rc = -1; return NULL; }
+    const int32_t ncodes = ix->per_subset ? ix->m : 1;
+    uint64_t *qc = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)ncodes);
+    if (!cand || !qc) { free(cand); free(qc); jb->rc = -1; return NULL; }
     for (int64_t q = jb->q0; q < jb->q1; ++q) {
         const float *qv = jb->Q + q * (int64_t)ix->d;
-        uint64_t qc = orc_query_code(ix->A, ix->L, ix->d, qv);
-        int64_t nc = orc_candidates(ix->codes, ix->sid, ix->n, ix->L, ix->R, qc, jb->T, cand, NULL);
+        for (int32_t j = 0; j < ncodes; ++j)
+            qc[j] = orc_query_code(ix->A + (int64_t)j * ix->L * (ix->d + 1), ix->L, ix->d, qv);
+        int64_t nc = orc_candidates2(ix->codes, ix->sid, ix->n, ix->L, ix->R, qc, ix->per_subset,
+                                     jb->T, cand, NULL);
         if (nc < 0) { jb->rc = -1; break; }
         orc_topk(ix->X, ix->d, qv, cand, nc, jb->k, jb->ids + q * jb->k, jb->ips + q * jb->k);
     }
     free(cand);
+    free(qc);
     return NULL;
 }
 

@@ -61,6 +61,7 @@ def _declare(L):
     L.orc_hash_vec.argtypes = [P, I32, I32, P]
     L.orc_hash_vec.restype = U64
     L.orc_item_codes.argtypes = [P, I64, I64, I32, I32, P, P, P, P, P, P]
+    L.orc_item_codes2.argtypes = [P, I64, I64, I32, I32, P, I32, P, P, P, P, P]
     L.orc_query_code.argtypes = [P, I32, I32, P]
     L.orc_query_code.restype = U64
     L.orc_same_bits.argtypes = [U64, U64, I32]
@@ -71,12 +72,18 @@ def _declare(L):
     L.orc_rank_table.restype = C.c_int
     L.orc_candidates.argtypes = [P, P, I64, I32, P, U64, I64, P, P]
     L.orc_candidates.restype = I64
+    L.orc_candidates2.argtypes = [P, P, I64, I32, P, P, I32, I64, P, P]
+    L.orc_candidates2.restype = I64
     L.orc_ip.argtypes = [P, P, I32]
     L.orc_ip.restype = F64
     L.orc_topk.argtypes = [P, I32, P, P, I64, I32, P, P]
     L.orc_topk.restype = C.c_int
     L.orc_build.argtypes = [P, I64, I32, I32, I32, U64, F64, I32]
     L.orc_build.restype = P
+    L.orc_build2.argtypes = [P, I64, I32, I32, I32, U64, F64, I32, I32]
+    L.orc_build2.restype = P
+    L.orc_build3.argtypes = [P, I64, I32, I32, I32, U64, F64, I32, I32, I32]
+    L.orc_build3.restype = P
     L.orc_free.argtypes = [P]
     L.orc_index_arrays.argtypes = [P] + [C.POINTER(P)] * 8
     L.orc_query.argtypes = [P, P, I64, I32, I64, I32, P, P]
@@ -149,17 +156,21 @@ def hash_vec(A, v) -> int:
     return int(lib().orc_hash_vec(_p(A), L, d1 - 1, _p(v)))
 
 
-def item_codes(X, A, key, sid, keymax, U) -> np.ndarray:
+def item_codes(X, A, key, sid, keymax, U, per_subset: bool = False) -> np.ndarray:
+    """Codes of all items.  per_subset: A holds m L rows and an item of
+    sub-dataset j hashes with rows j L .. j L + L - 1."""
     X = _f32(X)
     A = _f32(A)
     n, d = X.shape
-    L = A.shape[0]
+    m = np.asarray(U).shape[0]
+    L = A.shape[0] // m if per_subset else A.shape[0]
     key = np.ascontiguousarray(key, dtype=np.float64)
     sid = np.ascontiguousarray(sid, dtype=np.int32)
     keymax = np.ascontiguousarray(keymax, dtype=np.float64)
     U = np.ascontiguousarray(U, dtype=np.float64)
     out = np.empty(n, dtype=np.uint64)
-    lib().orc_item_codes(_p(X), 0, n, d, L, _p(A), _p(key), _p(sid), _p(keymax), _p(U), _p(out))
+    lib().orc_item_codes2(_p(X), 0, n, d, L, _p(A), int(per_subset), _p(key), _p(sid),
+                          _p(keymax), _p(U), _p(out))
     return out
 
 
@@ -192,7 +203,10 @@ def rank_table(U, L: int, eps: float = 0.0):
     return R, shat
 
 
-def candidates(codes, sid, L: int, R, qcode: int, T: int):
+def candidates(codes, sid, L: int, R, qcode, T: int):
+    """First min(T, n) items by (rank of (sub-dataset, same bits), index).
+    qcode: one query code, or an array of one code per sub-dataset (for
+    independent projections per sub-dataset)."""
     codes = np.ascontiguousarray(codes, dtype=np.uint64)
     sid = np.ascontiguousarray(sid, dtype=np.int32)
     R = np.ascontiguousarray(R, dtype=np.int32)
@@ -200,7 +214,11 @@ def candidates(codes, sid, L: int, R, qcode: int, T: int):
     Tq = min(T, n)
     cand = np.empty(max(Tq, 1), dtype=np.int64)
     ls = np.empty(max(Tq, 1), dtype=np.int32)
-    got = lib().orc_candidates(_p(codes), _p(sid), n, L, _p(R), qcode, T, _p(cand), _p(ls))
+    if np.ndim(qcode) == 0:
+        got = lib().orc_candidates(_p(codes), _p(sid), n, L, _p(R), int(qcode), T, _p(cand), _p(ls))
+    else:
+        qc = np.ascontiguousarray(qcode, dtype=np.uint64)
+        got = lib().orc_candidates2(_p(codes), _p(sid), n, L, _p(R), _p(qc), 1, T, _p(cand), _p(ls))
     if got < 0:
         raise MemoryError("oracle candidates")
     return cand[:got], ls[:got]
@@ -238,11 +256,19 @@ def bruteforce(X, Q, k: int, threads: int = 1):
 class OracleIndex:
     """Index built by the oracle (Algorithm 1).  Keeps a reference to X."""
 
-    def __init__(self, X, m: int, L: int, seed: int, eps: float = 0.0, threads: int = 1):
+    PARTITIONS = {"percentile": 0, "uniform": 1}
+    PROJECTIONS = {"shared": 0, "per_subset": 1}
+
+    def __init__(self, X, m: int, L: int, seed: int, eps: float = 0.0, threads: int = 1,
+                 partition: str = "percentile", projections: str = "shared"):
         self.X = _f32(X)
         self.n, self.d = self.X.shape
         self.m, self.L, self.seed, self.eps = m, L, seed, eps
-        self._h = lib().orc_build(_p(self.X), self.n, self.d, m, L, seed, eps, threads)
+        self.partition = partition
+        self.projections = projections
+        self.per_subset = self.PROJECTIONS[projections] == 1
+        self._h = lib().orc_build3(_p(self.X), self.n, self.d, m, L, seed, eps,
+                                   self.PARTITIONS[partition], int(self.per_subset), threads)
         if not self._h:
             raise MemoryError("oracle build")
         ptrs = [P() for _ in range(8)]
@@ -253,7 +279,8 @@ class OracleIndex:
             return np.ctypeslib.as_array(buf).view(dt).copy()
 
         n, d, L_ = self.n, self.d, L
-        self.A = view(ptrs[0], C.c_float, L_ * (d + 1), np.float32).reshape(L_, d + 1)
+        rows = m * L_ if self.per_subset else L_
+        self.A = view(ptrs[0], C.c_float, rows * (d + 1), np.float32).reshape(rows, d + 1)
         self.key = view(ptrs[1], C.c_double, n, np.float64)
         self.rank = view(ptrs[2], C.c_int64, n, np.int64)
         self.sid = view(ptrs[3], C.c_int32, n, np.int32)
@@ -271,8 +298,13 @@ class OracleIndex:
             raise MemoryError("oracle query")
         return ids, ips
 
-    def query_code(self, q) -> int:
-        return query_code(self.A, q)
+    def query_code(self, q):
+        """The query code; with per-subset projections, one code per sub-dataset."""
+        if not self.per_subset:
+            return query_code(self.A, q)
+        L = self.L
+        return np.array([query_code(self.A[j * L:(j + 1) * L], q) for j in range(self.m)],
+                        dtype=np.uint64)
 
     def candidates(self, q, T: int):
         return candidates(self.codes, self.sid, self.L, self.R, self.query_code(q), T)

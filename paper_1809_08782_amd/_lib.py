@@ -31,7 +31,11 @@ class NrlshError(RuntimeError):
 class BuildOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32),
                 ("stream", C.c_void_p), ("eps", C.c_double), ("hash_storage", C.c_int32),
-                ("margin_mode", C.c_int32), ("margin_param", C.c_double)]
+                ("margin_mode", C.c_int32), ("margin_param", C.c_double),
+                ("partition", C.c_int32), ("pad", C.c_int32)]
+
+
+PARTITIONS = {"percentile": 0, "uniform": 1}
 
 
 STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
@@ -289,26 +293,28 @@ class Index:
 
 # ------------------------------------------------------------------ C-ABI names
 def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None,
-                hash_storage: str = "fp32", margin="rigorous") -> Index:
+                hash_storage: str = "fp32", margin="rigorous", partition: str = "percentile") -> Index:
     """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
     tensor (n, d) float32 (device pointer, torch's current stream).
     ``hash_storage`` ("fp32", "bf16", "fp8") selects the precision form of the
-    hash GEMM; ``margin`` is "rigorous" or a relative margin (float)."""
+    hash GEMM; ``margin`` is "rigorous" or a relative margin (float);
+    ``partition`` is "percentile" (Algorithm 1) or "uniform" (Section 5)."""
     h = P()
     st = STORAGES[hash_storage]
+    part = PARTITIONS[partition]
     mmode, mparam = (0, 0.0) if margin == "rigorous" else (1, float(margin))
     if _is_torch_device(items):
         if items.dtype.__str__() != "torch.float32" or items.dim() != 2:
             raise ValueError("items must be a 2-D float32 tensor")
         items = items.contiguous()
         opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps), st,
-                         mmode, mparam)
+                         mmode, mparam, part)
         _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
                                     seed, C.byref(opts), C.byref(h)))
     else:
         X = _host_f32(items)
-        if eps != 0.0 or stream is not None or st != 0:
-            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam)
+        if eps != 0.0 or stream is not None or st != 0 or part != 0:
+            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam, part)
             _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
                                         C.byref(opts), C.byref(h)))
         else:

@@ -317,7 +317,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                  ova = T.reserve<int32_t>(n), ovb = T.reserve<int32_t>(n),
                  ortmp = T.reserve<uint8_t>(radix_sort_tmp_bytes(n)), ofix = T.reserve<FixEntry>(n),
                  octr = T.reserve<BuildCounters>(1),
-                 ostg = T.reserve<float>(on_device ? 1 : (size_t)n * d);
+                 ostg = T.reserve<float>(on_device ? 1 : (size_t)n * d),
+                 obnd = T.reserve<double>(m), osub = T.reserve<int32_t>(m);
     T.allocate(s);
     DBuf<float> tau = T.view<float>(otau);
     DBuf<uint64_t> ka = T.view<uint64_t>(oka), kb = T.view<uint64_t>(okb);
@@ -326,6 +327,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     DBuf<FixEntry> fix = T.view<FixEntry>(ofix);
     DBuf<BuildCounters> ctr = T.view<BuildCounters>(octr);
     DBuf<float> staging = T.view<float>(ostg);
+    DBuf<double> bounds = T.view<double>(obnd);
+    DBuf<int32_t> subend = T.view<int32_t>(osub);
     const float *X = items;
     if (!on_device) {
         HIPX(hipMemcpyAsync(staging.get(), items, (size_t)n * d * sizeof(float),
@@ -352,12 +355,35 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     int32_t *sv = in_b ? vb.get() : va.get();
     uint64_t *lk = in_b ? ka.get() : kb.get();
     int32_t *lv = in_b ? va.get() : vb.get();
-    HIPX(launch_assign_subsets(sk, sv, n, m, ix->sid.get(), lk, lv, ix->keymax.get(), s));
+    // uniform ranges (Section 5): boundaries from the smallest and largest
+    // key, b_j = nmin + j w, compared with the keys as b_j^2
+    const bool uniform = ix->partition == NRLSH_PARTITION_UNIFORM && m > 1;
+    if (uniform) {
+        double kext[2];
+        HIPX(hipMemcpyAsync(&kext[0], sk, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(&kext[1], sk + n - 1, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        const double nmin = std::sqrt(kext[0]), nmax = std::sqrt(kext[1]);
+        const double w = (nmax - nmin) / (double)m;
+        std::vector<double> bh((size_t)m - 1);
+        for (int j = 1; j < m; ++j) {
+            const double b = nmin + (double)j * w;
+            bh[(size_t)j - 1] = b * b;
+        }
+        HIPX(hipMemcpyAsync(bounds.get(), bh.data(), bh.size() * sizeof(double),
+                            hipMemcpyHostToDevice, s));
+    }
+    HIPX(hipMemsetAsync(ix->keymax.get(), 0, m * sizeof(double), s));
+    HIPX(hipMemsetAsync(subend.get(), 0xFF, m * sizeof(int32_t), s));
+    HIPX(launch_assign_subsets(sk, sv, n, m, uniform ? bounds.get() : nullptr, ix->sid.get(), lk, lv,
+                               ix->keymax.get(), subend.get(), s));
 
     BuildCounters hc{};
     ix->keymax_h.resize(m);
+    std::vector<int32_t> subend_h((size_t)m);
     HIPX(hipMemcpyAsync(ix->keymax_h.data(), ix->keymax.get(), m * sizeof(double),
                         hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(subend_h.data(), subend.get(), m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
     HIPX(hipStreamSynchronize(s));
     if (hc.nonfinite) throw Failure{NRLSH_E_NOT_FINITE, "items hold NaN or Inf"};
@@ -367,12 +393,15 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     for (int j = 0; j < m; ++j) ix->U_h[j] = std::sqrt(ix->keymax_h[j]);
     std::vector<int32_t> inv_h;
     make_rank_table(ix->U_h, L, ix->eps, ix->R_h, inv_h);
-    ix->off_h.resize(m + 1);
-    std::vector<int32_t> off32(m + 1);
-    for (int j = 0; j <= m; ++j) {
-        ix->off_h[j] = ((int64_t)j * n + m - 1) / m;
-        off32[j] = (int32_t)ix->off_h[j];
+    // sub-dataset j occupies sorted ranks [off_j, off_{j+1}); an empty one
+    // (no end rank written) starts and ends where the previous one ended
+    ix->off_h.assign(m + 1, 0);
+    std::vector<int32_t> off32(m + 1, 0);
+    for (int j = 0; j < m; ++j) {
+        ix->off_h[j + 1] = subend_h[j] >= 0 ? subend_h[j] : ix->off_h[j];
+        off32[j + 1] = (int32_t)ix->off_h[j + 1];
     }
+    if (ix->off_h[m] != n) throw Failure{NRLSH_E_INTERNAL, "sub-dataset runs do not cover the items"};
     HIPX(hipMemcpyAsync(ix->U.get(), ix->U_h.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(ix->R.get(), ix->R_h.data(), ix->R_h.size() * sizeof(int32_t),
                         hipMemcpyHostToDevice, s));
@@ -488,6 +517,17 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int nsplit = rerank_splits(B, sh.Tq);
     const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
     const int lsplit = rerank_splits(B, lcap);
+    // small batches: (tiles x sub-datasets) waves leave the machine idle, so
+    // the scans take chunks of a sub-dataset per wave (about 16k waves)
+    int64_t maxsub = 0;
+    for (int j = 0; j < sh.m; ++j) maxsub = std::max(maxsub, ix->off_h[j + 1] - ix->off_h[j]);
+    const bool chunked = !cand_out_d && tiles * sh.m < 4096 && maxsub > 4096;
+    int chunk = 0, nch = 1;
+    if (chunked) {
+        const int64_t want = (maxsub * tiles * sh.m + 16383) / 16384;
+        chunk = (int)std::max<int64_t>(2048, (want + 63) / 64 * 64);
+        nch = (int)((maxsub + chunk - 1) / chunk);
+    }
     Block blk;
     const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.W),
                  o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
@@ -498,6 +538,9 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_pv = blk.reserve<double>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_lc = blk.reserve<int32_t>(bf16_rows ? (size_t)B : 1),
+                 o_gt = blk.reserve<unsigned long long>(bf16_rows ? (size_t)B : 1),
+                 o_ps = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
+                 o_ct = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
                  o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
                  o_lv = blk.reserve<double>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
                  o_lp = blk.reserve<int32_t>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1);
@@ -508,6 +551,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<double> part_v = blk.view<double>(o_pv);
     DBuf<int32_t> part_i = blk.view<int32_t>(o_pi);
     DBuf<int32_t> lcount = blk.view<int32_t>(o_lc), lists = blk.view<int32_t>(o_li);
+    DBuf<unsigned long long> gtheta = blk.view<unsigned long long>(o_gt);
+    DBuf<int32_t> gpstar = blk.view<int32_t>(o_ps), ccount = blk.view<int32_t>(o_ct);
     DBuf<double> lpart_v = blk.view<double>(o_lv);
     DBuf<int32_t> lpart_i = blk.view<int32_t>(o_lp);
     std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
@@ -519,23 +564,42 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         tm.begin("qhash");
         HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qc, nonfinite_d, s));
         tm.end();
+        const int64_t tb = (nb + 63) / 64;
         tm.begin("scan_hist");
-        HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
+        if (chunked) {
+            HIPX(hipMemsetAsync(ghist.get(), 0, (size_t)tb * sh.m * L1 * 64 * sizeof(uint32_t), s));
+            HIPX(launch_scan_hist_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
+                                    ghist.get(), s));
+        } else {
+            HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
+        }
         tm.end();
         tm.begin("threshold");
         HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
                               ghthr.get(), gtie.get(), s));
         tm.end();
+        if (chunked) {
+            tm.begin("tie_locate");
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, gtie.get(),
+                                   gpstar.get(), s));
+            tm.end();
+            HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
+        }
         tm.begin("scan_emit");
-        HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
-                              ghthr.get(), gtie.get(), cb, s));
+        if (chunked)
+            HIPX(launch_scan_emit_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
+                                    ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
+        else
+            HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
+                                  ghthr.get(), gtie.get(), cb, s));
         tm.end();
         if (cand_out_d) continue;
         if (bf16_rows) {
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
+            HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
             tm.begin("rerank_lp");
             HIPX(launch_rerank_lp(ix->Xh.get(), ix->key_l.get(), ix->perm.get(), Qb, nb, sh, cb,
-                                  nsplit, (int)lcap, lcount.get(), lists.get(), s));
+                                  nsplit, (int)lcap, lcount.get(), lists.get(), gtheta.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
@@ -774,6 +838,11 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         return fail(NRLSH_E_INVALID_ARG, "margin_mode %d unknown", margin_mode);
     if (!(margin_param >= 0.0 && margin_param < 1e30))
         return fail(NRLSH_E_INVALID_ARG, "margin_param must be finite and >= 0");
+    int32_t partition = NRLSH_PARTITION_PERCENTILE;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, partition) + sizeof(int32_t)))
+        partition = opts->partition;
+    if (partition != NRLSH_PARTITION_PERCENTILE && partition != NRLSH_PARTITION_UNIFORM)
+        return fail(NRLSH_E_INVALID_ARG, "partition %d unknown", partition);
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
         const int dev = current_device();
@@ -792,6 +861,7 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         ix->storage = storage;
         ix->margin_mode = margin_mode;
         ix->margin_param = margin_param;
+        ix->partition = partition;
         ix->home = library_stream(dev);
         Timer tm(s);
         try {

@@ -182,22 +182,49 @@ __global__ __launch_bounds__(RS_THREADS) void k_rs_scatter(
 }
 
 // ---------------------------------------------------------------- partition
+// Sub-dataset of the item at sorted rank r: by percentile, floor(r m / n)
+// (Algorithm 1); with `bounds` (m - 1 increasing squared boundaries, the
+// uniform ranges of Section 5), the number of boundaries its key reaches.
+// Both are nondecreasing in r, so every sub-dataset is a run of ranks; the
+// last rank of a run writes the run's largest key and its end (subend,
+// sub-datasets without items keep what the caller set).
+__device__ __forceinline__ int64_t range_of(const double *__restrict__ bounds, int nb, double key)
+{
+    int lo = 0, hi = nb;  // number of bounds <= key
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (bounds[mid] <= key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
 __global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ skey,
                                                 const int32_t *__restrict__ sidx, int64_t n, int m,
+                                                const double *__restrict__ bounds,
                                                 int32_t *__restrict__ sid,
                                                 uint64_t *__restrict__ lkey,
                                                 int32_t *__restrict__ lval,
-                                                double *__restrict__ keymax)
+                                                double *__restrict__ keymax,
+                                                int32_t *__restrict__ subend)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
     const int32_t i = sidx[r];
-    const int64_t s = (r * (int64_t)m) / n;
+    const double key = __longlong_as_double((long long)skey[r]);
+    const int64_t s = bounds ? range_of(bounds, m - 1, key) : (r * (int64_t)m) / n;
     sid[i] = (int32_t)s;
     lkey[i] = (uint64_t)s;
     lval[r] = (int32_t)r;
-    // the last rank of each sub-dataset holds its largest key
-    if (r == n - 1 || ((r + 1) * (int64_t)m) / n != s) keymax[s] = __longlong_as_double((long long)skey[r]);
+    bool last = r == n - 1;
+    if (!last) {
+        const double kn = __longlong_as_double((long long)skey[r + 1]);
+        last = (bounds ? range_of(bounds, m - 1, kn) : ((r + 1) * (int64_t)m) / n) != s;
+    }
+    if (last) {
+        keymax[s] = key;
+        subend[s] = (int32_t)(r + 1);
+    }
 }
 
 // Stored copy: row p of Xl is item perm[p], zero-padded to dp floats; the
@@ -719,11 +746,11 @@ hipError_t radix_sort(uint64_t *ka, int32_t *va, uint64_t *kb, int32_t *vb, int6
 }
 
 hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sorted_idx, int64_t n,
-                                 int m, int32_t *sid, uint64_t *layout_key, int32_t *layout_val,
-                                 double *keymax, hipStream_t s)
+                                 int m, const double *bounds, int32_t *sid, uint64_t *layout_key,
+                                 int32_t *layout_val, double *keymax, int32_t *subend, hipStream_t s)
 {
     hipLaunchKernelGGL(k_assign, dim3(grid_for(n, 256)), dim3(256), 0, s, sorted_key, sorted_idx,
-                       n, m, sid, layout_key, layout_val, keymax);
+                       n, m, bounds, sid, layout_key, layout_val, keymax, subend);
     return hipGetLastError();
 }
 

@@ -232,6 +232,147 @@ __global__ __launch_bounds__(64) void k_scan_emit(const uint32_t *__restrict__ c
     }
 }
 
+// ---------------------------------------------------------------- chunked scans
+// Variants of the two passes for small query batches, where (query tiles) x
+// (sub-datasets) waves cannot fill the machine: a sub-dataset's stored items
+// are cut into chunks of `chunk` items, one wave per (tile, sub-dataset,
+// chunk) -- block b = (tile m + j) nch + c.  Pass 1 adds the chunk's
+// histogram into ghist (zeroed by the caller) with device atomics.  Pass 2
+// counts each query's probed items of the chunk, reserves room with one
+// atomic on the query's list length (counts, zeroed by the caller) and writes
+// them; the threshold bucket is cut at the stored position P* of its r*-th
+// item (k_tie_locate), so the probed set does not depend on the order of the
+// appends.
+template <int W>
+__global__ __launch_bounds__(64) void k_scan_hist_c(const uint32_t *__restrict__ codes_l,
+                                                    const int32_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ qcodes, int64_t nq,
+                                                    int m, int L, int chunk, int nch,
+                                                    uint32_t *__restrict__ ghist)
+{
+    extern __shared__ uint32_t hist[];  // (L+1) x 64, column = lane
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int c = (int)(b % nch);
+    const int j = (int)((b / nch) % m);
+    const int64_t tile = b / ((int64_t)nch * m);
+    const int64_t p0 = (int64_t)off[j] + (int64_t)c * chunk;
+    const int64_t p1 = min((int64_t)off[j + 1], p0 + chunk);
+    if (p0 >= p1) return;
+    const int64_t q = tile * 64 + lane;
+    uint32_t q0 = 0, q1 = 0;
+    if (q < nq) {
+        q0 = qcodes[q * W];
+        if (W == 2) q1 = qcodes[q * W + 1];
+    }
+    for (int h = 0; h <= L; ++h) hist[h * 64 + lane] = 0u;
+    int64_t p = p0;
+    for (; p + 16 <= p1; p += 16) {
+        uint32_t cc[16 * W];
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) cc[u] = codes_l[p * W + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            uint32_t h = (uint32_t)__popc(cc[u * W] ^ q0);
+            if (W == 2) h += (uint32_t)__popc(cc[u * W + 1] ^ q1);
+            __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    for (; p < p1; ++p) {
+        uint32_t h = (uint32_t)__popc(codes_l[p * W] ^ q0);
+        if (W == 2) h += (uint32_t)__popc(codes_l[p * W + 1] ^ q1);
+        __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    uint32_t *out = ghist + ((tile * m + j) * (int64_t)(L + 1)) * 64;
+    for (int h = 0; h <= L; ++h) {
+        const uint32_t v = hist[h * 64 + lane];
+        if (v) atomicAdd(&out[h * 64 + lane], v);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(64) void k_scan_emit_c(const uint32_t *__restrict__ codes_l,
+                                                    const int32_t *__restrict__ off,
+                                                    const uint32_t *__restrict__ qcodes, int64_t nq,
+                                                    int m, int64_t Tq, int chunk, int nch,
+                                                    const int32_t *__restrict__ ghthr,
+                                                    const int32_t *__restrict__ gtie,
+                                                    const int32_t *__restrict__ gpstar,
+                                                    int32_t *__restrict__ counts,
+                                                    int32_t *__restrict__ cand)
+{
+    const int lane = threadIdx.x;
+    const int64_t b = blockIdx.x;
+    const int c = (int)(b % nch);
+    const int j = (int)((b / nch) % m);
+    const int64_t tile = b / ((int64_t)nch * m);
+    const int64_t p0 = (int64_t)off[j] + (int64_t)c * chunk;
+    const int64_t p1 = min((int64_t)off[j + 1], p0 + chunk);
+    if (p0 >= p1) return;
+    const int64_t q = tile * 64 + lane;
+    const bool valid = q < nq;
+    int hthr = -1, htie = -1;
+    int32_t pstar = -1;
+    uint32_t q0 = 0, q1 = 0;
+    if (valid) {
+        const int32_t *tie = gtie + tile * 4 * 64;
+        hthr = ghthr[(tile * m + j) * 64 + lane];
+        if (tie[lane] == j) {
+            htie = tie[64 + lane];
+            pstar = gpstar[q];
+        }
+        q0 = qcodes[q * W];
+        if (W == 2) q1 = qcodes[q * W + 1];
+    }
+    if (__ballot(hthr >= 0 || htie >= 0) == 0ull) return;
+    int32_t cnt = 0;
+    int64_t p = p0;
+    for (; p + 16 <= p1; p += 16) {
+        uint32_t cc[16 * W];
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) cc[u] = codes_l[p * W + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int h = __popc(cc[u * W] ^ q0);
+            if (W == 2) h += __popc(cc[u * W + 1] ^ q1);
+            cnt += (h <= hthr || (h == htie && p + u <= pstar)) ? 1 : 0;
+        }
+    }
+    for (; p < p1; ++p) {
+        int h = __popc(codes_l[p * W] ^ q0);
+        if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+        cnt += (h <= hthr || (h == htie && p <= pstar)) ? 1 : 0;
+    }
+    if (__ballot(cnt > 0) == 0ull) return;
+    int64_t base = 0;
+    if (cnt > 0) base = atomicAdd(&counts[q], cnt);
+    const int64_t cap = cnt > 0 ? min((int64_t)cnt, Tq - base) : 0;  // never past the list
+    int32_t *out = cand + (valid ? q * Tq + base : 0);
+    int64_t w = 0;
+    for (p = p0; p + 16 <= p1; p += 16) {
+        uint32_t cc[16 * W];
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) cc[u] = codes_l[p * W + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int h = __popc(cc[u * W] ^ q0);
+            if (W == 2) h += __popc(cc[u * W + 1] ^ q1);
+            const bool e = h <= hthr || (h == htie && p + u <= pstar);
+            if (e && w < cap) out[w] = (int32_t)(p + u);
+            w += e ? 1 : 0;
+        }
+    }
+    for (; p < p1; ++p) {
+        int h = __popc(codes_l[p * W] ^ q0);
+        if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+        const bool e = h <= hthr || (h == htie && p <= pstar);
+        if (e && w < cap) out[w] = (int32_t)p;
+        w += e ? 1 : 0;
+    }
+}
+
 // ---------------------------------------------------------------- rerank
 // One wave per (query, slice of its probed list); the rows of 64 candidates
 // at a time are summed in FP64 (dev::ip64_rows_*), the running top-k kept by
@@ -243,9 +384,22 @@ using dev::WaveTopK;
 // LP = true: the rows come from the bfloat16 copy Xh.  ip~ = sum_t q_t x~_t in
 // FP64 satisfies |ip~ - ip| <= e = (2^-8 + 2^-40) ||q|| ||x|| (1 + 2^-20); the
 // wave keeps a top-k of the lower bounds ip~ - e and appends every item whose
-// upper bound ip~ + e reaches the current k-th lower bound to the query's
-// list (lists: nq x lcap, lcount: per query, may exceed lcap) -- a superset of
-// the exact top-k, re-ranked afterwards from the FP32 rows.
+// upper bound ip~ + e reaches the k-th lower bound to the query's list
+// (lists: nq x lcap, lcount: per query, may exceed lcap) -- a superset of
+// the exact top-k, re-ranked afterwards from the FP32 rows.  The slices of a
+// query share the largest k-th lower bound any of them has reached (gtheta,
+// order-preserving encoding, 0 = none yet): the k items behind it have exact
+// inner products at least that large, so it bounds the query's k-th best.
+__device__ __forceinline__ uint64_t order_key(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(uint64_t e)
+{
+    return __longlong_as_double((long long)((e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e));
+}
+
 template <int S, bool LP>
 __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                const int32_t *__restrict__ perm,
@@ -260,7 +414,8 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                const uint16_t *__restrict__ Xh,
                                                const double *__restrict__ key_l, int lcap,
                                                int32_t *__restrict__ lcount,
-                                               int32_t *__restrict__ lists)
+                                               int32_t *__restrict__ lists,
+                                               unsigned long long *__restrict__ gtheta)
 {
     __shared__ float tile[64 * RR_STRIDE];
     const int lane = threadIdx.x;
@@ -294,7 +449,12 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
         if (LP) {
             const double e = (0x1p-8 + 0x1p-40) * qn * __builtin_sqrt(valid ? key_l[p] : 0.0) * (1.0 + 0x1p-20);
             top.offer(acc - e, id, valid, lane);
-            const bool keep = valid && !(acc + e < top.th_v);
+            double th = top.th_v;
+            if (th > -INFINITY && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(th));
+            const unsigned long long ge =
+                __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ge != 0ull) th = fmax(th, order_value(ge));
+            const bool keep = valid && !(acc + e < th);
             const uint64_t kb = __ballot(keep);
             if (kb != 0ull) {
                 const int leader = __ffsll((long long)kb) - 1;
@@ -701,15 +861,18 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     }
     __syncthreads();
 
+    // NB column blocks of 16 items per wave iteration (bf16x3 keeps 2: its
+    // hi and lo operands double the registers)
+    constexpr int NB = X3 ? 2 : 4, IW = 16 * NB;
     const int r16 = lane & 15, g = lane >> 4;
     const bool all = all_s != 0;
-    for (int p0 = pbeg + wave * 64; p0 < pend; p0 += 256) {
-        int32_t pit[4];
-        uint32_t cw[4][W];
-        float xn[4];
-        bool iv[4];
+    for (int p0 = pbeg + wave * IW; p0 < pend; p0 += 4 * IW) {
+        int32_t pit[NB];
+        uint32_t cw[NB][W];
+        float xn[NB];
+        bool iv[NB];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < NB; ++ib) {
             pit[ib] = p0 + 16 * ib + r16;
             iv[ib] = pit[ib] < pend;
             const int64_t pp = iv[ib] ? pit[ib] : pbeg;
@@ -717,40 +880,40 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
             for (int w = 0; w < W; ++w) cw[ib][w] = all ? 0u : codes_l[pp * W + w];
             xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
         }
-        floatx4 acc[4][4];
+        floatx4 acc[4][NB];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-            for (int ib = 0; ib < 4; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+            for (int ib = 0; ib < NB; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
         // item operands of step kk: 8 coordinates of one row per lane.  The
         // loads are unconditional: an invalid item reads a valid row (its
         // results are never used), and coordinates past dp read the next
         // row or the zeroed tail pad of the array -- finite values that meet
         // the zero columns of the query tile.
-        const uint16_t *rh[4];
-        const uint16_t *rl[4];
+        const uint16_t *rh[NB];
+        const uint16_t *rl[NB];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < NB; ++ib) {
             const int64_t row = iv[ib] ? pit[ib] : pbeg;
             rh[ib] = Xh + row * dp + 8 * g;
             rl[ib] = X3 ? Xlo + row * dp + 8 * g : nullptr;
         }
-        u16x8 bh[4], bl[4];
+        u16x8 bh[NB], bl[NB];
 #pragma unroll
-        for (int ib = 0; ib < 4; ++ib) {
+        for (int ib = 0; ib < NB; ++ib) {
             bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib]);
             bl[ib] = X3 ? *reinterpret_cast<const u16x8 *>(rl[ib]) : z8;
         }
         for (int kk = 0; kk < dp; kk += 32) {
-            u16x8 ch[4], cl[4];
+            u16x8 ch[NB], cl[NB];
 #pragma unroll
-            for (int ib = 0; ib < 4; ++ib) {
+            for (int ib = 0; ib < NB; ++ib) {
                 ch[ib] = bh[ib];
                 cl[ib] = bl[ib];
             }
             if (kk + 32 < dp) {  // prefetch the next step
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
+                for (int ib = 0; ib < NB; ++ib) {
                     bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib] + kk + 32);
                     if (X3) bl[ib] = *reinterpret_cast<const u16x8 *>(rl[ib] + kk + 32);
                 }
@@ -766,7 +929,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
 #pragma unroll
             for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
+                for (int ib = 0; ib < NB; ++ib) {
                     acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
                         as_bf16x8(ah[qb]), as_bf16x8(ch[ib]), acc[qb][ib], 0, 0, 0);
                     if (X3) {
@@ -784,9 +947,11 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                 const int ql = 16 * qb + 4 * g + v;
                 const int hthr = hthr_s[ql], htie = htie_s[ql];
                 const float th = th_s[ql], qn = qn_s[ql];
-                float gmax[2] = {-INFINITY, -INFINITY};  // MAXMODE: groups of items 0-31, 32-63
+                float gmax[NB / 2];  // MAXMODE: per 32-item group of this iteration
 #pragma unroll
-                for (int ib = 0; ib < 4; ++ib) {
+                for (int hg = 0; hg < NB / 2; ++hg) gmax[hg] = -INFINITY;
+#pragma unroll
+                for (int ib = 0; ib < NB; ++ib) {
                     bool probed = iv[ib];
                     if (!all) {
                         int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
@@ -806,7 +971,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                 if (MAXMODE) {
                     // largest lower bound of each 32-item group for query ql
 #pragma unroll
-                    for (int hg = 0; hg < 2; ++hg) {
+                    for (int hg = 0; hg < NB / 2; ++hg) {
 #pragma unroll
                         for (int o = 1; o < 16; o <<= 1) gmax[hg] = fmaxf(gmax[hg], __shfl_xor(gmax[hg], o, 64));
                         if (r16 == 0 && q0 + ql < nq && p0 + 32 * hg < pend)
@@ -904,6 +1069,36 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
     else
         hipLaunchKernelGGL(k_scan_emit<2>, grid, dim3(64), 0, s, codes_l, off, qcodes, nq, sh.m,
                            sh.L, sh.Tq, gbase, ghthr, gtie, cand);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_hist_c(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                              int64_t nq, const QueryShape &sh, int chunk, int nch, uint32_t *ghist,
+                              hipStream_t s)
+{
+    const int64_t blocks = (int64_t)ceil_div(nq, 64) * sh.m * nch;
+    const size_t lds = (size_t)(sh.L + 1) * 64 * sizeof(uint32_t);
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_scan_hist_c<1>, dim3((unsigned)blocks), dim3(64), lds, s, codes_l, off,
+                           qcodes, nq, sh.m, sh.L, chunk, nch, ghist);
+    else
+        hipLaunchKernelGGL(k_scan_hist_c<2>, dim3((unsigned)blocks), dim3(64), lds, s, codes_l, off,
+                           qcodes, nq, sh.m, sh.L, chunk, nch, ghist);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                              int64_t nq, const QueryShape &sh, int chunk, int nch,
+                              const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar,
+                              int32_t *counts, int32_t *cand, hipStream_t s)
+{
+    const int64_t blocks = (int64_t)ceil_div(nq, 64) * sh.m * nch;
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_scan_emit_c<1>, dim3((unsigned)blocks), dim3(64), 0, s, codes_l, off,
+                           qcodes, nq, sh.m, sh.Tq, chunk, nch, ghthr, gtie, gpstar, counts, cand);
+    else
+        hipLaunchKernelGGL(k_scan_emit_c<2>, dim3((unsigned)blocks), dim3(64), 0, s, codes_l, off,
+                           qcodes, nq, sh.m, sh.Tq, chunk, nch, ghthr, gtie, gpstar, counts, cand);
     return hipGetLastError();
 }
 
@@ -1084,7 +1279,7 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     do {                                                                                         \
         hipLaunchKernelGGL((k_rerank<SS, false>), grid, block, 0, s, Xl, perm, Q, sh.n, sh.d,    \
                            sh.dp, sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips,    \
-                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr);               \
+                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr, nullptr);      \
         if (nsplit > 1)                                                                          \
             hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
                                nsplit, sh.k, out_ids, out_ips);                                  \
@@ -1100,7 +1295,8 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
 
 hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
-                            int nsplit, int lcap, int32_t *lcount, int32_t *lists, hipStream_t s)
+                            int nsplit, int lcap, int32_t *lcount, int32_t *lists,
+                            unsigned long long *gtheta, hipStream_t s)
 {
     const int S = (sh.k + 63) / 64;
     int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
@@ -1109,7 +1305,7 @@ hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32
 #define NRLSH_RERANK_LP(SS)                                                                       \
     hipLaunchKernelGGL((k_rerank<SS, true>), grid, block, 0, s, nullptr, perm, Q, sh.n, sh.d, sh.dp, \
                        sh.Tq, sh.k, cand, nullptr, nsplit, slice, nullptr, nullptr, nullptr,      \
-                       nullptr, Xh, key_l, lcap, lcount, lists)
+                       nullptr, Xh, key_l, lcap, lcount, lists, gtheta)
     if (S <= 1) NRLSH_RERANK_LP(1);
     else if (S <= 2) NRLSH_RERANK_LP(2);
     else if (S <= 4) NRLSH_RERANK_LP(4);

@@ -44,11 +44,14 @@ size_t radix_sort_tmp_bytes(int64_t n);
 hipError_t radix_sort(uint64_t *ka, int32_t *va, uint64_t *kb, int32_t *vb, int64_t n, int nbits,
                       void *tmp, bool *result_in_b, hipStream_t s);
 
-// Sub-dataset of every item from its rank (s = floor(rank m / n)), the
-// largest key of each sub-dataset, and (sid, index) pairs for the layout sort.
+// Sub-dataset of every item from its rank (s = floor(rank m / n)) or, with
+// bounds (m - 1 increasing squared boundaries), from the uniform norm ranges;
+// the largest key of each sub-dataset and the end rank of its run (subend;
+// entries of sub-datasets without items are left as the caller set them),
+// and (sid, index) pairs for the layout sort.
 hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sorted_idx, int64_t n,
-                                 int m, int32_t *sid, uint64_t *layout_key, int32_t *layout_val,
-                                 double *keymax, hipStream_t s);
+                                 int m, const double *bounds, int32_t *sid, uint64_t *layout_key,
+                                 int32_t *layout_val, double *keymax, int32_t *subend, hipStream_t s);
 
 // Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
 // key and sub-dataset of each stored row, plus its bfloat16 hi / lo split.
@@ -120,10 +123,25 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
 
 // Precision form of the re-rank: bounds from the bfloat16 copy Xh, appends to
 // lists (nq x lcap, lcount zeroed by the caller) every probed item that may
-// still belong to the exact top-k.
+// still belong to the exact top-k.  gtheta: nq words zeroed by the caller,
+// the k-th lower bound shared by the slices of each query.
 hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
-                            int nsplit, int lcap, int32_t *lcount, int32_t *lists, hipStream_t s);
+                            int nsplit, int lcap, int32_t *lcount, int32_t *lists,
+                            unsigned long long *gtheta, hipStream_t s);
+
+// Chunked passes for small query batches: one wave per (64-query tile,
+// sub-dataset, chunk of `chunk` stored items), nch chunks per sub-dataset.
+// Pass 1 adds into ghist (zeroed by the caller); pass 2 appends each query's
+// probed items to its list (counts zeroed by the caller; order unspecified),
+// cutting the threshold bucket at gpstar (launch_tie_locate).
+hipError_t launch_scan_hist_c(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                              int64_t nq, const QueryShape &sh, int chunk, int nch, uint32_t *ghist,
+                              hipStream_t s);
+hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
+                              int64_t nq, const QueryShape &sh, int chunk, int nch,
+                              const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar,
+                              int32_t *counts, int32_t *cand, hipStream_t s);
 
 // Stored position of the r*-th item of each query's threshold bucket (-1 if none).
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,

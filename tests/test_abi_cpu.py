@@ -63,6 +63,14 @@ def test_build_rejects_bad_eps():
         assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
 
 
+def test_build_rejects_unknown_partition():
+    X = np.ones((10, 4), np.float32)
+    h = C.c_void_p()
+    opts = _lib.BuildOpts(C.sizeof(_lib.BuildOpts), 0, None, 0.0, 0, 0, 0.0, 2)
+    assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
+    assert "partition" in nr.nrlsh_last_error()
+
+
 def test_query_rejects_bad_arguments():
     L = nr.lib()
     Q = np.ones((2, 4), np.float32)

@@ -229,3 +229,68 @@ def test_device_pointer_path_matches_host_path():
         torch.cuda.synchronize()
         assert np.array_equal(idd.cpu().numpy(), ih)
         assert np.array_equal(ipd.cpu().numpy(), ph)
+
+
+UNIFORM_CASES = [
+    # (n, d, m, L, kind, T)
+    (6000, 40, 16, 32, "lognormal", 600),
+    (5000, 64, 32, 64, "pareto", 5000),   # heavy tail: many empty ranges
+    (3000, 17, 1, 20, "lognormal", 300),
+    (4096, 128, 7, 31, "lowrank", 1000),
+]
+
+
+@pytest.mark.parametrize("case", UNIFORM_CASES, ids=lambda c: "n%d_d%d_m%d_L%d_%s" % c[:5])
+def test_parity_uniform_partition(case):
+    """Section 5's uniform norm ranges: partition (including empty ranges),
+    codes, rank table and query results equal the oracle's."""
+    n, d, m, L, kind, T = case
+    say(f"case uniform n={n} d={d} m={m} L={L} {kind}")
+    kw = {"alpha": 2.5} if kind == "pareto" else {"sigma": 1.0} if kind == "lognormal" else {}
+    X = make_items(kind, n, d, seed=n + m, **kw)
+    Q = make_queries(90, d, seed=n + 1)
+    oix = orc.OracleIndex(X, m, L, seed=23, threads=8, partition="uniform")
+    with nr.nrlsh_build(X, m, L, 23, partition="uniform") as gix:
+        sid, keymax, U = gix.partition()
+        say(f"  empty ranges: {int((np.bincount(oix.sid, minlength=m) == 0).sum())} of {m}")
+        check_build(gix, oix, "uniform")
+        check_query(gix, oix, Q, 10, T, "uniform")
+        for mode in ("screen", "gather"):
+            ids, ips = nr.nrlsh_query(gix, Q, 10, n, rerank=mode)
+            oids, oips = oix.query(Q, 10, n, threads=8)
+            assert np.array_equal(ids, oids), mode
+
+
+def test_uniform_partition_equal_norms():
+    """Every item has the same norm: all of them fall in the last range."""
+    say("case uniform equal norms")
+    X = make_queries(500, 12, seed=3) * 2.0  # unit rows scaled by 2
+    oix = orc.OracleIndex(X, 5, 16, 9, threads=4, partition="uniform")
+    with nr.nrlsh_build(X, 5, 16, 9, partition="uniform") as gix:
+        check_build(gix, oix, "equal norms")
+        check_query(gix, oix, make_queries(20, 12, seed=4), 5, 100, "equal norms")
+
+
+@pytest.mark.parametrize("n,d,m,L,nq,k,T", [
+    (30011, 75, 4, 32, 70, 10, 3001),     # 2 tiles x 4 sub-datasets: chunked scans
+    (40000, 33, 2, 48, 5, 100, 17777),    # W = 2, one tile, threshold bucket cut across chunks
+    (25000, 64, 3, 16, 130, 10, 25000),   # T = n
+])
+def test_parity_small_batch_chunked_scan(n, d, m, L, nq, k, T):
+    """Small batches over large sub-datasets take the chunked scans (appends
+    in any order, threshold bucket cut by stored position); the probed set
+    and the results equal the oracle's, also with the bfloat16 re-rank copy."""
+    say(f"case chunked scan n={n} d={d} m={m} L={L} nq={nq} k={k} T={T}")
+    X = make_items("lognormal", n, d, seed=n + 11, sigma=0.9)
+    Q = make_queries(nq, d, seed=n + 12)
+    oix = orc.OracleIndex(X, m, L, seed=41, threads=8)
+    oids, oips = oix.query(Q, k, T, threads=8)
+    with nr.nrlsh_build(X, m, L, 41) as gix:
+        for storage in ("fp32", "bf16"):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage=storage)
+            assert np.array_equal(ids, oids), storage
+            assert np.array_equal(ips, oips.astype(np.float32)), storage
+            if storage == "bf16":
+                st = nr.nrlsh_get_query_stats()
+                say(f"  bf16 lists: total {st['lp_kept_total']} max {st['lp_kept_max']} "
+                    f"fallbacks {st['lp_fallbacks']}")

@@ -133,6 +133,67 @@ def test_partition_invariants(n, m):
         assert np.array_equal(np.sort(rank[sid == j]), np.arange(lo, hi))
 
 
+# ------------------------------------------------------------- uniform partition
+def _integer_norm_items(norms):
+    """Items whose 2-norms are the given integers: (3k, 4k) has norm 5k, so
+    every key (a sum of integer squares) is exact."""
+    X = np.zeros((len(norms), 2), np.float32)
+    X[:, 0] = np.asarray(norms, np.float32)
+    return X
+
+
+def test_uniform_partition_hand_worked():
+    """Section 5's alternative: the norm domain [1, 10] cut into 3 ranges of
+    width 3 gives boundaries 4 and 7; an item exactly on a boundary belongs
+    to the upper range.  Percentile partitioning of the same 10 items gives
+    sizes 4, 3, 3 instead."""
+    X = _integer_norm_items(range(1, 11))
+    ix = orc.OracleIndex(X, 3, 8, 1, partition="uniform")
+    assert ix.sid.tolist() == [0, 0, 0, 1, 1, 1, 2, 2, 2, 2]
+    assert ix.keymax.tolist() == [9.0, 36.0, 100.0]
+    assert ix.U.tolist() == [3.0, 6.0, 10.0]
+    px = orc.OracleIndex(X, 3, 8, 1)
+    assert np.bincount(px.sid).tolist() == [4, 3, 3]
+
+
+def test_uniform_partition_empty_and_degenerate_ranges():
+    # norms {1, 2, 9, 10} with m = 3: ranges [1,4) [4,7) [7,10] -> sizes 2, 0, 2
+    ix = orc.OracleIndex(_integer_norm_items([1, 2, 9, 10]), 3, 8, 1, partition="uniform")
+    assert ix.sid.tolist() == [0, 0, 2, 2]
+    assert ix.keymax.tolist() == [4.0, 0.0, 100.0] and ix.U[1] == 0.0
+    # all norms equal: zero width, every boundary equals the norm -> last range
+    ix = orc.OracleIndex(_integer_norm_items([5] * 7), 4, 8, 1, partition="uniform")
+    assert ix.sid.tolist() == [3] * 7
+    # m = 1 is the whole dataset, as with percentiles
+    X = make_items("lognormal", 300, 7, seed=5, sigma=0.8)
+    a = orc.OracleIndex(X, 1, 16, 2, partition="uniform")
+    b = orc.OracleIndex(X, 1, 16, 2)
+    assert np.array_equal(a.sid, b.sid) and np.array_equal(a.codes, b.codes)
+
+
+@pytest.mark.parametrize("m", [2, 7, 32])
+def test_uniform_partition_ranges_have_equal_width(m):
+    """Every item lies in its range [nmin + j w, nmin + (j+1) w] of the norm
+    domain (checked on norms computed independently with numpy), ranges are
+    ordered, and keymax_j is the largest key of range j."""
+    X = make_items("lognormal", 2000, 11, seed=m, sigma=1.0)
+    ix = orc.OracleIndex(X, m, 16, 3, partition="uniform")
+    norms = np.linalg.norm(X.astype(np.float64), axis=1)
+    nmin, nmax = norms.min(), norms.max()
+    w = (nmax - nmin) / m
+    tol = 1e-12 * nmax
+    for j in range(m):
+        sel = ix.sid == j
+        if sel.any():
+            assert norms[sel].min() >= nmin + j * w - tol
+            assert norms[sel].max() <= nmin + (j + 1) * w + tol
+            assert ix.keymax[j] == ix.key[sel].max()
+        else:
+            assert ix.keymax[j] == 0.0
+    order = np.argsort(norms, kind="stable")
+    assert np.all(np.diff(ix.sid[order]) >= 0)
+
+
 # ------------------------------------------------------------- transform / hash
 def test_transform_unit_norm_and_inner_product():
     n, d, m = 400, 33, 5
@@ -462,3 +523,114 @@ def test_build_drivers_consistent_and_thread_invariant():
     assert np.array_equal(i1, i2) and np.array_equal(p1, p2)
     # codes use only the low L bits
     assert np.all(a.codes < (1 << 32))
+
+
+# ------------------------------------------- independent projections per subset
+def _per_subset_case(n=500, d=10, m=5, L=12, seed=81):
+    X = make_items("lognormal", n, d, seed=seed, sigma=1.0)
+    Q = make_queries(8, d, seed=seed + 1)
+    ix = orc.OracleIndex(X, m, L, seed=seed + 2, projections="per_subset")
+    return X, Q, ix
+
+
+def test_per_subset_projection_layout():
+    """Sub-dataset j draws rows j L .. j L + L - 1 of one m L-row projection, so
+    sub-dataset 0 sees the shared projection and every block is fresh."""
+    X, Q, ix = _per_subset_case()
+    m, L, d = ix.m, ix.L, ix.d
+    assert ix.A.shape == (m * L, d + 1)
+    assert np.array_equal(ix.A, orc.projection(ix.seed, m * L, d))
+    assert np.array_equal(ix.A[:L], orc.projection(ix.seed, L, d))
+    for j in range(1, m):
+        assert not np.array_equal(ix.A[j * L:(j + 1) * L], ix.A[:L])
+
+
+def test_per_subset_item_codes_use_own_rows():
+    """An item of sub-dataset j hashes exactly as the shared-projection routine
+    does with A_j; with m >= 2 these codes differ from the ones A_0 gives, so a
+    dropped sub-dataset offset fails here."""
+    X, Q, ix = _per_subset_case()
+    m, L = ix.m, ix.L
+    differs = 0
+    for j in range(m):
+        Aj = ix.A[j * L:(j + 1) * L]
+        own = orc.item_codes(X, Aj, ix.key, ix.sid, ix.keymax, ix.U)
+        sel = ix.sid == j
+        assert np.array_equal(ix.codes[sel], own[sel]), j
+        if j:
+            base = orc.item_codes(X, ix.A[:L], ix.key, ix.sid, ix.keymax, ix.U)
+            differs += int(np.count_nonzero(base[sel] != own[sel]))
+    assert differs > 0
+    assert np.array_equal(
+        orc.item_codes(X, ix.A, ix.key, ix.sid, ix.keymax, ix.U, per_subset=True), ix.codes)
+
+
+def test_per_subset_query_codes_basis():
+    X, Q, ix = _per_subset_case()
+    m, L, d = ix.m, ix.L, ix.d
+    for q in Q:
+        qc = ix.query_code(q)
+        assert qc.shape == (m,)
+        for j in range(m):
+            assert int(qc[j]) == orc.query_code(ix.A[j * L:(j + 1) * L], q)
+    for t in range(d):
+        e = np.zeros(d, np.float32)
+        e[t] = 1.0
+        qc = ix.query_code(e)
+        for j in range(m):
+            rows = ix.A[j * L:(j + 1) * L, t]
+            assert int(qc[j]) == sum(1 << r for r in range(L) if rows[r] > 0)
+
+
+def test_per_subset_single_subset_equals_shared():
+    X = make_items("pareto", 600, 12, seed=91, alpha=2.5)
+    Q = make_queries(10, 12, seed=92)
+    a = orc.OracleIndex(X, 1, 20, seed=93)
+    b = orc.OracleIndex(X, 1, 20, seed=93, projections="per_subset")
+    assert np.array_equal(a.A, b.A) and np.array_equal(a.codes, b.codes)
+    for T in (1, 50, 600):
+        ia, pa = a.query(Q, 10, T)
+        ib, pb = b.query(Q, 10, T)
+        assert np.array_equal(ia, ib) and np.array_equal(pa, pb)
+
+
+def _bucket_walk_per_subset(ix, q, T):
+    """Best-first walk over (U_j, l) where l counts agreement with the query
+    code of the item's own sub-dataset."""
+    qc = ix.query_code(q)
+    same = np.array([ix.L - bin(int(c) ^ int(qc[s])).count("1") for c, s in zip(ix.codes, ix.sid)])
+    pairs = sorted(((ix.R[j, l], j, l) for j in range(ix.m) for l in range(ix.L + 1)))
+    out = []
+    for _, j, l in pairs:
+        for i in np.flatnonzero((ix.sid == j) & (same == l)):
+            if len(out) == min(T, ix.n):
+                return out
+            out.append(int(i))
+    return out
+
+
+@pytest.mark.parametrize("m,L", [(4, 8), (9, 16)])
+def test_per_subset_candidates_equal_bucket_walk(m, L):
+    X = make_items("lognormal", 300, 10, seed=m * L + 1, sigma=1.0)
+    Q = make_queries(6, 10, seed=m + L + 1)
+    ix = orc.OracleIndex(X, m, L, seed=22, projections="per_subset")
+    shared = orc.OracleIndex(X, m, L, seed=22)
+    moved = 0
+    for q in Q:
+        for T in (1, 9, 50, 299, 300, 301):
+            cand, ls = ix.candidates(q, T)
+            assert sorted(cand.tolist()) == sorted(_bucket_walk_per_subset(ix, q, T))
+            qc = ix.query_code(q)
+            for c, l in zip(cand, ls):
+                assert l == L - bin(int(ix.codes[c]) ^ int(qc[ix.sid[c]])).count("1")
+            moved += set(cand.tolist()) != set(shared.candidates(q, T)[0].tolist())
+    assert moved > 0
+
+
+def test_per_subset_full_budget_is_exact_mips():
+    X = make_items("lognormal", 150, 7, seed=95, sigma=0.8)
+    Q = make_queries(6, 7, seed=96)
+    ix = orc.OracleIndex(X, 6, 16, seed=97, projections="per_subset")
+    ids, _ = ix.query(Q, k=5, T=150)
+    for qi, q in enumerate(Q):
+        assert ids[qi].tolist() == _exact_topk(X, q, 5)
