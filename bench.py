@@ -214,10 +214,11 @@ def main():
                     help="queries per nrlsh_query call (0: all in one call)")
     ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
     ap.add_argument("--variants",
-                    default="eps:0.1,eps:0.2,eps:0.3,uniform,bits,uniform+bits,m:8,m:128",
+                    default="eps:0.1,eps:0.2,eps:0.3,uniform,bits,uniform+bits,m:8,m:128,per_subset",
                     help="labelled variants timed after the headline, each at its own recall-0.9 "
                          "budget: eps:E (adjusted metric), uniform (norm ranges), bits (paper's "
-                         "code-bit accounting), m:M (sub-datasets); combine with '+'; '' for none")
+                         "code-bit accounting), m:M (sub-datasets), per_subset (independent "
+                         "projections per sub-dataset); combine with '+'; '' for none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-MiB buffer 3 times before the steps (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -361,11 +362,13 @@ def main():
     # recall-0.9 budget: the adjusted metric s_hat = U_j cos[pi (1 - eps)(1 - l/L)]
     # (Section 3.3), uniform norm ranges (Section 5), the paper's code-bit
     # accounting (ceil(log2 m) of the L bits spent on the sub-dataset id,
-    # Section 4) and other sub-dataset counts (Figure 3b's sweep)
+    # Section 4), other sub-dataset counts (Figure 3b's sweep) and
+    # independent projections per sub-dataset (Algorithm 1 read literally)
     variants = []
     spec = [v.strip() for v in args.variants.split(",") if v.strip()] if not args.no_sweep else []
     for v in spec:
-        cfg = {"label": v, "eps": 0.0, "partition": "percentile", "m": w.m, "L": w.L}
+        cfg = {"label": v, "eps": 0.0, "partition": "percentile", "m": w.m, "L": w.L,
+               "projections": "shared"}
         for part in v.split("+"):
             if part.startswith("eps:"):
                 cfg["eps"] = float(part[4:])
@@ -373,12 +376,18 @@ def main():
                 cfg["partition"] = "uniform"
             elif part.startswith("m:"):
                 cfg["m"] = int(part[2:])
+            elif part == "per_subset":
+                cfg["projections"] = "per_subset"
             elif part != "bits":
                 ap.error(f"unknown variant {v}")
         if "bits" in v.split("+"):  # after m is known
             cfg["L"] = w.L - (math.ceil(math.log2(cfg["m"])) if cfg["m"] > 1 else 0)
+        if cfg["projections"] != "shared" and args.hash_storage != "fp32":
+            log(f"variant {v} skipped: per-subset projections need the FP32 hash")
+            continue
         ex = nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
-                            margin=margin, eps=cfg["eps"], partition=cfg["partition"])
+                            margin=margin, eps=cfg["eps"], partition=cfg["partition"],
+                            projections=cfg["projections"])
         vcurve, vT = {}, None
         for T in budgets_sweep:
             ids, _ = nr.nrlsh_query(ex, Qd[:nrec], w.k, T)
@@ -391,7 +400,8 @@ def main():
 
         def vstep(T, cfg=cfg):
             with nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
-                                margin=margin, eps=cfg["eps"], partition=cfg["partition"]) as sx:
+                                margin=margin, eps=cfg["eps"], partition=cfg["partition"],
+                                projections=cfg["projections"]) as sx:
                 nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf), rerank=args.rerank,
                                rerank_storage=args.rerank_storage)
         vstep(vT)

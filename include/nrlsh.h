@@ -107,6 +107,18 @@ typedef enum { NRLSH_MARGIN_RIGOROUS = 0, NRLSH_MARGIN_SCALED = 1 } nrlsh_margin
  *               key is its FP64 squared norm.  Ranges may be empty (U_j = 0). */
 typedef enum { NRLSH_PARTITION_PERCENTILE = 0, NRLSH_PARTITION_UNIFORM = 1 } nrlsh_partition;
 
+/* Which hash functions the sub-datasets use (Algorithm 1 and Section 3.2
+ * build one SimpleLSH index per sub-dataset, independently of the others).
+ *   SHARED:     every sub-dataset hashes with the same L x (d+1) matrix A, so
+ *               a query has one code (default).
+ *   PER_SUBSET: sub-dataset j hashes with its own rows j L .. j L + L - 1 of
+ *               an (m L) x (d+1) matrix drawn exactly as A above (entry (r, c)
+ *               from counter t = r (d+1) + c), so rows 0 .. L-1 equal the
+ *               shared A; a query has m codes, and its code for sub-dataset j
+ *               decides the number of same bits l of j's items.  Only with
+ *               hash_storage FP32; not accepted by the batching form. */
+typedef enum { NRLSH_PROJECTIONS_SHARED = 0, NRLSH_PROJECTIONS_PER_SUBSET = 1 } nrlsh_projections;
+
 typedef struct nrlsh_build_opts {
     int32_t struct_size;  /* sizeof(nrlsh_build_opts) */
     int32_t device_ptrs;  /* 1: items is a device pointer */
@@ -117,7 +129,7 @@ typedef struct nrlsh_build_opts {
     int32_t margin_mode;  /* nrlsh_margin_mode */
     double margin_param;  /* SCALED: relative margin (>= 0) */
     int32_t partition;    /* nrlsh_partition (read when struct_size covers it) */
-    int32_t pad;
+    int32_t projections;  /* nrlsh_projections (read when struct_size covers it) */
 } nrlsh_build_opts;
 
 nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
@@ -284,7 +296,11 @@ const char *nrlsh_last_error(void);
 nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int32_t *m,
                               int32_t *L, int32_t *dp);
 
-/* A: L x (d+1) float32, row r = hash function r (Eq. 4). */
+/* sets: number of L-row projection blocks, 1 (SHARED) or m (PER_SUBSET). */
+nrlsh_status nrlsh_get_projection_sets(const nrlsh_index *ix, int32_t *sets);
+
+/* A: (sets L) x (d+1) float32, row r = hash function r (Eq. 4); block j
+ * (rows j L .. j L + L - 1) belongs to sub-dataset j when sets = m. */
 nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A);
 
 /* key: n float64 squared 2-norms in original order (Algorithm 1 ranking key). */
@@ -321,7 +337,8 @@ nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st)
 nrlsh_status nrlsh_get_hash_copy(const nrlsh_index *ix, void *data, float *scales,
                                  int32_t *storage);
 
-/* Query codes: nq uint64 (host in, host out), bit r = [A_r[:d] . q > 0]. */
+/* Query codes: nq x sets uint64 (host in, host out), bit r of code (q, j) =
+ * [A_{j L + r}[:d] . q > 0] (sets: nrlsh_get_projection_sets). */
 nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,
                                uint64_t *codes);
 

@@ -32,10 +32,11 @@ class BuildOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32),
                 ("stream", C.c_void_p), ("eps", C.c_double), ("hash_storage", C.c_int32),
                 ("margin_mode", C.c_int32), ("margin_param", C.c_double),
-                ("partition", C.c_int32), ("pad", C.c_int32)]
+                ("partition", C.c_int32), ("projections", C.c_int32)]
 
 
 PARTITIONS = {"percentile": 0, "uniform": 1}
+PROJECTIONS = {"shared": 0, "per_subset": 1}
 
 
 STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
@@ -116,6 +117,8 @@ def lib():
             f.restype = st
         L.nrlsh_get_partition.argtypes = [P, P, P, P]
         L.nrlsh_get_partition.restype = st
+        L.nrlsh_get_projection_sets.argtypes = [P, C.POINTER(I32)]
+        L.nrlsh_get_projection_sets.restype = st
         L.nrlsh_get_layout.argtypes = [P, P, P]
         L.nrlsh_get_layout.restype = st
         L.nrlsh_get_hash_copy.argtypes = [P, P, P, C.POINTER(I32)]
@@ -195,6 +198,9 @@ class Index:
         _check(lib().nrlsh_index_info(self._h, C.byref(n), C.byref(d), C.byref(m), C.byref(L),
                                       C.byref(dp)))
         self.n, self.d, self.m, self.L, self.dp = n.value, d.value, m.value, L.value, dp.value
+        sets = I32()
+        _check(lib().nrlsh_get_projection_sets(self._h, C.byref(sets)))
+        self.qsets = sets.value  # 1: shared projections; m: one block per sub-dataset
 
     @property
     def handle(self):
@@ -221,7 +227,8 @@ class Index:
 
     # -------------------------------------------------- inspection
     def projection(self) -> np.ndarray:
-        A = np.empty((self.L, self.d + 1), dtype=np.float32)
+        """(qsets L) x (d+1); block j serves sub-dataset j when qsets = m."""
+        A = np.empty((self.qsets * self.L, self.d + 1), dtype=np.float32)
         _check(lib().nrlsh_get_projection(self.handle, A.ctypes.data))
         return A
 
@@ -277,10 +284,11 @@ class Index:
         return name, buf[: n * dp].reshape(n, dp), sc
 
     def query_codes(self, queries) -> np.ndarray:
+        """(nq,) codes, or (nq, m) with a projection block per sub-dataset."""
         Q = _host_f32(queries)
-        out = np.empty(Q.shape[0], dtype=np.uint64)
+        out = np.empty(Q.shape[0] * self.qsets, dtype=np.uint64)
         _check(lib().nrlsh_query_codes(self.handle, Q.ctypes.data, Q.shape[0], out.ctypes.data))
-        return out
+        return out if self.qsets == 1 else out.reshape(Q.shape[0], self.qsets)
 
     def query_candidates(self, queries, probe_budget: int) -> np.ndarray:
         Q = _host_f32(queries)
@@ -293,28 +301,33 @@ class Index:
 
 # ------------------------------------------------------------------ C-ABI names
 def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None,
-                hash_storage: str = "fp32", margin="rigorous", partition: str = "percentile") -> Index:
+                hash_storage: str = "fp32", margin="rigorous", partition: str = "percentile",
+                projections: str = "shared") -> Index:
     """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
     tensor (n, d) float32 (device pointer, torch's current stream).
     ``hash_storage`` ("fp32", "bf16", "fp8") selects the precision form of the
     hash GEMM; ``margin`` is "rigorous" or a relative margin (float);
-    ``partition`` is "percentile" (Algorithm 1) or "uniform" (Section 5)."""
+    ``partition`` is "percentile" (Algorithm 1) or "uniform" (Section 5);
+    ``projections`` is "shared" (one matrix for all sub-datasets) or
+    "per_subset" (an independent block per sub-dataset)."""
     h = P()
     st = STORAGES[hash_storage]
     part = PARTITIONS[partition]
+    proj = PROJECTIONS[projections]
     mmode, mparam = (0, 0.0) if margin == "rigorous" else (1, float(margin))
     if _is_torch_device(items):
         if items.dtype.__str__() != "torch.float32" or items.dim() != 2:
             raise ValueError("items must be a 2-D float32 tensor")
         items = items.contiguous()
         opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps), st,
-                         mmode, mparam, part)
+                         mmode, mparam, part, proj)
         _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
                                     seed, C.byref(opts), C.byref(h)))
     else:
         X = _host_f32(items)
-        if eps != 0.0 or stream is not None or st != 0 or part != 0:
-            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam, part)
+        if eps != 0.0 or stream is not None or st != 0 or part != 0 or proj != 0:
+            opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam, part,
+                             proj)
             _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
                                         C.byref(opts), C.byref(h)))
         else:

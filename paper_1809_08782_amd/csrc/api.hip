@@ -263,15 +263,18 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     const int64_t n = ix->n;
     const int d = ix->d, dp = ix->dp, m = ix->m, L = ix->L, W = ix->W;
 
-    // projection matrix, its transpose and the FP32 uncertainty band factors
-    make_projection(ix->seed, L, d, ix->A_h);
-    std::vector<float> At_h((size_t)d * L), tau_h(L);
-    for (int r = 0; r < L; ++r) {
+    // projection matrix (one L-row block, or one per sub-dataset), the
+    // transpose of each block and the FP32 uncertainty band factors
+    const int rows = ix->qsets * L;
+    make_projection(ix->seed, rows, d, ix->A_h);
+    std::vector<float> At_h((size_t)rows * d), tau_h(rows);
+    for (int r = 0; r < rows; ++r) {
         double nrm2 = 0.0;
+        const int blk = r / L, rr = r - blk * L;
         for (int c = 0; c <= d; ++c) {
             const double a = ix->A_h[(size_t)r * (d + 1) + c];
             nrm2 += a * a;
-            if (c < d) At_h[(size_t)c * L + r] = (float)a;
+            if (c < d) At_h[((size_t)blk * d + c) * L + rr] = (float)a;
         }
         // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
         // rounded up so that the band is never narrower than the bound.
@@ -313,12 +316,13 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
 
     // build-time scratch, one block
     Block T;
-    const size_t otau = T.reserve<float>(L), oka = T.reserve<uint64_t>(n), okb = T.reserve<uint64_t>(n),
+    const size_t otau = T.reserve<float>(rows), oka = T.reserve<uint64_t>(n), okb = T.reserve<uint64_t>(n),
                  ova = T.reserve<int32_t>(n), ovb = T.reserve<int32_t>(n),
                  ortmp = T.reserve<uint8_t>(radix_sort_tmp_bytes(n)), ofix = T.reserve<FixEntry>(n),
                  octr = T.reserve<BuildCounters>(1),
                  ostg = T.reserve<float>(on_device ? 1 : (size_t)n * d),
-                 obnd = T.reserve<double>(m), osub = T.reserve<int32_t>(m);
+                 obnd = T.reserve<double>(m), osub = T.reserve<int32_t>(m),
+                 obst = T.reserve<int32_t>((size_t)m + 1);
     T.allocate(s);
     DBuf<float> tau = T.view<float>(otau);
     DBuf<uint64_t> ka = T.view<uint64_t>(oka), kb = T.view<uint64_t>(okb);
@@ -329,6 +333,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     DBuf<float> staging = T.view<float>(ostg);
     DBuf<double> bounds = T.view<double>(obnd);
     DBuf<int32_t> subend = T.view<int32_t>(osub);
+    DBuf<int32_t> bstart = T.view<int32_t>(obst);
     const float *X = items;
     if (!on_device) {
         HIPX(hipMemcpyAsync(staging.get(), items, (size_t)n * d * sizeof(float),
@@ -430,7 +435,24 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(hipMemsetAsync(ix->Xlo.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
-    if (ix->storage == NRLSH_STORAGE_FP32) {
+    if (ix->storage == NRLSH_STORAGE_FP32 && ix->qsets > 1) {
+        // one projection block per sub-dataset: the launch's blocks are dealt
+        // out sub-dataset by sub-dataset (first block of j = bstart[j])
+        std::vector<int32_t> bstart_h((size_t)m + 1, 0);
+        const int per_block = hash_items_per_block();
+        for (int j = 0; j < m; ++j) {
+            const int64_t nj = ix->off_h[j + 1] - ix->off_h[j];
+            bstart_h[j + 1] = bstart_h[j] + (int32_t)((nj + per_block - 1) / per_block);
+        }
+        HIPX(hipMemcpyAsync(bstart.get(), bstart_h.data(), bstart_h.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+        tm.begin("hash");
+        HIPX(launch_hash_per_subset(ix->Xl.get(), d, dp, ix->A.get(), L, ix->key_l.get(),
+                                    ix->sid_l.get(), ix->keymax.get(), ix->U.get(), tau.get(),
+                                    ix->off.get(), bstart.get(), m, bstart_h[m], ix->codes_l.get(),
+                                    fix.get(), ctr.get(), s));
+        tm.end();
+    } else if (ix->storage == NRLSH_STORAGE_FP32) {
         tm.begin("hash");
         HIPX(launch_hash(ix->Xl.get(), n, d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
                          ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_l.get(), fix.get(),
@@ -440,9 +462,9 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         hash_low_precision(ix, tau_h, tau.get(), fix.get(), ctr.get(), s, tm);
     }
     tm.begin("hash_fixup");
-    HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
-                           ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), ix->codes_l.get(),
-                           n, s));
+    HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, ix->A.get(), L, ix->qsets > 1, ix->key_l.get(),
+                           ix->sid_l.get(), ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(),
+                           ix->codes_l.get(), n, s));
     tm.end();
 
     HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
@@ -497,6 +519,7 @@ QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
     sh.W = ix->W;
     sh.Tq = std::min<int64_t>(T, ix->n);
     sh.k = k;
+    sh.qsets = ix->qsets;
     return sh;
 }
 
@@ -529,7 +552,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         nch = (int)((maxsub + chunk - 1) / chunk);
     }
     Block blk;
-    const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.W),
+    const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.qsets * sh.W),
                  o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
                  o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
                  o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
@@ -559,10 +582,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
-        uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.W : qcodes.get();
+        uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.qsets * sh.W : qcodes.get();
         int32_t *cb = cand_out_d ? cand_out_d + b0 * sh.Tq : cand.get();
         tm.begin("qhash");
-        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qc, nonfinite_d, s));
+        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qc, nonfinite_d, s));
         tm.end();
         const int64_t tb = (nb + 63) / 64;
         tm.begin("scan_hist");
@@ -580,7 +603,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         tm.end();
         if (chunked) {
             tm.begin("tie_locate");
-            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, gtie.get(),
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
                                    gpstar.get(), s));
             tm.end();
             HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
@@ -686,7 +709,7 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
     Block blk;
     const size_t o_ce = blk.reserve<int32_t>(ce.size()), o_ch = blk.reserve<int32_t>(ch.size()),
-                 o_qc = blk.reserve<uint32_t>((size_t)B * sh.W),
+                 o_qc = blk.reserve<uint32_t>((size_t)B * sh.qsets * sh.W),
                  o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
                  o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
                  o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
@@ -715,7 +738,8 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
         tm.begin("qhash");
-        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, qcodes.get(), nonfinite_d, s));
+        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qcodes.get(),
+                               nonfinite_d, s));
         tm.end();
         ScreenQueries sq{Qb, nullptr, nullptr, nullptr};
         if (kind != SCREEN_FP32) {
@@ -733,8 +757,8 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                               ghthr.get(), gtie.get(), s));
         tm.end();
         tm.begin("tie_locate");
-        HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, gtie.get(),
-                               gpstar.get(), s));
+        HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, sh.qsets,
+                               gtie.get(), gpstar.get(), s));
         tm.end();
         tm.begin("screen_max");
         HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), sq, nb, sh,
@@ -843,6 +867,15 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         partition = opts->partition;
     if (partition != NRLSH_PARTITION_PERCENTILE && partition != NRLSH_PARTITION_UNIFORM)
         return fail(NRLSH_E_INVALID_ARG, "partition %d unknown", partition);
+    int32_t projections = NRLSH_PROJECTIONS_SHARED;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, projections) + sizeof(int32_t)))
+        projections = opts->projections;
+    if (projections != NRLSH_PROJECTIONS_SHARED && projections != NRLSH_PROJECTIONS_PER_SUBSET)
+        return fail(NRLSH_E_INVALID_ARG, "projections %d unknown", projections);
+    if (projections == NRLSH_PROJECTIONS_PER_SUBSET && storage != NRLSH_STORAGE_FP32)
+        return fail(NRLSH_E_INVALID_ARG, "per-subset projections need hash_storage FP32");
+    if (projections == NRLSH_PROJECTIONS_PER_SUBSET && (int64_t)m * L > INT32_MAX / (d + 1))
+        return fail(NRLSH_E_INVALID_ARG, "m L (d+1) too large for per-subset projections");
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
         const int dev = current_device();
@@ -862,6 +895,7 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         ix->margin_mode = margin_mode;
         ix->margin_param = margin_param;
         ix->partition = partition;
+        ix->qsets = projections == NRLSH_PROJECTIONS_PER_SUBSET ? m : 1;
         ix->home = library_stream(dev);
         Timer tm(s);
         try {
@@ -969,6 +1003,13 @@ nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int
     return NRLSH_OK;
 }
 
+nrlsh_status nrlsh_get_projection_sets(const nrlsh_index *ix, int32_t *sets)
+{
+    if (!ix || !sets) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    *sets = ix->qsets;
+    return NRLSH_OK;
+}
+
 nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A)
 {
     if (!ix || !A) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
@@ -1072,15 +1113,17 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
         HIPX(hipSetDevice(ix->device));
         hipStream_t s = library_stream(ix->device);
         DBuf<float> Qd((size_t)nq * ix->d, s);
-        DBuf<uint32_t> qc((size_t)nq * ix->W, s);
+        const int64_t rows = nq * ix->qsets;
+        DBuf<uint32_t> qc((size_t)rows * ix->W, s);
         DBuf<uint32_t> flag(1, s);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
         HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));
-        HIPX(launch_query_hash(Qd.get(), nq, ix->d, ix->At.get(), ix->L, ix->W, qc.get(), flag.get(), s));
-        std::vector<uint32_t> w((size_t)nq * ix->W);
+        HIPX(launch_query_hash(Qd.get(), nq, ix->d, ix->At.get(), ix->L, ix->W, ix->qsets, qc.get(),
+                               flag.get(), s));
+        std::vector<uint32_t> w((size_t)rows * ix->W);
         HIPX(hipMemcpyAsync(w.data(), qc.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         HIPX(hipStreamSynchronize(s));
-        for (int64_t i = 0; i < nq; ++i) {
+        for (int64_t i = 0; i < rows; ++i) {
             uint64_t c = w[(size_t)i * ix->W];
             if (ix->W == 2) c |= (uint64_t)w[(size_t)i * 2 + 1] << 32;
             codes[i] = c;
@@ -1103,7 +1146,7 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
         Timer tm(s);
         DBuf<float> Qd((size_t)nq * ix->d, s);
         DBuf<int32_t> cd((size_t)nq * Tq, s);
-        DBuf<uint32_t> qc((size_t)nq * ix->W, s);
+        DBuf<uint32_t> qc((size_t)nq * ix->qsets * ix->W, s);
         DBuf<uint32_t> flag(1, s);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
         HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));

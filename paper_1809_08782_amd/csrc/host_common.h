@@ -188,6 +188,7 @@ struct nrlsh_index {
     int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
     double margin_param = 0.0;
     int32_t partition = NRLSH_PARTITION_PERCENTILE;
+    int32_t qsets = 1;  // projection blocks of L rows: 1 (shared) or m (one per sub-dataset)
     std::vector<float> A_h;
     std::vector<double> keymax_h, U_h;
     std::vector<int64_t> off_h;

@@ -295,14 +295,19 @@ constexpr int H_KC = 128;
 constexpr int H_KS = H_KC + 4;
 
 // With `rows` != NULL the kernel re-hashes the items rows[0 .. n) (a list of
-// stored positions, n = its length) and counts the bits it changes.
+// stored positions, n = its length) and counts the bits it changes.  With
+// `bstart` != NULL every sub-dataset has its own projection block: block b
+// hashes stored positions of sub-dataset j (bstart[j] <= b < bstart[j+1],
+// found by binary search) with rows j L .. j L + L - 1 of A and tau; the
+// n argument is unused and the items end at off[j+1].
 template <int CB>
 __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
-    const float *__restrict__ Xl, int64_t n, int d, int dp, const float *__restrict__ A, int L,
+    const float *__restrict__ Xl, int64_t n, int d, int dp, const float *__restrict__ A_all, int L,
     const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
-    const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ tau,
-    uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr,
-    const int32_t *__restrict__ rows)
+    const double *__restrict__ keymax, const double *__restrict__ U,
+    const float *__restrict__ tau_all, uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix,
+    BuildCounters *__restrict__ ctr, const int32_t *__restrict__ rows,
+    const int32_t *__restrict__ off, const int32_t *__restrict__ bstart, int m)
 {
     constexpr int NB = 16 * CB;
     __shared__ float As[NB * H_KS];
@@ -310,7 +315,24 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
     __shared__ float uf_s[H_WAVES][64];
     __shared__ int sp_s[H_WAVES][64];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t i0 = ((int64_t)blockIdx.x * H_WAVES + wave) * 64;
+    int64_t i0 = ((int64_t)blockIdx.x * H_WAVES + wave) * 64;
+    const float *A = A_all;
+    const float *tau = tau_all;
+    if (bstart) {
+        // largest j with bstart[j] <= b; an empty sub-dataset owns no block,
+        // so ties resolve to the last of equal starts, the one holding b
+        int lo = 0, hi = m;  // bstart[lo] <= b < bstart[hi]
+        const int b = (int)blockIdx.x;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (bstart[mid] <= b) lo = mid;
+            else hi = mid;
+        }
+        i0 = (int64_t)off[lo] + ((int64_t)(b - bstart[lo]) * H_WAVES + wave) * 64;
+        n = off[lo + 1];
+        A = A_all + (int64_t)lo * L * (d + 1);
+        tau = tau_all + (int64_t)lo * L;
+    }
     {
         const int64_t i = i0 + lane;
         float sq = 0.f, uf = 0.f;
@@ -653,7 +675,7 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
 // the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
 // when U_j = 0; sum over coordinates in ascending order, no contraction).
 __global__ __launch_bounds__(256) void k_hash_fixup(
-    const float *__restrict__ Xl, int d, int dp, const float *__restrict__ A, int L,
+    const float *__restrict__ Xl, int d, int dp, const float *__restrict__ A, int L, int per_subset,
     const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
     const double *__restrict__ keymax, const double *__restrict__ U,
     const FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr,
@@ -679,7 +701,7 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
         while (mask != 0ull) {
             const int r = __ffsll((long long)mask) - 1;
             mask &= mask - 1ull;
-            const float *a = A + (int64_t)r * (d + 1);
+            const float *a = A + ((per_subset ? (int64_t)s * L : 0) + r) * (int64_t)(d + 1);
             double sacc = 0.0;
             if (u == 0.0) {
                 for (int c = 0; c < d; ++c) sacc = sacc + (double)a[c] * 0.0;
@@ -809,25 +831,25 @@ hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A
     switch ((L + 15) / 16) {
     case 1:
         hipLaunchKernelGGL(k_hash<1>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr, rows);
+                           tau, codes_l, fix, ctr, rows, nullptr, nullptr, 0);
         break;
     case 2:
         hipLaunchKernelGGL(k_hash<2>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr, rows);
+                           tau, codes_l, fix, ctr, rows, nullptr, nullptr, 0);
         break;
     case 3:
         hipLaunchKernelGGL(k_hash<3>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr, rows);
+                           tau, codes_l, fix, ctr, rows, nullptr, nullptr, 0);
         break;
     default:
         hipLaunchKernelGGL(k_hash<4>, grid, block, 0, s, Xl, n, d, dp, A, L, key_l, sid_l, keymax, U,
-                           tau, codes_l, fix, ctr, rows);
+                           tau, codes_l, fix, ctr, rows, nullptr, nullptr, 0);
         break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L,
+hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L, bool per_subset,
                              const double *key_l, const int32_t *sid_l, const double *keymax,
                              const double *U, const FixEntry *fix, BuildCounters *ctr,
                              uint32_t *codes_l, int64_t max_entries, hipStream_t s)
@@ -836,8 +858,31 @@ hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int
     int64_t blocks = (max_entries + 255) / 256;
     if (blocks > 1024) blocks = 1024;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xl, d, dp, A, L, key_l,
-                       sid_l, keymax, U, fix, ctr, codes_l, W);
+    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xl, d, dp, A, L,
+                       per_subset ? 1 : 0, key_l, sid_l, keymax, U, fix, ctr, codes_l, W);
+    return hipGetLastError();
+}
+
+int hash_items_per_block() { return H_WAVES * 64; }
+
+hipError_t launch_hash_per_subset(const float *Xl, int d, int dp, const float *A, int L,
+                                  const double *key_l, const int32_t *sid_l, const double *keymax,
+                                  const double *U, const float *tau, const int32_t *off,
+                                  const int32_t *bstart, int m, int nblocks, uint32_t *codes_l,
+                                  FixEntry *fix, BuildCounters *ctr, hipStream_t s)
+{
+    if (nblocks < 1) return hipSuccess;
+    const dim3 grid((unsigned)nblocks), block(H_WAVES * 64);
+#define NRLSH_HPS(CB)                                                                           \
+    hipLaunchKernelGGL(k_hash<CB>, grid, block, 0, s, Xl, (int64_t)0, d, dp, A, L, key_l, sid_l, \
+                       keymax, U, tau, codes_l, fix, ctr, nullptr, off, bstart, m)
+    switch ((L + 15) / 16) {
+    case 1: NRLSH_HPS(1); break;
+    case 2: NRLSH_HPS(2); break;
+    case 3: NRLSH_HPS(3); break;
+    default: NRLSH_HPS(4); break;
+    }
+#undef NRLSH_HPS
     return hipGetLastError();
 }
 

@@ -1,7 +1,8 @@
 // Query kernels of norm-ranging LSH for gfx950 (Section 3.3 multi-probe,
 // Algorithm 2 re-rank).
 //
-//   query_hash  code of P(q) = [q; 0] under the shared projections (Eq. 4, 8)
+//   query_hash  code of P(q) = [q; 0] (Eq. 4, 8): one code under the shared
+//               projections, or one per sub-dataset under its own block
 //   scan_hist   pass 1: per (query tile, sub-dataset) histogram of the number
 //               of differing bits, h = popcount(c_i ^ c_q) = L - l
 //   threshold   walk the sorted (U_j, l) structure (Eq. 12) best-first until
@@ -30,18 +31,29 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
+// Row of the query-code array that holds query q's code for sub-dataset j:
+// one code per query with shared projections (qsets = 1), one per
+// (query, sub-dataset) with a projection block per sub-dataset (qsets = m).
+__device__ __forceinline__ int64_t qrow(int64_t q, int j, int qsets)
+{
+    return qsets > 1 ? q * qsets + j : q;
+}
+
 // ---------------------------------------------------------------- query_hash
-// One wave per query, lane r computes bit r: sum_t A[r][t] q_t in FP64 in
-// ascending t (products of two floats are exact in FP64).  At is A[:, :d]
-// transposed (d x L) so that the lanes read consecutive words.
+// One wave per (query, projection block), lane r computes bit r:
+// sum_t A[r][t] q_t in FP64 in ascending t (products of two floats are exact
+// in FP64).  At holds each block's A[:, :d] transposed (d x L) so that the
+// lanes read consecutive words.
 __global__ __launch_bounds__(256) void k_query_hash(const float *__restrict__ Q, int64_t nq, int d,
-                                                    const float *__restrict__ At, int L, int W,
-                                                    uint32_t *__restrict__ qcodes,
+                                                    const float *__restrict__ At_all, int L, int W,
+                                                    int qsets, uint32_t *__restrict__ qcodes,
                                                     uint32_t *__restrict__ nonfinite)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
-    if (q >= nq) return;
+    const int64_t row = (int64_t)blockIdx.x * 4 + wave;  // = qrow(q, j, qsets)
+    if (row >= nq * qsets) return;
+    const int64_t q = row / qsets;
+    const float *At = At_all + (row - q * qsets) * (int64_t)d * L;
     const float *qv = Q + q * d;
     const bool act = lane < L;
     double s = 0.0;
@@ -54,8 +66,8 @@ __global__ __launch_bounds__(256) void k_query_hash(const float *__restrict__ Q,
     }
     const uint64_t code = __ballot(act && s > 0.0);
     if (lane == 0) {
-        qcodes[q * W] = (uint32_t)code;
-        if (W == 2) qcodes[q * W + 1] = (uint32_t)(code >> 32);
+        qcodes[row * W] = (uint32_t)code;
+        if (W == 2) qcodes[row * W + 1] = (uint32_t)(code >> 32);
         if (bad) atomicOr(nonfinite, 1u);
     }
 }
@@ -65,7 +77,7 @@ template <int W>
 __global__ __launch_bounds__(64) void k_scan_hist(const uint32_t *__restrict__ codes_l,
                                                   const int32_t *__restrict__ off,
                                                   const uint32_t *__restrict__ qcodes, int64_t nq,
-                                                  int m, int L, uint32_t *__restrict__ ghist)
+                                                  int m, int L, int qsets, uint32_t *__restrict__ ghist)
 {
     extern __shared__ uint32_t hist[];  // (L+1) x 64, column = lane
     const int lane = threadIdx.x;
@@ -73,8 +85,9 @@ __global__ __launch_bounds__(64) void k_scan_hist(const uint32_t *__restrict__ c
     const int64_t q = (int64_t)tile * 64 + lane;
     uint32_t q0 = 0, q1 = 0;
     if (q < nq) {
-        q0 = qcodes[q * W];
-        if (W == 2) q1 = qcodes[q * W + 1];
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
     }
     for (int h = 0; h <= L; ++h) hist[h * 64 + lane] = 0u;
     const int64_t p0 = off[j], p1 = off[j + 1];
@@ -178,7 +191,7 @@ template <int W>
 __global__ __launch_bounds__(64) void k_scan_emit(const uint32_t *__restrict__ codes_l,
                                                   const int32_t *__restrict__ off,
                                                   const uint32_t *__restrict__ qcodes, int64_t nq,
-                                                  int m, int L, int64_t Tq,
+                                                  int m, int L, int64_t Tq, int qsets,
                                                   const int32_t *__restrict__ gbase,
                                                   const int32_t *__restrict__ ghthr,
                                                   const int32_t *__restrict__ gtie,
@@ -200,8 +213,9 @@ __global__ __launch_bounds__(64) void k_scan_emit(const uint32_t *__restrict__ c
         }
         base = gbase[((int64_t)tile * (m + 1) + j) * 64 + lane];
         cap = gbase[((int64_t)tile * (m + 1) + j + 1) * 64 + lane] - (int32_t)base;
-        q0 = qcodes[q * W];
-        if (W == 2) q1 = qcodes[q * W + 1];
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
     }
     if (__ballot(hthr >= 0 || htie >= 0) == 0ull) return;
     int32_t *out = cand + (valid ? q * Tq + base : 0);
@@ -247,7 +261,7 @@ template <int W>
 __global__ __launch_bounds__(64) void k_scan_hist_c(const uint32_t *__restrict__ codes_l,
                                                     const int32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ qcodes, int64_t nq,
-                                                    int m, int L, int chunk, int nch,
+                                                    int m, int L, int qsets, int chunk, int nch,
                                                     uint32_t *__restrict__ ghist)
 {
     extern __shared__ uint32_t hist[];  // (L+1) x 64, column = lane
@@ -262,8 +276,9 @@ __global__ __launch_bounds__(64) void k_scan_hist_c(const uint32_t *__restrict__
     const int64_t q = tile * 64 + lane;
     uint32_t q0 = 0, q1 = 0;
     if (q < nq) {
-        q0 = qcodes[q * W];
-        if (W == 2) q1 = qcodes[q * W + 1];
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
     }
     for (int h = 0; h <= L; ++h) hist[h * 64 + lane] = 0u;
     int64_t p = p0;
@@ -296,7 +311,7 @@ template <int W>
 __global__ __launch_bounds__(64) void k_scan_emit_c(const uint32_t *__restrict__ codes_l,
                                                     const int32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ qcodes, int64_t nq,
-                                                    int m, int64_t Tq, int chunk, int nch,
+                                                    int m, int64_t Tq, int qsets, int chunk, int nch,
                                                     const int32_t *__restrict__ ghthr,
                                                     const int32_t *__restrict__ gtie,
                                                     const int32_t *__restrict__ gpstar,
@@ -323,8 +338,9 @@ __global__ __launch_bounds__(64) void k_scan_emit_c(const uint32_t *__restrict__
             htie = tie[64 + lane];
             pstar = gpstar[q];
         }
-        q0 = qcodes[q * W];
-        if (W == 2) q1 = qcodes[q * W + 1];
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
     }
     if (__ballot(hthr >= 0 || htie >= 0) == 0ull) return;
     int32_t cnt = 0;
@@ -525,7 +541,8 @@ template <int W>
 __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__ codes_l,
                                                     const int32_t *__restrict__ off,
                                                     const uint32_t *__restrict__ qcodes,
-                                                    int64_t nq, const int32_t *__restrict__ gtie,
+                                                    int64_t nq, int qsets,
+                                                    const int32_t *__restrict__ gtie,
                                                     int32_t *__restrict__ gpstar)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -538,7 +555,8 @@ __global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__
     if (jstar >= 0 && rstar == INT_MAX) {
         P = INT_MAX;
     } else if (jstar >= 0) {
-        const uint32_t q0 = qcodes[q * W], q1 = W == 2 ? qcodes[q * W + 1] : 0u;
+        const int64_t r = qrow(q, jstar, qsets);
+        const uint32_t q0 = qcodes[r * W], q1 = W == 2 ? qcodes[r * W + 1] : 0u;
         const int64_t pe = off[jstar + 1];
         int cnt = 0;
         for (int64_t p0 = off[jstar]; p0 < pe; p0 += 64) {
@@ -592,7 +610,7 @@ __global__ __launch_bounds__(256) void k_screen(
     const int32_t *__restrict__ ghthr, const int32_t *__restrict__ gtie,
     const int32_t *__restrict__ gpstar, const float *__restrict__ theta, float gam, int cap,
     int32_t *__restrict__ counts, int32_t *__restrict__ lists, float *__restrict__ cmax,
-    int ncol, int L)
+    int ncol, int L, int qsets)
 {
     extern __shared__ __align__(16) float qs[];  // 64 x qstride
     __shared__ float th_s[64], qn_s[64];
@@ -619,7 +637,7 @@ __global__ __launch_bounds__(256) void k_screen(
             }
             if (!MAXMODE) th = theta[q];
 #pragma unroll
-            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
+            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[qrow(q, j, qsets) * W + w];
         }
         hthr_s[tid] = hthr;
         htie_s[tid] = htie;
@@ -793,10 +811,10 @@ __global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q,
         const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,                 \
         const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,                   \
         const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,      \
-        int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L
+        int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L, int qsets
 #define NRLSH_SCREEN_ARGS                                                                      \
     Xh, Xlo, dp, codes_l, key_l, Qh, Ql, qnorm, nq, chunks, m, qcodes, ghthr, gtie, gpstar, theta, \
-        gam, cap, counts, lists, cmax, ncol, qsb, L
+        gam, cap, counts, lists, cmax, ncol, qsb, L, qsets
 
 template <int W, bool MAXMODE, bool X3>
 __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
@@ -827,7 +845,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
             if (!MAXMODE) th = theta[q];
             qn = qnorm[q];
 #pragma unroll
-            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[q * W + w];
+            for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[qrow(q, j, qsets) * W + w];
         }
         hthr_s[tid] = hthr;
         htie_s[tid] = htie;
@@ -1027,10 +1045,11 @@ inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) /
 }  // namespace
 
 hipError_t launch_query_hash(const float *Q, int64_t nq, int d, const float *At, int L, int W,
-                             uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s)
+                             int qsets, uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_query_hash, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, nq, d, At, L, W,
-                       qcodes, nonfinite);
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_query_hash, dim3(ceil_div(nq * qsets, 4)), dim3(256), 0, s, Q, nq, d, At, L,
+                       W, qsets, qcodes, nonfinite);
     return hipGetLastError();
 }
 
@@ -1041,10 +1060,10 @@ hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const u
     const size_t lds = (size_t)(sh.L + 1) * 64 * sizeof(uint32_t);
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_hist<1>, grid, dim3(64), lds, s, codes_l, off, qcodes, nq, sh.m,
-                           sh.L, ghist);
+                           sh.L, sh.qsets, ghist);
     else
         hipLaunchKernelGGL(k_scan_hist<2>, grid, dim3(64), lds, s, codes_l, off, qcodes, nq, sh.m,
-                           sh.L, ghist);
+                           sh.L, sh.qsets, ghist);
     return hipGetLastError();
 }
 
@@ -1065,10 +1084,10 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
     const dim3 grid(ceil_div(nq, 64), (unsigned)sh.m);
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_emit<1>, grid, dim3(64), 0, s, codes_l, off, qcodes, nq, sh.m,
-                           sh.L, sh.Tq, gbase, ghthr, gtie, cand);
+                           sh.L, sh.Tq, sh.qsets, gbase, ghthr, gtie, cand);
     else
         hipLaunchKernelGGL(k_scan_emit<2>, grid, dim3(64), 0, s, codes_l, off, qcodes, nq, sh.m,
-                           sh.L, sh.Tq, gbase, ghthr, gtie, cand);
+                           sh.L, sh.Tq, sh.qsets, gbase, ghthr, gtie, cand);
     return hipGetLastError();
 }
 
@@ -1080,10 +1099,10 @@ hipError_t launch_scan_hist_c(const uint32_t *codes_l, const int32_t *off, const
     const size_t lds = (size_t)(sh.L + 1) * 64 * sizeof(uint32_t);
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_hist_c<1>, dim3((unsigned)blocks), dim3(64), lds, s, codes_l, off,
-                           qcodes, nq, sh.m, sh.L, chunk, nch, ghist);
+                           qcodes, nq, sh.m, sh.L, sh.qsets, chunk, nch, ghist);
     else
         hipLaunchKernelGGL(k_scan_hist_c<2>, dim3((unsigned)blocks), dim3(64), lds, s, codes_l, off,
-                           qcodes, nq, sh.m, sh.L, chunk, nch, ghist);
+                           qcodes, nq, sh.m, sh.L, sh.qsets, chunk, nch, ghist);
     return hipGetLastError();
 }
 
@@ -1095,22 +1114,25 @@ hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const
     const int64_t blocks = (int64_t)ceil_div(nq, 64) * sh.m * nch;
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_emit_c<1>, dim3((unsigned)blocks), dim3(64), 0, s, codes_l, off,
-                           qcodes, nq, sh.m, sh.Tq, chunk, nch, ghthr, gtie, gpstar, counts, cand);
+                           qcodes, nq, sh.m, sh.Tq, sh.qsets, chunk, nch, ghthr, gtie, gpstar, counts,
+                           cand);
     else
         hipLaunchKernelGGL(k_scan_emit_c<2>, dim3((unsigned)blocks), dim3(64), 0, s, codes_l, off,
-                           qcodes, nq, sh.m, sh.Tq, chunk, nch, ghthr, gtie, gpstar, counts, cand);
+                           qcodes, nq, sh.m, sh.Tq, sh.qsets, chunk, nch, ghthr, gtie, gpstar, counts,
+                           cand);
     return hipGetLastError();
 }
 
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
-                             int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s)
+                             int64_t nq, int W, int qsets, const int32_t *gtie, int32_t *gpstar,
+                             hipStream_t s)
 {
     if (W == 1)
         hipLaunchKernelGGL(k_tie_locate<1>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
-                           qcodes, nq, gtie, gpstar);
+                           qcodes, nq, qsets, gtie, gpstar);
     else
         hipLaunchKernelGGL(k_tie_locate<2>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
-                           qcodes, nq, gtie, gpstar);
+                           qcodes, nq, qsets, gtie, gpstar);
     return hipGetLastError();
 }
 
@@ -1159,11 +1181,12 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
     if (one)
         hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
                            Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
-                           cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+                           cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets);
     else
         hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
                            codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
-                           gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L);
+                           gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L,
+                           sh.qsets);
     return hipGetLastError();
 }
 
@@ -1213,11 +1236,11 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
     if (sh.W == 1)
         hipLaunchKernelGGL((k_screen<1, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q.Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, ncol, sh.L);
+                           counts, lists, cmax, ncol, sh.L, sh.qsets);
     else
         hipLaunchKernelGGL((k_screen<2, MAXMODE>), grid, dim3(256), lds, s, Xl, sh.d, sh.dp, codes_l,
                            key_l, Q.Q, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap,
-                           counts, lists, cmax, ncol, sh.L);
+                           counts, lists, cmax, ncol, sh.L, sh.qsets);
     return hipGetLastError();
 }
 

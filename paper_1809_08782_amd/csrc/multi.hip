@@ -174,9 +174,14 @@ nrlsh_status validate_descs(const nrlsh_query_desc *descs, int32_t count, int32_
         if (q.nq > 0 && (!q.queries || !q.out_ids || !q.out_ips))
             return fail(NRLSH_E_INVALID_ARG, "descs[%d] has a NULL query or output pointer", i);
     }
-    for (int32_t i = 1; i < count; ++i)
+    // index fields are read only once every scalar argument has passed
+    for (int32_t i = 0; i < count; ++i) {
         if (descs[i].index->device != descs[0].index->device)
             return fail(NRLSH_E_INVALID_ARG, "descs[%d].index lives on another device", i);
+        if (descs[i].index->qsets != 1)
+            return fail(NRLSH_E_INVALID_ARG,
+                        "descs[%d].index uses per-subset projections, which the batching form does not take", i);
+    }
     return NRLSH_OK;
 }
 

@@ -67,6 +67,17 @@ hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A
                        const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
                        BuildCounters *ctr, const int32_t *rows, hipStream_t s);
 
+// Independent projections per sub-dataset: sub-dataset j (stored positions
+// off[j] .. off[j+1]) hashes with rows j L .. j L + L - 1 of A and their band
+// factors tau[j L ..]; block b of the launch serves sub-dataset j where
+// bstart[j] <= b < bstart[j+1], covering hash_items_per_block() items each.
+int hash_items_per_block();
+hipError_t launch_hash_per_subset(const float *Xl, int d, int dp, const float *A, int L,
+                                  const double *key_l, const int32_t *sid_l, const double *keymax,
+                                  const double *U, const float *tau, const int32_t *off,
+                                  const int32_t *bstart, int m, int nblocks, uint32_t *codes_l,
+                                  FixEntry *fix, BuildCounters *ctr, hipStream_t s);
+
 // Precision form: quantise rows to bfloat16 (storage 1) or E4M3 with row scales
 // (storage 2), then hash from the quantised copy; items inside the margin
 // mq_r ||x|| + tq_r U_j are appended to rows (count in ctr->lowp_items).
@@ -79,7 +90,8 @@ hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64
                          int32_t *rows, BuildCounters *ctr, hipStream_t s);
 
 // FP64 recompute of the flagged projections, exactly as the definition.
-hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L,
+// per_subset: an item of sub-dataset s takes its rows from block s of A.
+hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int L, bool per_subset,
                              const double *key_l, const int32_t *sid_l, const double *keymax,
                              const double *U, const FixEntry *fix, BuildCounters *ctr,
                              uint32_t *codes_l, int64_t max_entries, hipStream_t s);
@@ -90,11 +102,16 @@ struct QueryShape {
     int d, dp, m, L, W;
     int64_t Tq;      // probed items per query, min(T, n)
     int k;
+    int qsets = 1;   // query codes per query: 1 (shared projections) or m
 };
 
 // Query codes (FP64 exact sign of A[:, :d] q); flags non-finite queries.
+// With qsets > 1 (one projection block per sub-dataset, At = qsets blocks of
+// d x L) query q gets qsets codes; code (q, j) sits at row q qsets + j of
+// qcodes (W words per row), the row every query kernel reads for
+// sub-dataset j.
 hipError_t launch_query_hash(const float *Q, int64_t nq, int d, const float *At, int L, int W,
-                             uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s);
+                             int qsets, uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s);
 
 // Pass 1: per query tile and sub-dataset, histogram of Hamming distance.
 hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
@@ -145,7 +162,8 @@ hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const
 
 // Stored position of the r*-th item of each query's threshold bucket (-1 if none).
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
-                             int64_t nq, int W, const int32_t *gtie, int32_t *gpstar, hipStream_t s);
+                             int64_t nq, int W, int qsets, const int32_t *gtie, int32_t *gpstar,
+                             hipStream_t s);
 
 // Query-tiled FP32-MFMA screen of the probed set.  Chunks / cells are
 // (sub-dataset, first, end) triples of stored items.

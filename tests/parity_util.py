@@ -50,8 +50,12 @@ def check_build(gix, oix, label=""):
 def check_query(gix, oix, Q, k, T, label=""):
     """Query parity: query codes, probed sets, top-k ids and inner products."""
     qc = gix.query_codes(Q)
-    oqc = orc.query_codes(oix.A, Q)
-    assert np.array_equal(qc, oqc), f"{label}: query codes"
+    if getattr(oix, "per_subset", False):  # one code per (query, sub-dataset)
+        oqc = np.stack([oix.query_code(q) for q in Q]).reshape(Q.shape[0], oix.m)
+    else:
+        oqc = orc.query_codes(oix.A, Q)
+    nq = Q.shape[0]
+    assert np.array_equal(qc.reshape(nq, -1), oqc.reshape(nq, -1)), f"{label}: query codes"
     cand = gix.query_candidates(Q, T)
     Tq = min(T, oix.n)
     assert cand.shape == (Q.shape[0], Tq)

@@ -71,6 +71,19 @@ def test_build_rejects_unknown_partition():
     assert "partition" in nr.nrlsh_last_error()
 
 
+def test_build_rejects_bad_projections():
+    X = np.ones((10, 4), np.float32)
+    h = C.c_void_p()
+    opts = _lib.BuildOpts(C.sizeof(_lib.BuildOpts), 0, None, 0.0, 0, 0, 0.0, 0, 2)
+    assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
+    assert "projections" in nr.nrlsh_last_error()
+    # per-subset projections exist only for the FP32 hash
+    for storage in (1, 2):
+        opts = _lib.BuildOpts(C.sizeof(_lib.BuildOpts), 0, None, 0.0, storage, 0, 0.0, 0, 1)
+        assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
+        assert "per-subset" in nr.nrlsh_last_error()
+
+
 def test_query_rejects_bad_arguments():
     L = nr.lib()
     Q = np.ones((2, 4), np.float32)

@@ -294,3 +294,61 @@ def test_parity_small_batch_chunked_scan(n, d, m, L, nq, k, T):
                 st = nr.nrlsh_get_query_stats()
                 say(f"  bf16 lists: total {st['lp_kept_total']} max {st['lp_kept_max']} "
                     f"fallbacks {st['lp_fallbacks']}")
+
+
+PER_SUBSET_CASES = [
+    # (n, d, m, L, kind, T, partition)
+    (6000, 40, 16, 32, "lognormal", 600, "percentile"),
+    (5000, 64, 8, 64, "pareto", 5000, "percentile"),     # W = 2, T = n
+    (3000, 17, 1, 20, "lognormal", 300, "percentile"),   # one sub-dataset: the shared index
+    (4100, 128, 7, 31, "lowrank", 1000, "percentile"),   # sub-datasets cut hash blocks raggedly
+    (5000, 64, 32, 48, "pareto", 2000, "uniform"),       # empty sub-datasets own no hash block
+]
+
+
+@pytest.mark.parametrize("case", PER_SUBSET_CASES, ids=lambda c: "n%d_d%d_m%d_L%d_%s_T%d_%s" % c)
+def test_parity_per_subset_projections(case):
+    """Independent projections per sub-dataset: projection blocks, item codes
+    (each sub-dataset hashed with its own rows), the m query codes, probed sets
+    and results equal the oracle's, for every re-rank mode."""
+    n, d, m, L, kind, T, part = case
+    say(f"case per-subset projections n={n} d={d} m={m} L={L} {kind} T={T} {part}")
+    kw = {"alpha": 2.5} if kind == "pareto" else {"sigma": 1.0} if kind == "lognormal" else {}
+    X = make_items(kind, n, d, seed=n + 3 * m, **kw)
+    Q = make_queries(70, d, seed=n + 5)
+    oix = orc.OracleIndex(X, m, L, seed=29, threads=8, partition=part, projections="per_subset")
+    with nr.nrlsh_build(X, m, L, 29, partition=part, projections="per_subset") as gix:
+        assert gix.qsets == m
+        check_build(gix, oix, "per-subset")
+        check_query(gix, oix, Q, 10, T, "per-subset")
+        oids, oips = oix.query(Q, 10, n, threads=8)
+        for mode in ("gather", "screen", "screen_fp32", "screen_bf16x3"):
+            ids, ips = nr.nrlsh_query(gix, Q, 10, n, rerank=mode)
+            assert np.array_equal(ids, oids), mode
+            assert np.array_equal(ips, oips.astype(np.float32)), mode
+
+
+def test_parity_per_subset_small_batch_chunked_scan():
+    """Per-subset query codes through the chunked scans and the tie cut."""
+    n, d, m, L, nq, k, T = 30011, 75, 4, 32, 70, 10, 3001
+    say(f"case per-subset chunked scan n={n} d={d} m={m} L={L} nq={nq} T={T}")
+    X = make_items("lognormal", n, d, seed=n + 13, sigma=0.9)
+    Q = make_queries(nq, d, seed=n + 14)
+    oix = orc.OracleIndex(X, m, L, seed=43, threads=8, projections="per_subset")
+    oids, oips = oix.query(Q, k, T, threads=8)
+    with nr.nrlsh_build(X, m, L, 43, projections="per_subset") as gix:
+        cand = gix.query_candidates(Q[:8], T)
+        for qi in range(8):
+            assert np.array_equal(np.sort(cand[qi]), np.sort(oix.candidates(Q[qi], T)[0])), qi
+        for storage in ("fp32", "bf16"):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage=storage)
+            assert np.array_equal(ids, oids), storage
+            assert np.array_equal(ips, oips.astype(np.float32)), storage
+
+
+def test_per_subset_index_rejected_by_batching_form():
+    X = make_items("lognormal", 2000, 16, seed=5, sigma=0.5)
+    Q = make_queries(4, 16, seed=6)
+    with nr.nrlsh_build(X, 4, 16, 7, projections="per_subset") as gix:
+        with pytest.raises(nr.NrlshError, match="per-subset"):
+            nr.nrlsh_query_multi([(gix, Q, 100)], 10)
