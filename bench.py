@@ -219,6 +219,13 @@ def main():
                          "budget: eps:E (adjusted metric), uniform (norm ranges), bits (paper's "
                          "code-bit accounting), m:M (sub-datasets), per_subset (independent "
                          "projections per sub-dataset); combine with '+'; '' for none")
+    ap.add_argument("--probe", default="scan", choices=["scan", "table"],
+                    help="how the timed step finds the probed items: linear scan of the codes, "
+                         "or the bucket tables (hash lookup, Section 3.3)")
+    ap.add_argument("--probe-sweep", default="", metavar="L,...",
+                    help="after the headline, time query batches of 1, 16 and 256 queries at "
+                         "budgets 100, 1000, 10000 with both probes, on indexes of these code "
+                         "lengths (e.g. '16,32'); '' for none")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-MiB buffer 3 times before the steps (a kernel of known "
                          "traffic that scales hardware byte counters)")
@@ -306,11 +313,12 @@ def main():
 
     def step(T, eps=0.0):
         with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage,
-                            margin=margin, eps=eps) as sx:
+                            margin=margin, eps=eps, bucket_tables=args.probe == "table") as sx:
             for b0 in range(0, w.nq, qb):
                 b1 = min(w.nq, b0 + qb)
                 nr.nrlsh_query(sx, Qd[b0:b1], w.k, T, out=(ids_buf[b0:b1], ips_buf[b0:b1]),
-                               rerank=args.rerank, rerank_storage=args.rerank_storage)
+                               rerank=args.rerank, rerank_storage=args.rerank_storage,
+                               probe=args.probe)
 
     def timed(T, steps, warmup, profile, eps=0.0):
         for i in range(warmup):
@@ -328,9 +336,9 @@ def main():
         nr.nrlsh_profile_enable(False)
         return el / steps
 
-    names = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "qhash",
-             "scan_hist", "threshold", "tie_locate", "scan_emit", "rerank", "rerank_lp",
-             "screen_max", "screen", "rerank_exact"]
+    names = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table", "qhash",
+             "scan_hist", "threshold", "tie_locate", "scan_emit", "table_count", "table_emit",
+             "rerank", "rerank_lp", "screen_max", "screen", "rerank_exact"]
     # unprofiled timing for the headline, profiled run for the per-kernel split
     s_step = timed(T_op, args.steps, args.warmup, False)
     qstats = nr.nrlsh_get_query_stats()
@@ -417,6 +425,37 @@ def main():
         log(f"variant {v}: m={cfg['m']} L={cfg['L']} T_op={vT} recall {vcurve.get(str(vT))} "
             f"{est * 1e3:.2f} ms/step")
 
+    # ---------------------------------------------------------------- probe sweep
+    # query-only latency of the two probes (same probed set, same results):
+    # small batches and budgets are where the bucket tables can skip the scan
+    probe_sweep = []
+    for Ls in [int(v) for v in args.probe_sweep.split(",") if v.strip()]:
+        with nr.nrlsh_build(Xd, w.m, Ls, w.index_seed, bucket_tables=True) as tx:
+            for nqs in (1, 16, 256):
+                for T in (100, 1000, 10000):
+                    row = {"L": Ls, "nq": nqs, "T": T}
+                    ref = None
+                    for probe in ("scan", "table"):
+                        qs = Qd[:nqs]
+                        ids, _ = nr.nrlsh_query(tx, qs, w.k, T, rerank="gather", probe=probe)
+                        st = nr.nrlsh_get_query_stats()
+                        torch.cuda.synchronize()
+                        reps = 10
+                        t = time.perf_counter()
+                        for _ in range(reps):
+                            nr.nrlsh_query(tx, qs, w.k, T, rerank="gather", probe=probe)
+                        torch.cuda.synchronize()
+                        row[probe + "_ms"] = (time.perf_counter() - t) / reps * 1e3
+                        if probe == "table":
+                            row["lookups_per_query"] = st["table_lookups"] / nqs
+                            row["walked_per_query"] = st["table_walked"] / nqs
+                            row["same_result"] = bool(torch.equal(ids, ref))
+                        ref = ids
+                    probe_sweep.append(row)
+                    log(f"probe L={Ls} nq={nqs} T={T}: scan {row['scan_ms']:.3f} ms, table "
+                        f"{row['table_ms']:.3f} ms ({row['lookups_per_query']:.0f} lookups, "
+                        f"{row['walked_per_query']:.0f} codes walked per query)")
+
     # ---------------------------------------------------------------- roofline
     Tq = min(T_op, w.n)
     dom = max(kern, key=lambda nm: kern[nm]["avg_ms"] * kern[nm]["launches_per_step"]) if kern else None
@@ -502,7 +541,7 @@ def main():
                    if args.budget is None else "fixed T", "parallelism": "single GPU",
                    "hash_storage": args.hash_storage, "margin": args.margin,
                    "rerank": args.rerank, "rerank_storage": args.rerank_storage,
-                   "query_batch": qb},
+                   "probe": args.probe, "query_batch": qb},
         "recall_at_T": curve.get(T_op),
         "recall_curve": {str(k): v for k, v in curve.items()},
         "budgets": budgets,
@@ -514,6 +553,7 @@ def main():
         "roofline": roof,
         "scan": scan,
         "variants": variants,
+        "probe_sweep": probe_sweep,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -130,6 +130,10 @@ typedef struct nrlsh_build_opts {
     double margin_param;  /* SCALED: relative margin (>= 0) */
     int32_t partition;    /* nrlsh_partition (read when struct_size covers it) */
     int32_t projections;  /* nrlsh_projections (read when struct_size covers it) */
+    int32_t bucket_tables; /* 1: also build the bucket tables that NRLSH_PROBE_TABLE
+                              queries read (about 16 n bytes more; read when
+                              struct_size covers it) */
+    int32_t pad;
 } nrlsh_build_opts;
 
 nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
@@ -174,6 +178,20 @@ typedef enum {
     NRLSH_RERANK_SCREEN_BF16X3 = 4
 } nrlsh_rerank_mode;
 
+/* How a query finds its probed items (both give the same probed set).
+ *   SCAN:  every item code of the index is compared with the query code (two
+ *          linear passes: per-bucket counts, then emission).
+ *   TABLE: the "standard hash lookup" of Section 3.3: buckets (j, l) are taken
+ *          in probing order from a table of each sub-dataset's distinct codes
+ *          (the index must be built with bucket_tables = 1).  The codes at
+ *          Hamming distance L - l from the query code are enumerated and looked
+ *          up, until the lookups spent on sub-dataset j would exceed its number
+ *          of distinct codes; then j's distinct codes are counted by distance
+ *          once.  Work grows with the buckets probed, not with n; it pays
+ *          where few buckets hold the budget (short codes, small T).  Goes with
+ *          the GATHER re-rank (AUTO selects it; a SCREEN mode is rejected). */
+typedef enum { NRLSH_PROBE_SCAN = 0, NRLSH_PROBE_TABLE = 1 } nrlsh_probe_mode;
+
 typedef struct nrlsh_query_opts {
     int32_t struct_size; /* sizeof(nrlsh_query_opts) */
     int32_t device_ptrs; /* 1: queries, out_ids, out_ips are device pointers */
@@ -184,6 +202,8 @@ typedef struct nrlsh_query_opts {
                                copy bound each item within (2^-8 + 2^-40) ||q|| ||x||;
                                items that may still reach the top-k are re-ranked
                                exactly from the FP32 rows (same result, fewer bytes) */
+    int32_t probe_mode;  /* nrlsh_probe_mode (read when struct_size covers it) */
+    int32_t pad;
 } nrlsh_query_opts;
 
 nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -337,6 +357,16 @@ nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st)
 nrlsh_status nrlsh_get_hash_copy(const nrlsh_index *ix, void *data, float *scales,
                                  int32_t *storage);
 
+/* Bucket table of an index built with bucket_tables = 1 (else
+ * NRLSH_E_INVALID_ARG).  *nunique = U, the number of distinct (sub-dataset,
+ * code) pairs; when ucode is not NULL also copies ucode: U uint64 codes,
+ * sub-dataset by sub-dataset and ascending inside each; ustart: U + 1 int64,
+ * run starts in titem (ustart[U] = n); uoff: m + 1 int64, first distinct code
+ * of each sub-dataset (uoff[m] = U); titem: n int32 stored positions sorted by
+ * (sub-dataset, code, position). */
+nrlsh_status nrlsh_get_bucket_table(const nrlsh_index *ix, int64_t *nunique, uint64_t *ucode,
+                                    int64_t *ustart, int64_t *uoff, int32_t *titem);
+
 /* Query codes: nq x sets uint64 (host in, host out), bit r of code (q, j) =
  * [A_{j L + r}[:d] . q > 0] (sets: nrlsh_get_projection_sets). */
 nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,
@@ -357,7 +387,10 @@ typedef struct nrlsh_query_stats {
     int64_t lp_kept_total; /* BF16 re-rank: items re-ranked exactly, all queries */
     int64_t lp_kept_max;   /* BF16 re-rank: largest exact list of one query */
     int32_t lp_fallbacks;  /* BF16 re-rank: batches that overflowed into the FP32 re-rank */
-    int32_t pad;
+    int32_t probe_mode;    /* nrlsh_probe_mode used */
+    int64_t table_lookups; /* TABLE: codes searched in the tables, all queries */
+    int64_t table_walked;  /* TABLE: distinct codes counted by whole-sub-dataset passes */
+    int64_t table_passes;  /* TABLE: whole-sub-dataset passes */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

@@ -32,7 +32,8 @@ class BuildOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32),
                 ("stream", C.c_void_p), ("eps", C.c_double), ("hash_storage", C.c_int32),
                 ("margin_mode", C.c_int32), ("margin_param", C.c_double),
-                ("partition", C.c_int32), ("projections", C.c_int32)]
+                ("partition", C.c_int32), ("projections", C.c_int32),
+                ("bucket_tables", C.c_int32), ("pad", C.c_int32)]
 
 
 PARTITIONS = {"percentile": 0, "uniform": 1}
@@ -44,7 +45,11 @@ STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
 
 class QueryOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
-                ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32)]
+                ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32),
+                ("probe_mode", C.c_int32), ("pad", C.c_int32)]
+
+
+PROBES = {"scan": 0, "table": 1}
 
 
 RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3, "screen_bf16x3": 4}
@@ -59,7 +64,9 @@ class BuildStats(C.Structure):
 class QueryStats(C.Structure):
     _fields_ = [("mode", C.c_int32), ("screen_passes", C.c_int32), ("kept_total", C.c_int64),
                 ("kept_max", C.c_int64), ("theta_unset", C.c_int64), ("lp_kept_total", C.c_int64),
-                ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("pad", C.c_int32)]
+                ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
+                ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
+                ("table_passes", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -119,6 +126,8 @@ def lib():
         L.nrlsh_get_partition.restype = st
         L.nrlsh_get_projection_sets.argtypes = [P, C.POINTER(I32)]
         L.nrlsh_get_projection_sets.restype = st
+        L.nrlsh_get_bucket_table.argtypes = [P, C.POINTER(I64), P, P, P, P]
+        L.nrlsh_get_bucket_table.restype = st
         L.nrlsh_get_layout.argtypes = [P, P, P]
         L.nrlsh_get_layout.restype = st
         L.nrlsh_get_hash_copy.argtypes = [P, P, P, C.POINTER(I32)]
@@ -290,6 +299,18 @@ class Index:
         _check(lib().nrlsh_query_codes(self.handle, Q.ctypes.data, Q.shape[0], out.ctypes.data))
         return out if self.qsets == 1 else out.reshape(Q.shape[0], self.qsets)
 
+    def bucket_table(self):
+        """(ucode, ustart, uoff, titem) of an index built with bucket tables."""
+        U = I64()
+        _check(lib().nrlsh_get_bucket_table(self.handle, C.byref(U), None, None, None, None))
+        ucode = np.empty(U.value, dtype=np.uint64)
+        ustart = np.empty(U.value + 1, dtype=np.int64)
+        uoff = np.empty(self.m + 1, dtype=np.int64)
+        titem = np.empty(self.n, dtype=np.int32)
+        _check(lib().nrlsh_get_bucket_table(self.handle, C.byref(U), ucode.ctypes.data,
+                                            ustart.ctypes.data, uoff.ctypes.data, titem.ctypes.data))
+        return ucode, ustart, uoff, titem
+
     def query_candidates(self, queries, probe_budget: int) -> np.ndarray:
         Q = _host_f32(queries)
         Tq = min(int(probe_budget), self.n)
@@ -302,32 +323,34 @@ class Index:
 # ------------------------------------------------------------------ C-ABI names
 def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None,
                 hash_storage: str = "fp32", margin="rigorous", partition: str = "percentile",
-                projections: str = "shared") -> Index:
+                projections: str = "shared", bucket_tables: bool = False) -> Index:
     """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
     tensor (n, d) float32 (device pointer, torch's current stream).
     ``hash_storage`` ("fp32", "bf16", "fp8") selects the precision form of the
     hash GEMM; ``margin`` is "rigorous" or a relative margin (float);
     ``partition`` is "percentile" (Algorithm 1) or "uniform" (Section 5);
     ``projections`` is "shared" (one matrix for all sub-datasets) or
-    "per_subset" (an independent block per sub-dataset)."""
+    "per_subset" (an independent block per sub-dataset); ``bucket_tables``
+    also builds the tables that probe="table" queries read."""
     h = P()
     st = STORAGES[hash_storage]
     part = PARTITIONS[partition]
     proj = PROJECTIONS[projections]
+    tabs = 1 if bucket_tables else 0
     mmode, mparam = (0, 0.0) if margin == "rigorous" else (1, float(margin))
     if _is_torch_device(items):
         if items.dtype.__str__() != "torch.float32" or items.dim() != 2:
             raise ValueError("items must be a 2-D float32 tensor")
         items = items.contiguous()
         opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps), st,
-                         mmode, mparam, part, proj)
+                         mmode, mparam, part, proj, tabs)
         _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
                                     seed, C.byref(opts), C.byref(h)))
     else:
         X = _host_f32(items)
-        if eps != 0.0 or stream is not None or st != 0 or part != 0 or proj != 0:
+        if eps != 0.0 or stream is not None or st != 0 or part != 0 or proj != 0 or tabs:
             opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam, part,
-                             proj)
+                             proj, tabs)
             _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
                                         C.byref(opts), C.byref(h)))
         else:
@@ -337,13 +360,14 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
 
 
 def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None,
-                rerank: str = "auto", rerank_storage: str = "fp32"):
+                rerank: str = "auto", rerank_storage: str = "fp32", probe: str = "scan"):
     """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
     numpy for host queries, torch tensors for CUDA torch queries.  ``rerank``
-    selects the re-rank mode ("auto", "gather", "screen"); all give the same
-    result."""
+    selects the re-rank mode ("auto", "gather", "screen", ...), ``probe`` how
+    the probed items are found ("scan" or "table"); all give the same result."""
     mode = RERANK_MODES[rerank]
     rst = STORAGES[rerank_storage]
+    prb = PROBES[probe]
     if _is_torch_device(queries):
         import torch
         Q = queries.contiguous()
@@ -353,7 +377,7 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
             ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         else:
             ids, ips = out
-        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst)
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst, prb)
         _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
                                     C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
         return ids, ips
@@ -361,8 +385,8 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
     nq = Q.shape[0]
     ids = np.empty((nq, k), dtype=np.int64)
     ips = np.empty((nq, k), dtype=np.float32)
-    if mode or rst or stream is not None:
-        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst)
+    if mode or rst or prb or stream is not None:
+        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst, prb)
         _check(lib().nrlsh_query_ex(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                     C.byref(opts), ids.ctypes.data, ips.ctypes.data))
     else:
@@ -373,7 +397,7 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
 
 class MultiPlan:
     """Owns an ``nrlsh_multi_plan*``: the batching form for a fixed set of
-    (index, query batch, probe budget) pairs, served by one persistent launch.
+    (index, query batch, probe budget) pairs, served by one graph of phase launches.
 
     ``pairs`` is a list of (Index, queries, probe_budget); the queries are all
     CUDA torch tensors (device pointers, torch's current stream) or all host
@@ -500,7 +524,9 @@ def nrlsh_get_query_stats() -> dict:
             "screen_passes": st.screen_passes, "kept_total": st.kept_total,
             "kept_max": st.kept_max, "theta_unset": st.theta_unset,
             "lp_kept_total": st.lp_kept_total, "lp_kept_max": st.lp_kept_max,
-            "lp_fallbacks": st.lp_fallbacks}
+            "lp_fallbacks": st.lp_fallbacks, "probe": {1: "table"}.get(st.probe_mode, "scan"),
+            "table_lookups": st.table_lookups, "table_walked": st.table_walked,
+            "table_passes": st.table_passes}
 
 
 def nrlsh_profile_enable(on: bool = True):

@@ -296,6 +296,13 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                  oR = B.reserve<int32_t>((size_t)m * (L + 1)),
                  oinv = B.reserve<int32_t>((size_t)m * (L + 1)),
                  ocodes = B.reserve<uint32_t>((size_t)n * W);
+    // bucket tables: room for n distinct codes (the actual count is known after the build)
+    const bool tab = ix->has_table;
+    const size_t otc = B.reserve<uint64_t>(tab ? (size_t)n : 1),
+                 ots = B.reserve<int32_t>(tab ? (size_t)n + 1 : 1),
+                 oto = B.reserve<int32_t>(tab ? (size_t)m + 1 : 1),
+                 oti = B.reserve<int32_t>(tab ? (size_t)n : 1),
+                 otb = B.reserve<uint64_t>(tab ? table_binom_words() : 1);
     B.allocate(s);
     ix->Xl = B.view<float>(oXl);
     ix->Xh = B.view<uint16_t>(oXh);
@@ -313,6 +320,13 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     ix->R = B.view<int32_t>(oR);
     ix->inv = B.view<int32_t>(oinv);
     ix->codes_l = B.view<uint32_t>(ocodes);
+    if (tab) {
+        ix->ucode = B.view<uint64_t>(otc);
+        ix->ustart = B.view<int32_t>(ots);
+        ix->uoff = B.view<int32_t>(oto);
+        ix->titem = B.view<int32_t>(oti);
+        ix->binom = B.view<uint64_t>(otb);
+    }
 
     // build-time scratch, one block
     Block T;
@@ -322,7 +336,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                  octr = T.reserve<BuildCounters>(1),
                  ostg = T.reserve<float>(on_device ? 1 : (size_t)n * d),
                  obnd = T.reserve<double>(m), osub = T.reserve<int32_t>(m),
-                 obst = T.reserve<int32_t>((size_t)m + 1);
+                 obst = T.reserve<int32_t>((size_t)m + 1),
+                 otbs = T.reserve<int32_t>(tab ? table_scan_words(n) + 1 : 1);
     T.allocate(s);
     DBuf<float> tau = T.view<float>(otau);
     DBuf<uint64_t> ka = T.view<uint64_t>(oka), kb = T.view<uint64_t>(okb);
@@ -363,6 +378,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     // uniform ranges (Section 5): boundaries from the smallest and largest
     // key, b_j = nmin + j w, compared with the keys as b_j^2
     const bool uniform = ix->partition == NRLSH_PARTITION_UNIFORM && m > 1;
+    std::vector<double> bnd_h;  // outlives its copy (the stream is synchronised below)
     if (uniform) {
         double kext[2];
         HIPX(hipMemcpyAsync(&kext[0], sk, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -370,12 +386,12 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         HIPX(hipStreamSynchronize(s));
         const double nmin = std::sqrt(kext[0]), nmax = std::sqrt(kext[1]);
         const double w = (nmax - nmin) / (double)m;
-        std::vector<double> bh((size_t)m - 1);
+        bnd_h.resize((size_t)m - 1);
         for (int j = 1; j < m; ++j) {
             const double b = nmin + (double)j * w;
-            bh[(size_t)j - 1] = b * b;
+            bnd_h[(size_t)j - 1] = b * b;
         }
-        HIPX(hipMemcpyAsync(bounds.get(), bh.data(), bh.size() * sizeof(double),
+        HIPX(hipMemcpyAsync(bounds.get(), bnd_h.data(), bnd_h.size() * sizeof(double),
                             hipMemcpyHostToDevice, s));
     }
     HIPX(hipMemsetAsync(ix->keymax.get(), 0, m * sizeof(double), s));
@@ -435,10 +451,10 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(hipMemsetAsync(ix->Xlo.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
+    std::vector<int32_t> bstart_h((size_t)m + 1, 0);  // outlives its copy
     if (ix->storage == NRLSH_STORAGE_FP32 && ix->qsets > 1) {
         // one projection block per sub-dataset: the launch's blocks are dealt
         // out sub-dataset by sub-dataset (first block of j = bstart[j])
-        std::vector<int32_t> bstart_h((size_t)m + 1, 0);
         const int per_block = hash_items_per_block();
         for (int j = 0; j < m; ++j) {
             const int64_t nj = ix->off_h[j + 1] - ix->off_h[j];
@@ -466,6 +482,40 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                            ix->sid_l.get(), ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(),
                            ix->codes_l.get(), n, s));
     tm.end();
+
+    // host sources of the copies below outlive them (synchronised at the end)
+    std::vector<uint64_t> bh;
+    std::vector<int32_t> uo;
+    int32_t nn = (int32_t)n;
+    if (tab) {
+        // bucket tables over the final codes (the sort buffers are free again)
+        DBuf<int32_t> tbs = T.view<int32_t>(otbs);
+        int32_t *total_d = tbs.get() + table_scan_words(n);
+        tm.begin("table");
+        HIPX(launch_table_build(ix->codes_l.get(), ix->sid_l.get(), n, m, L, ka.get(), va.get(), kb.get(),
+                                vb.get(), rtmp.get(), tbs.get(), total_d, ix->titem.get(),
+                                ix->ucode.get(), ix->ustart.get(), ix->uoff.get(), s));
+        tm.end();
+        bh.resize(table_binom_words());
+        table_binom(bh.data());
+        HIPX(hipMemcpyAsync(ix->binom.get(), bh.data(), bh.size() * sizeof(uint64_t),
+                            hipMemcpyHostToDevice, s));
+        int32_t U = 0;
+        uo.resize((size_t)m + 1);
+        HIPX(hipMemcpyAsync(&U, total_d, sizeof U, hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(uo.data(), ix->uoff.get(), (size_t)m * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        // empty sub-datasets (no run written) start where the next one starts
+        uo[m] = U;
+        for (int j = m - 1; j >= 0; --j)
+            if (ix->off_h[j + 1] == ix->off_h[j]) uo[j] = uo[j + 1];
+        ix->nunique = U;
+        ix->uoff_h.assign(uo.begin(), uo.end());
+        HIPX(hipMemcpyAsync(ix->uoff.get(), uo.data(), uo.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+        HIPX(hipMemcpyAsync(ix->ustart.get() + U, &nn, sizeof nn, hipMemcpyHostToDevice, s));
+    }
 
     HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
     HIPX(hipStreamSynchronize(s));
@@ -525,16 +575,19 @@ QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
 
 // Gather path: materialise each query's probed list, then re-rank it.  When
 // cand_out_d is given, the probed stored positions are copied there (nq x Tq)
-// and the re-rank is skipped.
+// and the re-rank is skipped.  With `table` the probed lists come from the
+// bucket tables instead of the scans.
 void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
                       int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
-                      hipStream_t s, Timer &tm, uint32_t *nonfinite_d, bool bf16_rows = false)
+                      hipStream_t s, Timer &tm, uint32_t *nonfinite_d, bool bf16_rows = false,
+                      bool table = false)
 {
     const QueryShape sh = make_shape(ix, T, k);
     // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^29 entries
     int64_t B = (int64_t(1) << 29) / sh.Tq;
     B = std::max<int64_t>(64, B / 64 * 64);
     B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
+    if (table) B = std::min<int64_t>(B, 16384);  // bounds the per-query bucket scratch
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
     const int nsplit = rerank_splits(B, sh.Tq);
@@ -544,7 +597,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     // the scans take chunks of a sub-dataset per wave (about 16k waves)
     int64_t maxsub = 0;
     for (int j = 0; j < sh.m; ++j) maxsub = std::max(maxsub, ix->off_h[j + 1] - ix->off_h[j]);
-    const bool chunked = !cand_out_d && tiles * sh.m < 4096 && maxsub > 4096;
+    const bool chunked = !table && !cand_out_d && tiles * sh.m < 4096 && maxsub > 4096;
     int chunk = 0, nch = 1;
     if (chunked) {
         const int64_t want = (maxsub * tiles * sh.m + 16383) / 16384;
@@ -553,16 +606,19 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     }
     Block blk;
     const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.qsets * sh.W),
-                 o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
+                 o_gh = blk.reserve<uint32_t>(table ? 1 : (size_t)tiles * sh.m * L1 * 64),
                  o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
                  o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
                  o_ti = blk.reserve<int32_t>((size_t)tiles * 4 * 64),
                  o_ca = blk.reserve<int32_t>(cand_out_d ? 1 : (size_t)B * sh.Tq),
+                 o_qs = blk.reserve<int32_t>(table ? (size_t)B * sh.m : 1),
+                 o_qhi = blk.reserve<int32_t>(table ? (size_t)B * sh.m * L1 : 1),
+                 o_tc = blk.reserve<uint8_t>(table ? table_counter_bytes() : 1),
                  o_pv = blk.reserve<double>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_lc = blk.reserve<int32_t>(bf16_rows ? (size_t)B : 1),
                  o_gt = blk.reserve<unsigned long long>(bf16_rows ? (size_t)B : 1),
-                 o_ps = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
+                 o_ps = blk.reserve<int32_t>(chunked || table ? (size_t)B : 1),
                  o_ct = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
                  o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
                  o_lv = blk.reserve<double>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
@@ -578,6 +634,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<int32_t> gpstar = blk.view<int32_t>(o_ps), ccount = blk.view<int32_t>(o_ct);
     DBuf<double> lpart_v = blk.view<double>(o_lv);
     DBuf<int32_t> lpart_i = blk.view<int32_t>(o_lp);
+    DBuf<int32_t> qstate = blk.view<int32_t>(o_qs), qhist = blk.view<int32_t>(o_qhi);
+    DBuf<uint8_t> tctr = blk.view<uint8_t>(o_tc);
+    const TableView tv{ix->ucode.get(), ix->ustart.get(), ix->uoff.get(), ix->titem.get(), ix->binom.get()};
+    if (table) HIPX(hipMemsetAsync(tctr.get(), 0, table_counter_bytes(), s));
     std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
@@ -588,34 +648,51 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qc, nonfinite_d, s));
         tm.end();
         const int64_t tb = (nb + 63) / 64;
-        tm.begin("scan_hist");
-        if (chunked) {
-            HIPX(hipMemsetAsync(ghist.get(), 0, (size_t)tb * sh.m * L1 * 64 * sizeof(uint32_t), s));
-            HIPX(launch_scan_hist_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
-                                    ghist.get(), s));
-        } else {
-            HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
-        }
-        tm.end();
-        tm.begin("threshold");
-        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
-                              ghthr.get(), gtie.get(), s));
-        tm.end();
-        if (chunked) {
+        if (table) {
+            HIPX(hipMemsetAsync(qstate.get(), 0, (size_t)nb * sh.m * sizeof(int32_t), s));
+            tm.begin("table_count");
+            HIPX(launch_table_count(tv, ix->R.get(), ix->inv.get(), qc, nb, sh, qstate.get(), qhist.get(),
+                                    ghthr.get(), gtie.get(), tctr.get(), s));
+            tm.end();
             tm.begin("tie_locate");
             HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
                                    gpstar.get(), s));
             tm.end();
-            HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
+            tm.begin("table_emit");
+            HIPX(launch_table_emit(tv, qc, nb, sh, qstate.get(), ghthr.get(), gtie.get(), gpstar.get(),
+                                   cb, s));
+            tm.end();
         }
-        tm.begin("scan_emit");
-        if (chunked)
-            HIPX(launch_scan_emit_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
-                                    ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
-        else
-            HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
-                                  ghthr.get(), gtie.get(), cb, s));
-        tm.end();
+        if (!table) {
+            tm.begin("scan_hist");
+            if (chunked) {
+                HIPX(hipMemsetAsync(ghist.get(), 0, (size_t)tb * sh.m * L1 * 64 * sizeof(uint32_t), s));
+                HIPX(launch_scan_hist_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
+                                        ghist.get(), s));
+            } else {
+                HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
+            }
+            tm.end();
+            tm.begin("threshold");
+            HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
+                                  ghthr.get(), gtie.get(), s));
+            tm.end();
+            if (chunked) {
+                tm.begin("tie_locate");
+                HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets,
+                                       gtie.get(), gpstar.get(), s));
+                tm.end();
+                HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
+            }
+            tm.begin("scan_emit");
+            if (chunked)
+                HIPX(launch_scan_emit_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
+                                        ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
+            else
+                HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
+                                      ghthr.get(), gtie.get(), cb, s));
+            tm.end();
+        }
         if (cand_out_d) continue;
         if (bf16_rows) {
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
@@ -651,6 +728,14 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, nullptr, nsplit,
                            part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
         tm.end();
+    }
+    if (table) {
+        unsigned long long c[3] = {0, 0, 0};
+        HIPX(hipMemcpyAsync(c, tctr.get(), sizeof c, hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        g_qstats.table_lookups = (int64_t)c[0];
+        g_qstats.table_walked = (int64_t)c[1];
+        g_qstats.table_passes = (int64_t)c[2];
     }
 }
 
@@ -816,13 +901,14 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
 }
 
 void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
-               bool bf16_rows, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+               bool bf16_rows, bool table, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
                uint32_t *nonfinite_d)
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
-    bool screen = mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
-                  mode == NRLSH_RERANK_SCREEN_BF16X3 ||
-                  (mode == NRLSH_RERANK_AUTO && Tq * 128 >= ix->n && nq >= 64 && Tq >= 2048);
+    g_qstats.probe_mode = table ? NRLSH_PROBE_TABLE : NRLSH_PROBE_SCAN;
+    bool screen = !table && (mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
+                             mode == NRLSH_RERANK_SCREEN_BF16X3 ||
+                             (mode == NRLSH_RERANK_AUTO && Tq * 128 >= ix->n && nq >= 64 && Tq >= 2048));
     const int kind = mode == NRLSH_RERANK_SCREEN_FP32     ? SCREEN_FP32
                      : mode == NRLSH_RERANK_SCREEN_BF16X3 ? SCREEN_BF16X3
                                                           : SCREEN_BF16;
@@ -835,7 +921,7 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
         run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d);
     else
         run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d,
-                         bf16_rows);
+                         bf16_rows, table);
 }
 
 }  // namespace
@@ -876,6 +962,10 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         return fail(NRLSH_E_INVALID_ARG, "per-subset projections need hash_storage FP32");
     if (projections == NRLSH_PROJECTIONS_PER_SUBSET && (int64_t)m * L > INT32_MAX / (d + 1))
         return fail(NRLSH_E_INVALID_ARG, "m L (d+1) too large for per-subset projections");
+    int32_t tables = 0;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, bucket_tables) + sizeof(int32_t)))
+        tables = opts->bucket_tables;
+    if (tables != 0 && tables != 1) return fail(NRLSH_E_INVALID_ARG, "bucket_tables must be 0 or 1");
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
         const int dev = current_device();
@@ -896,6 +986,7 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         ix->margin_param = margin_param;
         ix->partition = partition;
         ix->qsets = projections == NRLSH_PROJECTIONS_PER_SUBSET ? m : 1;
+        ix->has_table = tables == 1;
         ix->home = library_stream(dev);
         Timer tm(s);
         try {
@@ -938,6 +1029,16 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)) &&
         opts->rerank_storage != NRLSH_STORAGE_FP32 && opts->rerank_storage != NRLSH_STORAGE_BF16)
         return fail(NRLSH_E_INVALID_ARG, "rerank_storage %d unsupported", opts->rerank_storage);
+    bool table = false;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, probe_mode) + sizeof(int32_t))) {
+        if (opts->probe_mode != NRLSH_PROBE_SCAN && opts->probe_mode != NRLSH_PROBE_TABLE)
+            return fail(NRLSH_E_INVALID_ARG, "probe_mode %d unknown", opts->probe_mode);
+        table = opts->probe_mode == NRLSH_PROBE_TABLE;
+    }
+    if (table && !ix->has_table)
+        return fail(NRLSH_E_INVALID_ARG, "probe_mode TABLE needs an index built with bucket_tables = 1");
+    if (table && opts->rerank_mode != NRLSH_RERANK_AUTO && opts->rerank_mode != NRLSH_RERANK_GATHER)
+        return fail(NRLSH_E_INVALID_ARG, "probe_mode TABLE goes with the GATHER re-rank");
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
@@ -959,7 +1060,7 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)))
             bf16_rows = opts->rerank_storage == NRLSH_STORAGE_BF16;
         if (on_device) {
-            run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, out_ids, out_ips, s, tm,
+            run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, table, out_ids, out_ips, s, tm,
                       flag.get());
         } else {
             DBuf<float> Qd = blk.view<float>(o_q);
@@ -967,8 +1068,8 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
             DBuf<float> ips = blk.view<float>(o_p);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
-            run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, ids.get(), ips.get(), s, tm,
-                      flag.get());
+            run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, table, ids.get(), ips.get(), s,
+                      tm, flag.get());
             HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),
@@ -1001,6 +1102,27 @@ nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int
     *L = ix->L;
     *dp = ix->dp;
     return NRLSH_OK;
+}
+
+nrlsh_status nrlsh_get_bucket_table(const nrlsh_index *ix, int64_t *nunique, uint64_t *ucode,
+                                    int64_t *ustart, int64_t *uoff, int32_t *titem)
+{
+    if (!ix || !nunique) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    if (!ix->has_table) return fail(NRLSH_E_INVALID_ARG, "index built without bucket tables");
+    *nunique = ix->nunique;
+    if (!ucode) return NRLSH_OK;
+    if (!ustart || !uoff || !titem) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        const int64_t U = ix->nunique;
+        std::vector<int32_t> us((size_t)U + 1);
+        HIPX(hipMemcpy(ucode, ix->ucode.get(), (size_t)U * sizeof(uint64_t), hipMemcpyDeviceToHost));
+        HIPX(hipMemcpy(us.data(), ix->ustart.get(), us.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+        HIPX(hipMemcpy(titem, ix->titem.get(), (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToHost));
+        for (int64_t u = 0; u <= U; ++u) ustart[u] = us[(size_t)u];
+        for (int j = 0; j <= ix->m; ++j) uoff[j] = ix->uoff_h[(size_t)j];
+        return NRLSH_OK;
+    });
 }
 
 nrlsh_status nrlsh_get_projection_sets(const nrlsh_index *ix, int32_t *sets)

@@ -203,4 +203,10 @@ struct nrlsh_index {
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
     nrlsh::host::DBuf<int32_t> sid, sid_l, perm, off, R, inv;
     nrlsh::host::DBuf<uint32_t> codes_l;              // stored order
+    // bucket tables (built on request): distinct codes of each sub-dataset
+    bool has_table = false;
+    int64_t nunique = 0;
+    std::vector<int64_t> uoff_h;
+    nrlsh::host::DBuf<uint64_t> ucode, binom;
+    nrlsh::host::DBuf<int32_t> ustart, uoff, titem;
 };

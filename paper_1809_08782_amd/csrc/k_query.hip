@@ -31,14 +31,6 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
-// Row of the query-code array that holds query q's code for sub-dataset j:
-// one code per query with shared projections (qsets = 1), one per
-// (query, sub-dataset) with a projection block per sub-dataset (qsets = m).
-__device__ __forceinline__ int64_t qrow(int64_t q, int j, int qsets)
-{
-    return qsets > 1 ? q * qsets + j : q;
-}
-
 // ---------------------------------------------------------------- query_hash
 // One wave per (query, projection block), lane r computes bit r:
 // sum_t A[r][t] q_t in FP64 in ascending t (products of two floats are exact

@@ -97,6 +97,14 @@ hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int
                              uint32_t *codes_l, int64_t max_entries, hipStream_t s);
 
 // ------------------------------------------------------------------ query
+// Row of the query-code array that holds query q's code for sub-dataset j:
+// one code per query with shared projections (qsets = 1), one per
+// (query, sub-dataset) with a projection block per sub-dataset (qsets = m).
+__host__ __device__ inline int64_t qrow(int64_t q, int j, int qsets)
+{
+    return qsets > 1 ? q * qsets + j : q;
+}
+
 struct QueryShape {
     int64_t n;
     int d, dp, m, L, W;
@@ -204,6 +212,41 @@ hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xl
                          int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                          const int32_t *gtie, const int32_t *gpstar, const float *theta, int cap,
                          int32_t *counts, int32_t *lists, hipStream_t s);
+
+// ------------------------------------------------------------------ bucket tables
+// Read-only bucket table of an index (k_table.hip): titem = stored positions
+// sorted by (sub-dataset, code, position); ucode / ustart = the distinct
+// codes of each sub-dataset (ascending inside it) and the start of each one's
+// run in titem (ustart[U] = n); uoff[j] = first distinct code of
+// sub-dataset j (uoff[m] = U); binom = C(n, k) for n, k <= 64 (65 x 65).
+struct TableView {
+    const uint64_t *ucode;
+    const int32_t *ustart, *uoff, *titem;
+    const uint64_t *binom;
+};
+size_t table_binom_words();
+void table_binom(uint64_t *out);
+size_t table_scan_words(int64_t n);
+size_t table_counter_bytes();  // device counters of the table probe (3 x uint64)
+// Sorts (sub-dataset, code, position), compacts the distinct codes.  Writes
+// titem, ucode, ustart[0 .. U), and uoff[j] for non-empty sub-datasets; U goes
+// to *total.  ka / va / kb / vb: n-entry sort buffers; bsum: table_scan_words(n).
+hipError_t launch_table_build(const uint32_t *codes_l, const int32_t *sid_l, int64_t n, int m, int L,
+                              uint64_t *ka, int32_t *va, uint64_t *kb, int32_t *vb, void *sort_tmp,
+                              int32_t *bsum, int32_t *total, int32_t *titem, uint64_t *ucode,
+                              int32_t *ustart, int32_t *uoff, hipStream_t s);
+// Probe count: one wave per query walks the buckets in probing order until
+// Tq items; writes ghthr / gtie like launch_threshold.  qstate (nq x m,
+// zeroed by the caller) and qhist (nq x m x (L+1)) are per-query scratch;
+// counters (zeroed by the caller) gather lookup statistics.
+hipError_t launch_table_count(const TableView &T, const int32_t *R, const int32_t *inv,
+                              const uint32_t *qcodes, int64_t nq, const QueryShape &sh, int32_t *qstate,
+                              int32_t *qhist, int32_t *ghthr, int32_t *gtie, void *counters,
+                              hipStream_t s);
+// Emission of exactly Tq stored positions per query (order unspecified).
+hipError_t launch_table_emit(const TableView &T, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
+                             const int32_t *qstate, const int32_t *ghthr, const int32_t *gtie,
+                             const int32_t *gpstar, int32_t *cand, hipStream_t s);
 
 // ------------------------------------------------------------------ batching form
 // One (index, query batch) pair of a multi-index launch.  Index arrays are

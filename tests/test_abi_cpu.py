@@ -84,6 +84,24 @@ def test_build_rejects_bad_projections():
         assert "per-subset" in nr.nrlsh_last_error()
 
 
+def test_bucket_table_options_rejected():
+    X = np.ones((10, 4), np.float32)
+    h = C.c_void_p()
+    opts = _lib.BuildOpts(C.sizeof(_lib.BuildOpts), 0, None, 0.0, 0, 0, 0.0, 0, 0, 2)
+    assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
+    assert "bucket_tables" in nr.nrlsh_last_error()
+    U = C.c_int64()
+    assert nr.lib().nrlsh_get_bucket_table(None, C.byref(U), None, None, None, None) == INVALID
+    Q = np.ones((2, 4), np.float32)
+    ids = np.empty((2, 4), np.int64)
+    ips = np.empty((2, 4), np.float32)
+    fake = C.c_void_p(1)  # never dereferenced: the option check comes first
+    qo = _lib.QueryOpts(C.sizeof(_lib.QueryOpts), 0, None, 0, 0, 7)
+    assert nr.lib().nrlsh_query_ex(fake, Q.ctypes.data, 2, 4, 10, C.byref(qo), ids.ctypes.data,
+                                   ips.ctypes.data) == INVALID
+    assert "probe_mode" in nr.nrlsh_last_error()
+
+
 def test_query_rejects_bad_arguments():
     L = nr.lib()
     Q = np.ones((2, 4), np.float32)
