@@ -15,6 +15,7 @@
 #include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "host_common.h"
@@ -128,16 +129,29 @@ uint64_t splitmix64_at(uint64_t seed, uint64_t k)
 void make_projection(uint64_t seed, int L, int d, std::vector<float> &A)
 {
     A.resize((size_t)L * (d + 1));
-    for (int r = 0; r < L; ++r)
-        for (int c = 0; c <= d; ++c) {
-            const uint64_t t = (uint64_t)r * (uint64_t)(d + 1) + (uint64_t)c;
-            const uint64_t h1 = splitmix64_at(seed, 2u * t);
-            const uint64_t h2 = splitmix64_at(seed, 2u * t + 1u);
-            const double u1 = (double)((h1 >> 11) + 1u) * (1.0 / 9007199254740992.0);
-            const double u2 = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
-            const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
-            A[(size_t)r * (d + 1) + c] = (float)g;
-        }
+    auto rows = [&](int r0, int r1) {
+        for (int r = r0; r < r1; ++r)
+            for (int c = 0; c <= d; ++c) {
+                const uint64_t t = (uint64_t)r * (uint64_t)(d + 1) + (uint64_t)c;
+                const uint64_t h1 = splitmix64_at(seed, 2u * t);
+                const uint64_t h2 = splitmix64_at(seed, 2u * t + 1u);
+                const double u1 = (double)((h1 >> 11) + 1u) * (1.0 / 9007199254740992.0);
+                const double u2 = (double)(h2 >> 11) * (1.0 / 9007199254740992.0);
+                const double g = std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+                A[(size_t)r * (d + 1) + c] = (float)g;
+            }
+    };
+    // entries are independent (counter-based), so large matrices (one block
+    // per sub-dataset) are drawn by several host threads with the same result
+    const int64_t work = (int64_t)L * (d + 1);
+    const int nt = work < (1 << 16) ? 1 : (int)std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency()));
+    if (nt == 1) {
+        rows(0, L);
+        return;
+    }
+    std::vector<std::thread> th;
+    for (int i = 0; i < nt; ++i) th.emplace_back(rows, (int)((int64_t)L * i / nt), (int)((int64_t)L * (i + 1) / nt));
+    for (auto &t : th) t.join();
 }
 
 // ================================================================= rank table
@@ -270,11 +284,10 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     std::vector<float> At_h((size_t)rows * d), tau_h(rows);
     for (int r = 0; r < rows; ++r) {
         double nrm2 = 0.0;
-        const int blk = r / L, rr = r - blk * L;
         for (int c = 0; c <= d; ++c) {
             const double a = ix->A_h[(size_t)r * (d + 1) + c];
             nrm2 += a * a;
-            if (c < d) At_h[((size_t)blk * d + c) * L + rr] = (float)a;
+            if (c < d) At_h[(size_t)c * rows + r] = (float)a;
         }
         // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
         // rounded up so that the band is never narrower than the bound.
@@ -960,8 +973,8 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         return fail(NRLSH_E_INVALID_ARG, "projections %d unknown", projections);
     if (projections == NRLSH_PROJECTIONS_PER_SUBSET && storage != NRLSH_STORAGE_FP32)
         return fail(NRLSH_E_INVALID_ARG, "per-subset projections need hash_storage FP32");
-    if (projections == NRLSH_PROJECTIONS_PER_SUBSET && (int64_t)m * L > INT32_MAX / (d + 1))
-        return fail(NRLSH_E_INVALID_ARG, "m L (d+1) too large for per-subset projections");
+    if (projections == NRLSH_PROJECTIONS_PER_SUBSET && ((int64_t)m * L > INT32_MAX / (d + 1) || m > 65535))
+        return fail(NRLSH_E_INVALID_ARG, "per-subset projections need m <= 65535 and m L (d+1) < 2^31");
     int32_t tables = 0;
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, bucket_tables) + sizeof(int32_t)))
         tables = opts->bucket_tables;

@@ -32,35 +32,66 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 // ---------------------------------------------------------------- query_hash
-// One wave per (query, projection block), lane r computes bit r:
-// sum_t A[r][t] q_t in FP64 in ascending t (products of two floats are exact
-// in FP64).  At holds each block's A[:, :d] transposed (d x L) so that the
-// lanes read consecutive words.
-__global__ __launch_bounds__(256) void k_query_hash(const float *__restrict__ Q, int64_t nq, int d,
-                                                    const float *__restrict__ At_all, int L, int W,
-                                                    int qsets, uint32_t *__restrict__ qcodes,
-                                                    uint32_t *__restrict__ nonfinite)
+// Bit r of code (q, j) is the sign of sum_t A[jL + r][t] q_t, summed in FP64
+// in ascending t (products of two floats are exact in FP64).  At is
+// A[:, :d] transposed, d rows of qsets L floats, so that consecutive lanes
+// read consecutive words.  One wave per (QH_Q queries, group of cpw = 64 / L
+// codes, at least one): lane c L + r computes bit r of the group's code c for
+// all QH_Q queries at once (staged through LDS in tiles of QH_TD
+// coordinates), so each projection word read serves QH_Q queries.
+constexpr int QH_Q = 8;
+constexpr int QH_TD = 256;
+
+__global__ __launch_bounds__(64) void k_query_hash(const float *__restrict__ Q, int64_t nq, int d,
+                                                   const float *__restrict__ At, int L, int W,
+                                                   int qsets, uint32_t *__restrict__ qcodes,
+                                                   uint32_t *__restrict__ nonfinite)
 {
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * 4 + wave;  // = qrow(q, j, qsets)
-    if (row >= nq * qsets) return;
-    const int64_t q = row / qsets;
-    const float *At = At_all + (row - q * qsets) * (int64_t)d * L;
-    const float *qv = Q + q * d;
-    const bool act = lane < L;
-    double s = 0.0;
+    __shared__ float qs[QH_Q][QH_TD];
+    const int lane = threadIdx.x;
+    const int64_t q0 = (int64_t)blockIdx.x * QH_Q;
+    const int cpw = L <= 32 ? 64 / L : 1;
+    const int j0 = blockIdx.y * cpw;           // first code of this wave
+    const int c = lane / L, r = lane - c * L;  // code within the group, bit
+    const int j = j0 + c;
+    const bool act = c < cpw && j < qsets;
+    const int64_t R = (int64_t)qsets * L;
+    const int64_t col = (int64_t)j * L + r;
+    double acc[QH_Q];
+#pragma unroll
+    for (int i = 0; i < QH_Q; ++i) acc[i] = 0.0;
     bool bad = false;
-    for (int t = 0; t < d; ++t) {
-        const float qt = qv[t];
-        bad |= !__builtin_isfinite(qt);
-        const float a = act ? At[(int64_t)t * L + lane] : 0.f;
-        s = s + (double)a * (double)qt;
+    for (int t0 = 0; t0 < d; t0 += QH_TD) {
+        const int tn = min(QH_TD, d - t0);
+        __syncthreads();
+        for (int e = lane; e < QH_Q * QH_TD; e += 64) {
+            const int i = e / QH_TD, t = e - i * QH_TD;
+            float v = 0.f;
+            if (t < tn && q0 + i < nq) {
+                v = Q[(q0 + i) * d + t0 + t];
+                bad |= !__builtin_isfinite(v);
+            }
+            qs[i][t] = v;
+        }
+        __syncthreads();
+        for (int t = 0; t < tn; ++t) {
+            const double a = act ? (double)At[(int64_t)(t0 + t) * R + col] : 0.0;
+#pragma unroll
+            for (int i = 0; i < QH_Q; ++i) acc[i] = acc[i] + a * (double)qs[i][t];
+        }
     }
-    const uint64_t code = __ballot(act && s > 0.0);
-    if (lane == 0) {
-        qcodes[row * W] = (uint32_t)code;
-        if (W == 2) qcodes[row * W + 1] = (uint32_t)(code >> 32);
-        if (bad) atomicOr(nonfinite, 1u);
+    if (bad && blockIdx.y == 0) atomicOr(nonfinite, 1u);
+#pragma unroll
+    for (int i = 0; i < QH_Q; ++i) {
+        const uint64_t bits = __ballot(act && acc[i] > 0.0);
+        const int64_t q = q0 + i;
+        if (q < nq && lane < cpw && j0 + lane < qsets) {
+            // code `lane` of the group: bits lane L .. lane L + L - 1 of the ballot
+            const uint64_t code = L == 64 ? bits : (bits >> (lane * L)) & ((1ull << L) - 1ull);
+            const int64_t row = qrow(q, j0 + lane, qsets);
+            qcodes[row * W] = (uint32_t)code;
+            if (W == 2) qcodes[row * W + 1] = (uint32_t)(code >> 32);
+        }
     }
 }
 
@@ -107,45 +138,86 @@ __global__ __launch_bounds__(64) void k_scan_hist(const uint32_t *__restrict__ c
 }
 
 // ---------------------------------------------------------------- threshold
-// One wave per query tile (lane = query).  inv[b] is the histogram index
-// j*(L+1) + h of the bucket with probing rank b.
-__global__ __launch_bounds__(64) void k_threshold(const uint32_t *__restrict__ ghist,
-                                                  const int32_t *__restrict__ R,
-                                                  const int32_t *__restrict__ inv, int64_t nq,
-                                                  int m, int L, int64_t Tq,
-                                                  int32_t *__restrict__ gbase,
-                                                  int32_t *__restrict__ ghthr,
-                                                  int32_t *__restrict__ gtie)
+// One block of TH_WAVES waves per 64-query tile (lane = query).  inv[b] is
+// the histogram index j (L+1) + h of the bucket with probing rank b.
+//   1. Wave w sums the bucket counts of its contiguous share of the probing
+//      order; the wave whose share holds a lane's crossing of Tq walks that
+//      share again to find the threshold bucket b*, the items r* still
+//      probed in it and its (j*, h*).
+//   2. The sub-datasets are shared out among the waves: for each j,
+//      hthr = #{h : rank(j, h) < b*} - 1 by binary search (ranks grow with h
+//      inside a sub-dataset), the items probed in j, and their exclusive
+//      prefix over j (the emission offsets gbase).
+constexpr int TH_WAVES = 16;
+
+__device__ __forceinline__ int wave_max_int(int v)
 {
-    const int lane = threadIdx.x, tile = blockIdx.x;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__restrict__ ghist,
+                                                             const int32_t *__restrict__ R,
+                                                             const int32_t *__restrict__ inv, int64_t nq,
+                                                             int m, int L, int64_t Tq,
+                                                             int32_t *__restrict__ gbase,
+                                                             int32_t *__restrict__ ghthr,
+                                                             int32_t *__restrict__ gtie)
+{
+    __shared__ int64_t seg_s[TH_WAVES][64];
+    __shared__ int32_t res_s[5][64];  // b*, r*, j*, h*, whole
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, tile = blockIdx.x;
     const int64_t q = (int64_t)tile * 64 + lane;
     const bool valid = q < nq;
     const int L1 = L + 1;
     const int64_t P = (int64_t)m * L1;
     const uint32_t *H = ghist + (int64_t)tile * P * 64;
 
+    // 1a. sum of this wave's share of the probing order
+    const int64_t b0 = P * wave / TH_WAVES, b1 = P * (wave + 1) / TH_WAVES;
+    int64_t sum = 0;
+    int64_t b = b0;
+    for (; b + 16 <= b1; b += 16) {
+        uint32_t c[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u] = H[(int64_t)inv[b + u] * 64 + lane];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += c[u];
+    }
+    for (; b < b1; ++b) sum += H[(int64_t)inv[b] * 64 + lane];
+    seg_s[wave][lane] = sum;
+    if (wave == 0) {
+        res_s[0][lane] = -1;
+        res_s[1][lane] = 0;
+        res_s[2][lane] = -1;
+        res_s[3][lane] = -1;
+        res_s[4][lane] = 0;
+    }
+    __syncthreads();
     int64_t cum = 0;
-    int32_t bstar = -1, rstar = 0, jstar = -1, hstar = -1;
-    bool rfull = false;  // the budget ends exactly at the end of bucket b*
-    bool done = !valid;
-    for (int64_t b = 0; b < P; b += 16) {
-        if (__ballot(!done) == 0ull) break;
+    for (int w = 0; w < wave; ++w) cum += seg_s[w][lane];
+
+    // 1b. the wave holding the crossing finds b*
+    bool done = !(valid && cum < Tq && cum + sum >= Tq);
+    for (b = b0; b < b1 && __ballot(!done) != 0ull; b += 16) {
         int32_t io[16];
         uint32_t c[16];
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            io[u] = (b + u < P) ? inv[b + u] : 0;
-            c[u] = (b + u < P) ? H[(int64_t)io[u] * 64 + lane] : 0u;
+            io[u] = (b + u < b1) ? inv[b + u] : 0;
+            c[u] = (b + u < b1) ? H[(int64_t)io[u] * 64 + lane] : 0u;
         }
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            if (!done && b + u < P) {
+            if (!done && b + u < b1) {
                 if (cum + (int64_t)c[u] >= Tq) {
-                    bstar = (int32_t)(b + u);
-                    rstar = (int32_t)(Tq - cum);
-                    rfull = cum + (int64_t)c[u] == Tq;
-                    jstar = io[u] / L1;
-                    hstar = io[u] - jstar * L1;
+                    const int jj = io[u] / L1;
+                    res_s[0][lane] = (int32_t)(b + u);
+                    res_s[1][lane] = (int32_t)(Tq - cum);
+                    res_s[2][lane] = jj;
+                    res_s[3][lane] = io[u] - jj * L1;
+                    res_s[4][lane] = cum + (int64_t)c[u] == Tq;  // the budget ends with the bucket
                     done = true;
                 } else {
                     cum += c[u];
@@ -153,29 +225,49 @@ __global__ __launch_bounds__(64) void k_threshold(const uint32_t *__restrict__ g
             }
         }
     }
+    __syncthreads();
+    const int32_t bstar = res_s[0][lane], rstar = res_s[1][lane], jstar = res_s[2][lane];
 
-    int32_t run = 0;
-    for (int j = 0; j < m; ++j) {
-        int hthr = -1;
-        int32_t cnt = 0;
-        if (valid) {
-            int nl = 0;
-            for (int l = 0; l <= L; ++l) nl += (R[(int64_t)j * L1 + l] < bstar) ? 1 : 0;
-            hthr = nl - 1;
-            const uint32_t *Hj = H + (int64_t)j * L1 * 64;
-            for (int h = 0; h <= hthr; ++h) cnt += (int32_t)Hj[h * 64 + lane];
-            if (j == jstar) cnt += rstar;
+    // 2. per-sub-dataset bounds and emission offsets
+    const int ja = (int)((int64_t)m * wave / TH_WAVES), jb = (int)((int64_t)m * (wave + 1) / TH_WAVES);
+    int64_t run = 0;
+    for (int j = ja; j < jb; ++j) {
+        int lo = 0, hi = valid ? L1 : 0;
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (R[(int64_t)j * L1 + (L - mid)] < bstar) lo = mid + 1;
+            else hi = mid;
         }
-        gbase[((int64_t)tile * (m + 1) + j) * 64 + lane] = run;
+        const int hthr = lo - 1;
+        const int hmax = wave_max_int(hthr);
+        const uint32_t *Hj = H + (int64_t)j * L1 * 64;
+        int64_t cnt = 0;
+        for (int h = 0; h <= hmax; ++h) {
+            const uint32_t v = Hj[h * 64 + lane];
+            if (h <= hthr) cnt += v;
+        }
+        if (j == jstar) cnt += rstar;
+        gbase[((int64_t)tile * (m + 1) + j) * 64 + lane] = (int32_t)run;  // offset inside this wave's range
         ghthr[((int64_t)tile * m + j) * 64 + lane] = hthr;
         run += cnt;
     }
-    gbase[((int64_t)tile * (m + 1) + m) * 64 + lane] = run;
-    int32_t *tie = gtie + (int64_t)tile * 4 * 64;
-    tie[0 * 64 + lane] = valid ? jstar : -1;
-    tie[1 * 64 + lane] = hstar;
-    tie[2 * 64 + lane] = rfull ? INT_MAX : rstar;  // INT_MAX: every item of the bucket
-    tie[3 * 64 + lane] = bstar;
+    __syncthreads();  // every wave is done with seg_s
+    seg_s[wave][lane] = run;
+    __syncthreads();
+    int64_t offs = 0;
+    for (int w = 0; w < wave; ++w) offs += seg_s[w][lane];
+    for (int j = ja; j < jb; ++j) {
+        int32_t *g = gbase + ((int64_t)tile * (m + 1) + j) * 64 + lane;
+        *g = (int32_t)(*g + offs);  // this lane wrote *g above
+    }
+    if (wave == TH_WAVES - 1) gbase[((int64_t)tile * (m + 1) + m) * 64 + lane] = (int32_t)(offs + run);
+    if (wave == 0) {
+        int32_t *tie = gtie + (int64_t)tile * 4 * 64;
+        tie[0 * 64 + lane] = valid ? jstar : -1;
+        tie[1 * 64 + lane] = res_s[3][lane];
+        tie[2 * 64 + lane] = res_s[4][lane] ? INT_MAX : rstar;  // INT_MAX: every item of the bucket
+        tie[3 * 64 + lane] = bstar;
+    }
 }
 
 // ---------------------------------------------------------------- scan pass 2
@@ -527,51 +619,72 @@ __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ pa
 // Stored position of the r*-th item of the threshold bucket (j*, h*) of each
 // query: with it the probed set becomes a per-pair predicate,
 //   p in C_T  <=>  h <= hthr[q][j]  or  (j = j*, h = h*, p <= P*).
-// One wave per query walks sub-dataset j* 64 items at a time; a bucket that
-// is probed whole (r* = INT_MAX) needs no walk.
+// One block per query: each of its TL_WAVES waves counts the bucket's items
+// in a contiguous share of sub-dataset j*, and the wave whose share holds
+// the r*-th one walks it again to find its position; a bucket that is probed
+// whole (r* = INT_MAX) needs no walk.
+constexpr int TL_WAVES = 16;
+
 template <int W>
-__global__ __launch_bounds__(256) void k_tie_locate(const uint32_t *__restrict__ codes_l,
-                                                    const int32_t *__restrict__ off,
-                                                    const uint32_t *__restrict__ qcodes,
-                                                    int64_t nq, int qsets,
-                                                    const int32_t *__restrict__ gtie,
-                                                    int32_t *__restrict__ gpstar)
+__global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__restrict__ codes_l,
+                                                              const int32_t *__restrict__ off,
+                                                              const uint32_t *__restrict__ qcodes,
+                                                              int64_t nq, int qsets,
+                                                              const int32_t *__restrict__ gtie,
+                                                              int32_t *__restrict__ gpstar)
 {
+    __shared__ int32_t cnt_s[TL_WAVES];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t q = (int64_t)blockIdx.x * 4 + wave;
-    if (q >= nq) return;
+    const int64_t q = blockIdx.x;
     const int tile = (int)(q >> 6), ql = (int)(q & 63);
     const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
     const int jstar = tie[ql], hstar = tie[64 + ql], rstar = tie[128 + ql];
-    int32_t P = -1;
-    if (jstar >= 0 && rstar == INT_MAX) {
-        P = INT_MAX;
-    } else if (jstar >= 0) {
-        const int64_t r = qrow(q, jstar, qsets);
-        const uint32_t q0 = qcodes[r * W], q1 = W == 2 ? qcodes[r * W + 1] : 0u;
-        const int64_t pe = off[jstar + 1];
-        int cnt = 0;
-        for (int64_t p0 = off[jstar]; p0 < pe; p0 += 64) {
-            const int64_t p = p0 + lane;
-            bool match = false;
-            if (p < pe) {
-                int h = __popc(codes_l[p * W] ^ q0);
-                if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
-                match = h == hstar;
-            }
-            const uint64_t bal = __ballot(match);
-            const int c = __popcll(bal);
-            if (cnt + c >= rstar) {
-                const int need = rstar - cnt;  // 1-based rank inside this group
+    if (jstar < 0 || rstar == INT_MAX) {  // the same for the whole block: no barrier is skipped
+        if (threadIdx.x == 0) gpstar[q] = jstar < 0 ? -1 : INT_MAX;
+        return;
+    }
+    const int64_t r = qrow(q, jstar, qsets);
+    const uint32_t q0 = qcodes[r * W], q1 = W == 2 ? qcodes[r * W + 1] : 0u;
+    const int64_t ps = off[jstar], pe = off[jstar + 1];
+    const int64_t ng = (pe - ps + 63) / 64;  // 64-item groups, a contiguous share per wave
+    const int64_t g0 = ng * wave / TL_WAVES, g1 = ng * (wave + 1) / TL_WAVES;
+    auto match = [&](int64_t p) {
+        if (p >= pe) return false;
+        int h = __popc(codes_l[p * W] ^ q0);
+        if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+        return h == hstar;
+    };
+    int cnt = 0;
+    int64_t g = g0;
+    for (; g + 4 <= g1; g += 4) {
+        bool mt[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) mt[u] = match(ps + (g + u) * 64 + lane);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) cnt += __popcll(__ballot(mt[u]));
+    }
+    for (; g < g1; ++g) cnt += __popcll(__ballot(match(ps + g * 64 + lane)));
+    if (lane == 0) cnt_s[wave] = cnt;
+    if (threadIdx.x == 0) gpstar[q] = -1;  // replaced below by the wave that finds the item
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += cnt_s[w];
+    if (before < rstar && before + cnt >= rstar) {  // wave-uniform: the r*-th match is in this share
+        int c = before;
+        for (g = g0; g < g1; ++g) {
+            const int64_t p0 = ps + g * 64;
+            const uint64_t bal = __ballot(match(p0 + lane));
+            const int k = __popcll(bal);
+            if (c + k >= rstar) {
+                const int need = rstar - c;  // 1-based rank inside this group
                 const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-                const uint64_t sel = __ballot(match && rank == need - 1);
-                P = (int32_t)(p0 + __ffsll((long long)sel) - 1);
+                const uint64_t sel = __ballot(((bal >> lane) & 1ull) && rank == need - 1);
+                if (lane == 0) gpstar[q] = (int32_t)(p0 + __ffsll((long long)sel) - 1);
                 break;
             }
-            cnt += c;
+            c += k;
         }
     }
-    if (lane == 0) gpstar[q] = P;
 }
 
 // ---------------------------------------------------------------- screen
@@ -1040,8 +1153,10 @@ hipError_t launch_query_hash(const float *Q, int64_t nq, int d, const float *At,
                              int qsets, uint32_t *qcodes, uint32_t *nonfinite, hipStream_t s)
 {
     if (nq < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_query_hash, dim3(ceil_div(nq * qsets, 4)), dim3(256), 0, s, Q, nq, d, At, L,
-                       W, qsets, qcodes, nonfinite);
+    const int cpw = L <= 32 ? 64 / L : 1;
+    const dim3 grid(ceil_div(nq, QH_Q), ceil_div(qsets, cpw));
+    hipLaunchKernelGGL(k_query_hash, grid, dim3(64), 0, s, Q, nq, d, At, L, W, qsets, qcodes,
+                       nonfinite);
     return hipGetLastError();
 }
 
@@ -1063,7 +1178,7 @@ hipError_t launch_threshold(const uint32_t *ghist, const int32_t *R, const int32
                             const QueryShape &sh, int32_t *gbase, int32_t *ghthr, int32_t *gtie,
                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_threshold, dim3(ceil_div(nq, 64)), dim3(64), 0, s, ghist, R, inv, nq, sh.m,
+    hipLaunchKernelGGL(k_threshold, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv, nq, sh.m,
                        sh.L, sh.Tq, gbase, ghthr, gtie);
     return hipGetLastError();
 }
@@ -1120,10 +1235,10 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
                              hipStream_t s)
 {
     if (W == 1)
-        hipLaunchKernelGGL(k_tie_locate<1>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
+        hipLaunchKernelGGL(k_tie_locate<1>, dim3((unsigned)nq), dim3(TL_WAVES * 64), 0, s, codes_l, off,
                            qcodes, nq, qsets, gtie, gpstar);
     else
-        hipLaunchKernelGGL(k_tie_locate<2>, dim3(ceil_div(nq, 4)), dim3(256), 0, s, codes_l, off,
+        hipLaunchKernelGGL(k_tie_locate<2>, dim3((unsigned)nq), dim3(TL_WAVES * 64), 0, s, codes_l, off,
                            qcodes, nq, qsets, gtie, gpstar);
     return hipGetLastError();
 }
