@@ -630,7 +630,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_pv = blk.reserve<double>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_lc = blk.reserve<int32_t>(bf16_rows ? (size_t)B : 1),
-                 o_gt = blk.reserve<unsigned long long>(bf16_rows ? (size_t)B : 1),
+                 o_gt = blk.reserve<unsigned long long>((size_t)B),
                  o_ps = blk.reserve<int32_t>(chunked || table ? (size_t)B : 1),
                  o_ct = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
                  o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
@@ -737,9 +737,11 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             }
             g_qstats.lp_fallbacks += 1;  // a list overflowed: re-rank this batch from FP32 rows
         }
+        if (nsplit > 1) HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
         tm.begin("rerank");
         HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, nullptr, nsplit,
-                           part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s));
+                           part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s,
+                           gtheta.get()));
         tm.end();
     }
     if (table) {

@@ -52,10 +52,11 @@ struct WaveTopK {
         kl = (k - 1) & 63;
     }
 
-    // Offer one value per lane (ok = lane has a real candidate).
-    __device__ void offer(double v, int32_t id, bool ok, int lane)
+    // Offer one value per lane (ok = lane has a real candidate).  Values
+    // below `floor` (a known lower bound of the k-th best) are not kept.
+    __device__ void offer(double v, int32_t id, bool ok, int lane, double floor = -INFINITY)
     {
-        uint64_t mask = __ballot(ok && better(v, id, th_v, th_i));
+        uint64_t mask = __ballot(ok && !(v < floor) && better(v, id, th_v, th_i));
         while (mask != 0ull) {
             const int src = __ffsll((long long)mask) - 1;
             mask &= mask - 1ull;
@@ -94,6 +95,8 @@ struct WaveTopK {
 
 // sum_t q_t x_pt in FP64, ascending t, for the stored row p of each lane
 // (valid lanes only; 0 otherwise).  Xl rows are dp floats, zero past d.
+// The 32-float chunks are double-buffered: the loads of chunk c + 1 are in
+// flight while chunk c is summed from LDS.
 __device__ __forceinline__ double ip64_rows_fp32(const float *__restrict__ Xl, int d, int dp,
                                                  const float *__restrict__ qv, int32_t p, bool valid,
                                                  int lane, float *tile)
@@ -107,14 +110,24 @@ __device__ __forceinline__ double ip64_rows_fp32(const float *__restrict__ Xl, i
         roff[it] = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
         rval[it] = __shfl((int)valid, rr, 64) != 0;
     }
+    floatx4 buf[8];
+#pragma unroll
+    for (int it = 0; it < 8; ++it) {
+        buf[it] = floatx4{0.f, 0.f, 0.f, 0.f};
+        if (rval[it] && seg < dp) buf[it] = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + seg);
+    }
     double acc = 0.0;
     for (int k0 = 0; k0 < dp; k0 += 32) {
-        const int col = k0 + seg;
 #pragma unroll
-        for (int it = 0; it < 8; ++it) {
-            floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-            if (rval[it] && col < dp) v = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
-            *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = v;
+        for (int it = 0; it < 8; ++it)
+            *reinterpret_cast<floatx4 *>(&tile[(8 * it + sub) * RR_STRIDE + seg]) = buf[it];
+        const int col = k0 + 32 + seg;
+        if (k0 + 32 < dp) {
+#pragma unroll
+            for (int it = 0; it < 8; ++it) {
+                buf[it] = floatx4{0.f, 0.f, 0.f, 0.f};
+                if (rval[it] && col < dp) buf[it] = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
+            }
         }
         __syncthreads();
         const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);

@@ -536,14 +536,16 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
         qn = __builtin_sqrt(qn) * (1.0 + 0x1p-40);
     }
 
+    // the positions of the next 64 candidates are loaded one batch ahead
+    int32_t pn = (cbeg + lane < cend) ? cq[cbeg + lane] : -1;
     for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
+        int32_t p = pn;
+        pn = (c0 + 64 + lane < cend) ? cq[c0 + 64 + lane] : -1;
         bool valid = c0 + lane < cend;
-        int32_t id = 0, p = 0;
-        if (valid) {
-            p = cq[c0 + lane];
-            valid = p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
-            if (valid) id = perm[p];
-        }
+        int32_t id = 0;
+        valid = valid && p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
+        if (valid) id = perm[p];
+        else p = 0;
         const double acc = LP ? dev::ip64_rows_bf16(Xh, d, dp, qv, p, valid, lane, tile)
                               : dev::ip64_rows_fp32(Xl, d, dp, qv, p, valid, lane, tile);
         if (LP) {
@@ -565,7 +567,18 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                 if (keep && slot < lcap) lists[q * lcap + slot] = p;
             }
         } else {
-            top.offer(acc, id, valid, lane);
+            // slices of one query share the best k-th value any of them has
+            // reached (at least k items are that good): values below it
+            // cannot enter the query's top-k
+            double floor = -INFINITY;
+            if (gtheta) {
+                const unsigned long long ge =
+                    __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (ge != 0ull) floor = order_value(ge);
+            }
+            top.offer(acc, id, valid, lane, floor);
+            if (gtheta && top.th_v > -INFINITY && top.th_v > floor && lane == 0)
+                atomicMax(&gtheta[q], (unsigned long long)order_key(top.th_v));
         }
     }
     if (LP) return;
@@ -1399,8 +1412,9 @@ int rerank_splits(int64_t nq, int64_t Tq)
 hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, int64_t nq,
                          const QueryShape &sh, const int32_t *cand, const int32_t *counts,
                          int nsplit, double *part_v, int32_t *part_i, int64_t *out_ids,
-                         float *out_ips, hipStream_t s)
+                         float *out_ips, hipStream_t s, unsigned long long *gtheta)
 {
+    if (nsplit < 2) gtheta = nullptr;  // one slice per query: nothing to share
     const int S = (sh.k + 63) / 64;
     int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
     slice = (slice + 63) / 64 * 64;
@@ -1409,7 +1423,7 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     do {                                                                                         \
         hipLaunchKernelGGL((k_rerank<SS, false>), grid, block, 0, s, Xl, perm, Q, sh.n, sh.d,    \
                            sh.dp, sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips,    \
-                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr, nullptr);      \
+                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr, gtheta);       \
         if (nsplit > 1)                                                                          \
             hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
                                nsplit, sh.k, out_ids, out_ips);                                  \

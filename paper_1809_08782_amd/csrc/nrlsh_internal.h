@@ -141,10 +141,12 @@ hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const u
 // partial lists go to part_v / part_i (nq x nsplit x k) and are merged.
 // With counts != NULL, query q's list holds min(counts[q], Tq) entries (stride Tq).
 int rerank_splits(int64_t nq, int64_t Tq);
+// gtheta (nq words, zeroed by the caller; may be NULL) lets the slices of a
+// query share the best k-th value reached so far.
 hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, int64_t nq,
                          const QueryShape &sh, const int32_t *cand, const int32_t *counts,
                          int nsplit, double *part_v, int32_t *part_i, int64_t *out_ids,
-                         float *out_ips, hipStream_t s);
+                         float *out_ips, hipStream_t s, unsigned long long *gtheta = nullptr);
 
 // Precision form of the re-rank: bounds from the bfloat16 copy Xh, appends to
 // lists (nq x lcap, lcount zeroed by the caller) every probed item that may
