@@ -351,6 +351,20 @@ def main():
             kern[nm] = {"avg_ms": ms / cnt, "launches_per_step": cnt / max(2, args.steps // 2)}
     log(f"T={T_op}: {s_step * 1e3:.2f} ms/step; kernels {json.dumps(kern)}")
 
+    # at T >= n every item is probed, so the library runs no query hash, scan
+    # or threshold; T = n - 1 probes all but one item and runs every step of
+    # the path, which shows what that shortcut saves
+    full_path = None
+    if T_op >= w.n and w.n > 1 and not args.no_budgets:
+        st = timed(w.n - 1, max(2, args.steps // 2), 1, True)
+        fk = {}
+        for nm in names:
+            ms, cnt = nr.nrlsh_profile_get(nm)
+            if cnt:
+                fk[nm] = round(ms / max(2, args.steps // 2), 3)
+        full_path = {"T": w.n - 1, "ms_per_step": st * 1e3, "qps": w.nq / st, "kernel_ms_per_step": fk}
+        log(f"full path T={w.n - 1}: {st * 1e3:.2f} ms/step")
+
     budgets = []
     if not args.no_budgets:
         for T in w.budgets:
@@ -545,6 +559,7 @@ def main():
         "recall_at_T": curve.get(T_op),
         "recall_curve": {str(k): v for k, v in curve.items()},
         "budgets": budgets,
+        "full_path_at_n_minus_1": full_path,
         "kernels": kern,
         "hashed_items_per_s": (w.n / (kern["hash"]["avg_ms"] * 1e-3)) if "hash" in kern else None,
         "build_stats": build_stats,

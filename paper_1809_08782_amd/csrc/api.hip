@@ -837,29 +837,38 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
-        tm.begin("qhash");
-        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qcodes.get(),
-                               nonfinite_d, s));
-        tm.end();
+        // a budget covering every item probes every bucket whole: no codes,
+        // counts or threshold are needed (the bfloat16 image checks finiteness)
+        const bool everything = sh.Tq >= sh.n && kind != SCREEN_FP32;
+        if (!everything) {
+            tm.begin("qhash");
+            HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qcodes.get(),
+                                   nonfinite_d, s));
+            tm.end();
+        }
         ScreenQueries sq{Qb, nullptr, nullptr, nullptr};
         if (kind != SCREEN_FP32) {
             sq.Qh = qh.get();
             sq.Ql = kind == SCREEN_BF16X3 ? ql.get() : nullptr;
             sq.qn = qn.get();
             HIPX(launch_query_bf16(Qb, nb, sh.d, sh.dp, qh.get(), kind == SCREEN_BF16X3 ? ql.get() : nullptr,
-                                   qn.get(), s));
+                                   qn.get(), s, nonfinite_d));
         }
-        tm.begin("scan_hist");
-        HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh, ghist.get(), s));
-        tm.end();
-        tm.begin("threshold");
-        HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
-                              ghthr.get(), gtie.get(), s));
-        tm.end();
-        tm.begin("tie_locate");
-        HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, sh.qsets,
-                               gtie.get(), gpstar.get(), s));
-        tm.end();
+        if (everything) {
+            HIPX(launch_probe_all(nb, sh, ghthr.get(), gtie.get(), gpstar.get(), s));
+        } else {
+            tm.begin("scan_hist");
+            HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh, ghist.get(), s));
+            tm.end();
+            tm.begin("threshold");
+            HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
+                                  ghthr.get(), gtie.get(), s));
+            tm.end();
+            tm.begin("tie_locate");
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh.W, sh.qsets,
+                                   gtie.get(), gpstar.get(), s));
+            tm.end();
+        }
         tm.begin("screen_max");
         HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), sq, nb, sh,
                                cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),

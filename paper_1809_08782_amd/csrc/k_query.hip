@@ -18,6 +18,7 @@
 // scalar cache, so each (query, item) pair costs one XOR, one popcount and,
 // in pass 1, one conflict-free LDS increment of the lane's own histogram
 // column.
+#include <algorithm>
 #include <climits>
 #include <cmath>
 
@@ -898,14 +899,17 @@ __device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast
 __global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q, int64_t nq, int d,
                                                     int dp, uint16_t *__restrict__ Qh,
                                                     uint16_t *__restrict__ Ql,
-                                                    float *__restrict__ qn)
+                                                    float *__restrict__ qn,
+                                                    uint32_t *__restrict__ nonfinite)
 {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t q = (int64_t)blockIdx.x * 4 + wave;
     if (q >= nq) return;
     double s2 = 0.0;
+    bool bad = false;
     for (int c = lane; c < dp; c += 64) {
         const float f = c < d ? Q[q * d + c] : 0.f;
+        bad |= !__builtin_isfinite(f);
         const uint16_t hi = q_bf16_rne(f);
         Qh[q * dp + c] = hi;
         if (Ql) Ql[q * dp + c] = q_bf16_rne(f - __uint_as_float((uint32_t)hi << 16));
@@ -914,6 +918,26 @@ __global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q,
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) s2 += __shfl_xor(s2, o, 64);
     if (lane == 0) qn[q] = (float)__builtin_sqrt(s2) * (1.0f + 0x1p-18f);
+    if (nonfinite && __ballot(bad) != 0ull && lane == 0) atomicOr(nonfinite, 1u);
+}
+
+// Probe bounds when the budget covers every item (T >= n): every bucket of
+// every sub-dataset is probed whole and there is no threshold bucket to cut;
+// rows past nq get hthr = -1 as the threshold pass leaves them.  The bound
+// is 64, above any distance the screens can compute: the query codes are not
+// computed on this path, so a tile with rows past nq (which falls back to
+// the per-pair test) compares against whatever the code buffer holds.
+__global__ __launch_bounds__(256) void k_probe_all(int64_t nq, int64_t tiles, int m,
+                                                   int32_t *__restrict__ ghthr, int32_t *__restrict__ gtie,
+                                                   int32_t *__restrict__ gpstar)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e < tiles * m * 64) {
+        const int64_t q = (e / ((int64_t)m * 64)) * 64 + (e & 63);
+        ghthr[e] = q < nq ? 64 : -1;
+    }
+    if (e < tiles * 4 * 64) gtie[e] = (e / 64) % 4 == 2 ? INT_MAX : -1;
+    if (e < nq) gpstar[e] = -1;
 }
 
 // A block holds 64 queries (their bfloat16 rows staged in LDS) and one chunk
@@ -1256,10 +1280,21 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
     return hipGetLastError();
 }
 
-hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
-                             float *qn, hipStream_t s)
+hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
+                            int32_t *gpstar, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_query_bf16, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, nq, d, dp, Qh, Ql, qn);
+    const int64_t tiles = (nq + 63) / 64;
+    const int64_t cnt = std::max<int64_t>(std::max<int64_t>(tiles * sh.m * 64, tiles * 4 * 64), nq);
+    hipLaunchKernelGGL(k_probe_all, dim3(ceil_div(cnt, 256)), dim3(256), 0, s, nq, tiles, sh.m, ghthr, gtie,
+                       gpstar);
+    return hipGetLastError();
+}
+
+hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
+                             float *qn, hipStream_t s, uint32_t *nonfinite)
+{
+    hipLaunchKernelGGL(k_query_bf16, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, nq, d, dp, Qh, Ql, qn,
+                       nonfinite);
     return hipGetLastError();
 }
 

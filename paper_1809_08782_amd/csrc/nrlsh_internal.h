@@ -197,7 +197,12 @@ struct ScreenQueries {
     const float *qn;
 };
 hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
-                             float *qn, hipStream_t s);
+                             float *qn, hipStream_t s, uint32_t *nonfinite = nullptr);
+// Bounds for a budget that covers every item (T >= n): ghthr = 64 (at least
+// L and any distance) for every query and sub-dataset, no threshold bucket
+// (the layout launch_threshold writes), gpstar = -1.
+hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
+                            int32_t *gpstar, hipStream_t s);
 int screen_chunk_items();
 int screen_cell_items();
 int screen_cell_groups();  // lower-bound maxima kept per cell and query

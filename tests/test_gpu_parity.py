@@ -196,6 +196,12 @@ def test_non_finite_inputs_rejected():
         with pytest.raises(nr.NrlshError) as e:
             nr.nrlsh_query(gix, Q, 3, 10)
         assert e.value.status == 2
+        # a budget covering every item skips the query hash: the other
+        # query passes must still catch it, in every re-rank mode
+        for mode in ("screen", "screen_fp32", "screen_bf16x3", "gather"):
+            with pytest.raises(nr.NrlshError) as e:
+                nr.nrlsh_query(gix, Q, 3, 100, rerank=mode)
+            assert e.value.status == 2, mode
 
 
 def test_deterministic_and_batch_independent():
