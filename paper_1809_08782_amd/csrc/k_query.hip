@@ -1100,11 +1100,26 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     }
                 }
         }
+        // pass B: one bound for this lane's NB items (e grows with ||x||, and
+        // float rounding is monotone), so a pair whose ip + emax stays below
+        // theta is dropped with one add and one compare; only the rare
+        // survivors take the probe test and the exact bound
+        float xmax = xn[0];
+#pragma unroll
+        for (int ib = 1; ib < NB; ++ib) xmax = fmaxf(xmax, xn[ib]);
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int ql = 16 * qb + 4 * g + v;
+                if (!MAXMODE) {
+                    const float th = th_s[ql];
+                    const float emax = gam * qn_s[ql] * xmax + 0x1p-90f;
+                    bool near = false;
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) near |= !(acc[qb][ib][v] + emax < th);
+                    if (!near) continue;
+                }
                 const int hthr = hthr_s[ql], htie = htie_s[ql];
                 const float th = th_s[ql], qn = qn_s[ql];
                 float gmax[NB / 2];  // MAXMODE: per 32-item group of this iteration
