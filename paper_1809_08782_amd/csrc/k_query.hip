@@ -892,6 +892,12 @@ __device__ __forceinline__ uint16_t q_bf16_rne(float f)
 
 __device__ __forceinline__ bf16x8 as_bf16x8(u16x8 v) { return __builtin_bit_cast(bf16x8, v); }
 
+// 16 bytes at voffset + soffset of a raw buffer (0 past its size)
+__device__ __forceinline__ u16x8 buf_load16(__amdgpu_buffer_rsrc_t r, uint32_t voffset, int soffset)
+{
+    return __builtin_bit_cast(u16x8, __builtin_amdgcn_raw_buffer_load_b128(r, (int)voffset, soffset, 0));
+}
+
 // bfloat16 image of a query batch for the screen: hi = RNE(q), lo =
 // RNE(q - hi) (when Ql != NULL), rows zero-padded to dp columns, and qn = an
 // upper bound on ||q|| (exact squares, FP64 sum, rounded up).  One wave per
@@ -1026,43 +1032,40 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     constexpr int NB = X3 ? 2 : 4, IW = 16 * NB;
     const int r16 = lane & 15, g = lane >> 4;
     const bool all = all_s != 0;
+    // stored rows of this chunk through buffer descriptors: 32-bit offsets
+    // from the chunk's first row, and reads past the chunk's rows return 0
+    // (finite values that meet the zero columns of the query tile, or rows
+    // whose results are never used)
+    const uint32_t rbytes = (uint32_t)(pend - pbeg) * (uint32_t)dp * 2u;
+    const __amdgpu_buffer_rsrc_t bx =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(Xh + (int64_t)pbeg * dp), 0, (int)rbytes, 0x00020000);
+    const __amdgpu_buffer_rsrc_t bxl =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(X3 ? Xlo + (int64_t)pbeg * dp : Xh), 0, X3 ? (int)rbytes : 0,
+                                          0x00020000);
     for (int p0 = pbeg + wave * IW; p0 < pend; p0 += 4 * IW) {
-        int32_t pit[NB];
         uint32_t cw[NB][W];
         float xn[NB];
-        bool iv[NB];
+        uint32_t ro[NB];  // byte offset of this lane's 8 coordinates of row 16 ib + r16
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            pit[ib] = p0 + 16 * ib + r16;
-            iv[ib] = pit[ib] < pend;
-            const int64_t pp = iv[ib] ? pit[ib] : pbeg;
+            const int pi = p0 + 16 * ib + r16;
+            const int64_t pp = pi < pend ? pi : pbeg;
 #pragma unroll
             for (int w = 0; w < W; ++w) cw[ib][w] = all ? 0u : codes_l[pp * W + w];
             xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
+            ro[ib] = (uint32_t)(pi - pbeg) * (uint32_t)dp * 2u + 16u * g;
         }
         floatx4 acc[4][NB];
 #pragma unroll
         for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
             for (int ib = 0; ib < NB; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
-        // item operands of step kk: 8 coordinates of one row per lane.  The
-        // loads are unconditional: an invalid item reads a valid row (its
-        // results are never used), and coordinates past dp read the next
-        // row or the zeroed tail pad of the array -- finite values that meet
-        // the zero columns of the query tile.
-        const uint16_t *rh[NB];
-        const uint16_t *rl[NB];
-#pragma unroll
-        for (int ib = 0; ib < NB; ++ib) {
-            const int64_t row = iv[ib] ? pit[ib] : pbeg;
-            rh[ib] = Xh + row * dp + 8 * g;
-            rl[ib] = X3 ? Xlo + row * dp + 8 * g : nullptr;
-        }
+        // item operands of step kk: 8 coordinates of one row per lane
         u16x8 bh[NB], bl[NB];
 #pragma unroll
         for (int ib = 0; ib < NB; ++ib) {
-            bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib]);
-            bl[ib] = X3 ? *reinterpret_cast<const u16x8 *>(rl[ib]) : z8;
+            bh[ib] = buf_load16(bx, ro[ib], 0);
+            bl[ib] = X3 ? buf_load16(bxl, ro[ib], 0) : z8;
         }
         for (int kk = 0; kk < dp; kk += 32) {
             u16x8 ch[NB], cl[NB];
@@ -1074,8 +1077,8 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
             if (kk + 32 < dp) {  // prefetch the next step
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
-                    bh[ib] = *reinterpret_cast<const u16x8 *>(rh[ib] + kk + 32);
-                    if (X3) bl[ib] = *reinterpret_cast<const u16x8 *>(rl[ib] + kk + 32);
+                    bh[ib] = buf_load16(bx, ro[ib], 2 * (kk + 32));
+                    if (X3) bl[ib] = buf_load16(bxl, ro[ib], 2 * (kk + 32));
                 }
             }
             const int kc = kk + 8 * g;
@@ -1127,11 +1130,12 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                 for (int hg = 0; hg < NB / 2; ++hg) gmax[hg] = -INFINITY;
 #pragma unroll
                 for (int ib = 0; ib < NB; ++ib) {
-                    bool probed = iv[ib];
+                    const int pi = p0 + 16 * ib + r16;
+                    bool probed = pi < pend;
                     if (!all) {
                         int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
                         if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
-                        probed = probed && (h <= hthr || (h == htie && pit[ib] <= pstar_s[ql]));
+                        probed = probed && (h <= hthr || (h == htie && pi <= pstar_s[ql]));
                     }
                     const float ip = acc[qb][ib][v];
                     const float e = gam * qn * xn[ib] + 0x1p-90f;
@@ -1140,7 +1144,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     } else if (probed && !(ip + e < th)) {
                         const int64_t q = q0 + ql;
                         const int slot = atomicAdd(&counts[q], 1);
-                        if (slot < cap) lists[q * cap + slot] = pit[ib];
+                        if (slot < cap) lists[q * cap + slot] = pi;
                     }
                 }
                 if (MAXMODE) {
