@@ -386,7 +386,10 @@ typedef struct nrlsh_query_stats {
     int64_t theta_unset;   /* SCREEN: queries whose lower bound theta stayed -inf */
     int64_t lp_kept_total; /* BF16 re-rank: items re-ranked exactly, all queries */
     int64_t lp_kept_max;   /* BF16 re-rank: largest exact list of one query */
-    int32_t lp_fallbacks;  /* BF16 re-rank: batches that overflowed into the FP32 re-rank */
+    int32_t lp_fallbacks;  /* BF16 re-rank: batches that overflowed into the FP32 re-rank;
+                              after one, later batches of the call, and later calls on
+                              the index with at least that k and budget, use the FP32
+                              rows directly */
     int32_t probe_mode;    /* nrlsh_probe_mode used */
     int64_t table_lookups; /* TABLE: codes searched in the tables, all queries */
     int64_t table_walked;  /* TABLE: distinct codes counted by whole-sub-dataset passes */

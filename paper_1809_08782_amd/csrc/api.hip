@@ -652,6 +652,12 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const TableView tv{ix->ucode.get(), ix->ustart.get(), ix->uoff.get(), ix->titem.get(), ix->binom.get()};
     if (table) HIPX(hipMemsetAsync(tctr.get(), 0, table_counter_bytes(), s));
     std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
+    // once a batch's bfloat16 lists overflow (the bound keeps too many items
+    // for this data and k), later batches of the call go straight to the
+    // FP32 rows instead of paying for both passes
+    bool lp_on = bf16_rows;
+    const uint64_t ovf = ix->lp_overflow.load(std::memory_order_relaxed);
+    if (ovf != 0 && (uint64_t)k >= (ovf >> 32) && (uint64_t)sh.Tq >= (ovf & 0xFFFFFFFFull)) lp_on = false;
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
@@ -707,7 +713,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             tm.end();
         }
         if (cand_out_d) continue;
-        if (bf16_rows) {
+        if (lp_on) {
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
             HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
             tm.begin("rerank_lp");
@@ -736,6 +742,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 continue;
             }
             g_qstats.lp_fallbacks += 1;  // a list overflowed: re-rank this batch from FP32 rows
+            lp_on = false;
+            ix->lp_overflow.store(((uint64_t)k << 32) | (uint64_t)sh.Tq, std::memory_order_relaxed);
         }
         if (nsplit > 1) HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
         tm.begin("rerank");

@@ -25,6 +25,19 @@ typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 constexpr int RR_STRIDE = 36;  // floats per LDS row (16-byte aligned, conflict-free b128)
 constexpr int RR_TILE_FLOATS = 64 * RR_STRIDE;
 
+// Order-preserving encoding of a double as an unsigned word (a larger
+// double gives a larger word; 0 is below every encoded value), so that
+// slices of one query can publish their k-th best value with atomicMax.
+__device__ __forceinline__ uint64_t order_key(double x)
+{
+    const uint64_t u = (uint64_t)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
+}
+__device__ __forceinline__ double order_value(uint64_t e)
+{
+    return __longlong_as_double((long long)((e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e));
+}
+
 __device__ __forceinline__ bool better(double a, int32_t ia, double b, int32_t ib)
 {
     return a > b || (a == b && ia < ib);

@@ -8,6 +8,7 @@
 #include <cstdint>
 #include <new>
 #include <string>
+#include <atomic>
 #include <vector>
 
 #include "nrlsh.h"
@@ -203,6 +204,10 @@ struct nrlsh_index {
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
     nrlsh::host::DBuf<int32_t> sid, sid_l, perm, off, R, inv;
     nrlsh::host::DBuf<uint32_t> codes_l;              // stored order
+    // (k, Tq) of the last call whose bfloat16 re-rank lists overflowed, packed
+    // k << 32 | Tq (0: none): calls with at least that k and budget skip the
+    // bfloat16 pass (a speed hint only; results never depend on it)
+    mutable std::atomic<uint64_t> lp_overflow{0};
     // bucket tables (built on request): distinct codes of each sub-dataset
     bool has_table = false;
     int64_t nunique = 0;

@@ -137,6 +137,8 @@ __device__ void item_qhash(const Ctx &C, const MultiDesc &D, int64_t u)
     }
     if (bad && lane == 0)
         __hip_atomic_fetch_or(C.nonfinite, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the re-rank slices of these queries start from no shared bound
+    if (D.gtheta && q0 + lane < q1) D.gtheta[q0 + lane] = 0ull;
     if (SYNC) signal(tile_ctr(C, D, q0 >> 6, PH_QH));
 }
 
@@ -444,7 +446,17 @@ __device__ void item_rerank(const Ctx &C, const MultiDesc &D, int64_t u, float *
             if (valid) id = D.perm[p];
         }
         const double acc = dev::ip64_rows_fp32(D.Xl, D.d, D.dp, qv, p, valid, lane, tile_lds);
-        top.offer(acc, id, valid, lane);
+        // values below the best k-th value any slice of this query has
+        // reached cannot enter its top-k
+        double floor = -INFINITY;
+        if (D.gtheta) {
+            const unsigned long long ge =
+                __hip_atomic_load(&D.gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (ge != 0ull) floor = dev::order_value(ge);
+        }
+        top.offer(acc, id, valid, lane, floor);
+        if (D.gtheta && top.th_v > -INFINITY && top.th_v > floor && lane == 0)
+            atomicMax(&D.gtheta[q], (unsigned long long)dev::order_key(top.th_v));
     }
     if (D.nsplit == 1) {
         write_topk<S>(D, q, C.k, top);

@@ -491,15 +491,8 @@ using dev::WaveTopK;
 // query share the largest k-th lower bound any of them has reached (gtheta,
 // order-preserving encoding, 0 = none yet): the k items behind it have exact
 // inner products at least that large, so it bounds the query's k-th best.
-__device__ __forceinline__ uint64_t order_key(double x)
-{
-    const uint64_t u = (uint64_t)__double_as_longlong(x);
-    return (u >> 63) ? ~u : (u | 0x8000000000000000ull);
-}
-__device__ __forceinline__ double order_value(uint64_t e)
-{
-    return __longlong_as_double((long long)((e >> 63) ? (e & 0x7FFFFFFFFFFFFFFFull) : ~e));
-}
+using dev::order_key;
+using dev::order_value;
 
 template <int S, bool LP>
 __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,

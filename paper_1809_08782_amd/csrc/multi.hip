@@ -191,7 +191,8 @@ void lay_out(nrlsh_multi_plan *P)
     const int nb = (int)P->active.size();
     P->desc.assign(nb, MultiDesc{});
     size_t off = 0;
-    std::vector<size_t> o_qc(nb), o_gh(nb), o_th(nb), o_ti(nb), o_ps(nb), o_ca(nb), o_pv(nb), o_pi(nb);
+    std::vector<size_t> o_qc(nb), o_gh(nb), o_th(nb), o_ti(nb), o_ps(nb), o_ca(nb), o_pv(nb), o_pi(nb),
+        o_gt(nb);
     int64_t tiles_before = 0, q_before = 0, cand_total = 0;
     int maxL = 1;
     for (int b = 0; b < nb; ++b) {
@@ -242,6 +243,7 @@ void lay_out(nrlsh_multi_plan *P)
         const size_t parts = D.nsplit > 1 ? (size_t)D.nq * D.nsplit * P->k : 0;
         o_pv[b] = take(parts * 8);
         o_pi[b] = take(parts * 4);
+        o_gt[b] = take(D.nsplit > 1 ? (size_t)D.nq * 8 : 0);
     }
     if (cand_total > INT32_MAX)
         throw Failure{NRLSH_E_INVALID_ARG, "the probed lists of the set exceed 2^31 entries; split the set"};
@@ -262,6 +264,7 @@ void lay_out(nrlsh_multi_plan *P)
         D.cand = reinterpret_cast<int32_t *>(base + o_ca[b]);
         D.part_v = reinterpret_cast<double *>(base + o_pv[b]);
         D.part_i = reinterpret_cast<int32_t *>(base + o_pi[b]);
+        D.gtheta = D.nsplit > 1 ? reinterpret_cast<unsigned long long *>(base + o_gt[b]) : nullptr;
     }
     P->ctr = reinterpret_cast<int32_t *>(base + ctr_off);
 

@@ -286,6 +286,8 @@ struct MultiDesc {
     int32_t *cand;        // nq x Tq
     double *part_v;       // nq x nsplit x k (nsplit > 1)
     int32_t *part_i;
+    unsigned long long *gtheta;  // nq (nsplit > 1): best k-th value of the query's slices,
+                                 // order-preserving encoding, zeroed by the query-hash phase
     // tile shape
     int32_t chunk;        // stored items per scan work item
     int32_t nch;          // scan work items per sub-dataset

@@ -186,3 +186,30 @@ def test_bf16_rerank_copy_gives_exact_topk(k, T):
         assert np.array_equal(ids, oids)
         assert np.array_equal(ips, oips.astype(np.float32))
         assert st["lp_kept_total"] > 0 and st["lp_fallbacks"] == 0
+
+
+def test_bf16_rerank_overflow_is_remembered_per_index():
+    """Nearly equal rows keep every item inside the bfloat16 bound, so the
+    short lists overflow: the batch falls back to the FP32 rows, later calls
+    with at least that k and budget skip the bfloat16 pass, smaller budgets
+    still take it; every call returns the oracle's result."""
+    say("case bf16 rerank overflow hint")
+    rng = np.random.default_rng(5)
+    n, d = 20000, 16
+    X = (1.0 + 1e-4 * rng.standard_normal((n, d))).astype(np.float32)
+    Q = make_queries(30, d, seed=6)
+    oix = orc.OracleIndex(X, 4, 16, seed=7, threads=8)
+    with nr.nrlsh_build(X, 4, 16, 7) as gix:
+        for T, expect in ((n, "fallback"), (n, "skipped"), (4096, "bf16")):
+            oids, oips = oix.query(Q, 10, T, threads=8)
+            ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank="gather", rerank_storage="bf16")
+            st = nr.nrlsh_get_query_stats()
+            say(f"  T={T}: kept {st['lp_kept_total']} fallbacks {st['lp_fallbacks']}")
+            assert np.array_equal(ids, oids), T
+            assert np.array_equal(ips, oips.astype(np.float32)), T
+            if expect == "fallback":
+                assert st["lp_fallbacks"] >= 1
+            elif expect == "skipped":
+                assert st["lp_fallbacks"] == 0 and st["lp_kept_total"] == 0
+            else:
+                assert st["lp_fallbacks"] == 0 and st["lp_kept_total"] > 0
