@@ -476,11 +476,15 @@ def main():
     roof = None
     if dom == "screen":
         # algorithmic work of one screen launch: the inner products of the
-        # probed pairs ((queries per launch) x T pairs), 2d flop each on the
-        # bf16 (or FP32) matrix cores; the bf16x3 screen forms each one from
-        # three bfloat16 products (hi*hi + hi*lo + lo*hi), 3 x 2d flop.
+        # pairs it evaluates, 2d flop each on the bf16 (or FP32) matrix cores
+        # (the bf16x3 screen forms each one from three bfloat16 products,
+        # hi*hi + hi*lo + lo*hi, 3 x 2d flop).  The keep pass skips chunks no
+        # query of a tile can keep (norm bound), so its pairs are the ones the
+        # library reports evaluating, not all (queries x T) probed pairs.
         launches = kern["screen"]["launches_per_step"]
-        pairs = (w.nq / launches) * Tq
+        probed_pairs = (w.nq / launches) * Tq
+        passes = max(1, qstats.get("screen_passes") or 1)
+        pairs = qstats.get("screen_pairs") / passes if qstats.get("screen_pairs") else probed_pairs
         smode = qstats.get("mode")
         products = {"screen": 1, "screen_bf16x3": 3}.get(smode, 1)
         b16 = smode in ("screen", "screen_bf16x3")
@@ -498,6 +502,7 @@ def main():
                 "traffic_source": rec, "mfma_dtype": "bf16" if b16 else "f32",
                 "bf16_products_per_pair": products if b16 else None,
                 "flops_per_launch": flops, "pairs_per_launch": pairs,
+                "probed_pairs_per_launch": probed_pairs,
                 "fp32_equivalent_tflops": 2.0 * w.d * pairs / (kern["screen"]["avg_ms"] * 1e-3) / 1e12,
                 "dominant_kernel": dom}
     elif dom in ("rerank", "rerank_exact", "rerank_lp"):

@@ -394,6 +394,10 @@ typedef struct nrlsh_query_stats {
     int64_t table_lookups; /* TABLE: codes searched in the tables, all queries */
     int64_t table_walked;  /* TABLE: distinct codes counted by whole-sub-dataset passes */
     int64_t table_passes;  /* TABLE: whole-sub-dataset passes */
+    int64_t screen_pairs;  /* SCREEN: (query, item) pairs evaluated by the keep pass,
+                              summed over its launches (a chunk none of whose items
+                              any query of the tile can keep, by the norm bound U_j,
+                              is skipped) */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

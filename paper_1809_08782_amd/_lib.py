@@ -66,7 +66,7 @@ class QueryStats(C.Structure):
                 ("kept_max", C.c_int64), ("theta_unset", C.c_int64), ("lp_kept_total", C.c_int64),
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
-                ("table_passes", C.c_int64)]
+                ("table_passes", C.c_int64), ("screen_pairs", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -526,7 +526,7 @@ def nrlsh_get_query_stats() -> dict:
             "lp_kept_total": st.lp_kept_total, "lp_kept_max": st.lp_kept_max,
             "lp_fallbacks": st.lp_fallbacks, "probe": {1: "table"}.get(st.probe_mode, "scan"),
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
-            "table_passes": st.table_passes}
+            "table_passes": st.table_passes, "screen_pairs": st.screen_pairs}
 
 
 def nrlsh_profile_enable(on: bool = True):

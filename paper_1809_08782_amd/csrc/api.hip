@@ -828,9 +828,12 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_ql = blk.reserve<uint16_t>(kind == SCREEN_BF16X3 ? (size_t)B * sh.dp : 1),
                  o_qn = blk.reserve<float>(kind != SCREEN_FP32 ? (size_t)B : 1),
                  o_ta = blk.reserve<float>((size_t)B), o_co = blk.reserve<int32_t>((size_t)B),
-                 o_li = blk.reserve<int32_t>((size_t)B * cap);
+                 o_li = blk.reserve<int32_t>((size_t)B * cap),
+                 o_np = blk.reserve<unsigned long long>(1);
     blk.allocate(s);
     DBuf<int32_t> cells = blk.view<int32_t>(o_ce), chunks = blk.view<int32_t>(o_ch);
+    DBuf<unsigned long long> npairs = blk.view<unsigned long long>(o_np);
+    HIPX(hipMemsetAsync(npairs.get(), 0, sizeof(unsigned long long), s));
     HIPX(hipMemcpyAsync(cells.get(), ce.data(), ce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
@@ -854,7 +857,7 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                    nonfinite_d, s));
             tm.end();
         }
-        ScreenQueries sq{Qb, nullptr, nullptr, nullptr};
+        ScreenQueries sq{Qb, nullptr, nullptr, nullptr, ix->U.get(), npairs.get()};
         if (kind != SCREEN_FP32) {
             sq.Qh = qh.get();
             sq.Ql = kind == SCREEN_BF16X3 ? ql.get() : nullptr;
@@ -930,6 +933,10 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             lists = DBuf<int32_t>((size_t)B * cap, s);
         }
     }
+    unsigned long long np = 0;
+    HIPX(hipMemcpyAsync(&np, npairs.get(), sizeof np, hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    g_qstats.screen_pairs = (int64_t)np;
 }
 
 void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,

@@ -952,10 +952,11 @@ __global__ __launch_bounds__(256) void k_probe_all(int64_t nq, int64_t tiles, in
         const uint32_t *__restrict__ qcodes, const int32_t *__restrict__ ghthr,                 \
         const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,                   \
         const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,      \
-        int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L, int qsets
+        int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L, int qsets, \
+        const double *__restrict__ Usub, unsigned long long *__restrict__ npairs
 #define NRLSH_SCREEN_ARGS                                                                      \
     Xh, Xlo, dp, codes_l, key_l, Qh, Ql, qnorm, nq, chunks, m, qcodes, ghthr, gtie, gpstar, theta, \
-        gam, cap, counts, lists, cmax, ncol, qsb, L, qsets
+        gam, cap, counts, lists, cmax, ncol, qsb, L, qsets, Usub, npairs
 
 template <int W, bool MAXMODE, bool X3>
 __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
@@ -993,7 +994,12 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
         pstar_s[tid] = pstar;
         th_s[tid] = th;
         qn_s[tid] = qn;
-        const uint64_t b = __ballot(hthr >= 0 || htie >= 0);
+        // pass B: no item of sub-dataset j (norms <= U_j) can be kept for a
+        // query whose theta exceeds qn U_j (1 + 2 gam + 2^-15): ip32 + e is at
+        // most ||q|| ||x|| + 2 e (Cauchy-Schwarz); such queries skip the chunk
+        const bool reach = !Usub || q >= nq ||
+                           !((double)th > (double)qn * Usub[j] * (1.0 + 2.0 * (double)gam + 0x1p-15) + 0x1p-80);
+        const uint64_t b = __ballot((hthr >= 0 || htie >= 0) && reach);
         const uint64_t a = __ballot(hthr >= L);  // every possible h passes
         if (tid == 0) {
             any_s = b != 0ull;
@@ -1003,7 +1009,9 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
         for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
     __syncthreads();
-    if (!any_s) return;  // no query of this tile probes this chunk
+    if (!any_s) return;  // no query of this tile probes (or, pass B, can keep) an item of this chunk
+    if (npairs && tid == 0)
+        atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - q0) * (int64_t)(pend - pbeg)));
 
     // stage the query tile (rows beyond nq and columns beyond dp, up to a
     // multiple of 32, are zero)
@@ -1348,12 +1356,13 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
     if (one)
         hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
                            Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
-                           cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets);
+                           cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets,
+                           MAXMODE ? nullptr : Q.U, MAXMODE ? nullptr : Q.pairs);
     else
         hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
                            codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
                            gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L,
-                           sh.qsets);
+                           sh.qsets, MAXMODE ? nullptr : Q.U, MAXMODE ? nullptr : Q.pairs);
     return hipGetLastError();
 }
 

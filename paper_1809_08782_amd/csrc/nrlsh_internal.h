@@ -195,6 +195,13 @@ struct ScreenQueries {
     const float *Q;
     const uint16_t *Qh, *Ql;
     const float *qn;
+    // U_j of each sub-dataset (FP64), or NULL: with it the bfloat16 screens'
+    // pass B skips a chunk when no query of the tile can keep any of its items
+    // (theta_q above the Cauchy-Schwarz bound ||q|| U_j plus the error bounds)
+    const double *U = nullptr;
+    // pass B adds the (query, item) pairs of every chunk it does not skip
+    // (valid queries of the tile x items of the chunk), or NULL
+    unsigned long long *pairs = nullptr;
 };
 hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
                              float *qn, hipStream_t s, uint32_t *nonfinite = nullptr);

@@ -358,3 +358,25 @@ def test_per_subset_index_rejected_by_batching_form():
     with nr.nrlsh_build(X, 4, 16, 7, projections="per_subset") as gix:
         with pytest.raises(nr.NrlshError, match="per-subset"):
             nr.nrlsh_query_multi([(gix, Q, 100)], 10)
+
+
+@pytest.mark.parametrize("mode", ["screen", "screen_bf16x3"])
+def test_screen_norm_pruning_keeps_exact_result(mode):
+    """Heavy-tailed norms: the keep pass skips every chunk whose sub-dataset's
+    largest norm cannot reach any tile query's theta (Cauchy-Schwarz), yet the
+    result equals the oracle's exact top-k at T = n and at a smaller budget."""
+    n, d, m, L = 30000, 64, 16, 32
+    say(f"case screen norm pruning {mode}")
+    X = make_items("pareto", n, d, seed=71, alpha=2.0)
+    Q = make_queries(200, d, seed=72)
+    oix = orc.OracleIndex(X, m, L, seed=73, threads=8)
+    with nr.nrlsh_build(X, m, L, 73) as gix:
+        for T in (n, 3000):
+            oids, oips = oix.query(Q, 10, T, threads=8)
+            ids, ips = nr.nrlsh_query(gix, Q, 10, T, rerank=mode)
+            st = nr.nrlsh_get_query_stats()
+            say(f"  T={T}: pairs evaluated {st['screen_pairs']} of {Q.shape[0] * n}")
+            assert np.array_equal(ids, oids), T
+            assert np.array_equal(ips, oips.astype(np.float32)), T
+            if T == n:
+                assert 0 < st["screen_pairs"] < Q.shape[0] * n
