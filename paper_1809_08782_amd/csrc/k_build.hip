@@ -21,8 +21,9 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 
 // ---------------------------------------------------------------- keys
 // One wave owns 64 consecutive rows.  Columns are streamed 32 at a time:
-// each load instruction covers two rows x 128 contiguous bytes, the chunk is
-// transposed through LDS, and lane r then adds the squares of row r in
+// each load instruction brings 16 bytes per lane, 8 rows x 128 contiguous
+// bytes, and the next chunk's loads are in flight while the current chunk is
+// transposed through LDS and summed: lane r adds the squares of row r in
 // ascending column order.  Squares of FP32 values are exact in FP64, so the
 // sum is bit-identical to a sequential FP64 loop.
 constexpr int KC_ROWS = 64;
@@ -36,21 +37,38 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64
     __shared__ float tile[4][KC_ROWS][33];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * KC_ROWS;
-    const int half = lane >> 5, col = lane & 31;
+    const int sub = lane >> 3, seg = 4 * (lane & 7);  // row 8 it + sub, columns seg .. seg + 3
+    const bool vec = (d & 3) == 0;                     // rows 16-byte aligned
+    auto load = [&](floatx4 (&v)[8], int c0) {
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+            const int64_t row = row0 + 8 * it + sub;
+            const int c = c0 + seg;
+            v[it] = floatx4{0.f, 0.f, 0.f, 0.f};
+            if (row < n) {
+                if (vec && c + 3 < d) {
+                    v[it] = *reinterpret_cast<const floatx4 *>(X + row * d + c);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+                        if (c + u < d) v[it][u] = X[row * d + c + u];
+                }
+            }
+        }
+    };
+    floatx4 cur[8], nxt[8];
+    load(cur, 0);
     double acc = 0.0;
     bool bad = false;
     for (int c0 = 0; c0 < d; c0 += 32) {
-#pragma unroll 8
-        for (int it = 0; it < 32; ++it) {
-            const int r = 2 * it + half;
-            const int64_t row = row0 + r;
-            const int c = c0 + col;
-            float v = 0.0f;
-            if (row < n && c < d) {
-                v = X[row * d + c];
-                bad |= !__builtin_isfinite(v);
+        if (c0 + 32 < d) load(nxt, c0 + 32);
+#pragma unroll
+        for (int it = 0; it < 8; ++it) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                bad |= !__builtin_isfinite(cur[it][u]);
+                tile[wave][8 * it + sub][seg + u] = cur[it][u];
             }
-            tile[wave][r][col] = v;
         }
         __syncthreads();
         const int cend = min(32, d - c0);
@@ -59,6 +77,8 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64
             acc = acc + x * x;
         }
         __syncthreads();
+#pragma unroll
+        for (int it = 0; it < 8; ++it) cur[it] = nxt[it];
     }
     const int64_t myrow = row0 + lane;
     if (myrow < n) {
