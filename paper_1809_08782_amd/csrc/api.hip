@@ -301,7 +301,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     // reads whole 32-coordinate steps past the last row's dp values
     const size_t oXl = B.reserve<float>((size_t)n * dp),
                  oXh = B.reserve<uint16_t>((size_t)n * dp + 32),
-                 oXlo = B.reserve<uint16_t>((size_t)n * dp + 32), oA = B.reserve<float>(ix->A_h.size()),
+                 oA = B.reserve<float>(ix->A_h.size()),
                  oAt = B.reserve<float>(At_h.size()), okey = B.reserve<double>(n),
                  okeyl = B.reserve<double>(n), okm = B.reserve<double>(m), oU = B.reserve<double>(m),
                  osid = B.reserve<int32_t>(n), osidl = B.reserve<int32_t>(n),
@@ -319,7 +319,6 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     B.allocate(s);
     ix->Xl = B.view<float>(oXl);
     ix->Xh = B.view<uint16_t>(oXh);
-    ix->Xlo = B.view<uint16_t>(oXlo);
     ix->A = B.view<float>(oA);
     ix->At = B.view<float>(oAt);
     ix->key = B.view<double>(okey);
@@ -458,10 +457,9 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                         hipMemcpyDeviceToDevice, s));
     tm.begin("layout");
     HIPX(launch_layout(X, n, d, dp, ix->perm.get(), ix->key.get(), ix->sid.get(), ix->Xl.get(),
-                       ix->Xh.get(), ix->Xlo.get(), ix->key_l.get(), ix->sid_l.get(), s));
+                       ix->Xh.get(), nullptr, ix->key_l.get(), ix->sid_l.get(), s));
     tm.end();
     HIPX(hipMemsetAsync(ix->Xh.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
-    HIPX(hipMemsetAsync(ix->Xlo.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
     std::vector<int32_t> bstart_h((size_t)m + 1, 0);  // outlives its copy
@@ -762,6 +760,26 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     }
 }
 
+// The bfloat16 lo part of the stored rows (x - bf16(x), rounded to
+// bfloat16), needed by the bf16x3 screen only: made on the first such query
+// (under the index's lock, finished before anyone uses it) and kept.
+const uint16_t *lo_rows(const nrlsh_index *ix, hipStream_t s)
+{
+    if (ix->lo_ready.load(std::memory_order_acquire)) return ix->Xlo.get();
+    std::lock_guard<std::mutex> g(ix->lo_mu);
+    if (!ix->lo_ready.load(std::memory_order_relaxed)) {
+        const size_t count = (size_t)ix->n * ix->dp + 32;  // zeroed 32-value tail pad
+        DBuf<uint16_t> lo(count, s);
+        HIPX(launch_lo_rows(ix->Xl.get(), ix->Xh.get(), (int64_t)ix->n * ix->dp, lo.get(), s));
+        HIPX(hipMemsetAsync(lo.get() + (size_t)ix->n * ix->dp, 0, 32 * sizeof(uint16_t), s));
+        HIPX(hipStreamSynchronize(s));
+        lo.s = ix->home;  // released with the index, on the library stream
+        ix->Xlo = std::move(lo);
+        ix->lo_ready.store(true, std::memory_order_release);
+    }
+    return ix->Xlo.get();
+}
+
 bool screen_fits(const nrlsh_index *ix, int kind)
 {
     int lim = 0;
@@ -797,7 +815,7 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                       uint32_t *nonfinite_d)
 {
     const uint16_t *Xh = kind != SCREEN_FP32 ? ix->Xh.get() : nullptr;
-    const uint16_t *Xlo = kind == SCREEN_BF16X3 ? ix->Xlo.get() : nullptr;
+    const uint16_t *Xlo = kind == SCREEN_BF16X3 ? lo_rows(ix, s) : nullptr;
     const QueryShape sh = make_shape(ix, T, k);
     int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
     const int64_t tiles = B / 64;

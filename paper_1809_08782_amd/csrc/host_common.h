@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <new>
 #include <string>
 #include <atomic>
@@ -198,7 +199,11 @@ struct nrlsh_index {
     hipStream_t home = nullptr;  // library stream that releases the device buffers
     nrlsh::host::Block mem;      // the long-lived buffers below are views into it
     nrlsh::host::DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
-    nrlsh::host::DBuf<uint16_t> Xh, Xlo;              // its bfloat16 hi / lo split
+    nrlsh::host::DBuf<uint16_t> Xh;                   // its bfloat16 image (hi part)
+    // lo part x - hi (bfloat16), made on the first query that needs it
+    mutable nrlsh::host::DBuf<uint16_t> Xlo;
+    mutable std::mutex lo_mu;
+    mutable std::atomic<bool> lo_ready{false};
     nrlsh::host::DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
     nrlsh::host::DBuf<float> xscale;                  // its row scales
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order

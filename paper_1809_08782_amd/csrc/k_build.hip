@@ -280,18 +280,45 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
         const int64_t i = perm[p];
         const float *src = X + i * d;
         float *dst = Xl + p * dp;
-        for (int c = lane; c < dp; c += 64) {
-            const float v = c < d ? src[c] : 0.0f;
-            const uint16_t hi = bf16_rne(v);
-            dst[c] = v;
-            Xh[p * dp + c] = hi;
-            Xlo[p * dp + c] = bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
+        if ((d & 3) == 0) {  // 16-byte rows: 4 values per lane per step (dp is a multiple of 8)
+            for (int c = 4 * lane; c < dp; c += 256) {
+                floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
+                if (c < d) v = *reinterpret_cast<const floatx4 *>(src + c);
+                ushort4 h, l;
+                h.x = bf16_rne(v[0]);
+                h.y = bf16_rne(v[1]);
+                h.z = bf16_rne(v[2]);
+                h.w = bf16_rne(v[3]);
+                l.x = bf16_rne(v[0] - __uint_as_float((uint32_t)h.x << 16));
+                l.y = bf16_rne(v[1] - __uint_as_float((uint32_t)h.y << 16));
+                l.z = bf16_rne(v[2] - __uint_as_float((uint32_t)h.z << 16));
+                l.w = bf16_rne(v[3] - __uint_as_float((uint32_t)h.w << 16));
+                *reinterpret_cast<floatx4 *>(dst + c) = v;
+                *reinterpret_cast<ushort4 *>(Xh + p * dp + c) = h;
+                if (Xlo) *reinterpret_cast<ushort4 *>(Xlo + p * dp + c) = l;
+            }
+        } else {
+            for (int c = lane; c < dp; c += 64) {
+                const float v = c < d ? src[c] : 0.0f;
+                const uint16_t hi = bf16_rne(v);
+                dst[c] = v;
+                Xh[p * dp + c] = hi;
+                if (Xlo) Xlo[p * dp + c] = bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
+            }
         }
         if (lane == 0) {
             key_l[p] = key[i];
             sid_l[p] = sid[i];
         }
     }
+}
+
+// lo = bf16(x - hi) of every stored value, from the FP32 copy and its hi part.
+__global__ __launch_bounds__(256) void k_lo_rows(const float *__restrict__ Xl, const uint16_t *__restrict__ Xh,
+                                                 int64_t count, uint16_t *__restrict__ Xlo)
+{
+    for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < count; e += (int64_t)gridDim.x * 256)
+        Xlo[e] = bf16_rne(Xl[e] - __uint_as_float((uint32_t)Xh[e] << 16));
 }
 
 // ---------------------------------------------------------------- hash
@@ -802,6 +829,15 @@ hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t
 {
     hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 4 * LY_ROWS)), dim3(256), 0, s, X, n, d, dp,
                        perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+    return hipGetLastError();
+}
+
+hipError_t launch_lo_rows(const float *Xl, const uint16_t *Xh, int64_t count, uint16_t *Xlo, hipStream_t s)
+{
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_lo_rows, dim3((unsigned)blocks), dim3(256), 0, s, Xl, Xh, count, Xlo);
     return hipGetLastError();
 }
 

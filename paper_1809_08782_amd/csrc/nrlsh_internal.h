@@ -53,8 +53,13 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
                                  int m, const double *bounds, int32_t *sid, uint64_t *layout_key,
                                  int32_t *layout_val, double *keymax, int32_t *subend, hipStream_t s);
 
+// lo = bf16(x - hi) of `count` stored values (the bf16x3 screen's lo part).
+hipError_t launch_lo_rows(const float *Xl, const uint16_t *Xh, int64_t count, uint16_t *Xlo,
+                          hipStream_t s);
+
 // Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
-// key and sub-dataset of each stored row, plus its bfloat16 hi / lo split.
+// key and sub-dataset of each stored row, plus its bfloat16 image Xh and, when
+// Xlo is not NULL, the lo part bf16(x - hi).
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
                          const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
                          uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s);
