@@ -833,6 +833,8 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, 16);
     std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
+    int ncells_top = 0;  // cells of the whole top sub-datasets come first
+    while (ncells_top < ncells && ce[3 * (size_t)ncells_top] >= j_lo) ++ncells_top;
     Block blk;
     const size_t o_ce = blk.reserve<int32_t>(ce.size()), o_ch = blk.reserve<int32_t>(ch.size()),
                  o_qc = blk.reserve<uint32_t>((size_t)B * sh.qsets * sh.W),
@@ -900,7 +902,7 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         }
         tm.begin("screen_max");
         HIPX(launch_screen_max(ix->Xl.get(), Xh, Xlo, ix->key_l.get(), ix->codes_l.get(), sq, nb, sh,
-                               cells.get(), ncells, qcodes.get(), ghthr.get(), gtie.get(),
+                               cells.get(), ncells, ncells_top, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
         // screen, then the exact re-rank of the kept lists right behind it; the

@@ -984,7 +984,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                 htie = tie[64 + tid];
                 pstar = gpstar[q];
             }
-            if (!MAXMODE) th = theta[q];
+            if (!MAXMODE || Usub) th = theta[q];  // pass A reads it only to skip chunks
             qn = qnorm[q];
 #pragma unroll
             for (int w = 0; w < W; ++w) qc_s[tid * W + w] = qcodes[qrow(q, j, qsets) * W + w];
@@ -994,9 +994,10 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
         pstar_s[tid] = pstar;
         th_s[tid] = th;
         qn_s[tid] = qn;
-        // pass B: no item of sub-dataset j (norms <= U_j) can be kept for a
-        // query whose theta exceeds qn U_j (1 + 2 gam + 2^-15): ip32 + e is at
-        // most ||q|| ||x|| + 2 e (Cauchy-Schwarz); such queries skip the chunk
+        // no item of sub-dataset j (norms <= U_j) can be kept (pass B), or raise
+        // a group maximum to theta (pass A), for a query whose theta exceeds
+        // qn U_j (1 + 2 gam + 2^-15): ip32 + e is at most ||q|| ||x|| + 2 e
+        // (Cauchy-Schwarz); a chunk that no query of the tile reaches is skipped
         const bool reach = !Usub || q >= nq ||
                            !((double)th > (double)qn * Usub[j] * (1.0 + 2.0 * (double)gam + 0x1p-15) + 0x1p-80);
         const uint64_t b = __ballot((hthr >= 0 || htie >= 0) && reach);
@@ -1183,8 +1184,8 @@ __global__ __launch_bounds__(256, 3) void k_screen1(NRLSH_SCREEN_PARAMS)
 // to cover float rounding; -inf when fewer than k groups hold probed items.
 // One wave per query.
 template <int S>
-__global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int ncol, int k,
-                                              float *__restrict__ theta)
+__global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int stride, int ncol,
+                                              int k, float *__restrict__ theta)
 {
     const int lane = threadIdx.x;
     const int64_t q = blockIdx.x;
@@ -1192,7 +1193,7 @@ __global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, in
     top.init(k);
     for (int c0 = 0; c0 < ncol; c0 += 64) {
         const int c = c0 + lane;
-        const float v = c < ncol ? cmax[q * ncol + c] : -INFINITY;
+        const float v = c < ncol ? cmax[q * stride + c] : -INFINITY;
         top.offer((double)v, c, c < ncol && v > -INFINITY, lane);
     }
     const double kth = __shfl(top.tv[top.ks], top.kl, 64);
@@ -1357,12 +1358,12 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
         hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
                            Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
                            cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets,
-                           MAXMODE ? nullptr : Q.U, MAXMODE ? nullptr : Q.pairs);
+                           Q.U, MAXMODE ? nullptr : Q.pairs);
     else
         hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
                            codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
                            gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L,
-                           sh.qsets, MAXMODE ? nullptr : Q.U, MAXMODE ? nullptr : Q.pairs);
+                           sh.qsets, Q.U, MAXMODE ? nullptr : Q.pairs);
     return hipGetLastError();
 }
 
@@ -1373,9 +1374,10 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
                                   int nchunks, const uint32_t *qcodes, const int32_t *ghthr,
                                   const int32_t *gtie, const int32_t *gpstar, const float *theta,
                                   int cap, int32_t *counts, int32_t *lists, float *cmax,
-                                  hipStream_t s)
+                                  hipStream_t s, int stride = 0)
 {
-    const int ncol = MAXMODE ? nchunks * SC_GROUPS : 0;
+    // MAXMODE: row stride of cmax (stride, or this launch's own columns)
+    const int ncol = MAXMODE ? (stride ? stride : nchunks * SC_GROUPS) : 0;
     if (Xh && Xlo) {
         // per coordinate 3.1 * 2^-16 |q x| dropped by the split, plus FP32
         // accumulation of 3d exact products: 2 * 1.02 * gamma_{3d}
@@ -1420,25 +1422,50 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
     return hipGetLastError();
 }
 
+static void launch_theta(const float *cmax, int stride, int ncol, int64_t nq, int k, float *theta,
+                         hipStream_t s)
+{
+    const int S = (k + 63) / 64;
+    const dim3 grid((unsigned)nq), block(64);
+    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+}
+
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                              const double *key_l, const uint32_t *codes_l,
                              const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
-                             int ncells, const uint32_t *qcodes, const int32_t *ghthr,
+                             int ncells, int ncells_top, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s)
 {
-    hipError_t e = launch_screen_t<true>(Xl, Xh, Xlo, key_l, codes_l, Q, nq, sh, cells, ncells,
-                                         qcodes, ghthr, gtie, gpstar, nullptr, 0, nullptr, nullptr,
-                                         cmax, s);
-    if (e != hipSuccess) return e;
-    const int S = (sh.k + 63) / 64;
     const int ncol = ncells * SC_GROUPS;
-    const dim3 grid((unsigned)nq), block(64);
-    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, ncol, sh.k, theta);
-    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, ncol, sh.k, theta);
-    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, ncol, sh.k, theta);
-    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, ncol, sh.k, theta);
-    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, ncol, sh.k, theta);
+    if (Q.U && ncells_top > 0 && ncells_top < ncells) {
+        // theta from the top sub-datasets' cells first; the other cells skip
+        // every tile whose queries their items cannot lift above it (their
+        // groups stay -inf, and groups below it cannot change the k-th largest)
+        ScreenQueries q1 = Q;
+        q1.U = nullptr;
+        hipError_t e = launch_screen_t<true>(Xl, Xh, Xlo, key_l, codes_l, q1, nq, sh, cells, ncells_top,
+                                             qcodes, ghthr, gtie, gpstar, nullptr, 0, nullptr, nullptr,
+                                             cmax, s, ncol);
+        if (e != hipSuccess) return e;
+        launch_theta(cmax, ncol, ncells_top * SC_GROUPS, nq, sh.k, theta, s);
+        e = launch_screen_t<true>(Xl, Xh, Xlo, key_l, codes_l, Q, nq, sh, cells + 3 * ncells_top,
+                                  ncells - ncells_top, qcodes, ghthr, gtie, gpstar, theta, 0, nullptr,
+                                  nullptr, cmax + ncells_top * SC_GROUPS, s, ncol);
+        if (e != hipSuccess) return e;
+    } else {
+        ScreenQueries q1 = Q;
+        q1.U = nullptr;
+        hipError_t e = launch_screen_t<true>(Xl, Xh, Xlo, key_l, codes_l, q1, nq, sh, cells, ncells,
+                                             qcodes, ghthr, gtie, gpstar, nullptr, 0, nullptr, nullptr,
+                                             cmax, s, ncol);
+        if (e != hipSuccess) return e;
+    }
+    launch_theta(cmax, ncol, ncol, nq, sh.k, theta, s);
     return hipGetLastError();
 }
 

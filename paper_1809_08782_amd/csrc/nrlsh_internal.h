@@ -185,7 +185,9 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
 //   launch_screen_max: per (query, 32-item group of a cell) the largest lower
 //     bound over the group's probed items (cmax: nq x ncells x groups), then
 //     theta[q] = the k-th largest of them (lowered for rounding; -inf if fewer
-//     than k groups hold probed items).
+//     than k groups hold probed items).  With Q.U, the first ncells_top cells
+//     go first and give a theta that lets the other cells skip the tiles whose
+//     queries their items cannot lift above it (the result is the same).
 //   launch_screen: appends every probed pair whose FP32 upper bound reaches
 //     theta[q] to lists (nq x cap) and counts all of them (counts zeroed by
 //     the caller; counts[q] > cap means the list overflowed).
@@ -222,7 +224,7 @@ size_t screen_lds_bytes(int dp, int kind);
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
                              const double *key_l, const uint32_t *codes_l,
                              const ScreenQueries &Q, int64_t nq, const QueryShape &sh, const int32_t *cells,
-                             int ncells, const uint32_t *qcodes, const int32_t *ghthr,
+                             int ncells, int ncells_top, const uint32_t *qcodes, const int32_t *ghthr,
                              const int32_t *gtie, const int32_t *gpstar, float *cmax, float *theta,
                              hipStream_t s);
 hipError_t launch_screen(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,
