@@ -849,10 +849,16 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_qn = blk.reserve<float>(kind != SCREEN_FP32 ? (size_t)B : 1),
                  o_ta = blk.reserve<float>((size_t)B), o_co = blk.reserve<int32_t>((size_t)B),
                  o_li = blk.reserve<int32_t>((size_t)B * cap),
-                 o_np = blk.reserve<unsigned long long>(1);
+                 o_np = blk.reserve<unsigned long long>(1),
+                 o_oka = blk.reserve<uint64_t>((size_t)B), o_okb = blk.reserve<uint64_t>((size_t)B),
+                 o_ova = blk.reserve<int32_t>((size_t)B), o_ovb = blk.reserve<int32_t>((size_t)B),
+                 o_otmp = blk.reserve<uint8_t>(radix_sort_tmp_bytes(B));
     blk.allocate(s);
     DBuf<int32_t> cells = blk.view<int32_t>(o_ce), chunks = blk.view<int32_t>(o_ch);
     DBuf<unsigned long long> npairs = blk.view<unsigned long long>(o_np);
+    DBuf<uint64_t> oka = blk.view<uint64_t>(o_oka), okb = blk.view<uint64_t>(o_okb);
+    DBuf<int32_t> ova = blk.view<int32_t>(o_ova), ovb = blk.view<int32_t>(o_ovb);
+    DBuf<uint8_t> otmp = blk.view<uint8_t>(o_otmp);
     HIPX(hipMemsetAsync(npairs.get(), 0, sizeof(unsigned long long), s));
     HIPX(hipMemcpyAsync(cells.get(), ce.data(), ce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
@@ -905,6 +911,14 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                cells.get(), ncells, ncells_top, qcodes.get(), ghthr.get(), gtie.get(),
                                gpstar.get(), cmax.get(), theta.get(), s));
         tm.end();
+        if (kind != SCREEN_FP32) {
+            // pass B takes the queries in order of theta / ||q||: tiles of
+            // alike queries skip more chunks by the norm bound
+            int32_t *order = nullptr;
+            HIPX(launch_query_order(theta.get(), qn.get(), nb, oka.get(), ova.get(), okb.get(), ovb.get(),
+                                    otmp.get(), &order, s));
+            sq.order = order;
+        }
         // screen, then the exact re-rank of the kept lists right behind it; the
         // host checks afterwards whether a list overflowed (then the batch is
         // screened again with longer lists, which overwrites the results)

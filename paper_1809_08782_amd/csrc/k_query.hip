@@ -920,6 +920,21 @@ __global__ __launch_bounds__(256) void k_query_bf16(const float *__restrict__ Q,
     if (nonfinite && __ballot(bad) != 0ull && lane == 0) atomicOr(nonfinite, 1u);
 }
 
+// Sort keys of the keep pass's query order: theta / ||q|| descending (as an
+// order-preserving 32-bit word, complemented), queries without a theta last.
+__global__ __launch_bounds__(256) void k_query_order(const float *__restrict__ theta,
+                                                     const float *__restrict__ qn, int64_t nq,
+                                                     uint64_t *__restrict__ key, int32_t *__restrict__ val)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    const float r = qn[q] > 0.f ? theta[q] / qn[q] : -INFINITY;
+    uint32_t u = __float_as_uint(r == r ? r : -INFINITY);
+    u = (u >> 31) ? ~u : (u | 0x80000000u);  // larger r, larger word
+    key[q] = (uint64_t)(~u);
+    val[q] = (int32_t)q;
+}
+
 // Probe bounds when the budget covers every item (T >= n): every bucket of
 // every sub-dataset is probed whole and there is no threshold bucket to cut;
 // rows past nq get hthr = -1 as the threshold pass leaves them.  The bound
@@ -953,10 +968,11 @@ __global__ __launch_bounds__(256) void k_probe_all(int64_t nq, int64_t tiles, in
         const int32_t *__restrict__ gtie, const int32_t *__restrict__ gpstar,                   \
         const float *__restrict__ theta, float gam, int cap, int32_t *__restrict__ counts,      \
         int32_t *__restrict__ lists, float *__restrict__ cmax, int ncol, int qsb, int L, int qsets, \
-        const double *__restrict__ Usub, unsigned long long *__restrict__ npairs
+        const double *__restrict__ Usub, unsigned long long *__restrict__ npairs,                \
+        const int32_t *__restrict__ qidx
 #define NRLSH_SCREEN_ARGS                                                                      \
     Xh, Xlo, dp, codes_l, key_l, Qh, Ql, qnorm, nq, chunks, m, qcodes, ghthr, gtie, gpstar, theta, \
-        gam, cap, counts, lists, cmax, ncol, qsb, L, qsets, Usub, npairs
+        gam, cap, counts, lists, cmax, ncol, qsb, L, qsets, Usub, npairs, qidx
 
 template <int W, bool MAXMODE, bool X3>
 __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
@@ -972,16 +988,22 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
               pend = chunks[3 * blockIdx.y + 2];
     const int64_t q0 = (int64_t)tile * 64;
+    // row r of the tile is query qmap(q0 + r): the batch order, or (pass B)
+    // the order of qidx, which groups queries of similar theta / ||q|| so that
+    // whole tiles skip the chunks none of them can keep
+    auto qmap = [&](int64_t r) -> int64_t { return (qidx && r < nq) ? (int64_t)qidx[r] : r; };
 
     if (tid < 64) {
-        const int64_t q = q0 + tid;
+        const int64_t q = qmap(q0 + tid);
         int hthr = -1, htie = -1, pstar = -1;
         float th = -INFINITY, qn = 0.f;
         if (q < nq) {
-            hthr = ghthr[((int64_t)tile * m + j) * 64 + tid];
-            const int32_t *tie = gtie + (int64_t)tile * 4 * 64;
-            if (tie[tid] == j) {
-                htie = tie[64 + tid];
+            const int64_t qt = q >> 6;
+            const int ql0 = (int)(q & 63);
+            hthr = ghthr[(qt * m + j) * 64 + ql0];
+            const int32_t *tie = gtie + qt * 4 * 64;
+            if (tie[ql0] == j) {
+                htie = tie[64 + ql0];
                 pstar = gpstar[q];
             }
             if (!MAXMODE || Usub) th = theta[q];  // pass A reads it only to skip chunks
@@ -1021,11 +1043,12 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     for (int idx = tid; idx < 64 * v8; idx += 256) {
         const int r = idx / v8, c = 8 * (idx - r * v8);
         const bool ok = q0 + r < nq && c < dp;
+        const int64_t qr = qmap(q0 + r);
         *reinterpret_cast<u16x8 *>(&qsh[r * qsb + c]) =
-            ok ? *reinterpret_cast<const u16x8 *>(Qh + (q0 + r) * dp + c) : z8;
+            ok ? *reinterpret_cast<const u16x8 *>(Qh + qr * dp + c) : z8;
         if (X3)
             *reinterpret_cast<u16x8 *>(&qsl[r * qsb + c]) =
-                ok ? *reinterpret_cast<const u16x8 *>(Ql + (q0 + r) * dp + c) : z8;
+                ok ? *reinterpret_cast<const u16x8 *>(Ql + qr * dp + c) : z8;
     }
     __syncthreads();
 
@@ -1144,7 +1167,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     if (MAXMODE) {
                         if (probed) gmax[ib >> 1] = fmaxf(gmax[ib >> 1], ip - e);
                     } else if (probed && !(ip + e < th)) {
-                        const int64_t q = q0 + ql;
+                        const int64_t q = qmap(q0 + ql);
                         const int slot = atomicAdd(&counts[q], 1);
                         if (slot < cap) lists[q * cap + slot] = pi;
                     }
@@ -1301,6 +1324,16 @@ hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const 
     return hipGetLastError();
 }
 
+hipError_t launch_query_order(const float *theta, const float *qn, int64_t nq, uint64_t *ka, int32_t *va,
+                              uint64_t *kb, int32_t *vb, void *tmp, int32_t **order, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_query_order, dim3(ceil_div(nq, 256)), dim3(256), 0, s, theta, qn, nq, ka, va);
+    bool in_b = false;
+    hipError_t e = radix_sort(ka, va, kb, vb, nq, 32, tmp, &in_b, s);
+    *order = in_b ? vb : va;
+    return e;
+}
+
 hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
                             int32_t *gpstar, hipStream_t s)
 {
@@ -1358,12 +1391,12 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
         hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
                            Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
                            cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets,
-                           Q.U, MAXMODE ? nullptr : Q.pairs);
+                           Q.U, MAXMODE ? nullptr : Q.pairs, MAXMODE ? nullptr : Q.order);
     else
         hipLaunchKernelGGL((k_screen3<W, MAXMODE, X3>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp,
                            codes_l, key_l, Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie,
                            gpstar, theta, gam, cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L,
-                           sh.qsets, Q.U, MAXMODE ? nullptr : Q.pairs);
+                           sh.qsets, Q.U, MAXMODE ? nullptr : Q.pairs, MAXMODE ? nullptr : Q.order);
     return hipGetLastError();
 }
 

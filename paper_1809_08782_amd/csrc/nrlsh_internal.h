@@ -209,7 +209,15 @@ struct ScreenQueries {
     // pass B adds the (query, item) pairs of every chunk it does not skip
     // (valid queries of the tile x items of the chunk), or NULL
     unsigned long long *pairs = nullptr;
+    // pass B's query order (a permutation of the batch), or NULL for the
+    // batch order
+    const int32_t *order = nullptr;
 };
+// Permutation of a batch's queries by theta_q / ||q|| descending (queries
+// without a theta last), through a radix sort in the given buffers (nq each;
+// tmp: radix_sort_tmp_bytes(nq)); *order points into va or vb.
+hipError_t launch_query_order(const float *theta, const float *qn, int64_t nq, uint64_t *ka, int32_t *va,
+                              uint64_t *kb, int32_t *vb, void *tmp, int32_t **order, hipStream_t s);
 hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
                              float *qn, hipStream_t s, uint32_t *nonfinite = nullptr);
 // Bounds for a budget that covers every item (T >= n): ghthr = 64 (at least
