@@ -107,6 +107,107 @@ int current_device()
     return dev;
 }
 
+namespace {
+struct CacheEntry {
+    void *p;
+    size_t bytes;
+    hipStream_t s;  // stream of the release
+    hipEvent_t ev;  // recorded on s at the release
+    int dev;
+};
+constexpr size_t kCacheBytes = size_t(8) << 30;  // held at most, all devices
+std::mutex g_cache_mu;
+// never destroyed: blocks still cached when the process ends go with it
+std::vector<CacheEntry> &g_cache = *new std::vector<CacheEntry>();
+// idle events, per device (an event is recorded on streams of its own device)
+std::map<int, std::vector<hipEvent_t>> &g_events = *new std::map<int, std::vector<hipEvent_t>>();
+size_t g_cache_held = 0;
+
+void drop_entry(const CacheEntry &e)
+{
+    // the block's last use is finished once its event is: free it on the
+    // library stream of its device (the stream of the release may be gone)
+    (void)hipEventSynchronize(e.ev);
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    if (cur != e.dev) (void)hipSetDevice(e.dev);
+    (void)hipFreeAsync(e.p, library_stream(e.dev));
+    if (cur != e.dev) (void)hipSetDevice(cur);
+    g_events[e.dev].push_back(e.ev);
+}
+}  // namespace
+
+void *cached_alloc(size_t bytes, hipStream_t s, int *dev_out)
+{
+    const int dev = current_device();
+    *dev_out = dev;
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        int best = -1;
+        for (int i = 0; i < (int)g_cache.size(); ++i) {
+            const CacheEntry &e = g_cache[(size_t)i];
+            if (e.dev != dev || e.bytes < bytes || e.bytes > bytes + bytes / 2 + (size_t(1) << 20)) continue;
+            if (best >= 0 && e.bytes >= g_cache[(size_t)best].bytes) continue;
+            if (e.s == s || hipEventQuery(e.ev) == hipSuccess) best = i;
+        }
+        if (best >= 0) {
+            const CacheEntry e = g_cache[(size_t)best];
+            g_cache.erase(g_cache.begin() + best);
+            g_cache_held -= e.bytes;
+            g_events[e.dev].push_back(e.ev);
+            return e.p;
+        }
+    }
+    void *v = nullptr;
+    hipError_t e = hipMallocAsync(&v, bytes, s);
+    if (e != hipSuccess) {
+        // give the cached blocks back to the pool and try once more
+        {
+            std::lock_guard<std::mutex> g(g_cache_mu);
+            for (const CacheEntry &c : g_cache) drop_entry(c);
+            g_cache.clear();
+            g_cache_held = 0;
+        }
+        e = hipMallocAsync(&v, bytes, s);
+    }
+    if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
+    return v;
+}
+
+void cached_free(void *p, size_t bytes, hipStream_t s, int dev)
+{
+    if (!p) return;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    std::vector<hipEvent_t> &pool = g_events[dev];
+    hipEvent_t ev = nullptr;
+    if (!pool.empty()) {
+        ev = pool.back();
+        pool.pop_back();
+    } else {
+        int cur = 0;
+        (void)hipGetDevice(&cur);
+        if (cur != dev) (void)hipSetDevice(dev);
+        const hipError_t ce = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+        if (cur != dev) (void)hipSetDevice(cur);
+        if (ce != hipSuccess) {
+            (void)hipFreeAsync(p, s);
+            return;
+        }
+    }
+    if (hipEventRecord(ev, s) != hipSuccess) {
+        pool.push_back(ev);
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    g_cache.push_back(CacheEntry{p, bytes, s, ev, dev});
+    g_cache_held += bytes;
+    while (g_cache_held > kCacheBytes && !g_cache.empty()) {  // oldest first
+        drop_entry(g_cache.front());
+        g_cache_held -= g_cache.front().bytes;
+        g_cache.erase(g_cache.begin());
+    }
+}
+
 }  // namespace host
 }  // namespace nrlsh
 

@@ -107,6 +107,12 @@ hipStream_t library_stream(int dev);
 // Keeps freed stream-ordered memory in the device pool.
 void prepare_pool(int dev);
 int current_device();
+// Device memory with a small cache in front of the stream-ordered allocator
+// (whose calls cost tens of microseconds each): a released block is kept and
+// handed out again for a request of about its size on the same stream, or on
+// any stream once the work queued before its release has finished.
+void *cached_alloc(size_t bytes, hipStream_t s, int *dev);
+void cached_free(void *p, size_t bytes, hipStream_t s, int dev);
 
 // Stream-ordered device buffer; freed on the stream it was allocated on.  A
 // view (DBuf::view) points into memory owned elsewhere and frees nothing.
@@ -115,14 +121,14 @@ struct DBuf {
     T *p = nullptr;
     hipStream_t s = nullptr;
     bool own = true;
+    size_t bytes = 0;
+    int dev = 0;
     DBuf() = default;
     DBuf(size_t count, hipStream_t st) : s(st)
     {
         if (count == 0) count = 1;
-        void *v = nullptr;
-        hipError_t e = hipMallocAsync(&v, count * sizeof(T), st);
-        if (e != hipSuccess) throw_hip(e, "hipMallocAsync");
-        p = static_cast<T *>(v);
+        bytes = count * sizeof(T);
+        p = static_cast<T *>(cached_alloc(bytes, st, &dev));
     }
     static DBuf view(T *ptr)
     {
@@ -133,20 +139,22 @@ struct DBuf {
     }
     DBuf(const DBuf &) = delete;
     DBuf &operator=(const DBuf &) = delete;
-    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s), own(o.own) { o.p = nullptr; }
+    DBuf(DBuf &&o) noexcept : p(o.p), s(o.s), own(o.own), bytes(o.bytes), dev(o.dev) { o.p = nullptr; }
     DBuf &operator=(DBuf &&o) noexcept
     {
         reset();
         p = o.p;
         s = o.s;
         own = o.own;
+        bytes = o.bytes;
+        dev = o.dev;
         o.p = nullptr;
         return *this;
     }
     ~DBuf() { reset(); }
     void reset()
     {
-        if (p && own) (void)hipFreeAsync(p, s);
+        if (p && own) cached_free(p, bytes, s, dev);
         p = nullptr;
     }
     T *get() const { return p; }
