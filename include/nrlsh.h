@@ -121,7 +121,10 @@ typedef enum { NRLSH_PROJECTIONS_SHARED = 0, NRLSH_PROJECTIONS_PER_SUBSET = 1 } 
 
 typedef struct nrlsh_build_opts {
     int32_t struct_size;  /* sizeof(nrlsh_build_opts) */
-    int32_t device_ptrs;  /* 1: items is a device pointer */
+    int32_t device_ptrs;  /* 1: items is a device pointer, aligned to 16 bytes
+                             when d % 4 == 0, to 8 bytes when d is even, else
+                             to 4 (any row of an aligned allocation is);
+                             otherwise NRLSH_E_INVALID_ARG */
     void *stream;         /* hipStream_t to run on, or NULL for the library's stream */
     double eps;           /* adjusted metric s_hat = U_j cos[pi (1-eps)(1 - l/L)]
                              (Section 3.3), 0 <= eps < 1; 0 = Eq. 12 */

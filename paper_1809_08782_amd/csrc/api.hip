@@ -1141,6 +1141,12 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         tables = opts->bucket_tables;
     if (tables != 0 && tables != 1) return fail(NRLSH_E_INVALID_ARG, "bucket_tables must be 0 or 1");
     const bool on_device = opts && opts->device_ptrs;
+    // device rows are read in vectors of the widest of 4, 2, 1 floats that
+    // divides d, so the first row must start on such a vector
+    const int vw = d % 4 == 0 ? 4 : (d % 2 == 0 ? 2 : 1);
+    if (on_device && reinterpret_cast<uintptr_t>(items) % (uintptr_t)(4 * vw) != 0)
+        return fail(NRLSH_E_INVALID_ARG, "device items must be aligned to 16 bytes (d % 4 == 0), 8 bytes (d even) "
+                                         "or 4 bytes");
     return guarded([&]() -> nrlsh_status {
         const int dev = current_device();
         prepare_pool(dev);

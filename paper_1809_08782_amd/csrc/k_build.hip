@@ -14,6 +14,7 @@ namespace nrlsh {
 namespace {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef float floatx2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
@@ -249,11 +250,15 @@ __global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ ske
 
 // Stored copy: row p of Xl is item perm[p], zero-padded to dp floats; the
 // key and sub-dataset of each stored row come along.  The same rows are also
-// split into two bfloat16 parts, x = hi + lo + r with hi = bf16(x) and
-// lo = bf16(x - hi) (round to nearest even; |r| <= 2^-16 |x|), for the
-// query-tiled screen.  One wave copies LY_ROWS rows, 64 floats per
-// instruction.
-constexpr int LY_ROWS = 8;
+// rounded to bfloat16 (hi = bf16(x), round to nearest even) for the
+// query-tiled screen and, when Xlo is given, split further into lo =
+// bf16(x - hi) (|x - hi - lo| <= 2^-16 |x|).
+// A wave copies LY_ROWS consecutive stored rows: their source indices are
+// read once, then the rows are treated as one run of VW-float vectors
+// (VW = the widest of 4, 2, 1 dividing d, so no vector crosses a row end)
+// of which each lane keeps LY_B loads in flight before storing.
+constexpr int LY_ROWS = 16;
+constexpr int LY_B = 8;
 
 __device__ __forceinline__ uint16_t bf16_rne(float f)
 {
@@ -262,6 +267,25 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+template <int VW>
+struct LyVec;
+template <>
+struct LyVec<4> {
+    using F = floatx4;
+    using H = ushort4;
+};
+template <>
+struct LyVec<2> {
+    using F = floatx2;
+    using H = ushort2;
+};
+template <>
+struct LyVec<1> {
+    using F = float;
+    using H = uint16_t;
+};
+
+template <int VW>
 __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int64_t n, int d,
                                                 int dp, const int32_t *__restrict__ perm,
                                                 const double *__restrict__ key,
@@ -271,44 +295,48 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
                                                 double *__restrict__ key_l,
                                                 int32_t *__restrict__ sid_l)
 {
+    using F = typename LyVec<VW>::F;
+    using H = typename LyVec<VW>::H;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * LY_ROWS;
+    const bool mine = lane < LY_ROWS && p0 + lane < n;
+    const int32_t src_row = mine ? perm[p0 + lane] : 0;
+    if (mine) {
+        key_l[p0 + lane] = key[src_row];
+        sid_l[p0 + lane] = sid[src_row];
+    }
+    const int nv = dp / VW;  // vectors per stored row
+    const int total = LY_ROWS * nv;
+    for (int e0 = 0; e0 < total; e0 += 64 * LY_B) {
+        float v[LY_B][VW];
+        int64_t dst[LY_B];  // first stored element of the vector, -1 = none
 #pragma unroll
-    for (int r = 0; r < LY_ROWS; ++r) {
-        const int64_t p = p0 + r;
-        if (p >= n) break;
-        const int64_t i = perm[p];
-        const float *src = X + i * d;
-        float *dst = Xl + p * dp;
-        if ((d & 3) == 0) {  // 16-byte rows: 4 values per lane per step (dp is a multiple of 8)
-            for (int c = 4 * lane; c < dp; c += 256) {
-                floatx4 v = floatx4{0.f, 0.f, 0.f, 0.f};
-                if (c < d) v = *reinterpret_cast<const floatx4 *>(src + c);
-                ushort4 h, l;
-                h.x = bf16_rne(v[0]);
-                h.y = bf16_rne(v[1]);
-                h.z = bf16_rne(v[2]);
-                h.w = bf16_rne(v[3]);
-                l.x = bf16_rne(v[0] - __uint_as_float((uint32_t)h.x << 16));
-                l.y = bf16_rne(v[1] - __uint_as_float((uint32_t)h.y << 16));
-                l.z = bf16_rne(v[2] - __uint_as_float((uint32_t)h.z << 16));
-                l.w = bf16_rne(v[3] - __uint_as_float((uint32_t)h.w << 16));
-                *reinterpret_cast<floatx4 *>(dst + c) = v;
-                *reinterpret_cast<ushort4 *>(Xh + p * dp + c) = h;
-                if (Xlo) *reinterpret_cast<ushort4 *>(Xlo + p * dp + c) = l;
-            }
-        } else {
-            for (int c = lane; c < dp; c += 64) {
-                const float v = c < d ? src[c] : 0.0f;
-                const uint16_t hi = bf16_rne(v);
-                dst[c] = v;
-                Xh[p * dp + c] = hi;
-                if (Xlo) Xlo[p * dp + c] = bf16_rne(v - __uint_as_float((uint32_t)hi << 16));
-            }
+        for (int b = 0; b < LY_B; ++b) {
+            const int e = e0 + 64 * b + lane;
+            const int r = e / nv, c = (e - r * nv) * VW;
+            const int64_t i = __shfl(src_row, r & (LY_ROWS - 1), 64);
+            const bool ok = e < total && p0 + r < n;
+            dst[b] = ok ? (p0 + r) * dp + c : -1;
+            F t = F{};
+            if (ok && c < d) t = *reinterpret_cast<const F *>(X + i * d + c);
+#pragma unroll
+            for (int u = 0; u < VW; ++u) v[b][u] = reinterpret_cast<const float *>(&t)[u];
         }
-        if (lane == 0) {
-            key_l[p] = key[i];
-            sid_l[p] = sid[i];
+#pragma unroll
+        for (int b = 0; b < LY_B; ++b) {
+            if (dst[b] < 0) continue;
+            F t;
+            H h, l;
+#pragma unroll
+            for (int u = 0; u < VW; ++u) {
+                const uint16_t hu = bf16_rne(v[b][u]);
+                reinterpret_cast<float *>(&t)[u] = v[b][u];
+                reinterpret_cast<uint16_t *>(&h)[u] = hu;
+                reinterpret_cast<uint16_t *>(&l)[u] = bf16_rne(v[b][u] - __uint_as_float((uint32_t)hu << 16));
+            }
+            *reinterpret_cast<F *>(Xl + dst[b]) = t;
+            *reinterpret_cast<H *>(Xh + dst[b]) = h;
+            if (Xlo) *reinterpret_cast<H *>(Xlo + dst[b]) = l;
         }
     }
 }
@@ -410,10 +438,22 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
 
     const int r16 = lane & 15, g = lane >> 4;
     for (int kc0 = 0; kc0 < dp; kc0 += H_KC) {
+        // every load of the chunk is issued before the first LDS store, so the
+        // block waits for one round trip per chunk, not one per element
+        constexpr int PER = NB * H_KC / (H_WAVES * 64);
+        static_assert(NB * H_KC % (H_WAVES * 64) == 0, "whole staging rounds");
+        float av[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * H_WAVES * 64;
+            const int r = e / H_KC, k = kc0 + (e % H_KC);
+            av[u] = (r < L && k < d) ? A[(int64_t)r * (d + 1) + k] : 0.f;
+        }
         __syncthreads();
-        for (int e = threadIdx.x; e < NB * H_KC; e += H_WAVES * 64) {
-            const int r = e / H_KC, c = e - (e / H_KC) * H_KC, k = kc0 + c;
-            As[r * H_KS + c] = (r < L && k < d) ? A[(int64_t)r * (d + 1) + k] : 0.f;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * H_WAVES * 64;
+            As[(e / H_KC) * H_KS + (e % H_KC)] = av[u];
         }
         __syncthreads();
         const int kend = min(H_KC, dp - kc0);
@@ -607,15 +647,26 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
     const uint8_t *X8 = static_cast<const uint8_t *>(Xq);
     const uint8_t *A8 = static_cast<const uint8_t *>(Aq);
     for (int kc0 = 0; kc0 < dp; kc0 += KCQ) {
+        // all loads of the chunk first, then the LDS stores (one round trip)
+        constexpr int PER = NB * KCQ / (H_WAVES * 64);
+        static_assert(NB * KCQ % (H_WAVES * 64) == 0, "whole staging rounds");
+        uint16_t av[PER];
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * H_WAVES * 64;
+            const int r = e / KCQ, k = kc0 + (e % KCQ);
+            if (ST == 1)
+                av[u] = (r < L && k < dp) ? reinterpret_cast<const uint16_t *>(A8)[(int64_t)r * dp + k] : (uint16_t)0;
+            else
+                av[u] = (r < L && k < dp) ? A8[(int64_t)r * dp + k] : (uint8_t)0;
+        }
         __syncthreads();
-        for (int e = threadIdx.x; e < NB * KCQ; e += H_WAVES * 64) {
-            const int r = e / KCQ, c = e - (e / KCQ) * KCQ, k = kc0 + c;
-            if (ST == 1) {
-                reinterpret_cast<uint16_t *>(As + r * RB)[c] =
-                    (r < L && k < dp) ? reinterpret_cast<const uint16_t *>(A8)[(int64_t)r * dp + k] : (uint16_t)0;
-            } else {
-                As[r * RB + c] = (r < L && k < dp) ? A8[(int64_t)r * dp + k] : (uint8_t)0;
-            }
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int e = threadIdx.x + u * H_WAVES * 64;
+            const int r = e / KCQ, c = e % KCQ;
+            if (ST == 1) reinterpret_cast<uint16_t *>(As + r * RB)[c] = av[u];
+            else As[r * RB + c] = (uint8_t)av[u];
         }
         __syncthreads();
         const int kend = min(KCQ, dp - kc0);
@@ -827,8 +878,13 @@ hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t
                          const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
                          uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_layout, dim3(grid_for(n, 4 * LY_ROWS)), dim3(256), 0, s, X, n, d, dp,
-                       perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+    const dim3 grid(grid_for(n, 4 * LY_ROWS)), block(256);
+    if (d % 4 == 0)
+        hipLaunchKernelGGL(k_layout<4>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+    else if (d % 2 == 0)
+        hipLaunchKernelGGL(k_layout<2>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+    else
+        hipLaunchKernelGGL(k_layout<1>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
     return hipGetLastError();
 }
 

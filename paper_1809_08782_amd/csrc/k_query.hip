@@ -710,6 +710,22 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
 //                    and appends its stored position to the query's list
 //                    (capacity cap; counts may exceed cap, which the host
 //                    detects).  The exact top-k of the probed set lies in it.
+// maximum over the 16 lanes of a DPP row (lanes 16 r .. 16 r + 15), in every
+// lane of the row: two quad swaps, then the half-row and row mirrors, each
+// a data-parallel move into v_max (no LDS crossbar traffic)
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float row16_max(float v)
+{
+    v = fmaxf(v, dpp_move<0xB1>(v));   // quad_perm [1, 0, 3, 2]
+    v = fmaxf(v, dpp_move<0x4E>(v));   // quad_perm [2, 3, 0, 1]
+    v = fmaxf(v, dpp_move<0x141>(v));  // row_half_mirror
+    return fmaxf(v, dpp_move<0x140>(v));  // row_mirror
+}
+
 constexpr int SC_CHUNK = 4096;
 constexpr int SC_CELL = 1024;
 constexpr int SC_GROUPS = SC_CELL / 32;  // 32-item groups per cell (MAXMODE outputs)
@@ -762,9 +778,11 @@ __global__ __launch_bounds__(256) void k_screen(
             all_s = a == ~0ull;
         }
     }
-    if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
-        for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
     __syncthreads();
+    if (MAXMODE && tid < 64 && q0 + tid < nq) {  // groups this block never reaches stay -inf
+        for (int gi = any_s ? (pend - pbeg + 31) / 32 : 0; gi < SC_GROUPS; ++gi)
+            cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
+    }
     if (!any_s) return;  // no query of this tile probes this chunk
 
     // stage the query tile, zero-padded to dp columns
@@ -853,8 +871,7 @@ __global__ __launch_bounds__(256) void k_screen(
                 }
                 if (MAXMODE) {
                     // largest lower bound of this iteration's 32 items for query ql
-#pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) gmax = fmaxf(gmax, __shfl_xor(gmax, o, 64));
+                    gmax = row16_max(gmax);
                     if (r16 == 0 && q0 + ql < nq && p0 < pend)
                         cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32] = gmax;
                 }
@@ -1029,26 +1046,46 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
             all_s = a == ~0ull;
         }
     }
-    if (MAXMODE && tid < 64 && q0 + tid < nq)  // groups this block never reaches stay -inf
-        for (int gi = 0; gi < SC_GROUPS; ++gi) cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
     __syncthreads();
+    // groups this block never reaches stay -inf (the loop below writes every
+    // group of the chunk's items for every query row of the tile)
+    if (MAXMODE && tid < 64 && q0 + tid < nq) {
+        for (int gi = any_s ? (pend - pbeg + 31) / 32 : 0; gi < SC_GROUPS; ++gi)
+            cmax[(q0 + tid) * ncol + blockIdx.y * SC_GROUPS + gi] = -INFINITY;
+    }
     if (!any_s) return;  // no query of this tile probes (or, pass B, can keep) an item of this chunk
     if (npairs && tid == 0)
         atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - q0) * (int64_t)(pend - pbeg)));
 
     // stage the query tile (rows beyond nq and columns beyond dp, up to a
     // multiple of 32, are zero)
+    // (four threads per row, 8 columns each per round; the loads of SQ_U
+    // rounds are issued before their LDS stores, so a tile costs one or two
+    // round trips to memory rather than one per round)
     const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-    const int v8 = (dp + 31) / 32 * 4;
-    for (int idx = tid; idx < 64 * v8; idx += 256) {
-        const int r = idx / v8, c = 8 * (idx - r * v8);
-        const bool ok = q0 + r < nq && c < dp;
-        const int64_t qr = qmap(q0 + r);
-        *reinterpret_cast<u16x8 *>(&qsh[r * qsb + c]) =
-            ok ? *reinterpret_cast<const u16x8 *>(Qh + qr * dp + c) : z8;
-        if (X3)
-            *reinterpret_cast<u16x8 *>(&qsl[r * qsb + c]) =
-                ok ? *reinterpret_cast<const u16x8 *>(Ql + qr * dp + c) : z8;
+    {
+        constexpr int SQ_U = 8;
+        const int r = tid >> 2, cq = 8 * (tid & 3);
+        const bool rok = q0 + r < nq;
+        const int64_t qr = rok ? qmap(q0 + r) : 0;
+        const int nu = (dp + 31) / 32;  // 32-column rounds
+        for (int u0 = 0; u0 < nu; u0 += SQ_U) {
+            u16x8 th[SQ_U], tl[SQ_U];
+#pragma unroll
+            for (int u = 0; u < SQ_U; ++u) {
+                const int c = 32 * (u0 + u) + cq;
+                const bool ok = rok && u0 + u < nu && c < dp;
+                th[u] = ok ? *reinterpret_cast<const u16x8 *>(Qh + qr * dp + c) : z8;
+                tl[u] = (X3 && ok) ? *reinterpret_cast<const u16x8 *>(Ql + qr * dp + c) : z8;
+            }
+#pragma unroll
+            for (int u = 0; u < SQ_U; ++u) {
+                if (u0 + u >= nu) break;
+                const int c = 32 * (u0 + u) + cq;
+                *reinterpret_cast<u16x8 *>(&qsh[r * qsb + c]) = th[u];
+                if (X3) *reinterpret_cast<u16x8 *>(&qsl[r * qsb + c]) = tl[u];
+            }
+        }
     }
     __syncthreads();
 
@@ -1176,8 +1213,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     // largest lower bound of each 32-item group for query ql
 #pragma unroll
                     for (int hg = 0; hg < NB / 2; ++hg) {
-#pragma unroll
-                        for (int o = 1; o < 16; o <<= 1) gmax[hg] = fmaxf(gmax[hg], __shfl_xor(gmax[hg], o, 64));
+                        gmax[hg] = row16_max(gmax[hg]);
                         if (r16 == 0 && q0 + ql < nq && p0 + 32 * hg < pend)
                             cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32 + hg] = gmax[hg];
                     }
@@ -1223,6 +1259,77 @@ __global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, in
     if (lane == 0) {
         const float f = (float)kth;
         theta[q] = kth == -INFINITY ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
+    }
+}
+
+// Order-preserving 32-bit key of a float group maximum; 0 for -inf and NaN
+// (no probed item), below every finite value's key.
+__device__ __forceinline__ uint32_t theta_key(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    return v > -INFINITY ? ((u & 0x80000000u) ? ~u : (u | 0x80000000u)) : 0u;
+}
+__device__ __forceinline__ float theta_value(uint32_t key)
+{
+    return __uint_as_float((key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key);
+}
+// The k-th largest of the 64 lanes' keys (k <= 64), bit by bit from the top:
+// the largest c with at least k lanes at or above it (0 when fewer than k
+// lanes hold a key >= 1).
+__device__ __forceinline__ uint32_t wave_kth_key(uint32_t key, int k)
+{
+    uint32_t ans = 0;
+    for (int b = 31; b >= 0; --b) {
+        const uint32_t c = ans | (1u << b);
+        if (__popcll(__ballot(key >= c)) >= k) ans = c;
+    }
+    return ans;
+}
+
+// theta_q for k <= 64 (the same value as k_theta): the k-th largest lane
+// maximum is a floor that k distinct groups reach; usually few groups lie at
+// or above it, and those are gathered into one key per lane for an exact
+// select.  More than 64 of them (ties, or most values in one lane) fall back
+// to the insertion top-k above the floor.
+__global__ __launch_bounds__(64) void k_theta_small(const float *__restrict__ cmax, int stride, int ncol,
+                                                    int k, float *__restrict__ theta)
+{
+    __shared__ uint32_t cand[64];
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const float *row = cmax + q * stride;
+    float lm = -INFINITY;
+    for (int c = lane; c < ncol; c += 64) lm = fmaxf(lm, row[c]);
+    uint32_t floor_key = wave_kth_key(theta_key(lm), k);
+    if (floor_key == 0u) floor_key = 1u;  // fewer than k lanes hold a group: every group is a candidate
+    int n = 0;
+    for (int c0 = 0; c0 < ncol; c0 += 64) {
+        const int c = c0 + lane;
+        const bool ok = c < ncol && theta_key(row[c]) >= floor_key;
+        const uint64_t m = __ballot(ok);
+        const int pos = n + __popcll(m & ((1ull << lane) - 1ull));
+        if (ok && pos < 64) cand[pos] = theta_key(row[c]);
+        n += __popcll(m);
+    }
+    __syncthreads();
+    uint32_t kth = 0;
+    if (n <= 64) {
+        kth = wave_kth_key(lane < n ? cand[lane] : 0u, k);
+    } else {
+        WaveTopK<1> top;
+        top.init(k);
+        const double fl = floor_key > 1u ? (double)theta_value(floor_key) : -INFINITY;
+        for (int c0 = 0; c0 < ncol; c0 += 64) {
+            const int c = c0 + lane;
+            const float v = c < ncol ? row[c] : -INFINITY;
+            top.offer((double)v, c, c < ncol && v > -INFINITY, lane, fl);
+        }
+        const double kv = __shfl(top.tv[top.ks], top.kl, 64);
+        kth = kv == -INFINITY ? 0u : theta_key((float)kv);
+    }
+    if (lane == 0) {
+        const float f = theta_value(kth);
+        theta[q] = kth == 0u ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
     }
 }
 
@@ -1460,7 +1567,7 @@ static void launch_theta(const float *cmax, int stride, int ncol, int64_t nq, in
 {
     const int S = (k + 63) / 64;
     const dim3 grid((unsigned)nq), block(64);
-    if (S <= 1) hipLaunchKernelGGL(k_theta<1>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    if (S <= 1) hipLaunchKernelGGL(k_theta_small, grid, block, 0, s, cmax, stride, ncol, k, theta);
     else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, stride, ncol, k, theta);
     else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, stride, ncol, k, theta);
     else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, stride, ncol, k, theta);

@@ -63,6 +63,16 @@ def test_build_rejects_bad_eps():
         assert nr.lib().nrlsh_build_ex(X.ctypes.data, 10, 4, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
 
 
+def test_build_rejects_misaligned_device_items():
+    # rejected on the host before any device call: the pointer is never read
+    h = C.c_void_p()
+    opts = _lib.BuildOpts(C.sizeof(_lib.BuildOpts), 1, None, 0.0)
+    for d, addr in ((8, 0x1008), (6, 0x1004), (5, 0x1002)):
+        assert nr.lib().nrlsh_build_ex(C.c_void_p(addr), 10, d, 2, 8, 1, C.byref(opts), C.byref(h)) == INVALID
+        assert "aligned" in nr.nrlsh_last_error()
+        assert not h.value
+
+
 def test_build_rejects_unknown_partition():
     X = np.ones((10, 4), np.float32)
     h = C.c_void_p()
