@@ -924,14 +924,17 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     int64_t cap = std::min<int64_t>(sh.Tq, 1024);
 
     // pass-1 cells: the top sub-datasets whole (at least 16 k lower-bound
-    // groups) plus every 16th cell of the others, so that the
-    // witnesses of theta sit wherever a query's probed items are (a
-    // sub-dataset normalised by an outlying U_j can hash almost all of its
-    // items alike and be probed late); pass-2 chunks: every sub-dataset
+    // groups) plus, when the budget leaves items unprobed, every 16th cell of
+    // the others, so that the witnesses of theta sit wherever a query's
+    // probed items are (a sub-dataset normalised by an outlying U_j can hash
+    // almost all of its items alike and be probed late).  When every item is
+    // probed the top sub-datasets alone give every query k witnesses, and
+    // the highest-norm items are the ones that set theta; pass-2 chunks:
+    // every sub-dataset
     const int64_t want = std::max<int64_t>(2, 16 * (int64_t)k / screen_cell_groups());
     int j_lo = ix->m - 1;
     while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
-    std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, 16);
+    std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, sh.Tq >= sh.n ? 0 : 16);
     std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
     int ncells_top = 0;  // cells of the whole top sub-datasets come first
