@@ -40,6 +40,7 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * KC_ROWS;
     const int sub = lane >> 3, seg = 4 * (lane & 7);  // row 8 it + sub, columns seg .. seg + 3
     const bool vec = (d & 3) == 0;                     // rows 16-byte aligned
+    const bool vec2 = (d & 1) == 0;                    // rows 8-byte aligned
     auto load = [&](floatx4 (&v)[8], int c0) {
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
@@ -49,6 +50,10 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64
             if (row < n) {
                 if (vec && c + 3 < d) {
                     v[it] = *reinterpret_cast<const floatx4 *>(X + row * d + c);
+                } else if (vec2 && c + 3 < d) {  // even d: 8-byte aligned pairs
+                    const floatx2 a = *reinterpret_cast<const floatx2 *>(X + row * d + c);
+                    const floatx2 b = *reinterpret_cast<const floatx2 *>(X + row * d + c + 2);
+                    v[it] = floatx4{a[0], a[1], b[0], b[1]};
                 } else {
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
@@ -438,22 +443,33 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
 
     const int r16 = lane & 15, g = lane >> 4;
     for (int kc0 = 0; kc0 < dp; kc0 += H_KC) {
-        // every load of the chunk is issued before the first LDS store, so the
-        // block waits for one round trip per chunk, not one per element
+        // the chunk's loads are issued SB at a time before their LDS stores,
+        // so the block waits for one round trip per SB elements per thread
         constexpr int PER = NB * H_KC / (H_WAVES * 64);
-        static_assert(NB * H_KC % (H_WAVES * 64) == 0, "whole staging rounds");
-        float av[PER];
+        constexpr int SB = PER <= 16 ? PER : (PER % 16 == 0 ? 16 : 8);
+        static_assert(NB * H_KC % (H_WAVES * 64) == 0 && PER % SB == 0, "whole staging rounds");
+        float av[SB];
+        auto stage_load = [&](int u0) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + u * H_WAVES * 64;
-            const int r = e / H_KC, k = kc0 + (e % H_KC);
-            av[u] = (r < L && k < d) ? A[(int64_t)r * (d + 1) + k] : 0.f;
-        }
-        __syncthreads();
+            for (int u = 0; u < SB; ++u) {
+                const int e = threadIdx.x + (u0 + u) * H_WAVES * 64;
+                const int r = e / H_KC, k = kc0 + (e % H_KC);
+                av[u] = (r < L && k < d) ? A[(int64_t)r * (d + 1) + k] : 0.f;
+            }
+        };
+        auto stage_store = [&](int u0) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + u * H_WAVES * 64;
-            As[(e / H_KC) * H_KS + (e % H_KC)] = av[u];
+            for (int u = 0; u < SB; ++u) {
+                const int e = threadIdx.x + (u0 + u) * H_WAVES * 64;
+                As[(e / H_KC) * H_KS + (e % H_KC)] = av[u];
+            }
+        };
+        stage_load(0);
+        __syncthreads();  // the previous chunk's operands have been read
+        stage_store(0);
+        for (int u0 = SB; u0 < PER; u0 += SB) {
+            stage_load(u0);
+            stage_store(u0);
         }
         __syncthreads();
         const int kend = min(H_KC, dp - kc0);
@@ -647,26 +663,39 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
     const uint8_t *X8 = static_cast<const uint8_t *>(Xq);
     const uint8_t *A8 = static_cast<const uint8_t *>(Aq);
     for (int kc0 = 0; kc0 < dp; kc0 += KCQ) {
-        // all loads of the chunk first, then the LDS stores (one round trip)
+        // loads issued SB at a time before their LDS stores (one round trip
+        // per SB elements per thread)
         constexpr int PER = NB * KCQ / (H_WAVES * 64);
-        static_assert(NB * KCQ % (H_WAVES * 64) == 0, "whole staging rounds");
-        uint16_t av[PER];
+        constexpr int SB = PER <= 16 ? PER : (PER % 16 == 0 ? 16 : 8);
+        static_assert(NB * KCQ % (H_WAVES * 64) == 0 && PER % SB == 0, "whole staging rounds");
+        uint16_t av[SB];
+        auto stage_load = [&](int u0) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + u * H_WAVES * 64;
-            const int r = e / KCQ, k = kc0 + (e % KCQ);
-            if (ST == 1)
-                av[u] = (r < L && k < dp) ? reinterpret_cast<const uint16_t *>(A8)[(int64_t)r * dp + k] : (uint16_t)0;
-            else
-                av[u] = (r < L && k < dp) ? A8[(int64_t)r * dp + k] : (uint8_t)0;
-        }
-        __syncthreads();
+            for (int u = 0; u < SB; ++u) {
+                const int e = threadIdx.x + (u0 + u) * H_WAVES * 64;
+                const int r = e / KCQ, k = kc0 + (e % KCQ);
+                if (ST == 1)
+                    av[u] = (r < L && k < dp) ? reinterpret_cast<const uint16_t *>(A8)[(int64_t)r * dp + k]
+                                              : (uint16_t)0;
+                else
+                    av[u] = (r < L && k < dp) ? A8[(int64_t)r * dp + k] : (uint8_t)0;
+            }
+        };
+        auto stage_store = [&](int u0) {
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int e = threadIdx.x + u * H_WAVES * 64;
-            const int r = e / KCQ, c = e % KCQ;
-            if (ST == 1) reinterpret_cast<uint16_t *>(As + r * RB)[c] = av[u];
-            else As[r * RB + c] = (uint8_t)av[u];
+            for (int u = 0; u < SB; ++u) {
+                const int e = threadIdx.x + (u0 + u) * H_WAVES * 64;
+                const int r = e / KCQ, c = e % KCQ;
+                if (ST == 1) reinterpret_cast<uint16_t *>(As + r * RB)[c] = av[u];
+                else As[r * RB + c] = (uint8_t)av[u];
+            }
+        };
+        stage_load(0);
+        __syncthreads();  // the previous chunk's operands have been read
+        stage_store(0);
+        for (int u0 = SB; u0 < PER; u0 += SB) {
+            stage_load(u0);
+            stage_store(u0);
         }
         __syncthreads();
         const int kend = min(KCQ, dp - kc0);
