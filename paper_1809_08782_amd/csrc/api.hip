@@ -174,6 +174,87 @@ void *cached_alloc(size_t bytes, hipStream_t s, int *dev_out)
     return v;
 }
 
+hipEvent_t event_take(int dev)
+{
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        std::vector<hipEvent_t> &pool = g_events[dev];
+        if (!pool.empty()) {
+            hipEvent_t ev = pool.back();
+            pool.pop_back();
+            return ev;
+        }
+    }
+    int cur = 0;
+    HIPX(hipGetDevice(&cur));
+    if (cur != dev) HIPX(hipSetDevice(dev));
+    hipEvent_t ev = nullptr;
+    const hipError_t ce = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (cur != dev) (void)hipSetDevice(cur);
+    if (ce != hipSuccess) throw_hip(ce, "hipEventCreateWithFlags");
+    return ev;
+}
+
+void event_give(hipEvent_t ev, int dev)
+{
+    if (!ev) return;
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_events[dev].push_back(ev);
+}
+
+namespace {
+struct PinnedEntry {
+    void *p;
+    size_t bytes;
+    hipEvent_t ev;  // NULL: free now
+    int dev;
+};
+std::vector<PinnedEntry> &g_pinned = *new std::vector<PinnedEntry>();
+}  // namespace
+
+void *pinned_take(size_t bytes, size_t *got)
+{
+    {
+        std::lock_guard<std::mutex> g(g_cache_mu);
+        for (size_t i = 0; i < g_pinned.size(); ++i) {
+            const PinnedEntry e = g_pinned[i];
+            if (e.bytes < bytes || (e.ev && hipEventQuery(e.ev) != hipSuccess)) continue;
+            g_pinned.erase(g_pinned.begin() + (ptrdiff_t)i);
+            if (e.ev) g_events[e.dev].push_back(e.ev);
+            *got = e.bytes;
+            return e.p;
+        }
+    }
+    const size_t want = std::max<size_t>(bytes, size_t(64) << 10);
+    void *p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, want, hipHostMallocDefault);
+    if (e != hipSuccess) throw_hip(e, "hipHostMalloc");
+    *got = want;
+    return p;
+}
+
+void pinned_give(void *p, size_t bytes, hipStream_t s, int dev)
+{
+    if (!p) return;
+    hipEvent_t ev = nullptr;
+    if (s) {
+        try {
+            ev = event_take(dev);
+        } catch (...) {
+            ev = nullptr;
+        }
+        if (ev && hipEventRecord(ev, s) != hipSuccess) {
+            event_give(ev, dev);
+            (void)hipStreamSynchronize(s);
+            ev = nullptr;
+        } else if (!ev) {
+            (void)hipStreamSynchronize(s);
+        }
+    }
+    std::lock_guard<std::mutex> g(g_cache_mu);
+    g_pinned.push_back(PinnedEntry{p, bytes, ev, dev});
+}
+
 void cached_free(void *p, size_t bytes, hipStream_t s, int dev)
 {
     if (!p) return;
@@ -378,32 +459,18 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     const int64_t n = ix->n;
     const int d = ix->d, dp = ix->dp, m = ix->m, L = ix->L, W = ix->W;
 
-    // projection matrix (one L-row block, or one per sub-dataset), the
-    // transpose of each block and the FP32 uncertainty band factors
+    // projection matrix: one L-row block, or one per sub-dataset (drawn on
+    // the host once the first kernels are queued)
     const int rows = ix->qsets * L;
-    make_projection(ix->seed, rows, d, ix->A_h);
-    std::vector<float> At_h((size_t)rows * d), tau_h(rows);
-    for (int r = 0; r < rows; ++r) {
-        double nrm2 = 0.0;
-        for (int c = 0; c <= d; ++c) {
-            const double a = ix->A_h[(size_t)r * (d + 1) + c];
-            nrm2 += a * a;
-            if (c < d) At_h[(size_t)c * rows + r] = (float)a;
-        }
-        // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
-        // rounded up so that the band is never narrower than the bound.
-        const double ku = (double)(d + 3) * 0x1p-24;
-        const double tau = 2.0 * (ku / (1.0 - ku)) * std::sqrt(nrm2) * (1.0 + 0x1p-20);
-        tau_h[r] = std::nextafter((float)tau, INFINITY);
-    }
+    const size_t a_elems = (size_t)rows * (d + 1), at_elems = (size_t)rows * d;
 
     Block &B = ix->mem;
     // the bfloat16 copies carry a zeroed tail pad of 32 values: the screen
     // reads whole 32-coordinate steps past the last row's dp values
     const size_t oXl = B.reserve<float>((size_t)n * dp),
                  oXh = B.reserve<uint16_t>((size_t)n * dp + 32),
-                 oA = B.reserve<float>(ix->A_h.size()),
-                 oAt = B.reserve<float>(At_h.size()), okey = B.reserve<double>(n),
+                 oA = B.reserve<float>(a_elems),
+                 oAt = B.reserve<float>(at_elems), okey = B.reserve<double>(n),
                  okeyl = B.reserve<double>(n), okm = B.reserve<double>(m), oU = B.reserve<double>(m),
                  osid = B.reserve<int32_t>(n), osidl = B.reserve<int32_t>(n),
                  operm = B.reserve<int32_t>(n), ooff = B.reserve<int32_t>(m + 1),
@@ -468,12 +535,6 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                             hipMemcpyHostToDevice, s));
         X = staging.get();
     }
-    HIPX(hipMemcpyAsync(ix->A.get(), ix->A_h.data(), ix->A_h.size() * sizeof(float),
-                        hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(ix->At.get(), At_h.data(), At_h.size() * sizeof(float),
-                        hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(tau.get(), tau_h.data(), tau_h.size() * sizeof(float),
-                        hipMemcpyHostToDevice, s));
     HIPX(hipMemsetAsync(ctr.get(), 0, sizeof(BuildCounters), s));
 
     // Algorithm 1: rank by 2-norm, cut into m percentile ranges
@@ -484,6 +545,30 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     tm.begin("sort");
     HIPX(radix_sort(ka.get(), va.get(), kb.get(), vb.get(), n, 64, rtmp.get(), &in_b, s));
     tm.end();
+
+    // while the device ranks the items: the projection, the transpose of each
+    // block and the FP32 uncertainty band factors (first read by the hash)
+    make_projection(ix->seed, rows, d, ix->A_h);
+    std::vector<float> At_h(at_elems), tau_h(rows);
+    for (int r = 0; r < rows; ++r) {
+        double nrm2 = 0.0;
+        for (int c = 0; c <= d; ++c) {
+            const double a = ix->A_h[(size_t)r * (d + 1) + c];
+            nrm2 += a * a;
+            if (c < d) At_h[(size_t)c * rows + r] = (float)a;
+        }
+        // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
+        // rounded up so that the band is never narrower than the bound.
+        const double ku = (double)(d + 3) * 0x1p-24;
+        const double tau = 2.0 * (ku / (1.0 - ku)) * std::sqrt(nrm2) * (1.0 + 0x1p-20);
+        tau_h[r] = std::nextafter((float)tau, INFINITY);
+    }
+    HIPX(hipMemcpyAsync(ix->A.get(), ix->A_h.data(), ix->A_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->At.get(), At_h.data(), At_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(tau.get(), tau_h.data(), tau_h.size() * sizeof(float),
+                        hipMemcpyHostToDevice, s));
     uint64_t *sk = in_b ? kb.get() : ka.get();
     int32_t *sv = in_b ? vb.get() : va.get();
     uint64_t *lk = in_b ? ka.get() : kb.get();
@@ -512,37 +597,33 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(launch_assign_subsets(sk, sv, n, m, uniform ? bounds.get() : nullptr, ix->sid.get(), lk, lv,
                                ix->keymax.get(), subend.get(), s));
 
-    BuildCounters hc{};
-    ix->keymax_h.resize(m);
-    std::vector<int32_t> subend_h((size_t)m);
-    HIPX(hipMemcpyAsync(ix->keymax_h.data(), ix->keymax.get(), m * sizeof(double),
-                        hipMemcpyDeviceToHost, s));
-    HIPX(hipMemcpyAsync(subend_h.data(), subend.get(), m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
-    HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
-    HIPX(hipStreamSynchronize(s));
-    if (hc.nonfinite) throw Failure{NRLSH_E_NOT_FINITE, "items hold NaN or Inf"};
-
-    // U_j and the sorted (U_j, l) structure (host, FP64)
-    ix->U_h.resize(m);
-    for (int j = 0; j < m; ++j) ix->U_h[j] = std::sqrt(ix->keymax_h[j]);
-    std::vector<int32_t> inv_h;
-    make_rank_table(ix->U_h, L, ix->eps, ix->R_h, inv_h);
-    // sub-dataset j occupies sorted ranks [off_j, off_{j+1}); an empty one
-    // (no end rank written) starts and ends where the previous one ended
-    ix->off_h.assign(m + 1, 0);
-    std::vector<int32_t> off32(m + 1, 0);
-    for (int j = 0; j < m; ++j) {
-        ix->off_h[j + 1] = subend_h[j] >= 0 ? subend_h[j] : ix->off_h[j];
-        off32[j + 1] = (int32_t)ix->off_h[j + 1];
-    }
-    if (ix->off_h[m] != n) throw Failure{NRLSH_E_INTERNAL, "sub-dataset runs do not cover the items"};
-    HIPX(hipMemcpyAsync(ix->U.get(), ix->U_h.data(), m * sizeof(double), hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(ix->R.get(), ix->R_h.data(), ix->R_h.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(ix->inv.get(), inv_h.data(), inv_h.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice, s));
-    HIPX(hipMemcpyAsync(ix->off.get(), off32.data(), off32.size() * sizeof(int32_t),
-                        hipMemcpyHostToDevice, s));
+    // The host needs the counters, U_j and the sub-dataset ends for the rank
+    // table; they come back through pinned memory while the device already
+    // puts the items in stored order, which needs nothing from the host.
+    const size_t rank_n = (size_t)m * (L + 1);
+    const size_t p_hc = 0, p_km = 64, p_se = p_km + (size_t)m * 8, p_U = (p_se + (size_t)m * 4 + 15) / 16 * 16,
+                 p_R = p_U + (size_t)m * 8, p_inv = p_R + rank_n * 4, p_off = p_inv + rank_n * 4,
+                 p_end = p_off + ((size_t)m + 1) * 4;
+    static_assert(sizeof(BuildCounters) <= 64, "counters fit their slot");
+    size_t pin_bytes = 0;
+    uint8_t *pin = static_cast<uint8_t *>(pinned_take(p_end, &pin_bytes));
+    struct PinRelease {  // after every copy from or into it has been queued
+        void *p;
+        size_t b;
+        hipStream_t s;
+        int dev;
+        ~PinRelease() { pinned_give(p, b, s, dev); }
+    } pin_release{pin, pin_bytes, s, ix->device};
+    HIPX(hipMemcpyAsync(pin + p_hc, ctr.get(), sizeof(BuildCounters), hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(pin + p_km, ix->keymax.get(), m * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPX(hipMemcpyAsync(pin + p_se, subend.get(), m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    hipEvent_t ev_back = event_take(ix->device);
+    struct EvRelease {
+        hipEvent_t e;
+        int dev;
+        ~EvRelease() { event_give(e, dev); }
+    } ev_back_release{ev_back, ix->device};
+    HIPX(hipEventRecord(ev_back, s));
 
     // stored order: sub-dataset major, ascending original index inside
     int bits = 0;
@@ -561,6 +642,42 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                        ix->Xh.get(), nullptr, ix->key_l.get(), ix->sid_l.get(), s));
     tm.end();
     HIPX(hipMemsetAsync(ix->Xh.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
+    // the layout is the last reader of the caller's items
+    hipEvent_t ev_items = event_take(ix->device);
+    EvRelease ev_items_release{ev_items, ix->device};
+    HIPX(hipEventRecord(ev_items, s));
+
+    HIPX(hipEventSynchronize(ev_back));
+    BuildCounters hc;
+    std::memcpy(&hc, pin + p_hc, sizeof hc);
+    if (hc.nonfinite) throw Failure{NRLSH_E_NOT_FINITE, "items hold NaN or Inf"};
+    ix->keymax_h.resize(m);
+    std::vector<int32_t> subend_h((size_t)m);
+    std::memcpy(ix->keymax_h.data(), pin + p_km, m * sizeof(double));
+    std::memcpy(subend_h.data(), pin + p_se, m * sizeof(int32_t));
+
+    // U_j and the sorted (U_j, l) structure (host, FP64)
+    ix->U_h.resize(m);
+    for (int j = 0; j < m; ++j) ix->U_h[j] = std::sqrt(ix->keymax_h[j]);
+    std::vector<int32_t> inv_h;
+    make_rank_table(ix->U_h, L, ix->eps, ix->R_h, inv_h);
+    // sub-dataset j occupies sorted ranks [off_j, off_{j+1}); an empty one
+    // (no end rank written) starts and ends where the previous one ended
+    ix->off_h.assign(m + 1, 0);
+    std::vector<int32_t> off32(m + 1, 0);
+    for (int j = 0; j < m; ++j) {
+        ix->off_h[j + 1] = subend_h[j] >= 0 ? subend_h[j] : ix->off_h[j];
+        off32[j + 1] = (int32_t)ix->off_h[j + 1];
+    }
+    if (ix->off_h[m] != n) throw Failure{NRLSH_E_INTERNAL, "sub-dataset runs do not cover the items"};
+    std::memcpy(pin + p_U, ix->U_h.data(), m * sizeof(double));
+    std::memcpy(pin + p_R, ix->R_h.data(), rank_n * sizeof(int32_t));
+    std::memcpy(pin + p_inv, inv_h.data(), rank_n * sizeof(int32_t));
+    std::memcpy(pin + p_off, off32.data(), off32.size() * sizeof(int32_t));
+    HIPX(hipMemcpyAsync(ix->U.get(), pin + p_U, m * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->R.get(), pin + p_R, rank_n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->inv.get(), pin + p_inv, rank_n * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->off.get(), pin + p_off, off32.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
     // SimpleLSH transform + sign random projection, then the FP64 fix-up
     std::vector<int32_t> bstart_h((size_t)m + 1, 0);  // outlives its copy
@@ -629,19 +746,51 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         HIPX(hipMemcpyAsync(ix->ustart.get() + U, &nn, sizeof nn, hipMemcpyHostToDevice, s));
     }
 
-    HIPX(hipMemcpyAsync(&hc, ctr.get(), sizeof hc, hipMemcpyDeviceToHost, s));
-    HIPX(hipStreamSynchronize(s));
+    // the final counters arrive behind the last kernel; `ready` marks the
+    // end of the build's device work, which later calls wait for (queries on
+    // their stream, everything else on the host)
+    ix->counters_h = pinned_take(sizeof(BuildCounters), &ix->counters_bytes);
+    HIPX(hipMemcpyAsync(ix->counters_h, ctr.get(), sizeof(BuildCounters), hipMemcpyDeviceToHost, s));
+    ix->ready = event_take(ix->device);
+    HIPX(hipEventRecord(ix->ready, s));
     // long-lived buffers are released on the library stream by nrlsh_free
     ix->mem.mem.s = ix->home;
     ix->Xf8.s = ix->home;
     ix->xscale.s = ix->home;
-    ix->stats.lowp_items = hc.lowp_items;
-    ix->stats.lowp_bits = (int64_t)hc.lowp_bits;
-    ix->stats.lowp_changed = (int64_t)hc.lowp_changed;
-    ix->stats.recomputed_items = hc.fix_count;
-    ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
-    ix->stats.recompute_flips = (int64_t)hc.fix_flips;
+    // the caller may reuse its items once this returns
+    HIPX(hipEventSynchronize(ev_items));
 }
+
+}  // namespace
+
+// The build returns with its last kernels still queued.  Queries wait for
+// them on their own stream; every other use of the index waits on the host,
+// which also takes the build counters in.
+void index_wait(const nrlsh_index *ix, hipStream_t s)
+{
+    if (ix->ready && !ix->settled.load(std::memory_order_acquire)) HIPX(hipStreamWaitEvent(s, ix->ready, 0));
+}
+
+void index_settle(const nrlsh_index *ix)
+{
+    if (ix->settled.load(std::memory_order_acquire)) return;
+    std::lock_guard<std::mutex> g(ix->ready_mu);
+    if (ix->settled.load(std::memory_order_relaxed)) return;
+    if (ix->ready) HIPX(hipEventSynchronize(ix->ready));
+    if (ix->counters_h) {
+        BuildCounters hc;
+        std::memcpy(&hc, ix->counters_h, sizeof hc);
+        ix->stats.lowp_items = hc.lowp_items;
+        ix->stats.lowp_bits = (int64_t)hc.lowp_bits;
+        ix->stats.lowp_changed = (int64_t)hc.lowp_changed;
+        ix->stats.recomputed_items = hc.fix_count;
+        ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
+        ix->stats.recompute_flips = (int64_t)hc.fix_flips;
+    }
+    ix->settled.store(true, std::memory_order_release);
+}
+
+namespace {
 
 nrlsh_status validate_build(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
                             double eps, nrlsh_index **out)
@@ -1176,8 +1325,10 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
             build_index(ix, items, on_device, s, tm);
             tm.settle();
         } catch (...) {
-            delete ix;
             (void)hipStreamSynchronize(s);
+            pinned_give(ix->counters_h, ix->counters_bytes, nullptr, dev);
+            event_give(ix->ready, dev);
+            delete ix;
             throw;
         }
         *out = ix;
@@ -1195,6 +1346,12 @@ void nrlsh_free(nrlsh_index *ix)
 {
     if (!ix) return;
     hipStream_t s = ix->home;
+    // the build's device work ends before its buffers go back
+    if (ix->ready) (void)hipEventSynchronize(ix->ready);
+    pinned_give(ix->counters_h, ix->counters_bytes, nullptr, ix->device);
+    event_give(ix->ready, ix->device);
+    ix->counters_h = nullptr;
+    ix->ready = nullptr;
     delete ix;  // buffers are released on their home stream
     (void)hipStreamSynchronize(s);
 }
@@ -1227,6 +1384,7 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
         hipStream_t s = pick_stream(opts ? opts->stream : nullptr, ix->device);
+        index_wait(ix, s);
         Timer tm(s);
         Block blk;
         const size_t o_fl = blk.reserve<uint32_t>(1),
@@ -1297,6 +1455,7 @@ nrlsh_status nrlsh_get_bucket_table(const nrlsh_index *ix, int64_t *nunique, uin
     if (!ustart || !uoff || !titem) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         const int64_t U = ix->nunique;
         std::vector<int32_t> us((size_t)U + 1);
         HIPX(hipMemcpy(ucode, ix->ucode.get(), (size_t)U * sizeof(uint64_t), hipMemcpyDeviceToHost));
@@ -1327,6 +1486,7 @@ nrlsh_status nrlsh_get_keys(const nrlsh_index *ix, double *key)
     if (!ix || !key) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         HIPX(hipMemcpy(key, ix->key.get(), (size_t)ix->n * sizeof(double), hipMemcpyDeviceToHost));
         return NRLSH_OK;
     });
@@ -1337,6 +1497,7 @@ nrlsh_status nrlsh_get_partition(const nrlsh_index *ix, int32_t *sid, double *ke
     if (!ix || !sid || !keymax || !U) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         HIPX(hipMemcpy(sid, ix->sid.get(), (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToHost));
         std::memcpy(keymax, ix->keymax_h.data(), ix->m * sizeof(double));
         std::memcpy(U, ix->U_h.data(), ix->m * sizeof(double));
@@ -1349,6 +1510,7 @@ nrlsh_status nrlsh_get_layout(const nrlsh_index *ix, int32_t *perm, int64_t *off
     if (!ix || !perm || !off) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         HIPX(hipMemcpy(perm, ix->perm.get(), (size_t)ix->n * sizeof(int32_t), hipMemcpyDeviceToHost));
         std::memcpy(off, ix->off_h.data(), (ix->m + 1) * sizeof(int64_t));
         return NRLSH_OK;
@@ -1360,6 +1522,7 @@ nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes)
     if (!ix || !codes) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         std::vector<uint32_t> w((size_t)ix->n * ix->W);
         std::vector<int32_t> perm(ix->n);
         HIPX(hipMemcpy(w.data(), ix->codes_l.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
@@ -1378,6 +1541,7 @@ nrlsh_status nrlsh_get_hash_copy(const nrlsh_index *ix, void *data, float *scale
     if (!ix || !data || !storage) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         const size_t cnt = (size_t)ix->n * ix->dp;
         *storage = ix->storage;
         if (ix->storage == NRLSH_STORAGE_FP32) {
@@ -1403,8 +1567,12 @@ nrlsh_status nrlsh_get_rank_table(const nrlsh_index *ix, int32_t *R)
 nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st)
 {
     if (!ix || !st) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
-    *st = ix->stats;
-    return NRLSH_OK;
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
+        *st = ix->stats;
+        return NRLSH_OK;
+    });
 }
 
 nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int64_t nq,
@@ -1416,6 +1584,7 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
     if (!all_finite(queries, nq * (int64_t)ix->d)) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         hipStream_t s = library_stream(ix->device);
         DBuf<float> Qd((size_t)nq * ix->d, s);
         const int64_t rows = nq * ix->qsets;
@@ -1446,6 +1615,7 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
     if (!all_finite(queries, nq * (int64_t)ix->d)) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
         hipStream_t s = library_stream(ix->device);
         const int64_t Tq = std::min<int64_t>(probe_budget, ix->n);
         Timer tm(s);

@@ -84,6 +84,7 @@ class Timer {
     void settle()
     {
         if (!on_) return;
+        if (!pending_.empty()) HIPX(hipEventSynchronize(pending_.back().b));
         for (auto &p : pending_) {
             float ms = 0.f;
             HIPX(hipEventElapsedTime(&ms, p.a, p.b));
@@ -113,6 +114,14 @@ int current_device();
 // any stream once the work queued before its release has finished.
 void *cached_alloc(size_t bytes, hipStream_t s, int *dev);
 void cached_free(void *p, size_t bytes, hipStream_t s, int dev);
+// Pinned host staging for small copies: a block is handed out again once an
+// event recorded on the stream of its release has completed (or at once when
+// released with no stream).  Blocks are kept until the process ends.
+void *pinned_take(size_t bytes, size_t *got);
+void pinned_give(void *p, size_t bytes, hipStream_t s, int dev);
+// An idle event of device dev (timing disabled), and its return.
+hipEvent_t event_take(int dev);
+void event_give(hipEvent_t ev, int dev);
 
 // Stream-ordered device buffer; freed on the stream it was allocated on.  A
 // view (DBuf::view) points into memory owned elsewhere and frees nothing.
@@ -203,7 +212,15 @@ struct nrlsh_index {
     std::vector<double> keymax_h, U_h;
     std::vector<int64_t> off_h;
     std::vector<int32_t> R_h;
-    nrlsh_build_stats stats{};
+    // the build's last device work (queued, not waited for, when nrlsh_build
+    // returns): later calls wait for `ready` on their stream or on the host;
+    // the build counters arrive in pinned host memory behind it
+    mutable hipEvent_t ready = nullptr;
+    mutable std::mutex ready_mu;
+    mutable std::atomic<bool> settled{false};
+    void *counters_h = nullptr;  // pinned BuildCounters
+    size_t counters_bytes = 0;
+    mutable nrlsh_build_stats stats{};
     hipStream_t home = nullptr;  // library stream that releases the device buffers
     nrlsh::host::Block mem;      // the long-lived buffers below are views into it
     nrlsh::host::DBuf<float> Xl, A, At;               // Xl: stored-order padded item copy
@@ -228,3 +245,10 @@ struct nrlsh_index {
     nrlsh::host::DBuf<uint64_t> ucode, binom;
     nrlsh::host::DBuf<int32_t> ustart, uoff, titem;
 };
+
+// The build returns with its last kernels still queued: index_wait makes
+// stream s wait for them, index_settle waits on the host (and takes the
+// build counters in).
+void index_wait(const nrlsh_index *ix, hipStream_t s);
+void index_settle(const nrlsh_index *ix);
+

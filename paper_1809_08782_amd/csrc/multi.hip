@@ -556,6 +556,7 @@ nrlsh_status nrlsh_multi_plan_create(const nrlsh_query_desc *descs, int32_t coun
     if (st != NRLSH_OK) return st;
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(descs[0].index->device));
+        for (int32_t i = 0; i < count; ++i) index_settle(descs[i].index);
         int32_t tuned = 0;
         double tune_ms = 0.0;
         const std::vector<TileShape> tiles = choose_tiles(descs, count, k, po, &tuned, &tune_ms);
@@ -574,7 +575,10 @@ nrlsh_status nrlsh_multi_run(nrlsh_multi_plan *plan, const nrlsh_query_desc *des
     if (st != NRLSH_OK) return st;
     if (!same_shape(plan, descs, count))
         return fail(NRLSH_E_INVALID_ARG, "descs do not match the plan's shape (index, nq, probe budget)");
-    return guarded([&]() -> nrlsh_status { return run_plan(plan, descs, nullptr); });
+    return guarded([&]() -> nrlsh_status {
+        for (int32_t i = 0; i < count; ++i) index_settle(descs[i].index);
+        return run_plan(plan, descs, nullptr);
+    });
 }
 
 void nrlsh_multi_plan_free(nrlsh_multi_plan *plan)

@@ -237,6 +237,39 @@ def test_device_pointer_path_matches_host_path():
         assert np.array_equal(ipd.cpu().numpy(), ph)
 
 
+def test_build_returns_before_its_last_kernels():
+    """nrlsh_build returns once the caller's items are read: the items may be
+    overwritten at once on another stream, and a query on a third stream, the
+    build counters and the inspection calls all see the finished index."""
+    import torch
+    say("case asynchronous build end")
+    X = make_items("lognormal", 20000, 96, seed=43, sigma=0.8)
+    Q = make_queries(300, 96, seed=44)
+    with nr.nrlsh_build(X, 16, 32, 17) as h:
+        ih, ph = nr.nrlsh_query(h, Q, 10, 2000)
+        hc = h.codes()
+        hst = h.build_stats()
+    Xd = torch.from_numpy(X).cuda()
+    Qd = torch.from_numpy(Q).cuda()
+    sa, sb, sc = torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.Stream()
+    torch.cuda.synchronize()
+    for rep in range(2):
+        Xc = Xd.clone()
+        torch.cuda.synchronize()
+        g = nr.nrlsh_build(Xc, 16, 32, 17, stream=sa.cuda_stream)
+        with torch.cuda.stream(sb):
+            Xc.fill_(float("nan"))  # the caller reuses its items right away
+        with torch.cuda.stream(sc):
+            idd, ipd = nr.nrlsh_query(g, Qd, 10, 2000, stream=sc.cuda_stream)
+        sc.synchronize()
+        assert np.array_equal(idd.cpu().numpy(), ih), f"rep {rep}"
+        assert np.array_equal(ipd.cpu().numpy(), ph), f"rep {rep}"
+        assert g.build_stats() == hst
+        assert np.array_equal(g.codes(), hc)
+        g.close()
+    torch.cuda.synchronize()
+
+
 UNIFORM_CASES = [
     # (n, d, m, L, kind, T)
     (6000, 40, 16, 32, "lognormal", 600),
