@@ -1060,9 +1060,10 @@ std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo, int
     return ch;
 }
 
-void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
-                      int kind, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
-                      uint32_t *nonfinite_d)
+// Returns the non-finite flag as read with the last batch's record.
+uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
+                          int kind, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                          uint32_t *nonfinite_d)
 {
     const uint16_t *Xh = kind != SCREEN_FP32 ? ix->Xh.get() : nullptr;
     const uint16_t *Xlo = kind == SCREEN_BF16X3 ? lo_rows(ix, s) : nullptr;
@@ -1102,13 +1103,25 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_qn = blk.reserve<float>(kind != SCREEN_FP32 ? (size_t)B : 1),
                  o_ta = blk.reserve<float>((size_t)B), o_co = blk.reserve<int32_t>((size_t)B),
                  o_li = blk.reserve<int32_t>((size_t)B * cap),
-                 o_np = blk.reserve<unsigned long long>(1),
+                 o_np = blk.reserve<unsigned long long>(1), o_rec = blk.reserve<long long>(5),
                  o_oka = blk.reserve<uint64_t>((size_t)B), o_okb = blk.reserve<uint64_t>((size_t)B),
                  o_ova = blk.reserve<int32_t>((size_t)B), o_ovb = blk.reserve<int32_t>((size_t)B),
                  o_otmp = blk.reserve<uint8_t>(radix_sort_tmp_bytes(B));
     blk.allocate(s);
     DBuf<int32_t> cells = blk.view<int32_t>(o_ce), chunks = blk.view<int32_t>(o_ch);
     DBuf<unsigned long long> npairs = blk.view<unsigned long long>(o_np);
+    DBuf<long long> rec = blk.view<long long>(o_rec);
+    // the per-batch record comes back through pinned memory
+    size_t rec_bytes = 0;
+    long long *rec_h = static_cast<long long *>(pinned_take(5 * sizeof(long long), &rec_bytes));
+    struct RecRelease {
+        void *p;
+        size_t b;
+        hipStream_t s;
+        int dev;
+        ~RecRelease() { pinned_give(p, b, s, dev); }
+    } rec_release{rec_h, rec_bytes, s, ix->device};
+    uint32_t bad = 0;
     DBuf<uint64_t> oka = blk.view<uint64_t>(o_oka), okb = blk.view<uint64_t>(o_okb);
     DBuf<int32_t> ova = blk.view<int32_t>(o_ova), ovb = blk.view<int32_t>(o_ovb);
     DBuf<uint8_t> otmp = blk.view<uint8_t>(o_otmp);
@@ -1123,7 +1136,6 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<uint16_t> qh = blk.view<uint16_t>(o_qh), ql = blk.view<uint16_t>(o_ql);
     DBuf<float> qn = blk.view<float>(o_qn), theta = blk.view<float>(o_ta);
     DBuf<int32_t> counts = blk.view<int32_t>(o_co), lists = blk.view<int32_t>(o_li);
-    std::vector<int32_t> hcounts((size_t)B);
     for (int64_t b0 = 0; b0 < nq; b0 += B) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
@@ -1175,7 +1187,6 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         // screen, then the exact re-rank of the kept lists right behind it; the
         // host checks afterwards whether a list overflowed (then the batch is
         // screened again with longer lists, which overwrites the results)
-        std::vector<float> th((size_t)nb);
         for (bool first = true;; first = false) {
             HIPX(hipMemsetAsync(counts.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("screen");
@@ -1196,19 +1207,14 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(), counts.get(),
                                nsplit, pv.get(), pi.get(), ids_d + b0 * k, ips_d + b0 * k, s));
             tm.end();
-            if (first)
-                HIPX(hipMemcpyAsync(th.data(), theta.get(), (size_t)nb * sizeof(float),
-                                    hipMemcpyDeviceToHost, s));
-            HIPX(hipMemcpyAsync(hcounts.data(), counts.get(), (size_t)nb * sizeof(int32_t),
-                                hipMemcpyDeviceToHost, s));
+            HIPX(launch_list_stats(counts.get(), first ? theta.get() : nullptr, nb, npairs.get(), nonfinite_d,
+                                   rec.get(), s));
+            HIPX(hipMemcpyAsync(rec_h, rec.get(), 5 * sizeof(long long), hipMemcpyDeviceToHost, s));
             HIPX(hipStreamSynchronize(s));
-            if (first)
-                for (float t : th) g_qstats.theta_unset += std::isinf(t) && t < 0 ? 1 : 0;
-            int64_t mx = 0, tot = 0;
-            for (int64_t i = 0; i < nb; ++i) {
-                mx = std::max<int64_t>(mx, hcounts[i]);
-                tot += hcounts[i];
-            }
+            const int64_t mx = rec_h[0], tot = rec_h[1];
+            if (first) g_qstats.theta_unset += rec_h[2];
+            g_qstats.screen_pairs = rec_h[3];
+            bad = rec_h[4] != 0;
             g_qstats.screen_passes += 1;
             if (mx <= cap) {
                 g_qstats.kept_total += tot;
@@ -1220,15 +1226,15 @@ void run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             lists = DBuf<int32_t>((size_t)B * cap, s);
         }
     }
-    unsigned long long np = 0;
-    HIPX(hipMemcpyAsync(&np, npairs.get(), sizeof np, hipMemcpyDeviceToHost, s));
-    HIPX(hipStreamSynchronize(s));
-    g_qstats.screen_pairs = (int64_t)np;
+    return bad;
 }
 
-void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
-               bool bf16_rows, bool table, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
-               uint32_t *nonfinite_d)
+// Returns the non-finite flag when the path has already read it back after
+// its last device work (the screen), else kFlagUnread.
+constexpr uint32_t kFlagUnread = 0xFFFFFFFFu;
+uint32_t run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
+                   bool bf16_rows, bool table, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                   uint32_t *nonfinite_d)
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
     g_qstats.probe_mode = table ? NRLSH_PROBE_TABLE : NRLSH_PROBE_SCAN;
@@ -1243,11 +1249,9 @@ void run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, in
                     : kind == SCREEN_FP32   ? NRLSH_RERANK_SCREEN_FP32
                     : kind == SCREEN_BF16X3 ? NRLSH_RERANK_SCREEN_BF16X3
                                             : NRLSH_RERANK_SCREEN;
-    if (screen)
-        run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d);
-    else
-        run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d,
-                         bf16_rows, table);
+    if (screen) return run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d);
+    run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d, bf16_rows, table);
+    return kFlagUnread;
 }
 
 }  // namespace
@@ -1400,25 +1404,28 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         bool bf16_rows = false;
         if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)))
             bf16_rows = opts->rerank_storage == NRLSH_STORAGE_BF16;
+        uint32_t bad = kFlagUnread;
         if (on_device) {
-            run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, table, out_ids, out_ips, s, tm,
-                      flag.get());
+            bad = run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, table, out_ids, out_ips, s, tm,
+                            flag.get());
         } else {
             DBuf<float> Qd = blk.view<float>(o_q);
             DBuf<int64_t> ids = blk.view<int64_t>(o_i);
             DBuf<float> ips = blk.view<float>(o_p);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
-            run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, table, ids.get(), ips.get(), s,
-                      tm, flag.get());
+            (void)run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, table, ids.get(), ips.get(), s,
+                            tm, flag.get());
             HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),
                                 hipMemcpyDeviceToHost, s));
         }
-        uint32_t bad = 0;
-        HIPX(hipMemcpyAsync(&bad, flag.get(), sizeof bad, hipMemcpyDeviceToHost, s));
-        HIPX(hipStreamSynchronize(s));
+        if (bad == kFlagUnread) {  // (host outputs: the copies above are waited for here)
+            bad = 0;
+            HIPX(hipMemcpyAsync(&bad, flag.get(), sizeof bad, hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+        }
         tm.settle();
         if (bad) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
         return NRLSH_OK;

@@ -1333,6 +1333,51 @@ __global__ __launch_bounds__(64) void k_theta_small(const float *__restrict__ cm
     }
 }
 
+// One record per screened batch for the host: the largest and the total
+// kept-list length, the queries left without theta (theta != NULL), and the
+// call's evaluated-pair count and non-finite flag as they stand.  One block.
+__global__ __launch_bounds__(1024) void k_list_stats(const int32_t *__restrict__ counts,
+                                                     const float *__restrict__ theta, int64_t nb,
+                                                     const unsigned long long *__restrict__ npairs,
+                                                     const uint32_t *__restrict__ flag,
+                                                     long long *__restrict__ rec)
+{
+    __shared__ long long s_mx[16], s_sum[16], s_un[16];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    long long mx = 0, sum = 0, un = 0;
+    for (int64_t i = tid; i < nb; i += 1024) {
+        const long long c = counts[i];
+        mx = c > mx ? c : mx;
+        sum += c;
+        if (theta && theta[i] == -INFINITY) ++un;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const long long m2 = __shfl_xor(mx, o, 64);
+        mx = m2 > mx ? m2 : mx;
+        sum += __shfl_xor(sum, o, 64);
+        un += __shfl_xor(un, o, 64);
+    }
+    if (lane == 0) {
+        s_mx[wave] = mx;
+        s_sum[wave] = sum;
+        s_un[wave] = un;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 16; ++w) {
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+            sum += s_sum[w];
+            un += s_un[w];
+        }
+        rec[0] = mx;
+        rec[1] = sum;
+        rec[2] = un;
+        rec[3] = npairs ? (long long)*npairs : 0;
+        rec[4] = flag ? (long long)*flag : 0;
+    }
+}
+
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
@@ -1456,6 +1501,14 @@ hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t
 {
     hipLaunchKernelGGL(k_query_bf16, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, nq, d, dp, Qh, Ql, qn,
                        nonfinite);
+    return hipGetLastError();
+}
+
+hipError_t launch_list_stats(const int32_t *counts, const float *theta, int64_t nb,
+                             const unsigned long long *npairs, const uint32_t *flag, long long *rec,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_list_stats, dim3(1), dim3(1024), 0, s, counts, theta, nb, npairs, flag, rec);
     return hipGetLastError();
 }
 

@@ -216,6 +216,11 @@ struct ScreenQueries {
 // Permutation of a batch's queries by theta_q / ||q|| descending (queries
 // without a theta last), through a radix sort in the given buffers (nq each;
 // tmp: radix_sort_tmp_bytes(nq)); *order points into va or vb.
+// rec[0..4] = largest and total counts[0..nb), queries with theta = -inf
+// (theta != NULL), *npairs and *flag (0 where NULL); one block
+hipError_t launch_list_stats(const int32_t *counts, const float *theta, int64_t nb,
+                             const unsigned long long *npairs, const uint32_t *flag, long long *rec,
+                             hipStream_t s);
 hipError_t launch_query_order(const float *theta, const float *qn, int64_t nq, uint64_t *ka, int32_t *va,
                               uint64_t *kb, int32_t *vb, void *tmp, int32_t **order, hipStream_t s);
 hipError_t launch_query_bf16(const float *Q, int64_t nq, int d, int dp, uint16_t *Qh, uint16_t *Ql,
