@@ -991,14 +991,17 @@ __global__ __launch_bounds__(256) void k_probe_all(int64_t nq, int64_t tiles, in
     Xh, Xlo, dp, codes_l, key_l, Qh, Ql, qnorm, nq, chunks, m, qcodes, ghthr, gtie, gpstar, theta, \
         gam, cap, counts, lists, cmax, ncol, qsb, L, qsets, Usub, npairs, qidx
 
+// W = 0: every level of every sub-dataset is probed (a budget covering all
+// items), so no code is read and no probe test is made.
 template <int W, bool MAXMODE, bool X3>
 __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
 {
+    constexpr int WC = W > 0 ? W : 1;  // code words kept per item (storage)
     extern __shared__ __align__(16) uint16_t qsh[];  // hi: 64 x qsb, then (X3) lo: 64 x qsb
     uint16_t *qsl = qsh + 64 * qsb;
     __shared__ float th_s[64], qn_s[64];
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
-    __shared__ uint32_t qc_s[64 * W];
+    __shared__ uint32_t qc_s[64 * WC];
     __shared__ int any_s, all_s;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
@@ -1031,7 +1034,10 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
         hthr_s[tid] = hthr;
         htie_s[tid] = htie;
         pstar_s[tid] = pstar;
-        th_s[tid] = th;
+        // rows past the batch keep nothing (pass B): theta +inf makes every
+        // pair fall below it, whether or not a probe test runs (W = 0 and
+        // all-probed tiles skip it)
+        th_s[tid] = (!MAXMODE && q >= nq) ? INFINITY : th;
         qn_s[tid] = qn;
         // no item of sub-dataset j (norms <= U_j) can be kept (pass B), or raise
         // a group maximum to theta (pass A), for a query whose theta exceeds
@@ -1093,7 +1099,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     // hi and lo operands double the registers)
     constexpr int NB = X3 ? 2 : 4, IW = 16 * NB;
     const int r16 = lane & 15, g = lane >> 4;
-    const bool all = all_s != 0;
+    const bool all = W == 0 || all_s != 0;
     // stored rows of this chunk through buffer descriptors: 32-bit offsets
     // from the chunk's first row, and reads past the chunk's rows return 0
     // (finite values that meet the zero columns of the query tile, or rows
@@ -1105,7 +1111,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
         __builtin_amdgcn_make_buffer_rsrc((void *)(X3 ? Xlo + (int64_t)pbeg * dp : Xh), 0, X3 ? (int)rbytes : 0,
                                           0x00020000);
     for (int p0 = pbeg + wave * IW; p0 < pend; p0 += 4 * IW) {
-        uint32_t cw[NB][W];
+        uint32_t cw[NB][WC];
         float xn[NB];
         uint32_t ro[NB];  // byte offset of this lane's 8 coordinates of row 16 ib + r16
 #pragma unroll
@@ -1227,6 +1233,13 @@ template <int W, bool MAXMODE, bool X3>
 __global__ __launch_bounds__(256) void k_screen3(NRLSH_SCREEN_PARAMS)
 {
     screen_bf16<W, MAXMODE, X3>(NRLSH_SCREEN_ARGS);
+}
+
+// Pass A of the single-product screen when every item is probed: no codes,
+// so a register budget for three waves per SIMD fits without spilling much.
+__global__ __launch_bounds__(256, 3) void k_screen_a0(NRLSH_SCREEN_PARAMS)
+{
+    screen_bf16<0, true, false>(NRLSH_SCREEN_ARGS);
 }
 
 // Pass B of the single-product screen, the one that runs over every probed
@@ -1543,11 +1556,18 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
 {
     const size_t lds = screen_lds_bytes(sh.dp, X3 ? SCREEN_BF16X3 : SCREEN_BF16);
     const bool one = !MAXMODE && !X3;
-    const void *fn = one ? (const void *)k_screen1<W> : (const void *)k_screen3<W, MAXMODE, X3>;
+    const bool a0 = W == 0 && MAXMODE && !X3;
+    const void *fn = one  ? (const void *)k_screen1<W>
+                     : a0 ? (const void *)k_screen_a0
+                          : (const void *)k_screen3<W, MAXMODE, X3>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
-    if (one)
+    if (a0)
+        hipLaunchKernelGGL(k_screen_a0, grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l, Q.Qh, Q.Ql,
+                           Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam, cap, counts,
+                           lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets, Q.U, nullptr, nullptr);
+    else if (one)
         hipLaunchKernelGGL((k_screen1<W>), grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l,
                            Q.Qh, Q.Ql, Q.qn, nq, chunks, sh.m, qcodes, ghthr, gtie, gpstar, theta, gam,
                            cap, counts, lists, cmax, ncol, screen_qsb(sh.dp), sh.L, sh.qsets,
@@ -1576,7 +1596,11 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
         // accumulation of 3d exact products: 2 * 1.02 * gamma_{3d}
         const double u3 = 3.0 * sh.d * 0x1p-24;
         const float gam = (float)((3.2 * 0x1p-16 + 2.1 * u3 / (1.0 - u3)) * (1.0 + 0x1p-16));
-        return sh.W == 1
+        return sh.Tq >= sh.n
+                   ? launch_screen_bf16<0, MAXMODE, true>(Xh, Xlo, key_l, codes_l, Q, nq, sh, chunks,
+                                                          nchunks, qcodes, ghthr, gtie, gpstar, theta,
+                                                          gam, cap, counts, lists, cmax, ncol, s)
+               : sh.W == 1
                    ? launch_screen_bf16<1, MAXMODE, true>(Xh, Xlo, key_l, codes_l, Q, nq, sh, chunks,
                                                           nchunks, qcodes, ghthr, gtie, gpstar, theta,
                                                           gam, cap, counts, lists, cmax, ncol, s)
@@ -1589,7 +1613,13 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
         // coordinate, plus FP32 accumulation of d exact products: 2 * 1.01 * gamma_d
         const double ud = sh.d * 0x1p-24;
         const float gam = (float)((0x1p-8 + 0x1p-17 + 2.1 * ud / (1.0 - ud)) * (1.0 + 0x1p-16));
-        return sh.W == 1
+        // a budget covering every item probes every level: the variant that
+        // reads no codes
+        return sh.Tq >= sh.n
+                   ? launch_screen_bf16<0, MAXMODE, false>(Xh, nullptr, key_l, codes_l, Q, nq, sh,
+                                                           chunks, nchunks, qcodes, ghthr, gtie, gpstar,
+                                                           theta, gam, cap, counts, lists, cmax, ncol, s)
+               : sh.W == 1
                    ? launch_screen_bf16<1, MAXMODE, false>(Xh, nullptr, key_l, codes_l, Q, nq, sh,
                                                            chunks, nchunks, qcodes, ghthr, gtie, gpstar,
                                                            theta, gam, cap, counts, lists, cmax, ncol, s)
