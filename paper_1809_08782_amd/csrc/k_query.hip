@@ -1242,6 +1242,134 @@ __global__ __launch_bounds__(256, 3) void k_screen_a0(NRLSH_SCREEN_PARAMS)
     screen_bf16<0, true, false>(NRLSH_SCREEN_ARGS);
 }
 
+// Pass B of the single-product screen when every item is probed, on tiles of
+// 128 queries: eight waves share the tile's bfloat16 image in LDS and each
+// multiplies it with its own 64 items per iteration, so every item row read
+// from memory serves 128 queries (the 64-query kernel reads it for 64).  The
+// keep rule, the norm-bound skip of a chunk and the query order are those of
+// screen_bf16; rows past the batch get theta = +inf and keep nothing.
+__global__ __launch_bounds__(512) void k_screen_b128(
+    const uint16_t *__restrict__ Xh, int dp, const double *__restrict__ key_l,
+    const uint16_t *__restrict__ Qh, const float *__restrict__ qnorm, int64_t nq,
+    const int32_t *__restrict__ chunks, const float *__restrict__ theta, float gam, int cap,
+    int32_t *__restrict__ counts, int32_t *__restrict__ lists, int qsb,
+    const double *__restrict__ Usub, unsigned long long *__restrict__ npairs,
+    const int32_t *__restrict__ qidx)
+{
+    extern __shared__ __align__(16) uint16_t qsh[];  // 128 x qsb
+    __shared__ float th_s[128], qn_s[128];
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1], pend = chunks[3 * blockIdx.y + 2];
+    const int64_t q0 = (int64_t)blockIdx.x * 128;
+    auto qmap = [&](int64_t r) -> int64_t { return (qidx && r < nq) ? (int64_t)qidx[r] : r; };
+    bool reach = false;
+    if (tid < 128) {
+        const int64_t q = qmap(q0 + tid);
+        float th = INFINITY, qn = 0.f;
+        if (q < nq) {
+            th = theta[q];
+            qn = qnorm[q];
+            reach = !Usub ||
+                    !((double)th > (double)qn * Usub[j] * (1.0 + 2.0 * (double)gam + 0x1p-15) + 0x1p-80);
+        }
+        th_s[tid] = th;
+        qn_s[tid] = qn;
+    }
+    if (!__syncthreads_or(reach)) return;  // no query of the tile can keep an item of the chunk
+    if (npairs && tid == 0)
+        atomicAdd(npairs, (unsigned long long)(min((int64_t)128, nq - q0) * (int64_t)(pend - pbeg)));
+
+    // stage the query tile: four threads per row, 8 columns each per round
+    const u16x8 z8 = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+    {
+        constexpr int SQ_U = 8;
+        const int r = tid >> 2, cq = 8 * (tid & 3);
+        const bool rok = q0 + r < nq;
+        const int64_t qr = rok ? qmap(q0 + r) : 0;
+        const int nu = (dp + 31) / 32;
+        for (int u0 = 0; u0 < nu; u0 += SQ_U) {
+            u16x8 th8[SQ_U];
+#pragma unroll
+            for (int u = 0; u < SQ_U; ++u) {
+                const int c = 32 * (u0 + u) + cq;
+                th8[u] = (rok && u0 + u < nu && c < dp) ? *reinterpret_cast<const u16x8 *>(Qh + qr * dp + c) : z8;
+            }
+#pragma unroll
+            for (int u = 0; u < SQ_U; ++u) {
+                if (u0 + u >= nu) break;
+                *reinterpret_cast<u16x8 *>(&qsh[r * qsb + 32 * (u0 + u) + cq]) = th8[u];
+            }
+        }
+    }
+    __syncthreads();
+
+    const int r16 = lane & 15, g = lane >> 4;
+    const uint32_t rbytes = (uint32_t)(pend - pbeg) * (uint32_t)dp * 2u;
+    const __amdgpu_buffer_rsrc_t bx =
+        __builtin_amdgcn_make_buffer_rsrc((void *)(Xh + (int64_t)pbeg * dp), 0, (int)rbytes, 0x00020000);
+    for (int p0 = pbeg + wave * 64; p0 < pend; p0 += 8 * 64) {
+        float xn[4];
+        uint32_t ro[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) {
+            const int pi = p0 + 16 * ib + r16;
+            const int64_t pp = pi < pend ? pi : pbeg;
+            xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
+            ro[ib] = (uint32_t)(pi - pbeg) * (uint32_t)dp * 2u + 16u * g;
+        }
+        floatx4 acc[8][4];
+#pragma unroll
+        for (int qb = 0; qb < 8; ++qb)
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) acc[qb][ib] = floatx4{0.f, 0.f, 0.f, 0.f};
+        u16x8 bh[4];
+#pragma unroll
+        for (int ib = 0; ib < 4; ++ib) bh[ib] = buf_load16(bx, ro[ib], 0);
+        for (int kk = 0; kk < dp; kk += 32) {
+            u16x8 ch[4];
+#pragma unroll
+            for (int ib = 0; ib < 4; ++ib) ch[ib] = bh[ib];
+            if (kk + 32 < dp) {
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) bh[ib] = buf_load16(bx, ro[ib], 2 * (kk + 32));
+            }
+            const int kc = kk + 8 * g;
+#pragma unroll
+            for (int qb = 0; qb < 8; ++qb) {
+                const u16x8 ah = *reinterpret_cast<const u16x8 *>(&qsh[(16 * qb + r16) * qsb + kc]);
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib)
+                    acc[qb][ib] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(ch[ib]),
+                                                                          acc[qb][ib], 0, 0, 0);
+            }
+        }
+        float xmax = fmaxf(fmaxf(xn[0], xn[1]), fmaxf(xn[2], xn[3]));
+#pragma unroll
+        for (int qb = 0; qb < 8; ++qb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int ql = 16 * qb + 4 * g + v;
+                const float th = th_s[ql], qn = qn_s[ql];
+                const float emax = gam * qn * xmax + 0x1p-90f;
+                bool near = false;
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) near |= !(acc[qb][ib][v] + emax < th);
+                if (!near) continue;
+#pragma unroll
+                for (int ib = 0; ib < 4; ++ib) {
+                    const int pi = p0 + 16 * ib + r16;
+                    const float e = gam * qn * xn[ib] + 0x1p-90f;
+                    if (pi < pend && !(acc[qb][ib][v] + e < th)) {
+                        const int64_t q = qmap(q0 + ql);
+                        const int slot = atomicAdd(&counts[q], 1);
+                        if (slot < cap) lists[q * cap + slot] = pi;
+                    }
+                }
+            }
+        }
+    }
+}
+
 // Pass B of the single-product screen, the one that runs over every probed
 // pair: a register budget for three waves per SIMD (a few values spill)
 // hides the operand loads better than two waves with no spill.
@@ -1562,6 +1690,23 @@ static hipError_t launch_screen_bf16(const uint16_t *Xh, const uint16_t *Xlo, co
                           : (const void *)k_screen3<W, MAXMODE, X3>;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
+    if (W == 0 && one && sh.dp >= 256) {
+        // 128-query tiles when their image fits the work-group's LDS (rows of
+        // at least 256 coordinates: shorter ones gain less from the halved
+        // item reads than the coarser tiles lose in skipped chunks)
+        const size_t lds2 = (size_t)128 * screen_qsb(sh.dp) * sizeof(uint16_t);
+        int dev = 0, lim = 0;
+        if (hipGetDevice(&dev) == hipSuccess &&
+            hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+            lds2 + 2048 <= (size_t)lim &&
+            hipFuncSetAttribute((const void *)k_screen_b128, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds2) == hipSuccess) {
+            const dim3 grid2(ceil_div(nq, 128), (unsigned)nchunks);
+            hipLaunchKernelGGL(k_screen_b128, grid2, dim3(512), lds2, s, Xh, sh.dp, key_l, Q.Qh, Q.qn, nq, chunks,
+                               theta, gam, cap, counts, lists, screen_qsb(sh.dp), Q.U, Q.pairs, Q.order);
+            return hipGetLastError();
+        }
+    }
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
     if (a0)
         hipLaunchKernelGGL(k_screen_a0, grid, dim3(256), lds, s, Xh, Xlo, sh.dp, codes_l, key_l, Q.Qh, Q.Ql,

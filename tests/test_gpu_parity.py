@@ -70,6 +70,7 @@ SCREEN_CASES = [
     (12000, 300, 13, 17, 200, 16, 5000),    # d = 300, ragged L
     (9000, 33, 1, 20, 70, 10, 3000),        # m = 1
     (7000, 8, 4, 16, 65, 64, 6999),         # small d, T = n - 1
+    (15000, 260, 12, 32, 300, 10, 15000),   # d_p >= 256, T = n: 128-query tiles, last one ragged
 ]
 
 
