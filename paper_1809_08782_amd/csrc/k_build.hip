@@ -798,6 +798,171 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
     }
 }
 
+// The same hash with one shared projection, persistent: each block stages
+// the whole L x d_p projection in LDS once (row stride d_p + 4) and then
+// walks tiles of 256 stored rows (one 64-row tile per wave), loading the rows
+// of step kk + 16 while the matrix cores work on step kk.  Products, bounds,
+// codes and fix-up entries are those of k_hash.
+constexpr int HP_WAVES = 4;
+
+template <int CB>
+__global__ __launch_bounds__(HP_WAVES * 64) void k_hash_p(
+    const float *__restrict__ Xl, int64_t n, int d, int dp, const float *__restrict__ A, int L,
+    const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
+    const double *__restrict__ keymax, const double *__restrict__ U,
+    const float *__restrict__ tau, uint32_t *__restrict__ codes_l, FixEntry *__restrict__ fix,
+    BuildCounters *__restrict__ ctr, const int32_t *__restrict__ rows, int64_t ntiles)
+{
+    constexpr int NB = 16 * CB;
+    extern __shared__ __align__(16) float As[];  // NB x (dp + 4)
+    __shared__ float sq_s[HP_WAVES][64];
+    __shared__ float uf_s[HP_WAVES][64];
+    __shared__ int sp_s[HP_WAVES][64];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int ks = dp + 4;
+    {
+        // projection rows r < L, columns < d (zero elsewhere), 16 loads per
+        // thread in flight before their stores
+        const int total = NB * dp;
+        for (int e0 = 0; e0 < total; e0 += 16 * HP_WAVES * 64) {
+            float av[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * HP_WAVES * 64 + (int)threadIdx.x;
+                const int r = e / dp, c = e - (e / dp) * dp;
+                av[u] = (e < total && r < L && c < d) ? A[(int64_t)r * (d + 1) + c] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int e = e0 + u * HP_WAVES * 64 + (int)threadIdx.x;
+                if (e < total) As[(e / dp) * ks + (e - (e / dp) * dp)] = av[u];
+            }
+        }
+    }
+    __syncthreads();
+    const int r16 = lane & 15, g = lane >> 4;
+    const int my_rb = lane >> 4, my_g = (lane >> 2) & 3, my_v = lane & 3;
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t i0 = (tile * HP_WAVES + wave) * 64;
+        {
+            const int64_t i = i0 + lane;
+            float sq = 0.f, uf = 0.f;
+            int sp = 1;
+            if (i < n) {
+                const int64_t ii = rows ? rows[i] : i;
+                const int s = sid_l[ii];
+                const double km = keymax[s], u = U[s];
+                sq = sqrtf((float)(km - key_l[ii]));
+                uf = (float)u;
+                sp = !(u >= 0x1p-60 && u <= 0x1p60);
+            }
+            sq_s[wave][lane] = sq;
+            uf_s[wave][lane] = uf;
+            sp_s[wave][lane] = sp;
+        }
+        int64_t rowpos[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const int64_t row = i0 + 16 * rb + r16;
+            rowpos[rb] = (rows && row < n) ? (int64_t)rows[row] : row;
+        }
+        auto load_rows = [&](floatx4 (&xa)[4], int k) {
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+                const int64_t row = i0 + 16 * rb + r16;
+                xa[rb] = (row < n && k < dp) ? *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + k)
+                                             : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+        };
+        floatx4 acc[4][CB];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        floatx4 xn[4];
+        load_rows(xn, 4 * g);
+        for (int kk = 0; kk < dp; kk += 16) {
+            floatx4 xa[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) xa[rb] = xn[rb];
+            load_rows(xn, kk + 16 + 4 * g);
+            floatx4 bq[CB];
+#pragma unroll
+            for (int cb = 0; cb < CB; ++cb) {
+                const int k = kk + 4 * g;
+                bq[cb] = k < dp ? *reinterpret_cast<const floatx4 *>(&As[(16 * cb + r16) * ks + k])
+                                : floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+                    for (int cb = 0; cb < CB; ++cb)
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[rb][j], bq[cb][j], acc[rb][cb], 0, 0, 0);
+        }
+        __syncthreads();  // the wave's row parameters are in LDS
+
+        uint64_t mycode = 0, myfix = 0;
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+            const int r = 16 * cb + r16;
+            const float alast = (r < L) ? A[(int64_t)r * (d + 1) + d] : 0.f;
+            const float tr = (r < L) ? tau[r] : 0.f;
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = 16 * rb + 4 * g + v;
+                    const float p = acc[rb][cb][v] + alast * sq_s[wave][row];
+                    const bool inb = (r < L) && (i0 + row < n);
+                    const bool flag = inb && (sp_s[wave][row] != 0 || fabsf(p) <= tr * uf_s[wave][row]);
+                    const bool bit = inb && (p > 0.f);
+                    const uint64_t bb = __ballot(bit);
+                    const uint64_t fb = __ballot(flag);
+                    if (rb == my_rb && v == my_v) {
+                        mycode |= ((bb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                        myfix |= ((fb >> (16 * my_g)) & 0xFFFFull) << (16 * cb);
+                    }
+                }
+            }
+        }
+        const bool valid = i0 + lane < n;
+        const int64_t i = valid && rows ? (int64_t)rows[i0 + lane] : i0 + lane;
+        if (valid) {
+            if (rows) {  // bits the FP32 re-hash changes in the low-precision code
+                uint64_t old = codes_l[(CB <= 2 ? 1 : 2) * i];
+                if (CB > 2) old |= (uint64_t)codes_l[2 * i + 1] << 32;
+                const unsigned long long ch = (unsigned long long)__popcll(old ^ mycode);
+                if (ch) atomicAdd(&ctr->lowp_changed, ch);
+            }
+            if (CB <= 2) {
+                codes_l[i] = (uint32_t)mycode;
+            } else {
+                codes_l[2 * i] = (uint32_t)mycode;
+                codes_l[2 * i + 1] = (uint32_t)(mycode >> 32);
+            }
+        }
+        const bool has = valid && myfix != 0ull;
+        const uint64_t hb = __ballot(has);
+        if (hb != 0ull) {
+            const int leader = __ffsll((long long)hb) - 1;
+            uint32_t base = 0;
+            if (lane == leader) base = atomicAdd(&ctr->fix_count, (uint32_t)__popcll(hb));
+            base = __shfl(base, leader, 64);
+            if (has) {
+                const uint32_t slot = base + (uint32_t)__popcll(hb & lanemask_lt(lane));
+                FixEntry fe;
+                fe.mask = myfix;
+                fe.item = (int32_t)i;
+                fe.pad = 0;
+                fix[slot] = fe;
+            }
+        }
+        __syncthreads();  // row parameters of the next tile overwrite these
+    }
+}
+
 // One thread per list entry: recompute every flagged bit in FP64 exactly as
 // the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
 // when U_j = 0; sum over coordinates in ascending order, no contraction).
@@ -963,11 +1128,49 @@ hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64
     return hipGetLastError();
 }
 
+// Persistent form when the projection fits the work-group's LDS: as many
+// blocks as stay resident, each walking tiles of 256 rows.
+template <int CB>
+static bool launch_hash_p(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
+                          const double *key_l, const int32_t *sid_l, const double *keymax,
+                          const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
+                          BuildCounters *ctr, const int32_t *rows, hipStream_t s)
+{
+    const size_t lds = (size_t)16 * CB * (dp + 4) * sizeof(float);
+    int dev = 0, lim = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        return false;
+    if (lds + 4096 > (size_t)lim) return false;
+    if (hipFuncSetAttribute((const void *)k_hash_p<CB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) !=
+            hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_hash_p<CB>, HP_WAVES * 64, lds) != hipSuccess ||
+        per_cu < 1)
+        return false;
+    const int64_t ntiles = (n + HP_WAVES * 64 - 1) / (HP_WAVES * 64);
+    const int64_t blocks = std::min<int64_t>(ntiles, (int64_t)per_cu * cus);
+    hipLaunchKernelGGL(k_hash_p<CB>, dim3((unsigned)blocks), dim3(HP_WAVES * 64), lds, s, Xl, n, d, dp, A, L,
+                       key_l, sid_l, keymax, U, tau, codes_l, fix, ctr, rows, ntiles);
+    return true;
+}
+
 hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A, int L,
                        const double *key_l, const int32_t *sid_l, const double *keymax,
                        const double *U, const float *tau, uint32_t *codes_l, FixEntry *fix,
                        BuildCounters *ctr, const int32_t *rows, hipStream_t s)
 {
+    if (n < 1) return hipSuccess;
+    // more than 32 bits: the persistent form (at 32 or fewer the 8-wave
+    // blocks below keep one more wave per SIMD resident and measure faster)
+    bool done = false;
+    switch ((L + 15) / 16) {
+    case 1:
+    case 2: break;
+    case 3: done = launch_hash_p<3>(Xl, n, d, dp, A, L, key_l, sid_l, keymax, U, tau, codes_l, fix, ctr, rows, s); break;
+    default: done = launch_hash_p<4>(Xl, n, d, dp, A, L, key_l, sid_l, keymax, U, tau, codes_l, fix, ctr, rows, s); break;
+    }
+    if (done) return hipGetLastError();
     const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
     switch ((L + 15) / 16) {
     case 1:
