@@ -491,10 +491,18 @@ def main():
         flops = 2.0 * products * w.d * pairs
         peak = BF16_MFMA_PEAK_TFS if b16 else FP32_MFMA_PEAK_TFS
         achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
-        kname = {"screen": "k_screen1<1>",
-                 "screen_bf16x3": "k_screen3<1, false, true>"}.get(smode, "k_screen<1, false>")
-        if w.L > 32:
-            kname = kname.replace("<1", "<2")
+        # the kernel the library launches: budgets covering every item take
+        # the variants that read no codes (128-query tiles for rows of at
+        # least 256 coordinates); otherwise one or two code words per item
+        dp = (w.d + 7) // 8 * 8
+        if Tq >= w.n and smode in ("screen", "screen_bf16x3"):
+            kname = ("k_screen_b128" if dp >= 256 else "k_screen1<0>") if smode == "screen" \
+                else "k_screen3<0, false, true>"
+        else:
+            kname = {"screen": "k_screen1<1>",
+                     "screen_bf16x3": "k_screen3<1, false, true>"}.get(smode, "k_screen<1, false>")
+            if w.L > 32:
+                kname = kname.replace("<1", "<2")
         rec = traffic_record(kname, w.name, Tq)
         roof = {"kernel": kname, "bound": "mfma",
                 "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
