@@ -259,9 +259,10 @@ __global__ __launch_bounds__(256) void k_assign(const uint64_t *__restrict__ ske
 // query-tiled screen and, when Xlo is given, split further into lo =
 // bf16(x - hi) (|x - hi - lo| <= 2^-16 |x|).
 // A wave copies LY_ROWS consecutive stored rows: their source indices are
-// read once, then the rows are treated as one run of VW-float vectors
-// (VW = the widest of 4, 2, 1 dividing d, so no vector crosses a row end)
-// of which each lane keeps LY_B loads in flight before storing.
+// read once, then the rows are treated as one run of 4-float groups, each
+// read in VW-float pieces (VW = the widest of 4, 2, 1 dividing d, so no
+// piece crosses an item's row end), of which each lane keeps LY_B groups in
+// flight before storing them whole.
 constexpr int LY_ROWS = 16;
 constexpr int LY_B = 8;
 
@@ -301,7 +302,6 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
                                                 int32_t *__restrict__ sid_l)
 {
     using F = typename LyVec<VW>::F;
-    using H = typename LyVec<VW>::H;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * LY_ROWS;
     const bool mine = lane < LY_ROWS && p0 + lane < n;
@@ -310,38 +310,46 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
         key_l[p0 + lane] = key[src_row];
         sid_l[p0 + lane] = sid[src_row];
     }
-    const int nv = dp / VW;  // vectors per stored row
+    // each lane element is a group of 4 stored floats (dp is a multiple of
+    // 8, so groups never cross a stored row and their stores are 16- and
+    // 8-byte aligned), loaded as 4 / VW pieces that lie wholly inside or
+    // wholly past the item's d values
+    const int nv = dp / 4;  // groups per stored row
     const int total = LY_ROWS * nv;
     for (int e0 = 0; e0 < total; e0 += 64 * LY_B) {
-        float v[LY_B][VW];
-        int64_t dst[LY_B];  // first stored element of the vector, -1 = none
+        float v[LY_B][4];
+        int64_t dst[LY_B];  // first stored element of the group, -1 = none
 #pragma unroll
         for (int b = 0; b < LY_B; ++b) {
             const int e = e0 + 64 * b + lane;
-            const int r = e / nv, c = (e - r * nv) * VW;
+            const int r = e / nv, c = (e - r * nv) * 4;
             const int64_t i = __shfl(src_row, r & (LY_ROWS - 1), 64);
             const bool ok = e < total && p0 + r < n;
             dst[b] = ok ? (p0 + r) * dp + c : -1;
-            F t = F{};
-            if (ok && c < d) t = *reinterpret_cast<const F *>(X + i * d + c);
 #pragma unroll
-            for (int u = 0; u < VW; ++u) v[b][u] = reinterpret_cast<const float *>(&t)[u];
+            for (int q = 0; q < 4 / VW; ++q) {
+                const int cc = c + q * VW;
+                F t = F{};
+                if (ok && cc < d) t = *reinterpret_cast<const F *>(X + i * d + cc);
+#pragma unroll
+                for (int u = 0; u < VW; ++u) v[b][q * VW + u] = reinterpret_cast<const float *>(&t)[u];
+            }
         }
 #pragma unroll
         for (int b = 0; b < LY_B; ++b) {
             if (dst[b] < 0) continue;
-            F t;
-            H h, l;
+            floatx4 t;
+            ushort4 h, l;
 #pragma unroll
-            for (int u = 0; u < VW; ++u) {
+            for (int u = 0; u < 4; ++u) {
                 const uint16_t hu = bf16_rne(v[b][u]);
-                reinterpret_cast<float *>(&t)[u] = v[b][u];
+                t[u] = v[b][u];
                 reinterpret_cast<uint16_t *>(&h)[u] = hu;
                 reinterpret_cast<uint16_t *>(&l)[u] = bf16_rne(v[b][u] - __uint_as_float((uint32_t)hu << 16));
             }
-            *reinterpret_cast<F *>(Xl + dst[b]) = t;
-            *reinterpret_cast<H *>(Xh + dst[b]) = h;
-            if (Xlo) *reinterpret_cast<H *>(Xlo + dst[b]) = l;
+            *reinterpret_cast<floatx4 *>(Xl + dst[b]) = t;
+            *reinterpret_cast<ushort4 *>(Xh + dst[b]) = h;
+            if (Xlo) *reinterpret_cast<ushort4 *>(Xlo + dst[b]) = l;
         }
     }
 }
