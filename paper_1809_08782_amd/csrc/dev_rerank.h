@@ -144,7 +144,9 @@ __device__ __forceinline__ double ip64_rows_fp32(const float *__restrict__ Xl, i
         }
         __syncthreads();
         const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
-#pragma unroll
+        // the sum is one dependent chain: reading the tile two pieces at a
+        // time keeps registers (and so resident waves) free
+#pragma unroll 2
         for (int tt = 0; tt < 8; ++tt) {
             const floatx4 x4 = row[tt];
 #pragma unroll
@@ -185,7 +187,9 @@ __device__ __forceinline__ double ip64_rows_bf16(const uint16_t *__restrict__ Xh
         }
         __syncthreads();
         const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
-#pragma unroll
+        // the sum is one dependent chain: reading the tile two pieces at a
+        // time keeps registers (and so resident waves) free
+#pragma unroll 2
         for (int tt = 0; tt < 8; ++tt) {
             const floatx4 x4 = row[tt];
 #pragma unroll
