@@ -22,13 +22,14 @@ __device__ __forceinline__ uint64_t lanemask_lt(int lane) { return (1ull << lane
 
 // ---------------------------------------------------------------- keys
 // One wave owns 64 consecutive rows.  Columns are streamed 32 at a time:
-// each load instruction brings 16 bytes per lane, 8 rows x 128 contiguous
+// each load instruction brings up to 16 bytes per lane, 8 rows x 128 contiguous
 // bytes, and the next chunk's loads are in flight while the current chunk is
 // transposed through LDS and summed: lane r adds the squares of row r in
 // ascending column order.  Squares of FP32 values are exact in FP64, so the
 // sum is bit-identical to a sequential FP64 loop.
 constexpr int KC_ROWS = 64;
 
+template <int VW>
 __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64_t n, int d,
                                               double *__restrict__ key,
                                               uint64_t *__restrict__ skey,
@@ -39,52 +40,74 @@ __global__ __launch_bounds__(256) void k_keys(const float *__restrict__ X, int64
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t row0 = ((int64_t)blockIdx.x * 4 + wave) * KC_ROWS;
     const int sub = lane >> 3, seg = 4 * (lane & 7);  // row 8 it + sub, columns seg .. seg + 3
-    const bool vec = (d & 3) == 0;                     // rows 16-byte aligned
-    const bool vec2 = (d & 1) == 0;                    // rows 8-byte aligned
+    // Loads are issued from addresses clamped into the matrix and the values
+    // are masked only where the chunk is written to LDS, one chunk later,
+    // so the next chunk's loads stay in flight while this one is summed.
+    // VW: floats per load, the widest that d % VW == 0 keeps aligned.
     auto load = [&](floatx4 (&v)[8], int c0) {
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
             const int64_t row = row0 + 8 * it + sub;
+            const float *p = X + (row < n ? row : 0) * (int64_t)d;
             const int c = c0 + seg;
-            v[it] = floatx4{0.f, 0.f, 0.f, 0.f};
-            if (row < n) {
-                if (vec && c + 3 < d) {
-                    v[it] = *reinterpret_cast<const floatx4 *>(X + row * d + c);
-                } else if (vec2 && c + 3 < d) {  // even d: 8-byte aligned pairs
-                    const floatx2 a = *reinterpret_cast<const floatx2 *>(X + row * d + c);
-                    const floatx2 b = *reinterpret_cast<const floatx2 *>(X + row * d + c + 2);
-                    v[it] = floatx4{a[0], a[1], b[0], b[1]};
-                } else {
+            // a column past d reads the row's last VW floats instead, which
+            // the same or the previous chunk has just brought into the caches
+            if constexpr (VW == 4) {
+                v[it] = *reinterpret_cast<const floatx4 *>(p + min(c, d - 4));
+            } else if constexpr (VW == 2) {
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (c + u < d) v[it][u] = X[row * d + c + u];
+                for (int h = 0; h < 2; ++h) {
+                    const floatx2 t = *reinterpret_cast<const floatx2 *>(p + min(c + 2 * h, d - 2));
+                    v[it][2 * h] = t[0];
+                    v[it][2 * h + 1] = t[1];
                 }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[it][u] = p[min(c + u, d - 1)];
             }
         }
     };
-    floatx4 cur[8], nxt[8];
-    load(cur, 0);
+    // tile[wave] is written and read by its own wave only: LDS operations of
+    // one wave complete in issue order, so a wave-level barrier that keeps the
+    // compiler from moving them across suffices.
+    auto wave_sync = [] {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    };
     double acc = 0.0;
     bool bad = false;
-    for (int c0 = 0; c0 < d; c0 += 32) {
-        if (c0 + 32 < d) load(nxt, c0 + 32);
+    auto consume = [&](const floatx4 (&v)[8], int c0) {
 #pragma unroll
         for (int it = 0; it < 8; ++it) {
+            const bool rok = row0 + 8 * it + sub < n;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                bad |= !__builtin_isfinite(cur[it][u]);
-                tile[wave][8 * it + sub][seg + u] = cur[it][u];
+                const float x = rok && c0 + seg + u < d ? v[it][u] : 0.f;
+                bad |= !__builtin_isfinite(x);
+                tile[wave][8 * it + sub][seg + u] = x;
             }
         }
-        __syncthreads();
-        const int cend = min(32, d - c0);
-        for (int t = 0; t < cend; ++t) {
+        wave_sync();
+        // columns past d hold zeros, and adding +0 leaves a non-negative sum unchanged
+#pragma unroll
+        for (int t = 0; t < 32; ++t) {
             const double x = (double)tile[wave][lane][t];
             acc = acc + x * x;
         }
-        __syncthreads();
-#pragma unroll
-        for (int it = 0; it < 8; ++it) cur[it] = nxt[it];
+        wave_sync();
+    };
+    // Two register buffers taken in turn, with no copy between them and no
+    // branch around a load or between a load and the chunk before it: either
+    // lets the compiler wait for the loads in flight.  Chunks go in pairs; a
+    // chunk past d rereads cached columns (clamped) and adds only zeros.
+    floatx4 va[8], vb[8];
+    load(va, 0);
+    for (int c0 = 0; c0 < d; c0 += 64) {
+        load(vb, c0 + 32);
+        consume(va, c0);
+        load(va, c0 + 64);
+        consume(vb, c0 + 32);
     }
     const int64_t myrow = row0 + lane;
     if (myrow < n) {
@@ -1034,8 +1057,13 @@ inline unsigned grid_for(int64_t n, int per_block)
 hipError_t launch_keys(const float *X, int64_t n, int d, double *key, uint64_t *sort_key,
                        int32_t *sort_val, BuildCounters *ctr, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_keys, dim3(grid_for(n, 4 * KC_ROWS)), dim3(256), 0, s, X, n, d, key,
-                       sort_key, sort_val, ctr);
+    const dim3 grid(grid_for(n, 4 * KC_ROWS)), block(256);
+    if (d % 4 == 0)
+        hipLaunchKernelGGL(k_keys<4>, grid, block, 0, s, X, n, d, key, sort_key, sort_val, ctr);
+    else if (d % 2 == 0)
+        hipLaunchKernelGGL(k_keys<2>, grid, block, 0, s, X, n, d, key, sort_key, sort_val, ctr);
+    else
+        hipLaunchKernelGGL(k_keys<1>, grid, block, 0, s, X, n, d, key, sort_key, sort_val, ctr);
     return hipGetLastError();
 }
 
