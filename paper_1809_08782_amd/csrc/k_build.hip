@@ -459,12 +459,14 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
         uf_s[wave][lane] = uf;
         sp_s[wave][lane] = sp;
     }
-    // stored positions of this lane's four row-block rows (identity without a list)
+    // stored positions of this lane's four row-block rows (identity without a
+    // list); a row past n reads row n - 1 instead: an MFMA output row depends
+    // only on its own input row, and rows past n are never stored
     int64_t rowpos[4];
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb) {
-        const int64_t row = i0 + 16 * rb + (lane & 15);
-        rowpos[rb] = (rows && row < n) ? (int64_t)rows[row] : row;
+        const int64_t row = min(i0 + 16 * rb + (lane & 15), n - 1);
+        rowpos[rb] = rows ? (int64_t)rows[row] : row;
     }
     floatx4 acc[4][CB];
 #pragma unroll
@@ -504,16 +506,17 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
         }
         __syncthreads();
         const int kend = min(H_KC, dp - kc0);
-        for (int kk = 0; kk < kend; kk += 16) {
-            const int k = kc0 + kk + 4 * g;
-            floatx4 xa[4];
+        // Row loads run one step ahead in two register sets taken in turn;
+        // a step's columns past dp read columns dp - 4 .. dp - 1 instead and
+        // are masked to zero where they enter the matrix cores.
+        auto load_x = [&](floatx4 (&x)[4], int kk) {
+            const int k = min(kc0 + kk + 4 * g, dp - 4);
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const int64_t row = i0 + 16 * rb + r16;
-                xa[rb] = (row < n && k < dp)
-                             ? *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + k)
-                             : floatx4{0.f, 0.f, 0.f, 0.f};
-            }
+            for (int rb = 0; rb < 4; ++rb)
+                x[rb] = *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + k);
+        };
+        auto step = [&](const floatx4 (&x)[4], int kk) {
+            const bool kin = kc0 + kk + 4 * g < dp;
             floatx4 bq[CB];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb)
@@ -524,8 +527,24 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash(
                 for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
                     for (int cb = 0; cb < CB; ++cb)
-                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[rb][j], bq[cb][j],
+                        acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(kin ? x[rb][j] : 0.f, bq[cb][j],
                                                                            acc[rb][cb], 0, 0, 0);
+        };
+        // Steps go in pairs with no branch between them (a branch would let
+        // the compiler sink the loads to their use), and a scheduling barrier
+        // after each set of loads keeps them ahead of the previous set's
+        // matrix-core work.  An odd step count ends with a step wholly past
+        // dp, which reads staged zeros and in-bounds LDS (kk <= 112) and adds
+        // +0 to every sum.
+        floatx4 xa[4], xb[4];
+        load_x(xa, 0);
+        for (int kk = 0; kk < kend; kk += 32) {
+            load_x(xb, kk + 16);
+            __builtin_amdgcn_sched_barrier(0);
+            step(xa, kk);
+            load_x(xa, kk + 32);
+            __builtin_amdgcn_sched_barrier(0);
+            step(xb, kk + 16);
         }
     }
 
