@@ -112,6 +112,23 @@ def test_screen_with_duplicates_and_zero_rows():
                 assert np.array_equal(ips, oips.astype(np.float32)), f"T={T} {mode}"
 
 
+# dimensions around the norm keys' 32-column chunks (taken in pairs, so an
+# odd chunk count ends with a chunk wholly past d) and the hash's 16-coordinate
+# steps (also paired; d_p = d rounded up to 8), for each load width the keys
+# use (d % 4 == 0, d % 2 == 0, odd)
+CHUNK_DIMS = [1, 2, 3, 4, 6, 8, 24, 31, 32, 33, 62, 63, 64, 65, 96, 98, 120, 136, 161]
+
+
+@pytest.mark.parametrize("d", CHUNK_DIMS)
+def test_build_chunk_boundaries(d):
+    n = 333
+    say(f"case build chunk boundaries n={n} d={d}")
+    X = make_items("lognormal", n, d, seed=1000 + d, sigma=0.8)
+    oix = orc.OracleIndex(X, 5, 20, seed=31 + d, threads=8)
+    with nr.nrlsh_build(X, 5, 20, 31 + d) as gix:
+        check_build(gix, oix, f"d{d}")
+
+
 def test_parity_tiny_config():
     """The small recipe end to end: n = 1e4, d = 64, m = 8, L = 16, 100 queries,
     top-10, budget 500."""
