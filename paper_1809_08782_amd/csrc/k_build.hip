@@ -910,32 +910,41 @@ __global__ __launch_bounds__(HP_WAVES * 64) void k_hash_p(
             uf_s[wave][lane] = uf;
             sp_s[wave][lane] = sp;
         }
+        // a row past n reads row n - 1 (an MFMA output row depends only on its
+        // own input row, and rows past n are never stored) and a column past
+        // dp reads columns dp - 4 .. dp - 1, masked to zero where it is used:
+        // the loads need no branch, which would make the compiler wait for
+        // the loads in flight
         int64_t rowpos[4];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
-            const int64_t row = i0 + 16 * rb + r16;
-            rowpos[rb] = (rows && row < n) ? (int64_t)rows[row] : row;
+            const int64_t row = min(i0 + 16 * rb + r16, n - 1);
+            rowpos[rb] = rows ? (int64_t)rows[row] : row;
         }
         auto load_rows = [&](floatx4 (&xa)[4], int k) {
+            const int kc = min(k, dp - 4);
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) {
-                const int64_t row = i0 + 16 * rb + r16;
-                xa[rb] = (row < n && k < dp) ? *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + k)
-                                             : floatx4{0.f, 0.f, 0.f, 0.f};
-            }
+            for (int rb = 0; rb < 4; ++rb)
+                xa[rb] = *reinterpret_cast<const floatx4 *>(Xl + rowpos[rb] * dp + kc);
         };
         floatx4 acc[4][CB];
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = floatx4{0.f, 0.f, 0.f, 0.f};
-        floatx4 xn[4];
+        // rows two steps ahead
+        floatx4 xn[4], xn2[4];
         load_rows(xn, 4 * g);
+        load_rows(xn2, 16 + 4 * g);
         for (int kk = 0; kk < dp; kk += 16) {
+            const bool kin = kk + 4 * g < dp;
             floatx4 xa[4];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) xa[rb] = xn[rb];
-            load_rows(xn, kk + 16 + 4 * g);
+            for (int rb = 0; rb < 4; ++rb) {
+                xa[rb] = kin ? xn[rb] : floatx4{0.f, 0.f, 0.f, 0.f};
+                xn[rb] = xn2[rb];
+            }
+            load_rows(xn2, kk + 32 + 4 * g);
             floatx4 bq[CB];
 #pragma unroll
             for (int cb = 0; cb < CB; ++cb) {
