@@ -1263,10 +1263,12 @@ hipError_t launch_hash_fixup(const float *Xl, int d, int dp, const float *A, int
                              uint32_t *codes_l, int64_t max_entries, hipStream_t s)
 {
     const int W = L > 32 ? 2 : 1;
-    int64_t blocks = (max_entries + 255) / 256;
-    if (blocks > 1024) blocks = 1024;
+    // one wave per block: the few hundred waves a typical list needs spread
+    // over every compute unit instead of a quarter of them
+    int64_t blocks = (max_entries + 63) / 64;
+    if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(256), 0, s, Xl, d, dp, A, L,
+    hipLaunchKernelGGL(k_hash_fixup, dim3((unsigned)blocks), dim3(64), 0, s, Xl, d, dp, A, L,
                        per_subset ? 1 : 0, key_l, sid_l, keymax, U, fix, ctr, codes_l, W);
     return hipGetLastError();
 }
