@@ -1025,6 +1025,8 @@ __global__ __launch_bounds__(HP_WAVES * 64) void k_hash_p(
 // One thread per list entry: recompute every flagged bit in FP64 exactly as
 // the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
 // when U_j = 0; sum over coordinates in ascending order, no contraction).
+constexpr int FX_U = 8;
+
 __global__ __launch_bounds__(256) void k_hash_fixup(
     const float *__restrict__ Xl, int d, int dp, const float *__restrict__ A, int L, int per_subset,
     const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
@@ -1048,16 +1050,27 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
             vd = __builtin_sqrt(t);
         }
         const float *x = Xl + i * dp;
+        const double uu = u == 0.0 ? 1.0 : u;
         uint64_t mask = fe.mask;
         while (mask != 0ull) {
             const int r = __ffsll((long long)mask) - 1;
             mask &= mask - 1ull;
             const float *a = A + ((per_subset ? (int64_t)s * L : 0) + r) * (int64_t)(d + 1);
+            // FX_U products at a time with their loads issued together (a
+            // coordinate past d reads coordinate d - 1 and is not added; the
+            // quotient is always formed, by 1 when U_j = 0 and then replaced
+            // by 0), added in ascending order
             double sacc = 0.0;
-            if (u == 0.0) {
-                for (int c = 0; c < d; ++c) sacc = sacc + (double)a[c] * 0.0;
-            } else {
-                for (int c = 0; c < d; ++c) sacc = sacc + (double)a[c] * ((double)x[c] / u);
+            for (int c0 = 0; c0 < d; c0 += FX_U) {
+                double t[FX_U];
+#pragma unroll
+                for (int j = 0; j < FX_U; ++j) {
+                    const int c = min(c0 + j, d - 1);
+                    const double q = (double)x[c] / uu;
+                    t[j] = (double)a[c] * (u == 0.0 ? 0.0 : q);
+                }
+#pragma unroll
+                for (int j = 0; j < FX_U; ++j) sacc = c0 + j < d ? sacc + t[j] : sacc;
             }
             sacc = sacc + (double)a[d] * vd;
             const uint64_t bit = sacc > 0.0 ? 1ull : 0ull;
