@@ -28,6 +28,17 @@
  *   - the probe budget T is a number of items; the bucket where the budget
  *     runs out is cut by original index                   (Section 3.3)
  *   - the query is not normalised (bits and argmax are scale invariant)
+ *   - multi-table single probe (Section 4 names it as the alternative to
+ *     single-table multi-probe; its description is in the absent supplement):
+ *     t tables over the same partition, table tau hashing with its own
+ *     projection rows (block tau P + b of one (t P L) x (d+1) matrix from the
+ *     same generator, P = 1 shared or P = m per sub-dataset, b = 0 or the
+ *     item's sub-dataset); a query probes in each table only the bucket of
+ *     its own code in every sub-dataset (l = L).  f(i) = the first table whose
+ *     probed bucket holds item i.  Tables are probed in order until T items:
+ *     the probed items are taken in (f asc, sub-dataset desc, index asc)
+ *     order, so the budget is cut inside the table where it runs out with the
+ *     higher-norm sub-datasets first and by index inside a sub-dataset
  *   - uniform partitioning (Section 5, the alternative scheme): the 2-norm
  *     domain [min, max] of the items is cut into m ranges of equal width;
  *     boundary j (1 <= j < m) is b_j = nmin + j * w, w = (nmax - nmin) / m,
@@ -338,6 +349,38 @@ int64_t orc_candidates(const uint64_t *codes, const int32_t *sid, int64_t n, int
     return orc_candidates2(codes, sid, n, L, R, &qcode, 0, T, cand, l_out);
 }
 
+/* Candidates of one query under multi-table single probe (see the header):
+ * codes: tables x n; qcodes: tables x P query codes (P = m with per_subset,
+ * else 1), code (tau, b) at qcodes[tau P + b].  f(i) = the first table tau
+ * with codes[tau][i] == qcodes[tau][b(i)]; items without one are not probed.
+ * The probed items in (f asc, sub-dataset desc, index asc) order, the first
+ * min(T, |C|) of them, go to cand[]; returns their number.                 */
+int64_t orc_candidates_mt(const uint64_t *codes, const int32_t *sid, int64_t n, int32_t m,
+                          int32_t tables, const uint64_t *qcodes, int32_t per_subset, int64_t T,
+                          int64_t *cand)
+{
+    orc_ii *e = (orc_ii *)malloc(sizeof(orc_ii) * (size_t)(n > 0 ? n : 1));
+    if (!e) return -1;
+    const int32_t P = per_subset ? m : 1;
+    int64_t nc = 0;
+    for (int64_t i = 0; i < n; ++i) {
+        int32_t f = -1;
+        for (int32_t tb = 0; tb < tables && f < 0; ++tb) {
+            const uint64_t qc = qcodes[(int64_t)tb * P + (per_subset ? sid[i] : 0)];
+            if (codes[(int64_t)tb * n + i] == qc) f = tb;
+        }
+        if (f < 0) continue;
+        e[nc].key = (int64_t)f * m + (m - 1 - sid[i]);
+        e[nc].idx = i;
+        ++nc;
+    }
+    qsort(e, (size_t)nc, sizeof(orc_ii), orc_cmp_ii);
+    const int64_t Tq = T < nc ? T : nc;
+    for (int64_t c = 0; c < Tq; ++c) cand[c] = e[c].idx;
+    free(e);
+    return Tq;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Exact inner product (Eq. 1) in FP64, ascending t.                        */
 double orc_ip(const float *q, const float *x, int32_t d)
@@ -388,13 +431,14 @@ int orc_topk(const float *X, int32_t d, const float *q, const int64_t *cand, int
 typedef struct {
     int64_t n; int32_t d, m, L;
     int32_t per_subset; /* 1: sub-dataset j hashes with rows j L .. j L + L - 1 of A */
-    float *A;          /* L x (d+1), or m L x (d+1) with per_subset */
+    int32_t tables;    /* independent hash tables (single probe); 1 = the index itself */
+    float *A;          /* tables x (L or m L) x (d+1): block tau P + b, P = 1 or m */
     double *key;       /* n */
     int64_t *rank;     /* n */
     int32_t *sid;      /* n */
     double *keymax;    /* m */
     double *U;         /* m */
-    uint64_t *codes;   /* n */
+    uint64_t *codes;   /* tables x n: table 0 first */
     int32_t *R;        /* m x (L+1) */
     const float *X;    /* borrowed, n x d */
 } orc_index;
@@ -407,8 +451,10 @@ static void *orc_build_worker(void *arg)
 {
     orc_build_job *jb = (orc_build_job *)arg;
     const orc_index *ix = jb->ix;
-    orc_item_codes2(ix->X, jb->i0, jb->i1, ix->d, ix->L, ix->A, ix->per_subset, ix->key, ix->sid,
-                    ix->keymax, ix->U, ix->codes);
+    const int64_t blk = (int64_t)(ix->per_subset ? ix->m : 1) * ix->L * (ix->d + 1);
+    for (int32_t tb = 0; tb < ix->tables; ++tb)
+        orc_item_codes2(ix->X, jb->i0, jb->i1, ix->d, ix->L, ix->A + tb * blk, ix->per_subset, ix->key,
+                        ix->sid, ix->keymax, ix->U, ix->codes + (int64_t)tb * ix->n);
     return NULL;
 }
 
@@ -433,23 +479,25 @@ void orc_free(orc_index *ix)
 
 /* partition: 0 = norm percentiles (Algorithm 1), 1 = uniform ranges (Section 5);
  * per_subset: 1 = independent projections per sub-dataset */
-orc_index *orc_build3(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
+orc_index *orc_build4(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
                       uint64_t seed, double eps, int32_t partition, int32_t per_subset,
-                      int32_t nthreads)
+                      int32_t tables, int32_t nthreads)
 {
     if (nthreads < 1) nthreads = 1;
+    if (tables < 1) return NULL;
     orc_index *ix = (orc_index *)calloc(1, sizeof(orc_index));
     if (!ix) return NULL;
     ix->n = n; ix->d = d; ix->m = m; ix->L = L; ix->X = X;
     ix->per_subset = per_subset ? 1 : 0;
-    const int32_t rows = per_subset ? m * L : L;
+    ix->tables = tables;
+    const int32_t rows = (per_subset ? m * L : L) * tables;
     ix->A = (float *)malloc(sizeof(float) * (size_t)rows * (size_t)(d + 1));
     ix->key = (double *)malloc(sizeof(double) * (size_t)n);
     ix->rank = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
     ix->sid = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
     ix->keymax = (double *)malloc(sizeof(double) * (size_t)m);
     ix->U = (double *)malloc(sizeof(double) * (size_t)m);
-    ix->codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n);
+    ix->codes = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)n * (size_t)tables);
     ix->R = (int32_t *)malloc(sizeof(int32_t) * (size_t)m * (size_t)(L + 1));
     if (!ix->A || !ix->key || !ix->rank || !ix->sid || !ix->keymax || !ix->U ||
         !ix->codes || !ix->R) { orc_free(ix); return NULL; }
@@ -483,6 +531,13 @@ orc_index *orc_build3(const float *X, int64_t n, int32_t d, int32_t m, int32_t L
     return ix;
 }
 
+orc_index *orc_build3(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
+                      uint64_t seed, double eps, int32_t partition, int32_t per_subset,
+                      int32_t nthreads)
+{
+    return orc_build4(X, n, d, m, L, seed, eps, partition, per_subset, 1, nthreads);
+}
+
 orc_index *orc_build2(const float *X, int64_t n, int32_t d, int32_t m, int32_t L,
                       uint64_t seed, double eps, int32_t partition, int32_t nthreads)
 {
@@ -505,6 +560,7 @@ void orc_index_arrays(const orc_index *ix, float **A, double **key, int64_t **ra
 
 typedef struct {
     const orc_index *ix; const float *Q; int64_t q0, q1; int32_t k; int64_t T;
+    int32_t single_probe;  /* 1: multi-table single probe over every table */
     int64_t *ids; double *ips; int rc;
 } orc_query_job;
 
@@ -513,15 +569,18 @@ static void *orc_query_worker(void *arg)
     orc_query_job *jb = (orc_query_job *)arg;
     const orc_index *ix = jb->ix;
     int64_t *cand = (int64_t *)malloc(sizeof(int64_t) * (size_t)(ix->n > 0 ? ix->n : 1));
-    const int32_t ncodes = ix->per_subset ? ix->m : 1;
+    const int32_t ncodes = (ix->per_subset ? ix->m : 1) * (jb->single_probe ? ix->tables : 1);
     uint64_t *qc = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)ncodes);
     if (!cand || !qc) { free(cand); free(qc); jb->rc = -1; return NULL; }
     for (int64_t q = jb->q0; q < jb->q1; ++q) {
         const float *qv = jb->Q + q * (int64_t)ix->d;
         for (int32_t j = 0; j < ncodes; ++j)
             qc[j] = orc_query_code(ix->A + (int64_t)j * ix->L * (ix->d + 1), ix->L, ix->d, qv);
-        int64_t nc = orc_candidates2(ix->codes, ix->sid, ix->n, ix->L, ix->R, qc, ix->per_subset,
-                                     jb->T, cand, NULL);
+        int64_t nc = jb->single_probe
+                         ? orc_candidates_mt(ix->codes, ix->sid, ix->n, ix->m, ix->tables, qc,
+                                             ix->per_subset, jb->T, cand)
+                         : orc_candidates2(ix->codes, ix->sid, ix->n, ix->L, ix->R, qc, ix->per_subset,
+                                           jb->T, cand, NULL);
         if (nc < 0) { jb->rc = -1; break; }
         orc_topk(ix->X, ix->d, qv, cand, nc, jb->k, jb->ids + q * jb->k, jb->ips + q * jb->k);
     }
@@ -530,14 +589,15 @@ static void *orc_query_worker(void *arg)
     return NULL;
 }
 
-int orc_query(const orc_index *ix, const float *Q, int64_t nq, int32_t k, int64_t T,
-              int32_t nthreads, int64_t *ids, double *ips)
+int orc_query2(const orc_index *ix, const float *Q, int64_t nq, int32_t k, int64_t T,
+               int32_t single_probe, int32_t nthreads, int64_t *ids, double *ips)
 {
     if (nthreads < 1) nthreads = 1;
     pthread_t *th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)nthreads);
     orc_query_job *jb = (orc_query_job *)malloc(sizeof(orc_query_job) * (size_t)nthreads);
     for (int32_t t = 0; t < nthreads; ++t) {
         jb[t].ix = ix; jb[t].Q = Q; jb[t].k = k; jb[t].T = T; jb[t].ids = ids; jb[t].ips = ips;
+        jb[t].single_probe = single_probe ? 1 : 0;
         jb[t].q0 = nq * t / nthreads; jb[t].q1 = nq * (t + 1) / nthreads; jb[t].rc = 0;
         pthread_create(&th[t], NULL, orc_query_worker, &jb[t]);
     }
@@ -545,6 +605,12 @@ int orc_query(const orc_index *ix, const float *Q, int64_t nq, int32_t k, int64_
     for (int32_t t = 0; t < nthreads; ++t) { pthread_join(th[t], NULL); if (jb[t].rc) rc = -1; }
     free(th); free(jb);
     return rc;
+}
+
+int orc_query(const orc_index *ix, const float *Q, int64_t nq, int32_t k, int64_t T,
+              int32_t nthreads, int64_t *ids, double *ips)
+{
+    return orc_query2(ix, Q, nq, k, T, 0, nthreads, ids, ips);
 }
 
 /* Brute-force exact top-k MIPS over all items (Eq. 1), ground truth for recall. */

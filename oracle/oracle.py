@@ -84,6 +84,12 @@ def _declare(L):
     L.orc_build2.restype = P
     L.orc_build3.argtypes = [P, I64, I32, I32, I32, U64, F64, I32, I32, I32]
     L.orc_build3.restype = P
+    L.orc_build4.argtypes = [P, I64, I32, I32, I32, U64, F64, I32, I32, I32, I32]
+    L.orc_build4.restype = P
+    L.orc_candidates_mt.argtypes = [P, P, I64, I32, I32, P, I32, I64, P]
+    L.orc_candidates_mt.restype = I64
+    L.orc_query2.argtypes = [P, P, I64, I32, I64, I32, I32, P, P]
+    L.orc_query2.restype = C.c_int
     L.orc_free.argtypes = [P]
     L.orc_index_arrays.argtypes = [P] + [C.POINTER(P)] * 8
     L.orc_query.argtypes = [P, P, I64, I32, I64, I32, P, P]
@@ -260,15 +266,16 @@ class OracleIndex:
     PROJECTIONS = {"shared": 0, "per_subset": 1}
 
     def __init__(self, X, m: int, L: int, seed: int, eps: float = 0.0, threads: int = 1,
-                 partition: str = "percentile", projections: str = "shared"):
+                 partition: str = "percentile", projections: str = "shared", tables: int = 1):
         self.X = _f32(X)
         self.n, self.d = self.X.shape
         self.m, self.L, self.seed, self.eps = m, L, seed, eps
         self.partition = partition
         self.projections = projections
         self.per_subset = self.PROJECTIONS[projections] == 1
-        self._h = lib().orc_build3(_p(self.X), self.n, self.d, m, L, seed, eps,
-                                   self.PARTITIONS[partition], int(self.per_subset), threads)
+        self.tables = tables
+        self._h = lib().orc_build4(_p(self.X), self.n, self.d, m, L, seed, eps,
+                                   self.PARTITIONS[partition], int(self.per_subset), tables, threads)
         if not self._h:
             raise MemoryError("oracle build")
         ptrs = [P() for _ in range(8)]
@@ -279,14 +286,15 @@ class OracleIndex:
             return np.ctypeslib.as_array(buf).view(dt).copy()
 
         n, d, L_ = self.n, self.d, L
-        rows = m * L_ if self.per_subset else L_
+        rows = (m * L_ if self.per_subset else L_) * tables
         self.A = view(ptrs[0], C.c_float, rows * (d + 1), np.float32).reshape(rows, d + 1)
         self.key = view(ptrs[1], C.c_double, n, np.float64)
         self.rank = view(ptrs[2], C.c_int64, n, np.int64)
         self.sid = view(ptrs[3], C.c_int32, n, np.int32)
         self.keymax = view(ptrs[4], C.c_double, m, np.float64)
         self.U = view(ptrs[5], C.c_double, m, np.float64)
-        self.codes = view(ptrs[6], C.c_uint64, n, np.uint64)
+        self.codes_t = view(ptrs[6], C.c_uint64, n * tables, np.uint64).reshape(tables, n)
+        self.codes = self.codes_t[0].copy()
         self.R = view(ptrs[7], C.c_int32, m * (L_ + 1), np.int32).reshape(m, L_ + 1)
 
     def query(self, Q, k: int, T: int, threads: int = 1):
@@ -298,13 +306,41 @@ class OracleIndex:
             raise MemoryError("oracle query")
         return ids, ips
 
-    def query_code(self, q):
-        """The query code; with per-subset projections, one code per sub-dataset."""
-        if not self.per_subset:
-            return query_code(self.A, q)
+    def query_code(self, q, table: int = 0):
+        """The query code of one table; with per-subset projections, one code
+        per sub-dataset."""
         L = self.L
-        return np.array([query_code(self.A[j * L:(j + 1) * L], q) for j in range(self.m)],
-                        dtype=np.uint64)
+        P = self.m if self.per_subset else 1
+        blocks = [query_code(self.A[(table * P + b) * L:(table * P + b + 1) * L], q) for b in range(P)]
+        if not self.per_subset:
+            return blocks[0]
+        return np.array(blocks, dtype=np.uint64)
+
+    def query_codes_all(self, q) -> np.ndarray:
+        """Every table's codes, tables x P (P = m with per-subset projections, else 1)."""
+        P = self.m if self.per_subset else 1
+        return np.array([query_code(self.A[b * self.L:(b + 1) * self.L], q)
+                         for b in range(self.tables * P)], dtype=np.uint64).reshape(self.tables, P)
+
+    def candidates_single_probe(self, q, T: int) -> np.ndarray:
+        """Multi-table single probe: the probed items of query q, in probing order."""
+        qc = np.ascontiguousarray(self.query_codes_all(q).reshape(-1))
+        cand = np.empty(self.n, dtype=np.int64)
+        codes = np.ascontiguousarray(self.codes_t)
+        nc = lib().orc_candidates_mt(_p(codes), _p(self.sid), self.n, self.m, self.tables, _p(qc),
+                                     int(self.per_subset), T, _p(cand))
+        if nc < 0:
+            raise MemoryError("oracle candidates")
+        return cand[:nc]
+
+    def query_single_probe(self, Q, k: int, T: int, threads: int = 1):
+        Q = _f32(Q)
+        nq = Q.shape[0]
+        ids = np.empty((nq, k), dtype=np.int64)
+        ips = np.empty((nq, k), dtype=np.float64)
+        if lib().orc_query2(self._h, _p(Q), nq, k, T, 1, threads, _p(ids), _p(ips)):
+            raise MemoryError("oracle query")
+        return ids, ips
 
     def candidates(self, q, T: int):
         return candidates(self.codes, self.sid, self.L, self.R, self.query_code(q), T)

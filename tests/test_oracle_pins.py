@@ -634,3 +634,101 @@ def test_per_subset_full_budget_is_exact_mips():
     ids, _ = ix.query(Q, k=5, T=150)
     for qi, q in enumerate(Q):
         assert ids[qi].tolist() == _exact_topk(X, q, 5)
+
+
+# ---------------------------------------------------------------- multi-table single probe
+def _np_query_codes(A, q, L):
+    """Codes of P(q) = [q; 0] for each L-row block of A, by numpy (FP64 dot
+    products of float32 entries): independent of the oracle's loops."""
+    out = []
+    for b in range(A.shape[0] // L):
+        s = A[b * L:(b + 1) * L, :-1].astype(np.float64) @ q.astype(np.float64)
+        out.append(sum(1 << r for r in range(L) if s[r] > 0.0))
+    return out
+
+
+def test_multi_table_layout_extends_single_table():
+    """Table 0 of a multi-table index is the single-table index: the same
+    projection rows (the counter rule continues into the later blocks) and the
+    same item codes."""
+    X = make_items("lognormal", 1500, 12, seed=31, sigma=0.9)
+    for proj in ("shared", "per_subset"):
+        one = orc.OracleIndex(X, 5, 10, 77, projections=proj)
+        three = orc.OracleIndex(X, 5, 10, 77, projections=proj, tables=3)
+        rows = one.A.shape[0]
+        assert three.A.shape[0] == 3 * rows
+        assert np.array_equal(three.A[:rows], one.A)
+        assert np.array_equal(three.A, orc.projection(77, 3 * rows, 12))
+        assert np.array_equal(three.codes_t[0], one.codes)
+        assert not np.array_equal(three.codes_t[1], three.codes_t[0])
+
+
+@pytest.mark.parametrize("proj", ["shared", "per_subset"])
+def test_single_probe_candidates_by_independent_walk(proj):
+    """The probed items equal an independent computation: the first table
+    whose code for the item's sub-dataset equals the item's code, items
+    ordered by (that table, sub-dataset descending, index), cut at T."""
+    n, d, m, L, t = 3000, 10, 6, 6, 4
+    X = make_items("lognormal", n, d, seed=41, sigma=0.8)
+    Q = make_queries(6, d, seed=42)
+    ix = orc.OracleIndex(X, m, L, 5, projections=proj, tables=t)
+    P = m if proj == "per_subset" else 1
+    for q in Q:
+        qc = np.array(_np_query_codes(ix.A, q, L), dtype=np.uint64).reshape(t, P)
+        assert np.array_equal(qc, ix.query_codes_all(q).reshape(t, P))
+        f = np.full(n, -1)
+        for tb in range(t - 1, -1, -1):
+            hit = ix.codes_t[tb] == qc[tb, ix.sid if P > 1 else 0]
+            f[hit] = tb
+        members = np.nonzero(f >= 0)[0]
+        order = sorted(members.tolist(), key=lambda i: (f[i], -ix.sid[i], i))
+        for T in (1, 7, len(order) // 2 + 1, len(order), n):
+            got = ix.candidates_single_probe(q, T)
+            assert got.tolist() == order[:min(T, len(order))], T
+
+
+def test_single_probe_membership_rate_closed_form():
+    """Sign random projection (Eq. 4) with t independent tables: an item at
+    angle theta from the query shares the query's L-bit bucket in one table
+    with probability p^L, p = 1 - theta/pi, so it is probed with probability
+    1 - (1 - p^L)^t.  One item (m = 1, U = its norm), many seeds."""
+    d, L, t = 8, 3, 4
+    rng = np.random.Generator(np.random.PCG64(5))
+    q = rng.standard_normal(d)
+    q /= np.linalg.norm(q)
+    w = rng.standard_normal(d)
+    w -= (w @ q) * q
+    w /= np.linalg.norm(w)
+    theta = math.radians(60.0)
+    x = (math.cos(theta) * q + math.sin(theta) * w) * 3.0
+    X = x.astype(np.float32)[None, :]
+    Qf = q.astype(np.float32)
+    trials = 3000
+    hits = 0
+    for seed in range(trials):
+        ix = orc.OracleIndex(X, 1, L, 1000 + seed, tables=t)
+        hits += len(ix.candidates_single_probe(Qf, 1)) == 1
+        ix.close()
+    p = 1.0 - theta / math.pi
+    prob = 1.0 - (1.0 - p ** L) ** t
+    sd = math.sqrt(trials * prob * (1 - prob))
+    assert abs(hits - trials * prob) <= 5 * sd, (hits, trials * prob)
+    # one table would give p^L: far outside the band
+    assert abs(hits - trials * p ** L) > 10 * sd
+
+
+def test_single_probe_topk_is_exact_over_candidates():
+    n, d, m, L, t = 2500, 9, 4, 5, 3
+    X = make_items("lognormal", n, d, seed=51, sigma=1.0)
+    Q = make_queries(8, d, seed=52)
+    ix = orc.OracleIndex(X, m, L, 9, tables=t)
+    for T in (3, 40, n):
+        ids, ips = ix.query_single_probe(Q, 6, T, threads=2)
+        for qi, q in enumerate(Q):
+            cand = ix.candidates_single_probe(q, T)
+            exact = [sum(Fraction(float(a)) * Fraction(float(b)) for a, b in zip(q, X[i])) for i in cand]
+            order = sorted(range(len(cand)), key=lambda c: (-exact[c], cand[c]))[:6]
+            want = [int(cand[c]) for c in order] + [-1] * (6 - len(order))
+            assert ids[qi].tolist() == want, (T, qi)
+            fin = ids[qi] >= 0
+            assert np.all(np.isneginf(ips[qi][~fin]))
