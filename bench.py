@@ -4,12 +4,17 @@
 One step = the whole path on one batch of synthetic input already resident in
 HBM: index build (norm keys, radix sort, percentile partition, SimpleLSH
 transform + SRP hash, rank table) over all n items, then the multi-probe query
-(query hash, two-pass popcount scan with threshold, FP64 re-rank, top-k) of
-all nq queries at probe budget T.  value = nq / step time.
+(query hash, staged popcount scan, threshold, emission, re-rank, top-k) of all
+nq queries at probe budget T.  value = nq / query-phase time, measured with
+HIP events on the library's stream; the build is timed apart in the same steps
+and reported as items/s.
 
-The operating point T is the smallest power-of-two budget at which recall@k
-(measured on the first 1000 queries against exact MIPS) reaches 0.9; the
-stated budgets are timed as well and reported under "budgets".
+Default workload: n = 1e7 items of d = 128 with LogNormal(0, 1) norms,
+m = 128, L = 64, k = 100, T = 5e4 (0.5 % of n), 1e5 queries in batches of
+4096.  Forms: FP8 E4M3 hash + bfloat16 first-pass re-rank (exact FP64
+re-check) as the headline, the plain FP32 form on the same inputs for
+comparison; every form returns the same top-k.  The recall curve over
+power-of-two budgets shows where recall@10 >= 0.9 is first reached.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -191,47 +196,75 @@ def run_batching(args):
     print(json.dumps(out), flush=True)
 
 
+# Forms of the path timed on the same inputs.  Every form returns the same
+# top-k (the re-rank is exact in all of them); they differ in the precision of
+# the hash operands and of the rows the re-rank reads first.
+FORMS = {
+    "fp32": {"hash_storage": "fp32", "rerank_storage": "fp32",
+             "arith": {"hash": "fp32 mfma + fp64 sign fix-up", "scan": "u32 xor/popcount",
+                       "rerank": "fp64 (exact products of fp32 rows)"}},
+    "fp8_bf16": {"hash_storage": "fp8", "rerank_storage": "bf16",
+                 "arith": {"hash": "fp8 e4m3 mfma (fp32 accumulate), margin re-check in fp32 + fp64",
+                           "scan": "u32 xor/popcount",
+                           "rerank": "fp64 sums of bf16 rows (bounded), exact fp64 re-check from fp32 rows"}},
+    "bf16_hash": {"hash_storage": "bf16", "rerank_storage": "fp32",
+                  "arith": {"hash": "bf16 mfma (fp32 accumulate), margin re-check in fp32 + fp64",
+                            "scan": "u32 xor/popcount", "rerank": "fp64 (exact products of fp32 rows)"}},
+    "fp8_hash": {"hash_storage": "fp8", "rerank_storage": "fp32",
+                 "arith": {"hash": "fp8 e4m3 mfma (fp32 accumulate), margin re-check in fp32 + fp64",
+                           "scan": "u32 xor/popcount", "rerank": "fp64 (exact products of fp32 rows)"}},
+}
+# headline form first, then the forms it is compared with
+DEFAULT_FORMS = {"large": "fp8_bf16,fp32", "precision": "fp32,bf16_hash,fp8_hash", "mf": "fp32",
+                 "tiny": "fp32"}
+KERNELS = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table", "qhash",
+           "scan_hist", "threshold", "tie_locate", "scan_emit", "table_count", "table_emit",
+           "rerank", "rerank_lp", "screen_max", "screen", "rerank_exact"]
+BUILD_KERNELS = {"keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table"}
+INT_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes per clock x 2.4 GHz
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="mf", choices=["tiny", "mf", "precision", "large", "batching"])
-    ap.add_argument("--budget", type=int, default=None, help="time this T instead of the recall-0.9 point")
+    ap.add_argument("--workload", default="large", choices=["tiny", "mf", "precision", "large", "batching"])
+    ap.add_argument("--forms", default=None,
+                    help="comma list of forms to time, headline first (" + ", ".join(FORMS) + ")")
+    ap.add_argument("--budget", type=int, default=None,
+                    help="probe budget T of the timed steps (default: the workload's stated budget)")
+    ap.add_argument("--query-batch", type=int, default=None,
+                    help="queries per nrlsh_query call (default 4096 for large, else all at once)")
+    ap.add_argument("--extra-batches", default=None,
+                    help="comma list of other batch sizes timed for the headline form (large: 1024,256)")
     ap.add_argument("--recall-queries", type=int, default=1000)
-    ap.add_argument("--cpu-sample", type=int, default=256, help="queries the oracle baseline times")
+    ap.add_argument("--cpu-sample", type=int, default=None,
+                    help="queries the oracle baseline times (default 64 for large, 256 otherwise)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exact", action="store_true", help="skip the labelled T = n (exact MIPS) timing")
     ap.add_argument("--rerank", default="auto", choices=["auto", "gather", "screen", "screen_fp32", "screen_bf16x3"],
                     help="re-rank mode (all give identical results)")
-    ap.add_argument("--hash-storage", default="fp32", choices=["fp32", "bf16", "fp8"],
-                    help="precision form of the hash GEMM")
     ap.add_argument("--margin", default="rigorous",
                     help="'rigorous' or a relative margin for the low-precision hash")
-    ap.add_argument("--rerank-storage", default="fp32", choices=["fp32", "bf16"],
-                    help="rows the gather re-rank reads first (bf16: bounded, then exact)")
     ap.add_argument("--nq", type=int, default=None, help="override the number of queries")
-    ap.add_argument("--query-batch", type=int, default=0,
-                    help="queries per nrlsh_query call (0: all in one call)")
-    ap.add_argument("--no-budgets", action="store_true", help="skip timing the stated budgets")
-    ap.add_argument("--variants",
-                    default="eps:0.1,eps:0.2,eps:0.3,uniform,bits,uniform+bits,m:8,m:128,per_subset",
+    ap.add_argument("--variants", default="",
                     help="labelled variants timed after the headline, each at its own recall-0.9 "
                          "budget: eps:E (adjusted metric), uniform (norm ranges), bits (paper's "
                          "code-bit accounting), m:M (sub-datasets), per_subset (independent "
-                         "projections per sub-dataset); combine with '+'; '' for none")
+                         "projections per sub-dataset); combine with '+'")
     ap.add_argument("--probe", default="scan", choices=["scan", "table"],
-                    help="how the timed step finds the probed items: linear scan of the codes, "
+                    help="how the timed steps find the probed items: linear scan of the codes, "
                          "or the bucket tables (hash lookup, Section 3.3)")
     ap.add_argument("--probe-sweep", default="", metavar="L,...",
-                    help="after the headline, time query batches of 1, 16 and 256 queries at "
-                         "budgets 100, 1000, 10000 with both probes, on indexes of these code "
-                         "lengths (e.g. '16,32'); '' for none")
+                    help="time query batches of 1, 16 and 256 queries at budgets 100, 1000, 10000 "
+                         "with both probes, on indexes of these code lengths")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a MIB-MiB buffer 3 times before the steps (a kernel of known "
                          "traffic that scales hardware byte counters)")
     ap.add_argument("--no-sweep", action="store_true",
-                    help="skip the untimed recall sweep (needs --budget); used under a profiler so "
-                         "that only timed-step kernels are launched")
+                    help="skip the untimed recall sweep; used under a profiler so that only "
+                         "timed-step kernels are launched")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -253,9 +286,21 @@ def main():
     w = PRESETS[args.workload]()
     if args.nq is not None:
         w.nq = args.nq
+    large = args.workload == "large"
+    forms = [f.strip() for f in (args.forms or DEFAULT_FORMS[args.workload]).split(",") if f.strip()]
+    for f in forms:
+        if f not in FORMS:
+            ap.error(f"unknown form {f}")
+    qb = args.query_batch or (4096 if large else w.nq)
+    extra_batches = [int(v) for v in (args.extra_batches if args.extra_batches is not None
+                                      else ("1024,256" if large else "")).split(",") if v.strip()]
+    cpu_sample = args.cpu_sample or (64 if large else 256)
     margin = args.margin if args.margin == "rigorous" else float(args.margin)
+    T_op = args.budget or w.budgets[0]
+    Tq = min(T_op, w.n)
     torch.cuda.set_device(0)
-    log(f"workload {w.name}: n={w.n} d={w.d} m={w.m} L={w.L} nq={w.nq} k={w.k}")
+    log(f"workload {w.name}: n={w.n} d={w.d} m={w.m} L={w.L} nq={w.nq} k={w.k} T={T_op} "
+        f"batch={qb} forms={forms}")
     t0 = time.perf_counter()
     X = w.items()
     Q = w.queries()
@@ -265,40 +310,35 @@ def main():
     ids_buf = torch.empty((w.nq, w.k), dtype=torch.int64, device="cuda")
     ips_buf = torch.empty((w.nq, w.k), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-
-    # ---------------------------------------------------------------- recall sweep
-    if args.no_sweep and args.budget is None:
-        ap.error("--no-sweep needs --budget")
-    nrec = min(args.recall_queries, w.nq)
-    gt = ground_truth(Xd, Qd[:nrec], w.k) if not args.no_sweep else None
-    curve = {}
-    ix = nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage, margin=margin)
     norms = torch.linalg.vector_norm(Xd, dim=1).double()
     med = float(norms.median())
     norm_stats = {"max_over_median": float(norms.max()) / med,
                   "p999_over_median": float(torch.quantile(norms[:1_000_000].float(), 0.999)) / med}
     del norms
-    budgets_sweep = sorted({*(1 << e for e in range(8, 40) if (1 << e) < w.n), w.n, *w.budgets})
-    if args.no_sweep:
-        budgets_sweep = []
-    T_op = None
-    for T in budgets_sweep:
-        ids, _ = nr.nrlsh_query(ix, Qd[:nrec], w.k, T, rerank_storage=args.rerank_storage)
-        r = recall(ids.cpu().numpy(), gt)
-        curve[T] = r
-        log(f"recall@{w.k} T={T}: {r:.4f}")
-        if T_op is None and r >= 0.9 and (T & (T - 1) == 0 or T == w.n):
-            T_op = T
-    build_stats = ix.build_stats()
-    ix.close()
-    if args.budget is not None:
-        T_op = args.budget
-    if T_op is None:
-        T_op = w.n
+
+    # ------------------------------------------------------------ recall curve
+    # every form returns the same top-k, so one (plain) index serves the curve;
+    # recall@k against exact MIPS on the first `recall_queries` queries
+    nrec = min(args.recall_queries, w.nq)
+    curve, curve10 = {}, {}
+    gt = None
+    T_09 = None
+    if not args.no_sweep:
+        gt = ground_truth(Xd, Qd[:nrec], w.k)
+        sweep = sorted({*(1 << e for e in range(8, 21) if (1 << e) < w.n), w.n, *w.budgets, T_op})
+        with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed) as ix:
+            for T in sweep:
+                ids, _ = nr.nrlsh_query(ix, Qd[:nrec], w.k, T, rerank=args.rerank)
+                got = ids.cpu().numpy()
+                curve[T] = recall(got, gt)
+                curve10[T] = recall(got[:, :10], gt[:, :10])
+                log(f"recall@{w.k} T={T}: {curve[T]:.4f} (recall@10 {curve10[T]:.4f})")
+                if T_09 is None and curve10[T] >= 0.9:
+                    T_09 = T
 
     if args.copy_calibration > 0:
-        # a fill (writes B bytes) and an elementwise copy (reads B, writes B)
-        # of B = MIB MiB: kernels of known traffic for the byte counters
+        # an elementwise copy (reads B, writes B) of B = MIB MiB: a kernel of
+        # known traffic for the byte counters
         nel = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(nel, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -308,87 +348,243 @@ def main():
         log(f"copy calibration: fill + 3 elementwise copies of {args.copy_calibration} MiB")
         del src, dst
 
-    # ---------------------------------------------------------------- timed steps
-    qb = args.query_batch if args.query_batch > 0 else w.nq
+    # ------------------------------------------------------------ timed steps
+    # one step = the whole path: index build over all n items, then every
+    # query in batches of qb at budget T.  HIP events on the library's stream
+    # (torch's current stream, which the library is given) split the step
+    # into the build and the query phase.
+    stream = torch.cuda.current_stream()
 
-    def step(T, eps=0.0):
-        with nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=args.hash_storage,
-                            margin=margin, eps=eps, bucket_tables=args.probe == "table") as sx:
-            for b0 in range(0, w.nq, qb):
-                b1 = min(w.nq, b0 + qb)
-                nr.nrlsh_query(sx, Qd[b0:b1], w.k, T, out=(ids_buf[b0:b1], ips_buf[b0:b1]),
-                               rerank=args.rerank, rerank_storage=args.rerank_storage,
-                               probe=args.probe)
-
-    def timed(T, steps, warmup, profile, eps=0.0):
-        for i in range(warmup):
-            step(T, eps)
-            log(f"  T={T} warmup {i + 1}/{warmup} done")
+    def one_step(form, T, batch, nq):
+        cfg = FORMS[form]
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        ix = nr.nrlsh_build(Xd, w.m, w.L, w.index_seed, hash_storage=cfg["hash_storage"], margin=margin,
+                            bucket_tables=args.probe == "table")
+        e1.record(stream)
+        for b0 in range(0, nq, batch):
+            b1 = min(nq, b0 + batch)
+            nr.nrlsh_query(ix, Qd[b0:b1], w.k, T, out=(ids_buf[b0:b1], ips_buf[b0:b1]), rerank=args.rerank,
+                           rerank_storage=cfg["rerank_storage"], probe=args.probe)
+        e2.record(stream)
         torch.cuda.synchronize()
+        bst = ix.build_stats()
+        ix.close()
+        return e0.elapsed_time(e1), e1.elapsed_time(e2), bst
+
+    def timed(form, T, batch, nq, steps, warmup, profile=False):
+        for i in range(warmup):
+            one_step(form, T, batch, nq)
+            log(f"  [{form}] T={T} batch={batch} warmup {i + 1}/{warmup} done")
         nr.nrlsh_profile_reset()
         nr.nrlsh_profile_enable(profile)
-        t = time.perf_counter()
+        b_ms, q_ms, walls = [], [], []
+        bst = None
         for i in range(steps):
-            step(T, eps)
-            log(f"  T={T} step {i + 1}/{steps} done ({time.perf_counter() - t:.2f}s)")
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t
+            t = time.perf_counter()
+            b, q, bst = one_step(form, T, batch, nq)
+            walls.append(time.perf_counter() - t)
+            b_ms.append(b)
+            q_ms.append(q)
+            log(f"  [{form}] T={T} batch={batch} step {i + 1}/{steps}: build {b:.2f} ms, query {q:.2f} ms")
         nr.nrlsh_profile_enable(False)
-        return el / steps
-
-    names = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table", "qhash",
-             "scan_hist", "threshold", "tie_locate", "scan_emit", "table_count", "table_emit",
-             "rerank", "rerank_lp", "screen_max", "screen", "rerank_exact"]
-    # unprofiled timing for the headline, profiled run for the per-kernel split
-    s_step = timed(T_op, args.steps, args.warmup, False)
-    qstats = nr.nrlsh_get_query_stats()
-    ids_op = ids_buf.clone()
-    timed(T_op, max(2, args.steps // 2), 0, True)
-    kern = {}
-    for nm in names:
-        ms, cnt = nr.nrlsh_profile_get(nm)
-        if cnt:
-            kern[nm] = {"avg_ms": ms / cnt, "launches_per_step": cnt / max(2, args.steps // 2)}
-    log(f"T={T_op}: {s_step * 1e3:.2f} ms/step; kernels {json.dumps(kern)}")
-
-    # at T >= n every item is probed, so the library runs no query hash, scan
-    # or threshold; T = n - 1 probes all but one item and runs every step of
-    # the path, which shows what that shortcut saves
-    full_path = None
-    if T_op >= w.n and w.n > 1 and not args.no_budgets:
-        st = timed(w.n - 1, max(2, args.steps // 2), 1, True)
-        fk = {}
-        for nm in names:
-            ms, cnt = nr.nrlsh_profile_get(nm)
-            if cnt:
-                fk[nm] = round(ms / max(2, args.steps // 2), 3)
-        full_path = {"T": w.n - 1, "ms_per_step": st * 1e3, "qps": w.nq / st, "kernel_ms_per_step": fk}
-        log(f"full path T={w.n - 1}: {st * 1e3:.2f} ms/step")
-
-    budgets = []
-    if not args.no_budgets:
-        for T in w.budgets:
-            st = timed(T, max(2, args.steps // 2), 1, True)
-            bk = {}
-            for nm in names:
+        kern = {}
+        if profile:
+            for nm in KERNELS:
                 ms, cnt = nr.nrlsh_profile_get(nm)
                 if cnt:
-                    bk[nm] = round(ms / max(2, args.steps // 2), 3)
-            budgets.append({"T": T, "frac_of_n": T / w.n, "qps": w.nq / st, "ms_per_step": st * 1e3,
-                            "recall": curve.get(T), "query_stats": nr.nrlsh_get_query_stats(),
-                            "kernel_ms_per_step": bk})
-            log(f"budget T={T}: {st * 1e3:.2f} ms/step recall {curve.get(T)}")
+                    kern[nm] = {"avg_ms": ms / cnt, "launches_per_step": cnt / steps,
+                                "ms_per_step": ms / steps}
+        return {"build_ms": sum(b_ms) / steps, "query_ms": sum(q_ms) / steps,
+                "wall_ms": sum(walls) / steps * 1e3, "qps": nq / (sum(q_ms) / steps * 1e-3),
+                "build_stats": bst, "kernels": kern, "query_stats": nr.nrlsh_get_query_stats()}
 
-    # ---------------------------------------------------------------- labelled variants
-    # the same step under the paper's other settings, each at its own
-    # recall-0.9 budget: the adjusted metric s_hat = U_j cos[pi (1 - eps)(1 - l/L)]
-    # (Section 3.3), uniform norm ranges (Section 5), the paper's code-bit
-    # accounting (ceil(log2 m) of the L bits spent on the sub-dataset id,
-    # Section 4), other sub-dataset counts (Figure 3b's sweep) and
-    # independent projections per sub-dataset (Algorithm 1 read literally)
-    variants = []
-    spec = [v.strip() for v in args.variants.split(",") if v.strip()] if not args.no_sweep else []
-    for v in spec:
+    results = {}
+    head = forms[0]
+    for form in forms:
+        r = timed(form, T_op, qb, w.nq, args.steps, args.warmup)
+        if form == head:
+            ids_op = ids_buf.clone()
+            ips_op = ips_buf.clone()
+        else:
+            same = bool(torch.equal(ids_buf, ids_op) and torch.equal(ips_buf, ips_op))
+            r["identical_to_" + head] = same
+            log(f"[{form}] identical top-k to {head}: {same}")
+        # per-kernel split from a separate profiled run (event pairs per launch)
+        pr = timed(form, T_op, qb, w.nq, max(1, args.steps // 2), 0, profile=True)
+        r["kernels"] = pr["kernels"]
+        r["hashed_items_per_s"] = (w.n / (pr["kernels"]["hash"]["avg_ms"] * 1e-3)
+                                   if "hash" in pr["kernels"] else None)
+        r["built_items_per_s"] = w.n / (r["build_ms"] * 1e-3)
+        results[form] = r
+        log(f"[{form}] T={T_op}: query {r['query_ms']:.2f} ms ({r['qps']:.4g} q/s), build "
+            f"{r['build_ms']:.2f} ms; kernels {json.dumps({k: round(v['ms_per_step'], 3) for k, v in r['kernels'].items()})}")
+    hr = results[head]
+
+    batches = []
+    for b in extra_batches:
+        r = timed(head, T_op, b, w.nq, 1, 1)
+        batches.append({"batch": b, "query_ms": r["query_ms"], "qps": r["qps"]})
+        log(f"[{head}] batch {b}: {r['qps']:.4g} q/s")
+
+    # exact MIPS: a budget covering every item (the path then skips the scan)
+    exact = None
+    if not args.no_exact and T_op < w.n:
+        ne = min(w.nq, 16384)
+        r = timed("fp32", w.n, min(qb, ne) if large else ne, ne, 1, 1)
+        exact = {"T": w.n, "nq": ne, "query_ms": r["query_ms"], "qps": r["qps"], "recall@k": 1.0,
+                 "label": "exact MIPS (T = n probes every item), plain FP32 index"}
+        log(f"exact MIPS T=n: {r['qps']:.4g} q/s")
+
+    # ------------------------------------------------------------ labelled variants
+    variants = run_variants(args, w, Xd, Qd, gt, nrec, margin, ids_buf, ips_buf) if args.variants else []
+    probe_sweep = run_probe_sweep(args, w, Xd, Qd) if args.probe_sweep else []
+
+    # ------------------------------------------------------------ roofline
+    kern = hr["kernels"]
+    qkern = {k: v for k, v in kern.items() if k not in BUILD_KERNELS}
+    dom = max(qkern, key=lambda nm: qkern[nm]["ms_per_step"]) if qkern else None
+    roof = roofline(dom, kern, w, Tq, qb, hr["query_stats"])
+    scan = None
+    if "scan_hist" in kern:
+        W = (w.L + 31) // 32
+        st = hr["query_stats"]
+        pairs = st.get("scan_pairs") or 0
+        # the stats are the last query call's (one batch of qb queries)
+        per = kern["scan_hist"]
+        scan = {"pairs_counted_last_batch": pairs,
+                "pairs_all_last_batch": min(qb, w.nq) * w.n,
+                "counted_fraction": pairs / (min(qb, w.nq) * w.n),
+                "pass1_ms_per_step": per["ms_per_step"],
+                "pass1_pairs_per_s": (pairs * (w.nq / min(qb, w.nq))) / (per["ms_per_step"] * 1e-3) if pairs else None,
+                "int_ops_per_pair": 2 * W + 1,
+                "pass2_ms_per_step": kern.get("scan_emit", {}).get("ms_per_step"),
+                "code_stream_GBps": (w.nq * w.n * 4 * W) / (per["ms_per_step"] * 1e-3) / 1e9}
+        if scan["pass1_pairs_per_s"]:
+            scan["int_valu_tops"] = scan["pass1_pairs_per_s"] * (2 * W + 1) / 1e12
+            scan["int_valu_frac"] = scan["int_valu_tops"] / INT_VALU_PEAK_TOPS
+
+    # ------------------------------------------------------------ CPU oracle baseline
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle.oracle as orc
+        threads = max(1, min(16, os.cpu_count() or 1))
+        S = min(cpu_sample, w.nq)
+        t = time.perf_counter()
+        oix = orc.OracleIndex(X, w.m, w.L, w.index_seed, threads=threads)
+        tb = time.perf_counter() - t
+        t = time.perf_counter()
+        oids, oips = oix.query(Q[:S], w.k, T_op, threads=threads)
+        tq = time.perf_counter() - t
+        oix.close()
+        gpu_ids = ids_op[:S].cpu().numpy()
+        gpu_ips = ips_op[:S].cpu().numpy()
+        cpu = {"value": S / tq, "unit": "queries/s", "cores": threads, "kind": "oracle",
+               "sample": f"{S} of {w.nq} queries at T={T_op} on {threads} threads ({tq:.1f}s), "
+                         f"after a full oracle build of the {w.n} items ({tb:.1f}s, not counted)",
+               "build_s": tb, "build_items_per_s": w.n / tb, "query_s_per_query": tq / S,
+               "gpu_topk_equals_oracle_on_sample": bool(np.array_equal(gpu_ids, oids)),
+               "gpu_ips_equal_oracle_on_sample": bool(np.array_equal(gpu_ips, oips.astype(np.float32)))}
+        log(f"cpu baseline {json.dumps(cpu)}")
+
+    rec_T = curve.get(T_op)
+    out = {
+        "metric": "queries/sec at recall@10>=0.9 (plain FP32 vs BF16/FP8); scan+rerank HBM GB/s",
+        "value": hr["qps"],
+        "unit": "queries/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": hr["wall_ms"],
+        "query_ms_per_step": hr["query_ms"],
+        "build_ms_per_step": hr["build_ms"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32+f64",
+        "arith": FORMS[head]["arith"],
+        "data": "synthetic",
+        "config": {**w.describe(), "T": T_op, "form": head, "query_batch": qb,
+                   "op_point": ("stated budget; recall@10 >= 0.9 is first reached at T = %s" % T_09)
+                   if T_09 is not None else "stated budget (recall@10 >= 0.9 not reached by the sweep)",
+                   "rerank": args.rerank, "margin": args.margin, "probe": args.probe,
+                   "parallelism": "single GPU"},
+        "value_definition": "queries / query-phase time (HIP events on the library stream, inputs "
+                            "resident in HBM); the index build of every step is timed apart "
+                            "(build_ms_per_step, hashed_items_per_s)",
+        "recall_at_T": rec_T,
+        "recall10_at_T": curve10.get(T_op),
+        "recall_0_9_budget": T_09,
+        "recall_curve": {str(k): v for k, v in curve.items()},
+        "recall10_curve": {str(k): v for k, v in curve10.items()},
+        "forms": {f: {kk: vv for kk, vv in r.items() if kk != "kernels"} for f, r in results.items()},
+        "kernels": kern,
+        "hashed_items_per_s": hr["hashed_items_per_s"],
+        "built_items_per_s": hr["built_items_per_s"],
+        "other_batches": batches,
+        "exact_mips": exact,
+        "norm_stats": norm_stats,
+        "roofline": roof,
+        "scan": scan,
+        "variants": variants,
+        "probe_sweep": probe_sweep,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def roofline(dom, kern, w, Tq, qb, qstats):
+    """Roofline of the dominant query kernel from its algorithmic work per
+    launch and its HIP-event launch time."""
+    if dom is None:
+        return None
+    per = kern[dom]
+    launches = per["launches_per_step"]
+    nq_launch = w.nq / launches
+    W = (w.L + 31) // 32
+    if dom in ("rerank", "rerank_lp"):
+        # per probed item: its row (4d FP32 / 2d bf16 bytes), its stored
+        # position and original id (8); the bf16 pass also reads the key (8)
+        row = 4 * w.d if dom == "rerank" else 2 * w.d + 8
+        bytes_launch = nq_launch * Tq * (row + 8)
+        achieved = bytes_launch / (per["avg_ms"] * 1e-3) / 1e9
+        kname = {"rerank": "k_rerank<2, false>", "rerank_lp": "k_rerank<2, true>"}[dom]
+        rec = traffic_record(kname, w.name, Tq)
+        return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS,
+                "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+                "traffic_source": rec, "bytes_per_launch": bytes_launch, "unit_work": "probed item",
+                "bytes_per_unit": row + 8, "units_per_launch": nq_launch * Tq, "dominant_kernel": dom}
+    if dom in ("scan_hist", "scan_emit"):
+        pairs = (qstats.get("scan_pairs") or 0) if dom == "scan_hist" else None
+        if not pairs:
+            pairs = nq_launch * w.n
+        ops = pairs * (2 * W + 1)
+        achieved = ops / (per["avg_ms"] * 1e-3) / 1e12
+        kname = "k_scan_hist_s<%d>" % W if dom == "scan_hist" else "k_scan_emit_s<%d>" % W
+        return {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK_TOPS,
+                "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK_TOPS, "traffic": None,
+                "ops_per_launch": ops, "unit_work": "(query, item) pair", "ops_per_unit": 2 * W + 1,
+                "dominant_kernel": dom}
+    if dom == "screen":
+        pairs = (qstats.get("screen_pairs") or 0) / max(1, qstats.get("screen_passes") or 1)
+        flops = 2.0 * w.d * pairs
+        achieved = flops / (per["avg_ms"] * 1e-3) / 1e12
+        return {"kernel": "k_screen1<%d>" % W, "bound": "mfma", "achieved": achieved,
+                "peak": BF16_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFS,
+                "traffic": None, "flops_per_launch": flops, "unit_work": "evaluated pair",
+                "dominant_kernel": dom}
+    return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+            "traffic": None, "dominant_kernel": dom}
+
+
+def run_variants(args, w, Xd, Qd, gt, nrec, margin, ids_buf, ips_buf):
+    """The same step under the paper's other settings, each at its own
+    recall-0.9 budget: the adjusted metric (Section 3.3), uniform norm ranges
+    (Section 5), the paper's code-bit accounting (Section 4), other sub-dataset
+    counts (Figure 3b's sweep) and independent projections per sub-dataset."""
+    import torch
+
+    import paper_1809_08782_amd as nr
+    out = []
+    budgets_sweep = sorted({*(1 << e for e in range(8, 40) if (1 << e) < w.n), w.n, *w.budgets})
+    for v in [v.strip() for v in args.variants.split(",") if v.strip()]:
         cfg = {"label": v, "eps": 0.0, "partition": "percentile", "m": w.m, "L": w.L,
                "projections": "shared"}
         for part in v.split("+"):
@@ -401,48 +597,42 @@ def main():
             elif part == "per_subset":
                 cfg["projections"] = "per_subset"
             elif part != "bits":
-                ap.error(f"unknown variant {v}")
-        if "bits" in v.split("+"):  # after m is known
+                raise SystemExit(f"unknown variant {v}")
+        if "bits" in v.split("+"):
             cfg["L"] = w.L - (math.ceil(math.log2(cfg["m"])) if cfg["m"] > 1 else 0)
-        if cfg["projections"] != "shared" and args.hash_storage != "fp32":
-            log(f"variant {v} skipped: per-subset projections need the FP32 hash")
-            continue
-        ex = nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
-                            margin=margin, eps=cfg["eps"], partition=cfg["partition"],
-                            projections=cfg["projections"])
+        ex = nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, margin=margin, eps=cfg["eps"],
+                            partition=cfg["partition"], projections=cfg["projections"])
         vcurve, vT = {}, None
         for T in budgets_sweep:
             ids, _ = nr.nrlsh_query(ex, Qd[:nrec], w.k, T)
             r = recall(ids.cpu().numpy(), gt)
             vcurve[str(T)] = r
-            if vT is None and r >= 0.9 and (T & (T - 1) == 0 or T == w.n):
+            if vT is None and r >= 0.9:
                 vT = T
-        ex.close()
         vT = vT or w.n
-
-        def vstep(T, cfg=cfg):
-            with nr.nrlsh_build(Xd, cfg["m"], cfg["L"], w.index_seed, hash_storage=args.hash_storage,
-                                margin=margin, eps=cfg["eps"], partition=cfg["partition"],
-                                projections=cfg["projections"]) as sx:
-                nr.nrlsh_query(sx, Qd, w.k, T, out=(ids_buf, ips_buf), rerank=args.rerank,
-                               rerank_storage=args.rerank_storage)
-        vstep(vT)
+        nr.nrlsh_query(ex, Qd, w.k, vT, out=(ids_buf, ips_buf))
         torch.cuda.synchronize()
         t = time.perf_counter()
         reps = max(2, args.steps // 2)
         for _ in range(reps):
-            vstep(vT)
+            nr.nrlsh_query(ex, Qd, w.k, vT, out=(ids_buf, ips_buf))
         torch.cuda.synchronize()
         est = (time.perf_counter() - t) / reps
-        variants.append({**cfg, "T": vT, "frac_of_n": vT / w.n, "recall_at_T": vcurve.get(str(vT)),
-                         "qps": w.nq / est, "ms_per_step": est * 1e3, "recall_curve": vcurve})
+        ex.close()
+        out.append({**cfg, "T": vT, "frac_of_n": vT / w.n, "recall_at_T": vcurve.get(str(vT)),
+                    "qps_query_only": w.nq / est, "query_ms": est * 1e3, "recall_curve": vcurve})
         log(f"variant {v}: m={cfg['m']} L={cfg['L']} T_op={vT} recall {vcurve.get(str(vT))} "
-            f"{est * 1e3:.2f} ms/step")
+            f"query {est * 1e3:.2f} ms")
+    return out
 
-    # ---------------------------------------------------------------- probe sweep
-    # query-only latency of the two probes (same probed set, same results):
-    # small batches and budgets are where the bucket tables can skip the scan
-    probe_sweep = []
+
+def run_probe_sweep(args, w, Xd, Qd):
+    """Query-only latency of the two probes (same probed set, same results):
+    small batches and budgets are where the bucket tables can skip the scan."""
+    import torch
+
+    import paper_1809_08782_amd as nr
+    out = []
     for Ls in [int(v) for v in args.probe_sweep.split(",") if v.strip()]:
         with nr.nrlsh_build(Xd, w.m, Ls, w.index_seed, bucket_tables=True) as tx:
             for nqs in (1, 16, 256):
@@ -465,126 +655,10 @@ def main():
                             row["walked_per_query"] = st["table_walked"] / nqs
                             row["same_result"] = bool(torch.equal(ids, ref))
                         ref = ids
-                    probe_sweep.append(row)
+                    out.append(row)
                     log(f"probe L={Ls} nq={nqs} T={T}: scan {row['scan_ms']:.3f} ms, table "
-                        f"{row['table_ms']:.3f} ms ({row['lookups_per_query']:.0f} lookups, "
-                        f"{row['walked_per_query']:.0f} codes walked per query)")
-
-    # ---------------------------------------------------------------- roofline
-    Tq = min(T_op, w.n)
-    dom = max(kern, key=lambda nm: kern[nm]["avg_ms"] * kern[nm]["launches_per_step"]) if kern else None
-    roof = None
-    if dom == "screen":
-        # algorithmic work of one screen launch: the inner products of the
-        # pairs it evaluates, 2d flop each on the bf16 (or FP32) matrix cores
-        # (the bf16x3 screen forms each one from three bfloat16 products,
-        # hi*hi + hi*lo + lo*hi, 3 x 2d flop).  The keep pass skips chunks no
-        # query of a tile can keep (norm bound), so its pairs are the ones the
-        # library reports evaluating, not all (queries x T) probed pairs.
-        launches = kern["screen"]["launches_per_step"]
-        probed_pairs = (w.nq / launches) * Tq
-        passes = max(1, qstats.get("screen_passes") or 1)
-        pairs = qstats.get("screen_pairs") / passes if qstats.get("screen_pairs") else probed_pairs
-        smode = qstats.get("mode")
-        products = {"screen": 1, "screen_bf16x3": 3}.get(smode, 1)
-        b16 = smode in ("screen", "screen_bf16x3")
-        flops = 2.0 * products * w.d * pairs
-        peak = BF16_MFMA_PEAK_TFS if b16 else FP32_MFMA_PEAK_TFS
-        achieved = flops / (kern["screen"]["avg_ms"] * 1e-3) / 1e12
-        # the kernel the library launches: budgets covering every item take
-        # the variants that read no codes (128-query tiles for rows of at
-        # least 256 coordinates); otherwise one or two code words per item
-        dp = (w.d + 7) // 8 * 8
-        if Tq >= w.n and smode in ("screen", "screen_bf16x3"):
-            kname = ("k_screen_b128" if dp >= 256 else "k_screen1<0>") if smode == "screen" \
-                else "k_screen3<0, false, true>"
-        else:
-            kname = {"screen": "k_screen1<1>",
-                     "screen_bf16x3": "k_screen3<1, false, true>"}.get(smode, "k_screen<1, false>")
-            if w.L > 32:
-                kname = kname.replace("<1", "<2")
-        rec = traffic_record(kname, w.name, Tq)
-        roof = {"kernel": kname, "bound": "mfma",
-                "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
-                "traffic_source": rec, "mfma_dtype": "bf16" if b16 else "f32",
-                "bf16_products_per_pair": products if b16 else None,
-                "flops_per_launch": flops, "pairs_per_launch": pairs,
-                "probed_pairs_per_launch": probed_pairs,
-                "fp32_equivalent_tflops": 2.0 * w.d * pairs / (kern["screen"]["avg_ms"] * 1e-3) / 1e12,
-                "dominant_kernel": dom}
-    elif dom in ("rerank", "rerank_exact", "rerank_lp"):
-        # algorithmic bytes per probed item: its row (4d), stored position and id (8)
-        launches = kern[dom]["launches_per_step"]
-        row_bytes = (2 if dom == "rerank_lp" else 4) * w.d
-        per_launch_bytes = (w.nq / launches) * Tq * (row_bytes + 8)
-        achieved = per_launch_bytes / (kern[dom]["avg_ms"] * 1e-3) / 1e9
-        roof = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                "bytes_per_launch": per_launch_bytes, "dominant_kernel": dom}
-
-    # scan pass 1: effective code-stream rate (every query reads every code
-    # once: nq n 4W bytes) and (query, item) pairs per second
-    scan = None
-    if "scan_hist" in kern:
-        W = (w.L + 31) // 32
-        per = kern["scan_hist"]
-        qpl = w.nq / per["launches_per_step"]
-        scan = {"pairs_per_s": qpl * w.n / (per["avg_ms"] * 1e-3),
-                "code_stream_GBps": qpl * w.n * 4 * W / (per["avg_ms"] * 1e-3) / 1e9}
-
-    # ---------------------------------------------------------------- CPU oracle baseline
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle.oracle as orc
-        threads = max(1, min(16, os.cpu_count() or 1))
-        S = min(args.cpu_sample, w.nq)
-        t = time.perf_counter()
-        oix = orc.OracleIndex(X, w.m, w.L, w.index_seed, threads=threads)
-        tb = time.perf_counter() - t
-        t = time.perf_counter()
-        oids, _ = oix.query(Q[:S], w.k, T_op, threads=threads)
-        tq = time.perf_counter() - t
-        est = tb + tq / S * w.nq
-        gpu_ids = ids_op[:S].cpu().numpy()
-        cpu = {"value": w.nq / est, "unit": "queries/s", "cores": threads, "kind": "oracle",
-               "sample": f"full oracle build of all {w.n} items ({tb:.1f}s) + {S} of {w.nq} "
-                         f"queries at T={T_op} ({tq:.1f}s); step time extrapolated to {w.nq} queries",
-               "build_s": tb, "query_s_per_query": tq / S,
-               "gpu_topk_equals_oracle_on_sample": bool(np.array_equal(gpu_ids, oids))}
-        log(f"cpu baseline {json.dumps(cpu)}")
-
-    out = {
-        "metric": "queries/sec at recall@10>=0.9 (plain FP32 vs BF16/FP8); scan+rerank HBM GB/s",
-        "value": w.nq / s_step,
-        "unit": "queries/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": s_step * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32",
-        "arith": {"hash": "fp32 mfma + fp64 sign fix-up", "scan": "u32", "rerank": "f64"},
-        "data": "synthetic",
-        "config": {**w.describe(), "T": T_op, "op_point": "smallest power-of-two T with recall>=0.9"
-                   if args.budget is None else "fixed T", "parallelism": "single GPU",
-                   "hash_storage": args.hash_storage, "margin": args.margin,
-                   "rerank": args.rerank, "rerank_storage": args.rerank_storage,
-                   "probe": args.probe, "query_batch": qb},
-        "recall_at_T": curve.get(T_op),
-        "recall_curve": {str(k): v for k, v in curve.items()},
-        "budgets": budgets,
-        "full_path_at_n_minus_1": full_path,
-        "kernels": kern,
-        "hashed_items_per_s": (w.n / (kern["hash"]["avg_ms"] * 1e-3)) if "hash" in kern else None,
-        "build_stats": build_stats,
-        "query_stats": qstats,
-        "norm_stats": norm_stats,
-        "roofline": roof,
-        "scan": scan,
-        "variants": variants,
-        "probe_sweep": probe_sweep,
-        "cpu_baseline": cpu,
-    }
-    print(json.dumps(out), flush=True)
+                        f"{row['table_ms']:.3f} ms")
+    return out
 
 
 if __name__ == "__main__":

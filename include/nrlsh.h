@@ -25,9 +25,14 @@
  *   - Item / query / output pointers are HOST pointers unless an _ex call is
  *     given opts->device_ptrs = 1, in which case they are device pointers on
  *     the current HIP device (e.g. a torch tensor's data_ptr()).
- *   - Every call is synchronous: when it returns, outputs are written and
- *     the caller may reuse or free its inputs.  nrlsh_build copies the items;
- *     the index owns all of its device memory until nrlsh_free.
+ *   - When a call returns, its outputs are written and the caller may reuse
+ *     or free its inputs.  nrlsh_build copies the items and returns once the
+ *     last read of them is done; the rest of the index's device work (the
+ *     hash and its FP64 fix-up) may still be queued on the library's stream,
+ *     and every later call on the index is ordered after it (queries wait
+ *     on the index's ready event on their stream, inspection calls and
+ *     nrlsh_free on the host).  The index owns all of its device memory
+ *     until nrlsh_free.
  *   - Ids are 0-based original item indices.  Results are ordered by
  *     (inner product descending, id ascending).  When fewer than k items are
  *     probed (min(T, n) < k) the tail is padded with id -1 and ip -INFINITY.
@@ -136,7 +141,13 @@ typedef struct nrlsh_build_opts {
     int32_t bucket_tables; /* 1: also build the bucket tables that NRLSH_PROBE_TABLE
                               queries read (about 16 n bytes more; read when
                               struct_size covers it) */
-    int32_t pad;
+    int32_t hash_tables;  /* independent hash tables t, 1 <= t <= 8 (0 = 1): table tau
+                             hashes with its own projection block(s), rows
+                             (tau P + b) L .. + L - 1 of one (t P L) x (d+1) matrix
+                             drawn by the counter rule above (P = 1, or m with
+                             per-subset projections); table 0 is the index the
+                             multi-probe query reads, NRLSH_PROBE_SINGLE reads all
+                             (FP32 hash only; 4 n W t bytes of codes) */
 } nrlsh_build_opts;
 
 nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m, int32_t L,
@@ -165,9 +176,10 @@ nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq
  *   SCREEN:        queries are tiled 64 at a time against chunks of stored rows on
  *                  the bf16 matrix cores with q and x rounded to bfloat16 (one
  *                  product per pair); pairs that are probed and whose inner
- *                  product (with a rigorous bound of the rounding,
- *                  (2^-8 + 2^-17 + 2.1 gamma_d) ||q|| ||x||) can still reach a
- *                  lower bound of the k-th best are re-ranked exactly in FP64.
+ *                  product (with a rigorous bound of the rounding of both
+ *                  operands and the FP32 sum, (2^-7 + 2^-16 + 2.1 gamma_d)
+ *                  ||q|| ||x||) can still reach a lower bound of the k-th
+ *                  best are re-ranked exactly in FP64.
  *   SCREEN_FP32:   the same screen with FP32 matrix-core products.
  *   SCREEN_BF16X3: the same screen with a bfloat16 hi/lo split (three bf16
  *                  products per pair; tighter bounds, three times the work).
@@ -181,9 +193,13 @@ typedef enum {
     NRLSH_RERANK_SCREEN_BF16X3 = 4
 } nrlsh_rerank_mode;
 
-/* How a query finds its probed items (both give the same probed set).
+/* How a query finds its probed items (SCAN and TABLE give the same probed set).
  *   SCAN:  every item code of the index is compared with the query code (two
- *          linear passes: per-bucket counts, then emission).
+ *          linear passes: per-bucket counts, then emission).  The first pass
+ *          visits the sub-datasets in descending U_j and stops for a 64-query
+ *          tile once every query's threshold bucket is known (no bucket of a
+ *          sub-dataset not yet visited can rank before the first bucket
+ *          (j, L) of the next one).
  *   TABLE: the "standard hash lookup" of Section 3.3: buckets (j, l) are taken
  *          in probing order from a table of each sub-dataset's distinct codes
  *          (the index must be built with bucket_tables = 1).  The codes at
@@ -192,8 +208,18 @@ typedef enum {
  *          of distinct codes; then j's distinct codes are counted by distance
  *          once.  Work grows with the buckets probed, not with n; it pays
  *          where few buckets hold the budget (short codes, small T).  Goes with
- *          the GATHER re-rank (AUTO selects it; a SCREEN mode is rejected). */
-typedef enum { NRLSH_PROBE_SCAN = 0, NRLSH_PROBE_TABLE = 1 } nrlsh_probe_mode;
+ *          the GATHER re-rank (AUTO selects it; a SCREEN mode is rejected).
+ *   SINGLE: multi-table single probe, the alternative to the single-table
+ *          multi-probe that Section 4 names: in each of the index's
+ *          hash_tables tables only the bucket of the query's own code is
+ *          probed, in every sub-dataset (l = L).  With f(i) the first table
+ *          whose probed bucket holds item i, the probed set is the first
+ *          min(T, |C|) items of C = {i : f(i) exists} in the order (f asc,
+ *          sub-dataset desc, id asc): tables are probed in order until the
+ *          budget, the table where it runs out taken higher-norm sub-datasets
+ *          first.  It may hold fewer than min(T, n) items (then the result
+ *          is padded as usual).  Goes with the GATHER re-rank and FP32 rows. */
+typedef enum { NRLSH_PROBE_SCAN = 0, NRLSH_PROBE_TABLE = 1, NRLSH_PROBE_SINGLE = 2 } nrlsh_probe_mode;
 
 typedef struct nrlsh_query_opts {
     int32_t struct_size; /* sizeof(nrlsh_query_opts) */
@@ -202,9 +228,11 @@ typedef struct nrlsh_query_opts {
     int32_t rerank_mode; /* nrlsh_rerank_mode (read when struct_size covers it) */
     int32_t rerank_storage; /* GATHER re-rank rows: NRLSH_STORAGE_FP32 (default) or
                                NRLSH_STORAGE_BF16: inner products from the bfloat16
-                               copy bound each item within (2^-8 + 2^-40) ||q|| ||x||;
-                               items that may still reach the top-k are re-ranked
-                               exactly from the FP32 rows (same result, fewer bytes) */
+                               copy bound each item within ||q|| (||x - bf16(x)|| +
+                               (d + 1) 2^-52 ||x||) (the row's own rounding error,
+                               kept with the index); items that may still reach the
+                               top-k are re-ranked exactly from the FP32 rows (same
+                               result, fewer bytes) */
     int32_t probe_mode;  /* nrlsh_probe_mode (read when struct_size covers it) */
     int32_t pad;
 } nrlsh_query_opts;
@@ -319,11 +347,13 @@ const char *nrlsh_last_error(void);
 nrlsh_status nrlsh_index_info(const nrlsh_index *ix, int64_t *n, int32_t *d, int32_t *m,
                               int32_t *L, int32_t *dp);
 
-/* sets: number of L-row projection blocks, 1 (SHARED) or m (PER_SUBSET). */
+/* sets: number of L-row projection blocks of one hash table, 1 (SHARED) or
+ * m (PER_SUBSET). */
 nrlsh_status nrlsh_get_projection_sets(const nrlsh_index *ix, int32_t *sets);
 
-/* A: (sets L) x (d+1) float32, row r = hash function r (Eq. 4); block j
- * (rows j L .. j L + L - 1) belongs to sub-dataset j when sets = m. */
+/* A: (tables sets L) x (d+1) float32, row r = hash function r (Eq. 4); block
+ * tau sets + j (rows (tau sets + j) L .. + L - 1) belongs to hash table tau
+ * and, when sets = m, to sub-dataset j. */
 nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A);
 
 /* key: n float64 squared 2-norms in original order (Algorithm 1 ranking key). */
@@ -347,7 +377,10 @@ typedef struct nrlsh_build_stats {
     int64_t recomputed_items; /* items with at least one bit recomputed in FP64 */
     int64_t recomputed_bits;  /* (item, bit) projections recomputed in FP64 */
     int64_t recompute_flips;  /* of those, bits whose FP32 sign differed from FP64 */
-    int64_t lowp_items;       /* BF16 / FP8: items re-hashed from the FP32 copy */
+    int64_t lowp_items;       /* BF16 / FP8: items with more than 8 bits inside the
+                                 margin, re-hashed whole from the FP32 copy (the
+                                 in-margin bits of the others are recomputed in FP64
+                                 and counted in recomputed_items / recomputed_bits) */
     int64_t lowp_bits;        /* BF16 / FP8: (item, bit) projections inside the margin */
     int64_t lowp_changed;     /* BF16 / FP8: bits the FP32 re-hash changed */
 } nrlsh_build_stats;
@@ -376,9 +409,23 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
                                uint64_t *codes);
 
 /* Probed set of each query: cand is nq x min(T, n) int64 original ids (host),
- * listed sub-dataset by sub-dataset in stored order. */
+ * in no particular order (the set is the definition's). */
 nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
                                     int64_t probe_budget, int64_t *cand);
+
+/* The same under a probe mode (SCAN or SINGLE): counts (host, nq int64)
+ * receives the number of probed items of each query; entries of cand past it
+ * are -1. */
+nrlsh_status nrlsh_query_candidates_ex(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                       int64_t probe_budget, int32_t probe_mode, int64_t *cand,
+                                       int64_t *counts);
+
+/* Number of hash tables of the index (build option hash_tables). */
+nrlsh_status nrlsh_get_hash_tables(const nrlsh_index *ix, int32_t *tables);
+
+/* Item codes of hash table `table` (0 <= table < hash tables), n uint64 per
+ * original item as nrlsh_get_codes (which gives table 0). */
+nrlsh_status nrlsh_get_codes_table(const nrlsh_index *ix, int32_t table, uint64_t *codes);
 
 /* Re-rank statistics of this thread's last nrlsh_query / nrlsh_query_ex. */
 typedef struct nrlsh_query_stats {
@@ -401,6 +448,10 @@ typedef struct nrlsh_query_stats {
                               summed over its launches (a chunk none of whose items
                               any query of the tile can keep, by the norm bound U_j,
                               is skipped) */
+    int64_t scan_pairs;    /* SCAN: (query, item) pairs the first scan pass counted; the
+                              sub-datasets are scanned in descending U_j and a 64-query
+                              tile stops once all its queries' threshold buckets are
+                              known, so this is at most nq x n */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

@@ -33,7 +33,7 @@ class BuildOpts(C.Structure):
                 ("stream", C.c_void_p), ("eps", C.c_double), ("hash_storage", C.c_int32),
                 ("margin_mode", C.c_int32), ("margin_param", C.c_double),
                 ("partition", C.c_int32), ("projections", C.c_int32),
-                ("bucket_tables", C.c_int32), ("pad", C.c_int32)]
+                ("bucket_tables", C.c_int32), ("hash_tables", C.c_int32)]
 
 
 PARTITIONS = {"percentile": 0, "uniform": 1}
@@ -49,7 +49,7 @@ class QueryOpts(C.Structure):
                 ("probe_mode", C.c_int32), ("pad", C.c_int32)]
 
 
-PROBES = {"scan": 0, "table": 1}
+PROBES = {"scan": 0, "table": 1, "single": 2}
 
 
 RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3, "screen_bf16x3": 4}
@@ -66,7 +66,7 @@ class QueryStats(C.Structure):
                 ("kept_max", C.c_int64), ("theta_unset", C.c_int64), ("lp_kept_total", C.c_int64),
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
-                ("table_passes", C.c_int64), ("screen_pairs", C.c_int64)]
+                ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -138,6 +138,12 @@ def lib():
         L.nrlsh_query_codes.restype = st
         L.nrlsh_query_candidates.argtypes = [P, P, I64, I64, P]
         L.nrlsh_query_candidates.restype = st
+        L.nrlsh_query_candidates_ex.argtypes = [P, P, I64, I64, I32, P, P]
+        L.nrlsh_query_candidates_ex.restype = st
+        L.nrlsh_get_hash_tables.argtypes = [P, C.POINTER(I32)]
+        L.nrlsh_get_hash_tables.restype = st
+        L.nrlsh_get_codes_table.argtypes = [P, I32, P]
+        L.nrlsh_get_codes_table.restype = st
         L.nrlsh_get_query_stats.argtypes = [C.POINTER(QueryStats)]
         L.nrlsh_get_query_stats.restype = st
         L.nrlsh_multi_plan_create.argtypes = [C.POINTER(QueryDesc), I32, I32,
@@ -210,6 +216,9 @@ class Index:
         sets = I32()
         _check(lib().nrlsh_get_projection_sets(self._h, C.byref(sets)))
         self.qsets = sets.value  # 1: shared projections; m: one block per sub-dataset
+        tabs = I32()
+        _check(lib().nrlsh_get_hash_tables(self._h, C.byref(tabs)))
+        self.tables = tabs.value  # independent hash tables
 
     @property
     def handle(self):
@@ -236,8 +245,9 @@ class Index:
 
     # -------------------------------------------------- inspection
     def projection(self) -> np.ndarray:
-        """(qsets L) x (d+1); block j serves sub-dataset j when qsets = m."""
-        A = np.empty((self.qsets * self.L, self.d + 1), dtype=np.float32)
+        """(tables qsets L) x (d+1); block tau qsets + j serves hash table tau
+        and, when qsets = m, sub-dataset j."""
+        A = np.empty((self.tables * self.qsets * self.L, self.d + 1), dtype=np.float32)
         _check(lib().nrlsh_get_projection(self.handle, A.ctypes.data))
         return A
 
@@ -260,9 +270,12 @@ class Index:
         _check(lib().nrlsh_get_layout(self.handle, perm.ctypes.data, off.ctypes.data))
         return perm, off
 
-    def codes(self) -> np.ndarray:
+    def codes(self, table: int = 0) -> np.ndarray:
         c = np.empty(self.n, dtype=np.uint64)
-        _check(lib().nrlsh_get_codes(self.handle, c.ctypes.data))
+        if table == 0:
+            _check(lib().nrlsh_get_codes(self.handle, c.ctypes.data))
+        else:
+            _check(lib().nrlsh_get_codes_table(self.handle, int(table), c.ctypes.data))
         return c
 
     def rank_table(self) -> np.ndarray:
@@ -311,19 +324,26 @@ class Index:
                                             ustart.ctypes.data, uoff.ctypes.data, titem.ctypes.data))
         return ucode, ustart, uoff, titem
 
-    def query_candidates(self, queries, probe_budget: int) -> np.ndarray:
+    def query_candidates(self, queries, probe_budget: int, probe: str = "scan"):
+        """Probed ids per query: (nq, min(T, n)) for the scan; with probe="single"
+        a list of per-query arrays (their lengths vary)."""
         Q = _host_f32(queries)
         Tq = min(int(probe_budget), self.n)
         out = np.empty((Q.shape[0], Tq), dtype=np.int64)
-        _check(lib().nrlsh_query_candidates(self.handle, Q.ctypes.data, Q.shape[0],
-                                            int(probe_budget), out.ctypes.data))
-        return out
+        if probe == "scan":
+            _check(lib().nrlsh_query_candidates(self.handle, Q.ctypes.data, Q.shape[0],
+                                                int(probe_budget), out.ctypes.data))
+            return out
+        counts = np.empty(Q.shape[0], dtype=np.int64)
+        _check(lib().nrlsh_query_candidates_ex(self.handle, Q.ctypes.data, Q.shape[0], int(probe_budget),
+                                               PROBES[probe], out.ctypes.data, counts.ctypes.data))
+        return [out[i, :counts[i]].copy() for i in range(Q.shape[0])]
 
 
 # ------------------------------------------------------------------ C-ABI names
 def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=None,
                 hash_storage: str = "fp32", margin="rigorous", partition: str = "percentile",
-                projections: str = "shared", bucket_tables: bool = False) -> Index:
+                projections: str = "shared", bucket_tables: bool = False, hash_tables: int = 1) -> Index:
     """Algorithm 1.  ``items``: numpy (n, d) float32 on the host, or a CUDA torch
     tensor (n, d) float32 (device pointer, torch's current stream).
     ``hash_storage`` ("fp32", "bf16", "fp8") selects the precision form of the
@@ -331,7 +351,8 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
     ``partition`` is "percentile" (Algorithm 1) or "uniform" (Section 5);
     ``projections`` is "shared" (one matrix for all sub-datasets) or
     "per_subset" (an independent block per sub-dataset); ``bucket_tables``
-    also builds the tables that probe="table" queries read."""
+    also builds the tables that probe="table" queries read; ``hash_tables``
+    independent hash tables for probe="single" (multi-table single probe)."""
     h = P()
     st = STORAGES[hash_storage]
     part = PARTITIONS[partition]
@@ -343,14 +364,14 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
             raise ValueError("items must be a 2-D float32 tensor")
         items = items.contiguous()
         opts = BuildOpts(C.sizeof(BuildOpts), 1, stream or _torch_stream(items), float(eps), st,
-                         mmode, mparam, part, proj, tabs)
+                         mmode, mparam, part, proj, tabs, int(hash_tables))
         _check(lib().nrlsh_build_ex(P(items.data_ptr()), items.shape[0], items.shape[1], m, L,
                                     seed, C.byref(opts), C.byref(h)))
     else:
         X = _host_f32(items)
-        if eps != 0.0 or stream is not None or st != 0 or part != 0 or proj != 0 or tabs:
+        if eps != 0.0 or stream is not None or st != 0 or part != 0 or proj != 0 or tabs or hash_tables != 1:
             opts = BuildOpts(C.sizeof(BuildOpts), 0, stream, float(eps), st, mmode, mparam, part,
-                             proj, tabs)
+                             proj, tabs, int(hash_tables))
             _check(lib().nrlsh_build_ex(X.ctypes.data, X.shape[0], X.shape[1], m, L, seed,
                                         C.byref(opts), C.byref(h)))
         else:
@@ -526,7 +547,8 @@ def nrlsh_get_query_stats() -> dict:
             "lp_kept_total": st.lp_kept_total, "lp_kept_max": st.lp_kept_max,
             "lp_fallbacks": st.lp_fallbacks, "probe": {1: "table"}.get(st.probe_mode, "scan"),
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
-            "table_passes": st.table_passes, "screen_pairs": st.screen_pairs}
+            "table_passes": st.table_passes, "screen_pairs": st.screen_pairs,
+            "scan_pairs": st.scan_pairs}
 
 
 def nrlsh_profile_enable(on: bool = True):

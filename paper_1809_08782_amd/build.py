@@ -15,7 +15,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libnrlsh.so")
-SOURCES = ["api.hip", "k_build.hip", "k_query.hip", "k_table.hip", "k_multi.hip", "multi.hip"]
+SOURCES = ["api.hip", "k_build.hip", "k_query.hip", "k_single.hip", "k_table.hip", "k_multi.hip", "multi.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

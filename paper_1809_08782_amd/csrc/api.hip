@@ -393,8 +393,10 @@ hipStream_t pick_stream(void *user, int dev)
 }
 
 // Precision form of the hash: quantised copies of the items and projections,
-// the low-precision matrix-core hash with its margin, and the FP32 re-hash
-// (with its own FP64 band) of every item that had a projection in the margin.
+// the low-precision matrix-core hash with its margin; the bits inside the
+// margin of an item with few of them are recomputed in FP64 by the fix-up,
+// an item with many is re-hashed whole from the FP32 rows (with its own FP64
+// band).
 void hash_low_precision(nrlsh_index *ix, const std::vector<float> &tau_h, const float *tau_d,
                         FixEntry *fix, BuildCounters *ctr, hipStream_t s, Timer &tm)
 {
@@ -440,7 +442,7 @@ void hash_low_precision(nrlsh_index *ix, const std::vector<float> &tau_h, const 
     tm.begin("hash");
     HIPX(launch_hash_q(st, Xq, fp8 ? ix->xscale.get() : nullptr, n, d, dp, Aq.get(), ascale.get(),
                        ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(), ix->keymax.get(),
-                       ix->U.get(), mq.get(), tq.get(), ix->codes_l.get(), rows.get(), ctr, s));
+                       ix->U.get(), mq.get(), tq.get(), ix->codes_l.get(), rows.get(), fix, ctr, s));
     tm.end();
     BuildCounters hc{};
     HIPX(hipMemcpyAsync(&hc, ctr, sizeof hc, hipMemcpyDeviceToHost, s));
@@ -454,14 +456,64 @@ void hash_low_precision(nrlsh_index *ix, const std::vector<float> &tau_h, const 
     }
 }
 
+// Stages of the staged pass 1: the sub-datasets in jord_h order, cut at
+// positions e_1 = ceil(m / 16), e_{i+1} = max(e_i + 1, ceil(1.5 e_i)), ..., m;
+// each stage's sub-datasets cut into chunks sized so that a stage gives the
+// launch about 2048 (tile, chunk) blocks.  cut[s]: rank of the first bucket
+// of the first sub-dataset after stage s (the bound k_stage_check uses).
+struct ScanStages {
+    std::vector<int32_t> chunks;  // (sub-dataset, first, end) triples, stage by stage
+    std::vector<int> cbeg;        // first triple of each stage, then the total
+    std::vector<int> cut;         // per stage but the last
+};
+
+ScanStages scan_stages(const nrlsh_index *ix, int64_t tiles)
+{
+    ScanStages st;
+    const int m = ix->m, L1 = ix->L + 1;
+    std::vector<int> ends;
+    int e = std::max(1, (m + 15) / 16);
+    for (;;) {
+        e = std::min(e, m);
+        ends.push_back(e);
+        if (e == m) break;
+        e = std::max(e + 1, (e * 3 + 1) / 2);
+    }
+    int b = 0;
+    for (size_t s = 0; s < ends.size(); ++s) {
+        st.cbeg.push_back((int)(st.chunks.size() / 3));
+        int64_t items = 0;
+        for (int i = b; i < ends[s]; ++i) {
+            const int j = ix->jord_h[i];
+            items += ix->off_h[j + 1] - ix->off_h[j];
+        }
+        int64_t chunk = (items * std::max<int64_t>(tiles, 1) + 2047) / 2048;
+        chunk = std::max<int64_t>(2048, (chunk + 63) / 64 * 64);
+        for (int i = b; i < ends[s]; ++i) {
+            const int j = ix->jord_h[i];
+            for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += chunk) {
+                st.chunks.push_back(j);
+                st.chunks.push_back((int32_t)p);
+                st.chunks.push_back((int32_t)std::min<int64_t>(p + chunk, ix->off_h[j + 1]));
+            }
+        }
+        if (ends[s] < m) st.cut.push_back(ix->R_h[(size_t)ix->jord_h[ends[s]] * L1 + ix->L]);
+        b = ends[s];
+    }
+    st.cbeg.push_back((int)(st.chunks.size() / 3));
+    return st;
+}
+
 void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_t s, Timer &tm)
 {
     const int64_t n = ix->n;
     const int d = ix->d, dp = ix->dp, m = ix->m, L = ix->L, W = ix->W;
 
-    // projection matrix: one L-row block, or one per sub-dataset (drawn on
-    // the host once the first kernels are queued)
-    const int rows = ix->qsets * L;
+    // projection matrix: one L-row block, or one per sub-dataset, for each
+    // hash table (drawn on the host once the first kernels are queued)
+    const int tables = ix->tables;
+    const int trows = ix->qsets * L;  // rows of one table
+    const int rows = tables * trows;
     const size_t a_elems = (size_t)rows * (d + 1), at_elems = (size_t)rows * d;
 
     Block &B = ix->mem;
@@ -476,7 +528,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                  operm = B.reserve<int32_t>(n), ooff = B.reserve<int32_t>(m + 1),
                  oR = B.reserve<int32_t>((size_t)m * (L + 1)),
                  oinv = B.reserve<int32_t>((size_t)m * (L + 1)),
-                 ocodes = B.reserve<uint32_t>((size_t)n * W);
+                 ocodes = B.reserve<uint32_t>((size_t)n * W * tables), oxeb = B.reserve<float>(n),
+                 oRs = B.reserve<int32_t>((size_t)m * tables), oinvs = B.reserve<int32_t>((size_t)m * tables);
     // bucket tables: room for n distinct codes (the actual count is known after the build)
     const bool tab = ix->has_table;
     const size_t otc = B.reserve<uint64_t>(tab ? (size_t)n : 1),
@@ -500,6 +553,9 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     ix->R = B.view<int32_t>(oR);
     ix->inv = B.view<int32_t>(oinv);
     ix->codes_l = B.view<uint32_t>(ocodes);
+    ix->xeb = B.view<float>(oxeb);
+    ix->Rs = B.view<int32_t>(oRs);
+    ix->invs = B.view<int32_t>(oinvs);
     if (tab) {
         ix->ucode = B.view<uint64_t>(otc);
         ix->ustart = B.view<int32_t>(ots);
@@ -549,13 +605,15 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     // while the device ranks the items: the projection, the transpose of each
     // block and the FP32 uncertainty band factors (first read by the hash)
     make_projection(ix->seed, rows, d, ix->A_h);
+    // A[:, :d] transposed table by table: table tau's block is d x trows
     std::vector<float> At_h(at_elems), tau_h(rows);
     for (int r = 0; r < rows; ++r) {
+        const int tb = r / trows, rr = r - tb * trows;
         double nrm2 = 0.0;
         for (int c = 0; c <= d; ++c) {
             const double a = ix->A_h[(size_t)r * (d + 1) + c];
             nrm2 += a * a;
-            if (c < d) At_h[(size_t)c * rows + r] = (float)a;
+            if (c < d) At_h[(size_t)tb * d * trows + (size_t)c * trows + rr] = (float)a;
         }
         // tau_r = 2 gamma_{d+3} ||a_r||, gamma_k = k u / (1 - k u), u = 2^-24,
         // rounded up so that the band is never narrower than the bound.
@@ -639,7 +697,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                         hipMemcpyDeviceToDevice, s));
     tm.begin("layout");
     HIPX(launch_layout(X, n, d, dp, ix->perm.get(), ix->key.get(), ix->sid.get(), ix->Xl.get(),
-                       ix->Xh.get(), nullptr, ix->key_l.get(), ix->sid_l.get(), s));
+                       ix->Xh.get(), nullptr, ix->key_l.get(), ix->sid_l.get(), ix->xeb.get(), s));
     tm.end();
     HIPX(hipMemsetAsync(ix->Xh.get() + (size_t)n * dp, 0, 32 * sizeof(uint16_t), s));
     // the layout is the last reader of the caller's items
@@ -661,6 +719,11 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     for (int j = 0; j < m; ++j) ix->U_h[j] = std::sqrt(ix->keymax_h[j]);
     std::vector<int32_t> inv_h;
     make_rank_table(ix->U_h, L, ix->eps, ix->R_h, inv_h);
+    ix->jord_h.resize(m);
+    for (int j = 0; j < m; ++j) ix->jord_h[j] = j;
+    std::sort(ix->jord_h.begin(), ix->jord_h.end(), [&](int32_t a, int32_t b) {
+        return ix->U_h[a] != ix->U_h[b] ? ix->U_h[a] > ix->U_h[b] : a > b;
+    });
     // sub-dataset j occupies sorted ranks [off_j, off_{j+1}); an empty one
     // (no end rank written) starts and ends where the previous one ended
     ix->off_h.assign(m + 1, 0);
@@ -670,6 +733,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         off32[j + 1] = (int32_t)ix->off_h[j + 1];
     }
     if (ix->off_h[m] != n) throw Failure{NRLSH_E_INTERNAL, "sub-dataset runs do not cover the items"};
+
     std::memcpy(pin + p_U, ix->U_h.data(), m * sizeof(double));
     std::memcpy(pin + p_R, ix->R_h.data(), rank_n * sizeof(int32_t));
     std::memcpy(pin + p_inv, inv_h.data(), rank_n * sizeof(int32_t));
@@ -679,9 +743,25 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     HIPX(hipMemcpyAsync(ix->inv.get(), pin + p_inv, rank_n * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(ix->off.get(), pin + p_off, off32.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
 
-    // SimpleLSH transform + sign random projection, then the FP64 fix-up
+    // the (f, j) rank table of the multi-table single probe: bins ordered by
+    // the first table whose bucket holds the item (ascending), then
+    // sub-dataset descending; bin (j, f) sits where the multi-probe table
+    // keeps level l = t - 1 - f
+    ix->Rs_h.assign((size_t)m * tables, 0);
+    std::vector<int32_t> invs_h((size_t)m * tables);  // outlives its copy (synchronised below)
+    for (int f = 0; f < tables; ++f)
+        for (int j = 0; j < m; ++j) {
+            const int32_t rank = f * m + (m - 1 - j);
+            ix->Rs_h[(size_t)j * tables + (tables - 1 - f)] = rank;
+            invs_h[(size_t)rank] = j * tables + f;
+        }
+    HIPX(hipMemcpyAsync(ix->Rs.get(), ix->Rs_h.data(), ix->Rs_h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    HIPX(hipMemcpyAsync(ix->invs.get(), invs_h.data(), invs_h.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+
+    // SimpleLSH transform + sign random projection, then the FP64 fix-up,
+    // table by table (table tau: projection rows tau trows .., codes tau n W ..)
     std::vector<int32_t> bstart_h((size_t)m + 1, 0);  // outlives its copy
-    if (ix->storage == NRLSH_STORAGE_FP32 && ix->qsets > 1) {
+    if (ix->qsets > 1) {
         // one projection block per sub-dataset: the launch's blocks are dealt
         // out sub-dataset by sub-dataset (first block of j = bstart[j])
         const int per_block = hash_items_per_block();
@@ -691,26 +771,31 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         }
         HIPX(hipMemcpyAsync(bstart.get(), bstart_h.data(), bstart_h.size() * sizeof(int32_t),
                             hipMemcpyHostToDevice, s));
-        tm.begin("hash");
-        HIPX(launch_hash_per_subset(ix->Xl.get(), d, dp, ix->A.get(), L, ix->key_l.get(),
-                                    ix->sid_l.get(), ix->keymax.get(), ix->U.get(), tau.get(),
-                                    ix->off.get(), bstart.get(), m, bstart_h[m], ix->codes_l.get(),
-                                    fix.get(), ctr.get(), s));
-        tm.end();
-    } else if (ix->storage == NRLSH_STORAGE_FP32) {
-        tm.begin("hash");
-        HIPX(launch_hash(ix->Xl.get(), n, d, dp, ix->A.get(), L, ix->key_l.get(), ix->sid_l.get(),
-                         ix->keymax.get(), ix->U.get(), tau.get(), ix->codes_l.get(), fix.get(),
-                         ctr.get(), nullptr, s));
-        tm.end();
-    } else {
-        hash_low_precision(ix, tau_h, tau.get(), fix.get(), ctr.get(), s, tm);
     }
-    tm.begin("hash_fixup");
-    HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, ix->A.get(), L, ix->qsets > 1, ix->key_l.get(),
-                           ix->sid_l.get(), ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(),
-                           ix->codes_l.get(), n, s));
-    tm.end();
+    for (int tb = 0; tb < tables; ++tb) {
+        const float *At_b = ix->A.get() + (size_t)tb * trows * (d + 1);
+        const float *tau_b = tau.get() + (size_t)tb * trows;
+        uint32_t *codes_b = ix->codes_l.get() + (size_t)tb * n * W;
+        if (tb > 0) HIPX(launch_roll_fix_count(ctr.get(), s));  // the fix list starts over
+        if (ix->storage == NRLSH_STORAGE_FP32 && ix->qsets > 1) {
+            tm.begin("hash");
+            HIPX(launch_hash_per_subset(ix->Xl.get(), d, dp, At_b, L, ix->key_l.get(), ix->sid_l.get(),
+                                        ix->keymax.get(), ix->U.get(), tau_b, ix->off.get(), bstart.get(), m,
+                                        bstart_h[m], codes_b, fix.get(), ctr.get(), s));
+            tm.end();
+        } else if (ix->storage == NRLSH_STORAGE_FP32) {
+            tm.begin("hash");
+            HIPX(launch_hash(ix->Xl.get(), n, d, dp, At_b, L, ix->key_l.get(), ix->sid_l.get(), ix->keymax.get(),
+                             ix->U.get(), tau_b, codes_b, fix.get(), ctr.get(), nullptr, s));
+            tm.end();
+        } else {
+            hash_low_precision(ix, tau_h, tau.get(), fix.get(), ctr.get(), s, tm);
+        }
+        tm.begin("hash_fixup");
+        HIPX(launch_hash_fixup(ix->Xl.get(), d, dp, At_b, L, ix->qsets > 1, ix->key_l.get(), ix->sid_l.get(),
+                               ix->keymax.get(), ix->U.get(), fix.get(), ctr.get(), codes_b, n, s));
+        tm.end();
+    }
 
     // host sources of the copies below outlive them (synchronised at the end)
     std::vector<uint64_t> bh;
@@ -783,7 +868,7 @@ void index_settle(const nrlsh_index *ix)
         ix->stats.lowp_items = hc.lowp_items;
         ix->stats.lowp_bits = (int64_t)hc.lowp_bits;
         ix->stats.lowp_changed = (int64_t)hc.lowp_changed;
-        ix->stats.recomputed_items = hc.fix_count;
+        ix->stats.recomputed_items = (int64_t)hc.fix_count + hc.fix_prev;
         ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
         ix->stats.recompute_flips = (int64_t)hc.fix_flips;
     }
@@ -834,6 +919,24 @@ QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
     return sh;
 }
 
+// Staged pass 1 of a batch: clears the histograms, scans stage by stage and
+// stops each tile once all its queries are settled (k_stage_check).
+void run_scan_hist_staged(const nrlsh_index *ix, const QueryShape &sh, const uint32_t *qc, int64_t nb,
+                          const std::vector<int> &cbeg, const std::vector<int> &cut, const int32_t *chunks_d,
+                          int32_t *need, uint32_t *ghist, unsigned long long *npairs, hipStream_t s)
+{
+    const int64_t tb = (nb + 63) / 64;
+    HIPX(launch_fill32(ghist, tb * sh.m * (sh.L + 1) * 64, 0u, s));
+    HIPX(launch_fill32(need, tb, 1u, s));
+    if (cbeg.empty()) throw Failure{NRLSH_E_INTERNAL, "scan stages were not planned"};
+    const int S = (int)cbeg.size() - 1;
+    for (int k = 0; k < S; ++k) {
+        HIPX(launch_scan_hist_stage(ix->codes_l.get(), qc, nb, sh, chunks_d + 3 * (size_t)cbeg[k],
+                                    cbeg[k + 1] - cbeg[k], k == 0 ? nullptr : need, ghist, npairs, s));
+        if (k + 1 < S) HIPX(launch_stage_check(ghist, ix->inv.get(), nb, sh, cut[k], need, s));
+    }
+}
+
 // Gather path: materialise each query's probed list, then re-rank it.  When
 // cand_out_d is given, the probed stored positions are copied there (nq x Tq)
 // and the re-rank is skipped.  With `table` the probed lists come from the
@@ -841,7 +944,7 @@ QueryShape make_shape(const nrlsh_index *ix, int64_t T, int32_t k)
 void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
                       int64_t *ids_d, float *ips_d, int32_t *cand_out_d, uint32_t *qcodes_out_d,
                       hipStream_t s, Timer &tm, uint32_t *nonfinite_d, bool bf16_rows = false,
-                      bool table = false)
+                      bool table = false, unsigned long long *scan_pairs_d = nullptr)
 {
     const QueryShape sh = make_shape(ix, T, k);
     // queries per batch: a multiple of 64 keeping the candidate buffer <= 2^29 entries
@@ -854,20 +957,13 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int nsplit = rerank_splits(B, sh.Tq);
     const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
     const int lsplit = rerank_splits(B, lcap);
-    // small batches: (tiles x sub-datasets) waves leave the machine idle, so
-    // the scans take chunks of a sub-dataset per wave (about 16k waves)
-    int64_t maxsub = 0;
-    for (int j = 0; j < sh.m; ++j) maxsub = std::max(maxsub, ix->off_h[j + 1] - ix->off_h[j]);
-    const bool chunked = !table && !cand_out_d && tiles * sh.m < 4096 && maxsub > 4096;
-    int chunk = 0, nch = 1;
-    if (chunked) {
-        const int64_t want = (maxsub * tiles * sh.m + 16383) / 16384;
-        chunk = (int)std::max<int64_t>(2048, (want + 63) / 64 * 64);
-        nch = (int)((maxsub + chunk - 1) / chunk);
-    }
+    // both scan passes walk the chunks of the staged pass 1
+    const ScanStages st = table ? ScanStages{} : scan_stages(ix, tiles);
     Block blk;
     const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.qsets * sh.W),
                  o_gh = blk.reserve<uint32_t>(table ? 1 : (size_t)tiles * sh.m * L1 * 64),
+                 o_sc = blk.reserve<int32_t>(std::max<size_t>(1, st.chunks.size())),
+                 o_ne = blk.reserve<int32_t>((size_t)tiles),
                  o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
                  o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
                  o_ti = blk.reserve<int32_t>((size_t)tiles * 4 * 64),
@@ -879,8 +975,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
                  o_lc = blk.reserve<int32_t>(bf16_rows ? (size_t)B : 1),
                  o_gt = blk.reserve<unsigned long long>((size_t)B),
-                 o_ps = blk.reserve<int32_t>(chunked || table ? (size_t)B : 1),
-                 o_ct = blk.reserve<int32_t>(chunked ? (size_t)B : 1),
+                 o_ps = blk.reserve<int32_t>((size_t)B),
+                 o_ct = blk.reserve<int32_t>(table ? 1 : (size_t)B),
                  o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
                  o_lv = blk.reserve<double>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
                  o_lp = blk.reserve<int32_t>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1);
@@ -897,6 +993,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<int32_t> lpart_i = blk.view<int32_t>(o_lp);
     DBuf<int32_t> qstate = blk.view<int32_t>(o_qs), qhist = blk.view<int32_t>(o_qhi);
     DBuf<uint8_t> tctr = blk.view<uint8_t>(o_tc);
+    DBuf<int32_t> schunks = blk.view<int32_t>(o_sc), need = blk.view<int32_t>(o_ne);
+    if (!table)
+        HIPX(hipMemcpyAsync(schunks.get(), st.chunks.data(), st.chunks.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
     const TableView tv{ix->ucode.get(), ix->ustart.get(), ix->uoff.get(), ix->titem.get(), ix->binom.get()};
     if (table) HIPX(hipMemsetAsync(tctr.get(), 0, table_counter_bytes(), s));
     std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
@@ -914,7 +1014,6 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         tm.begin("qhash");
         HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qc, nonfinite_d, s));
         tm.end();
-        const int64_t tb = (nb + 63) / 64;
         if (table) {
             HIPX(hipMemsetAsync(qstate.get(), 0, (size_t)nb * sh.m * sizeof(int32_t), s));
             tm.begin("table_count");
@@ -932,32 +1031,21 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         }
         if (!table) {
             tm.begin("scan_hist");
-            if (chunked) {
-                HIPX(hipMemsetAsync(ghist.get(), 0, (size_t)tb * sh.m * L1 * 64 * sizeof(uint32_t), s));
-                HIPX(launch_scan_hist_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
-                                        ghist.get(), s));
-            } else {
-                HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qc, nb, sh, ghist.get(), s));
-            }
+            run_scan_hist_staged(ix, sh, qc, nb, st.cbeg, st.cut, schunks.get(), need.get(), ghist.get(),
+                                 scan_pairs_d, s);
             tm.end();
             tm.begin("threshold");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
                                   ghthr.get(), gtie.get(), s));
             tm.end();
-            if (chunked) {
-                tm.begin("tie_locate");
-                HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets,
-                                       gtie.get(), gpstar.get(), s));
-                tm.end();
-                HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
-            }
+            tm.begin("tie_locate");
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
+                                   gpstar.get(), s));
+            tm.end();
+            HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("scan_emit");
-            if (chunked)
-                HIPX(launch_scan_emit_c(ix->codes_l.get(), ix->off.get(), qc, nb, sh, chunk, nch,
+            HIPX(launch_scan_emit_stage(ix->codes_l.get(), qc, nb, sh, schunks.get(), st.cbeg.back(),
                                         ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
-            else
-                HIPX(launch_scan_emit(ix->codes_l.get(), ix->off.get(), qc, nb, sh, gbase.get(),
-                                      ghthr.get(), gtie.get(), cb, s));
             tm.end();
         }
         if (cand_out_d) continue;
@@ -965,7 +1053,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
             HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
             tm.begin("rerank_lp");
-            HIPX(launch_rerank_lp(ix->Xh.get(), ix->key_l.get(), ix->perm.get(), Qb, nb, sh, cb,
+            HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), ix->perm.get(), Qb, nb, sh, cb,
                                   nsplit, (int)lcap, lcount.get(), lists.get(), gtheta.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
@@ -1007,6 +1095,85 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         g_qstats.table_lookups = (int64_t)c[0];
         g_qstats.table_walked = (int64_t)c[1];
         g_qstats.table_passes = (int64_t)c[2];
+    }
+}
+
+// Multi-table single probe: every table's bucket of the query's own code in
+// each sub-dataset, tables in order until the budget (the passes of
+// k_single.hip around the threshold walk of the multi-probe path, on the
+// (sub-dataset, first table) bins), then the exact re-rank of the probed
+// lists, which may be shorter than min(T, n).  When cand_out_d is given the
+// probed stored positions go there (nq x Tq, count_out_d per query) and the
+// re-rank is skipped.
+void run_query_single(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int64_t *ids_d,
+                      float *ips_d, int32_t *cand_out_d, int32_t *count_out_d, hipStream_t s, Timer &tm,
+                      uint32_t *nonfinite_d)
+{
+    const QueryShape sh = make_shape(ix, T, k);
+    const int t = ix->tables, P = ix->qsets, L1 = t;
+    QueryShape shs = sh;  // the bins' shape: levels f = 0 .. t - 1
+    shs.L = t - 1;
+    int64_t B = (int64_t(1) << 29) / sh.Tq;
+    B = std::max<int64_t>(64, B / 64 * 64);
+    B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
+    const int64_t tiles = B / 64;
+    const int nsplit = rerank_splits(B, sh.Tq);
+    const ScanStages st = scan_stages(ix, tiles);
+    const int nchunks = st.cbeg.back();
+    Block blk;
+    const size_t o_qc = blk.reserve<uint32_t>((size_t)t * B * P * sh.W),
+                 o_gh = blk.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64),
+                 o_sc = blk.reserve<int32_t>(std::max<size_t>(1, st.chunks.size())),
+                 o_gb = blk.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64),
+                 o_th = blk.reserve<int32_t>((size_t)tiles * sh.m * 64),
+                 o_ti = blk.reserve<int32_t>((size_t)tiles * 4 * 64),
+                 o_ps = blk.reserve<int32_t>((size_t)B), o_ct = blk.reserve<int32_t>((size_t)B),
+                 o_ca = blk.reserve<int32_t>(cand_out_d ? 1 : (size_t)B * sh.Tq),
+                 o_pv = blk.reserve<double>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
+                 o_pi = blk.reserve<int32_t>(nsplit > 1 && !cand_out_d ? (size_t)B * nsplit * k : 1),
+                 o_gt = blk.reserve<unsigned long long>((size_t)B);
+    blk.allocate(s);
+    uint32_t *qc = blk.view<uint32_t>(o_qc).get(), *ghist = blk.view<uint32_t>(o_gh).get();
+    int32_t *chunks = blk.view<int32_t>(o_sc).get(), *gbase = blk.view<int32_t>(o_gb).get(),
+            *ghthr = blk.view<int32_t>(o_th).get(), *gtie = blk.view<int32_t>(o_ti).get(),
+            *gpstar = blk.view<int32_t>(o_ps).get(), *ccount = blk.view<int32_t>(o_ct).get(),
+            *cand = blk.view<int32_t>(o_ca).get(), *part_i = blk.view<int32_t>(o_pi).get();
+    double *part_v = blk.view<double>(o_pv).get();
+    unsigned long long *gtheta = blk.view<unsigned long long>(o_gt).get();
+    HIPX(hipMemcpyAsync(chunks, st.chunks.data(), st.chunks.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    const int64_t tstride_at = (int64_t)ix->d * P * sh.L;  // floats of one table's transposed block
+    for (int64_t b0 = 0; b0 < nq; b0 += B) {
+        const int64_t nb = std::min<int64_t>(B, nq - b0);
+        const float *Qb = Qd + b0 * sh.d;
+        const int64_t qstride = nb * P;  // query-code rows of one table
+        int32_t *cb = cand_out_d ? cand_out_d + b0 * sh.Tq : cand;
+        int32_t *cnt = count_out_d ? count_out_d + b0 : ccount;
+        tm.begin("qhash");
+        for (int tb = 0; tb < t; ++tb)
+            HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get() + tb * tstride_at, sh.L, sh.W, P,
+                                   qc + (size_t)tb * qstride * sh.W, nonfinite_d, s));
+        tm.end();
+        tm.begin("scan_hist");
+        HIPX(launch_fill32(ghist, ((nb + 63) / 64) * sh.m * L1 * 64, 0u, s));
+        HIPX(launch_mt_hist(ix->codes_l.get(), sh.n, qc, qstride, nb, sh.m, t, P, sh.W, chunks, nchunks, ghist, s));
+        tm.end();
+        tm.begin("threshold");
+        HIPX(launch_threshold(ghist, ix->Rs.get(), ix->invs.get(), nb, shs, gbase, ghthr, gtie, s));
+        tm.end();
+        tm.begin("tie_locate");
+        HIPX(launch_mt_tie(ix->codes_l.get(), sh.n, ix->off.get(), qc, qstride, nb, t, P, sh.W, gtie, gpstar, s));
+        tm.end();
+        HIPX(launch_fill32(cnt, nb, 0u, s));
+        tm.begin("scan_emit");
+        HIPX(launch_mt_emit(ix->codes_l.get(), sh.n, qc, qstride, nb, sh.m, t, P, sh.W, sh.Tq, chunks, nchunks, ghthr,
+                            gtie, gpstar, cnt, cb, s));
+        tm.end();
+        if (cand_out_d) continue;
+        if (nsplit > 1) HIPX(launch_fill32(gtheta, 2 * nb, 0u, s));
+        tm.begin("rerank");
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, cnt, nsplit, part_v, part_i, ids_d + b0 * k,
+                           ips_d + b0 * k, s, gtheta));
+        tm.end();
     }
 }
 
@@ -1063,7 +1230,7 @@ std::vector<int32_t> chunk_table(const nrlsh_index *ix, int items, int j_lo, int
 // Returns the non-finite flag as read with the last batch's record.
 uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
                           int kind, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
-                          uint32_t *nonfinite_d)
+                          uint32_t *nonfinite_d, unsigned long long *scan_pairs_d)
 {
     const uint16_t *Xh = kind != SCREEN_FP32 ? ix->Xh.get() : nullptr;
     const uint16_t *Xlo = kind == SCREEN_BF16X3 ? lo_rows(ix, s) : nullptr;
@@ -1071,7 +1238,10 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
     int64_t B = std::min<int64_t>((nq + 63) / 64 * 64, 16384);
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
-    int64_t cap = std::min<int64_t>(sh.Tq, 1024);
+    // kept-list room per query: the k best plus the items within the bounds'
+    // reach of the k-th, which grows with k (about 26 k were kept at k = 100 on
+    // the large workload); an overflow re-screens the batch with longer lists
+    int64_t cap = std::min<int64_t>(sh.Tq, std::max<int64_t>(1024, 32 * (int64_t)k));
 
     // pass-1 cells: the top sub-datasets whole (at least 16 k lower-bound
     // groups) plus, when the budget leaves items unprobed, every 16th cell of
@@ -1086,6 +1256,9 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
     while (j_lo > 0 && (ix->off_h[ix->m] - ix->off_h[j_lo]) / screen_cell_items() < want) --j_lo;
     std::vector<int32_t> ce = chunk_table(ix, screen_cell_items(), j_lo, sh.Tq >= sh.n ? 0 : 16);
     std::vector<int32_t> ch = chunk_table(ix, screen_chunk_items(), 0);
+    // (the FP32 screen runs the scan at every budget; the bfloat16 ones skip it
+    // when every item is probed)
+    const ScanStages st = sh.Tq >= sh.n && kind != SCREEN_FP32 ? ScanStages{} : scan_stages(ix, tiles);
     const int ncells = (int)(ce.size() / 3), nchunks = (int)(ch.size() / 3);
     int ncells_top = 0;  // cells of the whole top sub-datasets come first
     while (ncells_top < ncells && ce[3 * (size_t)ncells_top] >= j_lo) ++ncells_top;
@@ -1104,6 +1277,8 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
                  o_ta = blk.reserve<float>((size_t)B), o_co = blk.reserve<int32_t>((size_t)B),
                  o_li = blk.reserve<int32_t>((size_t)B * cap),
                  o_np = blk.reserve<unsigned long long>(1), o_rec = blk.reserve<long long>(5),
+                 o_sc = blk.reserve<int32_t>(std::max<size_t>(1, st.chunks.size())),
+                 o_ne = blk.reserve<int32_t>((size_t)tiles),
                  o_oka = blk.reserve<uint64_t>((size_t)B), o_okb = blk.reserve<uint64_t>((size_t)B),
                  o_ova = blk.reserve<int32_t>((size_t)B), o_ovb = blk.reserve<int32_t>((size_t)B),
                  o_otmp = blk.reserve<uint8_t>(radix_sort_tmp_bytes(B));
@@ -1128,6 +1303,10 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
     HIPX(hipMemsetAsync(npairs.get(), 0, sizeof(unsigned long long), s));
     HIPX(hipMemcpyAsync(cells.get(), ce.data(), ce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
     HIPX(hipMemcpyAsync(chunks.get(), ch.data(), ch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    DBuf<int32_t> schunks = blk.view<int32_t>(o_sc), need = blk.view<int32_t>(o_ne);
+    if (!st.chunks.empty())
+        HIPX(hipMemcpyAsync(schunks.get(), st.chunks.data(), st.chunks.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
 
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
@@ -1160,7 +1339,8 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
             HIPX(launch_probe_all(nb, sh, ghthr.get(), gtie.get(), gpstar.get(), s));
         } else {
             tm.begin("scan_hist");
-            HIPX(launch_scan_hist(ix->codes_l.get(), ix->off.get(), qcodes.get(), nb, sh, ghist.get(), s));
+            run_scan_hist_staged(ix, sh, qcodes.get(), nb, st.cbeg, st.cut, schunks.get(), need.get(),
+                                 ghist.get(), scan_pairs_d, s);
             tm.end();
             tm.begin("threshold");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(),
@@ -1233,11 +1413,17 @@ uint32_t run_query_screen(const nrlsh_index *ix, const float *Qd, int64_t nq, in
 // its last device work (the screen), else kFlagUnread.
 constexpr uint32_t kFlagUnread = 0xFFFFFFFFu;
 uint32_t run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T, int mode,
-                   bool bf16_rows, bool table, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
-                   uint32_t *nonfinite_d)
+                   bool bf16_rows, int probe, int64_t *ids_d, float *ips_d, hipStream_t s, Timer &tm,
+                   uint32_t *nonfinite_d, unsigned long long *scan_pairs_d)
 {
     const int64_t Tq = std::min<int64_t>(T, ix->n);
-    g_qstats.probe_mode = table ? NRLSH_PROBE_TABLE : NRLSH_PROBE_SCAN;
+    const bool table = probe == NRLSH_PROBE_TABLE;
+    g_qstats.probe_mode = probe;
+    if (probe == NRLSH_PROBE_SINGLE) {
+        g_qstats.mode = NRLSH_RERANK_GATHER;
+        run_query_single(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d);
+        return kFlagUnread;
+    }
     bool screen = !table && (mode == NRLSH_RERANK_SCREEN || mode == NRLSH_RERANK_SCREEN_FP32 ||
                              mode == NRLSH_RERANK_SCREEN_BF16X3 ||
                              (mode == NRLSH_RERANK_AUTO && Tq * 128 >= ix->n && nq >= 64 && Tq >= 2048));
@@ -1249,8 +1435,9 @@ uint32_t run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k
                     : kind == SCREEN_FP32   ? NRLSH_RERANK_SCREEN_FP32
                     : kind == SCREEN_BF16X3 ? NRLSH_RERANK_SCREEN_BF16X3
                                             : NRLSH_RERANK_SCREEN;
-    if (screen) return run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d);
-    run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d, bf16_rows, table);
+    if (screen) return run_query_screen(ix, Qd, nq, k, T, kind, ids_d, ips_d, s, tm, nonfinite_d, scan_pairs_d);
+    run_query_gather(ix, Qd, nq, k, T, ids_d, ips_d, nullptr, nullptr, s, tm, nonfinite_d, bf16_rows, table,
+                     scan_pairs_d);
     return kFlagUnread;
 }
 
@@ -1296,6 +1483,16 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, bucket_tables) + sizeof(int32_t)))
         tables = opts->bucket_tables;
     if (tables != 0 && tables != 1) return fail(NRLSH_E_INVALID_ARG, "bucket_tables must be 0 or 1");
+    int32_t htables = 1;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_build_opts, hash_tables) + sizeof(int32_t)))
+        htables = opts->hash_tables == 0 ? 1 : opts->hash_tables;
+    if (htables < 1 || htables > MT_MAX_TABLES)
+        return fail(NRLSH_E_INVALID_ARG, "hash_tables %d out of [1, %d]", htables, MT_MAX_TABLES);
+    if (htables > 1 && storage != NRLSH_STORAGE_FP32)
+        return fail(NRLSH_E_INVALID_ARG, "several hash tables need hash_storage FP32");
+    if ((int64_t)htables * (projections == NRLSH_PROJECTIONS_PER_SUBSET ? m : 1) * L > INT32_MAX / (d + 1) ||
+        (int64_t)htables * n * (L > 32 ? 2 : 1) > ((int64_t)1 << 40))
+        return fail(NRLSH_E_INVALID_ARG, "hash_tables: projection or code arrays too large");
     const bool on_device = opts && opts->device_ptrs;
     // device rows are read in vectors of the widest of 4, 2, 1 floats that
     // divides d, so the first row must start on such a vector
@@ -1323,6 +1520,7 @@ nrlsh_status nrlsh_build_ex(const float *items, int64_t n, int32_t d, int32_t m,
         ix->partition = partition;
         ix->qsets = projections == NRLSH_PROJECTIONS_PER_SUBSET ? m : 1;
         ix->has_table = tables == 1;
+        ix->tables = htables;
         ix->home = library_stream(dev);
         Timer tm(s);
         try {
@@ -1373,16 +1571,23 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) + sizeof(int32_t)) &&
         opts->rerank_storage != NRLSH_STORAGE_FP32 && opts->rerank_storage != NRLSH_STORAGE_BF16)
         return fail(NRLSH_E_INVALID_ARG, "rerank_storage %d unsupported", opts->rerank_storage);
-    bool table = false;
+    int probe = NRLSH_PROBE_SCAN;
     if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, probe_mode) + sizeof(int32_t))) {
-        if (opts->probe_mode != NRLSH_PROBE_SCAN && opts->probe_mode != NRLSH_PROBE_TABLE)
+        if (opts->probe_mode != NRLSH_PROBE_SCAN && opts->probe_mode != NRLSH_PROBE_TABLE &&
+            opts->probe_mode != NRLSH_PROBE_SINGLE)
             return fail(NRLSH_E_INVALID_ARG, "probe_mode %d unknown", opts->probe_mode);
-        table = opts->probe_mode == NRLSH_PROBE_TABLE;
+        probe = opts->probe_mode;
     }
+    const bool table = probe == NRLSH_PROBE_TABLE;
     if (table && !ix->has_table)
         return fail(NRLSH_E_INVALID_ARG, "probe_mode TABLE needs an index built with bucket_tables = 1");
-    if (table && opts->rerank_mode != NRLSH_RERANK_AUTO && opts->rerank_mode != NRLSH_RERANK_GATHER)
-        return fail(NRLSH_E_INVALID_ARG, "probe_mode TABLE goes with the GATHER re-rank");
+    if (probe != NRLSH_PROBE_SCAN && opts->rerank_mode != NRLSH_RERANK_AUTO &&
+        opts->rerank_mode != NRLSH_RERANK_GATHER)
+        return fail(NRLSH_E_INVALID_ARG, "probe_mode TABLE / SINGLE go with the GATHER re-rank");
+    if (probe == NRLSH_PROBE_SINGLE && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_storage) +
+                                                                     sizeof(int32_t)) &&
+        opts->rerank_storage != NRLSH_STORAGE_FP32)
+        return fail(NRLSH_E_INVALID_ARG, "probe_mode SINGLE re-ranks from the FP32 rows");
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
     return guarded([&]() -> nrlsh_status {
@@ -1391,13 +1596,15 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
         index_wait(ix, s);
         Timer tm(s);
         Block blk;
-        const size_t o_fl = blk.reserve<uint32_t>(1),
+        const size_t o_fl = blk.reserve<uint32_t>(1), o_sp = blk.reserve<unsigned long long>(1),
                      o_q = blk.reserve<float>(on_device ? 1 : (size_t)nq * ix->d),
                      o_i = blk.reserve<int64_t>(on_device ? 1 : (size_t)nq * k),
                      o_p = blk.reserve<float>(on_device ? 1 : (size_t)nq * k);
         blk.allocate(s);
         DBuf<uint32_t> flag = blk.view<uint32_t>(o_fl);
+        DBuf<unsigned long long> spairs = blk.view<unsigned long long>(o_sp);
         HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        HIPX(hipMemsetAsync(spairs.get(), 0, sizeof(unsigned long long), s));
         int mode = NRLSH_RERANK_AUTO;
         if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, rerank_mode) + sizeof(int32_t)))
             mode = opts->rerank_mode;
@@ -1406,26 +1613,30 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
             bf16_rows = opts->rerank_storage == NRLSH_STORAGE_BF16;
         uint32_t bad = kFlagUnread;
         if (on_device) {
-            bad = run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, table, out_ids, out_ips, s, tm,
-                            flag.get());
+            bad = run_query(ix, queries, nq, k, probe_budget, mode, bf16_rows, probe, out_ids, out_ips, s, tm,
+                            flag.get(), spairs.get());
         } else {
             DBuf<float> Qd = blk.view<float>(o_q);
             DBuf<int64_t> ids = blk.view<int64_t>(o_i);
             DBuf<float> ips = blk.view<float>(o_p);
             HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float),
                                 hipMemcpyHostToDevice, s));
-            (void)run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, table, ids.get(), ips.get(), s,
-                            tm, flag.get());
+            (void)run_query(ix, Qd.get(), nq, k, probe_budget, mode, bf16_rows, probe, ids.get(), ips.get(), s,
+                            tm, flag.get(), spairs.get());
             HIPX(hipMemcpyAsync(out_ids, ids.get(), (size_t)nq * k * sizeof(int64_t),
                                 hipMemcpyDeviceToHost, s));
             HIPX(hipMemcpyAsync(out_ips, ips.get(), (size_t)nq * k * sizeof(float),
                                 hipMemcpyDeviceToHost, s));
         }
-        if (bad == kFlagUnread) {  // (host outputs: the copies above are waited for here)
-            bad = 0;
-            HIPX(hipMemcpyAsync(&bad, flag.get(), sizeof bad, hipMemcpyDeviceToHost, s));
-            HIPX(hipStreamSynchronize(s));
-        }
+        // the pairs of the staged scan come back with the flag (host outputs:
+        // the copies above are waited for here)
+        unsigned long long sp = 0;
+        const bool read_flag = bad == kFlagUnread;
+        if (read_flag) bad = 0;
+        if (read_flag) HIPX(hipMemcpyAsync(&bad, flag.get(), sizeof bad, hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(&sp, spairs.get(), sizeof sp, hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        g_qstats.scan_pairs = (int64_t)sp;
         tm.settle();
         if (bad) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
         return NRLSH_OK;
@@ -1481,6 +1692,12 @@ nrlsh_status nrlsh_get_projection_sets(const nrlsh_index *ix, int32_t *sets)
     return NRLSH_OK;
 }
 
+nrlsh_status nrlsh_get_hash_tables(const nrlsh_index *ix, int32_t *tables)
+{
+    if (!ix || !tables) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    *tables = ix->tables;
+    return NRLSH_OK;
+}
 nrlsh_status nrlsh_get_projection(const nrlsh_index *ix, float *A)
 {
     if (!ix || !A) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
@@ -1526,13 +1743,19 @@ nrlsh_status nrlsh_get_layout(const nrlsh_index *ix, int32_t *perm, int64_t *off
 
 nrlsh_status nrlsh_get_codes(const nrlsh_index *ix, uint64_t *codes)
 {
+    return nrlsh_get_codes_table(ix, 0, codes);
+}
+nrlsh_status nrlsh_get_codes_table(const nrlsh_index *ix, int32_t table, uint64_t *codes)
+{
     if (!ix || !codes) return fail(NRLSH_E_INVALID_ARG, "NULL argument");
+    if (table < 0 || table >= ix->tables) return fail(NRLSH_E_INVALID_ARG, "table %d out of range", table);
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
         index_settle(ix);
         std::vector<uint32_t> w((size_t)ix->n * ix->W);
         std::vector<int32_t> perm(ix->n);
-        HIPX(hipMemcpy(w.data(), ix->codes_l.get(), w.size() * sizeof(uint32_t), hipMemcpyDeviceToHost));
+        HIPX(hipMemcpy(w.data(), ix->codes_l.get() + (size_t)table * ix->n * ix->W, w.size() * sizeof(uint32_t),
+                       hipMemcpyDeviceToHost));
         HIPX(hipMemcpy(perm.data(), ix->perm.get(), perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
         for (int64_t p = 0; p < ix->n; ++p) {
             uint64_t c = w[(size_t)p * ix->W];
@@ -1608,6 +1831,55 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
             uint64_t c = w[(size_t)i * ix->W];
             if (ix->W == 2) c |= (uint64_t)w[(size_t)i * 2 + 1] << 32;
             codes[i] = c;
+        }
+        return NRLSH_OK;
+    });
+}
+
+nrlsh_status nrlsh_query_candidates_ex(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                       int64_t probe_budget, int32_t probe_mode, int64_t *cand,
+                                       int64_t *counts)
+{
+    if (probe_mode == NRLSH_PROBE_SCAN) {
+        const nrlsh_status st = nrlsh_query_candidates(ix, queries, nq, probe_budget, cand);
+        if (st == NRLSH_OK && counts)
+            for (int64_t q = 0; q < nq; ++q) counts[q] = std::min<int64_t>(probe_budget, ix->n);
+        return st;
+    }
+    if (probe_mode != NRLSH_PROBE_SINGLE) return fail(NRLSH_E_INVALID_ARG, "probe_mode %d not supported here", probe_mode);
+    if (!ix || nq < 0 || (nq > 0 && (!queries || !cand || !counts)) || probe_budget < 1)
+        return fail(NRLSH_E_INVALID_ARG, "bad argument");
+    if (nq == 0) return NRLSH_OK;
+    if (!all_finite(queries, nq * (int64_t)ix->d)) return fail(NRLSH_E_NOT_FINITE, "queries hold NaN or Inf");
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        index_settle(ix);
+        hipStream_t s = library_stream(ix->device);
+        const int64_t Tq = std::min<int64_t>(probe_budget, ix->n);
+        Timer tm(s);
+        DBuf<float> Qd((size_t)nq * ix->d, s);
+        DBuf<int32_t> cd((size_t)nq * Tq, s), cn((size_t)nq, s);
+        DBuf<uint32_t> flag(1, s);
+        HIPX(hipMemsetAsync(flag.get(), 0, sizeof(uint32_t), s));
+        HIPX(hipMemcpyAsync(Qd.get(), queries, (size_t)nq * ix->d * sizeof(float), hipMemcpyHostToDevice, s));
+        run_query_single(ix, Qd.get(), nq, 1, probe_budget, nullptr, nullptr, cd.get(), cn.get(), s, tm, flag.get());
+        std::vector<int32_t> pos((size_t)nq * Tq), perm(ix->n), cnt((size_t)nq);
+        HIPX(hipMemcpyAsync(pos.data(), cd.get(), pos.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(cnt.data(), cn.get(), cnt.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipMemcpyAsync(perm.data(), ix->perm.get(), perm.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        for (int64_t q = 0; q < nq; ++q) {
+            const int64_t c = std::min<int64_t>(cnt[(size_t)q], Tq);
+            counts[q] = c;
+            for (int64_t e = 0; e < Tq; ++e) {
+                const int32_t p = pos[(size_t)(q * Tq + e)];
+                if (e >= c) {
+                    cand[q * Tq + e] = -1;
+                    continue;
+                }
+                if (p < 0 || p >= ix->n) throw Failure{NRLSH_E_INTERNAL, "probed position out of range"};
+                cand[q * Tq + e] = perm[p];
+            }
         }
         return NRLSH_OK;
     });

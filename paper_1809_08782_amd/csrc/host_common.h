@@ -207,11 +207,16 @@ struct nrlsh_index {
     int32_t storage = NRLSH_STORAGE_FP32, margin_mode = NRLSH_MARGIN_RIGOROUS;
     double margin_param = 0.0;
     int32_t partition = NRLSH_PARTITION_PERCENTILE;
-    int32_t qsets = 1;  // projection blocks of L rows: 1 (shared) or m (one per sub-dataset)
+    int32_t qsets = 1;  // projection blocks of L rows per table: 1 (shared) or m (one per sub-dataset)
+    int32_t tables = 1; // independent hash tables (codes_l holds tables x n x W words)
     std::vector<float> A_h;
     std::vector<double> keymax_h, U_h;
     std::vector<int64_t> off_h;
     std::vector<int32_t> R_h;
+    // sub-datasets by (U_j desc, j desc): the order in which the staged scan
+    // visits them (every bucket of a later one ranks after the first bucket
+    // (jord_h[i], L) of the earlier ones not yet visited)
+    std::vector<int32_t> jord_h;
     // the build's last device work (queued, not waited for, when nrlsh_build
     // returns): later calls wait for `ready` on their stream or on the host;
     // the build counters arrive in pinned host memory behind it
@@ -234,6 +239,11 @@ struct nrlsh_index {
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order
     nrlsh::host::DBuf<int32_t> sid, sid_l, perm, off, R, inv;
     nrlsh::host::DBuf<uint32_t> codes_l;              // stored order
+    nrlsh::host::DBuf<float> xeb;  // per stored row: bound on ||x - bf16(x)|| (+ FP64 sum term)
+    // rank table of the (sub-dataset, first-table) bins of the multi-table
+    // single probe, m x tables (level index tables - 1 - f), and its inverse
+    std::vector<int32_t> Rs_h;
+    nrlsh::host::DBuf<int32_t> Rs, invs;
     // (k, Tq) of the last call whose bfloat16 re-rank lists overflowed, packed
     // k << 32 | Tq (0: none): calls with at least that k and budget skip the
     // bfloat16 pass (a speed hint only; results never depend on it)

@@ -322,9 +322,11 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
                                                 float *__restrict__ Xl, uint16_t *__restrict__ Xh,
                                                 uint16_t *__restrict__ Xlo,
                                                 double *__restrict__ key_l,
-                                                int32_t *__restrict__ sid_l)
+                                                int32_t *__restrict__ sid_l,
+                                                float *__restrict__ xeb)
 {
     using F = typename LyVec<VW>::F;
+    __shared__ float dsq_s[4][LY_ROWS];  // per stored row: sum of (x - bf16(x))^2
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t p0 = ((int64_t)blockIdx.x * 4 + wave) * LY_ROWS;
     const bool mine = lane < LY_ROWS && p0 + lane < n;
@@ -333,6 +335,7 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
         key_l[p0 + lane] = key[src_row];
         sid_l[p0 + lane] = sid[src_row];
     }
+    if (lane < LY_ROWS) dsq_s[wave][lane] = 0.f;
     // each lane element is a group of 4 stored floats (dp is a multiple of
     // 8, so groups never cross a stored row and their stores are 16- and
     // 8-byte aligned), loaded as 4 / VW pieces that lie wholly inside or
@@ -342,10 +345,12 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
     for (int e0 = 0; e0 < total; e0 += 64 * LY_B) {
         float v[LY_B][4];
         int64_t dst[LY_B];  // first stored element of the group, -1 = none
+        int rr[LY_B];       // its row within the wave's rows
 #pragma unroll
         for (int b = 0; b < LY_B; ++b) {
             const int e = e0 + 64 * b + lane;
             const int r = e / nv, c = (e - r * nv) * 4;
+            rr[b] = r;
             const int64_t i = __shfl(src_row, r & (LY_ROWS - 1), 64);
             const bool ok = e < total && p0 + r < n;
             dst[b] = ok ? (p0 + r) * dp + c : -1;
@@ -363,17 +368,33 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
             if (dst[b] < 0) continue;
             floatx4 t;
             ushort4 h, l;
+            float sq = 0.f;
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const uint16_t hu = bf16_rne(v[b][u]);
+                // x - bf16(x) is exact in FP32 (the two share their leading bits)
+                const float dl = v[b][u] - __uint_as_float((uint32_t)hu << 16);
                 t[u] = v[b][u];
                 reinterpret_cast<uint16_t *>(&h)[u] = hu;
-                reinterpret_cast<uint16_t *>(&l)[u] = bf16_rne(v[b][u] - __uint_as_float((uint32_t)hu << 16));
+                reinterpret_cast<uint16_t *>(&l)[u] = bf16_rne(dl);
+                sq += dl * dl;
             }
             *reinterpret_cast<floatx4 *>(Xl + dst[b]) = t;
             *reinterpret_cast<ushort4 *>(Xh + dst[b]) = h;
             if (Xlo) *reinterpret_cast<ushort4 *>(Xlo + dst[b]) = l;
+            if (xeb) atomicAdd(&dsq_s[wave][rr[b]], sq);
         }
+    }
+    // error bound of the bfloat16 image of each row: ||x - bf16(x)|| (an FP32
+    // sum of d rounded squares is at most (1 + (d + 2) 2^-23) below the exact
+    // one; squares under the FP32 range add at most 2^-50 once rooted), plus
+    // (d + 1) 2^-52 ||x|| for an FP64 sum of d exact products with bf16(x),
+    // rounded up to FP32
+    if (xeb && mine) {
+        const double s2 = (double)dsq_s[wave][lane] * (1.0 + (double)(d + 2) * 0x1p-23);
+        const double b = __builtin_sqrt(s2) * (1.0 + 0x1p-40) + 0x1p-50 +
+                         (double)(d + 1) * 0x1p-52 * __builtin_sqrt(key[src_row]) * (1.0 + 0x1p-40);
+        xeb[p0 + lane] = (float)(b * (1.0 + 0x1p-22));
     }
 }
 
@@ -666,6 +687,8 @@ __global__ __launch_bounds__(256) void k_quant_rows(const float *__restrict__ sr
 // operands.  p~ = (scales) acc + a_d sqrt(keymax_j - key_i).  Every bit gets
 // sign(p~); an item with |p~| <= mq_r ||x_i|| + tq_r U_j for some bit (or with
 // U_j outside [2^-60, 2^60]) is appended to `rows` for the FP32 re-hash.
+constexpr int HQ_FEW = 8;
+
 template <int CB, int ST>
 __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
     const void *__restrict__ Xq, const float *__restrict__ xscale, int64_t n, int d, int dp,
@@ -673,7 +696,7 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
     int L, const double *__restrict__ key_l, const int32_t *__restrict__ sid_l,
     const double *__restrict__ keymax, const double *__restrict__ U, const float *__restrict__ mq,
     const float *__restrict__ tq, uint32_t *__restrict__ codes_l, int32_t *__restrict__ rows,
-    BuildCounters *__restrict__ ctr)
+    FixEntry *__restrict__ fix, BuildCounters *__restrict__ ctr)
 {
     constexpr int NB = 16 * CB;
     constexpr int ES = ST == 1 ? 2 : 1;       // bytes per element
@@ -830,21 +853,36 @@ __global__ __launch_bounds__(H_WAVES * 64) void k_hash_q(
             codes_l[2 * i + 1] = (uint32_t)(mycode >> 32);
         }
     }
-    const bool has = valid && myflag != 0ull;
-    const uint64_t hb = __ballot(has);
-    const unsigned long long nbits = (unsigned long long)__popcll(valid ? myflag : 0ull);
-    unsigned long long wbits = nbits;
+    // an item with at most HQ_FEW bits inside the margin has just those bits
+    // recomputed in FP64 (k_hash_fixup); one with more is re-hashed whole from
+    // the FP32 rows (then its own FP32 band goes through the fix-up)
+    const int nflag = __popcll(valid ? myflag : 0ull);
+    const bool few = valid && nflag > 0 && nflag <= HQ_FEW;
+    const bool many = valid && nflag > HQ_FEW;
+    const uint64_t fb = __ballot(few), hb = __ballot(many);
+    unsigned long long wbits = (unsigned long long)nflag;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) wbits += __shfl_xor(wbits, o, 64);
+    if (lane == 0 && wbits) atomicAdd(&ctr->lowp_bits, wbits);
+    if (fb != 0ull) {
+        const int leader = __ffsll((long long)fb) - 1;
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&ctr->fix_count, (uint32_t)__popcll(fb));
+        base = __shfl(base, leader, 64);
+        if (few) {
+            FixEntry fe;
+            fe.mask = myflag;
+            fe.item = (int32_t)i;
+            fe.pad = 0;
+            fix[base + (uint32_t)__popcll(fb & lanemask_lt(lane))] = fe;
+        }
+    }
     if (hb != 0ull) {
         const int leader = __ffsll((long long)hb) - 1;
         uint32_t base = 0;
-        if (lane == leader) {
-            base = atomicAdd(&ctr->lowp_items, (uint32_t)__popcll(hb));
-            atomicAdd(&ctr->lowp_bits, wbits);
-        }
+        if (lane == leader) base = atomicAdd(&ctr->lowp_items, (uint32_t)__popcll(hb));
         base = __shfl(base, leader, 64);
-        if (has) rows[base + (uint32_t)__popcll(hb & lanemask_lt(lane))] = (int32_t)i;
+        if (many) rows[base + (uint32_t)__popcll(hb & lanemask_lt(lane))] = (int32_t)i;
     }
 }
 
@@ -1025,7 +1063,10 @@ __global__ __launch_bounds__(HP_WAVES * 64) void k_hash_p(
 // One thread per list entry: recompute every flagged bit in FP64 exactly as
 // the definition (v = [x / U_j ; sqrt(max(0, 1 - key/keymax))], or [0; 1]
 // when U_j = 0; sum over coordinates in ascending order, no contraction).
-constexpr int FX_U = 8;
+// The flagged bits are taken FX_B at a time: each coordinate's quotient
+// x_c / U_j is formed once for the group and its product with each bit's
+// projection entry added to that bit's own sum, in ascending c.
+constexpr int FX_B = 8;
 
 __global__ __launch_bounds__(256) void k_hash_fixup(
     const float *__restrict__ Xl, int d, int dp, const float *__restrict__ A, int L, int per_subset,
@@ -1051,32 +1092,42 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
         }
         const float *x = Xl + i * dp;
         const double uu = u == 0.0 ? 1.0 : u;
+        const float *Ab = A + (per_subset ? (int64_t)s * L : 0) * (int64_t)(d + 1);
         uint64_t mask = fe.mask;
         while (mask != 0ull) {
-            const int r = __ffsll((long long)mask) - 1;
-            mask &= mask - 1ull;
-            const float *a = A + ((per_subset ? (int64_t)s * L : 0) + r) * (int64_t)(d + 1);
-            // FX_U products at a time with their loads issued together (a
-            // coordinate past d reads coordinate d - 1 and is not added; the
-            // quotient is always formed, by 1 when U_j = 0 and then replaced
-            // by 0), added in ascending order
-            double sacc = 0.0;
-            for (int c0 = 0; c0 < d; c0 += FX_U) {
-                double t[FX_U];
+            int rr[FX_B];
+            int nb = 0;
 #pragma unroll
-                for (int j = 0; j < FX_U; ++j) {
-                    const int c = min(c0 + j, d - 1);
-                    const double q = (double)x[c] / uu;
-                    t[j] = (double)a[c] * (u == 0.0 ? 0.0 : q);
+            for (int b = 0; b < FX_B; ++b) {
+                rr[b] = 0;
+                if (mask != 0ull) {
+                    rr[b] = __ffsll((long long)mask) - 1;
+                    mask &= mask - 1ull;
+                    nb = b + 1;
                 }
-#pragma unroll
-                for (int j = 0; j < FX_U; ++j) sacc = c0 + j < d ? sacc + t[j] : sacc;
             }
-            sacc = sacc + (double)a[d] * vd;
-            const uint64_t bit = sacc > 0.0 ? 1ull : 0ull;
-            nflip += ((code >> r) & 1ull) != bit;
-            ++nbits;
-            code = (code & ~(1ull << r)) | (bit << r);
+            double sacc[FX_B];
+#pragma unroll
+            for (int b = 0; b < FX_B; ++b) sacc[b] = 0.0;
+            for (int c = 0; c < d; ++c) {
+                const double q = (double)x[c] / uu;  // formed even when U_j = 0, then replaced by 0
+                const double vq = u == 0.0 ? 0.0 : q;
+#pragma unroll
+                for (int b = 0; b < FX_B; ++b) {
+                    const double t = (double)Ab[(int64_t)rr[b] * (d + 1) + c] * vq;
+                    sacc[b] = b < nb ? sacc[b] + t : sacc[b];
+                }
+            }
+#pragma unroll
+            for (int b = 0; b < FX_B; ++b) {
+                if (b >= nb) break;
+                const int r = rr[b];
+                const double sum = sacc[b] + (double)Ab[(int64_t)r * (d + 1) + d] * vd;
+                const uint64_t bit = sum > 0.0 ? 1ull : 0ull;
+                nflip += ((code >> r) & 1ull) != bit;
+                ++nbits;
+                code = (code & ~(1ull << r)) | (bit << r);
+            }
         }
         codes_l[W * i] = (uint32_t)code;
         if (W == 2) codes_l[W * i + 1] = (uint32_t)(code >> 32);
@@ -1085,6 +1136,12 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
         atomicAdd(&ctr->fix_bits, nbits);
         atomicAdd(&ctr->fix_flips, nflip);
     }
+}
+
+__global__ void k_roll_fix_count(BuildCounters *ctr)
+{
+    ctr->fix_prev += ctr->fix_count;
+    ctr->fix_count = 0;
 }
 
 inline unsigned grid_for(int64_t n, int per_block)
@@ -1147,15 +1204,18 @@ hipError_t launch_assign_subsets(const uint64_t *sorted_key, const int32_t *sort
 
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
                          const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
-                         uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s)
+                         uint16_t *Xlo, double *key_l, int32_t *sid_l, float *xeb, hipStream_t s)
 {
     const dim3 grid(grid_for(n, 4 * LY_ROWS)), block(256);
     if (d % 4 == 0)
-        hipLaunchKernelGGL(k_layout<4>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+        hipLaunchKernelGGL(k_layout<4>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l,
+                           sid_l, xeb);
     else if (d % 2 == 0)
-        hipLaunchKernelGGL(k_layout<2>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+        hipLaunchKernelGGL(k_layout<2>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l,
+                           sid_l, xeb);
     else
-        hipLaunchKernelGGL(k_layout<1>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l, sid_l);
+        hipLaunchKernelGGL(k_layout<1>, grid, block, 0, s, X, n, d, dp, perm, key, sid, Xl, Xh, Xlo, key_l,
+                           sid_l, xeb);
     return hipGetLastError();
 }
 
@@ -1183,13 +1243,13 @@ hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64
                          const void *Aq, const float *ascale, const float *A, int L,
                          const double *key_l, const int32_t *sid_l, const double *keymax,
                          const double *U, const float *mq, const float *tq, uint32_t *codes_l,
-                         int32_t *rows, BuildCounters *ctr, hipStream_t s)
+                         int32_t *rows, FixEntry *fix, BuildCounters *ctr, hipStream_t s)
 {
     const dim3 grid(grid_for(n, H_WAVES * 64)), block(H_WAVES * 64);
     const int cb = (L + 15) / 16;
 #define NRLSH_HQ(CB, ST)                                                                          \
     hipLaunchKernelGGL((k_hash_q<CB, ST>), grid, block, 0, s, Xq, xscale, n, d, dp, Aq, ascale, A, L, \
-                       key_l, sid_l, keymax, U, mq, tq, codes_l, rows, ctr)
+                       key_l, sid_l, keymax, U, mq, tq, codes_l, rows, fix, ctr)
     if (storage == 1) {
         if (cb == 1) NRLSH_HQ(1, 1);
         else if (cb == 2) NRLSH_HQ(2, 1);
@@ -1267,6 +1327,12 @@ hipError_t launch_hash(const float *Xl, int64_t n, int d, int dp, const float *A
                            tau, codes_l, fix, ctr, rows, nullptr, nullptr, 0);
         break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_roll_fix_count(BuildCounters *ctr, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_roll_fix_count, dim3(1), dim3(1), 0, s, ctr);
     return hipGetLastError();
 }
 

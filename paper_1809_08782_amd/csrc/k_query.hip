@@ -227,7 +227,12 @@ __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__r
         }
     }
     __syncthreads();
-    const int32_t bstar = res_s[0][lane], rstar = res_s[1][lane], jstar = res_s[2][lane];
+    int32_t bstar = res_s[0][lane];
+    const int32_t rstar = res_s[1][lane], jstar = res_s[2][lane];
+    // all buckets together hold fewer than Tq items (only possible when some
+    // items belong to no bucket, as under single probe): every bucket is
+    // probed whole
+    if (valid && bstar < 0) bstar = (int32_t)P;
 
     // 2. per-sub-dataset bounds and emission offsets
     const int ja = (int)((int64_t)m * wave / TH_WAVES), jb = (int)((int64_t)m * (wave + 1) / TH_WAVES);
@@ -474,6 +479,213 @@ __global__ __launch_bounds__(64) void k_scan_emit_c(const uint32_t *__restrict__
     }
 }
 
+// ---------------------------------------------------------------- fill
+// words 32-bit words of p set to v (a kernel rather than a memset, so that a
+// caller may capture the launches in a graph).
+__global__ __launch_bounds__(256) void k_fill32(uint32_t *__restrict__ p, int64_t words, uint32_t v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < words; i += (int64_t)gridDim.x * 256)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------- staged pass 1
+// Pass 1 with an exact early exit in descending norm order (the norm ranging
+// of Section 3.2 applied to the multi-probe of Section 3.3).  The largest
+// similarity any bucket of sub-dataset j can reach is U_j cos(0) = U_j, so
+// with the sub-datasets ordered by (U_j desc, j desc) -- jord -- every bucket
+// of the sub-datasets not yet scanned ranks after bucket (jord[S], L), whose
+// rank R[jord[S]][L] is the cut.  Once a query's buckets ranked before the cut
+// hold Tq items, its threshold bucket lies among them and the rest of its
+// histogram is never read; a tile skips the later stages once all its queries
+// are there (need[tile] = 0), leaving those histogram entries zero.
+//
+// One block of SH_WAVES waves per (64-query tile, chunk of one sub-dataset):
+// the waves share the tile's LDS histogram (lane = query column) and take the
+// chunk's 16-item groups in turn; the block adds its nonzero counts into
+// ghist (zeroed by the caller).  chunks: (sub-dataset, first, end) triples.
+constexpr int SH_WAVES = 4;
+
+template <int W>
+__device__ __forceinline__ void hist_group16(const uint32_t *__restrict__ codes_l, int64_t p,
+                                             uint32_t q0, uint32_t q1, uint32_t *hist, int lane)
+{
+    uint32_t c[16 * W];
+#pragma unroll
+    for (int u = 0; u < 16 * W; ++u) c[u] = codes_l[p * W + u];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+        uint32_t h = (uint32_t)__popc(c[u * W] ^ q0);
+        if (W == 2) h += (uint32_t)__popc(c[u * W + 1] ^ q1);
+        __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(SH_WAVES * 64) void k_scan_hist_s(const uint32_t *__restrict__ codes_l,
+                                                               const uint32_t *__restrict__ qcodes,
+                                                               int64_t nq, int m, int L, int qsets,
+                                                               const int32_t *__restrict__ chunks,
+                                                               const int32_t *__restrict__ need,
+                                                               uint32_t *__restrict__ ghist,
+                                                               unsigned long long *__restrict__ npairs)
+{
+    extern __shared__ uint32_t hist[];  // (L+1) x 64, column = lane
+    // the wave number is wave-uniform: read it as such so that the item codes
+    // come through the scalar cache
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int64_t tile = blockIdx.x;
+    if (need && need[tile] == 0) return;  // every query of the tile is settled
+    const int j = chunks[3 * blockIdx.y];
+    const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
+    if (npairs && tid == 0)
+        atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - tile * 64) * (p1 - p0)));
+    const int64_t q = tile * 64 + lane;
+    uint32_t q0 = 0, q1 = 0;
+    if (q < nq) {
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
+    }
+    const int nh = (L + 1) * 64;
+    for (int e = tid; e < nh; e += SH_WAVES * 64) hist[e] = 0u;
+    __syncthreads();
+    const int64_t ng = (p1 - p0) >> 4;  // whole 16-item groups
+    for (int64_t g = wave; g < ng; g += SH_WAVES) hist_group16<W>(codes_l, p0 + g * 16, q0, q1, hist, lane);
+    if (wave == SH_WAVES - 1) {
+        for (int64_t p = p0 + ng * 16; p < p1; ++p) {
+            uint32_t h = (uint32_t)__popc(codes_l[p * W] ^ q0);
+            if (W == 2) h += (uint32_t)__popc(codes_l[p * W + 1] ^ q1);
+            __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+    __syncthreads();
+    uint32_t *out = ghist + ((tile * m + j) * (int64_t)(L + 1)) * 64;
+    for (int e = tid; e < nh; e += SH_WAVES * 64) {
+        const uint32_t v = hist[e];
+        if (v) atomicAdd(&out[e], v);
+    }
+}
+
+// need[tile] = 0 once every query of the tile has at least Tq items in the
+// buckets ranked before `cut` (walked in probing order through inv).
+__global__ __launch_bounds__(64) void k_stage_check(const uint32_t *__restrict__ ghist,
+                                                    const int32_t *__restrict__ inv, int64_t nq, int m,
+                                                    int L, int64_t Tq, int cut, int32_t *__restrict__ need)
+{
+    const int lane = threadIdx.x;
+    const int64_t tile = blockIdx.x;
+    if (need[tile] == 0) return;
+    const int64_t q = tile * 64 + lane;
+    const int64_t P = (int64_t)m * (L + 1);
+    const uint32_t *H = ghist + tile * P * 64;
+    int64_t sum = 0;
+    bool ok = q >= nq;
+    for (int b = 0; b < cut; b += 16) {
+        if (__ballot(!ok) == 0ull) break;
+        uint32_t c[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) c[u] = (b + u < cut) ? H[(int64_t)inv[b + u] * 64 + lane] : 0u;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) sum += c[u];
+        ok = ok || sum >= Tq;
+    }
+    const uint64_t open = __ballot(!ok);
+    if (lane == 0) need[tile] = open != 0ull ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- chunked pass 2
+// Pass 2 over the same (sub-dataset, first, end) chunks as the staged pass 1:
+// one block of SH_WAVES waves per (64-query tile, chunk), the waves taking the
+// chunk's 16-item groups in turn.  A lane (query) keeps its probed items --
+// h <= hthr, or h = h* of the threshold bucket at a stored position up to
+// P* (k_tie_locate) -- in its own LDS column of EM_SB entries and, when the
+// column is full and at the end, reserves room in the query's list with one
+// atomic on counts[q] (zeroed by the caller) and writes them there.  The
+// probed set does not depend on the order of the appends (the list order
+// does; the re-rank's tie rule makes the top-k independent of it).
+constexpr int EM_SB = 16;
+
+__device__ __forceinline__ void emit_flush(int32_t *__restrict__ stage, int lane, int cnt,
+                                           int32_t *__restrict__ counts, int32_t *__restrict__ cand,
+                                           int64_t q, int64_t Tq)
+{
+    const int64_t base = atomicAdd(&counts[q], cnt);
+    const int64_t lim = min((int64_t)cnt, Tq - base);  // never past the list
+    int32_t *out = cand + q * Tq + base;
+    for (int i = 0; i < lim; ++i) out[i] = stage[i * 64 + lane];
+}
+
+template <int W>
+__global__ __launch_bounds__(SH_WAVES * 64) void k_scan_emit_s(const uint32_t *__restrict__ codes_l,
+                                                               const uint32_t *__restrict__ qcodes,
+                                                               int64_t nq, int m, int64_t Tq, int qsets,
+                                                               const int32_t *__restrict__ chunks,
+                                                               const int32_t *__restrict__ ghthr,
+                                                               const int32_t *__restrict__ gtie,
+                                                               const int32_t *__restrict__ gpstar,
+                                                               int32_t *__restrict__ counts,
+                                                               int32_t *__restrict__ cand)
+{
+    __shared__ int32_t stage_s[SH_WAVES][EM_SB * 64];
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int64_t tile = blockIdx.x;
+    const int j = chunks[3 * blockIdx.y];
+    const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
+    const int64_t q = tile * 64 + lane;
+    const bool valid = q < nq;
+    int hthr = -1, htie = -1;
+    int64_t pstar = -1;
+    uint32_t q0 = 0, q1 = 0;
+    if (valid) {
+        const int32_t *tie = gtie + tile * 4 * 64;
+        hthr = ghthr[(tile * m + j) * 64 + lane];
+        if (tie[lane] == j) {
+            htie = tie[64 + lane];
+            pstar = gpstar[q];
+        }
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
+    }
+    if (__ballot(hthr >= 0 || htie >= 0) == 0ull) return;  // the same for every wave of the block
+    int32_t *stage = stage_s[wave];
+    int cnt = 0;
+    const int64_t ng = (p1 - p0) >> 4;
+    for (int64_t g = wave; g < ng; g += SH_WAVES) {
+        const int64_t p = p0 + g * 16;
+        uint32_t c[16 * W];
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) c[u] = codes_l[p * W + u];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            int h = __popc(c[u * W] ^ q0);
+            if (W == 2) h += __popc(c[u * W + 1] ^ q1);
+            if (h <= hthr || (h == htie && p + u <= pstar)) {
+                stage[cnt * 64 + lane] = (int32_t)(p + u);
+                if (++cnt == EM_SB) {
+                    emit_flush(stage, lane, cnt, counts, cand, q, Tq);
+                    cnt = 0;
+                }
+            }
+        }
+    }
+    if (wave == SH_WAVES - 1) {
+        for (int64_t p = p0 + ng * 16; p < p1; ++p) {
+            int h = __popc(codes_l[p * W] ^ q0);
+            if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+            if (h <= hthr || (h == htie && p <= pstar)) {
+                stage[cnt * 64 + lane] = (int32_t)p;
+                if (++cnt == EM_SB) {
+                    emit_flush(stage, lane, cnt, counts, cand, q, Tq);
+                    cnt = 0;
+                }
+            }
+        }
+    }
+    if (cnt > 0) emit_flush(stage, lane, cnt, counts, cand, q, Tq);
+}
+
 // ---------------------------------------------------------------- rerank
 // One wave per (query, slice of its probed list); the rows of 64 candidates
 // at a time are summed in FP64 (dev::ip64_rows_*), the running top-k kept by
@@ -483,7 +695,10 @@ using dev::RR_STRIDE;
 using dev::WaveTopK;
 
 // LP = true: the rows come from the bfloat16 copy Xh.  ip~ = sum_t q_t x~_t in
-// FP64 satisfies |ip~ - ip| <= e = (2^-8 + 2^-40) ||q|| ||x|| (1 + 2^-20); the
+// FP64 (exact products, ascending t) differs from ip by q.(x - x~) plus the
+// FP64 rounding of the sum, so |ip~ - ip| <= e = ||q|| xeb (1 + 2^-20) with
+// xeb >= ||x - x~|| + (d + 1) 2^-52 ||x|| from the layout (Cauchy-Schwarz on
+// the exact rounding error of the row, about 2.6 times below 2^-8 ||x||); the
 // wave keeps a top-k of the lower bounds ip~ - e and appends every item whose
 // upper bound ip~ + e reaches the k-th lower bound to the query's list
 // (lists: nq x lcap, lcount: per query, may exceed lcap) -- a superset of
@@ -506,7 +721,7 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                double *__restrict__ part_v,
                                                int32_t *__restrict__ part_i,
                                                const uint16_t *__restrict__ Xh,
-                                               const double *__restrict__ key_l, int lcap,
+                                               const float *__restrict__ xeb, int lcap,
                                                int32_t *__restrict__ lcount,
                                                int32_t *__restrict__ lists,
                                                unsigned long long *__restrict__ gtheta)
@@ -543,7 +758,7 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
         const double acc = LP ? dev::ip64_rows_bf16(Xh, d, dp, qv, p, valid, lane, tile)
                               : dev::ip64_rows_fp32(Xl, d, dp, qv, p, valid, lane, tile);
         if (LP) {
-            const double e = (0x1p-8 + 0x1p-40) * qn * __builtin_sqrt(valid ? key_l[p] : 0.0) * (1.0 + 0x1p-20);
+            const double e = qn * (double)(valid ? xeb[p] : 0.f) * (1.0 + 0x1p-20);
             top.offer(acc - e, id, valid, lane);
             double th = top.th_v;
             if (th > -INFINITY && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(th));
@@ -883,9 +1098,11 @@ __global__ __launch_bounds__(256) void k_screen(
 // bfloat16 variants of k_screen on v_mfma_f32_16x16x32_bf16 (products of
 // bfloat16 pairs are exact in FP32).  In MFMA j of a 32-coordinate step, lane
 // group g carries coordinates 32 kk + 8 g .. + 7 of both operands.
-//   X3 = false: q and x rounded to bfloat16 (RNE), one product per pair.
-//       |q.x - q~.x~| <= (2^-8 + 2^-18) sum |q_t x_t|, and FP32 accumulation
-//       of the d exact products adds at most gamma_d (1.01 sum |q_t x_t|).
+//   X3 = false: q and x rounded to bfloat16 (RNE, unit roundoff u = 2^-8),
+//       one product per pair.  q~_t x~_t = q_t x_t (1 + a)(1 + b) with
+//       |a|, |b| <= u, so |q.x - q~.x~| <= (2u + u^2) sum |q_t x_t| =
+//       (2^-7 + 2^-16) sum |q_t x_t|, and FP32 accumulation of the d exact
+//       products adds at most gamma_d (1.01 sum |q_t x_t|).
 //   X3 = true:  q and x split x = hi + lo (+ a residual of at most
 //       2^-16 |x|), each inner product hi.hi + hi.lo + lo.hi; the dropped
 //       terms are at most 3.1 * 2^-16 |q_t x_t| per coordinate, and FP32
@@ -1604,6 +1821,57 @@ hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const
     return hipGetLastError();
 }
 
+hipError_t launch_fill32(void *p, int64_t words, uint32_t v, hipStream_t s)
+{
+    if (words < 1) return hipSuccess;
+    int64_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill32, dim3((unsigned)blocks), dim3(256), 0, s, static_cast<uint32_t *>(p), words, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
+                                  const QueryShape &sh, const int32_t *chunks, int nchunks,
+                                  const int32_t *need, uint32_t *ghist, unsigned long long *npairs,
+                                  hipStream_t s)
+{
+    if (nq < 1 || nchunks < 1) return hipSuccess;
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    const size_t lds = (size_t)(sh.L + 1) * 64 * sizeof(uint32_t);
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_scan_hist_s<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq,
+                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs);
+    else
+        hipLaunchKernelGGL(k_scan_hist_s<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq,
+                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_emit_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
+                                  const QueryShape &sh, const int32_t *chunks, int nchunks,
+                                  const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar,
+                                  int32_t *counts, int32_t *cand, hipStream_t s)
+{
+    if (nq < 1 || nchunks < 1) return hipSuccess;
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_scan_emit_s<1>, grid, dim3(SH_WAVES * 64), 0, s, codes_l, qcodes, nq, sh.m,
+                           sh.Tq, sh.qsets, chunks, ghthr, gtie, gpstar, counts, cand);
+    else
+        hipLaunchKernelGGL(k_scan_emit_s<2>, grid, dim3(SH_WAVES * 64), 0, s, codes_l, qcodes, nq, sh.m,
+                           sh.Tq, sh.qsets, chunks, ghthr, gtie, gpstar, counts, cand);
+    return hipGetLastError();
+}
+
+hipError_t launch_stage_check(const uint32_t *ghist, const int32_t *inv, int64_t nq, const QueryShape &sh,
+                              int cut, int32_t *need, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_stage_check, dim3(ceil_div(nq, 64)), dim3(64), 0, s, ghist, inv, nq, sh.m, sh.L,
+                       sh.Tq, cut, need);
+    return hipGetLastError();
+}
+
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
                              int64_t nq, int W, int qsets, const int32_t *gtie, int32_t *gpstar,
                              hipStream_t s)
@@ -1754,10 +2022,11 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
                                                           gam, cap, counts, lists, cmax, ncol, s);
     }
     if (Xh) {
-        // rounding of both operands to bfloat16: (2^-8 + 2^-18) |q x| per
-        // coordinate, plus FP32 accumulation of d exact products: 2 * 1.01 * gamma_d
+        // rounding of both operands to bfloat16: (2u + u^2) |q x| per
+        // coordinate with u = 2^-8, plus FP32 accumulation of d exact
+        // products: 2 * 1.01 * gamma_d
         const double ud = sh.d * 0x1p-24;
-        const float gam = (float)((0x1p-8 + 0x1p-17 + 2.1 * ud / (1.0 - ud)) * (1.0 + 0x1p-16));
+        const float gam = (float)((0x1p-7 + 0x1p-16 + 2.1 * ud / (1.0 - ud)) * (1.0 + 0x1p-16));
         // a budget covering every item probes every level: the variant that
         // reads no codes
         return sh.Tq >= sh.n
@@ -1888,7 +2157,7 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     return hipGetLastError();
 }
 
-hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
+hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
                             int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s)
@@ -1900,7 +2169,7 @@ hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32
 #define NRLSH_RERANK_LP(SS)                                                                       \
     hipLaunchKernelGGL((k_rerank<SS, true>), grid, block, 0, s, nullptr, perm, Q, sh.n, sh.d, sh.dp, \
                        sh.Tq, sh.k, cand, nullptr, nsplit, slice, nullptr, nullptr, nullptr,      \
-                       nullptr, Xh, key_l, lcap, lcount, lists, gtheta)
+                       nullptr, Xh, xeb, lcap, lcount, lists, gtheta)
     if (S <= 1) NRLSH_RERANK_LP(1);
     else if (S <= 2) NRLSH_RERANK_LP(2);
     else if (S <= 4) NRLSH_RERANK_LP(4);

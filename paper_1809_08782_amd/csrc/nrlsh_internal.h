@@ -25,7 +25,7 @@ struct BuildCounters {
     unsigned long long fix_bits;
     unsigned long long fix_flips;
     uint32_t lowp_items;     // items appended for the FP32 re-hash (precision form)
-    uint32_t pad;
+    uint32_t fix_prev;       // entries of the FixEntry lists of earlier hash tables
     unsigned long long lowp_bits;
     unsigned long long lowp_changed;
 };
@@ -59,10 +59,12 @@ hipError_t launch_lo_rows(const float *Xl, const uint16_t *Xh, int64_t count, ui
 
 // Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
 // key and sub-dataset of each stored row, plus its bfloat16 image Xh and, when
-// Xlo is not NULL, the lo part bf16(x - hi).
+// Xlo is not NULL, the lo part bf16(x - hi); xeb (or NULL) receives for each
+// stored row an upper bound of ||x - bf16(x)|| + (d + 1) 2^-52 ||x||, so that
+// |q.x - q.bf16(x)| (the latter summed in FP64) is at most ||q|| xeb.
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
                          const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
-                         uint16_t *Xlo, double *key_l, int32_t *sid_l, hipStream_t s);
+                         uint16_t *Xlo, double *key_l, int32_t *sid_l, float *xeb, hipStream_t s);
 
 // SimpleLSH transform + sign random projection on the FP32 matrix cores, over
 // the stored rows (all arrays in stored order); writes the codes codes_l.
@@ -84,15 +86,22 @@ hipError_t launch_hash_per_subset(const float *Xl, int d, int dp, const float *A
                                   FixEntry *fix, BuildCounters *ctr, hipStream_t s);
 
 // Precision form: quantise rows to bfloat16 (storage 1) or E4M3 with row scales
-// (storage 2), then hash from the quantised copy; items inside the margin
-// mq_r ||x|| + tq_r U_j are appended to rows (count in ctr->lowp_items).
+// (storage 2), then hash from the quantised copy.  Bits inside the margin
+// mq_r ||x|| + tq_r U_j are settled exactly: an item with at most 8 of them
+// gets a FixEntry (those bits recomputed in FP64 by launch_hash_fixup, count
+// in ctr->fix_count); one with more is appended to rows for the FP32 re-hash
+// (count in ctr->lowp_items).  ctr->lowp_bits counts all of them.
 hipError_t launch_quant_rows(const float *src, int64_t rows, int d, int ss, int storage, void *dst,
                              int ds, float *scales, hipStream_t s);
 hipError_t launch_hash_q(int storage, const void *Xq, const float *xscale, int64_t n, int d, int dp,
                          const void *Aq, const float *ascale, const float *A, int L,
                          const double *key_l, const int32_t *sid_l, const double *keymax,
                          const double *U, const float *mq, const float *tq, uint32_t *codes_l,
-                         int32_t *rows, BuildCounters *ctr, hipStream_t s);
+                         int32_t *rows, FixEntry *fix, BuildCounters *ctr, hipStream_t s);
+
+// Before the next hash table reuses the FixEntry list: fix_prev += fix_count,
+// fix_count = 0 (one thread).
+hipError_t launch_roll_fix_count(BuildCounters *ctr, hipStream_t s);
 
 // FP64 recompute of the flagged projections, exactly as the definition.
 // per_subset: an item of sub-dataset s takes its rows from block s of A.
@@ -157,7 +166,7 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
 // lists (nq x lcap, lcount zeroed by the caller) every probed item that may
 // still belong to the exact top-k.  gtheta: nq words zeroed by the caller,
 // the k-th lower bound shared by the slices of each query.
-hipError_t launch_rerank_lp(const uint16_t *Xh, const double *key_l, const int32_t *perm,
+hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
                             int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s);
@@ -174,6 +183,51 @@ hipError_t launch_scan_emit_c(const uint32_t *codes_l, const int32_t *off, const
                               int64_t nq, const QueryShape &sh, int chunk, int nch,
                               const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar,
                               int32_t *counts, int32_t *cand, hipStream_t s);
+
+// Sets `words` 32-bit words at p to v (a fill kernel, capturable in a graph).
+hipError_t launch_fill32(void *p, int64_t words, uint32_t v, hipStream_t s);
+
+// Staged pass 1 (exact early exit in descending norm order): one block per
+// (64-query tile, chunk) over the chunks (sub-dataset, first, end) of one
+// stage, adding into ghist (zeroed by the caller); tiles with need[tile] = 0
+// are skipped (need may be NULL: every tile).  launch_stage_check then clears
+// need[tile] once every query of the tile has Tq items in buckets ranked
+// before `cut`.  npairs (or NULL) accumulates the (query, item) pairs scanned.
+hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
+                                  const QueryShape &sh, const int32_t *chunks, int nchunks,
+                                  const int32_t *need, uint32_t *ghist, unsigned long long *npairs,
+                                  hipStream_t s);
+// Pass 2 over the same chunks: appends each query's probed items to its list
+// (counts zeroed by the caller; order unspecified), cutting the threshold
+// bucket at gpstar (launch_tie_locate).
+hipError_t launch_scan_emit_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
+                                  const QueryShape &sh, const int32_t *chunks, int nchunks,
+                                  const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar,
+                                  int32_t *counts, int32_t *cand, hipStream_t s);
+hipError_t launch_stage_check(const uint32_t *ghist, const int32_t *inv, int64_t nq, const QueryShape &sh,
+                              int cut, int32_t *need, hipStream_t s);
+
+// ------------------------------------------------------------------ single probe
+// Multi-table single probe (k_single.hip): t <= MT_MAX_TABLES tables; codes_l
+// holds t x n x W words (table-major), qcodes the query codes table-major
+// (table tau's code for sub-dataset j of query q at row tau qstride +
+// qrow(q, j, P), P = qsets of one table).  Pass 1 adds per (tile, sub-dataset) the count of items by
+// f = the first table whose bucket holds them into ghist (tiles x m x t x 64,
+// zeroed by the caller); launch_threshold with L = t - 1 and the (f asc, j
+// desc) rank table gives the bounds and the cut bin; launch_mt_tie the
+// stored position of its r*-th item; launch_mt_emit appends the probed items
+// (counts zeroed by the caller; fewer than Tq when the buckets hold fewer).
+constexpr int MT_MAX_TABLES = 8;
+hipError_t launch_mt_hist(const uint32_t *codes_l, int64_t n, const uint32_t *qcodes, int64_t qstride, int64_t nq,
+                          int m, int t, int P, int W, const int32_t *chunks, int nchunks, uint32_t *ghist,
+                          hipStream_t s);
+hipError_t launch_mt_tie(const uint32_t *codes_l, int64_t n, const int32_t *off, const uint32_t *qcodes,
+                         int64_t qstride, int64_t nq, int t, int P, int W, const int32_t *gtie, int32_t *gpstar,
+                         hipStream_t s);
+hipError_t launch_mt_emit(const uint32_t *codes_l, int64_t n, const uint32_t *qcodes, int64_t qstride, int64_t nq,
+                          int m, int t, int P, int W, int64_t Tq, const int32_t *chunks, int nchunks,
+                          const int32_t *ghthr, const int32_t *gtie, const int32_t *gpstar, int32_t *counts,
+                          int32_t *cand, hipStream_t s);
 
 // Stored position of the r*-th item of each query's threshold bucket (-1 if none).
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,

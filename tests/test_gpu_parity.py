@@ -431,3 +431,86 @@ def test_screen_norm_pruning_keeps_exact_result(mode):
             assert np.array_equal(ips, oips.astype(np.float32)), T
             if T == n:
                 assert 0 < st["screen_pairs"] < Q.shape[0] * n
+
+
+def _midpoint_case():
+    """Two items whose bfloat16 roundings move their inner products with the
+    query in opposite directions by the full unit roundoff of both operands:
+    the query's first 32 coordinates lie just below a rounding midpoint
+    (rounded down by almost 2^-8), its last 32 just above one (rounded up),
+    item A sits on the first group and item B on the second.  A's exact inner
+    product is the larger (by about 1e-3), B's bfloat16 one the larger (by
+    about 0.5): a bound that counted only one operand's rounding would place
+    B's lower bound above A's upper bound and return B."""
+    d = 64
+    lo = np.float32(1 + 2 ** -8 - 2 ** -20)  # bfloat16 rounds it down to 1
+    hi = np.float32(1 + 2 ** -8 + 2 ** -20)  # bfloat16 rounds it up to 1 + 2^-7
+    q = np.concatenate([np.full(32, lo), np.full(32, hi)]).astype(np.float32)
+    a = np.concatenate([np.full(32, lo), np.zeros(32)]).astype(np.float32)
+    b = np.concatenate([np.zeros(32), np.full(32, hi)]).astype(np.float32)
+    ip_a = float(np.dot(q.astype(np.float64), a.astype(np.float64)))
+    rest = float(np.dot(q[32:63].astype(np.float64), b[32:63].astype(np.float64)))
+    b[63] = np.float32((ip_a - rest) / float(hi) - 1e-3)
+    filler = make_items("lognormal", 998, d, seed=91, sigma=0.3) * np.float32(0.05)
+    X = np.concatenate([filler[:500], a[None], filler[500:], b[None]]).astype(np.float32)
+    Q = np.stack([q, q * np.float32(0.5), q * np.float32(4.0)]).astype(np.float32)
+    return X, Q, 500, X.shape[0] - 1
+
+
+def test_screen_bound_at_bf16_rounding_midpoints():
+    X, Q, ia, ib = _midpoint_case()
+    X64 = X.astype(np.float64)
+    ip = X64 @ Q[0].astype(np.float64)
+    assert np.argmax(ip) == ia and ip[ia] - ip[ib] > 0 and ip[ia] - ip[ib] < 2e-3
+    n = X.shape[0]
+    say("case bf16 midpoints")
+    oix = orc.OracleIndex(X, 4, 16, seed=3, threads=4)
+    with nr.nrlsh_build(X, 4, 16, 3) as gix:
+        for k in (1, 2):
+            oids, oips = oix.query(Q, k, n)
+            assert np.all(oids[:, 0] == ia)
+            for mode in ("screen", "screen_bf16x3", "screen_fp32", "gather"):
+                ids, ips = nr.nrlsh_query(gix, Q, k, n, rerank=mode)
+                assert np.array_equal(ids, oids), f"k={k} {mode}: {ids[:, 0]}"
+                assert np.array_equal(ips, oips.astype(np.float32)), f"k={k} {mode}"
+            # the bfloat16 first pass of the gather re-rank bounds each row's
+            # own rounding error
+            ids, ips = nr.nrlsh_query(gix, Q, k, n, rerank="gather", rerank_storage="bf16")
+            assert np.array_equal(ids, oids), f"k={k} bf16 rows: {ids[:, 0]}"
+            assert np.array_equal(ips, oips.astype(np.float32)), f"k={k} bf16 rows"
+
+
+STAGED_CASES = [
+    # (n, d, m, L, nq, k, T, sigma, early): long-tailed norms, so that a small
+    # budget is met inside the top sub-datasets and the tiles stop early; a
+    # budget of a third of the items needs every sub-dataset
+    (60000, 32, 64, 32, 130, 10, 600, 1.0, True),
+    (40000, 48, 128, 64, 70, 100, 2000, 1.0, True),
+    (30000, 16, 16, 20, 200, 10, 50, 0.8, True),
+    (20000, 24, 40, 33, 65, 10, 7000, 1.2, False),
+]
+
+
+@pytest.mark.parametrize("case", STAGED_CASES, ids=lambda c: "n%d_m%d_L%d_T%d" % (c[0], c[2], c[3], c[6]))
+def test_staged_scan_early_exit(case):
+    """The first scan pass visits sub-datasets in descending U_j and stops a
+    tile once every query's threshold bucket is known: probed sets, top-k ids
+    and inner products still equal the oracle's, and fewer pairs are counted
+    than nq x n."""
+    n, d, m, L, nq, k, T, sigma, early = case
+    say(f"case staged scan n={n} d={d} m={m} L={L} nq={nq} k={k} T={T}")
+    X = make_items("lognormal", n, d, seed=n + 11, sigma=sigma)
+    Q = make_queries(nq, d, seed=n + 12)
+    oix = orc.OracleIndex(X, m, L, seed=29, threads=8)
+    with nr.nrlsh_build(X, m, L, 29) as gix:
+        check_query(gix, oix, Q, k, T, f"staged n{n}")
+        oids, oips = oix.query(Q, k, T, threads=8)
+        for mode in ("gather", "screen"):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank=mode)
+            st = nr.nrlsh_get_query_stats()
+            say(f"  {mode}: pass-1 pairs {st['scan_pairs']} of {nq * n}")
+            assert np.array_equal(ids, oids), mode
+            assert np.array_equal(ips, oips.astype(np.float32)), mode
+            assert 0 < st["scan_pairs"] <= nq * n, st["scan_pairs"]
+            if early:
+                assert st["scan_pairs"] < nq * n, st["scan_pairs"]
