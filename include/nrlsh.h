@@ -241,6 +241,30 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
                             int64_t probe_budget, const nrlsh_query_opts *opts,
                             int64_t *out_ids, float *out_ips);
 
+/* ------------------------------------------------------ query, no allocation --
+ * nrlsh_query_noalloc: for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): the query of nrlsh_query_ex with device pointers, the linear
+ * scan probe and the FP32 gather re-rank, with every temporary buffer taken
+ * from a device scratch array of 64 MiB that the library holds on each device
+ * it runs on until the process ends.  It calls no allocation routine, copies
+ * nothing between host and device and does not synchronise: it queues kernels
+ * on `stream` (a hipStream_t; NULL is the default stream) and returns.
+ *   queries    nq x d float32, device pointer, finite (else *nonfinite != 0)
+ *   out_ids    nq x k int64, out_ips nq x k float32, device pointers
+ *   nonfinite  one device word, set to 0 and then to nonzero when a query
+ *              holds NaN or Inf (the results of such a call are unspecified)
+ * Queries are processed in batches of the largest multiple of 64 whose
+ * buffers fit the scratch; NRLSH_E_INVALID_ARG (before any device work) when
+ * even 64 queries do not fit, i.e. when 64 probed lists of min(T, n) entries
+ * plus 64 histograms of m (L + 1) bins exceed it (roughly T > 2e5 at
+ * m = 128, L = 64, k = 100).  All calls on one device share its scratch: calls that
+ * overlap on one device (different streams, or host threads) race and must
+ * be ordered by the caller.  Results equal those of nrlsh_query_ex. */
+nrlsh_status nrlsh_query_noalloc(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                                 int64_t probe_budget, void *stream, int64_t *out_ids, float *out_ips,
+                                 uint32_t *nonfinite);
+
 /* ------------------------------------------------------- batching form --
  * Many indexes (uneven n, d, L, m), each with its own query batch (uneven nq)
  * and probe budget, served together.  Each (index, batch) pair gets exactly

@@ -112,6 +112,8 @@ def lib():
         L.nrlsh_query.restype = st
         L.nrlsh_query_ex.argtypes = [P, P, I64, I32, I64, C.POINTER(QueryOpts), P, P]
         L.nrlsh_query_ex.restype = st
+        L.nrlsh_query_noalloc.argtypes = [P, P, I64, I32, I64, P, P, P, P]
+        L.nrlsh_query_noalloc.restype = st
         L.nrlsh_last_error.argtypes = []
         L.nrlsh_last_error.restype = C.c_char_p
         L.nrlsh_index_info.argtypes = [P, C.POINTER(I64), C.POINTER(I32), C.POINTER(I32),
@@ -414,6 +416,22 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
         _check(lib().nrlsh_query(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                  ids.ctypes.data, ips.ctypes.data))
     return ids, ips
+
+
+def nrlsh_query_noalloc(ix: Index, queries, k: int, probe_budget: int, out, nonfinite, stream=None):
+    """The query of nrlsh_query with every temporary buffer taken from the
+    library's device scratch (no allocation, no copy, no synchronisation).
+    ``queries``: CUDA torch tensor (nq, d) float32; ``out``: (ids int64,
+    ips float32) CUDA tensors (nq, k); ``nonfinite``: a CUDA int32 tensor of one
+    element, set nonzero when a query holds NaN or Inf.  Work is queued on
+    ``stream`` (default: torch's current stream) and the call returns."""
+    if not _is_torch_device(queries):
+        raise ValueError("queries must be a CUDA tensor (device pointers only)")
+    Q = queries.contiguous()
+    ids, ips = out
+    _check(lib().nrlsh_query_noalloc(ix.handle, P(Q.data_ptr()), Q.shape[0], k, int(probe_budget),
+                                     stream or _torch_stream(Q), P(ids.data_ptr()), P(ips.data_ptr()),
+                                     P(nonfinite.data_ptr())))
 
 
 class MultiPlan:

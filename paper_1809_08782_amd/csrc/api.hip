@@ -529,7 +529,8 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
                  oR = B.reserve<int32_t>((size_t)m * (L + 1)),
                  oinv = B.reserve<int32_t>((size_t)m * (L + 1)),
                  ocodes = B.reserve<uint32_t>((size_t)n * W * tables), oxeb = B.reserve<float>(n),
-                 oRs = B.reserve<int32_t>((size_t)m * tables), oinvs = B.reserve<int32_t>((size_t)m * tables);
+                 oRs = B.reserve<int32_t>((size_t)m * tables), oinvs = B.reserve<int32_t>((size_t)m * tables),
+                 ost1 = B.reserve<int32_t>(3 * ((size_t)n / 2048 + 2 * (size_t)m + 8));
     // bucket tables: room for n distinct codes (the actual count is known after the build)
     const bool tab = ix->has_table;
     const size_t otc = B.reserve<uint64_t>(tab ? (size_t)n : 1),
@@ -556,6 +557,7 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
     ix->xeb = B.view<float>(oxeb);
     ix->Rs = B.view<int32_t>(oRs);
     ix->invs = B.view<int32_t>(oinvs);
+    ix->st1_chunks_d = B.view<int32_t>(ost1);
     if (tab) {
         ix->ucode = B.view<uint64_t>(otc);
         ix->ustart = B.view<int32_t>(ots);
@@ -733,7 +735,18 @@ void build_index(nrlsh_index *ix, const float *items, bool on_device, hipStream_
         off32[j + 1] = (int32_t)ix->off_h[j + 1];
     }
     if (ix->off_h[m] != n) throw Failure{NRLSH_E_INTERNAL, "sub-dataset runs do not cover the items"};
-
+    // the staged-scan plan of a single 64-query tile, kept with the index for
+    // the query entry point that allocates nothing
+    {
+        ScanStages p1 = scan_stages(ix, 1);
+        if (p1.chunks.size() > 3 * ((size_t)n / 2048 + 2 * (size_t)m + 8))
+            throw Failure{NRLSH_E_INTERNAL, "scan plan exceeds its reserved room"};
+        ix->st1_chunks = std::move(p1.chunks);
+        ix->st1_cbeg = std::move(p1.cbeg);
+        ix->st1_cut = std::move(p1.cut);
+        HIPX(hipMemcpyAsync(ix->st1_chunks_d.get(), ix->st1_chunks.data(), ix->st1_chunks.size() * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s));
+    }
     std::memcpy(pin + p_U, ix->U_h.data(), m * sizeof(double));
     std::memcpy(pin + p_R, ix->R_h.data(), rank_n * sizeof(int32_t));
     std::memcpy(pin + p_inv, inv_h.data(), rank_n * sizeof(int32_t));
@@ -1441,6 +1454,111 @@ uint32_t run_query(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k
     return kFlagUnread;
 }
 
+// ================================================================= query without allocation
+// Device scratch of nrlsh_query_noalloc: a file-scope array that the code
+// object holds on every device it is loaded on, until the process ends.
+// Host code never passes the array's name to a kernel (on the host it is a
+// stand-in, not a device address): hipGetSymbolAddress gives each device its
+// own copy's address once, with that device current, and only that address
+// is used.  Every call on one device shares that device's copy, so calls
+// that overlap on one device race; what must start at zero is cleared by a
+// fill kernel at the start of each batch.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kScratchDevices] = {};
+
+// The calling thread's current device must be `dev`.
+uint8_t *scratch_base(int dev)
+{
+    if (dev < 0 || dev >= kScratchDevices) throw Failure{NRLSH_E_INVALID_ARG, "device id out of range"};
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        HIPX(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Failure{NRLSH_E_DEVICE, "no address for the device scratch"};
+        g_scratch_ptr[dev] = static_cast<uint8_t *>(p);
+    }
+    return g_scratch_ptr[dev];
+}
+
+// Buffers of one batch of B queries of the gather path, laid out in order.
+struct NoAllocLayout {
+    Block blk;
+    size_t qc, gh, ne, gb, th, ti, ca, pv, pi, gt, ps, ct;
+};
+
+void layout_noalloc(NoAllocLayout &a, const QueryShape &sh, int64_t B, int nsplit)
+{
+    const int64_t tiles = B / 64;
+    const int L1 = sh.L + 1;
+    Block &b = a.blk;
+    a.qc = b.reserve<uint32_t>((size_t)B * sh.qsets * sh.W);
+    a.gh = b.reserve<uint32_t>((size_t)tiles * sh.m * L1 * 64);
+    a.ne = b.reserve<int32_t>((size_t)tiles);
+    a.gb = b.reserve<int32_t>((size_t)tiles * (sh.m + 1) * 64);
+    a.th = b.reserve<int32_t>((size_t)tiles * sh.m * 64);
+    a.ti = b.reserve<int32_t>((size_t)tiles * 4 * 64);
+    a.ca = b.reserve<int32_t>((size_t)B * sh.Tq);
+    a.pv = b.reserve<double>(nsplit > 1 ? (size_t)B * nsplit * sh.k : 1);
+    a.pi = b.reserve<int32_t>(nsplit > 1 ? (size_t)B * nsplit * sh.k : 1);
+    a.gt = b.reserve<unsigned long long>((size_t)B);
+    a.ps = b.reserve<int32_t>((size_t)B);
+    a.ct = b.reserve<int32_t>((size_t)B);
+}
+
+// Scratch bytes of a batch of B queries.
+size_t noalloc_bytes(const QueryShape &sh, int64_t B)
+{
+    NoAllocLayout a;
+    layout_noalloc(a, sh, B, rerank_splits(B, sh.Tq));
+    return a.blk.size();
+}
+
+// The gather path (staged scan, threshold, tie location, emission, FP64
+// re-rank) with every buffer carved from the device scratch, in batches of
+// the largest multiple of 64 queries that fits (the caller has checked that
+// 64 do).  Only kernels are queued: no allocation, copy or synchronisation.
+void run_query_noalloc(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_t k, int64_t T,
+                       int64_t *ids_d, float *ips_d, uint32_t *nonfinite_d, hipStream_t s)
+{
+    const QueryShape sh = make_shape(ix, T, k);
+    uint8_t *base = scratch_base(ix->device);
+    int64_t B = std::min<int64_t>(std::max<int64_t>(64, ((int64_t(1) << 29) / sh.Tq) / 64 * 64),
+                                  (nq + 63) / 64 * 64);
+    while (B > 64 && noalloc_bytes(sh, B) > kScratchBytes) B = std::max<int64_t>(64, B / 2 / 64 * 64);
+    const int nsplit = rerank_splits(B, sh.Tq);
+    NoAllocLayout a;
+    layout_noalloc(a, sh, B, nsplit);
+    if (!a.blk.place(base, kScratchBytes))
+        throw Failure{NRLSH_E_INVALID_ARG, "batch does not fit the device scratch"};
+    const Block &b = a.blk;
+    uint32_t *qc = b.view<uint32_t>(a.qc).get(), *ghist = b.view<uint32_t>(a.gh).get();
+    int32_t *need = b.view<int32_t>(a.ne).get(), *gbase = b.view<int32_t>(a.gb).get(),
+            *ghthr = b.view<int32_t>(a.th).get(), *gtie = b.view<int32_t>(a.ti).get(),
+            *cand = b.view<int32_t>(a.ca).get(), *part_i = b.view<int32_t>(a.pi).get(),
+            *gpstar = b.view<int32_t>(a.ps).get(), *ccount = b.view<int32_t>(a.ct).get();
+    double *part_v = b.view<double>(a.pv).get();
+    unsigned long long *gtheta = b.view<unsigned long long>(a.gt).get();
+    const int nchunks = ix->st1_cbeg.back();
+    for (int64_t b0 = 0; b0 < nq; b0 += B) {
+        const int64_t nb = std::min<int64_t>(B, nq - b0);
+        const float *Qb = Qd + b0 * sh.d;
+        HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qc, nonfinite_d, s));
+        run_scan_hist_staged(ix, sh, qc, nb, ix->st1_cbeg, ix->st1_cut, ix->st1_chunks_d.get(), need, ghist,
+                             nullptr, s);
+        HIPX(launch_threshold(ghist, ix->R.get(), ix->inv.get(), nb, sh, gbase, ghthr, gtie, s));
+        HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie, gpstar, s));
+        HIPX(launch_fill32(ccount, nb, 0u, s));
+        HIPX(launch_scan_emit_stage(ix->codes_l.get(), qc, nb, sh, ix->st1_chunks_d.get(), nchunks, ghthr, gtie,
+                                    gpstar, ccount, cand, s));
+        if (nsplit > 1) HIPX(launch_fill32(gtheta, 2 * nb, 0u, s));
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cand, nullptr, nsplit, part_v, part_i,
+                           ids_d + b0 * k, ips_d + b0 * k, s, gtheta));
+    }
+}
+
 }  // namespace
 
 // ================================================================= C ABI
@@ -1647,6 +1765,33 @@ nrlsh_status nrlsh_query(const nrlsh_index *ix, const float *queries, int64_t nq
                          int64_t probe_budget, int64_t *out_ids, float *out_ips)
 {
     return nrlsh_query_ex(ix, queries, nq, k, probe_budget, nullptr, out_ids, out_ips);
+}
+
+nrlsh_status nrlsh_query_noalloc(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
+                                 int64_t probe_budget, void *stream, int64_t *out_ids, float *out_ips,
+                                 uint32_t *nonfinite)
+{
+    nrlsh_status st = validate_query(ix, queries, nq, k, probe_budget, out_ids, out_ips);
+    if (st != NRLSH_OK) return st;
+    if (!nonfinite) return fail(NRLSH_E_INVALID_ARG, "nonfinite is NULL");
+    const QueryShape sh = make_shape(ix, probe_budget, k);
+    const size_t need64 = noalloc_bytes(sh, 64);
+    if (need64 > kScratchBytes)
+        return fail(NRLSH_E_INVALID_ARG,
+                    "a 64-query batch at this budget needs %zu bytes of scratch; the entry point that "
+                    "allocates nothing holds %zu (use nrlsh_query_ex)",
+                    need64, kScratchBytes);
+    g_qstats = nrlsh_query_stats{};
+    g_qstats.mode = NRLSH_RERANK_GATHER;
+    g_qstats.probe_mode = NRLSH_PROBE_SCAN;
+    return guarded([&]() -> nrlsh_status {
+        HIPX(hipSetDevice(ix->device));
+        hipStream_t s = static_cast<hipStream_t>(stream);
+        index_wait(ix, s);
+        HIPX(launch_fill32(nonfinite, 1, 0u, s));
+        if (nq > 0) run_query_noalloc(ix, queries, nq, k, probe_budget, out_ids, out_ips, nonfinite, s);
+        return NRLSH_OK;
+    });
 }
 
 const char *nrlsh_last_error(void) { return g_err.c_str(); }

@@ -58,7 +58,7 @@ void prof_record(const char *name, float ms);
 // stream has been synchronised.
 class Timer {
   public:
-    explicit Timer(hipStream_t s) : s_(s), on_(prof_enabled()) {}
+    explicit Timer(hipStream_t s, bool allow = true) : s_(s), on_(allow && prof_enabled()) {}
     ~Timer()
     {
         for (auto &p : pending_) {
@@ -183,6 +183,15 @@ class Block {
         return off;
     }
     void allocate(hipStream_t s) { mem = DBuf<uint8_t>(size_ ? size_ : 1, s); }
+    // Carves the reserved buffers out of caller-owned memory of `cap` bytes
+    // (256-byte aligned) instead of allocating; false if they do not fit.
+    bool place(uint8_t *base, size_t cap)
+    {
+        if (size_ > cap) return false;
+        mem = DBuf<uint8_t>::view(base);
+        return true;
+    }
+    size_t size() const { return size_; }
     template <typename T>
     DBuf<T> view(size_t off) const
     {
@@ -244,6 +253,11 @@ struct nrlsh_index {
     // single probe, m x tables (level index tables - 1 - f), and its inverse
     std::vector<int32_t> Rs_h;
     nrlsh::host::DBuf<int32_t> Rs, invs;
+    // staged-scan plan of one 64-query tile (chunk triples, stage starts, cut
+    // ranks), read by the query entry point that allocates nothing
+    std::vector<int32_t> st1_chunks;
+    std::vector<int> st1_cbeg, st1_cut;
+    nrlsh::host::DBuf<int32_t> st1_chunks_d;
     // (k, Tq) of the last call whose bfloat16 re-rank lists overflowed, packed
     // k << 32 | Tq (0: none): calls with at least that k and budget skip the
     // bfloat16 pass (a speed hint only; results never depend on it)
