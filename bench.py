@@ -450,13 +450,17 @@ def main():
         W = (w.L + 31) // 32
         st = hr["query_stats"]
         pairs = st.get("scan_pairs") or 0
-        # the stats are the last query call's (one batch of qb queries)
+        # the stats are the last query call's: the last batch, of nq - (calls - 1) qb queries
+        last_nq = w.nq - (-(-w.nq // qb) - 1) * qb
+        frac = pairs / (last_nq * w.n)
         per = kern["scan_hist"]
+        step_pairs = frac * w.nq * w.n  # pass-1 pairs of the whole step, at the last batch's fraction
         scan = {"pairs_counted_last_batch": pairs,
-                "pairs_all_last_batch": min(qb, w.nq) * w.n,
-                "counted_fraction": pairs / (min(qb, w.nq) * w.n),
+                "last_batch_queries": last_nq,
+                "pairs_all_last_batch": last_nq * w.n,
+                "counted_fraction": frac,
                 "pass1_ms_per_step": per["ms_per_step"],
-                "pass1_pairs_per_s": (pairs * (w.nq / min(qb, w.nq))) / (per["ms_per_step"] * 1e-3) if pairs else None,
+                "pass1_pairs_per_s": step_pairs / (per["ms_per_step"] * 1e-3) if pairs else None,
                 "int_ops_per_pair": 2 * W + 1,
                 "pass2_ms_per_step": kern.get("scan_emit", {}).get("ms_per_step"),
                 "code_stream_GBps": (w.nq * w.n * 4 * W) / (per["ms_per_step"] * 1e-3) / 1e9}
@@ -540,11 +544,13 @@ def roofline(dom, kern, w, Tq, qb, qstats):
     W = (w.L + 31) // 32
     if dom in ("rerank", "rerank_lp"):
         # per probed item: its row (4d FP32 / 2d bf16 bytes), its stored
-        # position and original id (8); the bf16 pass also reads the key (8)
-        row = 4 * w.d if dom == "rerank" else 2 * w.d + 8
+        # position and original id (8); the bf16 pass also reads the row's
+        # error bound (4)
+        row = 4 * w.d if dom == "rerank" else 2 * w.d + 4
         bytes_launch = nq_launch * Tq * (row + 8)
         achieved = bytes_launch / (per["avg_ms"] * 1e-3) / 1e9
-        kname = {"rerank": "k_rerank<2, false>", "rerank_lp": "k_rerank<2, true>"}[dom]
+        S = next(v for v in (1, 2, 4, 8, 16) if v * 64 >= w.k or v == 16)  # top-k registers per lane
+        kname = ("k_rerank<%d>" if dom == "rerank" else "k_rerank_bf16<%d>") % S
         rec = traffic_record(kname, w.name, Tq)
         return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,

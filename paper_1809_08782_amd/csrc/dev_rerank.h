@@ -20,7 +20,6 @@ namespace nrlsh {
 namespace dev {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
-typedef uint16_t u16x8 __attribute__((ext_vector_type(8)));
 
 constexpr int RR_STRIDE = 36;  // floats per LDS row (16-byte aligned, conflict-free b128)
 constexpr int RR_TILE_FLOATS = 64 * RR_STRIDE;
@@ -100,9 +99,25 @@ struct WaveTopK {
                 tv[s] = nvv[s];
                 ti[s] = nii[s];
             }
-            th_v = __shfl(tv[ks], kl, 64);
-            th_i = __shfl(ti[ks], kl, 64);
+            refresh();
         }
+    }
+
+    // (th_v, th_i) = entry k - 1.  The register arrays are read with static
+    // indexes only (a runtime index would move them to scratch memory).
+    __device__ void refresh()
+    {
+        double v = tv[0];
+        int32_t i = ti[0];
+#pragma unroll
+        for (int s = 1; s < S; ++s) {
+            if (s == ks) {
+                v = tv[s];
+                i = ti[s];
+            }
+        }
+        th_v = __shfl(v, kl, 64);
+        th_i = __shfl(i, kl, 64);
     }
 };
 
@@ -141,49 +156,6 @@ __device__ __forceinline__ double ip64_rows_fp32(const float *__restrict__ Xl, i
                 buf[it] = floatx4{0.f, 0.f, 0.f, 0.f};
                 if (rval[it] && col < dp) buf[it] = *reinterpret_cast<const floatx4 *>(Xl + roff[it] + col);
             }
-        }
-        __syncthreads();
-        const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);
-        // the sum is one dependent chain: reading the tile two pieces at a
-        // time keeps registers (and so resident waves) free
-#pragma unroll 2
-        for (int tt = 0; tt < 8; ++tt) {
-            const floatx4 x4 = row[tt];
-#pragma unroll
-            for (int u = 0; u < 4; ++u) {
-                const int t = k0 + 4 * tt + u;
-                const float qt = t < d ? qv[t] : 0.f;
-                acc = acc + (double)qt * (double)x4[u];
-            }
-        }
-        __syncthreads();
-    }
-    return acc;
-}
-
-// The same sum over the bfloat16 copy Xh of the rows (rows of dp values).
-__device__ __forceinline__ double ip64_rows_bf16(const uint16_t *__restrict__ Xh, int d, int dp,
-                                                 const float *__restrict__ qv, int32_t p, bool valid,
-                                                 int lane, float *tile)
-{
-    double acc = 0.0;
-    for (int k0 = 0; k0 < dp; k0 += 32) {
-        // 4 lanes x 8 bfloat16 per row chunk: 16 rows per load instruction
-#pragma unroll
-        for (int it = 0; it < 4; ++it) {
-            const int rr = 16 * it + (lane >> 2), sg = 8 * (lane & 3);
-            const bool ok = __shfl((int)valid, rr, 64) != 0 && k0 + sg < dp;
-            const int64_t ro = (int64_t)__shfl(valid ? p : 0, rr, 64) * dp;
-            u16x8 v = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
-            if (ok) v = *reinterpret_cast<const u16x8 *>(Xh + ro + k0 + sg);
-            floatx4 lo4, hi4;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                lo4[e] = __uint_as_float((uint32_t)v[e] << 16);
-                hi4[e] = __uint_as_float((uint32_t)v[4 + e] << 16);
-            }
-            *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg]) = lo4;
-            *reinterpret_cast<floatx4 *>(&tile[rr * RR_STRIDE + sg + 4]) = hi4;
         }
         __syncthreads();
         const floatx4 *row = reinterpret_cast<const floatx4 *>(&tile[lane * RR_STRIDE]);

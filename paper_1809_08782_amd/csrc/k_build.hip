@@ -388,12 +388,13 @@ __global__ __launch_bounds__(256) void k_layout(const float *__restrict__ X, int
     // error bound of the bfloat16 image of each row: ||x - bf16(x)|| (an FP32
     // sum of d rounded squares is at most (1 + (d + 2) 2^-23) below the exact
     // one; squares under the FP32 range add at most 2^-50 once rooted), plus
-    // (d + 1) 2^-52 ||x|| for an FP64 sum of d exact products with bf16(x),
-    // rounded up to FP32
+    // (d + 8) 2^-23 ||x|| for an FP32 sum, in any order and with fused
+    // multiply-adds, of the dp <= d + 7 products of q with bf16(x) (at most
+    // gamma_dp (1 + 2^-8) ||q|| ||x|| off), rounded up to FP32
     if (xeb && mine) {
         const double s2 = (double)dsq_s[wave][lane] * (1.0 + (double)(d + 2) * 0x1p-23);
         const double b = __builtin_sqrt(s2) * (1.0 + 0x1p-40) + 0x1p-50 +
-                         (double)(d + 1) * 0x1p-52 * __builtin_sqrt(key[src_row]) * (1.0 + 0x1p-40);
+                         (double)(d + 8) * 0x1p-23 * __builtin_sqrt(key[src_row]) * (1.0 + 0x1p-40);
         xeb[p0 + lane] = (float)(b * (1.0 + 0x1p-22));
     }
 }

@@ -506,12 +506,17 @@ __global__ __launch_bounds__(256) void k_fill32(uint32_t *__restrict__ p, int64_
 constexpr int SH_WAVES = 4;
 
 template <int W>
-__device__ __forceinline__ void hist_group16(const uint32_t *__restrict__ codes_l, int64_t p,
-                                             uint32_t q0, uint32_t q1, uint32_t *hist, int lane)
+__device__ __forceinline__ void load_group16(const uint32_t *__restrict__ codes_l, int64_t p,
+                                             uint32_t (&c)[16 * W])
 {
-    uint32_t c[16 * W];
 #pragma unroll
     for (int u = 0; u < 16 * W; ++u) c[u] = codes_l[p * W + u];
+}
+
+template <int W>
+__device__ __forceinline__ void hist_group16(const uint32_t (&c)[16 * W], uint32_t q0, uint32_t q1,
+                                             uint32_t *hist, int lane)
+{
 #pragma unroll
     for (int u = 0; u < 16; ++u) {
         uint32_t h = (uint32_t)__popc(c[u * W] ^ q0);
@@ -550,7 +555,18 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_hist_s(const uint32_t *_
     for (int e = tid; e < nh; e += SH_WAVES * 64) hist[e] = 0u;
     __syncthreads();
     const int64_t ng = (p1 - p0) >> 4;  // whole 16-item groups
-    for (int64_t g = wave; g < ng; g += SH_WAVES) hist_group16<W>(codes_l, p0 + g * 16, q0, q1, hist, lane);
+    // the codes of the wave's next group are loaded while this one is counted
+    uint32_t c[16 * W], cn[16 * W];
+    if (wave < ng) load_group16<W>(codes_l, p0 + (int64_t)wave * 16, c);
+    // wait for the first group here (lgkmcnt(0)), so that the loop body only
+    // waits for its prefetch after counting, not at its top
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    for (int64_t g = wave; g < ng; g += SH_WAVES) {
+        if (g + SH_WAVES < ng) load_group16<W>(codes_l, p0 + (g + SH_WAVES) * 16, cn);
+        hist_group16<W>(c, q0, q1, hist, lane);
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) c[u] = cn[u];
+    }
     if (wave == SH_WAVES - 1) {
         for (int64_t p = p0 + ng * 16; p < p1; ++p) {
             uint32_t h = (uint32_t)__popc(codes_l[p * W] ^ q0);
@@ -651,24 +667,47 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_emit_s(const uint32_t *_
     if (__ballot(hthr >= 0 || htie >= 0) == 0ull) return;  // the same for every wave of the block
     int32_t *stage = stage_s[wave];
     int cnt = 0;
+    // h <= hthr  <=>  h - (hthr + 1) < 0: the popcounts accumulate onto
+    // -(hthr + 1) and the sign bit is the probe decision
+    const uint32_t negt = (uint32_t)(-(hthr + 1));
+    const bool anytie = __ballot(htie >= 0) != 0ull;  // the threshold bucket of some query is here
     const int64_t ng = (p1 - p0) >> 4;
+    uint32_t c[16 * W], cn[16 * W];
+    if (wave < ng) load_group16<W>(codes_l, p0 + (int64_t)wave * 16, c);
     for (int64_t g = wave; g < ng; g += SH_WAVES) {
         const int64_t p = p0 + g * 16;
-        uint32_t c[16 * W];
-#pragma unroll
-        for (int u = 0; u < 16 * W; ++u) c[u] = codes_l[p * W + u];
+        if (g + SH_WAVES < ng) load_group16<W>(codes_l, p + SH_WAVES * 16, cn);
+        uint32_t mask = 0;
 #pragma unroll
         for (int u = 0; u < 16; ++u) {
-            int h = __popc(c[u * W] ^ q0);
-            if (W == 2) h += __popc(c[u * W + 1] ^ q1);
-            if (h <= hthr || (h == htie && p + u <= pstar)) {
-                stage[cnt * 64 + lane] = (int32_t)(p + u);
-                if (++cnt == EM_SB) {
-                    emit_flush(stage, lane, cnt, counts, cand, q, Tq);
-                    cnt = 0;
-                }
+            uint32_t hd = (uint32_t)__popc(c[u * W] ^ q0) + negt;
+            if (W == 2) hd += (uint32_t)__popc(c[u * W + 1] ^ q1);
+            mask |= (hd >> 31) << u;
+        }
+        if (anytie) {
+            // h = h* at a stored position up to P*: items u <= P* - p of the group
+            const int64_t ul = pstar - p;
+            const uint32_t tmask = ul < 0 ? 0u : (ul >= 15 ? 0xFFFFu : ((2u << ul) - 1u));
+            uint32_t mt = 0;
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                int h = __popc(c[u * W] ^ q0);
+                if (W == 2) h += __popc(c[u * W + 1] ^ q1);
+                mt |= (uint32_t)(h == htie) << u;
+            }
+            mask |= mt & tmask;
+        }
+        while (mask != 0u) {  // rare: a few per cent of the items are probed
+            const int u = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            stage[cnt * 64 + lane] = (int32_t)(p + u);
+            if (++cnt == EM_SB) {
+                emit_flush(stage, lane, cnt, counts, cand, q, Tq);
+                cnt = 0;
             }
         }
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) c[u] = cn[u];
     }
     if (wave == SH_WAVES - 1) {
         for (int64_t p = p0 + ng * 16; p < p1; ++p) {
@@ -688,28 +727,19 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_emit_s(const uint32_t *_
 
 // ---------------------------------------------------------------- rerank
 // One wave per (query, slice of its probed list); the rows of 64 candidates
-// at a time are summed in FP64 (dev::ip64_rows_*), the running top-k kept by
+// at a time are summed in FP64 (dev::ip64_rows_fp32), the running top-k kept by
 // dev::WaveTopK.  With several slices per query, each slice writes a partial
 // list and k_topk_merge combines them.
 using dev::RR_STRIDE;
 using dev::WaveTopK;
 
-// LP = true: the rows come from the bfloat16 copy Xh.  ip~ = sum_t q_t x~_t in
-// FP64 (exact products, ascending t) differs from ip by q.(x - x~) plus the
-// FP64 rounding of the sum, so |ip~ - ip| <= e = ||q|| xeb (1 + 2^-20) with
-// xeb >= ||x - x~|| + (d + 1) 2^-52 ||x|| from the layout (Cauchy-Schwarz on
-// the exact rounding error of the row, about 2.6 times below 2^-8 ||x||); the
-// wave keeps a top-k of the lower bounds ip~ - e and appends every item whose
-// upper bound ip~ + e reaches the k-th lower bound to the query's list
-// (lists: nq x lcap, lcount: per query, may exceed lcap) -- a superset of
-// the exact top-k, re-ranked afterwards from the FP32 rows.  The slices of a
-// query share the largest k-th lower bound any of them has reached (gtheta,
-// order-preserving encoding, 0 = none yet): the k items behind it have exact
-// inner products at least that large, so it bounds the query's k-th best.
+// The slices of a query share the largest k-th value any of them has reached
+// (gtheta, order-preserving encoding, 0 = none yet): the k items behind it
+// have inner products at least that large, so it bounds the query's k-th best.
 using dev::order_key;
 using dev::order_value;
 
-template <int S, bool LP>
+template <int S>
 __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                const int32_t *__restrict__ perm,
                                                const float *__restrict__ Q, int64_t n, int d,
@@ -720,10 +750,6 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
                                                float *__restrict__ out_ips,
                                                double *__restrict__ part_v,
                                                int32_t *__restrict__ part_i,
-                                               const uint16_t *__restrict__ Xh,
-                                               const float *__restrict__ xeb, int lcap,
-                                               int32_t *__restrict__ lcount,
-                                               int32_t *__restrict__ lists,
                                                unsigned long long *__restrict__ gtheta)
 {
     __shared__ float tile[64 * RR_STRIDE];
@@ -737,13 +763,6 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
     const int64_t cend = min(len, cbeg + slice);
     WaveTopK<S> top;
     top.init(k);
-    double qn = 0.0;  // LP: ||q|| (exact squares, FP64 sum, rounded up)
-    if (LP) {
-        for (int t = lane; t < d; t += 64) qn += (double)qv[t] * (double)qv[t];
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o, 64);
-        qn = __builtin_sqrt(qn) * (1.0 + 0x1p-40);
-    }
 
     // the positions of the next 64 candidates are loaded one batch ahead
     int32_t pn = (cbeg + lane < cend) ? cq[cbeg + lane] : -1;
@@ -755,42 +774,19 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
         valid = valid && p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
         if (valid) id = perm[p];
         else p = 0;
-        const double acc = LP ? dev::ip64_rows_bf16(Xh, d, dp, qv, p, valid, lane, tile)
-                              : dev::ip64_rows_fp32(Xl, d, dp, qv, p, valid, lane, tile);
-        if (LP) {
-            const double e = qn * (double)(valid ? xeb[p] : 0.f) * (1.0 + 0x1p-20);
-            top.offer(acc - e, id, valid, lane);
-            double th = top.th_v;
-            if (th > -INFINITY && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(th));
+        const double acc = dev::ip64_rows_fp32(Xl, d, dp, qv, p, valid, lane, tile);
+        // values below the best k-th value any slice of the query has reached
+        // cannot enter the query's top-k
+        double floor = -INFINITY;
+        if (gtheta) {
             const unsigned long long ge =
                 __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (ge != 0ull) th = fmax(th, order_value(ge));
-            const bool keep = valid && !(acc + e < th);
-            const uint64_t kb = __ballot(keep);
-            if (kb != 0ull) {
-                const int leader = __ffsll((long long)kb) - 1;
-                int base = 0;
-                if (lane == leader) base = atomicAdd(&lcount[q], __popcll(kb));
-                base = __shfl(base, leader, 64);
-                const int slot = base + __popcll(kb & ((1ull << lane) - 1ull));
-                if (keep && slot < lcap) lists[q * lcap + slot] = p;
-            }
-        } else {
-            // slices of one query share the best k-th value any of them has
-            // reached (at least k items are that good): values below it
-            // cannot enter the query's top-k
-            double floor = -INFINITY;
-            if (gtheta) {
-                const unsigned long long ge =
-                    __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                if (ge != 0ull) floor = order_value(ge);
-            }
-            top.offer(acc, id, valid, lane, floor);
-            if (gtheta && top.th_v > -INFINITY && top.th_v > floor && lane == 0)
-                atomicMax(&gtheta[q], (unsigned long long)order_key(top.th_v));
+            if (ge != 0ull) floor = order_value(ge);
         }
+        top.offer(acc, id, valid, lane, floor);
+        if (gtheta && top.th_v > -INFINITY && top.th_v > floor && lane == 0)
+            atomicMax(&gtheta[q], (unsigned long long)order_key(top.th_v));
     }
-    if (LP) return;
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const int e = s * 64 + lane;
@@ -808,6 +804,127 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
 }
 
 // Merge the nsplit partial top-k lists of each query (one wave per query).
+// First pass of the gather re-rank over the bfloat16 rows Xh (the precision
+// form's re-rank copy): one wave per (query, slice of its probed list).  The
+// order of the sum does not matter here -- only a rigorous bound is needed --
+// so 16 lanes share a row, 8 coordinates each per 128-coordinate segment (a
+// load instruction brings four rows x 256 contiguous bytes), and the FP32
+// partial sums are reduced across the 16 lanes by shuffles (no LDS tile).
+// ip~ (FP32 products of q and bf16(x), FP32 sums in any order) satisfies
+// |ip~ - q.x| <= ||q|| (||x - bf16(x)|| + (d + 8) 2^-23 ||x||) <= ||q|| xeb;
+// with e = ||q|| xeb (1 + 2^-20) the wave keeps a top-k of the lower bounds
+// ip~ - e and appends every candidate whose upper bound ip~ + e reaches the
+// k-th lower bound (the largest any slice of the query has published in
+// gtheta) to the query's list (lists: nq x lcap, lcount per query, may
+// exceed lcap): a superset of the exact top-k, re-ranked afterwards from the
+// FP32 rows.
+// One step of the transposing butterfly: H = half the number of live sums;
+// the lane whose bit H is set keeps sums [H, 2H), the other [0, H).
+template <int H>
+__device__ __forceinline__ void reduce_half(float (&a)[16], int upper)
+{
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        const float keep = upper ? a[i + H] : a[i];
+        const float send = upper ? a[i] : a[i + H];
+        a[i] = keep + __shfl_xor(send, H, 64);
+    }
+}
+
+template <int S>
+__global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16_t *__restrict__ Xh,
+                                                    const float *__restrict__ xeb,
+                                                    const int32_t *__restrict__ perm,
+                                                    const float *__restrict__ Q, int64_t n, int d, int dp,
+                                                    int64_t Tq, int k, const int32_t *__restrict__ cand,
+                                                    int64_t slice, int lcap, int32_t *__restrict__ lcount,
+                                                    int32_t *__restrict__ lists,
+                                                    unsigned long long *__restrict__ gtheta)
+{
+    extern __shared__ float qs[];  // q, zero past d up to a multiple of 128
+    const int lane = threadIdx.x;
+    const int64_t q = blockIdx.x;
+    const int split = blockIdx.y;
+    const float *qv = Q + q * d;
+    const int32_t *cq = cand + q * Tq;
+    const int64_t cbeg = (int64_t)split * slice;
+    const int64_t cend = min(Tq, cbeg + slice);
+    double qn = 0.0;  // ||q|| (exact squares, FP64 sum, rounded up)
+    const int dq = (dp + 127) / 128 * 128;
+    for (int t = lane; t < dq; t += 64) {
+        const float v = t < d ? qv[t] : 0.f;
+        qs[t] = v;
+        qn += (double)v * (double)v;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) qn += __shfl_xor(qn, o, 64);
+    qn = __builtin_sqrt(qn) * (1.0 + 0x1p-40);
+    __syncthreads();
+    WaveTopK<S> top;
+    top.init(k);
+    const int grp = lane >> 4, sl = lane & 15;
+    int32_t pn = (cbeg + lane < cend) ? cq[cbeg + lane] : -1;
+    for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
+        int32_t p = pn;
+        pn = (c0 + 64 + lane < cend) ? cq[c0 + 64 + lane] : -1;
+        bool valid = c0 + lane < cend;
+        valid = valid && p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
+        int32_t id = 0;
+        if (valid) id = perm[p];
+        else p = 0;
+        const int32_t pv = valid ? p : -1;
+        float part[16];
+#pragma unroll
+        for (int g = 0; g < 16; ++g) part[g] = 0.f;
+        for (int s0 = 0; s0 < dp; s0 += 128) {
+            const int c = s0 + 8 * sl;
+            u16x8 v[16];
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+                const int32_t pr = __shfl(pv, 4 * g + grp, 64);
+                v[g] = u16x8{0, 0, 0, 0, 0, 0, 0, 0};
+                if (pr >= 0 && c < dp) v[g] = *reinterpret_cast<const u16x8 *>(Xh + (int64_t)pr * dp + c);
+            }
+            const floatx4 qa = *reinterpret_cast<const floatx4 *>(&qs[c]);
+            const floatx4 qb = *reinterpret_cast<const floatx4 *>(&qs[c + 4]);
+#pragma unroll
+            for (int g = 0; g < 16; ++g) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    part[g] = __builtin_fmaf(qa[e], __uint_as_float((uint32_t)v[g][e] << 16), part[g]);
+                    part[g] = __builtin_fmaf(qb[e], __uint_as_float((uint32_t)v[g][4 + e] << 16), part[g]);
+                }
+            }
+        }
+        // transposing butterfly over the 16 lanes of a row group: at each step
+        // a lane keeps half of its partial sums (the half its lane bit names)
+        // and adds the partner's copy of that half, so that lane sl ends with
+        // the full sum of row 4 sl + grp (15 exchanges instead of 60)
+        reduce_half<8>(part, sl & 8);
+        reduce_half<4>(part, sl & 4);
+        reduce_half<2>(part, sl & 2);
+        reduce_half<1>(part, sl & 1);
+        // row c sits in lane 16 (c & 3) + (c >> 2)
+        const double acc = (double)__shfl(part[0], 16 * (lane & 3) + (lane >> 2), 64);
+        const double e = qn * (double)(valid ? xeb[p] : 0.f) * (1.0 + 0x1p-20);
+        top.offer(acc - e, id, valid, lane);
+        double th = top.th_v;
+        if (th > -INFINITY && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(th));
+        const unsigned long long ge = __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (ge != 0ull) th = fmax(th, order_value(ge));
+        const bool keep = valid && !(acc + e < th);
+        const uint64_t kb = __ballot(keep);
+        if (kb != 0ull) {
+            const int leader = __ffsll((long long)kb) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&lcount[q], __popcll(kb));
+            base = __shfl(base, leader, 64);
+            const int slot = base + __popcll(kb & ((1ull << lane) - 1ull));
+            if (keep && slot < lcap) lists[q * lcap + slot] = p;
+        }
+    }
+}
+
 template <int S>
 __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ part_v,
                                                    const int32_t *__restrict__ part_i, int nsplit,
@@ -2141,9 +2258,9 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
 #define NRLSH_RERANK(SS)                                                                         \
     do {                                                                                         \
-        hipLaunchKernelGGL((k_rerank<SS, false>), grid, block, 0, s, Xl, perm, Q, sh.n, sh.d,    \
-                           sh.dp, sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips,    \
-                           part_v, part_i, nullptr, nullptr, 0, nullptr, nullptr, gtheta);       \
+        hipLaunchKernelGGL((k_rerank<SS>), grid, block, 0, s, Xl, perm, Q, sh.n, sh.d, sh.dp,    \
+                           sh.Tq, sh.k, cand, counts, nsplit, slice, out_ids, out_ips, part_v,   \
+                           part_i, gtheta);                                                      \
         if (nsplit > 1)                                                                          \
             hipLaunchKernelGGL(k_topk_merge<SS>, dim3((unsigned)nq), block, 0, s, part_v, part_i, \
                                nsplit, sh.k, out_ids, out_ips);                                  \
@@ -2166,10 +2283,10 @@ hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t 
     int64_t slice = (sh.Tq + nsplit - 1) / nsplit;
     slice = (slice + 63) / 64 * 64;
     const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
-#define NRLSH_RERANK_LP(SS)                                                                       \
-    hipLaunchKernelGGL((k_rerank<SS, true>), grid, block, 0, s, nullptr, perm, Q, sh.n, sh.d, sh.dp, \
-                       sh.Tq, sh.k, cand, nullptr, nsplit, slice, nullptr, nullptr, nullptr,      \
-                       nullptr, Xh, xeb, lcap, lcount, lists, gtheta)
+    const size_t lds = (size_t)(sh.dp + 127) / 128 * 128 * sizeof(float);
+#define NRLSH_RERANK_LP(SS)                                                                         \
+    hipLaunchKernelGGL((k_rerank_bf16<SS>), grid, block, lds, s, Xh, xeb, perm, Q, sh.n, sh.d, sh.dp, \
+                       sh.Tq, sh.k, cand, slice, lcap, lcount, lists, gtheta)
     if (S <= 1) NRLSH_RERANK_LP(1);
     else if (S <= 2) NRLSH_RERANK_LP(2);
     else if (S <= 4) NRLSH_RERANK_LP(4);

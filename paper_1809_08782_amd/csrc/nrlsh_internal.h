@@ -60,8 +60,8 @@ hipError_t launch_lo_rows(const float *Xl, const uint16_t *Xh, int64_t count, ui
 // Stored copy of the items (row p = item perm[p], zero-padded to dp) with the
 // key and sub-dataset of each stored row, plus its bfloat16 image Xh and, when
 // Xlo is not NULL, the lo part bf16(x - hi); xeb (or NULL) receives for each
-// stored row an upper bound of ||x - bf16(x)|| + (d + 1) 2^-52 ||x||, so that
-// |q.x - q.bf16(x)| (the latter summed in FP64) is at most ||q|| xeb.
+// stored row an upper bound of ||x - bf16(x)|| + (d + 8) 2^-23 ||x||, so that
+// |q.x - q.bf16(x)| (the latter summed in FP32, any order) is at most ||q|| xeb.
 hipError_t launch_layout(const float *X, int64_t n, int d, int dp, const int32_t *perm,
                          const double *key, const int32_t *sid, float *Xl, uint16_t *Xh,
                          uint16_t *Xlo, double *key_l, int32_t *sid_l, float *xeb, hipStream_t s);
