@@ -218,6 +218,7 @@ FORMS = {
 DEFAULT_FORMS = {"large": "fp8_bf16,fp32", "precision": "fp32,bf16_hash,fp8_hash", "mf": "fp32",
                  "tiny": "fp32"}
 KERNELS = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table", "qhash",
+           "scan_sample", "guess", "scan_collect", "filter",
            "scan_hist", "threshold", "tie_locate", "scan_emit", "table_count", "table_emit",
            "rerank", "rerank_lp", "screen_max", "screen", "rerank_exact"]
 BUILD_KERNELS = {"keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table"}
@@ -446,26 +447,33 @@ def main():
     dom = max(qkern, key=lambda nm: qkern[nm]["ms_per_step"]) if qkern else None
     roof = roofline(dom, kern, w, Tq, qb, hr["query_stats"])
     scan = None
-    if "scan_hist" in kern:
+    scan_kernel = "scan_collect" if "scan_collect" in kern else ("scan_hist" if "scan_hist" in kern else None)
+    if scan_kernel:
         W = (w.L + 31) // 32
         st = hr["query_stats"]
         pairs = st.get("scan_pairs") or 0
         # the stats are the last query call's: the last batch, of nq - (calls - 1) qb queries
         last_nq = w.nq - (-(-w.nq // qb) - 1) * qb
         frac = pairs / (last_nq * w.n)
-        per = kern["scan_hist"]
-        step_pairs = frac * w.nq * w.n  # pass-1 pairs of the whole step, at the last batch's fraction
-        scan = {"pairs_counted_last_batch": pairs,
+        per = kern[scan_kernel]
+        step_pairs = frac * w.nq * w.n  # scanned pairs of the whole step, at the last batch's fraction
+        # the collecting scan: XOR + popcount per code word, the sign test (3
+        # ops) against the query's cut per pair; the first of the two passes:
+        # XOR + popcount per word and the histogram address (1 op)
+        ops = 2 * W + (3 if scan_kernel == "scan_collect" else 1)
+        scan = {"kernel": scan_kernel,
+                "pairs_scanned_last_batch": pairs,
                 "last_batch_queries": last_nq,
                 "pairs_all_last_batch": last_nq * w.n,
-                "counted_fraction": frac,
-                "pass1_ms_per_step": per["ms_per_step"],
-                "pass1_pairs_per_s": step_pairs / (per["ms_per_step"] * 1e-3) if pairs else None,
-                "int_ops_per_pair": 2 * W + 1,
-                "pass2_ms_per_step": kern.get("scan_emit", {}).get("ms_per_step"),
-                "code_stream_GBps": (w.nq * w.n * 4 * W) / (per["ms_per_step"] * 1e-3) / 1e9}
-        if scan["pass1_pairs_per_s"]:
-            scan["int_valu_tops"] = scan["pass1_pairs_per_s"] * (2 * W + 1) / 1e12
+                "scanned_fraction": frac,
+                "scan_ms_per_step": per["ms_per_step"],
+                "pairs_per_s": step_pairs / (per["ms_per_step"] * 1e-3) if pairs else None,
+                "int_ops_per_pair": ops,
+                "other_ms_per_step": {nm: kern[nm]["ms_per_step"] for nm in
+                                      ("scan_sample", "guess", "threshold", "tie_locate", "filter",
+                                       "scan_hist", "scan_emit") if nm in kern and nm != scan_kernel}}
+        if scan["pairs_per_s"]:
+            scan["int_valu_tops"] = scan["pairs_per_s"] * ops / 1e12
             scan["int_valu_frac"] = scan["int_valu_tops"] / INT_VALU_PEAK_TOPS
 
     # ------------------------------------------------------------ CPU oracle baseline
@@ -557,16 +565,21 @@ def roofline(dom, kern, w, Tq, qb, qstats):
                 "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
                 "traffic_source": rec, "bytes_per_launch": bytes_launch, "unit_work": "probed item",
                 "bytes_per_unit": row + 8, "units_per_launch": nq_launch * Tq, "dominant_kernel": dom}
-    if dom in ("scan_hist", "scan_emit"):
-        pairs = (qstats.get("scan_pairs") or 0) if dom == "scan_hist" else None
-        if not pairs:
-            pairs = nq_launch * w.n
-        ops = pairs * (2 * W + 1)
-        achieved = ops / (per["avg_ms"] * 1e-3) / 1e12
-        kname = "k_scan_hist_s<%d>" % W if dom == "scan_hist" else "k_scan_emit_s<%d>" % W
+    if dom in ("scan_hist", "scan_emit", "scan_collect"):
+        # pairs of the step from the last batch's scanned fraction, over the
+        # kernel's time per step
+        last_nq = w.nq - (-(-w.nq // qb) - 1) * qb
+        frac = (qstats.get("scan_pairs") or 0) / (last_nq * w.n)
+        if dom == "scan_emit" or frac == 0:
+            frac = 1.0
+        ops_per_pair = 2 * W + (3 if dom == "scan_collect" else 1)
+        ops_step = frac * w.nq * w.n * ops_per_pair
+        achieved = ops_step / (per["ms_per_step"] * 1e-3) / 1e12
+        kname = {"scan_hist": "k_scan_hist_s<%d>", "scan_emit": "k_scan_emit_s<%d>",
+                 "scan_collect": "k_scan_collect<%d>"}[dom] % W
         return {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK_TOPS,
                 "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK_TOPS, "traffic": None,
-                "ops_per_launch": ops, "unit_work": "(query, item) pair", "ops_per_unit": 2 * W + 1,
+                "ops_per_step": ops_step, "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair,
                 "dominant_kernel": dom}
     if dom == "screen":
         pairs = (qstats.get("screen_pairs") or 0) / max(1, qstats.get("screen_passes") or 1)

@@ -228,13 +228,20 @@ typedef struct nrlsh_query_opts {
     int32_t rerank_mode; /* nrlsh_rerank_mode (read when struct_size covers it) */
     int32_t rerank_storage; /* GATHER re-rank rows: NRLSH_STORAGE_FP32 (default) or
                                NRLSH_STORAGE_BF16: inner products from the bfloat16
-                               copy bound each item within ||q|| (||x - bf16(x)|| +
-                               (d + 1) 2^-52 ||x||) (the row's own rounding error,
-                               kept with the index); items that may still reach the
-                               top-k are re-ranked exactly from the FP32 rows (same
-                               result, fewer bytes) */
+                               copy (FP32 sums) bound each item within ||q||
+                               (||x - bf16(x)|| + (d + 8) 2^-23 ||x||) (the row's own
+                               rounding error, kept with the index); items that may
+                               still reach the top-k are re-ranked exactly from the
+                               FP32 rows (same result, fewer bytes) */
     int32_t probe_mode;  /* nrlsh_probe_mode (read when struct_size covers it) */
-    int32_t pad;
+    int32_t scan_guess;  /* SCAN probe, how the probed sets are found (same result
+                            either way): 0 = default (budgets T >= 6400 below 2n/3
+                            take one collecting scan behind a sampled guess of each
+                            query's cut; others, and batches whose guess missed,
+                            take the two exact passes); -1 = the two passes only;
+                            g in 1..4096 = the collecting scan for every budget below
+                            2n/3, guessing g/16 T items (small or large g make the
+                            guess miss: for tests of the fallback) */
 } nrlsh_query_opts;
 
 nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -475,7 +482,14 @@ typedef struct nrlsh_query_stats {
     int64_t scan_pairs;    /* SCAN: (query, item) pairs the first scan pass counted; the
                               sub-datasets are scanned in descending U_j and a 64-query
                               tile stops once all its queries' threshold buckets are
-                              known, so this is at most nq x n */
+                              known, so this is at most nq x n.  With the collecting
+                              scan (budgets of 6400 and more, below 2n/3): the pairs of
+                              that scan, whose blocks skip sub-datasets no query of
+                              the tile reaches before its guessed cut */
+    int64_t collect_fallbacks; /* SCAN: batches whose collecting scan missed some query's
+                              budget (its guessed cut too tight, or more items than
+                              the key room) and that were probed again by the two
+                              exact passes; results never depend on it */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

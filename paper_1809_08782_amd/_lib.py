@@ -46,7 +46,7 @@ STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
 class QueryOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
                 ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32),
-                ("probe_mode", C.c_int32), ("pad", C.c_int32)]
+                ("probe_mode", C.c_int32), ("scan_guess", C.c_int32)]
 
 
 PROBES = {"scan": 0, "table": 1, "single": 2}
@@ -66,7 +66,8 @@ class QueryStats(C.Structure):
                 ("kept_max", C.c_int64), ("theta_unset", C.c_int64), ("lp_kept_total", C.c_int64),
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
-                ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64)]
+                ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64),
+                ("collect_fallbacks", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -383,11 +384,14 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
 
 
 def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None,
-                rerank: str = "auto", rerank_storage: str = "fp32", probe: str = "scan"):
+                rerank: str = "auto", rerank_storage: str = "fp32", probe: str = "scan",
+                scan_guess: int = 0):
     """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
     numpy for host queries, torch tensors for CUDA torch queries.  ``rerank``
     selects the re-rank mode ("auto", "gather", "screen", ...), ``probe`` how
-    the probed items are found ("scan" or "table"); all give the same result."""
+    the probed items are found ("scan" or "table"), ``scan_guess`` how the scan
+    finds them (0 default, -1 two passes only, g > 0 the collecting scan with a
+    guess of g/16 T items); all give the same result."""
     mode = RERANK_MODES[rerank]
     rst = STORAGES[rerank_storage]
     prb = PROBES[probe]
@@ -400,7 +404,7 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
             ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         else:
             ids, ips = out
-        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst, prb)
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst, prb, int(scan_guess))
         _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
                                     C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
         return ids, ips
@@ -408,8 +412,8 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
     nq = Q.shape[0]
     ids = np.empty((nq, k), dtype=np.int64)
     ips = np.empty((nq, k), dtype=np.float32)
-    if mode or rst or prb or stream is not None:
-        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst, prb)
+    if mode or rst or prb or scan_guess or stream is not None:
+        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst, prb, int(scan_guess))
         _check(lib().nrlsh_query_ex(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                     C.byref(opts), ids.ctypes.data, ips.ctypes.data))
     else:
@@ -566,7 +570,7 @@ def nrlsh_get_query_stats() -> dict:
             "lp_fallbacks": st.lp_fallbacks, "probe": {1: "table"}.get(st.probe_mode, "scan"),
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
             "table_passes": st.table_passes, "screen_pairs": st.screen_pairs,
-            "scan_pairs": st.scan_pairs}
+            "scan_pairs": st.scan_pairs, "collect_fallbacks": st.collect_fallbacks}
 
 
 def nrlsh_profile_enable(on: bool = True):

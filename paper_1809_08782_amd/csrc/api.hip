@@ -29,6 +29,9 @@ namespace {
 
 thread_local std::string g_err;
 thread_local nrlsh_query_stats g_qstats;
+// scan_guess of the calling nrlsh_query_ex (0 outside it): how the scan probe
+// finds the probed sets (nrlsh_query_opts)
+thread_local int32_t g_scan_guess = 0;
 
 struct ProfEntry {
     double ms = 0.0;
@@ -965,13 +968,34 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     B = std::max<int64_t>(64, B / 64 * 64);
     B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
     if (table) B = std::min<int64_t>(B, 16384);  // bounds the per-query bucket scratch
+    // Large budgets take the collecting scan: a sample pass (every gstride-th
+    // 16-item group) guesses each query's cut rho_q so that about 1.25 Tq
+    // items rank before it, one scan collects those items, and the threshold
+    // pass plus a filter of the collected keys give the probed set; a batch
+    // in which some query collected fewer than Tq (or more than kcap) items
+    // is probed again with the two exact passes.
+    const int32_t sguess = g_scan_guess;
+    const int gstride = (int)std::max<int64_t>(1, std::min<int64_t>(64, sh.Tq / 1600));
+    const bool collect = !table && sguess >= 0 && (sguess > 0 || gstride >= 4) && sh.Tq * 3 < ix->n * 2;
+    const int64_t guess16 = sguess > 0 ? sguess : 20;  // guessed items, in sixteenths of Tq
+    const int64_t kcap = collect ? 2 * sh.Tq + 16384 : 0;
+    if (collect) B = std::min<int64_t>(B, std::max<int64_t>(64, (int64_t(1) << 32) / (kcap * 8) / 64 * 64));
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
     const int nsplit = rerank_splits(B, sh.Tq);
     const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
     const int lsplit = rerank_splits(B, lcap);
-    // both scan passes walk the chunks of the staged pass 1
-    const ScanStages st = table ? ScanStages{} : scan_stages(ix, tiles);
+    const int64_t nbatches = (nq + B - 1) / B;
+    // both scan passes walk the chunks of the staged pass 1; the sample pass
+    // one chunk per sub-dataset (appended after them)
+    ScanStages st = table ? ScanStages{} : scan_stages(ix, tiles);
+    const int nstage_chunks = table ? 0 : st.cbeg.back();
+    if (collect)
+        for (int j = 0; j < sh.m; ++j) {
+            st.chunks.push_back(j);
+            st.chunks.push_back((int32_t)ix->off_h[j]);
+            st.chunks.push_back((int32_t)ix->off_h[j + 1]);
+        }
     Block blk;
     const size_t o_qc = blk.reserve<uint32_t>(qcodes_out_d ? 1 : (size_t)B * sh.qsets * sh.W),
                  o_gh = blk.reserve<uint32_t>(table ? 1 : (size_t)tiles * sh.m * L1 * 64),
@@ -992,8 +1016,17 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_ct = blk.reserve<int32_t>(table ? 1 : (size_t)B),
                  o_li = blk.reserve<int32_t>(bf16_rows ? (size_t)B * lcap : 1),
                  o_lv = blk.reserve<double>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
-                 o_lp = blk.reserve<int32_t>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1);
+                 o_lp = blk.reserve<int32_t>(bf16_rows && lsplit > 1 ? (size_t)B * lsplit * k : 1),
+                 o_ky = blk.reserve<uint64_t>(collect ? (size_t)B * kcap : 1),
+                 o_kc = blk.reserve<int32_t>(collect ? (size_t)B : 1),
+                 o_rh = blk.reserve<int32_t>(collect ? (size_t)B : 1),
+                 o_tg = blk.reserve<int32_t>(collect ? (size_t)tiles * 4 * 64 : 1),
+                 o_fl = blk.reserve<uint32_t>(collect ? (size_t)nbatches : 1);
     blk.allocate(s);
+    DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
+    DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
+    DBuf<uint32_t> gfail = blk.view<uint32_t>(o_fl);
+    if (collect) HIPX(launch_fill32(gfail.get(), nbatches, 0u, s));
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
                   gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
@@ -1019,7 +1052,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     bool lp_on = bf16_rows;
     const uint64_t ovf = ix->lp_overflow.load(std::memory_order_relaxed);
     if (ovf != 0 && (uint64_t)k >= (ovf >> 32) && (uint64_t)sh.Tq >= (ovf & 0xFFFFFFFFull)) lp_on = false;
-    for (int64_t b0 = 0; b0 < nq; b0 += B) {
+    auto run_batch = [&](int64_t b0, int64_t bi, bool staged) {
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
         uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.qsets * sh.W : qcodes.get();
@@ -1042,7 +1075,40 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                    cb, s));
             tm.end();
         }
-        if (!table) {
+        if (!table && collect && !staged) {
+            const int64_t tb = (nb + 63) / 64;
+            const int32_t P = sh.m * L1;
+            QueryShape shg = sh;  // the guess (1.25 Tq items by default), in sample units
+            shg.Tq = std::max<int64_t>(1, (sh.Tq * guess16 / 16 + gstride - 1) / gstride);
+            HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
+            tm.begin("scan_sample");
+            HIPX(launch_scan_hist_stage(ix->codes_l.get(), qc, nb, sh, schunks.get() + 3 * (size_t)nstage_chunks, sh.m,
+                                        nullptr, ghist.get(), nullptr, s, gstride));
+            tm.end();
+            tm.begin("guess");
+            HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, shg, gbase.get(), ghthr.get(),
+                                  gtie_g.get(), s));
+            HIPX(launch_rho_from_tie(gtie_g.get(), nb, P, grho.get(), s));
+            tm.end();
+            HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
+            HIPX(launch_fill32(kcount.get(), nb, 0u, s));
+            tm.begin("scan_collect");
+            HIPX(launch_scan_collect(ix->codes_l.get(), qc, nb, sh, schunks.get(), nstage_chunks, ix->R.get(),
+                                     grho.get(), kcap, kcount.get(), keys.get(), ghist.get(), scan_pairs_d, s));
+            tm.end();
+            tm.begin("threshold");
+            HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(), ghthr.get(),
+                                  gtie.get(), s));
+            tm.end();
+            tm.begin("tie_locate");
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
+                                   gpstar.get(), s));
+            tm.end();
+            tm.begin("filter");
+            HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), sh.Tq, cb,
+                                       ccount.get(), gfail.get() + bi, s));
+            tm.end();
+        } else if (!table) {
             tm.begin("scan_hist");
             run_scan_hist_staged(ix, sh, qc, nb, st.cbeg, st.cut, schunks.get(), need.get(), ghist.get(),
                                  scan_pairs_d, s);
@@ -1057,11 +1123,11 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             tm.end();
             HIPX(hipMemsetAsync(ccount.get(), 0, (size_t)nb * sizeof(int32_t), s));
             tm.begin("scan_emit");
-            HIPX(launch_scan_emit_stage(ix->codes_l.get(), qc, nb, sh, schunks.get(), st.cbeg.back(),
+            HIPX(launch_scan_emit_stage(ix->codes_l.get(), qc, nb, sh, schunks.get(), nstage_chunks,
                                         ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
             tm.end();
         }
-        if (cand_out_d) continue;
+        if (cand_out_d) return;
         if (lp_on) {
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
             HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
@@ -1088,7 +1154,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                    lcount.get(), ns, lpart_v.get(), lpart_i.get(), ids_d + b0 * k,
                                    ips_d + b0 * k, s));
                 tm.end();
-                continue;
+                return;
             }
             g_qstats.lp_fallbacks += 1;  // a list overflowed: re-rank this batch from FP32 rows
             lp_on = false;
@@ -1100,6 +1166,18 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                            part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s,
                            gtheta.get()));
         tm.end();
+    };
+    for (int64_t b0 = 0, bi = 0; b0 < nq; b0 += B, ++bi) run_batch(b0, bi, false);
+    if (collect) {
+        // batches whose collection was incomplete are probed again with the two passes
+        std::vector<uint32_t> fl((size_t)nbatches);
+        HIPX(hipMemcpyAsync(fl.data(), gfail.get(), fl.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPX(hipStreamSynchronize(s));
+        for (int64_t bi = 0; bi < nbatches; ++bi)
+            if (fl[(size_t)bi]) {
+                g_qstats.collect_fallbacks += 1;
+                run_batch(bi * B, bi, true);
+            }
     }
     if (table) {
         unsigned long long c[3] = {0, 0, 0};
@@ -1706,8 +1784,18 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
                                                                      sizeof(int32_t)) &&
         opts->rerank_storage != NRLSH_STORAGE_FP32)
         return fail(NRLSH_E_INVALID_ARG, "probe_mode SINGLE re-ranks from the FP32 rows");
+    int32_t sguess = 0;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, scan_guess) + sizeof(int32_t))) {
+        if (opts->scan_guess < -1 || opts->scan_guess > 4096)
+            return fail(NRLSH_E_INVALID_ARG, "scan_guess %d out of [-1, 4096]", opts->scan_guess);
+        sguess = opts->scan_guess;
+    }
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
+    struct GuessScope {  // the option lasts for this call only
+        explicit GuessScope(int32_t g) { g_scan_guess = g; }
+        ~GuessScope() { g_scan_guess = 0; }
+    } guess_scope(sguess);
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
         hipStream_t s = pick_stream(opts ? opts->stream : nullptr, ix->device);

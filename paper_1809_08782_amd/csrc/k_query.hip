@@ -532,7 +532,8 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_hist_s(const uint32_t *_
                                                                const int32_t *__restrict__ chunks,
                                                                const int32_t *__restrict__ need,
                                                                uint32_t *__restrict__ ghist,
-                                                               unsigned long long *__restrict__ npairs)
+                                                               unsigned long long *__restrict__ npairs,
+                                                               int gstride)
 {
     extern __shared__ uint32_t hist[];  // (L+1) x 64, column = lane
     // the wave number is wave-uniform: read it as such so that the item codes
@@ -555,19 +556,21 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_hist_s(const uint32_t *_
     for (int e = tid; e < nh; e += SH_WAVES * 64) hist[e] = 0u;
     __syncthreads();
     const int64_t ng = (p1 - p0) >> 4;  // whole 16-item groups
+    // gstride > 1: a sample, every gstride-th group (no partial group)
+    const int64_t g0 = (int64_t)wave * gstride, gs = (int64_t)SH_WAVES * gstride;
     // the codes of the wave's next group are loaded while this one is counted
     uint32_t c[16 * W], cn[16 * W];
-    if (wave < ng) load_group16<W>(codes_l, p0 + (int64_t)wave * 16, c);
+    if (g0 < ng) load_group16<W>(codes_l, p0 + g0 * 16, c);
     // wait for the first group here (lgkmcnt(0)), so that the loop body only
     // waits for its prefetch after counting, not at its top
     __builtin_amdgcn_s_waitcnt(0xC07F);
-    for (int64_t g = wave; g < ng; g += SH_WAVES) {
-        if (g + SH_WAVES < ng) load_group16<W>(codes_l, p0 + (g + SH_WAVES) * 16, cn);
+    for (int64_t g = g0; g < ng; g += gs) {
+        if (g + gs < ng) load_group16<W>(codes_l, p0 + (g + gs) * 16, cn);
         hist_group16<W>(c, q0, q1, hist, lane);
 #pragma unroll
         for (int u = 0; u < 16 * W; ++u) c[u] = cn[u];
     }
-    if (wave == SH_WAVES - 1) {
+    if (gstride == 1 && wave == SH_WAVES - 1) {
         for (int64_t p = p0 + ng * 16; p < p1; ++p) {
             uint32_t h = (uint32_t)__popc(codes_l[p * W] ^ q0);
             if (W == 2) h += (uint32_t)__popc(codes_l[p * W + 1] ^ q1);
@@ -723,6 +726,201 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_emit_s(const uint32_t *_
         }
     }
     if (cnt > 0) emit_flush(stage, lane, cnt, counts, cand, q, Tq);
+}
+
+// ---------------------------------------------------------------- collecting scan
+// One scan in place of the two passes when each query has a guessed cut
+// rho_q (a bucket rank, from a sample): every item whose bucket (j, h) ranks
+// before rho_q -- h <= hcut(q, j), the sub-dataset's deepest such level,
+// since ranks grow with h inside a sub-dataset -- is appended to the query's
+// list of keys rank << 32 | stored position and counted in ghist, the
+// per-query bucket histogram of the collected items (zeroed by the caller).
+// When a query collects at least Tq items, its first Tq items in probing
+// order (bucket rank, then stored position) are all among them, and the
+// threshold pass over ghist plus a filter of the keys give exactly its
+// probed set; otherwise (or past `cap` keys) the caller probes it again
+// with the two passes.  Blocks: (64-query tile, chunk) as in k_scan_emit_s.
+constexpr int CL_SB = 32;  // staged positions per lane of the collecting scan
+
+// Every lane empties its staged positions (cnt of them) into its query's
+// keys: one reservation per lane, then batches of 8 whose code loads are
+// issued together.  Called by the whole wave, so that no lane waits alone.
+template <int W>
+__device__ __forceinline__ void collect_flush(const int32_t *__restrict__ stage, int lane, int cnt,
+                                              const uint32_t *__restrict__ codes_l, uint32_t q0, uint32_t q1,
+                                              int L, const int32_t *__restrict__ Rrow, uint32_t *hist,
+                                              int32_t *__restrict__ counts, uint64_t *__restrict__ keys,
+                                              int64_t q, int64_t cap)
+{
+    int64_t base = 0;
+    if (cnt > 0) base = atomicAdd(&counts[q], cnt);
+    int top = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+    for (int i0 = 0; i0 < top; i0 += 8) {
+        int32_t pp[8];
+        uint32_t a[8], b[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) pp[v] = i0 + v < cnt ? stage[(i0 + v) * 64 + lane] : -1;
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            a[v] = pp[v] >= 0 ? codes_l[(int64_t)pp[v] * W] : 0u;
+            b[v] = (W == 2 && pp[v] >= 0) ? codes_l[(int64_t)pp[v] * W + 1] : 0u;
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            if (pp[v] < 0) continue;
+            int h = __popc(a[v] ^ q0);
+            if (W == 2) h += __popc(b[v] ^ q1);
+            __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (base + i0 + v < cap)
+                keys[q * cap + base + i0 + v] = ((uint64_t)(uint32_t)Rrow[L - h] << 32) | (uint32_t)pp[v];
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect(const uint32_t *__restrict__ codes_l,
+                                                                const uint32_t *__restrict__ qcodes,
+                                                                int64_t nq, int m, int L, int qsets,
+                                                                const int32_t *__restrict__ chunks,
+                                                                const int32_t *__restrict__ R,
+                                                                const int32_t *__restrict__ grho,
+                                                                int64_t cap, int32_t *__restrict__ counts,
+                                                                uint64_t *__restrict__ keys,
+                                                                uint32_t *__restrict__ ghist,
+                                                                unsigned long long *__restrict__ npairs)
+{
+    extern __shared__ uint32_t lds[];  // hist (L+1) x 64 | stage SH_WAVES x CL_SB x 64 | R row (L+1)
+    uint32_t *hist = lds;
+    int32_t *stage = reinterpret_cast<int32_t *>(lds + (L + 1) * 64);
+    int32_t *Rrow = stage + SH_WAVES * CL_SB * 64;
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int64_t tile = blockIdx.x;
+    const int j = chunks[3 * blockIdx.y];
+    const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
+    const int64_t q = tile * 64 + lane;
+    const bool valid = q < nq;
+    for (int e = tid; e <= L; e += SH_WAVES * 64) Rrow[e] = R[(int64_t)j * (L + 1) + e];
+    __syncthreads();
+    int hcut = -1;
+    uint32_t q0 = 0, q1 = 0;
+    if (valid) {
+        const int32_t rho = grho[q];
+        int lo = 0, hi = L + 1;  // #{h : rank(j, h) < rho}
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (Rrow[L - mid] < rho) lo = mid + 1;
+            else hi = mid;
+        }
+        hcut = lo - 1;
+        const int64_t r = qrow(q, j, qsets);
+        q0 = qcodes[r * W];
+        if (W == 2) q1 = qcodes[r * W + 1];
+    }
+    if (__ballot(hcut >= 0) == 0ull) return;  // the same for every wave of the block
+    if (npairs && tid == 0)
+        atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - tile * 64) * (p1 - p0)));
+    for (int e = tid; e < (L + 1) * 64; e += SH_WAVES * 64) hist[e] = 0u;
+    __syncthreads();
+    int32_t *st = stage + wave * CL_SB * 64;
+    int cnt = 0;
+    const uint32_t negt = (uint32_t)(-(hcut + 1));  // h <= hcut  <=>  h - (hcut + 1) < 0
+    const int64_t ng = (p1 - p0) >> 4;
+    uint32_t c[16 * W], cn[16 * W];
+    if (wave < ng) load_group16<W>(codes_l, p0 + (int64_t)wave * 16, c);
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    for (int64_t g = wave; g < ng; g += SH_WAVES) {
+        const int64_t p = p0 + g * 16;
+        if (g + SH_WAVES < ng) load_group16<W>(codes_l, p + SH_WAVES * 16, cn);
+        uint32_t mask = 0;
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            uint32_t hd = (uint32_t)__popc(c[u * W] ^ q0) + negt;
+            if (W == 2) hd += (uint32_t)__popc(c[u * W + 1] ^ q1);
+            mask |= (hd >> 31) << u;
+        }
+        // at most 16 more per group: room is left while every lane holds < 16
+        while (mask != 0u) {
+            const int u = __builtin_ctz(mask);
+            mask &= mask - 1u;
+            st[cnt * 64 + lane] = (int32_t)(p + u);
+            ++cnt;
+        }
+        if (__ballot(cnt >= CL_SB - 16) != 0ull) {
+            collect_flush<W>(st, lane, cnt, codes_l, q0, q1, L, Rrow, hist, counts, keys, q, cap);
+            cnt = 0;
+        }
+#pragma unroll
+        for (int u = 0; u < 16 * W; ++u) c[u] = cn[u];
+    }
+    if (wave == SH_WAVES - 1) {
+        for (int64_t p = p0 + ng * 16; p < p1; ++p) {  // fewer than 16 items
+            int h = __popc(codes_l[p * W] ^ q0);
+            if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
+            if (h <= hcut) st[(cnt++) * 64 + lane] = (int32_t)p;
+        }
+    }
+    if (__ballot(cnt > 0) != 0ull)
+        collect_flush<W>(st, lane, cnt, codes_l, q0, q1, L, Rrow, hist, counts, keys, q, cap);
+    __syncthreads();
+    uint32_t *out = ghist + ((tile * m + j) * (int64_t)(L + 1)) * 64;
+    for (int e = tid; e < (L + 1) * 64; e += SH_WAVES * 64) {
+        const uint32_t v = hist[e];
+        if (v) atomicAdd(&out[e], v);
+    }
+}
+
+// The probed list of each query from its collected keys: rank < b*, or
+// rank = b* and stored position <= P* (k_threshold, k_tie_locate).  One
+// block per query; the list order is that of arrival (the re-rank's tie rule
+// makes the top-k independent of it).  lcount[q] receives the list length
+// (Tq when the query's collection was complete); `fail` (one word per call
+// batch) is set when a query collected fewer than Tq keys or more than cap.
+__global__ __launch_bounds__(256) void k_collect_filter(const uint64_t *__restrict__ keys,
+                                                        const int32_t *__restrict__ counts, int64_t cap,
+                                                        const int32_t *__restrict__ gtie,
+                                                        const int32_t *__restrict__ gpstar, int64_t Tq,
+                                                        int32_t *__restrict__ cand,
+                                                        int32_t *__restrict__ lcount,
+                                                        uint32_t *__restrict__ fail)
+{
+    __shared__ int32_t total;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t q = blockIdx.x;
+    const int32_t *tie = gtie + (q >> 6) * 4 * 64;
+    const uint32_t bstar = (uint32_t)tie[3 * 64 + (q & 63)];
+    const uint32_t pstar = (uint32_t)gpstar[q];  // INT_MAX: the whole bucket
+    const int64_t C = counts[q];
+    const int64_t E = min(C, cap);
+    if (tid == 0) {
+        total = 0;
+        if (C < Tq || C > cap) atomicOr(fail, 1u);
+    }
+    __syncthreads();
+    const uint64_t *kq = keys + q * cap;
+    for (int64_t e0 = 0; e0 < E; e0 += 256) {
+        const int64_t e = e0 + tid;
+        bool keep = false;
+        uint32_t pos = 0;
+        if (e < E) {
+            const uint64_t key = kq[e];
+            const uint32_t rank = (uint32_t)(key >> 32);
+            pos = (uint32_t)key;
+            keep = rank < bstar || (rank == bstar && pos <= pstar);
+        }
+        const uint64_t kb = __ballot(keep);
+        if (kb != 0ull) {
+            const int leader = __ffsll((long long)kb) - 1;
+            int base = 0;
+            if (lane == leader) base = atomicAdd(&total, __popcll(kb));
+            base = __shfl(base, leader, 64);
+            const int64_t slot = base + __popcll(kb & ((1ull << lane) - 1ull));
+            if (keep && slot < Tq) cand[q * Tq + slot] = (int32_t)pos;
+        }
+    }
+    __syncthreads();
+    if (tid == 0) lcount[q] = total;
 }
 
 // ---------------------------------------------------------------- rerank
@@ -1950,17 +2148,62 @@ hipError_t launch_fill32(void *p, int64_t words, uint32_t v, hipStream_t s)
 hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
                                   const QueryShape &sh, const int32_t *chunks, int nchunks,
                                   const int32_t *need, uint32_t *ghist, unsigned long long *npairs,
-                                  hipStream_t s)
+                                  hipStream_t s, int gstride)
 {
     if (nq < 1 || nchunks < 1) return hipSuccess;
+    if (gstride < 1) return hipErrorInvalidValue;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
     const size_t lds = (size_t)(sh.L + 1) * 64 * sizeof(uint32_t);
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_hist_s<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq,
-                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs);
+                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs, gstride);
     else
         hipLaunchKernelGGL(k_scan_hist_s<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq,
-                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs);
+                           sh.m, sh.L, sh.qsets, chunks, need, ghist, npairs, gstride);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
+                               const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
+                               int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
+                               unsigned long long *npairs, hipStream_t s)
+{
+    if (nq < 1 || nchunks < 1) return hipSuccess;
+    const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    const size_t lds = ((size_t)(sh.L + 1) * 64 + (size_t)SH_WAVES * CL_SB * 64 + (sh.L + 1)) * sizeof(uint32_t);
+    if (sh.W == 1)
+        hipLaunchKernelGGL(k_scan_collect<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m, sh.L,
+                           sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+    else
+        hipLaunchKernelGGL(k_scan_collect<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m, sh.L,
+                           sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+    return hipGetLastError();
+}
+
+hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, int64_t cap, int64_t nq,
+                                 const int32_t *gtie, const int32_t *gpstar, int64_t Tq, int32_t *cand,
+                                 int32_t *lcount, uint32_t *fail, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_collect_filter, dim3((unsigned)nq), dim3(256), 0, s, keys, counts, cap, gtie, gpstar, Tq,
+                       cand, lcount, fail);
+    return hipGetLastError();
+}
+
+// rho[q] = b*' + 1 of a threshold pass (gtie's b* row), capped at P buckets.
+__global__ __launch_bounds__(64) void k_rho_from_tie(const int32_t *__restrict__ gtie, int64_t nq, int32_t P,
+                                                     int32_t *__restrict__ rho)
+{
+    const int64_t q = (int64_t)blockIdx.x * 64 + threadIdx.x;
+    if (q >= nq) return;
+    const int32_t b = gtie[(q >> 6) * 4 * 64 + 3 * 64 + (q & 63)];
+    rho[q] = b < 0 || b >= P ? P : b + 1;
+}
+
+hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_rho_from_tie, dim3(ceil_div(nq, 64)), dim3(64), 0, s, gtie, nq, P, rho);
     return hipGetLastError();
 }
 

@@ -193,10 +193,27 @@ hipError_t launch_fill32(void *p, int64_t words, uint32_t v, hipStream_t s);
 // are skipped (need may be NULL: every tile).  launch_stage_check then clears
 // need[tile] once every query of the tile has Tq items in buckets ranked
 // before `cut`.  npairs (or NULL) accumulates the (query, item) pairs scanned.
+// gstride > 1 counts a sample instead: every gstride-th 16-item group of each
+// chunk (no partial group).
 hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq,
                                   const QueryShape &sh, const int32_t *chunks, int nchunks,
                                   const int32_t *need, uint32_t *ghist, unsigned long long *npairs,
-                                  hipStream_t s);
+                                  hipStream_t s, int gstride = 1);
+// Collecting scan: every item whose bucket ranks before grho[q] is appended
+// to query q's keys (nq x cap, rank << 32 | stored position; counts zeroed by
+// the caller, may exceed cap) and counted in ghist (zeroed by the caller).
+hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
+                               const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
+                               int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
+                               unsigned long long *npairs, hipStream_t s);
+// The probed list (nq x Tq) of each query from its collected keys and the
+// threshold (gtie) and tie position (gpstar); lcount[q] = its length; *fail
+// is set when a query's keys were incomplete (fewer than Tq, or over cap).
+hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, int64_t cap, int64_t nq,
+                                 const int32_t *gtie, const int32_t *gpstar, int64_t Tq, int32_t *cand,
+                                 int32_t *lcount, uint32_t *fail, hipStream_t s);
+// rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
+hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
 // Pass 2 over the same chunks: appends each query's probed items to its list
 // (counts zeroed by the caller; order unspecified), cutting the threshold
 // bucket at gpstar (launch_tie_locate).
