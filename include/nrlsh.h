@@ -26,7 +26,8 @@
  *     given opts->device_ptrs = 1, in which case they are device pointers on
  *     the current HIP device (e.g. a torch tensor's data_ptr()).
  *   - When a call returns, its outputs are written and the caller may reuse
- *     or free its inputs.  nrlsh_build copies the items and returns once the
+ *     or free its inputs (nrlsh_query_noalloc excepted: it queues its work on
+ *     the caller's stream and returns).  nrlsh_build copies the items and returns once the
  *     last read of them is done; the rest of the index's device work (the
  *     hash and its FP64 fix-up) may still be queued on the library's stream,
  *     and every later call on the index is ordered after it (queries wait

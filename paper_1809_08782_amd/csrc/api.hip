@@ -491,7 +491,9 @@ ScanStages scan_stages(const nrlsh_index *ix, int64_t tiles)
             items += ix->off_h[j + 1] - ix->off_h[j];
         }
         int64_t chunk = (items * std::max<int64_t>(tiles, 1) + 2047) / 2048;
-        chunk = std::max<int64_t>(2048, (chunk + 63) / 64 * 64);
+        // fewer than 2^16 items: the collecting scan stages 16-bit offsets and
+        // counts a chunk's items per (query, level) in 16-bit halves
+        chunk = std::min<int64_t>(65472, std::max<int64_t>(2048, (chunk + 63) / 64 * 64));
         for (int i = b; i < ends[s]; ++i) {
             const int j = ix->jord_h[i];
             for (int64_t p = ix->off_h[j]; p < ix->off_h[j + 1]; p += chunk) {

@@ -745,13 +745,14 @@ constexpr int CL_SB = 32;  // staged positions per lane of the collecting scan
 // Every lane empties its staged positions (cnt of them) into its query's
 // keys: one reservation per lane, then batches of 8 whose code loads are
 // issued together.  Called by the whole wave, so that no lane waits alone.
-template <int W>
-__device__ __forceinline__ void collect_flush(const int32_t *__restrict__ stage, int lane, int cnt,
+template <int W, typename S = int32_t>
+__device__ __forceinline__ void collect_flush(const S *__restrict__ stage, int lane, int cnt,
                                               const uint32_t *__restrict__ codes_l, uint32_t q0, uint32_t q1,
                                               int L, const int32_t *__restrict__ Rrow, uint32_t *hist,
                                               int32_t *__restrict__ counts, uint64_t *__restrict__ keys,
-                                              int64_t q, int64_t cap)
+                                              int64_t q, int64_t cap, int col = -1, int64_t pbase = 0)
 {
+    if (col < 0) col = lane;
     int64_t base = 0;
     if (cnt > 0) base = atomicAdd(&counts[q], cnt);
     int top = cnt;
@@ -761,7 +762,7 @@ __device__ __forceinline__ void collect_flush(const int32_t *__restrict__ stage,
         int32_t pp[8];
         uint32_t a[8], b[8];
 #pragma unroll
-        for (int v = 0; v < 8; ++v) pp[v] = i0 + v < cnt ? stage[(i0 + v) * 64 + lane] : -1;
+        for (int v = 0; v < 8; ++v) pp[v] = i0 + v < cnt ? (int32_t)(pbase + stage[(i0 + v) * 64 + lane]) : -1;
 #pragma unroll
         for (int v = 0; v < 8; ++v) {
             a[v] = pp[v] >= 0 ? codes_l[(int64_t)pp[v] * W] : 0u;
@@ -772,7 +773,7 @@ __device__ __forceinline__ void collect_flush(const int32_t *__restrict__ stage,
             if (pp[v] < 0) continue;
             int h = __popc(a[v] ^ q0);
             if (W == 2) h += __popc(b[v] ^ q1);
-            __hip_atomic_fetch_add(&hist[h * 64 + lane], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            __hip_atomic_fetch_add(&hist[h * 64 + col], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (base + i0 + v < cap)
                 keys[q * cap + base + i0 + v] = ((uint64_t)(uint32_t)Rrow[L - h] << 32) | (uint32_t)pp[v];
         }
@@ -868,6 +869,226 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect(const uint32_t *
     for (int e = tid; e < (L + 1) * 64; e += SH_WAVES * 64) {
         const uint32_t v = hist[e];
         if (v) atomicAdd(&out[e], v);
+    }
+}
+
+// Matrix-core form of the collecting scan.  With a_k in {0, 1} the bits of
+// an item's code and t_k = 1 - 2 q_k the query's bits as +-1, the integer dot
+// product sum_k a_k t_k = popc(c) - 2 popc(c & q) = h - popc(q), so one
+// v_mfma_i32_32x32x32_i8 per 32 code bits gives the Hamming distances of 32
+// items x 32 queries; the accumulators start at popc(q) - hcut - 1, so that
+// an item is collected exactly when its accumulator ends negative (h <= hcut),
+// and its level is h = acc + hcut + 1.  A wave takes 32 items at a time
+// against both 32-query halves of the tile (lane l: query 32 c + (l & 31) of
+// half c; rows 8 (r / 4) + 4 (l / 32) + r % 4 of accumulator r); the sign
+// bits become a per-lane row mask with one funnel shift each and the low
+// bytes of the accumulators are packed four to a word, from which a hit's
+// level is read back.  Hits are staged in LDS as 16-bit offsets in the chunk
+// (chunks hold fewer than 2^16 items) plus their level, and counted per
+// (query, level) in 16-bit halves of the block's histogram words.
+typedef int int32x4_t __attribute__((ext_vector_type(4)));
+typedef int int32x16_t __attribute__((ext_vector_type(16)));
+constexpr int MX_SB = 24;  // staged hits per (lane, query half)
+
+// byte s of the result = bit s of the low 16 bits of v (0 or 1)
+__device__ __forceinline__ int32x4_t bits16_to_bytes(uint32_t v)
+{
+    int32x4_t r;
+#pragma unroll
+    for (int n = 0; n < 4; ++n) r[n] = (int)((((v >> (4 * n)) & 0xFu) * 0x00204081u) & 0x01010101u);
+    return r;
+}
+
+// Every lane empties its staged hits of one query half into the query's keys:
+// the reservation is issued first, the keys are formed (levels counted in the
+// LDS histogram, ranks read from the R row) while it is in flight, then
+// stored.  Called by the whole wave.
+__device__ __forceinline__ void collect_flush_mx(const uint16_t *__restrict__ so, const uint8_t *__restrict__ sh,
+                                                 int lane, int cnt, int L, const int32_t *__restrict__ Rrow,
+                                                 uint32_t *hist, int col, int32_t *__restrict__ counts,
+                                                 uint64_t *__restrict__ keys, int64_t q, int64_t cap, int64_t p0)
+{
+    int64_t base = 0;
+    if (cnt > 0) base = atomicAdd(&counts[q], cnt);
+    int top = cnt;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
+    const uint32_t inc = 1u << (16 * (col & 1)), hc = (uint32_t)(col >> 1);
+    for (int i0 = 0; i0 < top; i0 += 8) {
+        uint64_t kv[8];
+#pragma unroll
+        for (int v = 0; v < 8; ++v) {
+            kv[v] = ~0ull;
+            if (i0 + v < cnt) {
+                const int e = (i0 + v) * 64 + lane;
+                const int h = min((int)sh[e], L);  // a hit's level is at most its query's cut, <= L
+                __hip_atomic_fetch_add(&hist[h * 32 + hc], inc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                kv[v] = ((uint64_t)(uint32_t)Rrow[L - h] << 32) | (uint32_t)(p0 + so[e]);
+            }
+        }
+#pragma unroll
+        for (int v = 0; v < 8; ++v)
+            if (i0 + v < cnt && base + i0 + v < cap) keys[q * cap + base + i0 + v] = kv[v];
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_t *__restrict__ codes_l,
+                                                                   const uint32_t *__restrict__ qcodes,
+                                                                   int64_t nq, int m, int L, int qsets,
+                                                                   const int32_t *__restrict__ chunks,
+                                                                   const int32_t *__restrict__ R,
+                                                                   const int32_t *__restrict__ grho,
+                                                                   int64_t cap, int32_t *__restrict__ counts,
+                                                                   uint64_t *__restrict__ keys,
+                                                                   uint32_t *__restrict__ ghist,
+                                                                   unsigned long long *__restrict__ npairs)
+{
+    // hist (L+1) x 32 words (queries 2 w, 2 w + 1 in the low / high halves) |
+    // staged offsets SH_WAVES x 2 x MX_SB x 64 (u16) | staged levels (u8) | R row
+    extern __shared__ uint32_t lds[];
+    uint32_t *hist = lds;
+    uint16_t *stage_o = reinterpret_cast<uint16_t *>(lds + (L + 1) * 32);
+    uint8_t *stage_h = reinterpret_cast<uint8_t *>(stage_o + SH_WAVES * 2 * MX_SB * 64);
+    int32_t *Rrow = reinterpret_cast<int32_t *>(stage_h + SH_WAVES * 2 * MX_SB * 64);
+    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int64_t tile = blockIdx.x;
+    const int j = chunks[3 * blockIdx.y];
+    const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
+    for (int e = tid; e <= L; e += SH_WAVES * 64) Rrow[e] = R[(int64_t)j * (L + 1) + e];
+    __syncthreads();
+    // per query of the tile (lane = query): its cut level and code
+    int hq = -1;
+    uint32_t w0 = 0, w1 = 0;
+    {
+        const int64_t q = tile * 64 + lane;
+        if (q < nq) {
+            const int32_t rho = grho[q];
+            int lo = 0, hi = L + 1;  // #{h : rank(j, h) < rho}
+            while (lo < hi) {
+                const int mid = (lo + hi) >> 1;
+                if (Rrow[L - mid] < rho) lo = mid + 1;
+                else hi = mid;
+            }
+            hq = lo - 1;
+            const int64_t r = qrow(q, j, qsets);
+            w0 = qcodes[r * W];
+            if (W == 2) w1 = qcodes[r * W + 1];
+        }
+    }
+    if (__ballot(hq >= 0) == 0ull) return;  // the same for every wave of the block
+    if (npairs && tid == 0)
+        atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - tile * 64) * (p1 - p0)));
+    for (int e = tid; e < (L + 1) * 32; e += SH_WAVES * 64) hist[e] = 0u;
+    __syncthreads();
+
+    const int hb = lane >> 5, col0 = lane & 31;
+    int32x4_t bq[2][W];
+    int init[2], hcut[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int src = 32 * c + col0;
+        hcut[c] = __shfl(hq, src, 64);
+        const uint32_t qa = __shfl(w0, src, 64);
+        const uint32_t qb = W == 2 ? __shfl(w1, src, 64) : 0u;
+        init[c] = __popc(qa) + __popc(qb) - hcut[c] - 1;
+#pragma unroll
+        for (int mm = 0; mm < W; ++mm) {
+            const int32x4_t y = bits16_to_bytes(((mm == 0 ? qa : qb) >> (16 * hb)) & 0xFFFFu);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) bq[c][mm][n] = (int)(0x01010101u + (uint32_t)y[n] * 0xFEu);  // +-1 bytes
+        }
+    }
+    const int so0 = (wave * 2 + 0) * MX_SB * 64, so1 = (wave * 2 + 1) * MX_SB * 64;
+    int cnt0 = 0, cnt1 = 0;
+    const int64_t ng = (p1 - p0 + 31) >> 5;  // 32-item groups, the last one partial
+    // codes of item min(p + col0, p1 - 1) of a group: loads stay inside the
+    // chunk (rows past its end are masked out below)
+    uint32_t a0, a1 = 0;
+    {
+        const int64_t pi = min(p0 + (int64_t)wave * 32 + col0, p1 - 1);
+        a0 = codes_l[pi * W];
+        if (W == 2) a1 = codes_l[pi * W + 1];
+    }
+    // vmcnt(0): the first group is in before the loop, whose body then waits
+    // for its prefetch only at its end
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    for (int64_t g = wave; g < ng; g += SH_WAVES) {
+        const int64_t p = p0 + g * 32;
+        int32x4_t aa[W];
+        aa[0] = bits16_to_bytes((a0 >> (16 * hb)) & 0xFFFFu);
+        if (W == 2) aa[W - 1] = bits16_to_bytes((a1 >> (16 * hb)) & 0xFFFFu);
+        // the next group's codes load while this one is matched
+        {
+            const int64_t pi = min(p + SH_WAVES * 32 + col0, p1 - 1);
+            a0 = codes_l[pi * W];
+            if (W == 2) a1 = codes_l[pi * W + 1];
+        }
+        // rows past the chunk's end (last group only) are never collected
+        uint32_t vmask = 0xFFFFu;
+        if (p + 32 > p1) {
+            vmask = 0u;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) vmask |= (uint32_t)(p + 8 * (r >> 2) + 4 * hb + (r & 3) < p1) << r;
+        }
+        const int gofs = (int)(p - p0) + 4 * hb;  // chunk offset of row 0 of this lane
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            int32x16_t acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = init[c];
+#pragma unroll
+            for (int mm = 0; mm < W; ++mm) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[mm], bq[c][mm], acc, 0, 0, 0);
+            uint32_t mask = 0u;
+#pragma unroll
+            for (int r = 15; r >= 0; --r) mask = __builtin_amdgcn_alignbit(mask, (uint32_t)acc[r], 31);
+            mask &= vmask;
+            // low bytes of the accumulators, four to a word (byte r & 3 of word r >> 2)
+            uint32_t pk[4];
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+                const uint32_t lo = __builtin_amdgcn_perm((uint32_t)acc[4 * w + 1], (uint32_t)acc[4 * w], 0x0C0C0400u);
+                const uint32_t hi = __builtin_amdgcn_perm((uint32_t)acc[4 * w + 3], (uint32_t)acc[4 * w + 2], 0x0C0C0400u);
+                pk[w] = __builtin_amdgcn_perm(hi, lo, 0x05040100u);
+            }
+            const int sbase = c == 0 ? so0 : so1;
+            int cnt = c == 0 ? cnt0 : cnt1;
+            while (mask != 0u) {
+                const int r = __builtin_ctz(mask);
+                mask &= mask - 1u;
+                const uint32_t wsel = (r & 8) ? ((r & 4) ? pk[3] : pk[2]) : ((r & 4) ? pk[1] : pk[0]);
+                const int acc_lo = (int)((wsel >> (8 * (r & 3))) & 0xFFu);  // acc + 256 (acc in [-256, -1])
+                const int e = sbase + cnt * 64 + lane;
+                stage_o[e] = (uint16_t)(gofs + 8 * (r >> 2) + (r & 3));
+                stage_h[e] = (uint8_t)(acc_lo - 256 + hcut[c] + 1);
+                ++cnt;
+            }
+            if (c == 0) cnt0 = cnt;
+            else cnt1 = cnt;
+        }
+        // at most 16 more per half and group: room is left while every count is <= MX_SB - 16
+        if (__ballot(cnt0 > MX_SB - 16 || cnt1 > MX_SB - 16) != 0ull) {
+            collect_flush_mx(stage_o + so0, stage_h + so0, lane, cnt0, L, Rrow, hist, col0, counts, keys,
+                             tile * 64 + col0, cap, p0);
+            collect_flush_mx(stage_o + so1, stage_h + so1, lane, cnt1, L, Rrow, hist, 32 + col0, counts, keys,
+                             tile * 64 + 32 + col0, cap, p0);
+            cnt0 = cnt1 = 0;
+        }
+    }
+    if (__ballot(cnt0 > 0 || cnt1 > 0) != 0ull) {
+        collect_flush_mx(stage_o + so0, stage_h + so0, lane, cnt0, L, Rrow, hist, col0, counts, keys,
+                         tile * 64 + col0, cap, p0);
+        collect_flush_mx(stage_o + so1, stage_h + so1, lane, cnt1, L, Rrow, hist, 32 + col0, counts, keys,
+                         tile * 64 + 32 + col0, cap, p0);
+    }
+    __syncthreads();
+    uint32_t *out = ghist + ((tile * m + j) * (int64_t)(L + 1)) * 64;
+    for (int e = tid; e < (L + 1) * 32; e += SH_WAVES * 64) {
+        const uint32_t v = hist[e];
+        if (v == 0u) continue;
+        const int h = e >> 5, qq = 2 * (e & 31);
+        if (v & 0xFFFFu) atomicAdd(&out[h * 64 + qq], v & 0xFFFFu);
+        if (v >> 16) atomicAdd(&out[h * 64 + qq + 1], v >> 16);
     }
 }
 
@@ -2166,10 +2387,22 @@ hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcode
 hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
                                const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
                                int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
-                               unsigned long long *npairs, hipStream_t s)
+                               unsigned long long *npairs, hipStream_t s, bool mfma)
 {
     if (nq < 1 || nchunks < 1) return hipSuccess;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
+    if (mfma) {
+        const size_t lds = (size_t)(sh.L + 1) * 32 * sizeof(uint32_t) +
+                           (size_t)SH_WAVES * 2 * MX_SB * 64 * (sizeof(uint16_t) + sizeof(uint8_t)) +
+                           (size_t)(sh.L + 1) * sizeof(int32_t);
+        if (sh.W == 1)
+            hipLaunchKernelGGL(k_scan_collect_mx<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
+                               sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+        else
+            hipLaunchKernelGGL(k_scan_collect_mx<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
+                               sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+        return hipGetLastError();
+    }
     const size_t lds = ((size_t)(sh.L + 1) * 64 + (size_t)SH_WAVES * CL_SB * 64 + (sh.L + 1)) * sizeof(uint32_t);
     if (sh.W == 1)
         hipLaunchKernelGGL(k_scan_collect<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m, sh.L,

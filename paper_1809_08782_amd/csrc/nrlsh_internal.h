@@ -202,10 +202,11 @@ hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcode
 // Collecting scan: every item whose bucket ranks before grho[q] is appended
 // to query q's keys (nq x cap, rank << 32 | stored position; counts zeroed by
 // the caller, may exceed cap) and counted in ghist (zeroed by the caller).
+// mfma: the matrix-core form (chunks of at most 2^16 items).
 hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
                                const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
                                int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
-                               unsigned long long *npairs, hipStream_t s);
+                               unsigned long long *npairs, hipStream_t s, bool mfma = true);
 // The probed list (nq x Tq) of each query from its collected keys and the
 // threshold (gtie) and tie position (gpstar); lcount[q] = its length; *fail
 // is set when a query's keys were incomplete (fewer than Tq, or over cap).
