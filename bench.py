@@ -54,9 +54,9 @@ def ground_truth(Xd, Qs, k):
 
 
 def traffic_record(kernel, workload, T):
-    """HBM bytes per launch of `kernel` from a committed counter summary
-    (profiles/*.md, a line "traffic_record: {json}"), provided the sources it
-    names still hash to what they were when the counters were taken."""
+    """HBM bytes per query of a launch of `kernel` from a committed counter
+    summary (profiles/*.md, a line "traffic_record: {json}"), provided the
+    sources it names still hash to what they were when the counters were taken."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -223,6 +223,7 @@ KERNELS = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup
            "rerank", "rerank_lp", "screen_max", "screen", "rerank_exact"]
 BUILD_KERNELS = {"keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table"}
 INT_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes per clock x 2.4 GHz
+INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core peak, TOP/s
 
 
 def main():
@@ -457,10 +458,11 @@ def main():
         frac = pairs / (last_nq * w.n)
         per = kern[scan_kernel]
         step_pairs = frac * w.nq * w.n  # scanned pairs of the whole step, at the last batch's fraction
-        # the collecting scan: XOR + popcount per code word, the sign test (3
-        # ops) against the query's cut per pair; the first of the two passes:
-        # XOR + popcount per word and the histogram address (1 op)
-        ops = 2 * W + (3 if scan_kernel == "scan_collect" else 1)
+        # the two passes: XOR + popcount per code word and the histogram
+        # address (1 op) per pair, on the vector ALUs; the collecting scan:
+        # 32 W int8 multiply-adds per pair on the matrix cores (2 ops each)
+        collect = scan_kernel == "scan_collect"
+        ops = 64 * W if collect else 2 * W + 1
         scan = {"kernel": scan_kernel,
                 "pairs_scanned_last_batch": pairs,
                 "last_batch_queries": last_nq,
@@ -472,7 +474,10 @@ def main():
                 "other_ms_per_step": {nm: kern[nm]["ms_per_step"] for nm in
                                       ("scan_sample", "guess", "threshold", "tie_locate", "filter",
                                        "scan_hist", "scan_emit") if nm in kern and nm != scan_kernel}}
-        if scan["pairs_per_s"]:
+        if scan["pairs_per_s"] and collect:
+            scan["int8_mfma_tops"] = scan["pairs_per_s"] * ops / 1e12
+            scan["int8_mfma_frac"] = scan["int8_mfma_tops"] / INT8_MFMA_PEAK_TOPS
+        elif scan["pairs_per_s"]:
             scan["int_valu_tops"] = scan["pairs_per_s"] * ops / 1e12
             scan["int_valu_frac"] = scan["int_valu_tops"] / INT_VALU_PEAK_TOPS
 
@@ -560,9 +565,11 @@ def roofline(dom, kern, w, Tq, qb, qstats):
         S = next(v for v in (1, 2, 4, 8, 16) if v * 64 >= w.k or v == 16)  # top-k registers per lane
         kname = ("k_rerank<%d>" if dom == "rerank" else "k_rerank_bf16<%d>") % S
         rec = traffic_record(kname, w.name, Tq)
+        # counters were taken on full batches: bytes per query x this run's queries per launch
+        traffic = ((rec["fetch_bytes_per_query"] + rec["write_bytes_per_query"]) * nq_launch) if rec else None
         return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS,
-                "traffic": (rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]) if rec else None,
+                "traffic": traffic,
                 "traffic_source": rec, "bytes_per_launch": bytes_launch, "unit_work": "probed item",
                 "bytes_per_unit": row + 8, "units_per_launch": nq_launch * Tq, "dominant_kernel": dom}
     if dom in ("scan_hist", "scan_emit", "scan_collect"):
@@ -572,13 +579,15 @@ def roofline(dom, kern, w, Tq, qb, qstats):
         frac = (qstats.get("scan_pairs") or 0) / (last_nq * w.n)
         if dom == "scan_emit" or frac == 0:
             frac = 1.0
-        ops_per_pair = 2 * W + (3 if dom == "scan_collect" else 1)
+        mx = dom == "scan_collect"
+        ops_per_pair = 64 * W if mx else 2 * W + 1
+        peak = INT8_MFMA_PEAK_TOPS if mx else INT_VALU_PEAK_TOPS
         ops_step = frac * w.nq * w.n * ops_per_pair
         achieved = ops_step / (per["ms_per_step"] * 1e-3) / 1e12
         kname = {"scan_hist": "k_scan_hist_s<%d>", "scan_emit": "k_scan_emit_s<%d>",
-                 "scan_collect": "k_scan_collect<%d>"}[dom] % W
-        return {"kernel": kname, "bound": "alu", "achieved": achieved, "peak": INT_VALU_PEAK_TOPS,
-                "unit": "TOP/s", "frac": achieved / INT_VALU_PEAK_TOPS, "traffic": None,
+                 "scan_collect": "k_scan_collect_mx<%d>"}[dom] % W
+        return {"kernel": kname, "bound": "mfma" if mx else "alu", "achieved": achieved, "peak": peak,
+                "unit": "TOP/s", "frac": achieved / peak, "traffic": None,
                 "ops_per_step": ops_step, "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair,
                 "dominant_kernel": dom}
     if dom == "screen":
