@@ -971,7 +971,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     B = std::min<int64_t>(B, (nq + 63) / 64 * 64);
     if (table) B = std::min<int64_t>(B, 16384);  // bounds the per-query bucket scratch
     // Large budgets take the collecting scan: a sample pass (every gstride-th
-    // 16-item group) guesses each query's cut rho_q so that about 1.25 Tq
+    // 16-item group) guesses each query's cut rho_q so that about 1.125 Tq
     // items rank before it, one scan collects those items, and the threshold
     // pass plus a filter of the collected keys give the probed set; a batch
     // in which some query collected fewer than Tq (or more than kcap) items
@@ -979,7 +979,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int32_t sguess = g_scan_guess;
     const int gstride = (int)std::max<int64_t>(1, std::min<int64_t>(64, sh.Tq / 1600));
     const bool collect = !table && sguess >= 0 && (sguess > 0 || gstride >= 4) && sh.Tq * 3 < ix->n * 2;
-    const int64_t guess16 = sguess > 0 ? sguess : 20;  // guessed items, in sixteenths of Tq
+    const int64_t guess16 = sguess > 0 ? sguess : 18;  // guessed items, in sixteenths of Tq
     const int64_t kcap = collect ? 2 * sh.Tq + 16384 : 0;
     if (collect) B = std::min<int64_t>(B, std::max<int64_t>(64, (int64_t(1) << 32) / (kcap * 8) / 64 * 64));
     const int64_t tiles = B / 64;
@@ -1080,7 +1080,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         if (!table && collect && !staged) {
             const int64_t tb = (nb + 63) / 64;
             const int32_t P = sh.m * L1;
-            QueryShape shg = sh;  // the guess (1.25 Tq items by default), in sample units
+            QueryShape shg = sh;  // the guess (1.125 Tq items by default), in sample units
             shg.Tq = std::max<int64_t>(1, (sh.Tq * guess16 / 16 + gstride - 1) / gstride);
             HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
             tm.begin("scan_sample");
@@ -1089,7 +1089,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             tm.end();
             tm.begin("guess");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, shg, gbase.get(), ghthr.get(),
-                                  gtie_g.get(), s));
+                                  gtie_g.get(), s, false));
             HIPX(launch_rho_from_tie(gtie_g.get(), nb, P, grho.get(), s));
             tm.end();
             HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
@@ -1100,7 +1100,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             tm.end();
             tm.begin("threshold");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(), ghthr.get(),
-                                  gtie.get(), s));
+                                  gtie.get(), s, false));
             tm.end();
             tm.begin("tie_locate");
             HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),

@@ -158,6 +158,7 @@ __device__ __forceinline__ int wave_max_int(int v)
     return v;
 }
 
+template <bool BOUNDS>
 __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__restrict__ ghist,
                                                              const int32_t *__restrict__ R,
                                                              const int32_t *__restrict__ inv, int64_t nq,
@@ -233,6 +234,16 @@ __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__r
     // items belong to no bucket, as under single probe): every bucket is
     // probed whole
     if (valid && bstar < 0) bstar = (int32_t)P;
+    if (!BOUNDS) {  // the threshold bucket and its cut only
+        if (wave == 0) {
+            int32_t *tie = gtie + (int64_t)tile * 4 * 64;
+            tie[0 * 64 + lane] = valid ? jstar : -1;
+            tie[1 * 64 + lane] = res_s[3][lane];
+            tie[2 * 64 + lane] = res_s[4][lane] ? INT_MAX : rstar;
+            tie[3 * 64 + lane] = bstar;
+        }
+        return;
+    }
 
     // 2. per-sub-dataset bounds and emission offsets
     const int ja = (int)((int64_t)m * wave / TH_WAVES), jb = (int)((int64_t)m * (wave + 1) / TH_WAVES);
@@ -2303,10 +2314,14 @@ hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const u
 
 hipError_t launch_threshold(const uint32_t *ghist, const int32_t *R, const int32_t *inv, int64_t nq,
                             const QueryShape &sh, int32_t *gbase, int32_t *ghthr, int32_t *gtie,
-                            hipStream_t s)
+                            hipStream_t s, bool bounds)
 {
-    hipLaunchKernelGGL(k_threshold, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv, nq, sh.m,
-                       sh.L, sh.Tq, gbase, ghthr, gtie);
+    if (bounds)
+        hipLaunchKernelGGL(k_threshold<true>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv,
+                           nq, sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
+    else
+        hipLaunchKernelGGL(k_threshold<false>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv,
+                           nq, sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
     return hipGetLastError();
 }
 
