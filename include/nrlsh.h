@@ -243,6 +243,17 @@ typedef struct nrlsh_query_opts {
                             g in 1..4096 = the collecting scan for every budget below
                             2n/3, guessing g/16 T items (small or large g make the
                             guess miss: for tests of the fallback) */
+    int32_t dense_head;  /* BF16 re-rank storage with the collecting scan (same result
+                            either way): 0 = default, the contiguous range of
+                            sub-datasets around the one with the largest probed
+                            fraction, while that fraction is at least 3/128, is
+                            screened whole on the matrix cores (bfloat16 query
+                            tiles x all its items, the SCREEN path's two passes and
+                            probe test) instead of gathering its probed rows; the
+                            other sub-datasets' probed items are gathered as usual;
+                            -1 = no dense head; g in 1..256 = fraction at least
+                            g/256.  The fractions are estimated from the sample pass
+                            of the call's first batch (one host round trip). */
 } nrlsh_query_opts;
 
 nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t nq, int32_t k,
@@ -491,6 +502,8 @@ typedef struct nrlsh_query_stats {
                               budget (its guessed cut too tight, or more items than
                               the key room) and that were probed again by the two
                               exact passes; results never depend on it */
+    int64_t dense_head_items; /* BF16 re-rank: items of the sub-datasets screened whole
+                              (dense_head) in the call's last batch that used it, else 0 */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

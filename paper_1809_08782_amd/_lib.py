@@ -46,7 +46,7 @@ STORAGES = {"fp32": 0, "bf16": 1, "fp8": 2}
 class QueryOpts(C.Structure):
     _fields_ = [("struct_size", C.c_int32), ("device_ptrs", C.c_int32), ("stream", C.c_void_p),
                 ("rerank_mode", C.c_int32), ("rerank_storage", C.c_int32),
-                ("probe_mode", C.c_int32), ("scan_guess", C.c_int32)]
+                ("probe_mode", C.c_int32), ("scan_guess", C.c_int32), ("dense_head", C.c_int32)]
 
 
 PROBES = {"scan": 0, "table": 1, "single": 2}
@@ -67,7 +67,7 @@ class QueryStats(C.Structure):
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
                 ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64),
-                ("collect_fallbacks", C.c_int64)]
+                ("collect_fallbacks", C.c_int64), ("dense_head_items", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -385,13 +385,15 @@ def nrlsh_build(items, m: int, L: int, seed: int, *, eps: float = 0.0, stream=No
 
 def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stream=None,
                 rerank: str = "auto", rerank_storage: str = "fp32", probe: str = "scan",
-                scan_guess: int = 0):
+                scan_guess: int = 0, dense_head: int = 0):
     """Multi-probe query with exact re-rank.  Returns (ids int64, ips float32),
     numpy for host queries, torch tensors for CUDA torch queries.  ``rerank``
     selects the re-rank mode ("auto", "gather", "screen", ...), ``probe`` how
     the probed items are found ("scan" or "table"), ``scan_guess`` how the scan
     finds them (0 default, -1 two passes only, g > 0 the collecting scan with a
-    guess of g/16 T items); all give the same result."""
+    guess of g/16 T items), ``dense_head`` which sub-datasets the bfloat16
+    re-rank screens whole (0 default, -1 none, g > 0 those expected to have at
+    least g/256 of their items probed); all give the same result."""
     mode = RERANK_MODES[rerank]
     rst = STORAGES[rerank_storage]
     prb = PROBES[probe]
@@ -404,7 +406,8 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
             ips = torch.empty((nq, k), dtype=torch.float32, device=Q.device)
         else:
             ids, ips = out
-        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst, prb, int(scan_guess))
+        opts = QueryOpts(C.sizeof(QueryOpts), 1, stream or _torch_stream(Q), mode, rst, prb, int(scan_guess),
+                         int(dense_head))
         _check(lib().nrlsh_query_ex(ix.handle, P(Q.data_ptr()), nq, k, int(probe_budget),
                                     C.byref(opts), P(ids.data_ptr()), P(ips.data_ptr())))
         return ids, ips
@@ -412,8 +415,8 @@ def nrlsh_query(ix: Index, queries, k: int, probe_budget: int, *, out=None, stre
     nq = Q.shape[0]
     ids = np.empty((nq, k), dtype=np.int64)
     ips = np.empty((nq, k), dtype=np.float32)
-    if mode or rst or prb or scan_guess or stream is not None:
-        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst, prb, int(scan_guess))
+    if mode or rst or prb or scan_guess or dense_head or stream is not None:
+        opts = QueryOpts(C.sizeof(QueryOpts), 0, stream, mode, rst, prb, int(scan_guess), int(dense_head))
         _check(lib().nrlsh_query_ex(ix.handle, Q.ctypes.data, nq, k, int(probe_budget),
                                     C.byref(opts), ids.ctypes.data, ips.ctypes.data))
     else:
@@ -570,7 +573,8 @@ def nrlsh_get_query_stats() -> dict:
             "lp_fallbacks": st.lp_fallbacks, "probe": {1: "table"}.get(st.probe_mode, "scan"),
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
             "table_passes": st.table_passes, "screen_pairs": st.screen_pairs,
-            "scan_pairs": st.scan_pairs, "collect_fallbacks": st.collect_fallbacks}
+            "scan_pairs": st.scan_pairs, "collect_fallbacks": st.collect_fallbacks,
+            "dense_head_items": st.dense_head_items}
 
 
 def nrlsh_profile_enable(on: bool = True):

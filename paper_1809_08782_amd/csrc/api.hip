@@ -32,6 +32,9 @@ thread_local nrlsh_query_stats g_qstats;
 // scan_guess of the calling nrlsh_query_ex (0 outside it): how the scan probe
 // finds the probed sets (nrlsh_query_opts)
 thread_local int32_t g_scan_guess = 0;
+// dense_head of the calling nrlsh_query_ex (0 outside it): which sub-datasets
+// the bfloat16 re-rank screens whole instead of gathering their probed rows
+thread_local int32_t g_dense_head = 0;
 
 struct ProfEntry {
     double ms = 0.0;
@@ -955,6 +958,51 @@ void run_scan_hist_staged(const nrlsh_index *ix, const QueryShape &sh, const uin
     }
 }
 
+bool screen_fits(const nrlsh_index *ix, int kind);
+
+// Sub-datasets that the bfloat16 re-rank screens whole (64-query tiles
+// against all their items on the matrix cores, the screen path's two passes)
+// instead of gathering the rows of their probed items: the contiguous range
+// [jh0, jh1) around the sub-dataset with the largest probed fraction frac_j,
+// extended while frac_j >= frac ({0, 0}: none).  frac_j is estimated from
+// the sample pass (hits[j] sampled items of j rank before the batch's guessed
+// cuts, one item in `stride` sampled).  Only the speed depends on the choice:
+// the screen applies the same probe predicate, so both forms re-rank exactly
+// the probed set.
+std::pair<int, int> dense_head_range(const nrlsh_index *ix, const unsigned long long *hits, int64_t nb, int stride,
+                                     double frac)
+{
+    const int m = ix->m;
+    std::vector<double> f((size_t)m, 0.0);
+    int jb = 0;
+    for (int j = 0; j < m; ++j) {
+        const double nj = (double)(ix->off_h[(size_t)j + 1] - ix->off_h[(size_t)j]);
+        f[(size_t)j] = nj > 0.0 ? (double)hits[j] * stride / ((double)nb * nj) : 0.0;
+        if (f[(size_t)j] > f[(size_t)jb]) jb = j;
+    }
+    if (!(f[(size_t)jb] >= frac)) return {0, 0};
+    int j0 = jb, j1 = jb + 1;
+    while (j0 > 0 && f[(size_t)j0 - 1] >= frac) --j0;
+    while (j1 < m && f[(size_t)j1] >= frac) ++j1;
+    return {j0, j1};
+}
+
+// (sub-dataset, first, end) triples of at most `items` stored items covering
+// the sub-datasets js (with stride > 1: every stride-th such piece).
+std::vector<int32_t> subset_chunks(const nrlsh_index *ix, int items, const std::vector<int> &js, int stride = 1)
+{
+    std::vector<int32_t> ch;
+    int64_t c = 0;
+    for (const int j : js)
+        for (int64_t p = ix->off_h[(size_t)j]; p < ix->off_h[(size_t)j + 1]; p += items) {
+            if (c++ % stride != 0) continue;
+            ch.push_back(j);
+            ch.push_back((int32_t)p);
+            ch.push_back((int32_t)std::min<int64_t>(p + items, ix->off_h[(size_t)j + 1]));
+        }
+    return ch;
+}
+
 // Gather path: materialise each query's probed list, then re-rank it.  When
 // cand_out_d is given, the probed stored positions are copied there (nq x Tq)
 // and the re-rank is skipped.  With `table` the probed lists come from the
@@ -985,7 +1033,19 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
     const int nsplit = rerank_splits(B, sh.Tq);
-    const int64_t lcap = std::min<int64_t>(sh.Tq, 4096);
+    // dense head of the bfloat16 re-rank (collecting scan only; not when the
+    // probed lists themselves are the output): dense_head -1 = none, 0 = the
+    // sub-datasets with at least 3/128 of their items probed, g = at least
+    // g / 256; chosen on the call's first batch
+    const int32_t dh = g_dense_head;
+    const bool head_ok = collect && bf16_rows && !cand_out_d && dh >= 0 && screen_fits(ix, SCREEN_BF16);
+    const double head_frac = (dh > 0 ? dh : 6) / 256.0;
+    bool head_decided = false, head_any = false;
+    std::pair<int, int> hr{0, 0};
+    int nhcells = 0, nhchunks = 0;
+    Block hblk;
+    // the screen's kept pairs join the gather's in the exact re-rank's lists
+    const int64_t lcap = std::min<int64_t>(sh.Tq, head_ok ? 8192 : 4096);
     const int lsplit = rerank_splits(B, lcap);
     const int64_t nbatches = (nq + B - 1) / B;
     // both scan passes walk the chunks of the staged pass 1; the sample pass
@@ -1023,12 +1083,14 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_kc = blk.reserve<int32_t>(collect ? (size_t)B : 1),
                  o_rh = blk.reserve<int32_t>(collect ? (size_t)B : 1),
                  o_tg = blk.reserve<int32_t>(collect ? (size_t)tiles * 4 * 64 : 1),
-                 o_fl = blk.reserve<uint32_t>(collect ? (size_t)nbatches : 1);
+                 o_fl = blk.reserve<uint32_t>(collect ? (size_t)nbatches : 1),
+                 o_sh = blk.reserve<unsigned long long>(head_ok ? (size_t)sh.m : 1);
     blk.allocate(s);
     DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
     DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
     DBuf<uint32_t> gfail = blk.view<uint32_t>(o_fl);
     if (collect) HIPX(launch_fill32(gfail.get(), nbatches, 0u, s));
+    DBuf<unsigned long long> subhits = blk.view<unsigned long long>(o_sh);
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
                   gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
@@ -1054,7 +1116,55 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     bool lp_on = bf16_rows;
     const uint64_t ovf = ix->lp_overflow.load(std::memory_order_relaxed);
     if (ovf != 0 && (uint64_t)k >= (ovf >> 32) && (uint64_t)sh.Tq >= (ovf & 0xFFFFFFFFull)) lp_on = false;
-    auto run_batch = [&](int64_t b0, int64_t bi, bool staged) {
+    DBuf<uint16_t> hqh;
+    DBuf<float> hqn, htheta, hcmax;
+    DBuf<int32_t> hcells, hchunks;
+    // Chooses the head from the sample pass of the batch just guessed (one
+    // host round trip per call) and sets up its buffers.
+    auto decide_head = [&](int64_t nb) {
+        head_decided = true;
+        HIPX(launch_sub_hits(ghist.get(), ix->R.get(), grho.get(), nb, sh.m, sh.L, subhits.get(), s));
+        size_t pb = 0;
+        auto *hits = static_cast<unsigned long long *>(pinned_take((size_t)sh.m * sizeof(unsigned long long), &pb));
+        HIPX(hipMemcpyAsync(hits, subhits.get(), (size_t)sh.m * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                            s));
+        HIPX(hipStreamSynchronize(s));
+        hr = dense_head_range(ix, hits, nb, gstride, head_frac);
+        pinned_give(hits, pb, s, ix->device);
+        head_any = hr.second > hr.first;
+        if (!head_any) return;
+        // theta_q comes from the head's items as a whole: a sub-dataset
+        // normalised by an outlying U_j hashes almost all of its items alike,
+        // so that a query probes nearly all of them or nearly none, and no
+        // single sub-dataset holds k probed items for every query.  Every
+        // head_witness_stride-th cell is a witness.  (The screen path's norm
+        // bound skips nothing here: theta_q stays far below ||q|| U_j.)
+        std::vector<int> hjs;
+        for (int j = hr.second - 1; j >= hr.first; --j) hjs.push_back(j);
+        const int head_witness_stride = 4;
+        const std::vector<int32_t> hce = subset_chunks(ix, screen_cell_items(), hjs, head_witness_stride);
+        const std::vector<int32_t> hch = subset_chunks(ix, screen_chunk_items(), hjs);
+        nhcells = (int)(hce.size() / 3);
+        nhchunks = (int)(hch.size() / 3);
+        const size_t o_hq = hblk.reserve<uint16_t>((size_t)B * sh.dp), o_hn = hblk.reserve<float>((size_t)B),
+                     o_ht = hblk.reserve<float>((size_t)B),
+                     o_hm = hblk.reserve<float>((size_t)B * nhcells * screen_cell_groups()),
+                     o_hc = hblk.reserve<int32_t>(hce.size()), o_hk = hblk.reserve<int32_t>(hch.size());
+        hblk.allocate(s);
+        hqh = hblk.view<uint16_t>(o_hq);
+        hqn = hblk.view<float>(o_hn);
+        htheta = hblk.view<float>(o_ht);
+        hcmax = hblk.view<float>(o_hm);
+        hcells = hblk.view<int32_t>(o_hc);
+        hchunks = hblk.view<int32_t>(o_hk);
+        HIPX(hipMemcpyAsync(hcells.get(), hce.data(), hce.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        HIPX(hipMemcpyAsync(hchunks.get(), hch.data(), hch.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    };
+    // one batch; returns false when it has to run again without the dense
+    // head (its lists overflowed)
+    auto run_batch = [&](int64_t b0, int64_t bi, bool staged, bool head) -> bool {
+        bool hd = head && head_ok && !staged && lp_on;
+        int jh0 = 0, jh1 = 0;
         const int64_t nb = std::min<int64_t>(B, nq - b0);
         const float *Qb = Qd + b0 * sh.d;
         uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.qsets * sh.W : qcodes.get();
@@ -1092,23 +1202,31 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                   gtie_g.get(), s, false));
             HIPX(launch_rho_from_tie(gtie_g.get(), nb, P, grho.get(), s));
             tm.end();
+            if (hd && !head_decided) decide_head(nb);
+            hd = hd && head_any;
+            if (hd) {
+                jh0 = hr.first;
+                jh1 = hr.second;
+            }
             HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
             HIPX(launch_fill32(kcount.get(), nb, 0u, s));
             tm.begin("scan_collect");
             HIPX(launch_scan_collect(ix->codes_l.get(), qc, nb, sh, schunks.get(), nstage_chunks, ix->R.get(),
-                                     grho.get(), kcap, kcount.get(), keys.get(), ghist.get(), scan_pairs_d, s));
+                                     grho.get(), kcap, kcount.get(), keys.get(), ghist.get(), scan_pairs_d, s,
+                                     jh0, jh1));
             tm.end();
+            // (the dense head's screen reads every sub-dataset's level bound)
             tm.begin("threshold");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(), ghthr.get(),
-                                  gtie.get(), s, false));
+                                  gtie.get(), s, hd));
             tm.end();
             tm.begin("tie_locate");
             HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
                                    gpstar.get(), s));
             tm.end();
             tm.begin("filter");
-            HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), sh.Tq, cb,
-                                       ccount.get(), gfail.get() + bi, s));
+            HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), grho.get(),
+                                       sh.Tq, cb, ccount.get(), gfail.get() + bi, s));
             tm.end();
         } else if (!table) {
             tm.begin("scan_hist");
@@ -1129,13 +1247,35 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                         ghthr.get(), gtie.get(), gpstar.get(), ccount.get(), cb, s));
             tm.end();
         }
-        if (cand_out_d) return;
+        if (cand_out_d) return true;
         if (lp_on) {
             HIPX(hipMemsetAsync(lcount.get(), 0, (size_t)nb * sizeof(int32_t), s));
-            HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
+            if (hd) {
+                // the head sub-datasets: theta_q from the largest lower bounds of
+                // their 32-item groups, then every probed pair of them that may
+                // reach it into the lists; theta_q seeds the gather below, which
+                // takes the other sub-datasets' probed items (the filter left the
+                // head's out)
+                ScreenQueries sq{Qb, hqh.get(), nullptr, hqn.get(), nullptr, nullptr};
+                tm.begin("head_theta");
+                HIPX(launch_query_bf16(Qb, nb, sh.d, sh.dp, hqh.get(), nullptr, hqn.get(), s, nonfinite_d));
+                HIPX(launch_screen_max(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq,
+                                       nb, sh, hcells.get(), nhcells, nhcells, qc, ghthr.get(), gtie.get(),
+                                       gpstar.get(), hcmax.get(), htheta.get(), s));
+                tm.end();
+                tm.begin("head_screen");
+                HIPX(launch_screen(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq, nb,
+                                   sh, hchunks.get(), nhchunks, qc, ghthr.get(), gtie.get(), gpstar.get(),
+                                   htheta.get(), (int)lcap, lcount.get(), lists.get(), s));
+                tm.end();
+                HIPX(launch_theta_seed(htheta.get(), nb, gtheta.get(), s));
+            } else {
+                HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
+            }
             tm.begin("rerank_lp");
             HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), ix->perm.get(), Qb, nb, sh, cb,
-                                  nsplit, (int)lcap, lcount.get(), lists.get(), gtheta.get(), s));
+                                  hd ? ccount.get() : nullptr, nsplit, (int)lcap, lcount.get(), lists.get(),
+                                  gtheta.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
@@ -1156,11 +1296,14 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                    lcount.get(), ns, lpart_v.get(), lpart_i.get(), ids_d + b0 * k,
                                    ips_d + b0 * k, s));
                 tm.end();
-                return;
+                if (hd) g_qstats.dense_head_items = ix->off_h[(size_t)jh1] - ix->off_h[(size_t)jh0];
+                return true;
             }
             g_qstats.lp_fallbacks += 1;  // a list overflowed: re-rank this batch from FP32 rows
             lp_on = false;
             ix->lp_overflow.store(((uint64_t)k << 32) | (uint64_t)sh.Tq, std::memory_order_relaxed);
+            // without the head's items in the probed lists the batch runs again
+            if (hd) return false;
         }
         if (nsplit > 1) HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
         tm.begin("rerank");
@@ -1168,8 +1311,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                            part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s,
                            gtheta.get()));
         tm.end();
+        return true;
     };
-    for (int64_t b0 = 0, bi = 0; b0 < nq; b0 += B, ++bi) run_batch(b0, bi, false);
+    for (int64_t b0 = 0, bi = 0; b0 < nq; b0 += B, ++bi)
+        if (!run_batch(b0, bi, false, true)) run_batch(b0, bi, false, false);
     if (collect) {
         // batches whose collection was incomplete are probed again with the two passes
         std::vector<uint32_t> fl((size_t)nbatches);
@@ -1178,7 +1323,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         for (int64_t bi = 0; bi < nbatches; ++bi)
             if (fl[(size_t)bi]) {
                 g_qstats.collect_fallbacks += 1;
-                run_batch(bi * B, bi, true);
+                run_batch(bi * B, bi, true, false);
             }
     }
     if (table) {
@@ -1792,12 +1937,26 @@ nrlsh_status nrlsh_query_ex(const nrlsh_index *ix, const float *queries, int64_t
             return fail(NRLSH_E_INVALID_ARG, "scan_guess %d out of [-1, 4096]", opts->scan_guess);
         sguess = opts->scan_guess;
     }
+    int32_t dhead = 0;
+    if (opts && opts->struct_size >= (int32_t)(offsetof(nrlsh_query_opts, dense_head) + sizeof(int32_t))) {
+        if (opts->dense_head < -1 || opts->dense_head > 256)
+            return fail(NRLSH_E_INVALID_ARG, "dense_head %d out of [-1, 256]", opts->dense_head);
+        dhead = opts->dense_head;
+    }
     if (nq == 0) return st;
     const bool on_device = opts && opts->device_ptrs;
-    struct GuessScope {  // the option lasts for this call only
-        explicit GuessScope(int32_t g) { g_scan_guess = g; }
-        ~GuessScope() { g_scan_guess = 0; }
-    } guess_scope(sguess);
+    struct OptScope {  // the options last for this call only
+        OptScope(int32_t g, int32_t h)
+        {
+            g_scan_guess = g;
+            g_dense_head = h;
+        }
+        ~OptScope()
+        {
+            g_scan_guess = 0;
+            g_dense_head = 0;
+        }
+    } opt_scope(sguess, dhead);
     return guarded([&]() -> nrlsh_status {
         HIPX(hipSetDevice(ix->device));
         hipStream_t s = pick_stream(opts ? opts->stream : nullptr, ix->device);

@@ -751,139 +751,10 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_emit_s(const uint32_t *_
 // threshold pass over ghist plus a filter of the keys give exactly its
 // probed set; otherwise (or past `cap` keys) the caller probes it again
 // with the two passes.  Blocks: (64-query tile, chunk) as in k_scan_emit_s.
-constexpr int CL_SB = 32;  // staged positions per lane of the collecting scan
-
-// Every lane empties its staged positions (cnt of them) into its query's
-// keys: one reservation per lane, then batches of 8 whose code loads are
-// issued together.  Called by the whole wave, so that no lane waits alone.
-template <int W, typename S = int32_t>
-__device__ __forceinline__ void collect_flush(const S *__restrict__ stage, int lane, int cnt,
-                                              const uint32_t *__restrict__ codes_l, uint32_t q0, uint32_t q1,
-                                              int L, const int32_t *__restrict__ Rrow, uint32_t *hist,
-                                              int32_t *__restrict__ counts, uint64_t *__restrict__ keys,
-                                              int64_t q, int64_t cap, int col = -1, int64_t pbase = 0)
-{
-    if (col < 0) col = lane;
-    int64_t base = 0;
-    if (cnt > 0) base = atomicAdd(&counts[q], cnt);
-    int top = cnt;
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
-    for (int i0 = 0; i0 < top; i0 += 8) {
-        int32_t pp[8];
-        uint32_t a[8], b[8];
-#pragma unroll
-        for (int v = 0; v < 8; ++v) pp[v] = i0 + v < cnt ? (int32_t)(pbase + stage[(i0 + v) * 64 + lane]) : -1;
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            a[v] = pp[v] >= 0 ? codes_l[(int64_t)pp[v] * W] : 0u;
-            b[v] = (W == 2 && pp[v] >= 0) ? codes_l[(int64_t)pp[v] * W + 1] : 0u;
-        }
-#pragma unroll
-        for (int v = 0; v < 8; ++v) {
-            if (pp[v] < 0) continue;
-            int h = __popc(a[v] ^ q0);
-            if (W == 2) h += __popc(b[v] ^ q1);
-            __hip_atomic_fetch_add(&hist[h * 64 + col], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (base + i0 + v < cap)
-                keys[q * cap + base + i0 + v] = ((uint64_t)(uint32_t)Rrow[L - h] << 32) | (uint32_t)pp[v];
-        }
-    }
-}
-
-template <int W>
-__global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect(const uint32_t *__restrict__ codes_l,
-                                                                const uint32_t *__restrict__ qcodes,
-                                                                int64_t nq, int m, int L, int qsets,
-                                                                const int32_t *__restrict__ chunks,
-                                                                const int32_t *__restrict__ R,
-                                                                const int32_t *__restrict__ grho,
-                                                                int64_t cap, int32_t *__restrict__ counts,
-                                                                uint64_t *__restrict__ keys,
-                                                                uint32_t *__restrict__ ghist,
-                                                                unsigned long long *__restrict__ npairs)
-{
-    extern __shared__ uint32_t lds[];  // hist (L+1) x 64 | stage SH_WAVES x CL_SB x 64 | R row (L+1)
-    uint32_t *hist = lds;
-    int32_t *stage = reinterpret_cast<int32_t *>(lds + (L + 1) * 64);
-    int32_t *Rrow = stage + SH_WAVES * CL_SB * 64;
-    const int tid = threadIdx.x, wave = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
-    const int64_t tile = blockIdx.x;
-    const int j = chunks[3 * blockIdx.y];
-    const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
-    const int64_t q = tile * 64 + lane;
-    const bool valid = q < nq;
-    for (int e = tid; e <= L; e += SH_WAVES * 64) Rrow[e] = R[(int64_t)j * (L + 1) + e];
-    __syncthreads();
-    int hcut = -1;
-    uint32_t q0 = 0, q1 = 0;
-    if (valid) {
-        const int32_t rho = grho[q];
-        int lo = 0, hi = L + 1;  // #{h : rank(j, h) < rho}
-        while (lo < hi) {
-            const int mid = (lo + hi) >> 1;
-            if (Rrow[L - mid] < rho) lo = mid + 1;
-            else hi = mid;
-        }
-        hcut = lo - 1;
-        const int64_t r = qrow(q, j, qsets);
-        q0 = qcodes[r * W];
-        if (W == 2) q1 = qcodes[r * W + 1];
-    }
-    if (__ballot(hcut >= 0) == 0ull) return;  // the same for every wave of the block
-    if (npairs && tid == 0)
-        atomicAdd(npairs, (unsigned long long)(min((int64_t)64, nq - tile * 64) * (p1 - p0)));
-    for (int e = tid; e < (L + 1) * 64; e += SH_WAVES * 64) hist[e] = 0u;
-    __syncthreads();
-    int32_t *st = stage + wave * CL_SB * 64;
-    int cnt = 0;
-    const uint32_t negt = (uint32_t)(-(hcut + 1));  // h <= hcut  <=>  h - (hcut + 1) < 0
-    const int64_t ng = (p1 - p0) >> 4;
-    uint32_t c[16 * W], cn[16 * W];
-    if (wave < ng) load_group16<W>(codes_l, p0 + (int64_t)wave * 16, c);
-    __builtin_amdgcn_s_waitcnt(0xC07F);
-    for (int64_t g = wave; g < ng; g += SH_WAVES) {
-        const int64_t p = p0 + g * 16;
-        if (g + SH_WAVES < ng) load_group16<W>(codes_l, p + SH_WAVES * 16, cn);
-        uint32_t mask = 0;
-#pragma unroll
-        for (int u = 0; u < 16; ++u) {
-            uint32_t hd = (uint32_t)__popc(c[u * W] ^ q0) + negt;
-            if (W == 2) hd += (uint32_t)__popc(c[u * W + 1] ^ q1);
-            mask |= (hd >> 31) << u;
-        }
-        // at most 16 more per group: room is left while every lane holds < 16
-        while (mask != 0u) {
-            const int u = __builtin_ctz(mask);
-            mask &= mask - 1u;
-            st[cnt * 64 + lane] = (int32_t)(p + u);
-            ++cnt;
-        }
-        if (__ballot(cnt >= CL_SB - 16) != 0ull) {
-            collect_flush<W>(st, lane, cnt, codes_l, q0, q1, L, Rrow, hist, counts, keys, q, cap);
-            cnt = 0;
-        }
-#pragma unroll
-        for (int u = 0; u < 16 * W; ++u) c[u] = cn[u];
-    }
-    if (wave == SH_WAVES - 1) {
-        for (int64_t p = p0 + ng * 16; p < p1; ++p) {  // fewer than 16 items
-            int h = __popc(codes_l[p * W] ^ q0);
-            if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
-            if (h <= hcut) st[(cnt++) * 64 + lane] = (int32_t)p;
-        }
-    }
-    if (__ballot(cnt > 0) != 0ull)
-        collect_flush<W>(st, lane, cnt, codes_l, q0, q1, L, Rrow, hist, counts, keys, q, cap);
-    __syncthreads();
-    uint32_t *out = ghist + ((tile * m + j) * (int64_t)(L + 1)) * 64;
-    for (int e = tid; e < (L + 1) * 64; e += SH_WAVES * 64) {
-        const uint32_t v = hist[e];
-        if (v) atomicAdd(&out[e], v);
-    }
-}
-
-// Matrix-core form of the collecting scan.  With a_k in {0, 1} the bits of
+// The sub-datasets j in [jh0, jh1) -- those the re-rank screens whole on the
+// matrix cores -- are only counted: their hits enter the histogram (the
+// threshold needs them) but not the keys.
+// The scan runs on the matrix cores.  With a_k in {0, 1} the bits of
 // an item's code and t_k = 1 - 2 q_k the query's bits as +-1, the integer dot
 // product sum_k a_k t_k = popc(c) - 2 popc(c & q) = h - popc(q), so one
 // v_mfma_i32_32x32x32_i8 per 32 code bits gives the Hamming distances of 32
@@ -953,7 +824,8 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
                                                                    int64_t cap, int32_t *__restrict__ counts,
                                                                    uint64_t *__restrict__ keys,
                                                                    uint32_t *__restrict__ ghist,
-                                                                   unsigned long long *__restrict__ npairs)
+                                                                   unsigned long long *__restrict__ npairs,
+                                                                   int jh0, int jh1)
 {
     // hist (L+1) x 32 words (queries 2 w, 2 w + 1 in the low / high halves) |
     // staged offsets SH_WAVES x 2 x MX_SB x 64 (u16) | staged levels (u8) | R row
@@ -966,6 +838,7 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
     const int64_t tile = blockIdx.x;
     const int j = chunks[3 * blockIdx.y];
     const int64_t p0 = chunks[3 * blockIdx.y + 1], p1 = chunks[3 * blockIdx.y + 2];
+    const bool count_only = j >= jh0 && j < jh1;
     for (int e = tid; e <= L; e += SH_WAVES * 64) Rrow[e] = R[(int64_t)j * (L + 1) + e];
     __syncthreads();
     // per query of the tile (lane = query): its cut level and code
@@ -1054,6 +927,18 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
 #pragma unroll
             for (int r = 15; r >= 0; --r) mask = __builtin_amdgcn_alignbit(mask, (uint32_t)acc[r], 31);
             mask &= vmask;
+            if (count_only) {
+                // level h = acc + hcut + 1 of each hit counted straight into
+                // the histogram word of (h, query 32 c + col0)
+                const uint32_t inc = 1u << (16 * (col0 & 1));
+                const int hw = (hcut[c] + 1) * 32 + 16 * c + (col0 >> 1);
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    if ((mask >> r) & 1u)
+                        __hip_atomic_fetch_add(&hist[acc[r] * 32 + hw], inc, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                continue;
+            }
             // low bytes of the accumulators, four to a word (byte r & 3 of word r >> 2)
             uint32_t pk[4];
 #pragma unroll
@@ -1107,12 +992,16 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
 // rank = b* and stored position <= P* (k_threshold, k_tie_locate).  One
 // block per query; the list order is that of arrival (the re-rank's tie rule
 // makes the top-k independent of it).  lcount[q] receives the list length
-// (Tq when the query's collection was complete); `fail` (one word per call
-// batch) is set when a query collected fewer than Tq keys or more than cap.
+// (Tq when the query's collection was complete and no sub-dataset was only
+// counted); `fail` (one word per call batch) is set when a query's threshold
+// bucket does not rank before its guessed cut rho (the items ranked before
+// rho number fewer than Tq: the histogram of the collected items then never
+// reaches the budget) or it collected more keys than cap.
 __global__ __launch_bounds__(256) void k_collect_filter(const uint64_t *__restrict__ keys,
                                                         const int32_t *__restrict__ counts, int64_t cap,
                                                         const int32_t *__restrict__ gtie,
-                                                        const int32_t *__restrict__ gpstar, int64_t Tq,
+                                                        const int32_t *__restrict__ gpstar,
+                                                        const int32_t *__restrict__ grho, int64_t Tq,
                                                         int32_t *__restrict__ cand,
                                                         int32_t *__restrict__ lcount,
                                                         uint32_t *__restrict__ fail)
@@ -1127,7 +1016,7 @@ __global__ __launch_bounds__(256) void k_collect_filter(const uint64_t *__restri
     const int64_t E = min(C, cap);
     if (tid == 0) {
         total = 0;
-        if (C < Tq || C > cap) atomicOr(fail, 1u);
+        if ((int64_t)bstar >= (int64_t)grho[q] || C > cap) atomicOr(fail, 1u);
     }
     __syncthreads();
     const uint64_t *kq = keys + q * cap;
@@ -1188,9 +1077,11 @@ __global__ __launch_bounds__(64) void k_rerank(const float *__restrict__ Xl,
     const int split = blockIdx.y;
     const float *qv = Q + q * d;
     const int32_t *cq = cand + q * Tq;
+    // lists with their own lengths are cut into nsplit equal slices each
     const int64_t len = counts ? min((int64_t)counts[q], Tq) : Tq;
-    const int64_t cbeg = (int64_t)split * slice;
-    const int64_t cend = min(len, cbeg + slice);
+    const int64_t sl = counts ? ((len + nsplit - 1) / nsplit + 63) / 64 * 64 : slice;
+    const int64_t cbeg = (int64_t)split * sl;
+    const int64_t cend = min(len, cbeg + sl);
     WaveTopK<S> top;
     top.init(k);
 
@@ -1267,6 +1158,7 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
                                                     const int32_t *__restrict__ perm,
                                                     const float *__restrict__ Q, int64_t n, int d, int dp,
                                                     int64_t Tq, int k, const int32_t *__restrict__ cand,
+                                                    const int32_t *__restrict__ counts,
                                                     int64_t slice, int lcap, int32_t *__restrict__ lcount,
                                                     int32_t *__restrict__ lists,
                                                     unsigned long long *__restrict__ gtheta)
@@ -1277,8 +1169,13 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
     const int split = blockIdx.y;
     const float *qv = Q + q * d;
     const int32_t *cq = cand + q * Tq;
-    const int64_t cbeg = (int64_t)split * slice;
-    const int64_t cend = min(Tq, cbeg + slice);
+    // lists with their own lengths (counts) are cut into gridDim.y equal slices each
+    const int64_t len = counts ? min((int64_t)counts[q], Tq) : Tq;
+    const int64_t ns = gridDim.y;
+    const int64_t qsl = counts ? ((len + ns - 1) / ns + 63) / 64 * 64 : slice;
+    const int64_t cbeg = (int64_t)split * qsl;
+    const int64_t cend = min(len, cbeg + qsl);
+    if (cbeg >= cend) return;
     double qn = 0.0;  // ||q|| (exact squares, FP64 sum, rounded up)
     const int dq = (dp + 127) / 128 * 128;
     for (int t = lane; t < dq; t += 64) {
@@ -1295,6 +1192,10 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
     const int grp = lane >> 4, sl = lane & 15;
     int32_t pn = (cbeg + lane < cend) ? cq[cbeg + lane] : -1;
     for (int64_t c0 = cbeg; c0 < cend; c0 += 64) {
+        // the largest k-th lower bound published for the query so far (by
+        // another slice, or the seed of a dense screen): values below it can
+        // neither raise it nor enter the top-k that matters
+        const unsigned long long ge = __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         int32_t p = pn;
         pn = (c0 + 64 + lane < cend) ? cq[c0 + 64 + lane] : -1;
         bool valid = c0 + lane < cend;
@@ -1337,11 +1238,10 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
         // row c sits in lane 16 (c & 3) + (c >> 2)
         const double acc = (double)__shfl(part[0], 16 * (lane & 3) + (lane >> 2), 64);
         const double e = qn * (double)(valid ? xeb[p] : 0.f) * (1.0 + 0x1p-20);
-        top.offer(acc - e, id, valid, lane);
-        double th = top.th_v;
-        if (th > -INFINITY && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(th));
-        const unsigned long long ge = __hip_atomic_load(&gtheta[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (ge != 0ull) th = fmax(th, order_value(ge));
+        const double floor = ge != 0ull ? order_value(ge) : -INFINITY;
+        top.offer(acc - e, id, valid, lane, floor);
+        if (top.th_v > floor && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(top.th_v));
+        const double th = fmax(top.th_v, floor);
         const bool keep = valid && !(acc + e < th);
         const uint64_t kb = __ballot(keep);
         if (kb != 0ull) {
@@ -2402,39 +2302,29 @@ hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcode
 hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
                                const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
                                int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
-                               unsigned long long *npairs, hipStream_t s, bool mfma)
+                               unsigned long long *npairs, hipStream_t s, int jh0, int jh1)
 {
     if (nq < 1 || nchunks < 1) return hipSuccess;
     const dim3 grid(ceil_div(nq, 64), (unsigned)nchunks);
-    if (mfma) {
-        const size_t lds = (size_t)(sh.L + 1) * 32 * sizeof(uint32_t) +
-                           (size_t)SH_WAVES * 2 * MX_SB * 64 * (sizeof(uint16_t) + sizeof(uint8_t)) +
-                           (size_t)(sh.L + 1) * sizeof(int32_t);
-        if (sh.W == 1)
-            hipLaunchKernelGGL(k_scan_collect_mx<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
-                               sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
-        else
-            hipLaunchKernelGGL(k_scan_collect_mx<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
-                               sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
-        return hipGetLastError();
-    }
-    const size_t lds = ((size_t)(sh.L + 1) * 64 + (size_t)SH_WAVES * CL_SB * 64 + (sh.L + 1)) * sizeof(uint32_t);
+    const size_t lds = (size_t)(sh.L + 1) * 32 * sizeof(uint32_t) +
+                       (size_t)SH_WAVES * 2 * MX_SB * 64 * (sizeof(uint16_t) + sizeof(uint8_t)) +
+                       (size_t)(sh.L + 1) * sizeof(int32_t);
     if (sh.W == 1)
-        hipLaunchKernelGGL(k_scan_collect<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m, sh.L,
-                           sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+        hipLaunchKernelGGL(k_scan_collect_mx<1>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
+                           sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs, jh0, jh1);
     else
-        hipLaunchKernelGGL(k_scan_collect<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m, sh.L,
-                           sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs);
+        hipLaunchKernelGGL(k_scan_collect_mx<2>, grid, dim3(SH_WAVES * 64), lds, s, codes_l, qcodes, nq, sh.m,
+                           sh.L, sh.qsets, chunks, R, grho, cap, counts, keys, ghist, npairs, jh0, jh1);
     return hipGetLastError();
 }
 
 hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, int64_t cap, int64_t nq,
-                                 const int32_t *gtie, const int32_t *gpstar, int64_t Tq, int32_t *cand,
-                                 int32_t *lcount, uint32_t *fail, hipStream_t s)
+                                 const int32_t *gtie, const int32_t *gpstar, const int32_t *grho, int64_t Tq,
+                                 int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s)
 {
     if (nq < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_collect_filter, dim3((unsigned)nq), dim3(256), 0, s, keys, counts, cap, gtie, gpstar, Tq,
-                       cand, lcount, fail);
+    hipLaunchKernelGGL(k_collect_filter, dim3((unsigned)nq), dim3(256), 0, s, keys, counts, cap, gtie, gpstar, grho,
+                       Tq, cand, lcount, fail);
     return hipGetLastError();
 }
 
@@ -2446,6 +2336,39 @@ __global__ __launch_bounds__(64) void k_rho_from_tie(const int32_t *__restrict__
     if (q >= nq) return;
     const int32_t b = gtie[(q >> 6) * 4 * 64 + 3 * 64 + (q & 63)];
     rho[q] = b < 0 || b >= P ? P : b + 1;
+}
+
+// Per sub-dataset j: the sampled items (histogram of the sample pass) that
+// rank before each query's guessed cut rho, summed over the batch -- the
+// batch's probed items of j in sample units.  Ranks grow with h inside a
+// sub-dataset, so each query's walk stops at its first bucket not before rho.
+// One block per sub-dataset.
+__global__ __launch_bounds__(256) void k_sub_hits(const uint32_t *__restrict__ ghist, const int32_t *__restrict__ R,
+                                                  const int32_t *__restrict__ grho, int64_t nq, int m, int L,
+                                                  unsigned long long *__restrict__ out)
+{
+    __shared__ unsigned long long part[4];
+    const int j = blockIdx.x, tid = threadIdx.x, L1 = L + 1;
+    const int32_t *Rj = R + (int64_t)j * L1;
+    unsigned long long acc = 0;
+    for (int64_t q = tid; q < nq; q += 256) {
+        const int32_t rho = grho[q];
+        const uint32_t *H = ghist + (((q >> 6) * m + j) * (int64_t)L1) * 64 + (q & 63);
+        for (int h = 0; h <= L && Rj[L - h] < rho; ++h) acc += H[(int64_t)h * 64];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((tid & 63) == 0) part[tid >> 6] = acc;
+    __syncthreads();
+    if (tid == 0) out[j] = part[0] + part[1] + part[2] + part[3];
+}
+
+hipError_t launch_sub_hits(const uint32_t *ghist, const int32_t *R, const int32_t *grho, int64_t nq, int m, int L,
+                           unsigned long long *out, hipStream_t s)
+{
+    if (m < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_sub_hits, dim3((unsigned)m), dim3(256), 0, s, ghist, R, grho, nq, m, L, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s)
@@ -2765,9 +2688,27 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
     return hipGetLastError();
 }
 
+// The screen's theta (k distinct probed items reach it) as the order key the
+// bfloat16 re-rank shares between slices (0 = none).
+__global__ __launch_bounds__(256) void k_theta_seed(const float *__restrict__ theta, int64_t nq,
+                                                    unsigned long long *__restrict__ gtheta)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    const float t = theta[q];
+    gtheta[q] = t > -INFINITY ? (unsigned long long)order_key((double)t) : 0ull;
+}
+
+hipError_t launch_theta_seed(const float *theta, int64_t nq, unsigned long long *gtheta, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_theta_seed, dim3(ceil_div(nq, 256)), dim3(256), 0, s, theta, nq, gtheta);
+    return hipGetLastError();
+}
+
 hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
-                            int nsplit, int lcap, int32_t *lcount, int32_t *lists,
+                            const int32_t *counts, int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s)
 {
     const int S = (sh.k + 63) / 64;
@@ -2777,7 +2718,7 @@ hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t 
     const size_t lds = (size_t)(sh.dp + 127) / 128 * 128 * sizeof(float);
 #define NRLSH_RERANK_LP(SS)                                                                         \
     hipLaunchKernelGGL((k_rerank_bf16<SS>), grid, block, lds, s, Xh, xeb, perm, Q, sh.n, sh.d, sh.dp, \
-                       sh.Tq, sh.k, cand, slice, lcap, lcount, lists, gtheta)
+                       sh.Tq, sh.k, cand, counts, slice, lcap, lcount, lists, gtheta)
     if (S <= 1) NRLSH_RERANK_LP(1);
     else if (S <= 2) NRLSH_RERANK_LP(2);
     else if (S <= 4) NRLSH_RERANK_LP(4);

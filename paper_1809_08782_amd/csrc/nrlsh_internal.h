@@ -164,13 +164,18 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
                          float *out_ips, hipStream_t s, unsigned long long *gtheta = nullptr);
 
 // Precision form of the re-rank: bounds from the bfloat16 copy Xh, appends to
-// lists (nq x lcap, lcount zeroed by the caller) every probed item that may
-// still belong to the exact top-k.  gtheta: nq words zeroed by the caller,
-// the k-th lower bound shared by the slices of each query.
+// lists (nq x lcap, lcount set by the caller: zero, or the entries already
+// there) every probed item of cand (nq x Tq; counts[q] entries, or Tq when
+// counts is NULL) that may still belong to the exact top-k.  gtheta: nq
+// words set by the caller (0, or the order key of a value that k probed
+// items reach), the k-th lower bound shared by the slices of each query.
 hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
                             const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
-                            int nsplit, int lcap, int32_t *lcount, int32_t *lists,
+                            const int32_t *counts, int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s);
+// gtheta[q] = the order key of theta[q] (0 where theta is -inf): seeds the
+// bfloat16 re-rank with the screen's lower bound of the k-th best.
+hipError_t launch_theta_seed(const float *theta, int64_t nq, unsigned long long *gtheta, hipStream_t s);
 
 // Chunked passes for small query batches: one wave per (64-query tile,
 // sub-dataset, chunk of `chunk` stored items), nch chunks per sub-dataset.
@@ -200,22 +205,28 @@ hipError_t launch_scan_hist_stage(const uint32_t *codes_l, const uint32_t *qcode
                                   const QueryShape &sh, const int32_t *chunks, int nchunks,
                                   const int32_t *need, uint32_t *ghist, unsigned long long *npairs,
                                   hipStream_t s, int gstride = 1);
-// Collecting scan: every item whose bucket ranks before grho[q] is appended
-// to query q's keys (nq x cap, rank << 32 | stored position; counts zeroed by
-// the caller, may exceed cap) and counted in ghist (zeroed by the caller).
-// mfma: the matrix-core form (chunks of at most 2^16 items).
+// Collecting scan (matrix cores, chunks of at most 2^16 items): every item
+// whose bucket ranks before grho[q] is counted in ghist (zeroed by the
+// caller) and, unless its sub-dataset lies in [jh0, jh1), appended to query
+// q's keys (nq x cap, rank << 32 | stored position; counts zeroed by the
+// caller, may exceed cap).
 hipError_t launch_scan_collect(const uint32_t *codes_l, const uint32_t *qcodes, int64_t nq, const QueryShape &sh,
                                const int32_t *chunks, int nchunks, const int32_t *R, const int32_t *grho,
                                int64_t cap, int32_t *counts, uint64_t *keys, uint32_t *ghist,
-                               unsigned long long *npairs, hipStream_t s, bool mfma = true);
+                               unsigned long long *npairs, hipStream_t s, int jh0 = 0, int jh1 = 0);
 // The probed list (nq x Tq) of each query from its collected keys and the
 // threshold (gtie) and tie position (gpstar); lcount[q] = its length; *fail
-// is set when a query's keys were incomplete (fewer than Tq, or over cap).
+// is set when a query's collection was incomplete (its threshold bucket not
+// before the guessed cut grho, or more keys than cap).
 hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, int64_t cap, int64_t nq,
-                                 const int32_t *gtie, const int32_t *gpstar, int64_t Tq, int32_t *cand,
-                                 int32_t *lcount, uint32_t *fail, hipStream_t s);
+                                 const int32_t *gtie, const int32_t *gpstar, const int32_t *grho, int64_t Tq,
+                                 int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s);
 // rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
+// out[j] (m words) = the sample-pass items of sub-dataset j (ghist of a
+// sampled pass) that rank before grho[q], summed over the nq queries.
+hipError_t launch_sub_hits(const uint32_t *ghist, const int32_t *R, const int32_t *grho, int64_t nq, int m, int L,
+                           unsigned long long *out, hipStream_t s);
 // Pass 2 over the same chunks: appends each query's probed items to its list
 // (counts zeroed by the caller; order unspecified), cutting the threshold
 // bucket at gpstar (launch_tie_locate).

@@ -85,3 +85,70 @@ def test_collect_small_budget_and_tied_buckets():
             oids, oips = oix.query(Q, 12, T)
             assert np.array_equal(ids, oids), (T, g)
             assert np.array_equal(ips, oips.astype(np.float32)), (T, g)
+
+
+def test_dense_head_matches_oracle():
+    """The bfloat16 re-rank with its dense head (sub-datasets screened whole on
+    the matrix cores, seeded theta for the gather of the others): none, the
+    default range, the widest (probed fraction 1/256) and the narrowest (1/4),
+    on three batches with a ragged tail."""
+    say("case dense head")
+    n, d, m, L, nq, k, T = 120000, 32, 16, 32, 150, 20, 9000
+    X = make_items("lognormal", n, d, seed=95, sigma=1.0)
+    Q = make_queries(nq, d, seed=96)
+    oix = orc.OracleIndex(X, m, L, seed=13, threads=8)
+    oids, oips = oix.query(Q, k, T)
+    items = {}
+    with nr.nrlsh_build(X, m, L, 13) as gix:
+        for dense_head in (-1, 0, 1, 64):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage="bf16",
+                                      dense_head=dense_head)
+            st = nr.nrlsh_get_query_stats()
+            say(f"  dense_head {dense_head}: stats {st}")
+            assert st["collect_fallbacks"] == 0 and st["lp_fallbacks"] == 0, st
+            items[dense_head] = st["dense_head_items"]
+            assert np.array_equal(ids, oids), dense_head
+            assert np.array_equal(ips, oips.astype(np.float32)), dense_head
+    assert items[-1] == 0, items
+    assert items[1] >= items[0] >= items[64] and items[1] > 0, items
+
+
+def test_dense_head_tied_buckets():
+    """Dense head over every sub-dataset with threshold buckets holding long
+    runs of equal codes, cut by stored position inside the screened range."""
+    say("case dense head ties")
+    base = make_items("lognormal", 900, 16, seed=97, sigma=0.7)
+    X = np.ascontiguousarray(np.repeat(base, 14, axis=0)[:12000])
+    Q = make_queries(80, 16, seed=98)
+    oix = orc.OracleIndex(X, 6, 24, seed=21, threads=8)
+    with nr.nrlsh_build(X, 6, 24, 21) as gix:
+        for T, g in ((1500, 20), (4000, 18), (7000, 24)):
+            ids, ips = nr.nrlsh_query(gix, Q, 12, T, rerank="gather", rerank_storage="bf16", scan_guess=g,
+                                      dense_head=1)
+            st = nr.nrlsh_get_query_stats()
+            assert st["dense_head_items"] > 0 and st["collect_fallbacks"] == 0, (T, st)
+            oids, oips = oix.query(Q, 12, T)
+            assert np.array_equal(ids, oids), (T, g)
+            assert np.array_equal(ips, oips.astype(np.float32)), (T, g)
+
+
+def test_dense_head_overflow_reruns_without_head():
+    """Items alike to within the bfloat16 bounds: the screen keeps every probed
+    pair of the head, the lists overflow, and the batch runs again without the
+    head (then the FP32 re-rank), with the same result."""
+    say("case dense head overflow")
+    n, d, m, L, k, T = 30000, 16, 4, 16, 10, 19000
+    rng = np.random.default_rng(99)
+    v = rng.standard_normal(d).astype(np.float32)
+    X = np.ascontiguousarray((v[None, :] * (1.0 + 1e-4 * rng.standard_normal((n, 1)))
+                              + 1e-5 * rng.standard_normal((n, d))).astype(np.float32))
+    Q = make_queries(64, d, seed=100)
+    oix = orc.OracleIndex(X, m, L, seed=23, threads=8)
+    oids, oips = oix.query(Q, k, T)
+    with nr.nrlsh_build(X, m, L, 23) as gix:
+        ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage="bf16", dense_head=1)
+        st = nr.nrlsh_get_query_stats()
+        say(f"  stats {st}")
+        assert st["lp_fallbacks"] >= 1, st
+        assert np.array_equal(ids, oids)
+        assert np.array_equal(ips, oips.astype(np.float32))
