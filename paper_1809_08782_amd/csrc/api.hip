@@ -1084,7 +1084,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_rh = blk.reserve<int32_t>(collect ? (size_t)B : 1),
                  o_tg = blk.reserve<int32_t>(collect ? (size_t)tiles * 4 * 64 : 1),
                  o_fl = blk.reserve<uint32_t>(collect ? (size_t)nbatches : 1),
-                 o_sh = blk.reserve<unsigned long long>(head_ok ? (size_t)sh.m : 1);
+                 o_sh = blk.reserve<unsigned long long>(head_ok ? (size_t)sh.m * sub_hits_slices(B) : 1);
     blk.allocate(s);
     DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
     DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
@@ -1124,13 +1124,17 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     auto decide_head = [&](int64_t nb) {
         head_decided = true;
         HIPX(launch_sub_hits(ghist.get(), ix->R.get(), grho.get(), nb, sh.m, sh.L, subhits.get(), s));
+        const int ns = sub_hits_slices(nb);
+        const size_t words = (size_t)sh.m * ns;
         size_t pb = 0;
-        auto *hits = static_cast<unsigned long long *>(pinned_take((size_t)sh.m * sizeof(unsigned long long), &pb));
-        HIPX(hipMemcpyAsync(hits, subhits.get(), (size_t)sh.m * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                            s));
+        auto *part = static_cast<unsigned long long *>(pinned_take(words * sizeof(unsigned long long), &pb));
+        HIPX(hipMemcpyAsync(part, subhits.get(), words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
         HIPX(hipStreamSynchronize(s));
-        hr = dense_head_range(ix, hits, nb, gstride, head_frac);
-        pinned_give(hits, pb, s, ix->device);
+        std::vector<unsigned long long> hits((size_t)sh.m, 0ull);
+        for (int j = 0; j < sh.m; ++j)
+            for (int t = 0; t < ns; ++t) hits[(size_t)j] += part[(size_t)j * ns + t];
+        pinned_give(part, pb, s, ix->device);
+        hr = dense_head_range(ix, hits.data(), nb, gstride, head_frac);
         head_any = hr.second > hr.first;
         if (!head_any) return;
         // theta_q comes from the head's items as a whole: a sub-dataset

@@ -883,6 +883,11 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
             for (int n = 0; n < 4; ++n) bq[c][mm][n] = (int)(0x01010101u + (uint32_t)y[n] * 0xFEu);  // +-1 bytes
         }
     }
+    int32x16_t ini[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) ini[c][r] = init[c];
     const int so0 = (wave * 2 + 0) * MX_SB * 64, so1 = (wave * 2 + 1) * MX_SB * 64;
     int cnt0 = 0, cnt1 = 0;
     const int64_t ng = (p1 - p0 + 31) >> 5;  // 32-item groups, the last one partial
@@ -918,11 +923,9 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
         const int gofs = (int)(p - p0) + 4 * hb;  // chunk offset of row 0 of this lane
 #pragma unroll
         for (int c = 0; c < 2; ++c) {
-            int32x16_t acc;
+            int32x16_t acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[0], bq[c][0], ini[c], 0, 0, 0);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) acc[r] = init[c];
-#pragma unroll
-            for (int mm = 0; mm < W; ++mm) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[mm], bq[c][mm], acc, 0, 0, 0);
+            for (int mm = 1; mm < W; ++mm) acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(aa[mm], bq[c][mm], acc, 0, 0, 0);
             uint32_t mask = 0u;
 #pragma unroll
             for (int r = 15; r >= 0; --r) mask = __builtin_amdgcn_alignbit(mask, (uint32_t)acc[r], 31);
@@ -2035,10 +2038,12 @@ __global__ __launch_bounds__(512) void k_screen_b128(
 }
 
 // Pass B of the single-product screen, the one that runs over every probed
-// pair: a register budget for three waves per SIMD (a few values spill)
-// hides the operand loads better than two waves with no spill.
+// pair.  Without the probe test (W = 0) a register budget for three waves
+// per SIMD (a few values spill) hides the operand loads better than two
+// waves with no spill; with it (the codes' registers, 108 bytes of spills at
+// three waves) two waves per SIMD are faster (d = 128: 2.57 -> 2.39 ms).
 template <int W>
-__global__ __launch_bounds__(256, 3) void k_screen1(NRLSH_SCREEN_PARAMS)
+__global__ __launch_bounds__(256, W == 0 ? 3 : 2) void k_screen1(NRLSH_SCREEN_PARAMS)
 {
     screen_bf16<W, false, false>(NRLSH_SCREEN_ARGS);
 }
@@ -2339,19 +2344,22 @@ __global__ __launch_bounds__(64) void k_rho_from_tie(const int32_t *__restrict__
 }
 
 // Per sub-dataset j: the sampled items (histogram of the sample pass) that
-// rank before each query's guessed cut rho, summed over the batch -- the
-// batch's probed items of j in sample units.  Ranks grow with h inside a
-// sub-dataset, so each query's walk stops at its first bucket not before rho.
-// One block per sub-dataset.
-__global__ __launch_bounds__(256) void k_sub_hits(const uint32_t *__restrict__ ghist, const int32_t *__restrict__ R,
-                                                  const int32_t *__restrict__ grho, int64_t nq, int m, int L,
-                                                  unsigned long long *__restrict__ out)
+// rank before each query's guessed cut rho, summed over a slice of the batch
+// -- the slice's probed items of j in sample units.  Ranks grow with h inside
+// a sub-dataset, so each query's walk stops at its first bucket not before
+// rho.  Blocks: (sub-dataset, slice of SUB_HITS_Q queries); out[j][slice].
+constexpr int SUB_HITS_Q = 256;
+__global__ __launch_bounds__(SUB_HITS_Q) void k_sub_hits(const uint32_t *__restrict__ ghist,
+                                                         const int32_t *__restrict__ R,
+                                                         const int32_t *__restrict__ grho, int64_t nq, int m,
+                                                         int L, unsigned long long *__restrict__ out)
 {
-    __shared__ unsigned long long part[4];
+    __shared__ unsigned long long part[SUB_HITS_Q / 64];
     const int j = blockIdx.x, tid = threadIdx.x, L1 = L + 1;
     const int32_t *Rj = R + (int64_t)j * L1;
+    const int64_t q = (int64_t)blockIdx.y * SUB_HITS_Q + tid;
     unsigned long long acc = 0;
-    for (int64_t q = tid; q < nq; q += 256) {
+    if (q < nq) {
         const int32_t rho = grho[q];
         const uint32_t *H = ghist + (((q >> 6) * m + j) * (int64_t)L1) * 64 + (q & 63);
         for (int h = 0; h <= L && Rj[L - h] < rho; ++h) acc += H[(int64_t)h * 64];
@@ -2360,14 +2368,21 @@ __global__ __launch_bounds__(256) void k_sub_hits(const uint32_t *__restrict__ g
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((tid & 63) == 0) part[tid >> 6] = acc;
     __syncthreads();
-    if (tid == 0) out[j] = part[0] + part[1] + part[2] + part[3];
+    if (tid == 0) {
+        unsigned long long t = 0;
+        for (int w = 0; w < SUB_HITS_Q / 64; ++w) t += part[w];
+        out[(int64_t)j * gridDim.y + blockIdx.y] = t;
+    }
 }
+
+int sub_hits_slices(int64_t nq) { return (int)std::max<int64_t>(1, (nq + SUB_HITS_Q - 1) / SUB_HITS_Q); }
 
 hipError_t launch_sub_hits(const uint32_t *ghist, const int32_t *R, const int32_t *grho, int64_t nq, int m, int L,
                            unsigned long long *out, hipStream_t s)
 {
     if (m < 1) return hipSuccess;
-    hipLaunchKernelGGL(k_sub_hits, dim3((unsigned)m), dim3(256), 0, s, ghist, R, grho, nq, m, L, out);
+    hipLaunchKernelGGL(k_sub_hits, dim3((unsigned)m, (unsigned)sub_hits_slices(nq)), dim3(SUB_HITS_Q), 0, s, ghist,
+                       R, grho, nq, m, L, out);
     return hipGetLastError();
 }
 

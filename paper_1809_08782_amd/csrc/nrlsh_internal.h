@@ -223,8 +223,10 @@ hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, in
                                  int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s);
 // rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
-// out[j] (m words) = the sample-pass items of sub-dataset j (ghist of a
-// sampled pass) that rank before grho[q], summed over the nq queries.
+// out[j][s] (m x sub_hits_slices(nq) words) = the sample-pass items of
+// sub-dataset j (ghist of a sampled pass) that rank before grho[q], summed
+// over the queries of slice s.
+int sub_hits_slices(int64_t nq);
 hipError_t launch_sub_hits(const uint32_t *ghist, const int32_t *R, const int32_t *grho, int64_t nq, int m, int L,
                            unsigned long long *out, hipStream_t s);
 // Pass 2 over the same chunks: appends each query's probed items to its list
