@@ -1670,6 +1670,14 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     __shared__ int32_t hthr_s[64], htie_s[64], pstar_s[64];
     __shared__ uint32_t qc_s[64 * WC];
     __shared__ int any_s, all_s;
+    // pass B with the probe test: kept items of each query row, staged in LDS
+    // and appended to the query's list with one reservation at the block's end
+    // (a returning global atomic per kept pair would leave its latency
+    // exposed); rows whose room fills take that atomic for the rest.  With
+    // every item probed (W = 0) few pairs are kept and each takes its own.
+    constexpr bool STAGE = !MAXMODE && W > 0;
+    constexpr int KS = STAGE ? 24 : 1;
+    __shared__ int32_t kc_s[64], kl_s[64 * KS];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
     const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
@@ -1682,6 +1690,7 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
 
     if (tid < 64) {
         const int64_t q = qmap(q0 + tid);
+        kc_s[tid] = 0;
         int hthr = -1, htie = -1, pstar = -1;
         float th = -INFINITY, qn = 0.f;
         if (q < nq) {
@@ -1877,9 +1886,14 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     if (MAXMODE) {
                         if (probed) gmax[ib >> 1] = fmaxf(gmax[ib >> 1], ip - e);
                     } else if (probed && !(ip + e < th)) {
-                        const int64_t q = qmap(q0 + ql);
-                        const int slot = atomicAdd(&counts[q], 1);
-                        if (slot < cap) lists[q * cap + slot] = pi;
+                        const int ls = STAGE ? atomicAdd(&kc_s[ql], 1) : KS;
+                        if (ls < KS) {
+                            kl_s[ql * KS + ls] = pi;
+                        } else {
+                            const int64_t q = qmap(q0 + ql);
+                            const int slot = atomicAdd(&counts[q], 1);
+                            if (slot < cap) lists[q * cap + slot] = pi;
+                        }
                     }
                 }
                 if (MAXMODE) {
@@ -1891,6 +1905,18 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                             cmax[(q0 + ql) * ncol + blockIdx.y * SC_GROUPS + (p0 - pbeg) / 32 + hg] = gmax[hg];
                     }
                 }
+            }
+        }
+    }
+    if (STAGE) {
+        __syncthreads();
+        if (tid < 64 && q0 + tid < nq) {
+            const int n = min(kc_s[tid], KS);
+            if (n > 0) {
+                const int64_t q = qmap(q0 + tid);
+                const int base = atomicAdd(&counts[q], n);
+                for (int i = 0; i < n; ++i)
+                    if (base + i < cap) lists[q * cap + base + i] = kl_s[tid * KS + i];
             }
         }
     }
