@@ -53,10 +53,12 @@ def ground_truth(Xd, Qs, k):
     return torch.cat(out).numpy()
 
 
-def traffic_record(kernel, workload, T):
+def traffic_record(kernel, workload, T, timer=None):
     """HBM bytes per query of a launch of `kernel` from a committed counter
     summary (profiles/*.md, a line "traffic_record: {json}"), provided the
-    sources it names still hash to what they were when the counters were taken."""
+    sources it names still hash to what they were when the counters were taken.
+    A record that names the timer it belongs to (one kernel can serve two
+    steps, as the FP32 re-rank does) matches that timer only."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
@@ -65,6 +67,8 @@ def traffic_record(kernel, workload, T):
         for ln in lines:
             rec = json.loads(ln[len("traffic_record: "):])
             if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("T") != T:
+                continue
+            if timer is not None and rec.get("timer", timer) != timer:
                 continue
             same = True
             for src, digest in rec.get("sources", {}).items():
@@ -446,7 +450,7 @@ def main():
     kern = hr["kernels"]
     qkern = {k: v for k, v in kern.items() if k not in BUILD_KERNELS}
     dom = max(qkern, key=lambda nm: qkern[nm]["ms_per_step"]) if qkern else None
-    roof = roofline(dom, kern, w, Tq, qb, hr["query_stats"])
+    roof, roofs = roofline(dom, kern, w, Tq, qb, hr["query_stats"])
     scan = None
     scan_kernel = "scan_collect" if "scan_collect" in kern else ("scan_hist" if "scan_hist" in kern else None)
     if scan_kernel:
@@ -538,6 +542,7 @@ def main():
         "exact_mips": exact,
         "norm_stats": norm_stats,
         "roofline": roof,
+        "rooflines": roofs,
         "scan": scan,
         "variants": variants,
         "probe_sweep": probe_sweep,
@@ -546,60 +551,103 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def roofline(dom, kern, w, Tq, qb, qstats):
-    """Roofline of the dominant query kernel from its algorithmic work per
-    launch and its HIP-event launch time."""
-    if dom is None:
-        return None
-    per = kern[dom]
+def kernel_roof(nm, kern, w, Tq, qb, qstats):
+    """Roofline entry of one query kernel: its algorithmic work per launch
+    (or per step) over its HIP-event time, against the peak of the unit that
+    bounds it, plus the HBM traffic of a committed counter record when its
+    sources are unchanged."""
+    per = kern[nm]
     launches = per["launches_per_step"]
     nq_launch = w.nq / launches
     W = (w.L + 31) // 32
-    if dom in ("rerank", "rerank_lp"):
-        # per probed item: its row (4d FP32 / 2d bf16 bytes), its stored
-        # position and original id (8); the bf16 pass also reads the row's
-        # error bound (4)
-        row = 4 * w.d if dom == "rerank" else 2 * w.d + 4
-        bytes_launch = nq_launch * Tq * (row + 8)
-        achieved = bytes_launch / (per["avg_ms"] * 1e-3) / 1e9
-        S = next(v for v in (1, 2, 4, 8, 16) if v * 64 >= w.k or v == 16)  # top-k registers per lane
-        kname = ("k_rerank<%d>" if dom == "rerank" else "k_rerank_bf16<%d>") % S
-        rec = traffic_record(kname, w.name, Tq)
+    S = next(v for v in (1, 2, 4, 8, 16) if v * 64 >= w.k or v == 16)  # top-k registers per lane
+    # the stats are the last query call's: the last batch, of nq - (calls - 1) qb queries
+    last_nq = w.nq - (-(-w.nq // qb) - 1) * qb
+
+    def with_traffic(d, kname):
+        rec = traffic_record(kname, w.name, Tq, nm)
         # counters were taken on full batches: bytes per query x this run's queries per launch
-        traffic = ((rec["fetch_bytes_per_query"] + rec["write_bytes_per_query"]) * nq_launch) if rec else None
-        return {"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS,
-                "traffic": traffic,
-                "traffic_source": rec, "bytes_per_launch": bytes_launch, "unit_work": "probed item",
-                "bytes_per_unit": row + 8, "units_per_launch": nq_launch * Tq, "dominant_kernel": dom}
-    if dom in ("scan_hist", "scan_emit", "scan_collect"):
+        d["traffic"] = ((rec["fetch_bytes_per_query"] + rec["write_bytes_per_query"]) * nq_launch) if rec else None
+        d["traffic_source"] = rec
+        return d
+
+    if nm in ("rerank", "rerank_lp", "rerank_exact"):
+        # per re-ranked item: its row (4d FP32 / 2d bf16 bytes), its stored
+        # position and original id (8); the bf16 pass also reads the row's
+        # error bound (4).  The FP32 pass reads every probed item, the bf16
+        # pass every gathered one (all probed items less those of a dense
+        # head), the exact pass after it the kept ones.
+        row = 2 * w.d + 4 if nm == "rerank_lp" else 4 * w.d
+        if nm == "rerank":
+            items = nq_launch * Tq
+        elif nm == "rerank_lp":
+            items = (qstats.get("lp_gathered_total") or 0) / max(1, last_nq) * nq_launch
+        else:
+            items = (qstats.get("lp_kept_total") or 0) / max(1, last_nq) * nq_launch
+        bytes_launch = items * (row + 8)
+        achieved = bytes_launch / (per["avg_ms"] * 1e-3) / 1e9
+        kname = ("k_rerank_bf16<%d>" if nm == "rerank_lp" else "k_rerank<%d>") % S
+        return with_traffic({"kernel": kname, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                             "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "bytes_per_launch": bytes_launch,
+                             "unit_work": "re-ranked item", "bytes_per_unit": row + 8,
+                             "units_per_launch": items}, kname)
+    if nm in ("scan_hist", "scan_emit", "scan_collect"):
         # pairs of the step from the last batch's scanned fraction, over the
         # kernel's time per step
-        last_nq = w.nq - (-(-w.nq // qb) - 1) * qb
         frac = (qstats.get("scan_pairs") or 0) / (last_nq * w.n)
-        if dom == "scan_emit" or frac == 0:
+        if nm == "scan_emit" or frac == 0:
             frac = 1.0
-        mx = dom == "scan_collect"
+        mx = nm == "scan_collect"
         ops_per_pair = 64 * W if mx else 2 * W + 1
         peak = INT8_MFMA_PEAK_TOPS if mx else INT_VALU_PEAK_TOPS
         ops_step = frac * w.nq * w.n * ops_per_pair
         achieved = ops_step / (per["ms_per_step"] * 1e-3) / 1e12
         kname = {"scan_hist": "k_scan_hist_s<%d>", "scan_emit": "k_scan_emit_s<%d>",
-                 "scan_collect": "k_scan_collect_mx<%d>"}[dom] % W
-        return {"kernel": kname, "bound": "mfma" if mx else "alu", "achieved": achieved, "peak": peak,
-                "unit": "TOP/s", "frac": achieved / peak, "traffic": None,
-                "ops_per_step": ops_step, "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair,
-                "dominant_kernel": dom}
-    if dom == "screen":
+                 "scan_collect": "k_scan_collect_mx<%d>"}[nm] % W
+        return with_traffic({"kernel": kname, "bound": "mfma" if mx else "alu", "achieved": achieved,
+                             "peak": peak, "unit": "TOP/s", "frac": achieved / peak, "ops_per_step": ops_step,
+                             "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair}, kname)
+    if nm == "head_screen":
+        # the keep pass of the dense head: one bf16 product (2d flops) per
+        # (query, item) pair of the screened sub-datasets
+        pairs = nq_launch * (qstats.get("dense_head_items") or 0)
+        flops = 2.0 * w.d * pairs
+        achieved = flops / (per["avg_ms"] * 1e-3) / 1e12
+        kname = "k_screen1<%d>" % W
+        return with_traffic({"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFS,
+                             "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFS, "flops_per_launch": flops,
+                             "unit_work": "(query, item) pair of the dense head", "flops_per_unit": 2.0 * w.d,
+                             "units_per_launch": pairs}, kname)
+    if nm == "screen":
         pairs = (qstats.get("screen_pairs") or 0) / max(1, qstats.get("screen_passes") or 1)
         flops = 2.0 * w.d * pairs
         achieved = flops / (per["avg_ms"] * 1e-3) / 1e12
         return {"kernel": "k_screen1<%d>" % W, "bound": "mfma", "achieved": achieved,
                 "peak": BF16_MFMA_PEAK_TFS, "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFS,
-                "traffic": None, "flops_per_launch": flops, "unit_work": "evaluated pair",
-                "dominant_kernel": dom}
-    return {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
-            "traffic": None, "dominant_kernel": dom}
+                "traffic": None, "flops_per_launch": flops, "unit_work": "evaluated pair"}
+    return None
+
+
+def roofline(dom, kern, w, Tq, qb, qstats):
+    """Roofline of the dominant query kernel (the largest share of the step),
+    and of every query kernel with a work model, largest first."""
+    if dom is None:
+        return None, []
+    qk = sorted((nm for nm in kern if nm not in BUILD_KERNELS), key=lambda nm: -kern[nm]["ms_per_step"])
+    rows = []
+    for nm in qk:
+        r = kernel_roof(nm, kern, w, Tq, qb, qstats)
+        if r is not None:
+            r["timer"] = nm
+            r["ms_per_step"] = kern[nm]["ms_per_step"]
+            r["avg_ms"] = kern[nm]["avg_ms"]
+            rows.append(r)
+    top = kernel_roof(dom, kern, w, Tq, qb, qstats)
+    if top is None:
+        top = {"kernel": dom, "bound": None, "achieved": None, "peak": None, "unit": None, "frac": None,
+               "traffic": None}
+    top["dominant_kernel"] = dom
+    return top, rows
 
 
 def run_variants(args, w, Xd, Qd, gt, nrec, margin, ids_buf, ips_buf):

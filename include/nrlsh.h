@@ -504,6 +504,9 @@ typedef struct nrlsh_query_stats {
                               exact passes; results never depend on it */
     int64_t dense_head_items; /* BF16 re-rank: items of the sub-datasets screened whole
                               (dense_head) in the call's last batch that used it, else 0 */
+    int64_t lp_gathered_total; /* BF16 re-rank: probed items whose bfloat16 rows were
+                              gathered (all of them, less those of a dense head), all
+                              queries */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

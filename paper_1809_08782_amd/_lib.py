@@ -67,7 +67,8 @@ class QueryStats(C.Structure):
                 ("lp_kept_max", C.c_int64), ("lp_fallbacks", C.c_int32), ("probe_mode", C.c_int32),
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
                 ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64),
-                ("collect_fallbacks", C.c_int64), ("dense_head_items", C.c_int64)]
+                ("collect_fallbacks", C.c_int64), ("dense_head_items", C.c_int64),
+                ("lp_gathered_total", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -574,7 +575,7 @@ def nrlsh_get_query_stats() -> dict:
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
             "table_passes": st.table_passes, "screen_pairs": st.screen_pairs,
             "scan_pairs": st.scan_pairs, "collect_fallbacks": st.collect_fallbacks,
-            "dense_head_items": st.dense_head_items}
+            "dense_head_items": st.dense_head_items, "lp_gathered_total": st.lp_gathered_total}
 
 
 def nrlsh_profile_enable(on: bool = True):

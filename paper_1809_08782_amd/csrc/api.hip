@@ -1109,7 +1109,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                             hipMemcpyHostToDevice, s));
     const TableView tv{ix->ucode.get(), ix->ustart.get(), ix->uoff.get(), ix->titem.get(), ix->binom.get()};
     if (table) HIPX(hipMemsetAsync(tctr.get(), 0, table_counter_bytes(), s));
-    std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0);
+    std::vector<int32_t> hl(bf16_rows ? (size_t)B : 0), hg(head_ok ? (size_t)B : 0);
     // once a batch's bfloat16 lists overflow (the bound keeps too many items
     // for this data and k), later batches of the call go straight to the
     // FP32 rows instead of paying for both passes
@@ -1277,20 +1277,25 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
             }
             tm.begin("rerank_lp");
-            HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), ix->perm.get(), Qb, nb, sh, cb,
+            HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), Qb, nb, sh, cb,
                                   hd ? ccount.get() : nullptr, nsplit, (int)lcap, lcount.get(), lists.get(),
                                   gtheta.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
+            if (hd)
+                HIPX(hipMemcpyAsync(hg.data(), ccount.get(), (size_t)nb * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    s));
             HIPX(hipStreamSynchronize(s));
-            int64_t mx = 0, tot = 0;
+            int64_t mx = 0, tot = 0, gathered = hd ? 0 : nb * sh.Tq;
             for (int64_t i = 0; i < nb; ++i) {
                 mx = std::max<int64_t>(mx, hl[i]);
                 tot += hl[i];
+                if (hd) gathered += hg[i];
             }
             if (mx <= lcap) {
                 g_qstats.lp_kept_total += tot;
+                g_qstats.lp_gathered_total += gathered;
                 g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, mx);
                 QueryShape shl = sh;
                 shl.Tq = lcap;  // list stride; lengths come from lcount

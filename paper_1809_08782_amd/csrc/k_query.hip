@@ -1158,7 +1158,6 @@ __device__ __forceinline__ void reduce_half(float (&a)[16], int upper)
 template <int S>
 __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16_t *__restrict__ Xh,
                                                     const float *__restrict__ xeb,
-                                                    const int32_t *__restrict__ perm,
                                                     const float *__restrict__ Q, int64_t n, int d, int dp,
                                                     int64_t Tq, int k, const int32_t *__restrict__ cand,
                                                     const int32_t *__restrict__ counts,
@@ -1203,9 +1202,7 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
         pn = (c0 + 64 + lane < cend) ? cq[c0 + 64 + lane] : -1;
         bool valid = c0 + lane < cend;
         valid = valid && p >= 0 && (int64_t)p < n;  // positions come from the scan; never trust blindly
-        int32_t id = 0;
-        if (valid) id = perm[p];
-        else p = 0;
+        if (!valid) p = 0;
         const int32_t pv = valid ? p : -1;
         float part[16];
 #pragma unroll
@@ -1242,7 +1239,9 @@ __global__ __launch_bounds__(64, S <= 2 ? 4 : 1) void k_rerank_bf16(const uint16
         const double acc = (double)__shfl(part[0], 16 * (lane & 3) + (lane >> 2), 64);
         const double e = qn * (double)(valid ? xeb[p] : 0.f) * (1.0 + 0x1p-20);
         const double floor = ge != 0ull ? order_value(ge) : -INFINITY;
-        top.offer(acc - e, id, valid, lane, floor);
+        // only the k-th value matters here, not which items hold it: the
+        // stored position stands in for the id (no read of perm)
+        top.offer(acc - e, p, valid, lane, floor);
         if (top.th_v > floor && lane == 0) atomicMax(&gtheta[q], (unsigned long long)order_key(top.th_v));
         const double th = fmax(top.th_v, floor);
         const bool keep = valid && !(acc + e < th);
@@ -2747,8 +2746,8 @@ hipError_t launch_theta_seed(const float *theta, int64_t nq, unsigned long long 
     return hipGetLastError();
 }
 
-hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
-                            const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
+hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const float *Q, int64_t nq,
+                            const QueryShape &sh, const int32_t *cand,
                             const int32_t *counts, int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s)
 {
@@ -2758,7 +2757,7 @@ hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t 
     const dim3 grid((unsigned)nq, (unsigned)nsplit), block(64);
     const size_t lds = (size_t)(sh.dp + 127) / 128 * 128 * sizeof(float);
 #define NRLSH_RERANK_LP(SS)                                                                         \
-    hipLaunchKernelGGL((k_rerank_bf16<SS>), grid, block, lds, s, Xh, xeb, perm, Q, sh.n, sh.d, sh.dp, \
+    hipLaunchKernelGGL((k_rerank_bf16<SS>), grid, block, lds, s, Xh, xeb, Q, sh.n, sh.d, sh.dp, \
                        sh.Tq, sh.k, cand, counts, slice, lcap, lcount, lists, gtheta)
     if (S <= 1) NRLSH_RERANK_LP(1);
     else if (S <= 2) NRLSH_RERANK_LP(2);

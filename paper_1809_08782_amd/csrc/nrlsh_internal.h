@@ -169,8 +169,8 @@ hipError_t launch_rerank(const float *Xl, const int32_t *perm, const float *Q, i
 // counts is NULL) that may still belong to the exact top-k.  gtheta: nq
 // words set by the caller (0, or the order key of a value that k probed
 // items reach), the k-th lower bound shared by the slices of each query.
-hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const int32_t *perm,
-                            const float *Q, int64_t nq, const QueryShape &sh, const int32_t *cand,
+hipError_t launch_rerank_lp(const uint16_t *Xh, const float *xeb, const float *Q, int64_t nq,
+                            const QueryShape &sh, const int32_t *cand,
                             const int32_t *counts, int nsplit, int lcap, int32_t *lcount, int32_t *lists,
                             unsigned long long *gtheta, hipStream_t s);
 // gtheta[q] = the order key of theta[q] (0 where theta is -inf): seeds the
