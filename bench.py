@@ -224,7 +224,7 @@ DEFAULT_FORMS = {"large": "fp8_bf16,fp32", "precision": "fp32,bf16_hash,fp8_hash
 KERNELS = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table", "qhash",
            "scan_sample", "guess", "scan_collect", "filter",
            "scan_hist", "threshold", "tie_locate", "scan_emit", "table_count", "table_emit",
-           "rerank", "head_theta", "head_screen", "rerank_lp", "screen_max", "screen", "rerank_exact"]
+           "order", "rerank", "head_theta", "head_screen", "rerank_lp", "screen_max", "screen", "rerank_exact"]
 BUILD_KERNELS = {"keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table"}
 INT_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes per clock x 2.4 GHz
 INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core peak, TOP/s

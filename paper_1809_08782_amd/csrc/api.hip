@@ -1033,6 +1033,12 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const int64_t tiles = B / 64;
     const int L1 = sh.L + 1;
     const int nsplit = rerank_splits(B, sh.Tq);
+    // with the collecting scan each batch is processed in order of its
+    // queries' guessed cuts (tiles of alike cuts scan and screen fewer
+    // chunks); the results go back to the batch's rows at the end
+    const bool sortq = collect && !cand_out_d;
+    int sort_bits = 1;
+    while ((int64_t(1) << sort_bits) <= (int64_t)sh.m * L1) ++sort_bits;
     // dense head of the bfloat16 re-rank (collecting scan only; not when the
     // probed lists themselves are the output): dense_head -1 = none, 0 = the
     // sub-datasets with at least 3/128 of their items probed, g = at least
@@ -1084,13 +1090,27 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_rh = blk.reserve<int32_t>(collect ? (size_t)B : 1),
                  o_tg = blk.reserve<int32_t>(collect ? (size_t)tiles * 4 * 64 : 1),
                  o_fl = blk.reserve<uint32_t>(collect ? (size_t)nbatches : 1),
-                 o_sh = blk.reserve<unsigned long long>(head_ok ? (size_t)sh.m * sub_hits_slices(B) : 1);
+                 o_sh = blk.reserve<unsigned long long>(head_ok ? (size_t)sh.m * sub_hits_slices(B) : 1),
+                 o_ska = blk.reserve<uint64_t>(sortq ? (size_t)B : 1), o_skb = blk.reserve<uint64_t>(sortq ? (size_t)B : 1),
+                 o_sva = blk.reserve<int32_t>(sortq ? (size_t)B : 1), o_svb = blk.reserve<int32_t>(sortq ? (size_t)B : 1),
+                 o_stm = blk.reserve<uint8_t>(sortq ? radix_sort_tmp_bytes(B) : 1),
+                 o_sqp = blk.reserve<float>(sortq ? (size_t)B * sh.d : 1),
+                 o_sqc = blk.reserve<uint32_t>(sortq ? (size_t)B * sh.qsets * sh.W : 1),
+                 o_srh = blk.reserve<int32_t>(sortq ? (size_t)B : 1),
+                 o_sid = blk.reserve<int64_t>(sortq ? (size_t)B * k : 1),
+                 o_sip = blk.reserve<float>(sortq ? (size_t)B * k : 1);
     blk.allocate(s);
     DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
     DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
     DBuf<uint32_t> gfail = blk.view<uint32_t>(o_fl);
     if (collect) HIPX(launch_fill32(gfail.get(), nbatches, 0u, s));
     DBuf<unsigned long long> subhits = blk.view<unsigned long long>(o_sh);
+    DBuf<uint64_t> ska = blk.view<uint64_t>(o_ska), skb = blk.view<uint64_t>(o_skb);
+    DBuf<int32_t> sva = blk.view<int32_t>(o_sva), svb = blk.view<int32_t>(o_svb), srho = blk.view<int32_t>(o_srh);
+    DBuf<uint8_t> stmp = blk.view<uint8_t>(o_stm);
+    DBuf<float> sQ = blk.view<float>(o_sqp), sips = blk.view<float>(o_sip);
+    DBuf<uint32_t> sqc = blk.view<uint32_t>(o_sqc);
+    DBuf<int64_t> sids = blk.view<int64_t>(o_sid);
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
                   gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
@@ -1173,6 +1193,13 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         const float *Qb = Qd + b0 * sh.d;
         uint32_t *qc = qcodes_out_d ? qcodes_out_d + b0 * sh.qsets * sh.W : qcodes.get();
         int32_t *cb = cand_out_d ? cand_out_d + b0 * sh.Tq : cand.get();
+        // the batch as the steps after the guess take it: its own order, or
+        // sorted by guessed cut (qord: sorted row -> batch row)
+        const float *Qx = Qb;
+        uint32_t *qx = qc;
+        int32_t *rx = grho.get(), *qord = nullptr;
+        int64_t *ox_ids = ids_d + b0 * k;
+        float *ox_ips = ips_d + b0 * k;
         tm.begin("qhash");
         HIPX(launch_query_hash(Qb, nb, sh.d, ix->At.get(), sh.L, sh.W, sh.qsets, qc, nonfinite_d, s));
         tm.end();
@@ -1212,12 +1239,24 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 jh0 = hr.first;
                 jh1 = hr.second;
             }
+            if (sortq) {
+                tm.begin("order");
+                HIPX(launch_rho_order(grho.get(), nb, sort_bits, ska.get(), sva.get(), skb.get(), svb.get(),
+                                      stmp.get(), &qord, s));
+                HIPX(launch_permute_batch(Qb, qc, grho.get(), qord, nb, sh.d, sh.qsets * sh.W, sQ.get(), sqc.get(),
+                                          srho.get(), s));
+                tm.end();
+                Qx = sQ.get();
+                qx = sqc.get();
+                rx = srho.get();
+                ox_ids = sids.get();
+                ox_ips = sips.get();
+            }
             HIPX(launch_fill32(ghist.get(), tb * sh.m * L1 * 64, 0u, s));
             HIPX(launch_fill32(kcount.get(), nb, 0u, s));
             tm.begin("scan_collect");
-            HIPX(launch_scan_collect(ix->codes_l.get(), qc, nb, sh, schunks.get(), nstage_chunks, ix->R.get(),
-                                     grho.get(), kcap, kcount.get(), keys.get(), ghist.get(), scan_pairs_d, s,
-                                     jh0, jh1));
+            HIPX(launch_scan_collect(ix->codes_l.get(), qx, nb, sh, schunks.get(), nstage_chunks, ix->R.get(),
+                                     rx, kcap, kcount.get(), keys.get(), ghist.get(), scan_pairs_d, s, jh0, jh1));
             tm.end();
             // (the dense head's screen reads every sub-dataset's level bound)
             tm.begin("threshold");
@@ -1225,12 +1264,12 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                   gtie.get(), s, hd));
             tm.end();
             tm.begin("tie_locate");
-            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qc, nb, sh.W, sh.qsets, gtie.get(),
+            HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qx, nb, sh.W, sh.qsets, gtie.get(),
                                    gpstar.get(), s));
             tm.end();
             tm.begin("filter");
-            HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), grho.get(),
-                                       sh.Tq, cb, ccount.get(), gfail.get() + bi, s));
+            HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), rx, sh.Tq, cb,
+                                       ccount.get(), gfail.get() + bi, s));
             tm.end();
         } else if (!table) {
             tm.begin("scan_hist");
@@ -1260,16 +1299,16 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 // reach it into the lists; theta_q seeds the gather below, which
                 // takes the other sub-datasets' probed items (the filter left the
                 // head's out)
-                ScreenQueries sq{Qb, hqh.get(), nullptr, hqn.get(), nullptr, nullptr};
+                ScreenQueries sq{Qx, hqh.get(), nullptr, hqn.get(), nullptr, nullptr};
                 tm.begin("head_theta");
-                HIPX(launch_query_bf16(Qb, nb, sh.d, sh.dp, hqh.get(), nullptr, hqn.get(), s, nonfinite_d));
+                HIPX(launch_query_bf16(Qx, nb, sh.d, sh.dp, hqh.get(), nullptr, hqn.get(), s, nonfinite_d));
                 HIPX(launch_screen_max(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq,
-                                       nb, sh, hcells.get(), nhcells, nhcells, qc, ghthr.get(), gtie.get(),
+                                       nb, sh, hcells.get(), nhcells, nhcells, qx, ghthr.get(), gtie.get(),
                                        gpstar.get(), hcmax.get(), htheta.get(), s));
                 tm.end();
                 tm.begin("head_screen");
                 HIPX(launch_screen(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq, nb,
-                                   sh, hchunks.get(), nhchunks, qc, ghthr.get(), gtie.get(), gpstar.get(),
+                                   sh, hchunks.get(), nhchunks, qx, ghthr.get(), gtie.get(), gpstar.get(),
                                    htheta.get(), (int)lcap, lcount.get(), lists.get(), s));
                 tm.end();
                 HIPX(launch_theta_seed(htheta.get(), nb, gtheta.get(), s));
@@ -1277,7 +1316,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
             }
             tm.begin("rerank_lp");
-            HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), Qb, nb, sh, cb,
+            HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), Qx, nb, sh, cb,
                                   hd ? ccount.get() : nullptr, nsplit, (int)lcap, lcount.get(), lists.get(),
                                   gtheta.get(), s));
             tm.end();
@@ -1301,10 +1340,11 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 shl.Tq = lcap;  // list stride; lengths come from lcount
                 const int ns = std::min(rerank_splits(nb, lcap), lsplit);
                 tm.begin("rerank_exact");
-                HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, shl, lists.get(),
-                                   lcount.get(), ns, lpart_v.get(), lpart_i.get(), ids_d + b0 * k,
-                                   ips_d + b0 * k, s));
+                HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qx, nb, shl, lists.get(),
+                                   lcount.get(), ns, lpart_v.get(), lpart_i.get(), ox_ids, ox_ips, s));
                 tm.end();
+                if (qord)
+                    HIPX(launch_unpermute_results(qord, nb, k, ox_ids, ox_ips, ids_d + b0 * k, ips_d + b0 * k, s));
                 if (hd) g_qstats.dense_head_items = ix->off_h[(size_t)jh1] - ix->off_h[(size_t)jh0];
                 return true;
             }
@@ -1316,10 +1356,10 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         }
         if (nsplit > 1) HIPX(hipMemsetAsync(gtheta.get(), 0, (size_t)nb * sizeof(unsigned long long), s));
         tm.begin("rerank");
-        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qb, nb, sh, cb, nullptr, nsplit,
-                           part_v.get(), part_i.get(), ids_d + b0 * k, ips_d + b0 * k, s,
-                           gtheta.get()));
+        HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qx, nb, sh, cb, nullptr, nsplit, part_v.get(),
+                           part_i.get(), ox_ids, ox_ips, s, gtheta.get()));
         tm.end();
+        if (qord) HIPX(launch_unpermute_results(qord, nb, k, ox_ids, ox_ips, ids_d + b0 * k, ips_d + b0 * k, s));
         return true;
     };
     for (int64_t b0 = 0, bi = 0; b0 < nq; b0 += B, ++bi)

@@ -2466,6 +2466,78 @@ hipError_t launch_query_order(const float *theta, const float *qn, int64_t nq, u
     return e;
 }
 
+// A batch's queries in order of their guessed cut rho: a 64-query tile scans
+// (and the dense head screens) every chunk of a sub-dataset whose first
+// bucket ranks before the largest cut among its queries, so tiles of alike
+// cuts touch fewer chunks.  Keys rho, values the batch index.
+__global__ __launch_bounds__(256) void k_rho_keys(const int32_t *__restrict__ rho, int64_t nq,
+                                                  uint64_t *__restrict__ ka, int32_t *__restrict__ va)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    ka[q] = (uint64_t)(uint32_t)max(rho[q], 0);
+    va[q] = (int32_t)q;
+}
+
+hipError_t launch_rho_order(const int32_t *rho, int64_t nq, int nbits, uint64_t *ka, int32_t *va, uint64_t *kb,
+                            int32_t *vb, void *tmp, int32_t **order, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_rho_keys, dim3(ceil_div(nq, 256)), dim3(256), 0, s, rho, nq, ka, va);
+    bool in_b = false;
+    hipError_t e = radix_sort(ka, va, kb, vb, nq, nbits, tmp, &in_b, s);
+    *order = in_b ? vb : va;
+    return e;
+}
+
+// Row i of the permuted batch is row order[i] of the batch: its query (d
+// floats), its codes (cw words) and its guessed cut.  One wave per row.
+__global__ __launch_bounds__(256) void k_permute_batch(const float *__restrict__ Q, const uint32_t *__restrict__ qc,
+                                                       const int32_t *__restrict__ rho,
+                                                       const int32_t *__restrict__ order, int64_t nq, int d, int cw,
+                                                       float *__restrict__ Qp, uint32_t *__restrict__ qcp,
+                                                       int32_t *__restrict__ rhop)
+{
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= nq) return;
+    const int64_t src = order[i];
+    for (int t = lane; t < d; t += 64) Qp[i * d + t] = Q[src * d + t];
+    for (int t = lane; t < cw; t += 64) qcp[i * cw + t] = qc[src * cw + t];
+    if (lane == 0) rhop[i] = rho[src];
+}
+
+// The results of permuted row i go to row order[i] of the batch's outputs.
+__global__ __launch_bounds__(256) void k_unpermute_results(const int32_t *__restrict__ order, int64_t nq, int k,
+                                                           const int64_t *__restrict__ tids,
+                                                           const float *__restrict__ tips,
+                                                           int64_t *__restrict__ ids, float *__restrict__ ips)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nq * k) return;
+    const int64_t i = e / k, c = e - i * k;
+    const int64_t dst = (int64_t)order[i] * k + c;
+    ids[dst] = tids[e];
+    ips[dst] = tips[e];
+}
+
+hipError_t launch_permute_batch(const float *Q, const uint32_t *qc, const int32_t *rho, const int32_t *order,
+                                int64_t nq, int d, int cw, float *Qp, uint32_t *qcp, int32_t *rhop, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_permute_batch, dim3(ceil_div(nq, 4)), dim3(256), 0, s, Q, qc, rho, order, nq, d, cw, Qp,
+                       qcp, rhop);
+    return hipGetLastError();
+}
+
+hipError_t launch_unpermute_results(const int32_t *order, int64_t nq, int k, const int64_t *tids, const float *tips,
+                                    int64_t *ids, float *ips, hipStream_t s)
+{
+    if (nq < 1 || k < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_unpermute_results, dim3(ceil_div(nq * k, 256)), dim3(256), 0, s, order, nq, k, tids, tips,
+                       ids, ips);
+    return hipGetLastError();
+}
+
 hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
                             int32_t *gpstar, hipStream_t s)
 {

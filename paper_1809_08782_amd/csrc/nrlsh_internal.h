@@ -223,6 +223,17 @@ hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, in
                                  int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s);
 // rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
+// Permutation of a batch by its guessed cuts rho (ascending; keys of nbits
+// bits), through a radix sort in the given buffers (nq each; tmp:
+// radix_sort_tmp_bytes(nq)); *order points into va or vb.
+hipError_t launch_rho_order(const int32_t *rho, int64_t nq, int nbits, uint64_t *ka, int32_t *va, uint64_t *kb,
+                            int32_t *vb, void *tmp, int32_t **order, hipStream_t s);
+// Qp / qcp / rhop row i = Q (d floats) / qc (cw words) / rho row order[i].
+hipError_t launch_permute_batch(const float *Q, const uint32_t *qc, const int32_t *rho, const int32_t *order,
+                                int64_t nq, int d, int cw, float *Qp, uint32_t *qcp, int32_t *rhop, hipStream_t s);
+// ids / ips row order[i] = tids / tips row i (k entries each).
+hipError_t launch_unpermute_results(const int32_t *order, int64_t nq, int k, const int64_t *tids, const float *tips,
+                                    int64_t *ids, float *ips, hipStream_t s);
 // out[j][s] (m x sub_hits_slices(nq) words) = the sample-pass items of
 // sub-dataset j (ghist of a sampled pass) that rank before grho[q], summed
 // over the queries of slice s.
