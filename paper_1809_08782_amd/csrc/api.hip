@@ -1047,6 +1047,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     const bool head_ok = collect && bf16_rows && !cand_out_d && dh >= 0 && screen_fits(ix, SCREEN_BF16);
     const double head_frac = (dh > 0 ? dh : 6) / 256.0;
     bool head_decided = false, head_any = false;
+    int head_lp_split = 1;  // slices per query of the gather beside the head
     std::pair<int, int> hr{0, 0};
     int nhcells = 0, nhchunks = 0;
     Block hblk;
@@ -1157,6 +1158,16 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         hr = dense_head_range(ix, hits.data(), nb, gstride, head_frac);
         head_any = hr.second > hr.first;
         if (!head_any) return;
+        // the probed items left to the gather, per query (the sample counts
+        // items ranked before the guess, guess16 / 16 Tq of them): slices of
+        // about 320 items keep the machine busy on these short lists (large
+        // workload, 4,984 items per query: 1.05 ms per call in 2 slices, 0.71
+        // in 16)
+        double rest = 0.0;
+        for (int j = 0; j < sh.m; ++j)
+            if (j < hr.first || j >= hr.second) rest += (double)hits[(size_t)j];
+        rest *= (double)gstride / (double)nb * 16.0 / (double)guess16;
+        head_lp_split = (int)std::min<double>(16.0, std::max<double>(1.0, std::ceil(rest / 320.0)));
         // theta_q comes from the head's items as a whole: a sub-dataset
         // normalised by an outlying U_j hashes almost all of its items alike,
         // so that a query probes nearly all of them or nearly none, and no
@@ -1317,7 +1328,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             }
             tm.begin("rerank_lp");
             HIPX(launch_rerank_lp(ix->Xh.get(), ix->xeb.get(), Qx, nb, sh, cb,
-                                  hd ? ccount.get() : nullptr, nsplit, (int)lcap, lcount.get(), lists.get(),
+                                  hd ? ccount.get() : nullptr, hd ? head_lp_split : nsplit, (int)lcap,
+                                  lcount.get(), lists.get(),
                                   gtheta.get(), s));
             tm.end();
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),

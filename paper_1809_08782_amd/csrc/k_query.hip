@@ -932,14 +932,14 @@ __global__ __launch_bounds__(SH_WAVES * 64) void k_scan_collect_mx(const uint32_
             mask &= vmask;
             if (count_only) {
                 // level h = acc + hcut + 1 of each hit counted straight into
-                // the histogram word of (h, query 32 c + col0)
+                // the histogram word of (h, query 32 c + col0); the other rows
+                // add 0 to a word of their own level (h <= L), so no branches
                 const uint32_t inc = 1u << (16 * (col0 & 1));
                 const int hw = (hcut[c] + 1) * 32 + 16 * c + (col0 >> 1);
 #pragma unroll
                 for (int r = 0; r < 16; ++r)
-                    if ((mask >> r) & 1u)
-                        __hip_atomic_fetch_add(&hist[acc[r] * 32 + hw], inc, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_fetch_add(&hist[acc[r] * 32 + hw], ((mask >> r) & 1u) * inc, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WORKGROUP);
                 continue;
             }
             // low bytes of the accumulators, four to a word (byte r & 3 of word r >> 2)
