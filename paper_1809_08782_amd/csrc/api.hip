@@ -960,6 +960,44 @@ void run_scan_hist_staged(const nrlsh_index *ix, const QueryShape &sh, const uin
 
 bool screen_fits(const nrlsh_index *ix, int kind);
 
+// Witnesses of the dense head, made once per index (see nrlsh_index): the
+// kWitnessTop largest-norm items of each sub-dataset and every
+// kWitnessStride-th one.
+constexpr int kWitnessTop = 4096, kWitnessStride = 32;
+void witness_rows(const nrlsh_index *ix, hipStream_t s)
+{
+    if (ix->wit_ready.load(std::memory_order_acquire)) return;
+    std::lock_guard<std::mutex> g(ix->wit_mu);
+    if (ix->wit_ready.load(std::memory_order_relaxed)) return;
+    int64_t nmax = 0;
+    for (int j = 0; j < ix->m; ++j) nmax = std::max<int64_t>(nmax, ix->off_h[(size_t)j + 1] - ix->off_h[(size_t)j]);
+    const int W = (int)std::min<int64_t>(nmax, kWitnessTop + (nmax + kWitnessStride - 1) / kWitnessStride);
+    const int m = ix->m, dp = ix->dp, cw = ix->W;
+    const size_t slots = (size_t)m * W;
+    DBuf<int32_t> pos(slots, s), cnt((size_t)m, s);
+    DBuf<uint16_t> xw(slots * dp + 32, s);  // zeroed 32-value tail pad, as the row copies
+    DBuf<uint32_t> cwo(slots * cw, s);
+    DBuf<double> kw(slots, s);
+    HIPX(hipMemsetAsync(xw.get() + slots * dp, 0, 32 * sizeof(uint16_t), s));
+    HIPX(launch_wit_build(ix->Xh.get(), ix->codes_l.get(), ix->key_l.get(), ix->off.get(), m, dp, cw, kWitnessTop,
+                          kWitnessStride, std::max(1, W), pos.get(), cnt.get(), xw.get(), cwo.get(), kw.get(), s));
+    std::vector<int32_t> ch((size_t)m);
+    HIPX(hipMemcpyAsync(ch.data(), cnt.get(), (size_t)m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPX(hipStreamSynchronize(s));
+    for (DBuf<int32_t> *b : {&pos, &cnt}) b->s = ix->home;  // released with the index, on the library stream
+    xw.s = ix->home;
+    cwo.s = ix->home;
+    kw.s = ix->home;
+    ix->wit_pos = std::move(pos);
+    ix->wit_cnt = std::move(cnt);
+    ix->wit_xh = std::move(xw);
+    ix->wit_codes = std::move(cwo);
+    ix->wit_key = std::move(kw);
+    ix->wit_cnt_h = std::move(ch);
+    ix->wit_per_sub = W;
+    ix->wit_ready.store(true, std::memory_order_release);
+}
+
 // Sub-datasets that the bfloat16 re-rank screens whole (64-query tiles
 // against all their items on the matrix cores, the screen path's two passes)
 // instead of gathering the rows of their probed items: the contiguous range
@@ -988,14 +1026,12 @@ std::pair<int, int> dense_head_range(const nrlsh_index *ix, const unsigned long 
 }
 
 // (sub-dataset, first, end) triples of at most `items` stored items covering
-// the sub-datasets js (with stride > 1: every stride-th such piece).
-std::vector<int32_t> subset_chunks(const nrlsh_index *ix, int items, const std::vector<int> &js, int stride = 1)
+// the sub-datasets js.
+std::vector<int32_t> subset_chunks(const nrlsh_index *ix, int items, const std::vector<int> &js)
 {
     std::vector<int32_t> ch;
-    int64_t c = 0;
     for (const int j : js)
         for (int64_t p = ix->off_h[(size_t)j]; p < ix->off_h[(size_t)j + 1]; p += items) {
-            if (c++ % stride != 0) continue;
             ch.push_back(j);
             ch.push_back((int32_t)p);
             ch.push_back((int32_t)std::min<int64_t>(p + items, ix->off_h[(size_t)j + 1]));
@@ -1139,7 +1175,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     if (ovf != 0 && (uint64_t)k >= (ovf >> 32) && (uint64_t)sh.Tq >= (ovf & 0xFFFFFFFFull)) lp_on = false;
     DBuf<uint16_t> hqh;
     DBuf<float> hqn, htheta, hcmax;
-    DBuf<int32_t> hcells, hchunks;
+    DBuf<int32_t> hcells, hchunks, hpw;
     // Chooses the head from the sample pass of the batch just guessed (one
     // host round trip per call) and sets up its buffers.
     auto decide_head = [&](int64_t nb) {
@@ -1168,24 +1204,34 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             if (j < hr.first || j >= hr.second) rest += (double)hits[(size_t)j];
         rest *= (double)gstride / (double)nb * 16.0 / (double)guess16;
         head_lp_split = (int)std::min<double>(16.0, std::max<double>(1.0, std::ceil(rest / 320.0)));
-        // theta_q comes from the head's items as a whole: a sub-dataset
-        // normalised by an outlying U_j hashes almost all of its items alike,
-        // so that a query probes nearly all of them or nearly none, and no
-        // single sub-dataset holds k probed items for every query.  Every
-        // head_witness_stride-th cell is a witness.  (The screen path's norm
-        // bound skips nothing here: theta_q stays far below ||q|| U_j.)
+        // theta_q comes from witnesses in every sub-dataset of the head (a
+        // sub-dataset normalised by an outlying U_j hashes almost all of its
+        // items alike, so that a query probes nearly all of them or nearly
+        // none, and no single sub-dataset holds k probed items for every
+        // query): each one's largest-norm items, which set the k-th best
+        // lower bound, screened from their compact copy.  (The screen path's
+        // norm bound skips nothing here: theta_q stays far below ||q|| U_j.)
+        witness_rows(ix, s);
         std::vector<int> hjs;
         for (int j = hr.second - 1; j >= hr.first; --j) hjs.push_back(j);
-        const int head_witness_stride = 4;
-        const std::vector<int32_t> hce = subset_chunks(ix, screen_cell_items(), hjs, head_witness_stride);
+        std::vector<int32_t> hce;
+        const int Wp = ix->wit_per_sub;
+        for (const int j : hjs)
+            for (int c0 = 0; c0 < ix->wit_cnt_h[(size_t)j]; c0 += screen_cell_items()) {
+                hce.push_back(j);
+                hce.push_back(j * Wp + c0);
+                hce.push_back(j * Wp + std::min(c0 + screen_cell_items(), ix->wit_cnt_h[(size_t)j]));
+            }
         const std::vector<int32_t> hch = subset_chunks(ix, screen_chunk_items(), hjs);
         nhcells = (int)(hce.size() / 3);
         nhchunks = (int)(hch.size() / 3);
         const size_t o_hq = hblk.reserve<uint16_t>((size_t)B * sh.dp), o_hn = hblk.reserve<float>((size_t)B),
                      o_ht = hblk.reserve<float>((size_t)B),
                      o_hm = hblk.reserve<float>((size_t)B * nhcells * screen_cell_groups()),
-                     o_hc = hblk.reserve<int32_t>(hce.size()), o_hk = hblk.reserve<int32_t>(hch.size());
+                     o_hc = hblk.reserve<int32_t>(std::max<size_t>(1, hce.size())),
+                     o_hk = hblk.reserve<int32_t>(hch.size()), o_hp = hblk.reserve<int32_t>((size_t)B);
         hblk.allocate(s);
+        hpw = hblk.view<int32_t>(o_hp);
         hqh = hblk.view<uint16_t>(o_hq);
         hqn = hblk.view<float>(o_hn);
         htheta = hblk.view<float>(o_ht);
@@ -1313,9 +1359,11 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 ScreenQueries sq{Qx, hqh.get(), nullptr, hqn.get(), nullptr, nullptr};
                 tm.begin("head_theta");
                 HIPX(launch_query_bf16(Qx, nb, sh.d, sh.dp, hqh.get(), nullptr, hqn.get(), s, nonfinite_d));
-                HIPX(launch_screen_max(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq,
-                                       nb, sh, hcells.get(), nhcells, nhcells, qx, ghthr.get(), gtie.get(),
-                                       gpstar.get(), hcmax.get(), htheta.get(), s));
+                HIPX(launch_wit_pstar(gtie.get(), gpstar.get(), ix->wit_pos.get(), ix->wit_cnt.get(),
+                                      ix->wit_per_sub, nb, hpw.get(), s));
+                HIPX(launch_screen_max(ix->Xl.get(), ix->wit_xh.get(), nullptr, ix->wit_key.get(),
+                                       ix->wit_codes.get(), sq, nb, sh, hcells.get(), nhcells, nhcells, qx,
+                                       ghthr.get(), gtie.get(), hpw.get(), hcmax.get(), htheta.get(), s));
                 tm.end();
                 tm.begin("head_screen");
                 HIPX(launch_screen(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq, nb,

@@ -243,6 +243,17 @@ struct nrlsh_index {
     mutable nrlsh::host::DBuf<uint16_t> Xlo;
     mutable std::mutex lo_mu;
     mutable std::atomic<bool> lo_ready{false};
+    // witnesses of the dense head (made on the first query that screens one):
+    // per sub-dataset its wit_per_sub largest-norm items, positions in stored
+    // order and compact copies of their bfloat16 rows, codes and keys
+    mutable std::mutex wit_mu;
+    mutable std::atomic<bool> wit_ready{false};
+    mutable int32_t wit_per_sub = 0;
+    mutable std::vector<int32_t> wit_cnt_h;
+    mutable nrlsh::host::DBuf<int32_t> wit_pos, wit_cnt;
+    mutable nrlsh::host::DBuf<uint16_t> wit_xh;
+    mutable nrlsh::host::DBuf<uint32_t> wit_codes;
+    mutable nrlsh::host::DBuf<double> wit_key;
     nrlsh::host::DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
     nrlsh::host::DBuf<float> xscale;                  // its row scales
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order

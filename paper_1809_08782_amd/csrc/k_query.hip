@@ -2538,6 +2538,178 @@ hipError_t launch_unpermute_results(const int32_t *order, int64_t nq, int k, con
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- witnesses
+// The witnesses of each sub-dataset, in stored order: its `top` largest-norm
+// items (ties by stored position) -- the k-th best lower bound of a query's
+// probed items is mostly set by high-norm ones -- and every `stride`-th item
+// of its stored range (so that a query whose probed items are low-norm ones
+// still finds k witnesses among them).  One block per sub-dataset: radix
+// selection of the top-th largest key (keys are non-negative doubles, ordered
+// as their bit patterns), then an ordered compaction.  wpos: m x W stored
+// positions (W >= top + ceil(n_j / stride)), wcnt[j] their number.
+constexpr int WIT_THREADS = 1024;
+__global__ __launch_bounds__(WIT_THREADS) void k_wit_select(const double *__restrict__ key_l,
+                                                            const int32_t *__restrict__ off, int top, int stride,
+                                                            int W, int32_t *__restrict__ wpos,
+                                                            int32_t *__restrict__ wcnt)
+{
+    constexpr int NW = WIT_THREADS / 64;
+    __shared__ uint32_t hist[256];
+    __shared__ unsigned long long s_prefix;
+    __shared__ int s_need, s_base, s_tbase;
+    __shared__ int wsum[2 * NW];
+    const int j = blockIdx.x, tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int64_t p0 = off[j], p1 = off[j + 1], nj = p1 - p0;
+    const int want = (int)min<int64_t>(nj, (int64_t)top);
+    int32_t *out = wpos + (int64_t)j * W;
+    if (want == nj || nj <= W && stride == 1) {  // every item of the sub-dataset
+        for (int64_t i = tid; i < nj; i += WIT_THREADS) out[i] = (int32_t)(p0 + i);
+        if (tid == 0) wcnt[j] = want;
+        return;
+    }
+    unsigned long long prefix = 0, mask = 0;
+    int need = want;
+    for (int shift = 56; shift >= 0; shift -= 8) {
+        for (int b = tid; b < 256; b += WIT_THREADS) hist[b] = 0u;
+        __syncthreads();
+        for (int64_t p = p0 + tid; p < p1; p += WIT_THREADS) {
+            const unsigned long long u = (unsigned long long)__double_as_longlong(key_l[p]);
+            if ((u & mask) == prefix) atomicAdd(&hist[(u >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int cum = 0, sel = 0;
+            for (int b = 255; b >= 0; --b) {
+                if (cum + (int)hist[b] >= need) {
+                    sel = b;
+                    break;
+                }
+                cum += (int)hist[b];
+            }
+            s_need = need - cum;
+            s_prefix = prefix | ((unsigned long long)sel << shift);
+        }
+        __syncthreads();
+        need = s_need;
+        prefix = s_prefix;
+        mask |= 0xFFull << shift;
+        __syncthreads();
+    }
+    // prefix: the bits of the want-th largest key t; need: how many keys equal
+    // to t to take (the first ones in stored order), after every key above t
+    if (tid == 0) {
+        s_base = 0;
+        s_tbase = 0;
+    }
+    __syncthreads();
+    const unsigned long long below = (1ull << lane) - 1ull;
+    for (int64_t c0 = p0; c0 < p1; c0 += WIT_THREADS) {
+        const int64_t p = c0 + tid;
+        bool gt = false, eq = false;
+        if (p < p1) {
+            const unsigned long long u = (unsigned long long)__double_as_longlong(key_l[p]);
+            gt = u > prefix;
+            eq = u == prefix;
+        }
+        const unsigned long long be = __ballot(eq);
+        if (lane == 0) wsum[wv] = __popcll(be);
+        __syncthreads();
+        int eoff = 0;
+        for (int w = 0; w < wv; ++w) eoff += wsum[w];
+        const bool keep = gt || (eq && s_tbase + eoff + __popcll(be & below) < need) ||
+                          (p < p1 && (p - p0) % stride == 0);
+        const unsigned long long bk = __ballot(keep);
+        if (lane == 0) wsum[NW + wv] = __popcll(bk);
+        __syncthreads();
+        int koff = 0;
+        for (int w = 0; w < wv; ++w) koff += wsum[NW + w];
+        if (keep) out[s_base + koff + __popcll(bk & below)] = (int32_t)p;
+        __syncthreads();
+        if (tid == 0) {
+            int te = 0, tk = 0;
+            for (int w = 0; w < NW; ++w) {
+                te += wsum[w];
+                tk += wsum[NW + w];
+            }
+            s_tbase += te;
+            s_base += tk;
+        }
+        __syncthreads();
+    }
+    if (tid == 0) wcnt[j] = s_base;
+}
+
+// Compact copies of the witnesses: slot j W + i holds item wpos[j W + i] (i <
+// wcnt[j]): its bfloat16 row (dp values), codes (cw words) and key.  One wave
+// per slot.
+__global__ __launch_bounds__(256) void k_wit_gather(const uint16_t *__restrict__ Xh,
+                                                    const uint32_t *__restrict__ codes_l,
+                                                    const double *__restrict__ key_l, int dp, int cw,
+                                                    const int32_t *__restrict__ wpos,
+                                                    const int32_t *__restrict__ wcnt, int W, int64_t slots,
+                                                    uint16_t *__restrict__ xw, uint32_t *__restrict__ cwo,
+                                                    double *__restrict__ kw)
+{
+    const int64_t slot = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (slot >= slots) return;
+    const int64_t j = slot / W, i = slot - j * W;
+    if (i >= wcnt[j]) return;
+    const int64_t pos = wpos[slot];
+    for (int t = lane; t < dp; t += 64) xw[slot * dp + t] = Xh[pos * dp + t];
+    if (lane < cw) cwo[slot * cw + lane] = codes_l[pos * cw + lane];
+    if (lane == 0) kw[slot] = key_l[pos];
+}
+
+// P* of each query in the witnesses' numbering: the tie bucket's sub-dataset
+// j* keeps its witnesses in stored order, so "stored position <= P*" becomes
+// "slot <= j* W + (witnesses of j* at or before P*) - 1" (INT_MAX, the whole
+// bucket, stays).
+__global__ __launch_bounds__(256) void k_wit_pstar(const int32_t *__restrict__ gtie,
+                                                   const int32_t *__restrict__ gpstar,
+                                                   const int32_t *__restrict__ wpos,
+                                                   const int32_t *__restrict__ wcnt, int W, int64_t nq,
+                                                   int32_t *__restrict__ pw)
+{
+    const int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (q >= nq) return;
+    const int32_t js = gtie[(q >> 6) * 4 * 64 + (q & 63)];
+    const int32_t ps = gpstar[q];
+    if (js < 0 || ps == INT_MAX) {
+        pw[q] = ps;
+        return;
+    }
+    const int32_t *w = wpos + (int64_t)js * W;
+    int lo = 0, hi = wcnt[js];  // first witness after P*
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (w[mid] <= ps) lo = mid + 1;
+        else hi = mid;
+    }
+    pw[q] = js * W + lo - 1;
+}
+
+hipError_t launch_wit_build(const uint16_t *Xh, const uint32_t *codes_l, const double *key_l, const int32_t *off,
+                            int m, int dp, int cw, int top, int stride, int W, int32_t *wpos, int32_t *wcnt,
+                            uint16_t *xw, uint32_t *cwo, double *kw, hipStream_t s)
+{
+    if (m < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_wit_select, dim3((unsigned)m), dim3(WIT_THREADS), 0, s, key_l, off, top, stride, W, wpos,
+                       wcnt);
+    const int64_t slots = (int64_t)m * W;
+    hipLaunchKernelGGL(k_wit_gather, dim3(ceil_div(slots, 4)), dim3(256), 0, s, Xh, codes_l, key_l, dp, cw, wpos,
+                       wcnt, W, slots, xw, cwo, kw);
+    return hipGetLastError();
+}
+
+hipError_t launch_wit_pstar(const int32_t *gtie, const int32_t *gpstar, const int32_t *wpos, const int32_t *wcnt,
+                            int W, int64_t nq, int32_t *pw, hipStream_t s)
+{
+    if (nq < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_wit_pstar, dim3(ceil_div(nq, 256)), dim3(256), 0, s, gtie, gpstar, wpos, wcnt, W, nq, pw);
+    return hipGetLastError();
+}
+
 hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
                             int32_t *gpstar, hipStream_t s)
 {

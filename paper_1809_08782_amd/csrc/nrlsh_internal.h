@@ -223,6 +223,18 @@ hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, in
                                  int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s);
 // rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
+// Witnesses of the dense head: per sub-dataset j the stored positions, in
+// stored order, of its `top` largest keys and of every `stride`-th item
+// (wpos[j W ..], wcnt[j] of them; W >= top + ceil(n_j / stride)), and compact
+// copies of their bfloat16 rows (xw, m W x dp), codes (cwo, m W x cw words)
+// and keys (kw).
+hipError_t launch_wit_build(const uint16_t *Xh, const uint32_t *codes_l, const double *key_l, const int32_t *off,
+                            int m, int dp, int cw, int top, int stride, int W, int32_t *wpos, int32_t *wcnt,
+                            uint16_t *xw, uint32_t *cwo, double *kw, hipStream_t s);
+// pw[q] = gpstar[q] in the witnesses' slot numbering (gtie names the tie
+// bucket's sub-dataset).
+hipError_t launch_wit_pstar(const int32_t *gtie, const int32_t *gpstar, const int32_t *wpos, const int32_t *wcnt,
+                            int W, int64_t nq, int32_t *pw, hipStream_t s);
 // Permutation of a batch by its guessed cuts rho (ascending; keys of nbits
 // bits), through a radix sort in the given buffers (nq each; tmp:
 // radix_sort_tmp_bytes(nq)); *order points into va or vb.

@@ -113,15 +113,18 @@ def test_dense_head_matches_oracle():
     assert items[1] >= items[0] >= items[64] and items[1] > 0, items
 
 
-def test_dense_head_tied_buckets():
+@pytest.mark.parametrize("m", [6, 2])
+def test_dense_head_tied_buckets(m):
     """Dense head over every sub-dataset with threshold buckets holding long
-    runs of equal codes, cut by stored position inside the screened range."""
-    say("case dense head ties")
+    runs of equal codes, cut by stored position inside the screened range;
+    with m = 2 each sub-dataset holds more items than its witnesses, whose
+    selection by norm then meets long runs of equal keys."""
+    say(f"case dense head ties m={m}")
     base = make_items("lognormal", 900, 16, seed=97, sigma=0.7)
     X = np.ascontiguousarray(np.repeat(base, 14, axis=0)[:12000])
     Q = make_queries(80, 16, seed=98)
-    oix = orc.OracleIndex(X, 6, 24, seed=21, threads=8)
-    with nr.nrlsh_build(X, 6, 24, 21) as gix:
+    oix = orc.OracleIndex(X, m, 24, seed=21, threads=8)
+    with nr.nrlsh_build(X, m, 24, 21) as gix:
         for T, g in ((1500, 20), (4000, 18), (7000, 24)):
             ids, ips = nr.nrlsh_query(gix, Q, 12, T, rerank="gather", rerank_storage="bf16", scan_guess=g,
                                       dense_head=1)
