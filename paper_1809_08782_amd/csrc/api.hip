@@ -1135,7 +1135,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_sqc = blk.reserve<uint32_t>(sortq ? (size_t)B * sh.qsets * sh.W : 1),
                  o_srh = blk.reserve<int32_t>(sortq ? (size_t)B : 1),
                  o_sid = blk.reserve<int64_t>(sortq ? (size_t)B * k : 1),
-                 o_sip = blk.reserve<float>(sortq ? (size_t)B * k : 1);
+                 o_sip = blk.reserve<float>(sortq ? (size_t)B * k : 1),
+                 o_lst = blk.reserve<unsigned long long>(3);
     blk.allocate(s);
     DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
     DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
@@ -1148,6 +1149,9 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<float> sQ = blk.view<float>(o_sqp), sips = blk.view<float>(o_sip);
     DBuf<uint32_t> sqc = blk.view<uint32_t>(o_sqc);
     DBuf<int64_t> sids = blk.view<int64_t>(o_sid);
+    // kept-list totals of the batches whose check is left to the device
+    DBuf<unsigned long long> lstats = blk.view<unsigned long long>(o_lst);
+    if (collect && bf16_rows) HIPX(hipMemsetAsync(lstats.get(), 0, 3 * sizeof(unsigned long long), s));
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
                   gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
@@ -1180,30 +1184,52 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     // host round trip per call) and sets up its buffers.
     auto decide_head = [&](int64_t nb) {
         head_decided = true;
-        HIPX(launch_sub_hits(ghist.get(), ix->R.get(), grho.get(), nb, sh.m, sh.L, subhits.get(), s));
-        const int ns = sub_hits_slices(nb);
-        const size_t words = (size_t)sh.m * ns;
-        size_t pb = 0;
-        auto *part = static_cast<unsigned long long *>(pinned_take(words * sizeof(unsigned long long), &pb));
-        HIPX(hipMemcpyAsync(part, subhits.get(), words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
-        HIPX(hipStreamSynchronize(s));
-        std::vector<unsigned long long> hits((size_t)sh.m, 0ull);
-        for (int j = 0; j < sh.m; ++j)
-            for (int t = 0; t < ns; ++t) hits[(size_t)j] += part[(size_t)j * ns + t];
-        pinned_give(part, pb, s, ix->device);
-        hr = dense_head_range(ix, hits.data(), nb, gstride, head_frac);
+        bool cached = false;
+        {
+            std::lock_guard<std::mutex> g(ix->head_mu);
+            if (ix->head_hint_valid && ix->head_hint_k == k && ix->head_hint_T == sh.Tq &&
+                ix->head_hint_frac == head_frac) {
+                hr = {ix->head_hint_j0, ix->head_hint_j1};
+                head_lp_split = ix->head_hint_split;
+                cached = true;
+            }
+        }
+        if (!cached) {
+            HIPX(launch_sub_hits(ghist.get(), ix->R.get(), grho.get(), nb, sh.m, sh.L, subhits.get(), s));
+            const int ns = sub_hits_slices(nb);
+            const size_t words = (size_t)sh.m * ns;
+            size_t pb = 0;
+            auto *part = static_cast<unsigned long long *>(pinned_take(words * sizeof(unsigned long long), &pb));
+            HIPX(hipMemcpyAsync(part, subhits.get(), words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            std::vector<unsigned long long> hits((size_t)sh.m, 0ull);
+            for (int j = 0; j < sh.m; ++j)
+                for (int t = 0; t < ns; ++t) hits[(size_t)j] += part[(size_t)j * ns + t];
+            pinned_give(part, pb, s, ix->device);
+            hr = dense_head_range(ix, hits.data(), nb, gstride, head_frac);
+            if (hr.second > hr.first) {
+                // the probed items left to the gather, per query (the sample
+                // counts items ranked before the guess, guess16 / 16 Tq of them):
+                // slices of about 320 items keep the machine busy on these short
+                // lists (large workload, 4,984 items per query: 1.05 ms per call
+                // in 2 slices, 0.71 in 16)
+                double rest = 0.0;
+                for (int j = 0; j < sh.m; ++j)
+                    if (j < hr.first || j >= hr.second) rest += (double)hits[(size_t)j];
+                rest *= (double)gstride / (double)nb * 16.0 / (double)guess16;
+                head_lp_split = (int)std::min<double>(16.0, std::max<double>(1.0, std::ceil(rest / 320.0)));
+            }
+            std::lock_guard<std::mutex> g(ix->head_mu);
+            ix->head_hint_valid = true;
+            ix->head_hint_k = k;
+            ix->head_hint_T = sh.Tq;
+            ix->head_hint_frac = head_frac;
+            ix->head_hint_j0 = hr.first;
+            ix->head_hint_j1 = hr.second;
+            ix->head_hint_split = head_lp_split;
+        }
         head_any = hr.second > hr.first;
         if (!head_any) return;
-        // the probed items left to the gather, per query (the sample counts
-        // items ranked before the guess, guess16 / 16 Tq of them): slices of
-        // about 320 items keep the machine busy on these short lists (large
-        // workload, 4,984 items per query: 1.05 ms per call in 2 slices, 0.71
-        // in 16)
-        double rest = 0.0;
-        for (int j = 0; j < sh.m; ++j)
-            if (j < hr.first || j >= hr.second) rest += (double)hits[(size_t)j];
-        rest *= (double)gstride / (double)nb * 16.0 / (double)guess16;
-        head_lp_split = (int)std::min<double>(16.0, std::max<double>(1.0, std::ceil(rest / 320.0)));
         // theta_q comes from witnesses in every sub-dataset of the head (a
         // sub-dataset normalised by an outlying U_j hashes almost all of its
         // items alike, so that a query probes nearly all of them or nearly
@@ -1243,7 +1269,9 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     };
     // one batch; returns false when it has to run again without the dense
     // head (its lists overflowed)
-    auto run_batch = [&](int64_t b0, int64_t bi, bool staged, bool head) -> bool {
+    // defer: the collecting path's batches leave the kept lists' overflow
+    // check to the device (a failure bit read once at the end of the call)
+    auto run_batch = [&](int64_t b0, int64_t bi, bool staged, bool head, bool defer) -> bool {
         bool hd = head && head_ok && !staged && lp_on;
         int jh0 = 0, jh1 = 0;
         const int64_t nb = std::min<int64_t>(B, nq - b0);
@@ -1380,6 +1408,23 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                   lcount.get(), lists.get(),
                                   gtheta.get(), s));
             tm.end();
+            if (defer && collect && !staged) {
+                // the exact re-rank reads at most lcap entries per list; a batch
+                // with a longer list is run again at the end of the call
+                HIPX(launch_list_check(lcount.get(), hd ? ccount.get() : nullptr, nb, (int)lcap, sh.Tq, lstats.get(),
+                                       gfail.get() + bi, s));
+                QueryShape shl = sh;
+                shl.Tq = lcap;  // list stride; lengths come from lcount
+                const int ns = std::min(rerank_splits(nb, lcap), lsplit);
+                tm.begin("rerank_exact");
+                HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qx, nb, shl, lists.get(), lcount.get(), ns,
+                                   lpart_v.get(), lpart_i.get(), ox_ids, ox_ips, s));
+                tm.end();
+                if (qord)
+                    HIPX(launch_unpermute_results(qord, nb, k, ox_ids, ox_ips, ids_d + b0 * k, ips_d + b0 * k, s));
+                if (hd) g_qstats.dense_head_items = ix->off_h[(size_t)jh1] - ix->off_h[(size_t)jh0];
+                return true;
+            }
             HIPX(hipMemcpyAsync(hl.data(), lcount.get(), (size_t)nb * sizeof(int32_t),
                                 hipMemcpyDeviceToHost, s));
             if (hd)
@@ -1423,17 +1468,31 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         return true;
     };
     for (int64_t b0 = 0, bi = 0; b0 < nq; b0 += B, ++bi)
-        if (!run_batch(b0, bi, false, true)) run_batch(b0, bi, false, false);
+        if (!run_batch(b0, bi, false, true, true)) run_batch(b0, bi, false, false, false);
     if (collect) {
-        // batches whose collection was incomplete are probed again with the two passes
+        // batches whose collection was incomplete (bit 1) are probed again with
+        // the two passes; batches whose kept lists overflowed (bit 2) run
+        // again without them, from the FP32 rows
         std::vector<uint32_t> fl((size_t)nbatches);
+        unsigned long long ls[3] = {0, 0, 0};
         HIPX(hipMemcpyAsync(fl.data(), gfail.get(), fl.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        if (bf16_rows) HIPX(hipMemcpyAsync(ls, lstats.get(), sizeof ls, hipMemcpyDeviceToHost, s));
         HIPX(hipStreamSynchronize(s));
-        for (int64_t bi = 0; bi < nbatches; ++bi)
-            if (fl[(size_t)bi]) {
+        g_qstats.lp_kept_total += (int64_t)ls[0];
+        g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, (int64_t)ls[1]);
+        g_qstats.lp_gathered_total += (int64_t)ls[2];
+        for (int64_t bi = 0; bi < nbatches; ++bi) {
+            const uint32_t f = fl[(size_t)bi];
+            if (f & 1u) {
                 g_qstats.collect_fallbacks += 1;
-                run_batch(bi * B, bi, true, false);
+                run_batch(bi * B, bi, true, false, false);
+            } else if (f & 2u) {
+                g_qstats.lp_fallbacks += 1;
+                lp_on = false;
+                ix->lp_overflow.store(((uint64_t)k << 32) | (uint64_t)sh.Tq, std::memory_order_relaxed);
+                run_batch(bi * B, bi, false, false, false);
             }
+        }
     }
     if (table) {
         unsigned long long c[3] = {0, 0, 0};

@@ -254,6 +254,14 @@ struct nrlsh_index {
     mutable nrlsh::host::DBuf<uint16_t> wit_xh;
     mutable nrlsh::host::DBuf<uint32_t> wit_codes;
     mutable nrlsh::host::DBuf<double> wit_key;
+    // the dense head chosen from the sample of the last call that measured
+    // one, reused by later calls with the same k, budget and fraction (a speed
+    // hint only; results never depend on it)
+    mutable std::mutex head_mu;
+    mutable bool head_hint_valid = false;
+    mutable int32_t head_hint_k = 0, head_hint_j0 = 0, head_hint_j1 = 0, head_hint_split = 1;
+    mutable int64_t head_hint_T = 0;
+    mutable double head_hint_frac = 0.0;
     nrlsh::host::DBuf<uint8_t> Xf8;                   // FP8 E4M3 hash copy (precision form)
     nrlsh::host::DBuf<float> xscale;                  // its row scales
     nrlsh::host::DBuf<double> key, key_l, keymax, U;  // key: original order; key_l: stored order

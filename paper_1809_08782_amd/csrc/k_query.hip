@@ -2710,6 +2710,59 @@ hipError_t launch_wit_pstar(const int32_t *gtie, const int32_t *gpstar, const in
     return hipGetLastError();
 }
 
+// A batch's kept lists against their room, on the device: the total and the
+// largest of lcount and the total of the gathered counts (gcount, or gdef
+// per query without it) are added to stats[0..2] (stats[1] by maximum), and
+// bit 2 of *fail is set when a list outgrew lcap (the call then runs the
+// batch again without the lists).  One block.
+__global__ __launch_bounds__(1024) void k_list_check(const int32_t *__restrict__ lcount,
+                                                     const int32_t *__restrict__ gcount, int64_t nb, int lcap,
+                                                     int64_t gdef, unsigned long long *__restrict__ stats,
+                                                     uint32_t *__restrict__ fail)
+{
+    __shared__ unsigned long long s_tot[16], s_mx[16], s_g[16];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    unsigned long long tot = 0, mx = 0, g = 0;
+    for (int64_t q = tid; q < nb; q += 1024) {
+        const unsigned long long c = (unsigned long long)max(lcount[q], 0);
+        tot += c;
+        mx = c > mx ? c : mx;
+        g += gcount ? (unsigned long long)max(gcount[q], 0) : (unsigned long long)gdef;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        tot += __shfl_xor(tot, o, 64);
+        const unsigned long long om = __shfl_xor(mx, o, 64);
+        mx = om > mx ? om : mx;
+        g += __shfl_xor(g, o, 64);
+    }
+    if (lane == 0) {
+        s_tot[wv] = tot;
+        s_mx[wv] = mx;
+        s_g[wv] = g;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int w = 1; w < 16; ++w) {
+            tot += s_tot[w];
+            mx = s_mx[w] > mx ? s_mx[w] : mx;
+            g += s_g[w];
+        }
+        atomicAdd(&stats[0], tot);
+        atomicMax(&stats[1], mx);
+        atomicAdd(&stats[2], g);
+        if (mx > (unsigned long long)lcap) atomicOr(fail, 2u);
+    }
+}
+
+hipError_t launch_list_check(const int32_t *lcount, const int32_t *gcount, int64_t nb, int lcap, int64_t gdef,
+                             unsigned long long *stats, uint32_t *fail, hipStream_t s)
+{
+    if (nb < 1) return hipSuccess;
+    hipLaunchKernelGGL(k_list_check, dim3(1), dim3(1024), 0, s, lcount, gcount, nb, lcap, gdef, stats, fail);
+    return hipGetLastError();
+}
+
 hipError_t launch_probe_all(int64_t nq, const QueryShape &sh, int32_t *ghthr, int32_t *gtie,
                             int32_t *gpstar, hipStream_t s)
 {

@@ -223,6 +223,11 @@ hipError_t launch_collect_filter(const uint64_t *keys, const int32_t *counts, in
                                  int32_t *cand, int32_t *lcount, uint32_t *fail, hipStream_t s);
 // rho[q] = (threshold bucket of gtie) + 1, at most P: the guessed cut.
 hipError_t launch_rho_from_tie(const int32_t *gtie, int64_t nq, int32_t P, int32_t *rho, hipStream_t s);
+// stats[0] += sum lcount, stats[1] = max(stats[1], max lcount), stats[2] +=
+// sum gcount (gdef per query when gcount is NULL); *fail |= 2 when some
+// lcount exceeds lcap.
+hipError_t launch_list_check(const int32_t *lcount, const int32_t *gcount, int64_t nb, int lcap, int64_t gdef,
+                             unsigned long long *stats, uint32_t *fail, hipStream_t s);
 // Witnesses of the dense head: per sub-dataset j the stored positions, in
 // stored order, of its `top` largest keys and of every `stride`-th item
 // (wpos[j W ..], wcnt[j] of them; W >= top + ceil(n_j / stride)), and compact
