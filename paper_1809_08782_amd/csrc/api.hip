@@ -1415,7 +1415,9 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                        gfail.get() + bi, s));
                 QueryShape shl = sh;
                 shl.Tq = lcap;  // list stride; lengths come from lcount
-                const int ns = std::min(rerank_splits(nb, lcap), lsplit);
+                // kept lists are short (hundreds of items): with 2048 queries or
+                // more one wave per query fills the machine, and no merge runs
+                const int ns = nb >= 2048 ? 1 : std::min(rerank_splits(nb, lcap), lsplit);
                 tm.begin("rerank_exact");
                 HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qx, nb, shl, lists.get(), lcount.get(), ns,
                                    lpart_v.get(), lpart_i.get(), ox_ids, ox_ips, s));
@@ -1443,7 +1445,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                 g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, mx);
                 QueryShape shl = sh;
                 shl.Tq = lcap;  // list stride; lengths come from lcount
-                const int ns = std::min(rerank_splits(nb, lcap), lsplit);
+                const int ns = nb >= 2048 ? 1 : std::min(rerank_splits(nb, lcap), lsplit);
                 tm.begin("rerank_exact");
                 HIPX(launch_rerank(ix->Xl.get(), ix->perm.get(), Qx, nb, shl, lists.get(),
                                    lcount.get(), ns, lpart_v.get(), lpart_i.get(), ox_ids, ox_ips, s));
