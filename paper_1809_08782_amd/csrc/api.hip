@@ -1346,7 +1346,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             // (the dense head's screen reads every sub-dataset's level bound)
             tm.begin("threshold");
             HIPX(launch_threshold(ghist.get(), ix->R.get(), ix->inv.get(), nb, sh, gbase.get(), ghthr.get(),
-                                  gtie.get(), s, hd));
+                                  gtie.get(), s, hd, false));
             tm.end();
             tm.begin("tie_locate");
             HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qx, nb, sh.W, sh.qsets, gtie.get(),

@@ -158,7 +158,9 @@ __device__ __forceinline__ int wave_max_int(int v)
     return v;
 }
 
-template <bool BOUNDS>
+// MODE 0: the threshold bucket and its cut only; 1: also the per-sub-dataset
+// level bounds ghthr; 2: also the emission offsets gbase (the two-pass scan).
+template <int MODE>
 __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__restrict__ ghist,
                                                              const int32_t *__restrict__ R,
                                                              const int32_t *__restrict__ inv, int64_t nq,
@@ -234,7 +236,7 @@ __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__r
     // items belong to no bucket, as under single probe): every bucket is
     // probed whole
     if (valid && bstar < 0) bstar = (int32_t)P;
-    if (!BOUNDS) {  // the threshold bucket and its cut only
+    if (MODE == 0) {  // the threshold bucket and its cut only
         if (wave == 0) {
             int32_t *tie = gtie + (int64_t)tile * 4 * 64;
             tie[0 * 64 + lane] = valid ? jstar : -1;
@@ -256,6 +258,8 @@ __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__r
             else hi = mid;
         }
         const int hthr = lo - 1;
+        ghthr[((int64_t)tile * m + j) * 64 + lane] = hthr;
+        if (MODE < 2) continue;
         const int hmax = wave_max_int(hthr);
         const uint32_t *Hj = H + (int64_t)j * L1 * 64;
         int64_t cnt = 0;
@@ -265,19 +269,20 @@ __global__ __launch_bounds__(TH_WAVES * 64) void k_threshold(const uint32_t *__r
         }
         if (j == jstar) cnt += rstar;
         gbase[((int64_t)tile * (m + 1) + j) * 64 + lane] = (int32_t)run;  // offset inside this wave's range
-        ghthr[((int64_t)tile * m + j) * 64 + lane] = hthr;
         run += cnt;
     }
-    __syncthreads();  // every wave is done with seg_s
-    seg_s[wave][lane] = run;
-    __syncthreads();
-    int64_t offs = 0;
-    for (int w = 0; w < wave; ++w) offs += seg_s[w][lane];
-    for (int j = ja; j < jb; ++j) {
-        int32_t *g = gbase + ((int64_t)tile * (m + 1) + j) * 64 + lane;
-        *g = (int32_t)(*g + offs);  // this lane wrote *g above
+    if (MODE == 2) {
+        __syncthreads();  // every wave is done with seg_s
+        seg_s[wave][lane] = run;
+        __syncthreads();
+        int64_t offs = 0;
+        for (int w = 0; w < wave; ++w) offs += seg_s[w][lane];
+        for (int j = ja; j < jb; ++j) {
+            int32_t *g = gbase + ((int64_t)tile * (m + 1) + j) * 64 + lane;
+            *g = (int32_t)(*g + offs);  // this lane wrote *g above
+        }
+        if (wave == TH_WAVES - 1) gbase[((int64_t)tile * (m + 1) + m) * 64 + lane] = (int32_t)(offs + run);
     }
-    if (wave == TH_WAVES - 1) gbase[((int64_t)tile * (m + 1) + m) * 64 + lane] = (int32_t)(offs + run);
     if (wave == 0) {
         int32_t *tie = gtie + (int64_t)tile * 4 * 64;
         tie[0 * 64 + lane] = valid ? jstar : -1;
@@ -2077,26 +2082,6 @@ __global__ __launch_bounds__(256, W == 0 ? 3 : 2) void k_screen1(NRLSH_SCREEN_PA
 // exact inner product: k distinct items reach it), lowered by 2^-22 relative
 // to cover float rounding; -inf when fewer than k groups hold probed items.
 // One wave per query.
-template <int S>
-__global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int stride, int ncol,
-                                              int k, float *__restrict__ theta)
-{
-    const int lane = threadIdx.x;
-    const int64_t q = blockIdx.x;
-    WaveTopK<S> top;
-    top.init(k);
-    for (int c0 = 0; c0 < ncol; c0 += 64) {
-        const int c = c0 + lane;
-        const float v = c < ncol ? cmax[q * stride + c] : -INFINITY;
-        top.offer((double)v, c, c < ncol && v > -INFINITY, lane);
-    }
-    const double kth = __shfl(top.tv[top.ks], top.kl, 64);
-    if (lane == 0) {
-        const float f = (float)kth;
-        theta[q] = kth == -INFINITY ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
-    }
-}
-
 // Order-preserving 32-bit key of a float group maximum; 0 for -inf and NaN
 // (no probed item), below every finite value's key.
 __device__ __forceinline__ uint32_t theta_key(float v)
@@ -2108,63 +2093,70 @@ __device__ __forceinline__ float theta_value(uint32_t key)
 {
     return __uint_as_float((key & 0x80000000u) ? (key & 0x7FFFFFFFu) : ~key);
 }
-// The k-th largest of the 64 lanes' keys (k <= 64), bit by bit from the top:
-// the largest c with at least k lanes at or above it (0 when fewer than k
-// lanes hold a key >= 1).
-__device__ __forceinline__ uint32_t wave_kth_key(uint32_t key, int k)
+// theta_q: the k-th largest of a query's ncol group maxima (each the largest
+// lower bound among a group's probed items, so that k distinct items reach
+// the k-th largest), lowered for rounding.  A radix selection
+// on the order-preserving keys (-inf and NaN as 0, so that fewer than k
+// finite maxima give -inf): four 8-bit passes, each counting the keys that
+// share the digits found so far in a 256-bin LDS histogram and keeping the
+// bin where the count from the top reaches k.  One wave per query.
+__global__ __launch_bounds__(64) void k_theta(const float *__restrict__ cmax, int stride, int ncol, int k,
+                                              float *__restrict__ theta)
 {
-    uint32_t ans = 0;
-    for (int b = 31; b >= 0; --b) {
-        const uint32_t c = ans | (1u << b);
-        if (__popcll(__ballot(key >= c)) >= k) ans = c;
-    }
-    return ans;
-}
-
-// theta_q for k <= 64 (the same value as k_theta): the k-th largest lane
-// maximum is a floor that k distinct groups reach; usually few groups lie at
-// or above it, and those are gathered into one key per lane for an exact
-// select.  More than 64 of them (ties, or most values in one lane) fall back
-// to the insertion top-k above the floor.
-__global__ __launch_bounds__(64) void k_theta_small(const float *__restrict__ cmax, int stride, int ncol,
-                                                    int k, float *__restrict__ theta)
-{
-    __shared__ uint32_t cand[64];
+    __shared__ uint32_t hist[256];
     const int lane = threadIdx.x;
     const int64_t q = blockIdx.x;
     const float *row = cmax + q * stride;
-    float lm = -INFINITY;
-    for (int c = lane; c < ncol; c += 64) lm = fmaxf(lm, row[c]);
-    uint32_t floor_key = wave_kth_key(theta_key(lm), k);
-    if (floor_key == 0u) floor_key = 1u;  // fewer than k lanes hold a group: every group is a candidate
-    int n = 0;
-    for (int c0 = 0; c0 < ncol; c0 += 64) {
-        const int c = c0 + lane;
-        const bool ok = c < ncol && theta_key(row[c]) >= floor_key;
-        const uint64_t m = __ballot(ok);
-        const int pos = n + __popcll(m & ((1ull << lane) - 1ull));
-        if (ok && pos < 64) cand[pos] = theta_key(row[c]);
-        n += __popcll(m);
-    }
-    __syncthreads();
-    uint32_t kth = 0;
-    if (n <= 64) {
-        kth = wave_kth_key(lane < n ? cand[lane] : 0u, k);
-    } else {
-        WaveTopK<1> top;
-        top.init(k);
-        const double fl = floor_key > 1u ? (double)theta_value(floor_key) : -INFINITY;
-        for (int c0 = 0; c0 < ncol; c0 += 64) {
-            const int c = c0 + lane;
-            const float v = c < ncol ? row[c] : -INFINITY;
-            top.offer((double)v, c, c < ncol && v > -INFINITY, lane, fl);
+    uint32_t prefix = 0u, mask = 0u;
+    uint32_t need = (uint32_t)k;
+    bool found = true;
+    for (int shift = 24; shift >= 0 && found; shift -= 8) {
+        for (int b = lane; b < 256; b += 64) hist[b] = 0u;
+        __syncthreads();
+        for (int c = lane; c < ncol; c += 64) {
+            const uint32_t key = theta_key(row[c]);
+            if ((key & mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
         }
-        const double kv = __shfl(top.tv[top.ks], top.kl, 64);
-        kth = kv == -INFINITY ? 0u : theta_key((float)kv);
+        __syncthreads();
+        // lane l holds bins 4 l .. 4 l + 3; `above` = keys in the bins above them
+        uint32_t h[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h[i] = hist[4 * lane + i];
+        const uint32_t part = h[0] + h[1] + h[2] + h[3];
+        uint32_t incl = part;  // parts of lanes >= this one
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t y = __shfl_down(incl, o, 64);
+            if (lane + o < 64) incl += y;
+        }
+        const uint32_t above = incl - part;
+        int sel = -1;
+        uint32_t rest = 0u;
+        if (above < need && need <= above + part) {
+            uint32_t c = above;
+            for (int i = 3; i >= 0; --i) {
+                if (c + h[i] >= need) {
+                    sel = 4 * lane + i;
+                    rest = need - c;
+                    break;
+                }
+                c += h[i];
+            }
+        }
+        const uint64_t who = __ballot(sel >= 0);
+        found = who != 0ull;
+        if (found) {
+            const int src = __ffsll((long long)who) - 1;
+            sel = __shfl(sel, src, 64);
+            need = __shfl(rest, src, 64);
+            prefix |= (uint32_t)sel << shift;
+            mask |= 0xFFu << shift;
+        }
+        __syncthreads();
     }
     if (lane == 0) {
-        const float f = theta_value(kth);
-        theta[q] = kth == 0u ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
+        const float f = theta_value(prefix);
+        theta[q] = (!found || prefix == 0u) ? -INFINITY : f - fabsf(f) * 0x1p-22f - 0x1p-126f;
     }
 }
 
@@ -2244,14 +2236,17 @@ hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const u
 
 hipError_t launch_threshold(const uint32_t *ghist, const int32_t *R, const int32_t *inv, int64_t nq,
                             const QueryShape &sh, int32_t *gbase, int32_t *ghthr, int32_t *gtie,
-                            hipStream_t s, bool bounds)
+                            hipStream_t s, bool bounds, bool offsets)
 {
-    if (bounds)
-        hipLaunchKernelGGL(k_threshold<true>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv,
-                           nq, sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
+    if (bounds && offsets)
+        hipLaunchKernelGGL(k_threshold<2>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv, nq,
+                           sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
+    else if (bounds)
+        hipLaunchKernelGGL(k_threshold<1>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv, nq,
+                           sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
     else
-        hipLaunchKernelGGL(k_threshold<false>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv,
-                           nq, sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
+        hipLaunchKernelGGL(k_threshold<0>, dim3(ceil_div(nq, 64)), dim3(TH_WAVES * 64), 0, s, ghist, R, inv, nq,
+                           sh.m, sh.L, sh.Tq, gbase, ghthr, gtie);
     return hipGetLastError();
 }
 
@@ -2930,13 +2925,7 @@ static hipError_t launch_screen_t(const float *Xl, const uint16_t *Xh, const uin
 static void launch_theta(const float *cmax, int stride, int ncol, int64_t nq, int k, float *theta,
                          hipStream_t s)
 {
-    const int S = (k + 63) / 64;
-    const dim3 grid((unsigned)nq), block(64);
-    if (S <= 1) hipLaunchKernelGGL(k_theta_small, grid, block, 0, s, cmax, stride, ncol, k, theta);
-    else if (S <= 2) hipLaunchKernelGGL(k_theta<2>, grid, block, 0, s, cmax, stride, ncol, k, theta);
-    else if (S <= 4) hipLaunchKernelGGL(k_theta<4>, grid, block, 0, s, cmax, stride, ncol, k, theta);
-    else if (S <= 8) hipLaunchKernelGGL(k_theta<8>, grid, block, 0, s, cmax, stride, ncol, k, theta);
-    else hipLaunchKernelGGL(k_theta<16>, grid, block, 0, s, cmax, stride, ncol, k, theta);
+    hipLaunchKernelGGL(k_theta, dim3((unsigned)nq), dim3(64), 0, s, cmax, stride, ncol, k, theta);
 }
 
 hipError_t launch_screen_max(const float *Xl, const uint16_t *Xh, const uint16_t *Xlo,

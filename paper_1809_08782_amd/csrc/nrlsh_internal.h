@@ -140,10 +140,11 @@ hipError_t launch_scan_hist(const uint32_t *codes_l, const int32_t *off, const u
                             int64_t nq, const QueryShape &sh, uint32_t *ghist, hipStream_t s);
 
 // Threshold bucket, tie cut and per-sub-dataset emission bounds and offsets
-// (bounds = false: gtie only; gbase and ghthr are left as they are).
+// (bounds = false: gtie only; gbase and ghthr are left as they are; offsets =
+// false: gbase is left as it is).
 hipError_t launch_threshold(const uint32_t *ghist, const int32_t *R, const int32_t *inv, int64_t nq,
                             const QueryShape &sh, int32_t *gbase, int32_t *ghthr, int32_t *gtie,
-                            hipStream_t s, bool bounds = true);
+                            hipStream_t s, bool bounds = true, bool offsets = true);
 
 // Pass 2: emit the probed items (stored positions) of every query.
 hipError_t launch_scan_emit(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
