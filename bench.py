@@ -572,12 +572,13 @@ def kernel_roof(nm, kern, w, Tq, qb, qstats):
         return d
 
     if nm in ("rerank", "rerank_lp", "rerank_exact"):
-        # per re-ranked item: its row (4d FP32 / 2d bf16 bytes), its stored
-        # position and original id (8); the bf16 pass also reads the row's
-        # error bound (4).  The FP32 pass reads every probed item, the bf16
-        # pass every gathered one (all probed items less those of a dense
-        # head), the exact pass after it the kept ones.
-        row = 2 * w.d + 4 if nm == "rerank_lp" else 4 * w.d
+        # per re-ranked item: its row (4d FP32 / 2d bf16 bytes) and stored
+        # position (4); the FP32 passes also read its original id (4), the
+        # bf16 pass the row's error bound (4) instead (its top-k of lower
+        # bounds needs no ids).  The FP32 pass reads every probed item, the
+        # bf16 pass every gathered one (all probed items less those of a
+        # dense head), the exact pass after it the kept ones.
+        row = 2 * w.d if nm == "rerank_lp" else 4 * w.d
         if nm == "rerank":
             items = nq_launch * Tq
         elif nm == "rerank_lp":
@@ -609,8 +610,9 @@ def kernel_roof(nm, kern, w, Tq, qb, qstats):
                              "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair}, kname)
     if nm == "head_screen":
         # the keep pass of the dense head: one bf16 product (2d flops) per
-        # (query, item) pair of the screened sub-datasets
-        pairs = nq_launch * (qstats.get("dense_head_items") or 0)
+        # (query, item) pair it evaluates (tiles skip the chunks none of their
+        # queries probes), per query of the last call x queries per launch
+        pairs = (qstats.get("dense_head_pairs") or 0) / max(1, last_nq) * nq_launch
         flops = 2.0 * w.d * pairs
         achieved = flops / (per["avg_ms"] * 1e-3) / 1e12
         kname = "k_screen1<%d>" % W

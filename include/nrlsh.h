@@ -507,6 +507,9 @@ typedef struct nrlsh_query_stats {
     int64_t lp_gathered_total; /* BF16 re-rank: probed items whose bfloat16 rows were
                               gathered (all of them, less those of a dense head), all
                               queries */
+    int64_t dense_head_pairs; /* BF16 re-rank: (query, item) pairs the dense head's keep
+                              pass evaluated (64-query tiles skip the chunks of a
+                              sub-dataset none of their queries probes), all queries */
 } nrlsh_query_stats;
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st);

@@ -68,7 +68,7 @@ class QueryStats(C.Structure):
                 ("table_lookups", C.c_int64), ("table_walked", C.c_int64),
                 ("table_passes", C.c_int64), ("screen_pairs", C.c_int64), ("scan_pairs", C.c_int64),
                 ("collect_fallbacks", C.c_int64), ("dense_head_items", C.c_int64),
-                ("lp_gathered_total", C.c_int64)]
+                ("lp_gathered_total", C.c_int64), ("dense_head_pairs", C.c_int64)]
 
 
 class QueryDesc(C.Structure):
@@ -575,7 +575,8 @@ def nrlsh_get_query_stats() -> dict:
             "table_lookups": st.table_lookups, "table_walked": st.table_walked,
             "table_passes": st.table_passes, "screen_pairs": st.screen_pairs,
             "scan_pairs": st.scan_pairs, "collect_fallbacks": st.collect_fallbacks,
-            "dense_head_items": st.dense_head_items, "lp_gathered_total": st.lp_gathered_total}
+            "dense_head_items": st.dense_head_items, "lp_gathered_total": st.lp_gathered_total,
+            "dense_head_pairs": st.dense_head_pairs}
 
 
 def nrlsh_profile_enable(on: bool = True):

@@ -1136,7 +1136,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                  o_srh = blk.reserve<int32_t>(sortq ? (size_t)B : 1),
                  o_sid = blk.reserve<int64_t>(sortq ? (size_t)B * k : 1),
                  o_sip = blk.reserve<float>(sortq ? (size_t)B * k : 1),
-                 o_lst = blk.reserve<unsigned long long>(3);
+                 o_lst = blk.reserve<unsigned long long>(4);
     blk.allocate(s);
     DBuf<uint64_t> keys = blk.view<uint64_t>(o_ky);
     DBuf<int32_t> kcount = blk.view<int32_t>(o_kc), grho = blk.view<int32_t>(o_rh), gtie_g = blk.view<int32_t>(o_tg);
@@ -1151,7 +1151,8 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
     DBuf<int64_t> sids = blk.view<int64_t>(o_sid);
     // kept-list totals of the batches whose check is left to the device
     DBuf<unsigned long long> lstats = blk.view<unsigned long long>(o_lst);
-    if (collect && bf16_rows) HIPX(hipMemsetAsync(lstats.get(), 0, 3 * sizeof(unsigned long long), s));
+    // (word 3: the (query, item) pairs the dense head's keep pass evaluates)
+    if (collect && bf16_rows) HIPX(hipMemsetAsync(lstats.get(), 0, 4 * sizeof(unsigned long long), s));
     DBuf<uint32_t> qcodes = blk.view<uint32_t>(o_qc), ghist = blk.view<uint32_t>(o_gh);
     DBuf<int32_t> gbase = blk.view<int32_t>(o_gb), ghthr = blk.view<int32_t>(o_th),
                   gtie = blk.view<int32_t>(o_ti), cand = blk.view<int32_t>(o_ca);
@@ -1393,6 +1394,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
                                        ix->wit_codes.get(), sq, nb, sh, hcells.get(), nhcells, nhcells, qx,
                                        ghthr.get(), gtie.get(), hpw.get(), hcmax.get(), htheta.get(), s));
                 tm.end();
+                sq.pairs = lstats.get() + 3;
                 tm.begin("head_screen");
                 HIPX(launch_screen(ix->Xl.get(), ix->Xh.get(), nullptr, ix->key_l.get(), ix->codes_l.get(), sq, nb,
                                    sh, hchunks.get(), nhchunks, qx, ghthr.get(), gtie.get(), gpstar.get(),
@@ -1476,13 +1478,14 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
         // the two passes; batches whose kept lists overflowed (bit 2) run
         // again without them, from the FP32 rows
         std::vector<uint32_t> fl((size_t)nbatches);
-        unsigned long long ls[3] = {0, 0, 0};
+        unsigned long long ls[4] = {0, 0, 0, 0};
         HIPX(hipMemcpyAsync(fl.data(), gfail.get(), fl.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
         if (bf16_rows) HIPX(hipMemcpyAsync(ls, lstats.get(), sizeof ls, hipMemcpyDeviceToHost, s));
         HIPX(hipStreamSynchronize(s));
         g_qstats.lp_kept_total += (int64_t)ls[0];
         g_qstats.lp_kept_max = std::max<int64_t>(g_qstats.lp_kept_max, (int64_t)ls[1]);
         g_qstats.lp_gathered_total += (int64_t)ls[2];
+        g_qstats.dense_head_pairs += (int64_t)ls[3];
         for (int64_t bi = 0; bi < nbatches; ++bi) {
             const uint32_t f = fl[(size_t)bi];
             if (f & 1u) {

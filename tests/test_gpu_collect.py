@@ -107,6 +107,9 @@ def test_dense_head_matches_oracle():
             say(f"  dense_head {dense_head}: stats {st}")
             assert st["collect_fallbacks"] == 0 and st["lp_fallbacks"] == 0, st
             items[dense_head] = st["dense_head_items"]
+            # the keep pass evaluates at most every (query, head item) pair
+            assert 0 <= st["dense_head_pairs"] <= nq * st["dense_head_items"], st
+            assert (st["dense_head_pairs"] > 0) == (st["dense_head_items"] > 0), st
             assert np.array_equal(ids, oids), dense_head
             assert np.array_equal(ips, oips.astype(np.float32)), dense_head
     assert items[-1] == 0, items
