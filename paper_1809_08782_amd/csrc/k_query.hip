@@ -1382,6 +1382,15 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
 // maximum over the 16 lanes of a DPP row (lanes 16 r .. 16 r + 15), in every
 // lane of the row: two quad swaps, then the half-row and row mirrors, each
 // a data-parallel move into v_max (no LDS crossbar traffic)
+// LDS written by some lanes of a wave and read by others: the stores are
+// complete (and not moved past this point) before the wave goes on
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int CTRL>
 __device__ __forceinline__ float dpp_move(float v)
 {
@@ -1682,6 +1691,10 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     constexpr bool STAGE = !MAXMODE && W > 0;
     constexpr int KS = STAGE ? 24 : 1;
     __shared__ int32_t kc_s[64], kl_s[64 * KS];
+    // pass B: per wave, a queue of the pairs that reach theta (see below)
+    constexpr int WQ = MAXMODE ? 1 : 512;
+    __shared__ uint16_t wq_s[4 * WQ];
+    __shared__ int wqn_s[4];
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int tile = blockIdx.x;
     const int j = chunks[3 * blockIdx.y], pbeg = chunks[3 * blockIdx.y + 1],
@@ -1790,6 +1803,8 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
     const __amdgpu_buffer_rsrc_t bxl =
         __builtin_amdgcn_make_buffer_rsrc((void *)(X3 ? Xlo + (int64_t)pbeg * dp : Xh), 0, X3 ? (int)rbytes : 0,
                                           0x00020000);
+    if (!MAXMODE && lane == 0) wqn_s[wave] = 0;
+    wave_sync();
     for (int p0 = pbeg + wave * IW; p0 < pend; p0 += 4 * IW) {
         uint32_t cw[NB][WC];
         float xn[NB];
@@ -1799,7 +1814,8 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
             const int pi = p0 + 16 * ib + r16;
             const int64_t pp = pi < pend ? pi : pbeg;
 #pragma unroll
-            for (int w = 0; w < W; ++w) cw[ib][w] = all ? 0u : codes_l[pp * W + w];
+            // (pass B reads the codes of its candidates only)
+            for (int w = 0; w < W; ++w) cw[ib][w] = (all || !MAXMODE) ? 0u : codes_l[pp * W + w];
             xn[ib] = sqrtf((float)key_l[pp]) * (1.0f + 0x1p-18f);
             ro[ib] = (uint32_t)(pi - pbeg) * (uint32_t)dp * 2u + 16u * g;
         }
@@ -1851,45 +1867,35 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                     }
                 }
         }
-        // pass B: one bound for this lane's NB items (e grows with ||x||, and
-        // float rounding is monotone), so a pair whose ip + emax stays below
-        // theta is dropped with one add and one compare; only the rare
-        // survivors take the probe test and the exact bound
-        float xmax = xn[0];
+        if (!MAXMODE) {
+            // pass B in two steps.  A pair whose upper bound ip32 + e reaches
+            // theta is a candidate: one bound for the lane's NB items first (e
+            // grows with ||x|| and float rounding is monotone, so a pair whose
+            // ip + emax stays below theta is dropped with one add and one
+            // compare), then each item's own bound.  Candidates, about one
+            // pair in a hundred, go to the wave's queue in LDS, and only they
+            // take the probe test and the list append: evaluated in place,
+            // the probe test ran for nearly every pair, since almost every
+            // (query row, 64 items) step of the wave holds some candidate.
+            float xmax = xn[0];
 #pragma unroll
-        for (int ib = 1; ib < NB; ++ib) xmax = fmaxf(xmax, xn[ib]);
-#pragma unroll
-        for (int qb = 0; qb < 4; ++qb) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int ql = 16 * qb + 4 * g + v;
-                if (!MAXMODE) {
-                    const float th = th_s[ql];
-                    const float emax = gam * qn_s[ql] * xmax + 0x1p-90f;
-                    bool near = false;
-#pragma unroll
-                    for (int ib = 0; ib < NB; ++ib) near |= !(acc[qb][ib][v] + emax < th);
-                    if (!near) continue;
-                }
-                const int hthr = hthr_s[ql], htie = htie_s[ql];
-                const float th = th_s[ql], qn = qn_s[ql];
-                float gmax[NB / 2];  // MAXMODE: per 32-item group of this iteration
-#pragma unroll
-                for (int hg = 0; hg < NB / 2; ++hg) gmax[hg] = -INFINITY;
-#pragma unroll
-                for (int ib = 0; ib < NB; ++ib) {
-                    const int pi = p0 + 16 * ib + r16;
+            for (int ib = 1; ib < NB; ++ib) xmax = fmaxf(xmax, xn[ib]);
+            uint16_t *wq = wq_s + wave * WQ;
+            // the whole wave (every lane active) empties its queue: entry
+            // (row ql << 6 | item offset in this iteration), one per lane
+            auto drain = [&]() {
+                wave_sync();
+                const int nw = __builtin_amdgcn_readfirstlane(min(wqn_s[wave], WQ));
+                for (int i = lane; i < nw; i += 64) {
+                    const uint32_t e = wq[i];
+                    const int ql = (int)(e >> 6), pi = p0 + (int)(e & 63u);
                     bool probed = pi < pend;
-                    if (!all) {
-                        int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
-                        if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
-                        probed = probed && (h <= hthr || (h == htie && pi <= pstar_s[ql]));
+                    if (!all && probed) {
+                        int h = __popc(codes_l[(int64_t)pi * W] ^ qc_s[ql * W]);
+                        if (W == 2) h += __popc(codes_l[(int64_t)pi * W + 1] ^ qc_s[ql * W + 1]);
+                        probed = h <= hthr_s[ql] || (h == htie_s[ql] && pi <= pstar_s[ql]);
                     }
-                    const float ip = acc[qb][ib][v];
-                    const float e = gam * qn * xn[ib] + 0x1p-90f;
-                    if (MAXMODE) {
-                        if (probed) gmax[ib >> 1] = fmaxf(gmax[ib >> 1], ip - e);
-                    } else if (probed && !(ip + e < th)) {
+                    if (probed) {
                         const int ls = STAGE ? atomicAdd(&kc_s[ql], 1) : KS;
                         if (ls < KS) {
                             kl_s[ql * KS + ls] = pi;
@@ -1900,8 +1906,64 @@ __device__ __forceinline__ void screen_bf16(NRLSH_SCREEN_PARAMS)
                         }
                     }
                 }
-                if (MAXMODE) {
-                    // largest lower bound of each 32-item group for query ql
+                wave_sync();
+                if (lane == 0) wqn_s[wave] = 0;
+                wave_sync();
+            };
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    // room for this step's entries (at most 64 NB), made here
+                    // where every lane is active (each takes a share of the queue)
+                    if (__builtin_amdgcn_readfirstlane(wqn_s[wave]) > WQ - 64 * NB) drain();
+                    const int ql = 16 * qb + 4 * g + v;
+                    const float th = th_s[ql], qn = qn_s[ql];
+                    const float emax = gam * qn * xmax + 0x1p-90f;
+                    bool near = false;
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) near |= !(acc[qb][ib][v] + emax < th);
+                    if (!near) continue;
+                    uint32_t cm = 0u;
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) {
+                        const float e = gam * qn * xn[ib] + 0x1p-90f;
+                        cm |= (uint32_t)!(acc[qb][ib][v] + e < th) << ib;
+                    }
+                    if (cm != 0u) {
+                        int o = atomicAdd(&wqn_s[wave], __popc(cm));
+#pragma unroll
+                        for (int ib = 0; ib < NB; ++ib)
+                            if ((cm >> ib) & 1u) wq[o++] = (uint16_t)((ql << 6) | (16 * ib + r16));
+                    }
+                }
+            }
+            drain();
+        } else {
+            // pass A: the largest lower bound ip32 - e over the probed items of
+            // each 32-item group, per query row
+#pragma unroll
+            for (int qb = 0; qb < 4; ++qb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int ql = 16 * qb + 4 * g + v;
+                    const int hthr = hthr_s[ql], htie = htie_s[ql];
+                    const float qn = qn_s[ql];
+                    float gmax[NB / 2];
+#pragma unroll
+                    for (int hg = 0; hg < NB / 2; ++hg) gmax[hg] = -INFINITY;
+#pragma unroll
+                    for (int ib = 0; ib < NB; ++ib) {
+                        const int pi = p0 + 16 * ib + r16;
+                        bool probed = pi < pend;
+                        if (!all) {
+                            int h = __popc(cw[ib][0] ^ qc_s[ql * W]);
+                            if (W == 2) h += __popc(cw[ib][1] ^ qc_s[ql * W + 1]);
+                            probed = probed && (h <= hthr || (h == htie && pi <= pstar_s[ql]));
+                        }
+                        const float e = gam * qn * xn[ib] + 0x1p-90f;
+                        if (probed) gmax[ib >> 1] = fmaxf(gmax[ib >> 1], acc[qb][ib][v] - e);
+                    }
 #pragma unroll
                     for (int hg = 0; hg < NB / 2; ++hg) {
                         gmax[hg] = row16_max(gmax[hg]);
@@ -2068,12 +2130,10 @@ __global__ __launch_bounds__(512) void k_screen_b128(
 }
 
 // Pass B of the single-product screen, the one that runs over every probed
-// pair.  Without the probe test (W = 0) a register budget for three waves
-// per SIMD (a few values spill) hides the operand loads better than two
-// waves with no spill; with it (the codes' registers, 108 bytes of spills at
-// three waves) two waves per SIMD are faster (d = 128: 2.57 -> 2.39 ms).
+// pair.  It holds no item codes (its candidates read theirs from the queue),
+// so a register budget for three waves per SIMD fits without spills.
 template <int W>
-__global__ __launch_bounds__(256, W == 0 ? 3 : 2) void k_screen1(NRLSH_SCREEN_PARAMS)
+__global__ __launch_bounds__(256, 3) void k_screen1(NRLSH_SCREEN_PARAMS)
 {
     screen_bf16<W, false, false>(NRLSH_SCREEN_ARGS);
 }
