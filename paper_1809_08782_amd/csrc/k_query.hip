@@ -787,16 +787,20 @@ __device__ __forceinline__ int32x4_t bits16_to_bytes(uint32_t v)
 }
 
 // Every lane empties its staged hits of one query half into the query's keys:
-// the reservation is issued first, the keys are formed (levels counted in the
-// LDS histogram, ranks read from the R row) while it is in flight, then
-// stored.  Called by the whole wave.
+// the reservation (one atomic for the two lanes of a query) is issued first,
+// the keys are formed (levels counted in the LDS histogram, ranks read from
+// the R row) while it is in flight, then stored.  Called by the whole wave.
 __device__ __forceinline__ void collect_flush_mx(const uint16_t *__restrict__ so, const uint8_t *__restrict__ sh,
                                                  int lane, int cnt, int L, const int32_t *__restrict__ Rrow,
                                                  uint32_t *hist, int col, int32_t *__restrict__ counts,
                                                  uint64_t *__restrict__ keys, int64_t q, int64_t cap, int64_t p0)
 {
-    int64_t base = 0;
-    if (cnt > 0) base = atomicAdd(&counts[q], cnt);
+    // lanes l and l + 32 hold the same query: one reservation for both
+    const int other = __shfl_xor(cnt, 32, 64);
+    int b = 0;
+    if (lane < 32 && cnt + other > 0) b = atomicAdd(&counts[q], cnt + other);
+    b = __shfl(b, lane & 31, 64);
+    const int64_t base = lane < 32 ? b : b + other;
     int top = cnt;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) top = max(top, __shfl_xor(top, o, 64));
