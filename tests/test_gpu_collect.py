@@ -158,3 +158,21 @@ def test_dense_head_overflow_reruns_without_head():
         assert st["lp_fallbacks"] >= 1, st
         assert np.array_equal(ids, oids)
         assert np.array_equal(ips, oips.astype(np.float32))
+
+
+def test_probing_order_too_long_for_lds():
+    """m (L + 1) buckets beyond what the threshold pass stages in LDS (12,288):
+    it then reads the probing order from memory; the two-pass scan (small
+    budget) and the collecting scan (large budget) against the oracle."""
+    say("case threshold order in memory")
+    n, d, m, L, k = 48000, 12, 400, 32, 10
+    X = make_items("lognormal", n, d, seed=101, sigma=1.0)
+    Q = make_queries(70, d, seed=102)
+    oix = orc.OracleIndex(X, m, L, seed=31, threads=8)
+    with nr.nrlsh_build(X, m, L, 31) as gix:
+        for T in (3000, 12000):
+            ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather")
+            oids, oips = oix.query(Q, k, T)
+            assert np.array_equal(ids, oids), T
+            assert np.array_equal(ips, oips.astype(np.float32)), T
+        assert nr.nrlsh_get_query_stats()["scan_pairs"] > 0
