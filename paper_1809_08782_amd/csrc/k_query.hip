@@ -1310,11 +1310,15 @@ __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ pa
 // Stored position of the r*-th item of the threshold bucket (j*, h*) of each
 // query: with it the probed set becomes a per-pair predicate,
 //   p in C_T  <=>  h <= hthr[q][j]  or  (j = j*, h = h*, p <= P*).
-// One block per query: each of its TL_WAVES waves counts the bucket's items
-// in a contiguous share of sub-dataset j*, and the wave whose share holds
-// the r*-th one walks it again to find its position; a bucket that is probed
-// whole (r* = INT_MAX) needs no walk.
+// One block per query walks sub-dataset j* from its first stored item in
+// rounds of TL_WAVES x TL_GROUPS 64-item groups (each wave a contiguous 256
+// items, its match masks kept in registers); the block adds up the round's
+// matches and stops in the round that holds the r*-th one, whose wave reads
+// the position off its masks.  The walk ends where r* falls (on average half
+// way through the sub-dataset) instead of counting all of it first; a bucket
+// that is probed whole (r* = INT_MAX) needs no walk.
 constexpr int TL_WAVES = 16;
+constexpr int TL_GROUPS = 4;
 
 template <int W>
 __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__restrict__ codes_l,
@@ -1324,7 +1328,7 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
                                                               const int32_t *__restrict__ gtie,
                                                               int32_t *__restrict__ gpstar)
 {
-    __shared__ int32_t cnt_s[TL_WAVES];
+    __shared__ int32_t cnt_s[2][TL_WAVES];  // per round (two buffers: one barrier per round)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int64_t q = blockIdx.x;
     const int tile = (int)(q >> 6), ql = (int)(q & 63);
@@ -1337,44 +1341,52 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
     const int64_t r = qrow(q, jstar, qsets);
     const uint32_t q0 = qcodes[r * W], q1 = W == 2 ? qcodes[r * W + 1] : 0u;
     const int64_t ps = off[jstar], pe = off[jstar + 1];
-    const int64_t ng = (pe - ps + 63) / 64;  // 64-item groups, a contiguous share per wave
-    const int64_t g0 = ng * wave / TL_WAVES, g1 = ng * (wave + 1) / TL_WAVES;
     auto match = [&](int64_t p) {
         if (p >= pe) return false;
         int h = __popc(codes_l[p * W] ^ q0);
         if (W == 2) h += __popc(codes_l[p * W + 1] ^ q1);
         return h == hstar;
     };
-    int cnt = 0;
-    int64_t g = g0;
-    for (; g + 4 <= g1; g += 4) {
-        bool mt[4];
+    if (threadIdx.x == 0) gpstar[q] = -1;  // replaced below if the bucket holds r* items
+    int c = 0;  // matches before this round
+    for (int64_t p0 = ps, rd = 0; p0 < pe; p0 += TL_WAVES * TL_GROUPS * 64, ++rd) {
+        const int64_t pw = p0 + (int64_t)wave * TL_GROUPS * 64;
+        uint64_t bal[TL_GROUPS];
+        bool mt[TL_GROUPS];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) mt[u] = match(ps + (g + u) * 64 + lane);
+        for (int u = 0; u < TL_GROUPS; ++u) mt[u] = match(pw + u * 64 + lane);
+        int cw = 0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) cnt += __popcll(__ballot(mt[u]));
-    }
-    for (; g < g1; ++g) cnt += __popcll(__ballot(match(ps + g * 64 + lane)));
-    if (lane == 0) cnt_s[wave] = cnt;
-    if (threadIdx.x == 0) gpstar[q] = -1;  // replaced below by the wave that finds the item
-    __syncthreads();
-    int before = 0;
-    for (int w = 0; w < wave; ++w) before += cnt_s[w];
-    if (before < rstar && before + cnt >= rstar) {  // wave-uniform: the r*-th match is in this share
-        int c = before;
-        for (g = g0; g < g1; ++g) {
-            const int64_t p0 = ps + g * 64;
-            const uint64_t bal = __ballot(match(p0 + lane));
-            const int k = __popcll(bal);
-            if (c + k >= rstar) {
-                const int need = rstar - c;  // 1-based rank inside this group
-                const int rank = __popcll(bal & ((1ull << lane) - 1ull));
-                const uint64_t sel = __ballot(((bal >> lane) & 1ull) && rank == need - 1);
-                if (lane == 0) gpstar[q] = (int32_t)(p0 + __ffsll((long long)sel) - 1);
-                break;
-            }
-            c += k;
+        for (int u = 0; u < TL_GROUPS; ++u) {
+            bal[u] = __ballot(mt[u]);
+            cw += __popcll(bal[u]);
         }
+        int32_t *cs = cnt_s[rd & 1];
+        if (lane == 0) cs[wave] = cw;
+        __syncthreads();
+        int before = 0, tot = 0;
+        for (int w = 0; w < TL_WAVES; ++w) {
+            const int v = cs[w];
+            before += w < wave ? v : 0;
+            tot += v;
+        }
+        if (c + tot >= rstar) {  // the same for the whole block: the r*-th match is in this round
+            if (c + before < rstar && c + before + cw >= rstar) {
+                int need = rstar - c - before;  // 1-based rank inside this wave's matches
+#pragma unroll
+                for (int u = 0; u < TL_GROUPS; ++u) {
+                    const int k = __popcll(bal[u]);
+                    if (need > 0 && need <= k) {
+                        const int rank = __popcll(bal[u] & ((1ull << lane) - 1ull));
+                        const uint64_t sel = __ballot(((bal[u] >> lane) & 1ull) && rank == need - 1);
+                        if (lane == 0) gpstar[q] = (int32_t)(pw + u * 64 + __ffsll((long long)sel) - 1);
+                    }
+                    need -= k;
+                }
+            }
+            return;
+        }
+        c += tot;
     }
 }
 

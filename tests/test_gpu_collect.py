@@ -176,3 +176,27 @@ def test_probing_order_too_long_for_lds():
             assert np.array_equal(ids, oids), T
             assert np.array_equal(ips, oips.astype(np.float32)), T
         assert nr.nrlsh_get_query_stats()["scan_pairs"] > 0
+
+
+@pytest.mark.parametrize("T", [6500, 7000])
+def test_dense_head_every_pair_a_candidate(T):
+    """Items alike to within the bfloat16 bounds and a budget below the kept
+    lists' room: every evaluated pair of the head reaches theta, so the keep
+    pass's candidate queue fills and empties many times per iteration, and
+    the kept lists (every probed pair of the head) are used, not run again."""
+    say(f"case dense head every pair a candidate T={T}")
+    n, d, m, L, k = 30000, 16, 4, 16, 10
+    rng = np.random.default_rng(103)
+    v = rng.standard_normal(d).astype(np.float32)
+    X = np.ascontiguousarray((v[None, :] * (1.0 + 1e-4 * rng.standard_normal((n, 1)))
+                              + 1e-5 * rng.standard_normal((n, d))).astype(np.float32))
+    Q = make_queries(64, d, seed=104)
+    oix = orc.OracleIndex(X, m, L, seed=29, threads=8)
+    oids, oips = oix.query(Q, k, T)
+    with nr.nrlsh_build(X, m, L, 29) as gix:
+        ids, ips = nr.nrlsh_query(gix, Q, k, T, rerank="gather", rerank_storage="bf16", dense_head=1)
+        st = nr.nrlsh_get_query_stats()
+        say(f"  stats {st}")
+        assert st["dense_head_items"] > 0 and st["lp_fallbacks"] == 0 and st["collect_fallbacks"] == 0, st
+        assert np.array_equal(ids, oids)
+        assert np.array_equal(ips, oips.astype(np.float32))
