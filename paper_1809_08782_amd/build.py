@@ -26,6 +26,11 @@ FLAGS = [
     "-ffp-contract=off",
     # no packed FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary vector registers: the compiler's
+    # default puts them in accumulation registers and copies each one out
+    # (and each initial value in) with an instruction of its own, 64 per
+    # 32-item group in the collecting scan
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", INCLUDE, "-I", CSRC,
     "-Wall", "-Wno-unused-result",
 ]
