@@ -426,6 +426,11 @@ typedef struct nrlsh_build_stats {
                                  and counted in recomputed_items / recomputed_bits) */
     int64_t lowp_bits;        /* BF16 / FP8: (item, bit) projections inside the margin */
     int64_t lowp_changed;     /* BF16 / FP8: bits the FP32 re-hash changed */
+    int64_t recompute_flips_tiny; /* of recompute_flips, those whose exact projection
+                              a . P(x) (P(x) of unit norm, Eq. 8) is below 1e-6 in
+                              magnitude; recompute_flips - recompute_flips_tiny flipped
+                              at 1e-6 or more.  Every flip is corrected: the codes are
+                              the FP64 definition's either way */
 } nrlsh_build_stats;
 
 nrlsh_status nrlsh_get_build_stats(const nrlsh_index *ix, nrlsh_build_stats *st);
@@ -455,6 +460,17 @@ nrlsh_status nrlsh_query_codes(const nrlsh_index *ix, const float *queries, int6
  * in no particular order (the set is the definition's). */
 nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
                                     int64_t probe_budget, int64_t *cand);
+
+/* The probed set with each item's level (Section 3.3: the probed buckets are
+ * (sub-dataset, l) pairs, l = the number of the item's L code bits equal to
+ * the query's, L minus their Hamming distance).  cand as nrlsh_query_candidates
+ * (host, nq x min(T, n) int64 original ids, in no particular order); levels
+ * (host, same shape, int32) receives l of each entry.  NRLSH_E_INVALID_ARG
+ * for a NULL levels with nq > 0, otherwise as nrlsh_query_candidates.  The
+ * levels are formed on the host from copies of the codes (n x ceil(L/32)
+ * words): a checking aid, not a fast path. */
+nrlsh_status nrlsh_query_candidates_levels(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                           int64_t probe_budget, int64_t *cand, int32_t *levels);
 
 /* The same under a probe mode (SCAN or SINGLE): counts (host, nq int64)
  * receives the number of probed items of each query; entries of cand past it

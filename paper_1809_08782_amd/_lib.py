@@ -58,7 +58,8 @@ RERANK_MODES = {"auto": 0, "gather": 1, "screen": 2, "screen_fp32": 3, "screen_b
 class BuildStats(C.Structure):
     _fields_ = [("recomputed_items", C.c_int64), ("recomputed_bits", C.c_int64),
                 ("recompute_flips", C.c_int64), ("lowp_items", C.c_int64),
-                ("lowp_bits", C.c_int64), ("lowp_changed", C.c_int64)]
+                ("lowp_bits", C.c_int64), ("lowp_changed", C.c_int64),
+                ("recompute_flips_tiny", C.c_int64)]
 
 
 class QueryStats(C.Structure):
@@ -144,6 +145,8 @@ def lib():
         L.nrlsh_query_candidates.restype = st
         L.nrlsh_query_candidates_ex.argtypes = [P, P, I64, I64, I32, P, P]
         L.nrlsh_query_candidates_ex.restype = st
+        L.nrlsh_query_candidates_levels.argtypes = [P, P, I64, I64, P, P]
+        L.nrlsh_query_candidates_levels.restype = st
         L.nrlsh_get_hash_tables.argtypes = [P, C.POINTER(I32)]
         L.nrlsh_get_hash_tables.restype = st
         L.nrlsh_get_codes_table.argtypes = [P, I32, P]
@@ -292,7 +295,8 @@ class Index:
         _check(lib().nrlsh_get_build_stats(self.handle, C.byref(st)))
         return {"recomputed_items": st.recomputed_items, "recomputed_bits": st.recomputed_bits,
                 "recompute_flips": st.recompute_flips, "lowp_items": st.lowp_items,
-                "lowp_bits": st.lowp_bits, "lowp_changed": st.lowp_changed}
+                "lowp_bits": st.lowp_bits, "lowp_changed": st.lowp_changed,
+                "recompute_flips_tiny": st.recompute_flips_tiny}
 
     def hash_copy(self):
         """(storage name, copy in stored order n x dp, row scales or None)."""
@@ -342,6 +346,17 @@ class Index:
         _check(lib().nrlsh_query_candidates_ex(self.handle, Q.ctypes.data, Q.shape[0], int(probe_budget),
                                                PROBES[probe], out.ctypes.data, counts.ctypes.data))
         return [out[i, :counts[i]].copy() for i in range(Q.shape[0])]
+
+    def query_candidates_levels(self, queries, probe_budget: int):
+        """Probed ids per query and each one's level l (equal code bits):
+        two (nq, min(T, n)) arrays, int64 ids and int32 levels."""
+        Q = _host_f32(queries)
+        Tq = min(int(probe_budget), self.n)
+        out = np.empty((Q.shape[0], Tq), dtype=np.int64)
+        lv = np.empty((Q.shape[0], Tq), dtype=np.int32)
+        _check(lib().nrlsh_query_candidates_levels(self.handle, Q.ctypes.data, Q.shape[0], int(probe_budget),
+                                                   out.ctypes.data, lv.ctypes.data))
+        return out, lv
 
 
 # ------------------------------------------------------------------ C-ABI names

@@ -892,6 +892,7 @@ void index_settle(const nrlsh_index *ix)
         ix->stats.recomputed_items = (int64_t)hc.fix_count + hc.fix_prev;
         ix->stats.recomputed_bits = (int64_t)hc.fix_bits;
         ix->stats.recompute_flips = (int64_t)hc.fix_flips;
+        ix->stats.recompute_flips_tiny = (int64_t)hc.fix_flips_tiny;
     }
     ix->settled.store(true, std::memory_order_release);
 }
@@ -2452,8 +2453,11 @@ nrlsh_status nrlsh_query_candidates_ex(const nrlsh_index *ix, const float *queri
     });
 }
 
-nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
-                                    int64_t probe_budget, int64_t *cand)
+namespace {
+// The probed set of each query (original ids) and, when levels is not NULL,
+// each probed item's number of bits equal to its query's code, l = L - h.
+nrlsh_status query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq, int64_t probe_budget,
+                              int64_t *cand, int32_t *levels)
 {
     if (!ix || nq < 0 || (nq > 0 && (!queries || !cand)) || probe_budget < 1)
         return fail(NRLSH_E_INVALID_ARG, "bad argument");
@@ -2481,8 +2485,43 @@ nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries,
             if (pos[e] < 0 || pos[e] >= ix->n) throw Failure{NRLSH_E_INTERNAL, "probed position out of range"};
             cand[e] = perm[pos[e]];
         }
+        if (levels) {
+            // codes in stored order and the query codes, then l per entry (the
+            // sub-dataset of a stored position from the offsets)
+            const int W = ix->W;
+            std::vector<uint32_t> codes((size_t)ix->n * W), qch((size_t)nq * ix->qsets * W);
+            HIPX(hipMemcpyAsync(codes.data(), ix->codes_l.get(), codes.size() * sizeof(uint32_t),
+                                hipMemcpyDeviceToHost, s));
+            HIPX(hipMemcpyAsync(qch.data(), qc.get(), qch.size() * sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPX(hipStreamSynchronize(s));
+            const std::vector<int64_t> &off = ix->off_h;
+            for (int64_t q = 0; q < nq; ++q)
+                for (int64_t e = 0; e < Tq; ++e) {
+                    const int64_t p = pos[(size_t)(q * Tq + e)];
+                    const int j = (int)(std::upper_bound(off.begin(), off.end(), p) - off.begin()) - 1;
+                    const int64_t r = qrow(q, j, ix->qsets);
+                    int h = 0;
+                    for (int w = 0; w < W; ++w)
+                        h += __builtin_popcount(codes[(size_t)(p * W + w)] ^ qch[(size_t)(r * W + w)]);
+                    levels[q * Tq + e] = ix->L - h;
+                }
+        }
         return NRLSH_OK;
     });
+}
+}  // namespace
+
+nrlsh_status nrlsh_query_candidates(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                    int64_t probe_budget, int64_t *cand)
+{
+    return query_candidates(ix, queries, nq, probe_budget, cand, nullptr);
+}
+
+nrlsh_status nrlsh_query_candidates_levels(const nrlsh_index *ix, const float *queries, int64_t nq,
+                                           int64_t probe_budget, int64_t *cand, int32_t *levels)
+{
+    if (nq > 0 && !levels) return fail(NRLSH_E_INVALID_ARG, "NULL levels");
+    return query_candidates(ix, queries, nq, probe_budget, cand, levels);
 }
 
 nrlsh_status nrlsh_get_query_stats(nrlsh_query_stats *st)

@@ -1077,7 +1077,7 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
     uint32_t *__restrict__ codes_l, int W)
 {
     const uint32_t cnt = ctr->fix_count;
-    unsigned long long nbits = 0, nflip = 0;
+    unsigned long long nbits = 0, nflip = 0, ntiny = 0;
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < cnt; e += gridDim.x * blockDim.x) {
         const FixEntry fe = fix[e];
         const int64_t i = fe.item;
@@ -1125,7 +1125,11 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
                 const int r = rr[b];
                 const double sum = sacc[b] + (double)Ab[(int64_t)r * (d + 1) + d] * vd;
                 const uint64_t bit = sum > 0.0 ? 1ull : 0ull;
-                nflip += ((code >> r) & 1ull) != bit;
+                // flips counted in two bands of the exact projection a . P(x)
+                // (P(x) has unit norm): below 1e-6 in magnitude, and the rest
+                const bool flip = ((code >> r) & 1ull) != bit;
+                nflip += flip;
+                ntiny += flip && __builtin_fabs(sum) < 1e-6;
                 ++nbits;
                 code = (code & ~(1ull << r)) | (bit << r);
             }
@@ -1136,6 +1140,7 @@ __global__ __launch_bounds__(256) void k_hash_fixup(
     if (nbits) {
         atomicAdd(&ctr->fix_bits, nbits);
         atomicAdd(&ctr->fix_flips, nflip);
+        if (ntiny) atomicAdd(&ctr->fix_flips_tiny, ntiny);
     }
 }
 

@@ -28,6 +28,7 @@ struct BuildCounters {
     uint32_t fix_prev;       // entries of the FixEntry lists of earlier hash tables
     unsigned long long lowp_bits;
     unsigned long long lowp_changed;
+    unsigned long long fix_flips_tiny;  // of fix_flips, those with |a . P(x)| < 1e-6 in FP64
 };
 
 // ------------------------------------------------------------------ build

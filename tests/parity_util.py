@@ -44,6 +44,7 @@ def check_build(gix, oix, label=""):
     say(f"  [{label}] code mismatches {nbad}/{gix.n}, recomputed items "
         f"{st['recomputed_items']} bits {st['recomputed_bits']} fp32 flips {st['recompute_flips']}")
     assert nbad == 0, f"{label}: {nbad} item codes differ"
+    assert 0 <= st["recompute_flips_tiny"] <= st["recompute_flips"] <= st["recomputed_bits"], st
     return st
 
 

@@ -514,3 +514,23 @@ def test_staged_scan_early_exit(case):
             assert 0 < st["scan_pairs"] <= nq * n, st["scan_pairs"]
             if early:
                 assert st["scan_pairs"] < nq * n, st["scan_pairs"]
+
+
+@pytest.mark.parametrize("proj", ["shared", "per_subset"])
+def test_candidates_with_levels(proj):
+    """The probed set with each item's level l (equal code bits) against the
+    oracle's probing order: the same (id, l) pairs, as sets."""
+    say(f"case candidates with levels {proj}")
+    n, d, m, L, nq, T = 20000, 16, 8, 24, 24, 3000
+    X = make_items("lognormal", n, d, seed=105, sigma=1.0)
+    Q = make_queries(nq, d, seed=106)
+    oix = orc.OracleIndex(X, m, L, seed=33, projections=proj)
+    with nr.nrlsh_build(X, m, L, 33, projections=proj) as gix:
+        ids, lv = gix.query_candidates_levels(Q, T)
+        assert ids.shape == (nq, T) and lv.shape == (nq, T)
+        # the same set as the ids-only call (the order of a probed list is
+        # that of its appends, which varies from call to call)
+        assert np.array_equal(np.sort(ids, axis=1), np.sort(gix.query_candidates(Q, T), axis=1))
+        for i in range(nq):
+            oc, ol = oix.candidates(Q[i], T)
+            assert sorted(zip(ids[i].tolist(), lv[i].tolist())) == sorted(zip(oc.tolist(), ol.tolist())), i
