@@ -53,19 +53,20 @@ def ground_truth(Xd, Qs, k):
     return torch.cat(out).numpy()
 
 
-def traffic_record(kernel, workload, T, timer=None):
+def traffic_record(kernel, workload, T, timer=None, tag="traffic_record"):
     """HBM bytes per query of a launch of `kernel` from a committed counter
     summary (profiles/*.md, a line "traffic_record: {json}"), provided the
     sources it names still hash to what they were when the counters were taken.
     A record that names the timer it belongs to (one kernel can serve two
-    steps, as the FP32 re-rank does) matches that timer only."""
+    steps, as the FP32 re-rank does) matches that timer only.  tag
+    "sq_record" reads the instruction counts of the same summaries."""
     import glob
     import hashlib
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         with open(path) as f:
-            lines = [ln for ln in f if ln.startswith("traffic_record: ")]
+            lines = [ln for ln in f if ln.startswith(tag + ": ")]
         for ln in lines:
-            rec = json.loads(ln[len("traffic_record: "):])
+            rec = json.loads(ln[len(tag) + 2:])
             if rec.get("kernel") != kernel or rec.get("workload") != workload or rec.get("T") != T:
                 continue
             if timer is not None and rec.get("timer", timer) != timer:
@@ -228,6 +229,7 @@ KERNELS = ["keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup
 BUILD_KERNELS = {"keys", "sort", "layout", "quant", "hash", "hash_rehash", "hash_fixup", "table"}
 INT_VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12  # 256 CUs x 64 lanes per clock x 2.4 GHz
 INT8_MFMA_PEAK_TOPS = 5000.0                    # dense int8 matrix-core peak, TOP/s
+VALU_ISSUE_PEAK = 256 * 4 * 2.4e9 / 4            # wave-wide vector instructions per second
 
 
 def main():
@@ -605,9 +607,20 @@ def kernel_roof(nm, kern, w, Tq, qb, qstats):
         achieved = ops_step / (per["ms_per_step"] * 1e-3) / 1e12
         kname = {"scan_hist": "k_scan_hist_s<%d>", "scan_emit": "k_scan_emit_s<%d>",
                  "scan_collect": "k_scan_collect_mx<%d>"}[nm] % W
-        return with_traffic({"kernel": kname, "bound": "mfma" if mx else "alu", "achieved": achieved,
-                             "peak": peak, "unit": "TOP/s", "frac": achieved / peak, "ops_per_step": ops_step,
-                             "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair}, kname)
+        d = with_traffic({"kernel": kname, "bound": "mfma" if mx else "alu", "achieved": achieved,
+                          "peak": peak, "unit": "TOP/s", "frac": achieved / peak, "ops_per_step": ops_step,
+                          "unit_work": "(query, item) pair", "ops_per_unit": ops_per_pair}, kname)
+        # the vector instructions around the products bound it: their issue
+        # rate (committed SQ_INSTS_VALU per query x queries per launch over
+        # the launch's time) against one wave-wide instruction per 4 cycles
+        # per SIMD (256 CUs x 4 SIMDs x 2.4 GHz / 4)
+        sq = traffic_record(kname, w.name, Tq, nm, tag="sq_record")
+        if sq:
+            insts = sq["valu_insts_per_query"] * nq_launch
+            rate = insts / (per["avg_ms"] * 1e-3)
+            d["valu_issue"] = {"insts_per_launch": insts, "per_s": rate, "peak_per_s": VALU_ISSUE_PEAK,
+                               "frac": rate / VALU_ISSUE_PEAK, "source": sq}
+        return d
     if nm == "head_screen":
         # the keep pass of the dense head: one bf16 product (2d flops) per
         # (query, item) pair it evaluates (tiles skip the chunks none of their
@@ -616,10 +629,17 @@ def kernel_roof(nm, kern, w, Tq, qb, qstats):
         flops = 2.0 * w.d * pairs
         achieved = flops / (per["avg_ms"] * 1e-3) / 1e12
         kname = "k_screen1<%d>" % W
-        return with_traffic({"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFS,
-                             "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFS, "flops_per_launch": flops,
-                             "unit_work": "(query, item) pair of the dense head", "flops_per_unit": 2.0 * w.d,
-                             "units_per_launch": pairs}, kname)
+        d = with_traffic({"kernel": kname, "bound": "mfma", "achieved": achieved, "peak": BF16_MFMA_PEAK_TFS,
+                          "unit": "TFLOP/s", "frac": achieved / BF16_MFMA_PEAK_TFS, "flops_per_launch": flops,
+                          "unit_work": "(query, item) pair of the dense head", "flops_per_unit": 2.0 * w.d,
+                          "units_per_launch": pairs}, kname)
+        sq = traffic_record(kname, w.name, Tq, nm, tag="sq_record")
+        if sq:
+            insts = sq["valu_insts_per_query"] * nq_launch
+            rate = insts / (per["avg_ms"] * 1e-3)
+            d["valu_issue"] = {"insts_per_launch": insts, "per_s": rate, "peak_per_s": VALU_ISSUE_PEAK,
+                               "frac": rate / VALU_ISSUE_PEAK, "source": sq}
+        return d
     if nm == "screen":
         pairs = (qstats.get("screen_pairs") or 0) / max(1, qstats.get("screen_passes") or 1)
         flops = 2.0 * w.d * pairs
