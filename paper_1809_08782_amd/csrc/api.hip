@@ -1352,7 +1352,7 @@ void run_query_gather(const nrlsh_index *ix, const float *Qd, int64_t nq, int32_
             tm.end();
             tm.begin("tie_locate");
             HIPX(launch_tie_locate(ix->codes_l.get(), ix->off.get(), qx, nb, sh.W, sh.qsets, gtie.get(),
-                                   gpstar.get(), s));
+                                   gpstar.get(), s, ghist.get(), sh.m, sh.L));
             tm.end();
             tm.begin("filter");
             HIPX(launch_collect_filter(keys.get(), kcount.get(), kcap, nb, gtie.get(), gpstar.get(), rx, sh.Tq, cb,

@@ -1314,9 +1314,13 @@ __global__ __launch_bounds__(64) void k_topk_merge(const double *__restrict__ pa
 // rounds of TL_WAVES x TL_GROUPS 64-item groups (each wave a contiguous 256
 // items, its match masks kept in registers); the block adds up the round's
 // matches and stops in the round that holds the r*-th one, whose wave reads
-// the position off its masks.  The walk ends where r* falls (on average half
-// way through the sub-dataset) instead of counting all of it first; a bucket
-// that is probed whole (r* = INT_MAX) needs no walk.
+// the position off its masks.  The walk ends where r* falls instead of
+// counting all of it first.  Given the tile histograms (ghist: the bucket's
+// exact item count N* at [tile][j*][h*][query]), a cut past the middle,
+// r* > N* / 2, is found from the other end, as the (N* - r* + 1)-th match
+// counted from the last stored item, so that no walk covers more than about
+// half of the sub-dataset.  A bucket that is probed whole (r* = INT_MAX)
+// needs no walk.
 constexpr int TL_WAVES = 16;
 constexpr int TL_GROUPS = 4;
 
@@ -1326,7 +1330,8 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
                                                               const uint32_t *__restrict__ qcodes,
                                                               int64_t nq, int qsets,
                                                               const int32_t *__restrict__ gtie,
-                                                              int32_t *__restrict__ gpstar)
+                                                              int32_t *__restrict__ gpstar,
+                                                              const uint32_t *__restrict__ ghist, int m, int L)
 {
     __shared__ int32_t cnt_s[2][TL_WAVES];  // per round (two buffers: one barrier per round)
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -1348,8 +1353,26 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
         return h == hstar;
     };
     if (threadIdx.x == 0) gpstar[q] = -1;  // replaced below if the bucket holds r* items
-    int c = 0;  // matches before this round
-    for (int64_t p0 = ps, rd = 0; p0 < pe; p0 += TL_WAVES * TL_GROUPS * 64, ++rd) {
+    // from the back: the target is the rk-th match in descending stored order
+    int rk = rstar;
+    bool back = false;
+    if (ghist) {
+        const int L1 = L + 1;
+        const int64_t nstar = ghist[(((int64_t)tile * m + jstar) * L1 + hstar) * 64 + ql];
+        if (2 * (int64_t)rstar > nstar && rstar <= nstar) {
+            back = true;
+            rk = (int)(nstar - rstar + 1);
+        }
+    }
+    constexpr int64_t RW = TL_WAVES * TL_GROUPS * 64;  // items per round
+    int c = 0;  // matches before this round (in the walk's direction)
+    const int64_t nrounds = (pe - ps + RW - 1) / RW;
+    for (int64_t rd = 0; rd < nrounds; ++rd) {
+        // round rd covers [p0, p0 + RW); walking back, the rounds are taken
+        // from the last one down and, inside a round, the waves (and each
+        // wave's groups and lanes) in descending order
+        const int64_t p0 = back ? ps + (nrounds - 1 - rd) * RW : ps + rd * RW;
+        const int wv = back ? TL_WAVES - 1 - wave : wave;  // this wave's place in the walk
         const int64_t pw = p0 + (int64_t)wave * TL_GROUPS * 64;
         uint64_t bal[TL_GROUPS];
         bool mt[TL_GROUPS];
@@ -1367,17 +1390,21 @@ __global__ __launch_bounds__(TL_WAVES * 64) void k_tie_locate(const uint32_t *__
         int before = 0, tot = 0;
         for (int w = 0; w < TL_WAVES; ++w) {
             const int v = cs[w];
-            before += w < wave ? v : 0;
+            const int place = back ? TL_WAVES - 1 - w : w;
+            before += place < wv ? v : 0;
             tot += v;
         }
-        if (c + tot >= rstar) {  // the same for the whole block: the r*-th match is in this round
-            if (c + before < rstar && c + before + cw >= rstar) {
-                int need = rstar - c - before;  // 1-based rank inside this wave's matches
+        if (c + tot >= rk) {  // the same for the whole block: the target match is in this round
+            if (c + before < rk && c + before + cw >= rk) {
+                int need = rk - c - before;  // 1-based rank inside this wave's matches, walk order
 #pragma unroll
-                for (int u = 0; u < TL_GROUPS; ++u) {
+                for (int uu = 0; uu < TL_GROUPS; ++uu) {
+                    const int u = back ? TL_GROUPS - 1 - uu : uu;
                     const int k = __popcll(bal[u]);
                     if (need > 0 && need <= k) {
-                        const int rank = __popcll(bal[u] & ((1ull << lane) - 1ull));
+                        // the need-th set bit from the low end, or from the high end walking back
+                        const int below = __popcll(bal[u] & ((1ull << lane) - 1ull));
+                        const int rank = back ? k - 1 - below : below;
                         const uint64_t sel = __ballot(((bal[u] >> lane) & 1ull) && rank == need - 1);
                         if (lane == 0) gpstar[q] = (int32_t)(pw + u * 64 + __ffsll((long long)sel) - 1);
                     }
@@ -2537,14 +2564,14 @@ hipError_t launch_stage_check(const uint32_t *ghist, const int32_t *inv, int64_t
 
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
                              int64_t nq, int W, int qsets, const int32_t *gtie, int32_t *gpstar,
-                             hipStream_t s)
+                             hipStream_t s, const uint32_t *ghist, int m, int L)
 {
     if (W == 1)
         hipLaunchKernelGGL(k_tie_locate<1>, dim3((unsigned)nq), dim3(TL_WAVES * 64), 0, s, codes_l, off,
-                           qcodes, nq, qsets, gtie, gpstar);
+                           qcodes, nq, qsets, gtie, gpstar, ghist, m, L);
     else
         hipLaunchKernelGGL(k_tie_locate<2>, dim3((unsigned)nq), dim3(TL_WAVES * 64), 0, s, codes_l, off,
-                           qcodes, nq, qsets, gtie, gpstar);
+                           qcodes, nq, qsets, gtie, gpstar, ghist, m, L);
     return hipGetLastError();
 }
 

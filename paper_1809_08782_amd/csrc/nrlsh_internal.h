@@ -292,9 +292,11 @@ hipError_t launch_mt_emit(const uint32_t *codes_l, int64_t n, const uint32_t *qc
                           int32_t *cand, hipStream_t s);
 
 // Stored position of the r*-th item of each query's threshold bucket (-1 if none).
+// ghist (or NULL): the tile histograms of the threshold pass, whose bucket
+// counts let a cut past the bucket's middle be found from its last item.
 hipError_t launch_tie_locate(const uint32_t *codes_l, const int32_t *off, const uint32_t *qcodes,
                              int64_t nq, int W, int qsets, const int32_t *gtie, int32_t *gpstar,
-                             hipStream_t s);
+                             hipStream_t s, const uint32_t *ghist = nullptr, int m = 0, int L = 0);
 
 // Query-tiled FP32-MFMA screen of the probed set.  Chunks / cells are
 // (sub-dataset, first, end) triples of stored items.
